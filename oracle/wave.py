@@ -1,0 +1,496 @@
+"""FP64 numpy oracle of the stabilised parareal-like method (Nguyen & Tsai,
+arXiv 1905.00473).
+
+TEST INFRASTRUCTURE ONLY: imported by tests, the smoke check and the CPU
+baseline of the benchmark, never by the HIP library.
+
+Array conventions
+-----------------
+* A grid function on the periodic box is a numpy array of shape
+  ``(n_y, n_x)`` (2D), ``(n_z, n_y, n_x)`` (3D) or ``(n_x,)`` (1D); x is the
+  last (fastest) axis.  Spatial axis ``a = 0, 1, 2`` means x, y, z, i.e. numpy
+  axis ``ndim - 1 - a``.
+* The box has the same length ``L = n * dx`` along every axis (``L = 1`` for
+  the unit box of eq. (1)); wavenumbers are ``xi = 2*pi*k/L`` with integer
+  ``k`` from ``numpy.fft.fftfreq``.
+* A column of the data matrices (the energy components of eqs. matrixF /
+  matrixG) is the concatenation ``[d_x U ; d_y U ; (d_z U) ; P / c]`` of
+  flattened fields (x fastest), without the ``dx**d`` factor.
+
+Parity status (what pins each routine; see tests/test_oracle_pins.py)
+--------------------------------------------------------------------
+* laplacian, vv_step, propagate ........ pinned (discrete closed form for
+  constant c, conservation of the modified discrete energy, observed order
+  2 on a plane wave, time reversibility)
+* restrict, interp ...................... pinned (R I = identity, exact
+  reproduction of trigonometric polynomials, I(0) = 0)
+* gradient, grad2func, lambda_dag ....... pinned (per-mode multipliers of
+  Lambda^dag Lambda in closed form; the paper's printed reconstruction
+  errors of the Sec. 6.4 gradient-order table, third column)
+* energy ................................. pinned (the Frobenius identity of
+  eq. partOPP, hand-computed values)
+* procrustes, update_svd ................. pinned (brute force over O(2) and
+  O(3); the minimum-residual closed form; incremental == direct SVD of the
+  explicitly summed correlation matrix; rank identity of Sec. 3.3.1)
+* theta_parareal .......................... pinned (exactness of the first k
+  slices after k iterations; reduction to textbook parareal with the
+  spectral gradient, identical grids and Omega = I; energy preservation of
+  the corrected coarse propagator of Sec. 6.3).  The full-loop values on
+  the synthetic workloads are not printed in the paper: parity unpinned
+  beyond these invariants.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+__all__ = [
+    "Problem", "laplacian", "vv_step", "propagate", "restrict", "interp",
+    "gradient", "FD_COEFFS", "energy_components", "split_components",
+    "grad2func", "lambda_dag", "energy", "procrustes", "update_svd",
+    "omega_apply", "theta_parareal", "serial_fine", "energy_error",
+    "l2_error", "PararealResult",
+]
+
+
+# ---------------------------------------------------------------------------
+# Problem description (parameter columns of the Sec. 6 tables)
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class Problem:
+    """Discretisation parameters of one wave problem.
+
+    ``shape``: fine grid, numpy order (x last).  ``ratio``: dx_coarse /
+    dx_fine (coarse node J sits on fine node ratio*J, Sec. 6 "coarse grid
+    nodes overlap with the fine grid nodes").  ``T``: final time, ``N``:
+    number of coupling intervals of length dt_com = T/N.  ``m_fine`` /
+    ``m_coarse``: steps per interval of F and C (Sec. 3.1).  ``length``: box
+    length L per axis.
+    """
+
+    shape: tuple
+    ratio: int
+    T: float
+    N: int
+    m_fine: int
+    m_coarse: int
+    grad_order: object = 4
+    tol: float = 1e-14
+    length: float = 1.0
+
+    @property
+    def dim(self):
+        return len(self.shape)
+
+    @property
+    def coarse_shape(self):
+        return tuple(n // self.ratio for n in self.shape)
+
+    @property
+    def dx_fine(self):
+        return self.length / self.shape[-1]
+
+    @property
+    def dx_coarse(self):
+        return self.dx_fine * self.ratio
+
+    @property
+    def dt_com(self):
+        return self.T / self.N
+
+    @property
+    def dt_fine(self):
+        return self.dt_com / self.m_fine
+
+    @property
+    def dt_coarse(self):
+        return self.dt_com / self.m_coarse
+
+
+# ---------------------------------------------------------------------------
+# Sec. 3.1: second-order central differences + velocity Verlet
+# ---------------------------------------------------------------------------
+def laplacian(u, dx):
+    """Periodic second-order central-difference Laplacian: the sum over the
+    axes of (u[i+1] - 2 u[i] + u[i-1]) / dx^2 (Sec. 3.1)."""
+    out = np.zeros_like(u)
+    for ax in range(u.ndim):
+        out += (np.roll(u, -1, ax) - 2.0 * u + np.roll(u, 1, ax)) / dx ** 2
+    return out
+
+
+def vv_step(u, p, c2, h, dx):
+    """One velocity-Verlet step of u_tt = c^2 Lap u (Sec. 3.1): half kick,
+    drift, half kick."""
+    p = p + 0.5 * h * c2 * laplacian(u, dx)
+    u = u + h * p
+    p = p + 0.5 * h * c2 * laplacian(u, dx)
+    return u, p
+
+
+def propagate(u, p, c2, h, dx, m):
+    """m velocity-Verlet steps of size h.  With the fine grid and
+    h = dt_com/m_F this is the fine propagator F; with the coarse grid,
+    pointwise coarse c and h = dt_com/m_C it is the coarse propagator C
+    (Sec. 3.1)."""
+    u = np.array(u, dtype=np.float64, copy=True)
+    p = np.array(p, dtype=np.float64, copy=True)
+    for _ in range(m):
+        u, p = vv_step(u, p, c2, h, dx)
+    return u, p
+
+
+# ---------------------------------------------------------------------------
+# Grid transfer (Sec. 3.1; Sec. 5 "R I = 1"; Sec. 6 interpft)
+# ---------------------------------------------------------------------------
+def restrict(u, ratio):
+    """Pointwise restriction R: the values at the fine nodes that coincide
+    with coarse nodes (coarse J <-> fine ratio*J on every axis)."""
+    sl = tuple(slice(None, None, ratio) for _ in range(u.ndim))
+    return np.array(u[sl], copy=True)
+
+
+def _interp_axis(U, ratio, ax):
+    n = U.shape[ax]
+    nf = n * ratio
+    A = np.moveaxis(np.fft.fft(U, axis=ax), ax, -1)
+    B = np.zeros(A.shape[:-1] + (nf,), dtype=complex)
+    h = n // 2
+    if n % 2 == 0:
+        # non-negative frequencies below Nyquist, then the Nyquist
+        # coefficient split equally between +n/2 and -n/2, then the
+        # negative frequencies
+        B[..., :h] = A[..., :h]
+        B[..., h] = 0.5 * A[..., h]
+        B[..., nf - h] = 0.5 * A[..., h]
+        B[..., nf - h + 1:] = A[..., h + 1:]
+    else:
+        B[..., :h + 1] = A[..., :h + 1]
+        B[..., nf - h:] = A[..., h + 1:]
+    out = np.fft.ifft(B, axis=-1).real * ratio
+    return np.moveaxis(out, -1, ax)
+
+
+def interp(U, ratio):
+    """Trigonometric (Fourier) interpolation I from the coarse to the fine
+    grid, one axis at a time: the coarse spectrum is zero-padded, the
+    Nyquist coefficient of an even length is split between +n/2 and -n/2,
+    and the real part of the inverse transform is returned (the `interpft`
+    interpolation of Sec. 6)."""
+    out = np.asarray(U, dtype=np.float64)
+    if ratio == 1:
+        return np.array(out, copy=True)
+    for ax in range(out.ndim):
+        out = _interp_axis(out, ratio, ax)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Energy components (eqs. matrixF / matrixG, discrete-wave-energy)
+# ---------------------------------------------------------------------------
+#: beta_j of the central 2m-order first-derivative stencil
+#: d u ~ sum_j beta_j (u[i+j] - u[i-j]) / dx (Sec. 3.4)
+FD_COEFFS = {
+    2: (1.0 / 2.0,),
+    4: (2.0 / 3.0, -1.0 / 12.0),
+    6: (3.0 / 4.0, -3.0 / 20.0, 1.0 / 60.0),
+    8: (4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0),
+}
+
+
+def _wavenumbers(n, dx):
+    return 2.0 * np.pi * np.fft.fftfreq(n, d=dx)
+
+
+def gradient(U, dx, order=4):
+    """Numerical gradient nabla_h U as a list [d_x U, d_y U, (d_z U)]: a
+    periodic central difference of the given even order, or the Fourier
+    derivative real(ifft(i xi fft U)) for order 'spectral' (Sec. 3.4)."""
+    U = np.asarray(U, dtype=np.float64)
+    out = []
+    for a in range(U.ndim):
+        ax = U.ndim - 1 - a
+        if order == "spectral":
+            xi = _wavenumbers(U.shape[ax], dx)
+            shp = [1] * U.ndim
+            shp[ax] = -1
+            d = np.fft.ifft(1j * xi.reshape(shp) * np.fft.fft(U, axis=ax),
+                            axis=ax).real
+        else:
+            d = np.zeros_like(U)
+            for j, b in enumerate(FD_COEFFS[order], start=1):
+                d += b * (np.roll(U, -j, ax) - np.roll(U, j, ax))
+            d /= dx
+        out.append(d)
+    return out
+
+
+def energy_components(U, P, c, dx, order=4):
+    """Lambda[U, P] = [nabla_h U ; P / c] as one column (eqs. matrixF /
+    matrixG)."""
+    g = gradient(U, dx, order)
+    return np.concatenate([x.ravel() for x in g] + [(P / c).ravel()])
+
+
+def split_components(z, shape):
+    """Inverse of the concatenation in energy_components: returns the list
+    of d gradient blocks and the momentum block."""
+    n = int(np.prod(shape))
+    d = len(shape)
+    q = [z[a * n:(a + 1) * n].reshape(shape) for a in range(d)]
+    return q, z[d * n:(d + 1) * n].reshape(shape)
+
+
+def energy(u, p, c, dx, order=4):
+    """Discrete wave energy (eq. discrete-wave-energy):
+    1/2 sum |nabla_h u|^2 dx^d + 1/2 sum c^-2 p^2 dx^d."""
+    d = np.ndim(u)
+    g = gradient(u, dx, order)
+    return 0.5 * (sum(np.sum(x * x) for x in g)
+                  + np.sum(p * p / (c * c))) * dx ** d
+
+
+# ---------------------------------------------------------------------------
+# Reconstruction of the wavefield from its gradient (Sec. 3.4)
+# ---------------------------------------------------------------------------
+def grad2func(q, s, dx):
+    """Algorithm 2 / eq. gradient2coordinate: given gradient components q
+    (list of d fields) and the sum s of the sought function, return
+    real(ifft(W)) with W(xi) = -i xi.fft(q) / |xi|^2 for xi != 0 and
+    W(0) = s (unnormalised forward transform)."""
+    shape = q[0].shape
+    d = len(shape)
+    num = np.zeros(shape, dtype=complex)
+    xi2 = np.zeros(shape)
+    for a in range(d):
+        ax = d - 1 - a
+        xi = _wavenumbers(shape[ax], dx)
+        shp = [1] * d
+        shp[ax] = -1
+        xi = xi.reshape(shp)
+        num = num + xi * np.fft.fftn(q[a])
+        xi2 = xi2 + xi * xi
+    W = np.zeros(shape, dtype=complex)
+    nz = xi2 != 0
+    W[nz] = -1j * num[nz] / xi2[nz]
+    W[(0,) * d] = s
+    return np.fft.ifftn(W).real
+
+
+def lambda_dag(z, s, c, dx, shape):
+    """Lambda^dag: energy components [q ; p] -> wavefield [w, w_t] with
+    w = grad2func(q, s) and w_t = c p (Sec. 3.4)."""
+    q, pm = split_components(z, shape)
+    return grad2func(q, s, dx), c * pm
+
+
+# ---------------------------------------------------------------------------
+# Orthogonal Procrustes problem (Secs. 3.2, 3.3)
+# ---------------------------------------------------------------------------
+def procrustes(F, G):
+    """Full-rank solution of min ||F - Omega G||_F over orthogonal Omega:
+    Omega = X Y^T from the SVD F G^T = X Sigma Y^T, and the minimum
+    residual ||F||^2 + ||G||^2 - 2 trace(Sigma) (Sec. 3.3)."""
+    X, sig, Yt = np.linalg.svd(F @ G.T)
+    omega = X @ Yt
+    rmin2 = np.sum(F * F) + np.sum(G * G) - 2.0 * np.sum(sig)
+    return omega, rmin2
+
+
+def _reduced_qr(A):
+    # "truncatedqr" of Algorithm 1, read as the economy-size QR
+    Q, R = np.linalg.qr(A, mode="reduced")
+    return Q, R
+
+
+def _rank(sig, tol):
+    if sig.size == 0 or sig[0] <= 0.0:
+        return 0
+    return int(np.sum(sig / np.max(sig) > tol))
+
+
+def update_svd(U, S, V, F, G, tol):
+    """Algorithm 1: truncated SVD of M_new = U diag(S) V^T + F G^T.
+
+    With S empty (first call): reduced QR of F and G, SVD of R_F R_G^T,
+    rank = #{sigma_i / sigma_max > tol}.  Otherwise: projections U_F = U^T F
+    and V_G = V^T G, reduced QR of the residuals (one classical
+    Gram-Schmidt re-orthogonalisation pass against U / V, exact no-op in
+    exact arithmetic), SVD of H = [U_F; R_F][V_G; R_G]^T + diag(S, 0),
+    truncation, and the rotated bases [U Q_F] X_h, [V Q_G] Y_h.
+    Returns (U_new, S_new, V_new).
+    """
+    F = np.asarray(F, dtype=np.float64)
+    G = np.asarray(G, dtype=np.float64)
+    if S is None or len(S) == 0:
+        QF, RF = _reduced_qr(F)
+        QG, RG = _reduced_qr(G)
+        X, sig, Yt = np.linalg.svd(RF @ RG.T)
+        r = _rank(sig, tol)
+        return QF @ X[:, :r], sig[:r].copy(), QG @ Yt.T[:, :r]
+    UF = U.T @ F
+    VG = V.T @ G
+    Fp = F - U @ UF
+    Gp = G - V @ VG
+    UF2 = U.T @ Fp
+    Fp = Fp - U @ UF2
+    UF = UF + UF2
+    VG2 = V.T @ Gp
+    Gp = Gp - V @ VG2
+    VG = VG + VG2
+    QF, RF = _reduced_qr(Fp)
+    QG, RG = _reduced_qr(Gp)
+    H = np.vstack([UF, RF]) @ np.vstack([VG, RG]).T
+    r0 = len(S)
+    H[:r0, :r0] += np.diag(S)
+    X, sig, Yt = np.linalg.svd(H)
+    r = _rank(sig, tol)
+    Un = np.hstack([U, QF]) @ X[:, :r]
+    Vn = np.hstack([V, QG]) @ Yt.T[:, :r]
+    return Un, sig[:r].copy(), Vn
+
+
+def omega_apply(U, V, z):
+    """Action of the truncated phase corrector Omega = U V^T on z."""
+    return U @ (V.T @ z)
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 3 (eq. thetarelation)
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class PararealResult:
+    u: list                 # u^{K+1}_n, n = 0..N (fine grid)
+    p: list
+    rho: list               # ||F^k - Omega^k G^k||_F / ||F^k||_F, k = 1..K
+    rank: list              # rank of Omega^k, k = 1..K
+    history: list           # [(u list, p list)] for k = 1..K+1 if kept
+    sigma: list             # singular values after each update
+
+
+def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
+                   omega="procrustes", correction=True):
+    """Algorithm 3 of the paper, step by step.
+
+    Initialisation u^1_n = I C R u^1_{n-1}; then K iterations of: parallel
+    v_n = F u^k_{n-1} and U_n = C R u^k_{n-1} for n = 1..N; data matrices
+    F = [Lambda R v_n], G = [Lambda U_n]; UpdateSVD; serial sweep
+    w = C R u^{k+1}_{n-1}, [q,p] = Omega Lambda w, [q~,p~] = Omega Lambda U_n,
+    u^{k+1}_n = v_n + I[real(grad2func(q, sum w) - grad2func(q~, sum U_n)),
+    c (p - p~)].  Slice indices n = 0..N with u^k_0 = u0.
+
+    ``omega='identity'`` uses Omega = I (Sec. 6.2); ``correction=False``
+    drops the parareal-style additive term (Sec. 6.3).
+    """
+    r = prob.ratio
+    N = prob.N
+    cf = np.asarray(c, dtype=np.float64)
+    cc = restrict(cf, r)
+    c2f, c2c = cf * cf, cc * cc
+    dxf, dxc = prob.dx_fine, prob.dx_coarse
+    hf, hc = prob.dt_fine, prob.dt_coarse
+    cshape = prob.coarse_shape
+    order = prob.grad_order
+
+    def Fprop(u, p):
+        return propagate(u, p, c2f, hf, dxf, prob.m_fine)
+
+    def Cprop(U, P):
+        return propagate(U, P, c2c, hc, dxc, prob.m_coarse)
+
+    def Lam(U, P):
+        return energy_components(U, P, cc, dxc, order)
+
+    u = [np.array(u0, dtype=np.float64)] + [None] * N
+    p = [np.array(p0, dtype=np.float64)] + [None] * N
+    for n in range(1, N + 1):
+        W, Wp = Cprop(restrict(u[n - 1], r), restrict(p[n - 1], r))
+        u[n], p[n] = interp(W, r), interp(Wp, r)
+    history = [([x.copy() for x in u], [x.copy() for x in p])] \
+        if keep_history else []
+
+    Us = S = Vs = None
+    rhos, ranks, sigmas = [], [], []
+    for _k in range(K):
+        v, vp, Uc, Ucp = [None] * (N + 1), [None] * (N + 1), \
+            [None] * (N + 1), [None] * (N + 1)
+        for n in range(1, N + 1):           # the parallel loop
+            v[n], vp[n] = Fprop(u[n - 1], p[n - 1])
+            Uc[n], Ucp[n] = Cprop(restrict(u[n - 1], r),
+                                  restrict(p[n - 1], r))
+        Fm = np.column_stack([Lam(restrict(v[n], r), restrict(vp[n], r))
+                              for n in range(1, N + 1)])
+        Gm = np.column_stack([Lam(Uc[n], Ucp[n]) for n in range(1, N + 1)])
+        if omega == "procrustes":
+            Us, S, Vs = update_svd(Us, S, Vs, Fm, Gm, prob.tol)
+            res = Fm - omega_apply(Us, Vs, Gm)
+            ranks.append(len(S))
+            sigmas.append(S.copy())
+        else:
+            res = Fm - Gm
+            ranks.append(Fm.shape[0])
+            sigmas.append(np.zeros(0))
+        nF = np.linalg.norm(Fm)
+        rhos.append(float(np.linalg.norm(res) / nF) if nF > 0 else 0.0)
+
+        def Om(z):
+            return omega_apply(Us, Vs, z) if omega == "procrustes" else z
+
+        un = [u[0]] + [None] * N
+        pn = [p[0]] + [None] * N
+        for n in range(1, N + 1):            # the serial sweep
+            w, wp = Cprop(restrict(un[n - 1], r), restrict(pn[n - 1], r))
+            zq = Om(Lam(w, wp))
+            q, pq = split_components(zq, cshape)
+            q1 = grad2func(q, np.sum(w), dxc)
+            if correction:
+                zt = Om(Lam(Uc[n], Ucp[n]))
+                qt, pt = split_components(zt, cshape)
+                qt1 = grad2func(qt, np.sum(Uc[n]), dxc)
+                du = q1 - qt1
+                dp = cc * (pq - pt)
+                un[n] = v[n] + interp(du, r)
+                pn[n] = vp[n] + interp(dp, r)
+            else:
+                un[n] = interp(q1, r)
+                pn[n] = interp(cc * pq, r)
+        u, p = un, pn
+        if keep_history:
+            history.append(([x.copy() for x in u], [x.copy() for x in p]))
+    return PararealResult(u=u, p=p, rho=rhos, rank=ranks,
+                            history=history, sigma=sigmas)
+
+
+def serial_fine(prob: Problem, c, u0, p0):
+    """Serial fine reference u(t_n) = F^n [u0, p0], n = 0..N (Sec. 6: the
+    reference solution is computed serially with the fine propagator)."""
+    cf = np.asarray(c, dtype=np.float64)
+    c2 = cf * cf
+    us = [np.array(u0, dtype=np.float64)]
+    ps = [np.array(p0, dtype=np.float64)]
+    for _ in range(prob.N):
+        a, b = propagate(us[-1], ps[-1], c2, prob.dt_fine, prob.dx_fine,
+                         prob.m_fine)
+        us.append(a)
+        ps.append(b)
+    return us, ps
+
+
+# ---------------------------------------------------------------------------
+# Error measures (Sec. 6 preamble)
+# ---------------------------------------------------------------------------
+def energy_error(u, p, u_ref, p_ref, c, dx, order=4):
+    """sqrt(E([u - u_ref, p - p_ref]) / E([u_ref, p_ref])) on the fine grid."""
+    e = energy(u - u_ref, p - p_ref, c, dx, order)
+    e0 = energy(u_ref, p_ref, c, dx, order)
+    return math.sqrt(e / e0) if e0 > 0 else math.sqrt(e)
+
+
+def l2_error(u, u_ref):
+    """||u - u_ref||_2 / ||u_ref||_2 of the displacement component."""
+    n0 = np.linalg.norm(u_ref)
+    return float(np.linalg.norm(u - u_ref) / n0) if n0 > 0 else \
+        float(np.linalg.norm(u - u_ref))

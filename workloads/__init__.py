@@ -1,0 +1,159 @@
+"""Seeded synthetic inputs shared by the oracle-side and the HIP-side tests
+and by the benchmark.
+
+This module holds no arithmetic of the method: it only builds the medium
+c(x), the initial state (u0, p0) on the fine grid and the discretisation
+parameters of each workload, in float64, deterministically.
+
+Workloads (fine grid / coarse grid, unit periodic box):
+
+* ``wave1d``  1D, 256 / 64 points, c = 1 + 0.2 sin(2 pi x),
+  u0 = exp(-(x - 0.5)^2 / 0.05^2), p0 = 0, T = 1, N = 16, dt/dx = 0.5
+  (m_F = 32), coarse step 4x the fine one (m_C = 8), K = 6, FP64,
+  tol 1e-14.
+* ``disc2d``  2D, 512^2 / 128^2, c = 1 with c = 2 inside the open disc of
+  radius 0.2 centred at (0.5, 0.5), u0 = Gaussian pulse of standard
+  deviation 0.03 at (0.3, 0.5), p0 = 0, T = 2, N = 64, Courant number
+  c_max dt/dx = 0.5 (m_F = 64, m_C = 16), K = 8, FP32 state, tol 1e-13.
+* ``layers3d`` 3D, 256^3 / 64^3, c(z) piecewise constant 1.0 / 1.5 / 2.2 /
+  3.0 on four equal layers, times (1 + 0.05 eta) with eta ~ U[-1, 1] i.i.d.
+  per node (seed 0), Gaussian pulse sigma = 0.04 at the centre, T = 1.5,
+  N = 32, Courant number <= 0.5 with m_F a multiple of 4 (m_F = 76,
+  m_C = 19), K = 6, FP32 compensated state, tol 1e-13.
+
+``scaled(name, ...)`` gives the same recipe on smaller grids / fewer slices
+for tests that must finish in seconds.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    shape: tuple            # fine grid, numpy order (x last)
+    ratio: int
+    T: float
+    N: int
+    m_fine: int
+    m_coarse: int
+    K: int
+    tol: float
+    grad_order: int
+    dtype: str              # "f64" or "f32"
+    compensated: bool
+    c: np.ndarray
+    u0: np.ndarray
+    p0: np.ndarray
+
+    @property
+    def dim(self):
+        return len(self.shape)
+
+    @property
+    def coarse_shape(self):
+        return tuple(n // self.ratio for n in self.shape)
+
+    @property
+    def npts(self):
+        return int(np.prod(self.shape))
+
+    def updates_per_sweep(self):
+        """Fine point-updates of one F sweep over all slices."""
+        return self.N * self.m_fine * self.npts
+
+
+def _axes(shape):
+    """Node coordinates j/n on [0,1) per numpy axis."""
+    return np.meshgrid(*[np.arange(n) / n for n in shape], indexing="ij")
+
+
+def _steps_for_courant(c_max, n, dt_com, courant=0.5, multiple=4):
+    """Smallest m (a multiple of `multiple`) with c_max (dt_com/m) n <= courant."""
+    m = math.ceil(c_max * dt_com * n / courant - 1e-12)
+    return multiple * math.ceil(m / multiple)
+
+
+def wave1d(n=256, ratio=4, N=16, K=6):
+    x = np.arange(n) / n
+    c = 1.0 + 0.2 * np.sin(2 * np.pi * x)
+    u0 = np.exp(-(x - 0.5) ** 2 / 0.05 ** 2)
+    p0 = np.zeros(n)
+    T = 1.0
+    # dt_fine / dx_fine = 0.5 -> m_F = (T/N) / (0.5/n)
+    m_f = int(round((T / N) * n / 0.5))
+    return Workload("wave1d", (n,), ratio, T, N, m_f, m_f // 4, K, 1e-14, 4,
+                    "f64", False, c, u0, p0)
+
+
+def disc2d(n=512, ratio=4, N=64, K=8, T=2.0, dtype="f32", compensated=True):
+    Y, X = _axes((n, n))
+    r2 = (X - 0.5) ** 2 + (Y - 0.5) ** 2
+    c = np.where(r2 < 0.2 ** 2, 2.0, 1.0)
+    s = 0.03
+    u0 = np.exp(-((X - 0.3) ** 2 + (Y - 0.5) ** 2) / (2 * s * s))
+    p0 = np.zeros((n, n))
+    m_f = _steps_for_courant(2.0, n, T / N)
+    return Workload("disc2d", (n, n), ratio, T, N, m_f, m_f // 4, K, 1e-13, 4,
+                    dtype, compensated, c, u0, p0)
+
+
+def layers3d(n=256, ratio=4, N=32, K=6, T=1.5, dtype="f32",
+             compensated=True):
+    Z, Y, X = _axes((n, n, n))
+    base = np.select([Z < 0.25, Z < 0.5, Z < 0.75], [1.0, 1.5, 2.2], 3.0)
+    eta = np.random.default_rng(0).uniform(-1.0, 1.0, size=(n, n, n))
+    c = base * (1.0 + 0.05 * eta)
+    s = 0.04
+    u0 = np.exp(-((X - 0.5) ** 2 + (Y - 0.5) ** 2 + (Z - 0.5) ** 2)
+                / (2 * s * s))
+    p0 = np.zeros((n, n, n))
+    m_f = _steps_for_courant(3.0 * 1.05, n, T / N)
+    return Workload("layers3d", (n, n, n), ratio, T, N, m_f, m_f // 4, K,
+                    1e-13, 4, dtype, compensated, c, u0, p0)
+
+
+def smooth_random_field(shape, corr, seed):
+    """Unit-variance periodic Gaussian random field with covariance
+    exp(-r^2 / (2 corr^2)), synthesised spectrally on the given grid."""
+    rng = np.random.default_rng(seed)
+    white = rng.standard_normal(shape)
+    k2 = np.zeros(shape)
+    for ax, n in enumerate(shape):
+        k = 2 * np.pi * np.fft.fftfreq(n, d=1.0 / n)
+        shp = [1] * len(shape)
+        shp[ax] = -1
+        k2 = k2 + k.reshape(shp) ** 2
+    filt = np.exp(-0.25 * corr * corr * k2)
+    g = np.fft.ifftn(np.fft.fftn(white) * filt).real
+    g -= g.mean()
+    sd = g.std()
+    return g / sd if sd > 0 else g
+
+
+def grf2d(n=64, ratio=4, N=8, K=3, T=0.25, seed=0, dtype="f32",
+          compensated=True):
+    """Smooth random medium c = exp(0.3 g), g a unit GRF of correlation
+    length 0.1, with a random Gaussian pulse (the batched-problem recipe)."""
+    g = smooth_random_field((n, n), 0.1, 1000 + seed)
+    c = np.exp(0.3 * g)
+    rng = np.random.default_rng(2000 + seed)
+    x0, y0 = rng.uniform(0, 1, size=2)
+    s = rng.uniform(0.02, 0.05)
+    Y, X = _axes((n, n))
+    dxp = (X - x0 + 0.5) % 1.0 - 0.5
+    dyp = (Y - y0 + 0.5) % 1.0 - 0.5
+    u0 = np.exp(-(dxp ** 2 + dyp ** 2) / (2 * s * s))
+    p0 = np.zeros((n, n))
+    m_f = _steps_for_courant(float(c.max()), n, T / N)
+    return Workload("grf2d", (n, n), ratio, T, N, m_f, m_f // 4, K, 1e-13, 4,
+                    dtype, compensated, c, u0, p0)
+
+
+BY_NAME = {"wave1d": wave1d, "disc2d": disc2d, "layers3d": layers3d,
+           "grf2d": grf2d}
