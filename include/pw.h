@@ -1,0 +1,221 @@
+/*
+ * pw.h -- C ABI of the MI355X (gfx950) implementation of the stabilised
+ * parareal-like method for the second-order wave equation of
+ * H. Nguyen and R. Tsai, "A stable parareal-like method for the second
+ * order wave equation" (arXiv 1905.00473).
+ *
+ * Problem (eq. (1)): u_tt = c(x)^2 Lap u on the periodic box [0,1)^d,
+ * d = 1, 2, 3, with u(.,0) = u0 and u_t(.,0) = p0.  The state of a wave
+ * field is the pair [u, p] with p = u_t.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Grids (Sec. 3.1): the fine grid has n_fine[a] points on axis a
+ *   (a = 0: x, 1: y, 2: z; unused axes are 1), spacing dx = 1 / n_fine[0]
+ *   on every axis (cubic cells; n_fine[a] * dx is the box length along a).
+ *   The coarse grid has n_fine[a] / ratio points; coarse node J is fine
+ *   node ratio * J on every axis.
+ * - A field is stored x-fastest: element (x, y, z) at x + nx (y + ny z).
+ *   A "state" is a u field followed by a p field when it is stored in one
+ *   block (coarse FP64 state columns); otherwise u and p are separate
+ *   arrays of fields.  Batches of fields are contiguous (field stride =
+ *   number of grid points).
+ * - State dtype: PW_F64 (double) or PW_F32 (float), chosen per problem.
+ *   Energy components, singular vectors, residuals and energies are always
+ *   double.
+ * - Energy-component column (eqs. matrixF / matrixG): rows
+ *   [d_x U ; d_y U ; (d_z U) ; P / c] on the coarse grid, each block
+ *   x-fastest, length (d+1) * n_coarse_points.  Columns are stored
+ *   column-major (column j at offset j * rows).
+ * - Pointers: arguments named *_dev are device pointers (hipMalloc'd or
+ *   torch CUDA tensors) owned by the caller and must stay valid until the
+ *   call's work on the context stream has finished; arguments named *_host
+ *   are host pointers read or written synchronously.  The library never
+ *   frees caller memory.  Device pointers must be 16-byte aligned.
+ * - Streams: every call enqueues its kernels on the context's stream and
+ *   returns without waiting unless stated otherwise.  Calls that return
+ *   host data synchronise the stream first.
+ * - Errors: every call returns a pw_status <= 0.  pw_last_error() gives a
+ *   message for the last failing call on the calling thread.  No C++
+ *   exception crosses the ABI.  A context is not thread-safe.
+ */
+#ifndef PW_H
+#define PW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PW_OK = 0,
+  PW_EINVAL = -1,      /* bad argument or size                                */
+  PW_EUNSTABLE = -2,   /* c_max dt/dx >= 1/sqrt(d): velocity Verlet unstable  */
+  PW_ENOMEM = -3,      /* device allocation failed                            */
+  PW_EHIP = -4,        /* a HIP runtime call failed (message has the reason)  */
+  PW_ESTATE = -5,      /* call order violated (e.g. run before set_initial)   */
+  PW_ENUMERIC = -6     /* non-finite value or breakdown in the corrector      */
+} pw_status;
+
+typedef enum { PW_F32 = 0, PW_F64 = 1 } pw_dtype;
+
+/* which propagator (Sec. 3.1) */
+typedef enum { PW_FINE = 0, PW_COARSE = 1 } pw_grid;
+
+/*
+ * Discretisation of one problem (the parameter columns of the Sec. 6
+ * tables).  dt_com = T / n_slices; the fine propagator F takes m_fine
+ * velocity-Verlet steps of dt_com / m_fine on the fine grid, the coarse
+ * propagator C takes m_coarse steps of dt_com / m_coarse on the coarse
+ * grid with the pointwise coarse medium c(ratio J dx).
+ */
+typedef struct {
+  int dim;             /* 1, 2 or 3                                           */
+  int n_fine[3];       /* fine points per axis (x, y, z); unused axes = 1     */
+  int ratio;           /* coarse spacing / fine spacing (>= 1, divides n)    */
+  double T;            /* final time                                         */
+  int n_slices;        /* N coupling intervals                               */
+  int m_fine;          /* fine steps per interval                            */
+  int m_coarse;        /* coarse steps per interval                          */
+  int grad_order;      /* order of the central gradient nabla_h: 2 or 4      */
+  double svd_tol;      /* relative rank tolerance of Algorithm 1 (> 0)       */
+  int state_dtype;     /* pw_dtype of u, p                                   */
+  int compensated;     /* FP32 only: compensated (Kahan) accumulation in F/C */
+  int max_iters;       /* largest K that pw_run will be asked for (sizes the
+                          corrector bases: rank <= max_iters * n_slices)     */
+} pw_problem;
+
+typedef struct pw_ctx pw_ctx;
+
+/* Create a context holding n_problems problems; all device buffers are
+ * allocated here.  stream is a hipStream_t (NULL = default stream).
+ * Returns PW_EINVAL for inconsistent sizes, PW_ENOMEM if allocation fails. */
+pw_status pw_create(const pw_problem* probs, int n_problems, void* stream,
+                    pw_ctx** out);
+
+/* Release every device buffer of the context (synchronises first). */
+pw_status pw_destroy(pw_ctx* ctx);
+
+/* Message of the last failing call on this thread (valid until the next
+ * failing call on the thread). */
+const char* pw_last_error(void);
+
+/* Number of problems / library version string. */
+int pw_num_problems(const pw_ctx* ctx);
+const char* pw_version(void);
+
+/* Set the medium c(x) > 0 of problem `prob` from a double field on the
+ * fine grid (eq. (1); the coarse propagator samples it pointwise, Sec.
+ * 3.1).  Copies; returns PW_EUNSTABLE if c_max * dt / dx >= 1/sqrt(d) on
+ * either grid.  on_device: 1 if c is a device pointer, 0 for host.       */
+pw_status pw_set_medium(pw_ctx* ctx, int prob, const double* c,
+                        int on_device);
+
+/* Set the initial state u0, p0 (double fields on the fine grid, eq. (1)),
+ * converted to the state dtype.  Resets the iteration (k = 0).          */
+pw_status pw_set_initial(pw_ctx* ctx, int prob, const double* u0,
+                         const double* p0, int on_device);
+
+/*
+ * Algorithm 3 (eq. thetarelation): the coarse initialisation
+ * u^1_n = I C R u^1_{n-1} followed by K iterations of: F on all slices in
+ * one batched launch, the data matrices F^k = [Lambda R v_n],
+ * G^k = [Lambda C R u^k_{n-1}], the incremental Procrustes SVD of
+ * Algorithm 1, the corrected sweep over n and the update
+ * u^{k+1}_n = v_n + I delta_n.  K <= max_iters.  Runs on the context
+ * stream; synchronises once per iteration to read the new rank.  Each
+ * call restarts from u0 (the iteration count and corrector are reset).
+ */
+pw_status pw_run(pw_ctx* ctx, int prob, int K);
+
+/* Wait for all work on the context stream. */
+pw_status pw_sync(pw_ctx* ctx);
+
+/* Copy the current iterate u^k_n, n = 0..N (after pw_run: k = K+1) into
+ * caller buffers of n_points elements of the state dtype.  on_device
+ * selects device or host destination; host copies are synchronous.     */
+pw_status pw_get_state(pw_ctx* ctx, int prob, int n, void* u, void* p,
+                       int on_device);
+
+/* Per-iteration diagnostics of the last pw_run, k = 1..K: relative
+ * Procrustes residual rho_k = ||F^k - Omega^k G^k||_F / ||F^k||_F
+ * (Sec. 6.4) and the rank of Omega^k (Algorithm 1).  cap = array length;
+ * returns the number of iterations in *count.  Host output, synchronous. */
+pw_status pw_get_residuals(pw_ctx* ctx, int prob, double* rho_host,
+                           int* rank_host, int cap, int* count);
+
+/* Serial fine reference u(t_n) = F^n [u0, p0] (Sec. 6: computed serially
+ * with the fine propagator) written to caller device buffers u_dev, p_dev
+ * of n_points elements of the state dtype.  0 <= n <= N.               */
+pw_status pw_serial_fine(pw_ctx* ctx, int prob, int n, void* u_dev,
+                         void* p_dev);
+
+/* ------------------------------------------------------------------------
+ * Building blocks of the path, exposed for parity checks.  All pointers
+ * are device pointers; n_states fields are processed in one launch.
+ * ------------------------------------------------------------------------ */
+
+/* F (grid = PW_FINE) or C (PW_COARSE) of problem `prob` applied to
+ * n_states states: u_out[s], p_out[s] = prop(u_in[s], p_in[s]) in the
+ * state dtype (Sec. 3.1).  Inputs and outputs may not overlap.          */
+pw_status pw_propagate(pw_ctx* ctx, int prob, int grid, const void* u_in,
+                       const void* p_in, void* u_out, void* p_out,
+                       int n_states);
+
+/* Energy components Lambda[U, P] (eqs. matrixF / matrixG) of n_states
+ * states given on the fine grid (grid = PW_FINE: restricted first, i.e.
+ * Lambda R) or on the coarse grid (PW_COARSE), in the state dtype, into
+ * out (double, column-major, rows = (d+1) * n_coarse_points).           */
+pw_status pw_energy_components(pw_ctx* ctx, int prob, int grid,
+                               const void* u, const void* p,
+                               double* out, int n_states);
+
+/* Trigonometric interpolation and update (Algorithm 3, last line):
+ * u_out[s] = v[s] + I(du[s]), p_out[s] = vp[s] + I(dp[s]), with du, dp
+ * double coarse fields rounded to the state dtype before I.            */
+pw_status pw_interp_add(pw_ctx* ctx, int prob, const double* du,
+                        const double* dp, const void* v, const void* vp,
+                        void* u_out, void* p_out, int n_states);
+
+/* Lambda^dag displacement part (Algorithm 2, eq. gradient2coordinate):
+ * w[s] = real(ifft(W)), W(xi) = -i xi.fft(q[s]) / |xi|^2, W(0) = sums[s];
+ * q is n_states columns of d gradient blocks (double, d * n_coarse
+ * rows each), w is n_states coarse double fields.                      */
+pw_status pw_grad2func(pw_ctx* ctx, int prob, const double* q,
+                       const double* sums, double* w, int n_states);
+
+/* Algorithm 1 on the context's corrector of problem `prob`: given data
+ * matrices F, G (double, rows x n_cols, column-major, device) update the
+ * truncated SVD U S V^T of sum F G^T.  reset != 0 starts from an empty
+ * SVD.  The new rank is returned in *rank (synchronises).               */
+pw_status pw_update_svd(pw_ctx* ctx, int prob, const double* F,
+                        const double* G, int n_cols, int reset, int* rank);
+
+/* Copy the corrector of problem `prob` (U: rows x rank, S: rank,
+ * V: rows x rank, double, column-major) to caller device buffers sized
+ * for `cap` columns; PW_EINVAL if rank > cap.  With U, S and V all NULL
+ * only the rank is returned.  Synchronises.                             */
+pw_status pw_get_corrector(pw_ctx* ctx, int prob, double* U, double* S,
+                           double* V, int cap, int* rank);
+
+/* Discrete wave energy (eq. discrete-wave-energy) on the fine grid with
+ * the fine medium and the context's gradient order, of the difference
+ * [u - u_ref, p - p_ref] and of [u_ref, p_ref], in double (synchronous;
+ * results to host).  u_ref may be NULL (then the energy of [u, p]).     */
+pw_status pw_energy(pw_ctx* ctx, int prob, const void* u, const void* p,
+                    const void* u_ref, const void* p_ref, double* e_diff,
+                    double* e_ref);
+
+/* Per-phase device time of the last pw_run in milliseconds, measured with
+ * HIP events on the context stream: [0] parallel fine+coarse propagation,
+ * [1] creating the corrector (data matrices + Algorithm 1), [2] corrected
+ * sweep and update, [3] whole run.  Host output, synchronous.           */
+pw_status pw_get_timings(pw_ctx* ctx, int prob, double* ms_host, int cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PW_H */

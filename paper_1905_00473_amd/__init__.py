@@ -1,0 +1,326 @@
+"""MI355X (gfx950) implementation of the stabilised parareal-like method for
+the second-order wave equation (Nguyen & Tsai, arXiv 1905.00473).
+
+Thin Python binding over the C ABI of ``libpwave.so`` (include/pw.h):
+argument marshalling only.  Every step of the method runs in the HIP
+kernels of the library; torch is used for device memory and the stream.
+There is no CPU fallback: if the library is missing or fails to load, every
+call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["Problem", "Solver", "lib", "PwError", "LIB_PATH", "F32", "F64",
+           "FINE", "COARSE"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                        "libpwave.so")
+F32, F64 = 0, 1
+FINE, COARSE = 0, 1
+
+_STATUS = {0: "PW_OK", -1: "PW_EINVAL", -2: "PW_EUNSTABLE", -3: "PW_ENOMEM",
+           -4: "PW_EHIP", -5: "PW_ESTATE", -6: "PW_ENUMERIC"}
+
+
+class PwError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    """Mirror of pw_problem (include/pw.h)."""
+    _fields_ = [
+        ("dim", ctypes.c_int),
+        ("n_fine", ctypes.c_int * 3),
+        ("ratio", ctypes.c_int),
+        ("T", ctypes.c_double),
+        ("n_slices", ctypes.c_int),
+        ("m_fine", ctypes.c_int),
+        ("m_coarse", ctypes.c_int),
+        ("grad_order", ctypes.c_int),
+        ("svd_tol", ctypes.c_double),
+        ("state_dtype", ctypes.c_int),
+        ("compensated", ctypes.c_int),
+        ("max_iters", ctypes.c_int),
+    ]
+
+    @classmethod
+    def make(cls, shape, ratio, T, N, m_fine, m_coarse, grad_order=4,
+             tol=1e-14, dtype="f64", compensated=False, max_iters=8):
+        """shape: fine grid in numpy order (x last)."""
+        p = cls()
+        p.dim = len(shape)
+        xyz = list(reversed(shape)) + [1] * (3 - len(shape))
+        for a in range(3):
+            p.n_fine[a] = int(xyz[a])
+        p.ratio = int(ratio)
+        p.T = float(T)
+        p.n_slices = int(N)
+        p.m_fine = int(m_fine)
+        p.m_coarse = int(m_coarse)
+        p.grad_order = int(grad_order)
+        p.svd_tol = float(tol)
+        p.state_dtype = F64 if dtype in ("f64", "float64", F64) else F32
+        p.compensated = int(bool(compensated))
+        p.max_iters = int(max_iters)
+        return p
+
+
+_LIB = None
+
+_SIGS = {
+    "pw_create": [ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_void_p,
+                  ctypes.POINTER(ctypes.c_void_p)],
+    "pw_destroy": [ctypes.c_void_p],
+    "pw_sync": [ctypes.c_void_p],
+    "pw_set_medium": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                      ctypes.c_int],
+    "pw_set_initial": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                       ctypes.c_void_p, ctypes.c_int],
+    "pw_run": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int],
+    "pw_get_state": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
+    "pw_get_residuals": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                         ctypes.c_void_p, ctypes.c_int,
+                         ctypes.POINTER(ctypes.c_int)],
+    "pw_serial_fine": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                       ctypes.c_void_p, ctypes.c_void_p],
+    "pw_propagate": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                     ctypes.c_void_p, ctypes.c_int],
+    "pw_energy_components": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                             ctypes.c_void_p, ctypes.c_void_p,
+                             ctypes.c_void_p, ctypes.c_int],
+    "pw_interp_add": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
+    "pw_grad2func": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
+    "pw_update_svd": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                      ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                      ctypes.POINTER(ctypes.c_int)],
+    "pw_get_corrector": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                         ctypes.POINTER(ctypes.c_int)],
+    "pw_energy": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.POINTER(ctypes.c_double),
+                  ctypes.POINTER(ctypes.c_double)],
+    "pw_get_timings": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                       ctypes.c_int],
+}
+
+#: every symbol include/pw.h declares
+SYMBOLS = sorted(list(_SIGS) + ["pw_last_error", "pw_version",
+                                "pw_num_problems"])
+
+
+def lib():
+    """Load libpwave.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -m paper_1905_00473_amd.build` (no fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.pw_last_error.restype = ctypes.c_char_p
+        L.pw_last_error.argtypes = []
+        L.pw_version.restype = ctypes.c_char_p
+        L.pw_version.argtypes = []
+        L.pw_num_problems.restype = ctypes.c_int
+        L.pw_num_problems.argtypes = [ctypes.c_void_p]
+        _LIB = L
+    return _LIB
+
+
+def _check(st):
+    if st != 0:
+        raise PwError(st, lib().pw_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Solver:
+    """A context of one or more wave problems on the current CUDA (HIP)
+    device and stream."""
+
+    def __init__(self, problems):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("pwave needs a GPU (torch.cuda.is_available() "
+                               "is False)")
+        if isinstance(problems, Problem):
+            problems = [problems]
+        self.problems = list(problems)
+        arr = (Problem * len(self.problems))(*self.problems)
+        self.stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(lib().pw_create(arr, len(self.problems),
+                               ctypes.c_void_p(self.stream.cuda_stream),
+                               ctypes.byref(h)))
+        self._h = h
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pw_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- helpers ------------------------------------------------------------
+    def dtype(self, prob=0):
+        import torch
+        return torch.float64 if self.problems[prob].state_dtype == F64 \
+            else torch.float32
+
+    def shape(self, prob=0):
+        p = self.problems[prob]
+        return tuple(reversed([p.n_fine[a] for a in range(p.dim)]))
+
+    def coarse_shape(self, prob=0):
+        p = self.problems[prob]
+        return tuple(n // p.ratio for n in self.shape(prob))
+
+    def rows(self, prob=0):
+        import math
+        p = self.problems[prob]
+        return (p.dim + 1) * math.prod(self.coarse_shape(prob))
+
+    def _dev(self, x, dtype=None):
+        import torch
+        t = torch.as_tensor(x)
+        return t.to(device="cuda", dtype=dtype or torch.float64).contiguous()
+
+    # -- the method -----------------------------------------------------------
+    def set_medium(self, c, prob=0):
+        import torch
+        t = self._dev(c, torch.float64)
+        _check(lib().pw_set_medium(self._h, prob, _ptr(t), 1))
+
+    def set_initial(self, u0, p0, prob=0):
+        import torch
+        a, b = self._dev(u0, torch.float64), self._dev(p0, torch.float64)
+        _check(lib().pw_set_initial(self._h, prob, _ptr(a), _ptr(b), 1))
+
+    def run(self, K, prob=0):
+        _check(lib().pw_run(self._h, prob, int(K)))
+
+    def sync(self):
+        _check(lib().pw_sync(self._h))
+
+    def state(self, n, prob=0):
+        import torch
+        u = torch.empty(self.shape(prob), dtype=self.dtype(prob), device="cuda")
+        p = torch.empty_like(u)
+        _check(lib().pw_get_state(self._h, prob, int(n), _ptr(u), _ptr(p), 1))
+        return u, p
+
+    def residuals(self, prob=0, cap=256):
+        rho = (ctypes.c_double * cap)()
+        rk = (ctypes.c_int * cap)()
+        cnt = ctypes.c_int()
+        _check(lib().pw_get_residuals(self._h, prob, rho, rk, cap,
+                                      ctypes.byref(cnt)))
+        return list(rho[:cnt.value]), list(rk[:cnt.value])
+
+    def serial_fine(self, n, prob=0):
+        import torch
+        u = torch.empty(self.shape(prob), dtype=self.dtype(prob), device="cuda")
+        p = torch.empty_like(u)
+        _check(lib().pw_serial_fine(self._h, prob, int(n), _ptr(u), _ptr(p)))
+        return u, p
+
+    def timings(self, prob=0):
+        ms = (ctypes.c_double * 4)()
+        _check(lib().pw_get_timings(self._h, prob, ms, 4))
+        return dict(parallel=ms[0], corrector=ms[1], sweep=ms[2], total=ms[3])
+
+    def energy(self, u, p, u_ref=None, p_ref=None, prob=0):
+        ed, er = ctypes.c_double(), ctypes.c_double()
+        _check(lib().pw_energy(self._h, prob, _ptr(u), _ptr(p), _ptr(u_ref),
+                               _ptr(p_ref), ctypes.byref(ed),
+                               ctypes.byref(er)))
+        return ed.value, er.value
+
+    # -- building blocks (parity checks) --------------------------------------
+    def propagate(self, u, p, grid=FINE, prob=0):
+        """u, p: (n_states, *grid) tensors of the state dtype."""
+        import torch
+        uo, po = torch.empty_like(u), torch.empty_like(p)
+        _check(lib().pw_propagate(self._h, prob, grid, _ptr(u), _ptr(p),
+                                  _ptr(uo), _ptr(po), int(u.shape[0])))
+        return uo, po
+
+    def energy_components(self, u, p, grid=FINE, prob=0):
+        import torch
+        n = int(u.shape[0])
+        out = torch.empty((n, self.rows(prob)), dtype=torch.float64,
+                          device="cuda")
+        _check(lib().pw_energy_components(self._h, prob, grid, _ptr(u),
+                                          _ptr(p), _ptr(out), n))
+        return out
+
+    def interp_add(self, du, dp, v=None, vp=None, prob=0):
+        import torch
+        n = int(du.shape[0])
+        shp = (n,) + self.shape(prob)
+        uo = torch.empty(shp, dtype=self.dtype(prob), device="cuda")
+        po = torch.empty_like(uo)
+        _check(lib().pw_interp_add(self._h, prob, _ptr(du), _ptr(dp), _ptr(v),
+                                   _ptr(vp), _ptr(uo), _ptr(po), n))
+        return uo, po
+
+    def grad2func(self, q, sums=None, prob=0):
+        import torch
+        n = int(q.shape[0])
+        w = torch.empty((n,) + self.coarse_shape(prob), dtype=torch.float64,
+                        device="cuda")
+        _check(lib().pw_grad2func(self._h, prob, _ptr(q), _ptr(sums), _ptr(w),
+                                  n))
+        return w
+
+    def update_svd(self, F, G, reset=False, prob=0):
+        """F, G: (n_cols, rows) float64 device tensors (column j = row j)."""
+        rk = ctypes.c_int()
+        _check(lib().pw_update_svd(self._h, prob, _ptr(F), _ptr(G),
+                                   int(F.shape[0]), int(bool(reset)),
+                                   ctypes.byref(rk)))
+        return rk.value
+
+    def corrector(self, prob=0):
+        """(U, S, V) of the current corrector: U, V as (rank, rows) tensors
+        (row j = singular vector j)."""
+        import torch
+        rk = ctypes.c_int()
+        _check(lib().pw_get_corrector(self._h, prob, None, None, None, 0,
+                                      ctypes.byref(rk)))
+        r = rk.value
+        rows = self.rows(prob)
+        U = torch.empty((max(r, 1), rows), dtype=torch.float64, device="cuda")
+        V = torch.empty_like(U)
+        S = torch.empty((max(r, 1),), dtype=torch.float64, device="cuda")
+        _check(lib().pw_get_corrector(self._h, prob, _ptr(U), _ptr(S), _ptr(V),
+                                      r, ctypes.byref(rk)))
+        return U[:r], S[:r], V[:r]

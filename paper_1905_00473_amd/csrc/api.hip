@@ -1,0 +1,952 @@
+// C ABI of libpwave: context, device memory plan and the driver of
+// Algorithm 3 (eq. thetarelation) of Nguyen & Tsai.
+//
+// One iteration on the device:
+//  1. parallel phase: v_n = F u^k_{n-1} for all n in one batched launch
+//     sequence; U_n = C R u^k_{n-1} batched on the coarse grid;
+//  2. corrector: data matrices F^k = [Lambda R v_n], G^k = [Lambda U_n],
+//     Algorithm 1 (projections on the FP64 matrix cores, Gram-eigenvector
+//     orthonormalisation, one-sided Jacobi SVD of the core, basis rotation);
+//  3. corrected sweep.  By linearity of C, Lambda, Omega and Lambda^dag the
+//     serial loop of Algorithm 3 is carried in the coordinates of the
+//     corrector: with delta_n = u^{k+1}_n - v_n on the coarse grid,
+//        Delta_n = C R u^{k+1}_{n-1} - C R u^k_{n-1} = a_n + C delta_{n-1},
+//        a_n = C (R v_{n-1} - R u^k_{n-1}),
+//        delta_n = Lambda^dag_u Omega Lambda Delta_n (+ the mean term)
+//                = E t_n,  t_n = P^T Delta_n,
+//     where E = [Lambda^dag_u U~ , 1/Nc ; c U~_p , 0] and
+//     P = [Lambda^T V~ , 1_u] (Lambda^T = [-div_h ; 1/c]).  Hence
+//        t_n = P^T a_n + (P^T C E) t_{n-1},
+//     an (r+1)-dimensional recurrence; the a_n and C E are batched coarse
+//     propagations and the products are matrix-core GEMMs.  Slices whose
+//     inputs did not change get a_n = 0 and t_n = 0 exactly, so the
+//     exactness of the first k slices after k iterations is kept.
+//  4. u^{k+1}_n = v_n + I(delta_n) for all n (R I = 1).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pw_internal.h"
+
+namespace pw {
+
+void fail(pw_status st, const std::string& msg) { throw Error{st, msg}; }
+
+void check_hip(hipError_t e, const char* what, const char* file, int line) {
+  if (e == hipSuccess) return;
+  char buf[512];
+  snprintf(buf, sizeof(buf), "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+  fail(e == hipErrorOutOfMemory ? PW_ENOMEM : PW_EHIP, buf);
+}
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Buffers {
+  std::vector<void*> ptrs;
+  void* get(size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      char buf[160];
+      snprintf(buf, sizeof(buf), "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+      fail(PW_ENOMEM, buf);
+    }
+    ptrs.push_back(p);
+    return p;
+  }
+  template <typename T>
+  T* get_n(long long n) {
+    return (T*)get(sizeof(T) * (size_t)std::max(1LL, n));
+  }
+  ~Buffers() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+};
+
+struct Prob {
+  pw_problem P{};
+  Grid gf, gc;
+  int ratio = 1, N = 1, mF = 1, mC = 1, order = 4;
+  double hF = 0, hC = 0, tol = 1e-14;
+  bool f64 = true, comp = false;
+  long long Nf = 0, Nc = 0, rows = 0;
+  int rmax = 0, cap = 0;
+  size_t tsize = 8;
+
+  Buffers mem;
+  // medium
+  double* cf = nullptr;   // fine c
+  double* cc = nullptr;   // coarse c
+  void* c2f = nullptr;    // fine c^2, state dtype
+  void* c2c = nullptr;    // coarse c^2, state dtype
+  double* c2c_d = nullptr;
+  double* itab[3] = {nullptr, nullptr, nullptr};
+  double* dtab[3] = {nullptr, nullptr, nullptr};
+  // fine states (state dtype)
+  void *u = nullptr, *p = nullptr;    // (N+1) fields: u^k_n
+  void *v = nullptr, *vp = nullptr;   // N fields: v_n at index n-1
+  void *fw[2][4] = {{nullptr}};       // fine work sets (u, p, eu, ep), N fields each
+  void *sfa_u = nullptr, *sfa_p = nullptr, *sfb_u = nullptr, *sfb_p = nullptr;  // serial fine
+  // coarse states (state dtype)
+  void *Uc = nullptr, *Ucp = nullptr;  // U_n, N fields
+  void *Rc = nullptr, *Rcp = nullptr;  // restricted inputs, N+1 fields
+  void *cw[2][4] = {{nullptr}};       // coarse work sets, N+1 fields
+  void *du_T = nullptr, *dp_T = nullptr;  // cast corrections, N fields
+  // coarse FP64
+  double* Din = nullptr;   // 2Nc x N
+  double* Acol = nullptr;  // 2Nc x N
+  double* E[2] = {nullptr, nullptr};   // 2Nc x cap
+  double* Vp[2] = {nullptr, nullptr};  // 2Nc x cap
+  double* CE = nullptr;                // 2Nc x (rmax+1)
+  double* dw[2] = {nullptr, nullptr};  // FP64 coarse work, 2Nc x max(rmax+1, N)
+  double* delta = nullptr;             // 2Nc x N
+  // corrector
+  double *Fm = nullptr, *Gm = nullptr;        // rows x N
+  double *Fp = nullptr, *Gp = nullptr;        // rows x N
+  double* Ub[2] = {nullptr, nullptr};         // rows x cap
+  double* Vb[2] = {nullptr, nullptr};
+  double* S = nullptr;                        // cap
+  double *UF = nullptr, *VG = nullptr, *UF2 = nullptr, *VG2 = nullptr;  // cap x N
+  double *RF = nullptr, *RG = nullptr;        // N x N
+  double *Af = nullptr, *Bg = nullptr;        // cap x N
+  double *H = nullptr, *X = nullptr, *Y = nullptr, *sig = nullptr, *Hw = nullptr, *Vw = nullptr;
+  int* counters = nullptr;
+  int* rank_dev = nullptr;
+  double *M = nullptr, *Bn = nullptr, *Tn = nullptr;
+  double* ctmp = nullptr;   // complex DFT scratch
+  double* itmp = nullptr;   // interpolation scratch
+  double* gwork = nullptr;  // split-K partials
+  double* red = nullptr;    // reduction partials
+  double* res = nullptr;    // per-iteration [||F - Omega G||^2, ||F||^2]
+  OrthScratch os;
+  int cur = 0;    // which of the ping-pong corrector buffers is current
+  int r = 0;      // current rank
+  int k_done = 0;
+  bool have_medium = false, have_initial = false;
+  std::vector<int> ranks;
+  double ms[4] = {0, 0, 0, 0};
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+}  // namespace
+}  // namespace pw
+
+struct pw_ctx {
+  hipStream_t stream = nullptr;
+  std::vector<std::unique_ptr<pw::Prob>> probs;
+};
+
+namespace pw {
+namespace {
+
+template <typename T>
+T* tp(void* x) {
+  return reinterpret_cast<T*>(x);
+}
+
+Prob& get_prob(pw_ctx* ctx, int i) {
+  if (!ctx) fail(PW_EINVAL, "null context");
+  if (i < 0 || i >= (int)ctx->probs.size()) fail(PW_EINVAL, "problem index out of range");
+  return *ctx->probs[i];
+}
+
+void validate(const pw_problem& P) {
+  if (P.dim < 1 || P.dim > 3) fail(PW_EINVAL, "dim must be 1, 2 or 3");
+  for (int a = 0; a < 3; ++a) {
+    if (a < P.dim && P.n_fine[a] < 1) fail(PW_EINVAL, "n_fine must be positive");
+    if (a >= P.dim && P.n_fine[a] != 1) fail(PW_EINVAL, "unused axes must have n_fine = 1");
+  }
+  if (P.ratio < 1) fail(PW_EINVAL, "ratio must be >= 1");
+  for (int a = 0; a < P.dim; ++a) {
+    if (P.n_fine[a] % P.ratio) fail(PW_EINVAL, "ratio must divide every n_fine");
+    if (P.n_fine[a] / P.ratio < 5) fail(PW_EINVAL, "coarse grid needs at least 5 points per axis");
+  }
+  if (!(P.T > 0)) fail(PW_EINVAL, "T must be positive");
+  if (P.n_slices < 1 || P.m_fine < 1 || P.m_coarse < 1) fail(PW_EINVAL, "bad slice/step counts");
+  if (P.grad_order != 2 && P.grad_order != 4) fail(PW_EINVAL, "grad_order must be 2 or 4");
+  if (!(P.svd_tol > 0)) fail(PW_EINVAL, "svd_tol must be positive");
+  if (P.state_dtype != PW_F32 && P.state_dtype != PW_F64) fail(PW_EINVAL, "bad state dtype");
+  if (P.compensated && P.state_dtype != PW_F32) fail(PW_EINVAL, "compensation is an FP32 mode");
+  if (P.max_iters < 1) fail(PW_EINVAL, "max_iters must be >= 1");
+  if (P.n_slices > 64) fail(PW_EINVAL, "at most 64 slices per problem");
+}
+
+void setup(Prob& pr, const pw_problem& P) {
+  validate(P);
+  pr.P = P;
+  pr.ratio = P.ratio;
+  pr.N = P.n_slices;
+  pr.mF = P.m_fine;
+  pr.mC = P.m_coarse;
+  pr.order = P.grad_order;
+  pr.tol = P.svd_tol;
+  pr.f64 = P.state_dtype == PW_F64;
+  pr.comp = P.compensated != 0;
+  pr.tsize = pr.f64 ? 8 : 4;
+  pr.gf.dim = pr.gc.dim = P.dim;
+  for (int a = 0; a < 3; ++a) {
+    pr.gf.n[a] = P.n_fine[a];
+    pr.gc.n[a] = a < P.dim ? P.n_fine[a] / P.ratio : 1;
+  }
+  pr.gf.dx = 1.0 / P.n_fine[0];
+  pr.gc.dx = pr.gf.dx * P.ratio;
+  const double dtc = P.T / P.n_slices;
+  pr.hF = dtc / P.m_fine;
+  pr.hC = dtc / P.m_coarse;
+  pr.Nf = pr.gf.npts();
+  pr.Nc = pr.gc.npts();
+  pr.rows = (long long)(P.dim + 1) * pr.Nc;
+  pr.rmax = (int)std::min<long long>((long long)P.max_iters * pr.N, pr.rows);
+  pr.cap = pr.rmax + pr.N + 1;
+  const int N = pr.N;
+  const size_t ts = pr.tsize;
+  Buffers& m = pr.mem;
+  const long long Nf = pr.Nf, Nc = pr.Nc, rows = pr.rows, cap = pr.cap;
+  pr.cf = m.get_n<double>(Nf);
+  pr.cc = m.get_n<double>(Nc);
+  pr.c2f = m.get(ts * Nf);
+  pr.c2c = m.get(ts * Nc);
+  pr.c2c_d = m.get_n<double>(Nc);
+  for (int a = 0; a < P.dim; ++a) {
+    std::vector<double> t = trig_interp_table(pr.gc.n[a], P.ratio);
+    pr.itab[a] = m.get_n<double>((long long)t.size());
+    PW_HIP(hipMemcpy(pr.itab[a], t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice));
+    std::vector<double> d = dft_table(pr.gc.n[a]);
+    pr.dtab[a] = m.get_n<double>((long long)d.size());
+    PW_HIP(hipMemcpy(pr.dtab[a], d.data(), sizeof(double) * d.size(), hipMemcpyHostToDevice));
+  }
+  pr.u = m.get(ts * Nf * (N + 1));
+  pr.p = m.get(ts * Nf * (N + 1));
+  pr.v = m.get(ts * Nf * N);
+  pr.vp = m.get(ts * Nf * N);
+  for (int s = 0; s < 2; ++s)
+    for (int f = 0; f < 4; ++f)
+      pr.fw[s][f] = (f < 2 || pr.comp) ? m.get(ts * Nf * N) : nullptr;
+  pr.sfa_u = m.get(ts * Nf);
+  pr.sfa_p = m.get(ts * Nf);
+  pr.sfb_u = m.get(ts * Nf);
+  pr.sfb_p = m.get(ts * Nf);
+  pr.Uc = m.get(ts * Nc * N);
+  pr.Ucp = m.get(ts * Nc * N);
+  pr.Rc = m.get(ts * Nc * (N + 1));
+  pr.Rcp = m.get(ts * Nc * (N + 1));
+  for (int s = 0; s < 2; ++s)
+    for (int f = 0; f < 4; ++f)
+      pr.cw[s][f] = (f < 2 || pr.comp) ? m.get(ts * Nc * (N + 1)) : nullptr;
+  pr.du_T = m.get(ts * Nc * N);
+  pr.dp_T = m.get(ts * Nc * N);
+  const long long dstates = std::max<long long>(pr.rmax + 1, N);
+  pr.Din = m.get_n<double>(2 * Nc * N);
+  pr.Acol = m.get_n<double>(2 * Nc * N);
+  for (int s = 0; s < 2; ++s) {
+    pr.E[s] = m.get_n<double>(2 * Nc * cap);
+    pr.Vp[s] = m.get_n<double>(2 * Nc * cap);
+    pr.dw[s] = m.get_n<double>(2 * Nc * dstates);
+    pr.Ub[s] = m.get_n<double>(rows * cap);
+    pr.Vb[s] = m.get_n<double>(rows * cap);
+  }
+  pr.CE = m.get_n<double>(2 * Nc * (pr.rmax + 1));
+  pr.delta = m.get_n<double>(2 * Nc * N);
+  pr.Fm = m.get_n<double>(rows * N);
+  pr.Gm = m.get_n<double>(rows * N);
+  pr.Fp = m.get_n<double>(rows * N);
+  pr.Gp = m.get_n<double>(rows * N);
+  pr.S = m.get_n<double>(cap);
+  pr.UF = m.get_n<double>(cap * N);
+  pr.VG = m.get_n<double>(cap * N);
+  pr.UF2 = m.get_n<double>(cap * N);
+  pr.VG2 = m.get_n<double>(cap * N);
+  pr.RF = m.get_n<double>((long long)N * N);
+  pr.RG = m.get_n<double>((long long)N * N);
+  pr.Af = m.get_n<double>(cap * N);
+  pr.Bg = m.get_n<double>(cap * N);
+  pr.H = m.get_n<double>(cap * cap);
+  pr.X = m.get_n<double>(cap * cap);
+  pr.Y = m.get_n<double>(cap * cap);
+  pr.sig = m.get_n<double>(cap);
+  pr.Hw = m.get_n<double>(cap * cap + 2 * cap + 16);
+  pr.Vw = m.get_n<double>(cap * cap);
+  pr.counters = m.get_n<int>(64);
+  pr.rank_dev = m.get_n<int>(4);
+  pr.M = m.get_n<double>((long long)(pr.rmax + 1) * (pr.rmax + 1));
+  pr.Bn = m.get_n<double>((long long)(pr.rmax + 1) * N);
+  pr.Tn = m.get_n<double>((long long)(pr.rmax + 1) * N);
+  const int gcols = std::max(N, 1);
+  pr.ctmp = m.get_n<double>(4LL * P.dim * Nc * gcols);
+  pr.itmp = m.get_n<double>(2LL * (Nf + Nf) * N + 16);
+  // split-K partials: the largest A^T B of the path
+  size_t gw = 0;
+  gw = std::max(gw, gemm_tn_work(rows, (int)cap, N));
+  gw = std::max(gw, gemm_tn_work(rows, N, N));
+  gw = std::max(gw, gemm_tn_work(2 * Nc, pr.rmax + 1, pr.rmax + 1));
+  gw = std::max(gw, gemm_tn_work(2 * Nc, pr.rmax + 1, N));
+  pr.gwork = m.get_n<double>((long long)gw + 16);
+  pr.red = m.get_n<double>(4096);
+  pr.res = m.get_n<double>(2LL * (P.max_iters + 1));
+  pr.os.gram = m.get_n<double>((long long)N * N);
+  pr.os.W = m.get_n<double>((long long)N * N);
+  pr.os.lam = m.get_n<double>(N);
+  pr.os.T = m.get_n<double>((long long)N * N);
+  pr.os.R1 = m.get_n<double>((long long)N * N);
+  pr.os.Q1 = m.get_n<double>(rows * N);
+  pr.os.work = pr.gwork;
+  for (int i = 0; i < 4; ++i) PW_HIP(hipEventCreate(&pr.ev[i]));
+}
+
+// ---------------------------------------------------------------------------
+// typed helpers
+// ---------------------------------------------------------------------------
+template <typename T>
+StateSet<T> fine_work(Prob& pr, int s) {
+  return StateSet<T>{tp<T>(pr.fw[s][0]), tp<T>(pr.fw[s][1]), tp<T>(pr.fw[s][2]),
+                     tp<T>(pr.fw[s][3])};
+}
+template <typename T>
+StateSet<T> coarse_work(Prob& pr, int s) {
+  return StateSet<T>{tp<T>(pr.cw[s][0]), tp<T>(pr.cw[s][1]), tp<T>(pr.cw[s][2]),
+                     tp<T>(pr.cw[s][3])};
+}
+
+template <typename T>
+void prop_fine(Prob& pr, const T* u, const T* p, T* uo, T* po, int n, hipStream_t st) {
+  if (n > pr.N) fail(PW_EINVAL, "too many fine states for one batched propagation");
+  propagate<T>(pr.gf, tp<T>(pr.c2f), u, p, uo, po, pr.Nf, n, pr.mF, (T)pr.hF, pr.comp,
+               fine_work<T>(pr, 0), fine_work<T>(pr, 1), st);
+}
+
+template <typename T>
+void prop_coarse(Prob& pr, const T* u, const T* p, T* uo, T* po, int n, hipStream_t st) {
+  if (n > pr.N + 1) fail(PW_EINVAL, "too many coarse states for one batched propagation");
+  propagate<T>(pr.gc, tp<T>(pr.c2c), u, p, uo, po, pr.Nc, n, pr.mC, (T)pr.hC, pr.comp,
+               coarse_work<T>(pr, 0), coarse_work<T>(pr, 1), st);
+}
+
+// FP64 coarse propagation of state columns [u (Nc) ; p (Nc)] (linear C)
+void prop_coarse_cols(Prob& pr, const double* in, double* out, int ncols, hipStream_t st) {
+  const long long Nc = pr.Nc;
+  StateSet<double> a{pr.dw[0], pr.dw[0] + Nc, nullptr, nullptr};
+  StateSet<double> b{pr.dw[1], pr.dw[1] + Nc, nullptr, nullptr};
+  propagate<double>(pr.gc, pr.c2c_d, in, in + Nc, out, out + Nc, 2 * Nc, ncols, pr.mC, pr.hC,
+                    false, a, b, st);
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 1 on the device (see linalg.hip for the pieces)
+// ---------------------------------------------------------------------------
+void sync_rank(Prob& pr, hipStream_t st, int* out) {
+  int h = 0;
+  PW_HIP(hipMemcpyAsync(&h, pr.rank_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+  PW_HIP(hipStreamSynchronize(st));
+  *out = h;
+}
+
+__global__ void k_add_inplace(double* a, const double* b, long long n) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) a[t] += b[t];
+}
+
+void add_inplace(double* a, const double* b, long long n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_add_inplace, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, n);
+  PW_LAUNCH_CHECK();
+}
+
+// remove the components along basis B (rows x r) from X (rows x n) twice,
+// accumulating the coefficients in C (r x n): X <- X - B (B^T X)
+void project_out(Prob& pr, long long rows, int r, int n, const double* B, double* X, double* C,
+                 double* C2, hipStream_t st) {
+  gemm_tn(rows, r, n, 1.0, B, rows, X, rows, 0.0, C, r, pr.gwork, st);
+  gemm_nn(rows, n, r, -1.0, B, rows, C, r, 1.0, X, rows, st);
+  gemm_tn(rows, r, n, 1.0, B, rows, X, rows, 0.0, C2, r, pr.gwork, st);
+  gemm_nn(rows, n, r, -1.0, B, rows, C2, r, 1.0, X, rows, st);
+  // C += C2 (both r x n, contiguous)
+  add_inplace(C, C2, (long long)r * n, st);
+}
+
+void update_svd_dev(Prob& pr, const double* F, const double* G, int ncols, hipStream_t st) {
+  const long long rows = pr.rows;
+  const int r = pr.r;
+  const int cur = pr.cur, nxt = 1 - pr.cur;
+  if (r + ncols + 1 > pr.cap) fail(PW_EINVAL, "corrector capacity exceeded (raise max_iters)");
+  double* U = pr.Ub[cur];
+  double* V = pr.Vb[cur];
+  int n;
+  if (r == 0) {
+    orth(rows, ncols, F, rows, U, rows, pr.RF, pr.os, st);
+    orth(rows, ncols, G, rows, V, rows, pr.RG, pr.os, st);
+    gemm_small(ncols, ncols, ncols, 1.0, pr.RF, ncols, false, pr.RG, ncols, true, 0.0, pr.H,
+               ncols, st);
+    n = ncols;
+  } else {
+    PW_HIP(hipMemcpyAsync(pr.Fp, F, sizeof(double) * rows * ncols, hipMemcpyDeviceToDevice, st));
+    PW_HIP(hipMemcpyAsync(pr.Gp, G, sizeof(double) * rows * ncols, hipMemcpyDeviceToDevice, st));
+    project_out(pr, rows, r, ncols, U, pr.Fp, pr.UF, pr.UF2, st);
+    project_out(pr, rows, r, ncols, V, pr.Gp, pr.VG, pr.VG2, st);
+    orth(rows, ncols, pr.Fp, rows, U + rows * r, rows, pr.RF, pr.os, st);
+    orth(rows, ncols, pr.Gp, rows, V + rows * r, rows, pr.RG, pr.os, st);
+    n = r + ncols;
+    // Af = [UF; RF], Bg = [VG; RG] ((r + ncols) x ncols)
+    copy_block(r, ncols, pr.UF, r, pr.Af, n, st);
+    copy_block(ncols, ncols, pr.RF, ncols, pr.Af + r, n, st);
+    copy_block(r, ncols, pr.VG, r, pr.Bg, n, st);
+    copy_block(ncols, ncols, pr.RG, ncols, pr.Bg + r, n, st);
+    gemm_small(n, n, ncols, 1.0, pr.Af, n, false, pr.Bg, n, true, 0.0, pr.H, n, st);
+    add_diag(n, r, pr.S, pr.H, n, st);
+  }
+  svd_jacobi(n, pr.H, pr.X, pr.Y, pr.sig, pr.tol, pr.rank_dev, pr.Hw, pr.Vw, pr.counters, st);
+  int rn = 0;
+  sync_rank(pr, st, &rn);
+  rn = std::min(rn, pr.rmax);
+  // new columns of E and P for the sweep: Lambda^dag of Q_F, Lambda^T of Q_G
+  const long long Nc = pr.Nc;
+  lambda_dag_cols(pr.gc, pr.dtab, U + rows * r, rows, pr.cc, pr.E[cur] + 2 * Nc * r, 2 * Nc,
+                  ncols, pr.ctmp, st);
+  lambda_adjoint_cols(pr.gc, V + rows * r, rows, pr.cc, pr.order, pr.Vp[cur] + 2 * Nc * r, 2 * Nc,
+                      ncols, st);
+  // rotate: [U Q_F] X(:, 1:rn) etc.
+  gemm_nn(rows, rn, n, 1.0, U, rows, pr.X, n, 0.0, pr.Ub[nxt], rows, st);
+  gemm_nn(rows, rn, n, 1.0, V, rows, pr.Y, n, 0.0, pr.Vb[nxt], rows, st);
+  gemm_nn(2 * Nc, rn, n, 1.0, pr.E[cur], 2 * Nc, pr.X, n, 0.0, pr.E[nxt], 2 * Nc, st);
+  gemm_nn(2 * Nc, rn, n, 1.0, pr.Vp[cur], 2 * Nc, pr.Y, n, 0.0, pr.Vp[nxt], 2 * Nc, st);
+  set_dc_column(pr.E[nxt], 2 * Nc, rn, Nc, 1.0 / (double)Nc, st);
+  set_dc_column(pr.Vp[nxt], 2 * Nc, rn, Nc, 1.0, st);
+  if (rn > 0)
+    PW_HIP(hipMemcpyAsync(pr.S, pr.sig, sizeof(double) * rn, hipMemcpyDeviceToDevice, st));
+  pr.cur = nxt;
+  pr.r = rn;
+}
+
+void reset_corrector(Prob& pr) {
+  pr.r = 0;
+  pr.cur = 0;
+  pr.ranks.clear();
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 3
+// ---------------------------------------------------------------------------
+__global__ void k_split_cast_f(const double* delta, long long ld, long long nc, int ncols,
+                               float* du, float* dp) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nc * ncols) return;
+  const long long col = t / nc, J = t - col * nc;
+  du[t] = (float)delta[col * ld + J];
+  dp[t] = (float)delta[col * ld + nc + J];
+}
+__global__ void k_split_cast_d(const double* delta, long long ld, long long nc, int ncols,
+                               double* du, double* dp) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nc * ncols) return;
+  const long long col = t / nc, J = t - col * nc;
+  du[t] = delta[col * ld + J];
+  dp[t] = delta[col * ld + nc + J];
+}
+
+template <typename T>
+void split_cast(const double* delta, long long ld, long long nc, int ncols, T* du, T* dp,
+                hipStream_t st) {
+  const long long n = nc * ncols;
+  if (n == 0) return;
+  if constexpr (sizeof(T) == 4)
+    hipLaunchKernelGGL(k_split_cast_f, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, delta,
+                       ld, nc, ncols, du, dp);
+  else
+    hipLaunchKernelGGL(k_split_cast_d, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, delta,
+                       ld, nc, ncols, du, dp);
+  PW_LAUNCH_CHECK();
+}
+
+template <typename T>
+void run_typed(Prob& pr, int K, hipStream_t st) {
+  const int N = pr.N;
+  const long long Nf = pr.Nf, Nc = pr.Nc, rows = pr.rows;
+  T* u = tp<T>(pr.u);
+  T* p = tp<T>(pr.p);
+  T* v = tp<T>(pr.v);
+  T* vp = tp<T>(pr.vp);
+  T* Uc = tp<T>(pr.Uc);
+  T* Ucp = tp<T>(pr.Ucp);
+  T* Rc = tp<T>(pr.Rc);
+  T* Rcp = tp<T>(pr.Rcp);
+  reset_corrector(pr);
+  for (int i = 0; i < 4; ++i) pr.ms[i] = 0.0;
+  hipEvent_t e0, e1;
+  PW_HIP(hipEventCreate(&e0));
+  PW_HIP(hipEventCreate(&e1));
+  PW_HIP(hipEventRecord(e0, st));
+  // initialisation: W_0 = R u0, W_n = C W_{n-1}; u^1_n = I W_n
+  restrict_fields<T>(pr.gf, pr.ratio, pr.gc, u, Nf, Rc, Nc, 1, st);
+  restrict_fields<T>(pr.gf, pr.ratio, pr.gc, p, Nf, Rcp, Nc, 1, st);
+  for (int n = 1; n <= N; ++n) {
+    const T* su = n == 1 ? Rc : Uc + (n - 2) * Nc;
+    const T* sp = n == 1 ? Rcp : Ucp + (n - 2) * Nc;
+    prop_coarse<T>(pr, su, sp, Uc + (n - 1) * Nc, Ucp + (n - 1) * Nc, 1, st);
+  }
+  interp_add<T>(pr.gf, pr.gc, pr.ratio, pr.itab, Uc, Nc, (const T*)nullptr, u + Nf, Nf, N,
+                pr.itmp, st);
+  interp_add<T>(pr.gf, pr.gc, pr.ratio, pr.itab, Ucp, Nc, (const T*)nullptr, p + Nf, Nf, N,
+                pr.itmp, st);
+  for (int k = 1; k <= K; ++k) {
+    PW_HIP(hipEventRecord(pr.ev[0], st));
+    // 1. parallel phase
+    prop_fine<T>(pr, u, p, v, vp, N, st);
+    restrict_fields<T>(pr.gf, pr.ratio, pr.gc, u, Nf, Rc, Nc, N, st);
+    restrict_fields<T>(pr.gf, pr.ratio, pr.gc, p, Nf, Rcp, Nc, N, st);
+    prop_coarse<T>(pr, Rc, Rcp, Uc, Ucp, N, st);
+    PW_HIP(hipEventRecord(pr.ev[1], st));
+    // 2. corrector
+    energy_columns<T>(pr.gf, pr.ratio, pr.gc, v, vp, Nf, pr.cc, pr.order, pr.Fm, rows, N, st);
+    energy_columns<T>(pr.gc, 1, pr.gc, Uc, Ucp, Nc, pr.cc, pr.order, pr.Gm, rows, N, st);
+    update_svd_dev(pr, pr.Fm, pr.Gm, N, st);
+    pr.ranks.push_back(pr.r);
+    {
+      // rho_k: || F - U (V^T G) ||_F / ||F||_F
+      const int r = pr.r;
+      gemm_tn(rows, r, N, 1.0, pr.Vb[pr.cur], rows, pr.Gm, rows, 0.0, pr.UF, std::max(r, 1),
+              pr.gwork, st);
+      PW_HIP(hipMemcpyAsync(pr.Fp, pr.Fm, sizeof(double) * rows * N, hipMemcpyDeviceToDevice, st));
+      gemm_nn(rows, N, r, -1.0, pr.Ub[pr.cur], rows, pr.UF, std::max(r, 1), 1.0, pr.Fp, rows, st);
+      frob_norm2(pr.Fp, rows, N, rows, pr.red, pr.res + 2 * (k - 1), st);
+      frob_norm2(pr.Fm, rows, N, rows, pr.red, pr.res + 2 * (k - 1) + 1, st);
+    }
+    PW_HIP(hipEventRecord(pr.ev[2], st));
+    // 3. corrected sweep in corrector coordinates
+    const int dim = pr.r + 1;
+    const double* E = pr.E[pr.cur];
+    const double* P = pr.Vp[pr.cur];
+    // a_n = C (R v_{n-1} - R u^k_{n-1}), v_0 = u0 -> column 0 is zero
+    fill(pr.Din, 2 * Nc, 0.0, st);
+    if (N > 1)
+      restrict_diff<T>(pr.gf, pr.ratio, pr.gc, v, vp, u + Nf, p + Nf, Nf, pr.Din + 2 * Nc, 2 * Nc,
+                       N - 1, st);
+    prop_coarse_cols(pr, pr.Din, pr.Acol, N, st);
+    prop_coarse_cols(pr, E, pr.CE, dim, st);
+    gemm_tn(2 * Nc, dim, dim, 1.0, P, 2 * Nc, pr.CE, 2 * Nc, 0.0, pr.M, dim, pr.gwork, st);
+    gemm_tn(2 * Nc, dim, N, 1.0, P, 2 * Nc, pr.Acol, 2 * Nc, 0.0, pr.Bn, dim, pr.gwork, st);
+    recurrence(dim, N, pr.M, pr.Bn, pr.Tn, st);
+    gemm_nn(2 * Nc, N, dim, 1.0, E, 2 * Nc, pr.Tn, dim, 0.0, pr.delta, 2 * Nc, st);
+    // 4. u^{k+1}_n = v_n + I(delta_n), n = 1..N
+    split_cast<T>(pr.delta, 2 * Nc, Nc, N, tp<T>(pr.du_T), tp<T>(pr.dp_T), st);
+    interp_add<T>(pr.gf, pr.gc, pr.ratio, pr.itab, tp<T>(pr.du_T), Nc, v, u + Nf, Nf, N, pr.itmp,
+                  st);
+    interp_add<T>(pr.gf, pr.gc, pr.ratio, pr.itab, tp<T>(pr.dp_T), Nc, vp, p + Nf, Nf, N,
+                  pr.itmp, st);
+    PW_HIP(hipEventRecord(pr.ev[3], st));
+    PW_HIP(hipEventSynchronize(pr.ev[3]));
+    float a = 0, b = 0, c = 0;
+    PW_HIP(hipEventElapsedTime(&a, pr.ev[0], pr.ev[1]));
+    PW_HIP(hipEventElapsedTime(&b, pr.ev[1], pr.ev[2]));
+    PW_HIP(hipEventElapsedTime(&c, pr.ev[2], pr.ev[3]));
+    pr.ms[0] += a;
+    pr.ms[1] += b;
+    pr.ms[2] += c;
+    pr.k_done = k;
+  }
+  PW_HIP(hipEventRecord(e1, st));
+  PW_HIP(hipEventSynchronize(e1));
+  float tot = 0;
+  PW_HIP(hipEventElapsedTime(&tot, e0, e1));
+  pr.ms[3] = tot;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
+template <typename T>
+__global__ void k_from_double(const double* in, T* out, long long n) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) out[t] = (T)in[t];
+}
+__global__ void k_square(const double* in, double* out, long long n) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) out[t] = in[t] * in[t];
+}
+
+template <typename T>
+void set_medium_typed(Prob& pr, hipStream_t st) {
+  const long long Nf = pr.Nf, Nc = pr.Nc;
+  restrict_fields<double>(pr.gf, pr.ratio, pr.gc, pr.cf, Nf, pr.cc, Nc, 1, st);
+  double* tmp = pr.c2c_d;  // coarse c^2 in double
+  hipLaunchKernelGGL(k_square, dim3((unsigned)((Nc + 255) / 256)), dim3(256), 0, st,
+                     (const double*)pr.cc, tmp, Nc);
+  PW_LAUNCH_CHECK();
+  hipLaunchKernelGGL((k_from_double<T>), dim3((unsigned)((Nc + 255) / 256)), dim3(256), 0, st,
+                     (const double*)tmp, tp<T>(pr.c2c), Nc);
+  PW_LAUNCH_CHECK();
+  // fine c^2: square in double then round once
+  double* ftmp = (double*)pr.itmp;
+  hipLaunchKernelGGL(k_square, dim3((unsigned)((Nf + 255) / 256)), dim3(256), 0, st,
+                     (const double*)pr.cf, ftmp, Nf);
+  PW_LAUNCH_CHECK();
+  hipLaunchKernelGGL((k_from_double<T>), dim3((unsigned)((Nf + 255) / 256)), dim3(256), 0, st,
+                     (const double*)ftmp, tp<T>(pr.c2f), Nf);
+  PW_LAUNCH_CHECK();
+}
+
+template <typename T>
+void set_initial_typed(Prob& pr, const double* u0, const double* p0, hipStream_t st) {
+  const long long Nf = pr.Nf;
+  hipLaunchKernelGGL((k_from_double<T>), dim3((unsigned)((Nf + 255) / 256)), dim3(256), 0, st, u0,
+                     tp<T>(pr.u), Nf);
+  PW_LAUNCH_CHECK();
+  hipLaunchKernelGGL((k_from_double<T>), dim3((unsigned)((Nf + 255) / 256)), dim3(256), 0, st, p0,
+                     tp<T>(pr.p), Nf);
+  PW_LAUNCH_CHECK();
+}
+
+template <typename T>
+void serial_fine_typed(Prob& pr, int n, T* uo, T* po, hipStream_t st) {
+  const long long Nf = pr.Nf;
+  const T* su = tp<T>(pr.u);
+  const T* sp = tp<T>(pr.p);
+  if (n == 0) {
+    PW_HIP(hipMemcpyAsync(uo, su, sizeof(T) * Nf, hipMemcpyDeviceToDevice, st));
+    PW_HIP(hipMemcpyAsync(po, sp, sizeof(T) * Nf, hipMemcpyDeviceToDevice, st));
+    return;
+  }
+  T* bu[2] = {tp<T>(pr.sfa_u), tp<T>(pr.sfb_u)};
+  T* bp[2] = {tp<T>(pr.sfa_p), tp<T>(pr.sfb_p)};
+  for (int i = 0; i < n; ++i) {
+    T* du = (i == n - 1) ? uo : bu[i % 2];
+    T* dp = (i == n - 1) ? po : bp[i % 2];
+    prop_fine<T>(pr, su, sp, du, dp, 1, st);
+    su = du;
+    sp = dp;
+  }
+}
+
+pw_status report(const Error& e) {
+  g_last_error = e.msg;
+  return e.status;
+}
+
+template <typename F>
+pw_status guarded(F&& f) {
+  try {
+    f();
+    return PW_OK;
+  } catch (const Error& e) {
+    return report(e);
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return PW_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return PW_EINVAL;
+  }
+}
+
+const void* stage_in(const double* src, long long n, int on_device, Prob& pr, double* scratch,
+                     hipStream_t st) {
+  (void)pr;
+  if (on_device) return src;
+  PW_HIP(hipMemcpyAsync(scratch, src, sizeof(double) * n, hipMemcpyHostToDevice, st));
+  return scratch;
+}
+
+}  // namespace
+}  // namespace pw
+
+using namespace pw;
+
+extern "C" {
+
+const char* pw_last_error(void) { return g_last_error.c_str(); }
+
+const char* pw_version(void) { return "pwave 0.1 (gfx950)"; }
+
+int pw_num_problems(const pw_ctx* ctx) { return ctx ? (int)ctx->probs.size() : 0; }
+
+pw_status pw_create(const pw_problem* probs, int n_problems, void* stream, pw_ctx** out) {
+  return guarded([&] {
+    if (!probs || n_problems < 1 || !out) fail(PW_EINVAL, "bad arguments to pw_create");
+    auto ctx = std::make_unique<pw_ctx>();
+    ctx->stream = (hipStream_t)stream;
+    for (int i = 0; i < n_problems; ++i) {
+      auto pr = std::make_unique<Prob>();
+      setup(*pr, probs[i]);
+      ctx->probs.push_back(std::move(pr));
+    }
+    PW_HIP(hipDeviceSynchronize());
+    *out = ctx.release();
+  });
+}
+
+pw_status pw_destroy(pw_ctx* ctx) {
+  return guarded([&] {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& pr : ctx->probs)
+      for (int i = 0; i < 4; ++i)
+        if (pr->ev[i]) (void)hipEventDestroy(pr->ev[i]);
+    delete ctx;
+  });
+}
+
+pw_status pw_sync(pw_ctx* ctx) {
+  return guarded([&] {
+    if (!ctx) fail(PW_EINVAL, "null context");
+    PW_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+pw_status pw_set_medium(pw_ctx* ctx, int prob, const double* c, int on_device) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (!c) fail(PW_EINVAL, "null medium");
+    hipStream_t st = ctx->stream;
+    PW_HIP(hipMemcpyAsync(pr.cf, c, sizeof(double) * pr.Nf,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    // stability: c_max * dt / dx < 1 / sqrt(d) on both grids
+    std::vector<double> h(pr.Nf);
+    PW_HIP(hipMemcpyAsync(h.data(), pr.cf, sizeof(double) * pr.Nf, hipMemcpyDeviceToHost, st));
+    PW_HIP(hipStreamSynchronize(st));
+    double cmax = 0.0;
+    for (double x : h) {
+      if (!(x > 0.0) || !std::isfinite(x)) fail(PW_EINVAL, "medium must be positive and finite");
+      cmax = std::max(cmax, x);
+    }
+    const double lim = 1.0 / std::sqrt((double)pr.gf.dim);
+    if (cmax * pr.hF / pr.gf.dx >= lim || cmax * pr.hC / pr.gc.dx >= lim) {
+      char buf[200];
+      snprintf(buf, sizeof(buf),
+               "unstable: c_max dt/dx = %.4g (fine), %.4g (coarse) >= 1/sqrt(d) = %.4g",
+               cmax * pr.hF / pr.gf.dx, cmax * pr.hC / pr.gc.dx, lim);
+      fail(PW_EUNSTABLE, buf);
+    }
+    if (pr.f64) set_medium_typed<double>(pr, st);
+    else set_medium_typed<float>(pr, st);
+    PW_HIP(hipStreamSynchronize(st));
+    pr.have_medium = true;
+  });
+}
+
+pw_status pw_set_initial(pw_ctx* ctx, int prob, const double* u0, const double* p0,
+                         int on_device) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (!u0 || !p0) fail(PW_EINVAL, "null initial state");
+    hipStream_t st = ctx->stream;
+    double* s0 = pr.itmp;
+    double* s1 = pr.itmp + pr.Nf;
+    const double* du = (const double*)stage_in(u0, pr.Nf, on_device, pr, s0, st);
+    const double* dp = (const double*)stage_in(p0, pr.Nf, on_device, pr, s1, st);
+    if (pr.f64) set_initial_typed<double>(pr, du, dp, st);
+    else set_initial_typed<float>(pr, du, dp, st);
+    PW_HIP(hipStreamSynchronize(st));
+    pr.have_initial = true;
+    pr.k_done = 0;
+    reset_corrector(pr);
+  });
+}
+
+pw_status pw_run(pw_ctx* ctx, int prob, int K) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (!pr.have_medium || !pr.have_initial) fail(PW_ESTATE, "set medium and initial state first");
+    if (K < 0 || K > pr.P.max_iters) fail(PW_EINVAL, "K must be in [0, max_iters]");
+    if (pr.f64) run_typed<double>(pr, K, ctx->stream);
+    else run_typed<float>(pr, K, ctx->stream);
+  });
+}
+
+pw_status pw_get_state(pw_ctx* ctx, int prob, int n, void* u, void* p, int on_device) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (n < 0 || n > pr.N) fail(PW_EINVAL, "slice index out of range");
+    if (!u || !p) fail(PW_EINVAL, "null output");
+    const size_t bytes = pr.tsize * pr.Nf;
+    const char* su = (const char*)pr.u + bytes * n;
+    const char* sp = (const char*)pr.p + bytes * n;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    PW_HIP(hipMemcpyAsync(u, su, bytes, kind, ctx->stream));
+    PW_HIP(hipMemcpyAsync(p, sp, bytes, kind, ctx->stream));
+    if (!on_device) PW_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+pw_status pw_get_residuals(pw_ctx* ctx, int prob, double* rho, int* rank, int cap, int* count) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    const int K = pr.k_done;
+    std::vector<double> h(2 * (size_t)std::max(K, 1));
+    if (K > 0) {
+      PW_HIP(hipMemcpyAsync(h.data(), pr.res, sizeof(double) * 2 * K, hipMemcpyDeviceToHost,
+                            ctx->stream));
+      PW_HIP(hipStreamSynchronize(ctx->stream));
+    }
+    for (int k = 0; k < K && k < cap; ++k) {
+      if (rho) rho[k] = h[2 * k + 1] > 0 ? std::sqrt(h[2 * k] / h[2 * k + 1]) : 0.0;
+      if (rank) rank[k] = k < (int)pr.ranks.size() ? pr.ranks[k] : 0;
+    }
+    if (count) *count = K;
+  });
+}
+
+pw_status pw_serial_fine(pw_ctx* ctx, int prob, int n, void* u, void* p) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (!pr.have_medium || !pr.have_initial) fail(PW_ESTATE, "set medium and initial state first");
+    if (n < 0 || n > pr.N) fail(PW_EINVAL, "n out of range");
+    if (!u || !p) fail(PW_EINVAL, "null output");
+    if (pr.f64) serial_fine_typed<double>(pr, n, (double*)u, (double*)p, ctx->stream);
+    else serial_fine_typed<float>(pr, n, (float*)u, (float*)p, ctx->stream);
+  });
+}
+
+pw_status pw_propagate(pw_ctx* ctx, int prob, int grid, const void* u_in, const void* p_in,
+                       void* u_out, void* p_out, int n_states) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (!pr.have_medium) fail(PW_ESTATE, "set the medium first");
+    if (!u_in || !p_in || !u_out || !p_out || n_states < 0) fail(PW_EINVAL, "bad arguments");
+    if (grid == PW_FINE) {
+      if (pr.f64)
+        prop_fine<double>(pr, (const double*)u_in, (const double*)p_in, (double*)u_out,
+                          (double*)p_out, n_states, ctx->stream);
+      else
+        prop_fine<float>(pr, (const float*)u_in, (const float*)p_in, (float*)u_out,
+                         (float*)p_out, n_states, ctx->stream);
+    } else if (grid == PW_COARSE) {
+      if (pr.f64)
+        prop_coarse<double>(pr, (const double*)u_in, (const double*)p_in, (double*)u_out,
+                            (double*)p_out, n_states, ctx->stream);
+      else
+        prop_coarse<float>(pr, (const float*)u_in, (const float*)p_in, (float*)u_out,
+                           (float*)p_out, n_states, ctx->stream);
+    } else {
+      fail(PW_EINVAL, "grid must be PW_FINE or PW_COARSE");
+    }
+  });
+}
+
+pw_status pw_energy_components(pw_ctx* ctx, int prob, int grid, const void* u, const void* p,
+                               double* out, int n_states) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (!pr.have_medium) fail(PW_ESTATE, "set the medium first");
+    if (!u || !p || !out || n_states < 0) fail(PW_EINVAL, "bad arguments");
+    if (grid != PW_FINE && grid != PW_COARSE) fail(PW_EINVAL, "bad grid");
+    const Grid& src = grid == PW_FINE ? pr.gf : pr.gc;
+    const int ratio = grid == PW_FINE ? pr.ratio : 1;
+    const long long ss = src.npts();
+    if (pr.f64)
+      energy_columns<double>(src, ratio, pr.gc, (const double*)u, (const double*)p, ss, pr.cc,
+                             pr.order, out, pr.rows, n_states, ctx->stream);
+    else
+      energy_columns<float>(src, ratio, pr.gc, (const float*)u, (const float*)p, ss, pr.cc,
+                            pr.order, out, pr.rows, n_states, ctx->stream);
+  });
+}
+
+pw_status pw_interp_add(pw_ctx* ctx, int prob, const double* du, const double* dp, const void* v,
+                        const void* vp, void* u_out, void* p_out, int n_states) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (!du || !dp || !u_out || !p_out || n_states < 0 || n_states > pr.N)
+      fail(PW_EINVAL, "bad arguments (n_states must be <= n_slices)");
+    hipStream_t st = ctx->stream;
+    const long long Nc = pr.Nc, Nf = pr.Nf;
+    if (pr.f64) {
+      cast_from_double<double>(du, tp<double>(pr.du_T), Nc * n_states, st);
+      cast_from_double<double>(dp, tp<double>(pr.dp_T), Nc * n_states, st);
+      interp_add<double>(pr.gf, pr.gc, pr.ratio, pr.itab, tp<double>(pr.du_T), Nc,
+                         (const double*)v, (double*)u_out, Nf, n_states, pr.itmp, st);
+      interp_add<double>(pr.gf, pr.gc, pr.ratio, pr.itab, tp<double>(pr.dp_T), Nc,
+                         (const double*)vp, (double*)p_out, Nf, n_states, pr.itmp, st);
+    } else {
+      cast_from_double<float>(du, tp<float>(pr.du_T), Nc * n_states, st);
+      cast_from_double<float>(dp, tp<float>(pr.dp_T), Nc * n_states, st);
+      interp_add<float>(pr.gf, pr.gc, pr.ratio, pr.itab, tp<float>(pr.du_T), Nc, (const float*)v,
+                        (float*)u_out, Nf, n_states, pr.itmp, st);
+      interp_add<float>(pr.gf, pr.gc, pr.ratio, pr.itab, tp<float>(pr.dp_T), Nc,
+                        (const float*)vp, (float*)p_out, Nf, n_states, pr.itmp, st);
+    }
+  });
+}
+
+pw_status pw_grad2func(pw_ctx* ctx, int prob, const double* q, const double* sums, double* w,
+                       int n_states) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (!q || !w || n_states < 0 || n_states > pr.N)
+      fail(PW_EINVAL, "bad arguments (n_states must be <= n_slices)");
+    grad2func_cols(pr.gc, pr.dtab, q, (long long)pr.gc.dim * pr.Nc, sums, w, pr.Nc, n_states,
+                   pr.ctmp, ctx->stream);
+  });
+}
+
+pw_status pw_update_svd(pw_ctx* ctx, int prob, const double* F, const double* G, int n_cols,
+                        int reset, int* rank) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (!F || !G || n_cols < 1 || n_cols > pr.N) fail(PW_EINVAL, "bad arguments");
+    if (!pr.have_medium) fail(PW_ESTATE, "set the medium first");
+    if (reset) reset_corrector(pr);
+    update_svd_dev(pr, F, G, n_cols, ctx->stream);
+    if (rank) *rank = pr.r;
+  });
+}
+
+pw_status pw_get_corrector(pw_ctx* ctx, int prob, double* U, double* S, double* V, int cap,
+                           int* rank) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    const int r = pr.r;
+    if (rank) *rank = r;
+    if (!U && !S && !V) return;  // rank query
+    if (r > cap) fail(PW_EINVAL, "output capacity smaller than the rank");
+    hipStream_t st = ctx->stream;
+    if (r > 0) {
+      if (U)
+        PW_HIP(hipMemcpyAsync(U, pr.Ub[pr.cur], sizeof(double) * pr.rows * r,
+                              hipMemcpyDeviceToDevice, st));
+      if (V)
+        PW_HIP(hipMemcpyAsync(V, pr.Vb[pr.cur], sizeof(double) * pr.rows * r,
+                              hipMemcpyDeviceToDevice, st));
+      if (S) PW_HIP(hipMemcpyAsync(S, pr.S, sizeof(double) * r, hipMemcpyDeviceToDevice, st));
+    }
+    PW_HIP(hipStreamSynchronize(st));
+  });
+}
+
+pw_status pw_energy(pw_ctx* ctx, int prob, const void* u, const void* p, const void* u_ref,
+                    const void* p_ref, double* e_diff, double* e_ref) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (!pr.have_medium) fail(PW_ESTATE, "set the medium first");
+    if (!u || !p || (u_ref && !p_ref)) fail(PW_EINVAL, "bad arguments");
+    hipStream_t st = ctx->stream;
+    double* res = pr.red + 4000;
+    if (pr.f64)
+      energy_pair<double>(pr.gf, (const double*)u, (const double*)p, (const double*)u_ref,
+                          (const double*)p_ref, pr.cf, pr.order, pr.red, res, st);
+    else
+      energy_pair<float>(pr.gf, (const float*)u, (const float*)p, (const float*)u_ref,
+                         (const float*)p_ref, pr.cf, pr.order, pr.red, res, st);
+    double h[2] = {0, 0};
+    PW_HIP(hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, st));
+    PW_HIP(hipStreamSynchronize(st));
+    if (e_diff) *e_diff = h[0];
+    if (e_ref) *e_ref = h[1];
+  });
+}
+
+pw_status pw_get_timings(pw_ctx* ctx, int prob, double* ms, int cap) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    for (int i = 0; i < 4 && i < cap; ++i) ms[i] = pr.ms[i];
+  });
+}
+
+}  // extern "C"

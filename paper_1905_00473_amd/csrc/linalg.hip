@@ -1,0 +1,675 @@
+// Dense FP64 linear algebra for the Procrustes corrector (Secs. 3.3,
+// 3.3.1, Algorithm 1):
+//  * tall-skinny A^T B products (the snapshot Gram / projection step) and
+//    tall A B products (basis updates) on the FP64 matrix cores
+//    (v_mfma_f64_16x16x4f64), the A^T B products split over rows with a
+//    fixed-order second-stage sum so results do not depend on scheduling;
+//  * cyclic two-sided Jacobi for small symmetric Gram matrices, used to
+//    orthonormalise tall blocks (two passes of Gram eigen-orthonormalisation,
+//    the "truncated QR" of Algorithm 1);
+//  * one-sided (Hestenes) Jacobi SVD of the small core matrix H of
+//    Algorithm 1 with round-robin pair ordering, singular values sorted and
+//    the rank counted on the device;
+//  * the (r+1)-dimensional linear recurrence of the corrected sweep.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "pw_internal.h"
+
+namespace pw {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int kTB = 256;
+inline unsigned nblocks(long long n, int tb = kTB) { return (unsigned)((n + tb - 1) / tb); }
+
+// ---------------------------------------------------------------------------
+// MFMA GEMMs.  Operand layout of v_mfma_f64_16x16x4f64 (64 lanes):
+//   lane l supplies A[m = l%16][k = l/16] and B[k = l/16][n = l%16];
+//   the 16x16 result lives in 4 doubles per lane: D[4*(l/16) + v][l%16].
+// ---------------------------------------------------------------------------
+constexpr int TBM = 64, TBN = 64;
+
+template <int BK>
+__global__ __launch_bounds__(256) void k_gemm_tn(long long rows, int a, int b, const double* A,
+                                                  long long lda, const double* B, long long ldb,
+                                                  double* part, long long rows_per_split) {
+  __shared__ double As[BK][TBM + 1];
+  __shared__ double Bs[BK][TBN + 1];
+  const int m0 = blockIdx.x * TBM, n0 = blockIdx.y * TBN;
+  const long long r0 = (long long)blockIdx.z * rows_per_split;
+  const long long r1 = std::min(rows, r0 + rows_per_split);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  v4d acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int kk_ld = tid % BK;
+  const int cc_ld = tid / BK;
+  constexpr int CSTEP = 256 / BK;
+  for (long long k0 = r0; k0 < r1; k0 += BK) {
+    const long long r = k0 + kk_ld;
+    const bool rok = r < r1;
+#pragma unroll
+    for (int j = 0; j < TBM / CSTEP; ++j) {
+      const int cc = cc_ld + CSTEP * j;
+      As[kk_ld][cc] = (rok && m0 + cc < a) ? A[r + (long long)(m0 + cc) * lda] : 0.0;
+      Bs[kk_ld][cc] = (rok && n0 + cc < b) ? B[r + (long long)(n0 + cc) * ldb] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      double av[2], bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) av[i] = As[kk + lane / 16][wm + i * 16 + lane % 16];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bv[j] = Bs[kk + lane / 16][wn + j * 16 + lane % 16];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* P = part + (long long)blockIdx.z * a * b;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wm + i * 16 + 4 * (lane / 16) + v;
+        const int n = n0 + wn + j * 16 + lane % 16;
+        if (m < a && n < b) P[m + (long long)n * a] = acc[i][j][v];
+      }
+}
+
+__global__ void k_reduce_splits(const double* part, int nsplit, int a, int b, double alpha,
+                                double beta, double* C, long long ldc) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long ab = (long long)a * b;
+  if (t >= ab) return;
+  double s = 0.0;
+  for (int k = 0; k < nsplit; ++k) s += part[(long long)k * ab + t];
+  const int m = (int)(t % a), n = (int)(t / a);
+  double* c = C + m + (long long)n * ldc;
+  *c = beta == 0.0 ? alpha * s : alpha * s + beta * (*c);
+}
+
+template <int BK>
+__global__ __launch_bounds__(256) void k_gemm_nn(long long rows, int n, int k, double alpha,
+                                                  const double* A, long long lda, const double* B,
+                                                  long long ldb, double beta, double* C,
+                                                  long long ldc) {
+  __shared__ double As[BK][TBM + 1];
+  __shared__ double Bs[BK][TBN + 1];
+  const long long m0 = (long long)blockIdx.x * TBM;
+  const int n0 = blockIdx.y * TBN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  v4d acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int am = tid % TBM, ak = tid / TBM;  // A tile: 64 rows x BK
+  const int bk = tid % BK, bn = tid / BK;    // B tile: BK x 64
+  for (int k0 = 0; k0 < k; k0 += BK) {
+#pragma unroll
+    for (int j = 0; j < BK / (256 / TBM); ++j) {
+      const int kk = ak + (256 / TBM) * j;
+      const long long r = m0 + am;
+      As[kk][am] = (r < rows && k0 + kk < k) ? A[r + (long long)(k0 + kk) * lda] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < TBN / (256 / BK); ++j) {
+      const int nn = bn + (256 / BK) * j;
+      Bs[bk][nn] = (k0 + bk < k && n0 + nn < n) ? B[(k0 + bk) + (long long)(n0 + nn) * ldb] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      double av[2], bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) av[i] = As[kk + lane / 16][wm + i * 16 + lane % 16];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bv[j] = Bs[kk + lane / 16][wn + j * 16 + lane % 16];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const long long m = m0 + wm + i * 16 + 4 * (lane / 16) + v;
+        const int nn = n0 + wn + j * 16 + lane % 16;
+        if (m < rows && nn < n) {
+          double* c = C + m + (long long)nn * ldc;
+          *c = beta == 0.0 ? alpha * acc[i][j][v] : alpha * acc[i][j][v] + beta * (*c);
+        }
+      }
+}
+
+__global__ void k_gemm_small(int m, int n, int k, double alpha, const double* A, int lda, int ta,
+                             const double* B, int ldb, int tb, double beta, double* C, int ldc) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)m * n) return;
+  const int i = (int)(t % m), j = (int)(t / m);
+  double s = 0.0;
+  for (int l = 0; l < k; ++l) {
+    const double x = ta ? A[l + (long long)i * lda] : A[i + (long long)l * lda];
+    const double y = tb ? B[j + (long long)l * ldb] : B[l + (long long)j * ldb];
+    s += x * y;
+  }
+  double* c = C + i + (long long)j * ldc;
+  *c = beta == 0.0 ? alpha * s : alpha * s + beta * (*c);
+}
+
+// ---------------------------------------------------------------------------
+// cyclic Jacobi eigen-decomposition of a symmetric n x n matrix (n <= 64)
+// in one workgroup; round-robin ordering, n/2 disjoint rotations per round
+// ---------------------------------------------------------------------------
+constexpr int kEigMax = 64;
+
+__device__ __forceinline__ int rr_index(int j, int round, int np) {
+  return j == 0 ? 0 : ((j - 1 + round) % (np - 1)) + 1;
+}
+
+__global__ __launch_bounds__(256) void k_sym_eig(int n, double* Ag, int lda, double* Wg,
+                                                  double* lam) {
+  __shared__ double A[kEigMax][kEigMax + 1];
+  __shared__ double W[kEigMax][kEigMax + 1];
+  __shared__ double cs[kEigMax / 2][2];
+  __shared__ int pq[kEigMax / 2][2];
+  __shared__ int nrot;
+  const int tid = threadIdx.x;
+  const int np = (n + 1) & ~1;
+  for (int t = tid; t < np * np; t += blockDim.x) {
+    const int i = t % np, j = t / np;
+    A[i][j] = (i < n && j < n) ? Ag[i + (long long)j * lda] : 0.0;
+    W[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int npairs = np / 2;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) nrot = 0;
+    __syncthreads();
+    for (int round = 0; round < np - 1; ++round) {
+      if (tid < npairs) {
+        int p = rr_index(tid, round, np);
+        int q = rr_index(np - 1 - tid, round, np);
+        if (p > q) {
+          const int tmp = p;
+          p = q;
+          q = tmp;
+        }
+        double c = 1.0, s = 0.0;
+        const double apq = A[p][q];
+        const double app = A[p][p], aqq = A[q][q];
+        if (p < n && q < n && apq != 0.0 &&
+            fabs(apq) > 1e-15 * sqrt(fabs(app) * fabs(aqq))) {
+          const double tau = (aqq - app) / (2.0 * apq);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
+          atomicAdd(&nrot, 1);
+        }
+        cs[tid][0] = c;
+        cs[tid][1] = s;
+        pq[tid][0] = p;
+        pq[tid][1] = q;
+      }
+      __syncthreads();
+      // columns: A <- A J, W <- W J
+      for (int t = tid; t < npairs * np; t += blockDim.x) {
+        const int k = t / np, r = t % np;
+        const double c = cs[k][0], s = cs[k][1];
+        if (s != 0.0) {
+          const int p = pq[k][0], q = pq[k][1];
+          const double ap = A[r][p], aq = A[r][q];
+          A[r][p] = c * ap - s * aq;
+          A[r][q] = s * ap + c * aq;
+          const double wp = W[r][p], wq = W[r][q];
+          W[r][p] = c * wp - s * wq;
+          W[r][q] = s * wp + c * wq;
+        }
+      }
+      __syncthreads();
+      // rows: A <- J^T A
+      for (int t = tid; t < npairs * np; t += blockDim.x) {
+        const int k = t / np, r = t % np;
+        const double c = cs[k][0], s = cs[k][1];
+        if (s != 0.0) {
+          const int p = pq[k][0], q = pq[k][1];
+          const double ap = A[p][r], aq = A[q][r];
+          A[p][r] = c * ap - s * aq;
+          A[q][r] = s * ap + c * aq;
+        }
+      }
+      __syncthreads();
+    }
+    if (nrot == 0) break;
+    __syncthreads();
+  }
+  for (int t = tid; t < n * n; t += blockDim.x) {
+    const int i = t % n, j = t / n;
+    Wg[i + (long long)j * n] = W[i][j];
+  }
+  for (int i = tid; i < n; i += blockDim.x) lam[i] = A[i][i];
+}
+
+// T = W diag(kappa) with kappa_i = 1/sqrt(lam_i) for kept directions and
+// R = diag(sqrt(lam_i)) W^T (rows of dropped directions zero); a direction
+// is kept when lam_i > thr * max(lam) (rel) and lam_i > abs_thr.
+__global__ void k_orth_factors(int n, const double* W, const double* lam, double rel,
+                               double abs_thr, double* T, double* R) {
+  __shared__ double lmax;
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int i = 0; i < n; ++i) m = fmax(m, lam[i]);
+    lmax = m;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    const int i = t % n, j = t / n;  // element (i, j)
+    const double lj = lam[j];
+    const bool keepj = lj > rel * lmax && lj > abs_thr;
+    T[i + j * n] = keepj ? W[i + j * n] / sqrt(lj) : 0.0;
+    const double li = lam[i];
+    const bool keepi = li > rel * lmax && li > abs_thr;
+    R[i + j * n] = keepi ? sqrt(li) * W[j + i * n] : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// one-sided Jacobi SVD: one launch per round of disjoint column pairs
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_jacobi_round(int n, int np, int round, double* H,
+                                                       double* V, int* counter) {
+  const int lane = threadIdx.x & 63;
+  const int pair = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (pair >= np / 2) return;
+  int p = rr_index(pair, round, np);
+  int q = rr_index(np - 1 - pair, round, np);
+  if (p > q) {
+    const int t = p;
+    p = q;
+    q = t;
+  }
+  if (q >= n) return;
+  double* hp = H + (long long)p * n;
+  double* hq = H + (long long)q * n;
+  double al = 0.0, be = 0.0, ga = 0.0;
+  for (int i = lane; i < n; i += 64) {
+    const double x = hp[i], y = hq[i];
+    al += x * x;
+    be += y * y;
+    ga += x * y;
+  }
+  al = wave_sum(al);
+  be = wave_sum(be);
+  ga = wave_sum(ga);
+  if (ga == 0.0 || fabs(ga) <= 1e-15 * sqrt(al * be)) return;
+  const double zeta = (be - al) / (2.0 * ga);
+  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double c = 1.0 / sqrt(1.0 + t * t);
+  const double s = c * t;
+  for (int i = lane; i < n; i += 64) {
+    const double x = hp[i], y = hq[i];
+    hp[i] = c * x - s * y;
+    hq[i] = s * x + c * y;
+  }
+  double* vp = V + (long long)p * n;
+  double* vq = V + (long long)q * n;
+  for (int i = lane; i < n; i += 64) {
+    const double x = vp[i], y = vq[i];
+    vp[i] = c * x - s * y;
+    vq[i] = s * x + c * y;
+  }
+  if (lane == 0) atomicAdd(counter, 1);
+}
+
+__global__ void k_col_norms(int n, const double* H, double* sig) {
+  const int lane = threadIdx.x & 63;
+  const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (col >= n) return;
+  double s = 0.0;
+  for (int i = lane; i < n; i += 64) {
+    const double x = H[(long long)col * n + i];
+    s += x * x;
+  }
+  s = wave_sum(s);
+  if (lane == 0) sig[col] = sqrt(s);
+}
+
+// position of every column in descending order of its norm (ties by index)
+// and the rank count
+__global__ void k_sort_rank(int n, const double* sig_unsorted, int* pos, double tol,
+                            int* rank_dev, double* sig_sorted) {
+  __shared__ double smax;
+  __shared__ int cnt;
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int i = 0; i < n; ++i) m = fmax(m, sig_unsorted[i]);
+    smax = m;
+    cnt = 0;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const double sj = sig_unsorted[j];
+    int r = 0;
+    for (int i = 0; i < n; ++i) {
+      const double si = sig_unsorted[i];
+      r += (si > sj || (si == sj && i < j)) ? 1 : 0;
+    }
+    pos[j] = r;
+    sig_sorted[r] = sj;
+    if (smax > 0.0 && sj / smax > tol) atomicAdd(&cnt, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *rank_dev = cnt;
+}
+
+__global__ void k_scatter_svd(int n, const double* Hw, const double* Vw, const int* pos,
+                              const double* sig_unsorted, double* X, double* Y) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)n * n) return;
+  const int i = (int)(t % n), j = (int)(t / n);
+  const int dst = pos[j];
+  const double s = sig_unsorted[j];
+  X[i + (long long)dst * n] = s > 0.0 ? Hw[i + (long long)j * n] / s : 0.0;
+  Y[i + (long long)dst * n] = Vw[i + (long long)j * n];
+}
+
+__global__ void k_identity(int n, double* V) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)n * n) return;
+  V[t] = (t % n == t / n) ? 1.0 : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// t_1 = b_1; t_n = b_n + M t_{n-1}
+// ---------------------------------------------------------------------------
+constexpr int kRecMax = 8192;
+
+__global__ __launch_bounds__(1024) void k_recurrence(int dim, int N, const double* M,
+                                                      const double* b, double* t) {
+  __shared__ double prev[kRecMax];
+  for (int i = threadIdx.x; i < dim; i += blockDim.x) {
+    prev[i] = b[i];
+    t[i] = b[i];
+  }
+  __syncthreads();
+  for (int s = 1; s < N; ++s) {
+    double nv[kRecMax / 1024];
+#pragma unroll
+    for (int k = 0; k < kRecMax / 1024; ++k) {
+      const int i = threadIdx.x + k * 1024;
+      nv[k] = 0.0;
+      if (i < dim) {
+        double acc = b[(long long)s * dim + i];
+        for (int j = 0; j < dim; ++j) acc += M[i + (long long)j * dim] * prev[j];
+        nv[k] = acc;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRecMax / 1024; ++k) {
+      const int i = threadIdx.x + k * 1024;
+      if (i < dim) {
+        prev[i] = nv[k];
+        t[(long long)s * dim + i] = nv[k];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_add_diag(int r, const double* S, double* H, int ldh) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < r) H[i + (long long)i * ldh] += S[i];
+}
+
+__global__ void k_copy_block(int m, int n, const double* src, long long lds, double* dst,
+                             long long ldd) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)m * n) return;
+  const long long i = t % m, j = t / m;
+  dst[i + j * ldd] = src[i + j * lds];
+}
+
+__global__ void k_fill(double* p, long long n, double v) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = v;
+}
+
+__global__ void k_sumsq_cols(const double* A, long long rows, int cols, long long lda,
+                             double* partials) {
+  __shared__ double s[kTB];
+  const long long total = rows * cols;
+  double acc = 0.0;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const long long i = t % rows, j = t / rows;
+    const double x = A[i + j * lda];
+    acc += x * x;
+  }
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kTB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = s[0];
+}
+
+__global__ void k_sum(const double* partials, int nb, double* out) {
+  __shared__ double s[kTB];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += partials[i];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kTB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = s[0];
+}
+
+constexpr int kSplitTarget = 2048;
+constexpr int kTnBK = 32;
+constexpr int kNnBK = 16;
+
+int tn_splits(long long rows, int a, int b) {
+  const long long tiles = (long long)((a + TBM - 1) / TBM) * ((b + TBN - 1) / TBN);
+  long long s = (kSplitTarget + tiles - 1) / tiles;
+  const long long maxs = (rows + kTnBK - 1) / kTnBK;
+  s = std::max(1LL, std::min(s, maxs));
+  return (int)s;
+}
+
+}  // namespace
+
+size_t gemm_tn_work(long long rows, int a, int b) {
+  return (size_t)tn_splits(rows, a, b) * a * b;
+}
+
+void gemm_tn(long long rows, int a, int b, double alpha, const double* A, long long lda,
+             const double* B, long long ldb, double beta, double* C, long long ldc, double* work,
+             hipStream_t st) {
+  if (a <= 0 || b <= 0) return;
+  if (rows <= 0) {
+    // empty contraction: C = beta C
+    for (int j = 0; j < b; ++j) {
+      if (beta == 0.0) {
+        hipLaunchKernelGGL(k_fill, dim3(nblocks(a)), dim3(kTB), 0, st, C + (long long)j * ldc,
+                           (long long)a, 0.0);
+        PW_LAUNCH_CHECK();
+      }
+    }
+    return;
+  }
+  const int splits = tn_splits(rows, a, b);
+  long long rps = (rows + splits - 1) / splits;
+  rps = (rps + kTnBK - 1) / kTnBK * kTnBK;
+  const int ns = (int)((rows + rps - 1) / rps);
+  dim3 grid((a + TBM - 1) / TBM, (b + TBN - 1) / TBN, ns);
+  hipLaunchKernelGGL((k_gemm_tn<kTnBK>), grid, dim3(256), 0, st, rows, a, b, A, lda, B, ldb, work,
+                     rps);
+  PW_LAUNCH_CHECK();
+  const long long ab = (long long)a * b;
+  hipLaunchKernelGGL(k_reduce_splits, dim3(nblocks(ab)), dim3(kTB), 0, st, (const double*)work, ns,
+                     a, b, alpha, beta, C, ldc);
+  PW_LAUNCH_CHECK();
+}
+
+void gemm_nn(long long rows, int n, int k, double alpha, const double* A, long long lda,
+             const double* B, long long ldb, double beta, double* C, long long ldc,
+             hipStream_t st) {
+  if (rows <= 0 || n <= 0) return;
+  if (k <= 0) {
+    if (beta != 1.0) {
+      // C = beta C (only used with beta 0 by the library)
+      for (int j = 0; j < n; ++j) {
+        hipLaunchKernelGGL(k_fill, dim3(nblocks(rows)), dim3(kTB), 0, st, C + (long long)j * ldc,
+                           rows, 0.0);
+        PW_LAUNCH_CHECK();
+      }
+    }
+    return;
+  }
+  dim3 grid((unsigned)((rows + TBM - 1) / TBM), (n + TBN - 1) / TBN);
+  hipLaunchKernelGGL((k_gemm_nn<kNnBK>), grid, dim3(256), 0, st, rows, n, k, alpha, A, lda, B, ldb,
+                     beta, C, ldc);
+  PW_LAUNCH_CHECK();
+}
+
+void gemm_small(int m, int n, int k, double alpha, const double* A, int lda, bool ta,
+                const double* B, int ldb, bool tb, double beta, double* C, int ldc,
+                hipStream_t st) {
+  if (m <= 0 || n <= 0) return;
+  const long long mn = (long long)m * n;
+  hipLaunchKernelGGL(k_gemm_small, dim3(nblocks(mn)), dim3(kTB), 0, st, m, n, k, alpha, A, lda,
+                     (int)ta, B, ldb, (int)tb, beta, C, ldc);
+  PW_LAUNCH_CHECK();
+}
+
+void sym_eig(int n, double* A, int lda, double* W, double* lam, hipStream_t st) {
+  if (n > kEigMax) fail(PW_EINVAL, "Gram eigen-solver supports at most 64 columns per block");
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_sym_eig, dim3(1), dim3(256), 0, st, n, A, lda, W, lam);
+  PW_LAUNCH_CHECK();
+}
+
+void orth(long long rows, int n, const double* A, long long lda, double* Q, long long ldq,
+          double* R, OrthScratch s, hipStream_t st) {
+  // pass 1: Gram eigenvectors of A
+  gemm_tn(rows, n, n, 1.0, A, lda, A, lda, 0.0, s.gram, n, s.work, st);
+  sym_eig(n, s.gram, n, s.W, s.lam, st);
+  hipLaunchKernelGGL(k_orth_factors, dim3(1), dim3(kTB), 0, st, n, (const double*)s.W,
+                     (const double*)s.lam, 1e-13, 1e-290, s.T, s.R1);
+  PW_LAUNCH_CHECK();
+  gemm_nn(rows, n, n, 1.0, A, lda, s.T, n, 0.0, s.Q1, rows, st);
+  // pass 2: re-orthonormalise Q1 (its Gram is the identity up to rounding)
+  gemm_tn(rows, n, n, 1.0, s.Q1, rows, s.Q1, rows, 0.0, s.gram, n, s.work, st);
+  sym_eig(n, s.gram, n, s.W, s.lam, st);
+  double* R2 = s.gram;  // gram is consumed by sym_eig; reuse as R2
+  hipLaunchKernelGGL(k_orth_factors, dim3(1), dim3(kTB), 0, st, n, (const double*)s.W,
+                     (const double*)s.lam, 0.0, 0.25, s.T, R2);
+  PW_LAUNCH_CHECK();
+  gemm_nn(rows, n, n, 1.0, s.Q1, rows, s.T, n, 0.0, Q, ldq, st);
+  gemm_small(n, n, n, 1.0, R2, n, false, s.R1, n, false, 0.0, R, n, st);
+}
+
+void svd_jacobi(int n, const double* H, double* X, double* Y, double* sig, double tol,
+                int* rank_dev, double* Hw, double* Vw, int* counters, hipStream_t st) {
+  if (n <= 0) {
+    PW_HIP(hipMemsetAsync(rank_dev, 0, sizeof(int), st));
+    return;
+  }
+  const long long nn = (long long)n * n;
+  PW_HIP(hipMemcpyAsync(Hw, H, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL(k_identity, dim3(nblocks(nn)), dim3(kTB), 0, st, n, Vw);
+  PW_LAUNCH_CHECK();
+  const int np = (n + 1) & ~1;
+  const int maxsweeps = 40;
+  PW_HIP(hipMemsetAsync(counters, 0, sizeof(int) * maxsweeps, st));
+  const unsigned blocks = (unsigned)((np / 2 + 3) / 4);
+  for (int sw = 0; sw < maxsweeps; ++sw) {
+    for (int round = 0; round < np - 1; ++round) {
+      hipLaunchKernelGGL(k_jacobi_round, dim3(blocks), dim3(256), 0, st, n, np, round, Hw, Vw,
+                         counters + sw);
+      PW_LAUNCH_CHECK();
+    }
+    int h = 0;
+    PW_HIP(hipMemcpyAsync(&h, counters + sw, sizeof(int), hipMemcpyDeviceToHost, st));
+    PW_HIP(hipStreamSynchronize(st));
+    if (h == 0) break;
+  }
+  double* sig_u = Hw + nn;  // Hw has n*n + 2n doubles of room
+  int* pos = (int*)(sig_u + n);
+  hipLaunchKernelGGL(k_col_norms, dim3((n + 3) / 4), dim3(256), 0, st, n, (const double*)Hw, sig_u);
+  PW_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_sort_rank, dim3(1), dim3(1024), 0, st, n, (const double*)sig_u, pos, tol,
+                     rank_dev, sig);
+  PW_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_scatter_svd, dim3(nblocks(nn)), dim3(kTB), 0, st, n, (const double*)Hw,
+                     (const double*)Vw, (const int*)pos, (const double*)sig_u, X, Y);
+  PW_LAUNCH_CHECK();
+}
+
+void recurrence(int dim, int N, const double* M, const double* b, double* t, hipStream_t st) {
+  if (dim > kRecMax) fail(PW_EINVAL, "corrector rank too large for the sweep recurrence");
+  if (dim <= 0 || N <= 0) return;
+  hipLaunchKernelGGL(k_recurrence, dim3(1), dim3(1024), 0, st, dim, N, M, b, t);
+  PW_LAUNCH_CHECK();
+}
+
+void add_diag(int n, int r, const double* S, double* H, int ldh, hipStream_t st) {
+  (void)n;
+  if (r <= 0) return;
+  hipLaunchKernelGGL(k_add_diag, dim3(nblocks(r)), dim3(kTB), 0, st, r, S, H, ldh);
+  PW_LAUNCH_CHECK();
+}
+
+void copy_block(int m, int n, const double* src, long long lds, double* dst, long long ldd,
+                hipStream_t st) {
+  const long long mn = (long long)m * n;
+  if (mn <= 0) return;
+  hipLaunchKernelGGL(k_copy_block, dim3(nblocks(mn)), dim3(kTB), 0, st, m, n, src, lds, dst, ldd);
+  PW_LAUNCH_CHECK();
+}
+
+void fill(double* p, long long n, double v, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill, dim3(nblocks(n)), dim3(kTB), 0, st, p, n, v);
+  PW_LAUNCH_CHECK();
+}
+
+void frob_norm2(const double* A, long long rows, int cols, long long lda, double* partials,
+                double* out, hipStream_t st) {
+  const int nb = 512;
+  hipLaunchKernelGGL(k_sumsq_cols, dim3(nb), dim3(kTB), 0, st, A, rows, cols, lda, partials);
+  PW_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(kTB), 0, st, (const double*)partials, nb, out);
+  PW_LAUNCH_CHECK();
+}
+
+}  // namespace pw

@@ -1,0 +1,200 @@
+// Internal declarations shared by the HIP translation units of libpwave.
+// Not part of the public ABI (see include/pw.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pw.h"
+
+namespace pw {
+
+// ---------------------------------------------------------------------------
+// error handling: internal functions throw pw::Error, the ABI layer turns it
+// into a status code + thread-local message
+// ---------------------------------------------------------------------------
+struct Error {
+  pw_status status;
+  std::string msg;
+};
+
+[[noreturn]] void fail(pw_status st, const std::string& msg);
+void check_hip(hipError_t e, const char* what, const char* file, int line);
+#define PW_HIP(call) ::pw::check_hip((call), #call, __FILE__, __LINE__)
+#define PW_LAUNCH_CHECK() ::pw::check_hip(hipGetLastError(), "kernel launch", __FILE__, __LINE__)
+
+// ---------------------------------------------------------------------------
+// grid geometry of one periodic grid (fine or coarse)
+// ---------------------------------------------------------------------------
+struct Grid {
+  int dim = 1;
+  int n[3] = {1, 1, 1};  // points per axis (x, y, z)
+  double dx = 1.0;       // spacing (same on every axis)
+  long long npts() const { return (long long)n[0] * n[1] * n[2]; }
+};
+
+// ---------------------------------------------------------------------------
+// propagators (stencil.hip)
+// ---------------------------------------------------------------------------
+// Batched velocity-Verlet propagation of `nstates` states by `m` steps of
+// size h on grid g.  State s is u[s*sstride ...], p[s*sstride ...].
+// src and dst must not overlap.  work_* are scratch state sets used to
+// ping-pong between time blocks (each nstates*sstride elements; the e*
+// arrays are only used with compensation).  When m is done in a single
+// launch the scratch sets are not touched.
+template <typename T>
+struct StateSet {
+  T* u = nullptr;
+  T* p = nullptr;
+  T* eu = nullptr;  // compensation terms (FP32 compensated mode only)
+  T* ep = nullptr;
+};
+
+template <typename T>
+void propagate(const Grid& g, const T* c2, const T* u_src, const T* p_src, T* u_dst, T* p_dst,
+               long long sstride, int nstates, int m, T h, bool compensated, StateSet<T> work_a,
+               StateSet<T> work_b, hipStream_t stream);
+
+// largest number of steps one launch of the tiled kernel may take for this
+// grid (the whole propagation when the grid is one periodic line in LDS)
+int steps_per_launch(const Grid& g, bool is_double);
+
+// ---------------------------------------------------------------------------
+// grid transfer and energy components (transfer.hip)
+// ---------------------------------------------------------------------------
+// out[:, s] = Lambda R [u_s, p_s] (double columns, rows = (d+1) * coarse
+// points).  `ratio` = 1 when u, p already live on the coarse grid.
+template <typename T>
+void energy_columns(const Grid& fine_or_coarse, int ratio, const Grid& coarse, const T* u,
+                    const T* p, long long sstride, const double* cc, int order, double* out,
+                    long long ldo, int nstates, hipStream_t stream);
+
+// out[:, s] = [R(a_u - b_u) ; R(a_p - b_p)] as double coarse states
+// (column length 2 * coarse points, leading dimension ldo).  Column s uses
+// state s of a and b.
+template <typename T>
+void restrict_diff(const Grid& fine, int ratio, const Grid& coarse, const T* au, const T* ap,
+                   const T* bu, const T* bp, long long sstride, double* out, long long ldo,
+                   int nstates, hipStream_t stream);
+
+// coarse T state from a double state column: u_T = (T) x (elementwise cast)
+template <typename T>
+void cast_from_double(const double* in, T* out, long long n, hipStream_t stream);
+template <typename T>
+void cast_to_double(const T* in, double* out, long long n, hipStream_t stream);
+template <typename T>
+void restrict_fields(const Grid& fine, int ratio, const Grid& coarse, const T* in,
+                     long long sstride_in, T* out, long long sstride_out, int nfields,
+                     hipStream_t stream);
+
+// polyphase weights of trigonometric interpolation along one axis:
+// table[s * nc + d], s in [0, ratio), d in [0, nc) (host-built)
+std::vector<double> trig_interp_table(int nc, int ratio);
+
+// u_out[s] = (v ? v[s] : 0) + I(in[s]) on the fine grid, fields of type T.
+// tmp: double scratch of nfields * (fine points) * 2 elements.
+template <typename T>
+void interp_add(const Grid& fine, const Grid& coarse, int ratio, const double* const* tables,
+                const T* in, long long sstride_in, const T* v, T* out, long long sstride_out,
+                int nfields, double* tmp, hipStream_t stream);
+
+// DFT tables e^{-2 pi i j / n}, j < n, for each axis of the coarse grid
+std::vector<double> dft_table(int n);
+
+// w[s] = grad2func(q[s], sums[s]) (Algorithm 2) for n columns; q columns
+// hold d gradient blocks with leading dimension ldq; w columns have
+// leading dimension ldw.  sums may be null (all zero).  ctmp: complex
+// scratch (double2) of (d + 1) * coarse points * ncols elements.
+void grad2func_cols(const Grid& coarse, const double* const* dft, const double* q, long long ldq,
+                    const double* sums, double* w, long long ldw, int ncols, double* ctmp,
+                    hipStream_t stream);
+
+// Adjoint of Lambda on coarse energy-component columns:
+// out_u = -sum_a grad_a(q_a) (gradient order `order`), out_p = p / cc.
+// in: rows (d+1)*Nc, ld ldi; out: 2*Nc rows, ld ldo.
+void lambda_adjoint_cols(const Grid& coarse, const double* in, long long ldi, const double* cc,
+                         int order, double* out, long long ldo, int ncols, hipStream_t stream);
+
+// B'-columns from corrector columns: out_u = grad2func(q, 0), out_p = cc * p.
+void lambda_dag_cols(const Grid& coarse, const double* const* dft, const double* in,
+                     long long ldi, const double* cc, double* out, long long ldo, int ncols,
+                     double* ctmp, hipStream_t stream);
+
+// set column `col` of a 2*Nc-row matrix to [val_u * 1 ; 0]
+void set_dc_column(double* mat, long long ld, int col, long long nc, double val,
+                   hipStream_t stream);
+
+// energy of fine-grid state differences (double partials on device, reduced
+// on device in a fixed order).  result[0] = E(u - uref), result[1] = E(uref)
+template <typename T>
+void energy_pair(const Grid& fine, const T* u, const T* p, const T* uref, const T* pref,
+                 const double* cfine, int order, double* partials, double* result,
+                 hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// dense linear algebra (linalg.hip)
+// ---------------------------------------------------------------------------
+// C (a x b, ldc) = alpha * A^T B + beta * C with A (rows x a, lda),
+// B (rows x b, ldb), column-major.  FP64 MFMA, split over rows, fixed-order
+// reduction.  work: double scratch >= gemm_tn_work(rows, a, b).
+size_t gemm_tn_work(long long rows, int a, int b);
+void gemm_tn(long long rows, int a, int b, double alpha, const double* A, long long lda,
+             const double* B, long long ldb, double beta, double* C, long long ldc, double* work,
+             hipStream_t stream);
+
+// C (rows x n, ldc) = alpha * A (rows x k, lda) B (k x n, ldb) + beta * C.
+// FP64 MFMA.  C must not overlap A or B (it may be read when beta != 0).
+void gemm_nn(long long rows, int n, int k, double alpha, const double* A, long long lda,
+             const double* B, long long ldb, double beta, double* C, long long ldc,
+             hipStream_t stream);
+
+// small dense products: C (m x n) = alpha op(A) op(B) + beta C (column-major)
+void gemm_small(int m, int n, int k, double alpha, const double* A, int lda, bool ta,
+                const double* B, int ldb, bool tb, double beta, double* C, int ldc,
+                hipStream_t stream);
+
+// symmetric eigen-decomposition of n x n (n <= 128) A (in place destroyed):
+// W (n x n, column eigenvectors), lam (n), cyclic Jacobi in one workgroup.
+void sym_eig(int n, double* A, int lda, double* W, double* lam, hipStream_t stream);
+
+// Orthonormalisation for truncated QR (two passes of the eigenvector
+// orthonormalisation of the Gram matrix): A (rows x n) = Q R approximately;
+// Q (rows x n, ldq), R (n x n). Directions whose Gram eigenvalue is below
+// rel_tol * max are dropped (zero Q column, zero R row).
+struct OrthScratch {
+  double* gram = nullptr;   // n*n
+  double* W = nullptr;      // n*n
+  double* lam = nullptr;    // n
+  double* T = nullptr;      // n*n
+  double* R1 = nullptr;     // n*n
+  double* Q1 = nullptr;     // rows*n
+  double* work = nullptr;   // gemm_tn work
+};
+void orth(long long rows, int n, const double* A, long long lda, double* Q, long long ldq,
+          double* R, OrthScratch s, hipStream_t stream);
+
+// one-sided Jacobi SVD of the n x n matrix H (column-major, ld = n):
+// on return X (n x n, ld n) holds left singular vectors, Y right singular
+// vectors, sig singular values, sorted descending; *rank_dev the number
+// with sig/sig_max > tol.  Scratch: Hw, Vw (n*n each), counters (int).
+void svd_jacobi(int n, const double* H, double* X, double* Y, double* sig, double tol,
+                int* rank_dev, double* Hw, double* Vw, int* counters, hipStream_t stream);
+
+// linear recurrence t_1 = b_1, t_n = b_n + M t_{n-1} (t, b: dim x N
+// column-major, M: dim x dim).  One workgroup.
+void recurrence(int dim, int N, const double* M, const double* b, double* t,
+                hipStream_t stream);
+
+// H = [Ua; Ra][Vb; Rb]^T + diag(S, 0): (r+N) x (r+N) helper pieces
+void add_diag(int n, int r, const double* S, double* H, int ldh, hipStream_t stream);
+void copy_block(int m, int n, const double* src, long long lds, double* dst, long long ldd,
+                hipStream_t stream);
+void fill(double* p, long long n, double v, hipStream_t stream);
+void frob_norm2(const double* A, long long rows, int cols, long long lda, double* partials,
+                double* out, hipStream_t stream);
+
+}  // namespace pw

@@ -1,0 +1,451 @@
+// Fine and coarse propagators (Sec. 3.1): periodic second-order central
+// difference Laplacian + velocity Verlet, batched over states.
+//
+// Inside one launch the velocity-Verlet half kicks of consecutive steps are
+// merged into one full kick (the leapfrog form): starting from the true
+// state (u_i, p_i) at a slice start the first kick is a half kick, the last
+// launch of a slice closes with a half kick.  Between launches of the same
+// slice the carried momentum is the half-step one.
+//
+// Two kernels:
+//  * k_prop_line: a 1D periodic line lives entirely in LDS; all steps of a
+//    propagation run in one launch (no halo).
+//  * k_prop_tile: 2D/3D (and long 1D) grids are cut into tiles; a tile plus
+//    a halo of H = (steps in this launch) + (closing kick) points is loaded,
+//    every thread keeps u, p, c^2 (and the compensation terms) of its points
+//    in registers, u is mirrored in LDS for the neighbour reads, and the
+//    valid region shrinks by one point per Laplacian evaluation, so after
+//    H evaluations the tile interior is exact.
+//
+// FP32 compensated mode: every increment of p and u is added with Kahan's
+// compensated summation; the compensation is carried across launches of a
+// slice and folded into the state at the slice end.
+#include <algorithm>
+
+#include "pw_internal.h"
+
+namespace pw {
+namespace {
+
+template <typename T>
+struct PropArgs {
+  const T* u_in;
+  const T* p_in;
+  const T* eu_in;
+  const T* ep_in;
+  T* u_out;
+  T* p_out;
+  T* eu_out;
+  T* ep_out;
+  const T* c2;
+  long long sstride;
+  int nx, ny, nz;
+  int tx, ty, tz;     // tile interior
+  int ntx, nty, ntz;  // tiles per axis
+  int H;              // halo
+  int rx, ry, rz;     // region = tile + 2H per used axis
+  int nstates;
+  T h, idx2;
+  int nsteps, first, last;
+};
+
+__device__ __forceinline__ int wrap_idx(int g, int n) {
+  g %= n;
+  return g < 0 ? g + n : g;
+}
+
+// s += x, with Kahan compensation e when COMP
+template <typename T, bool COMP>
+__device__ __forceinline__ void kadd(T& s, T& e, T x) {
+  if constexpr (COMP) {
+    const T y = x - e;
+    const T t = s + y;
+    e = (t - s) - y;
+    s = t;
+  } else {
+    s += x;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// whole periodic line in LDS
+// ---------------------------------------------------------------------------
+template <typename T, bool COMP, int NT, int PPT>
+__global__ __launch_bounds__(NT) void k_prop_line(PropArgs<T> a) {
+  extern __shared__ unsigned char smem_raw[];
+  T* su = reinterpret_cast<T*>(smem_raw);
+  const int tid = threadIdx.x;
+  const int n = a.nx;
+  const long long base = (long long)blockIdx.x * a.sstride;
+  T ru[PPT], rp[PPT], rc[PPT], reu[PPT], rep[PPT];
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int i = tid + k * NT;
+    ru[k] = rp[k] = rc[k] = reu[k] = rep[k] = T(0);
+    if (i < n) {
+      ru[k] = a.u_in[base + i];
+      rp[k] = a.p_in[base + i];
+      rc[k] = a.c2[i];
+      if (COMP && !a.first) {
+        reu[k] = a.eu_in[base + i];
+        rep[k] = a.ep_in[base + i];
+      }
+      su[i] = ru[k];
+    }
+  }
+  __syncthreads();
+  for (int j = 0; j < a.nsteps; ++j) {
+    const T w = (a.first && j == 0) ? a.h * T(0.5) : a.h;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      const int i = tid + k * NT;
+      if (i < n) {
+        const int im = i == 0 ? n - 1 : i - 1;
+        const int ip = i == n - 1 ? 0 : i + 1;
+        const T lap = su[ip] - T(2) * ru[k] + su[im];
+        kadd<T, COMP>(rp[k], rep[k], w * (rc[k] * (lap * a.idx2)));
+        kadd<T, COMP>(ru[k], reu[k], a.h * rp[k]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      const int i = tid + k * NT;
+      if (i < n) su[i] = ru[k];
+    }
+    __syncthreads();
+  }
+  if (a.last) {
+    const T w = a.h * T(0.5);
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      const int i = tid + k * NT;
+      if (i < n) {
+        const int im = i == 0 ? n - 1 : i - 1;
+        const int ip = i == n - 1 ? 0 : i + 1;
+        const T lap = su[ip] - T(2) * ru[k] + su[im];
+        kadd<T, COMP>(rp[k], rep[k], w * (rc[k] * (lap * a.idx2)));
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int i = tid + k * NT;
+    if (i < n) {
+      if (COMP && a.last) {
+        a.u_out[base + i] = ru[k] - reu[k];
+        a.p_out[base + i] = rp[k] - rep[k];
+      } else {
+        a.u_out[base + i] = ru[k];
+        a.p_out[base + i] = rp[k];
+        if (COMP) {
+          a.eu_out[base + i] = reu[k];
+          a.ep_out[base + i] = rep[k];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tiled, time-blocked kernel for D = 1, 2, 3
+// ---------------------------------------------------------------------------
+template <typename T, int D, bool COMP, int NT, int PPT>
+__global__ __launch_bounds__(NT) void k_prop_tile(PropArgs<T> a) {
+  extern __shared__ unsigned char smem_raw[];
+  T* su = reinterpret_cast<T*>(smem_raw);
+  const int tid = threadIdx.x;
+  const int ntiles = a.ntx * a.nty * a.ntz;
+  const long long total = (long long)ntiles * a.nstates;
+  long long b = blockIdx.x;
+  // consecutive block ids go to different XCDs; remap so that the blocks
+  // of one XCD cover consecutive tiles (shared halos stay in one L2)
+  if ((total & 7) == 0) b = (b & 7) * (total >> 3) + (b >> 3);
+  const int state = (int)(b / ntiles);
+  const int tile = (int)(b - (long long)state * ntiles);
+  const int tix = tile % a.ntx;
+  const int tiy = (tile / a.ntx) % a.nty;
+  const int tiz = tile / (a.ntx * a.nty);
+  const int H = a.H;
+  const int ox = tix * a.tx - H;
+  const int oy = (D >= 2) ? tiy * a.ty - H : 0;
+  const int oz = (D >= 3) ? tiz * a.tz - H : 0;
+  const int rx = a.rx, ry = a.ry, rz = a.rz;
+  const int RN = rx * ry * rz;
+  const int sy = rx, sz = rx * ry;
+  const long long base = (long long)state * a.sstride;
+
+  T ru[PPT], rp[PPT], rc[PPT], reu[PPT], rep[PPT];
+  unsigned inner = 0u;  // bit k: point k has all neighbours inside the region
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int i = tid + k * NT;
+    ru[k] = rp[k] = rc[k] = reu[k] = rep[k] = T(0);
+    if (i < RN) {
+      const int x = i % rx;
+      const int y = (i / rx) % ry;
+      const int z = i / sz;
+      bool ring = (x == 0 || x == rx - 1);
+      if (D >= 2) ring = ring || (y == 0 || y == ry - 1);
+      if (D >= 3) ring = ring || (z == 0 || z == rz - 1);
+      if (!ring) inner |= (1u << k);
+      const int gx = wrap_idx(ox + x, a.nx);
+      const int gy = (D >= 2) ? wrap_idx(oy + y, a.ny) : 0;
+      const int gz = (D >= 3) ? wrap_idx(oz + z, a.nz) : 0;
+      const long long gi = (long long)gx + (long long)a.nx * (gy + (long long)a.ny * gz);
+      ru[k] = a.u_in[base + gi];
+      rp[k] = a.p_in[base + gi];
+      rc[k] = a.c2[gi];
+      if (COMP && !a.first) {
+        reu[k] = a.eu_in[base + gi];
+        rep[k] = a.ep_in[base + gi];
+      }
+      su[i] = ru[k];
+    }
+  }
+  __syncthreads();
+
+  auto kick = [&](T w) {
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      if (inner & (1u << k)) {
+        const int i = tid + k * NT;
+        const T uc = ru[k];
+        T lap = su[i + 1] - T(2) * uc + su[i - 1];
+        if (D >= 2) lap += su[i + sy] - T(2) * uc + su[i - sy];
+        if (D >= 3) lap += su[i + sz] - T(2) * uc + su[i - sz];
+        kadd<T, COMP>(rp[k], rep[k], w * (rc[k] * (lap * a.idx2)));
+      }
+    }
+  };
+
+  for (int j = 0; j < a.nsteps; ++j) {
+    kick((a.first && j == 0) ? a.h * T(0.5) : a.h);
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      if (tid + k * NT < RN) kadd<T, COMP>(ru[k], reu[k], a.h * rp[k]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      const int i = tid + k * NT;
+      if (i < RN) su[i] = ru[k];
+    }
+    __syncthreads();
+  }
+  if (a.last) kick(a.h * T(0.5));
+
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int i = tid + k * NT;
+    if (i < RN) {
+      const int x = i % rx;
+      const int y = (i / rx) % ry;
+      const int z = i / sz;
+      bool in = (x >= H && x < H + a.tx);
+      if (D >= 2) in = in && (y >= H && y < H + a.ty);
+      if (D >= 3) in = in && (z >= H && z < H + a.tz);
+      const int gx = ox + x, gy = oy + y, gz = oz + z;
+      in = in && gx < a.nx && gy < a.ny && gz < a.nz;
+      if (in) {
+        const long long gi = (long long)gx + (long long)a.nx * (gy + (long long)a.ny * gz);
+        if (COMP && a.last) {
+          a.u_out[base + gi] = ru[k] - reu[k];
+          a.p_out[base + gi] = rp[k] - rep[k];
+        } else {
+          a.u_out[base + gi] = ru[k];
+          a.p_out[base + gi] = rp[k];
+          if (COMP) {
+            a.eu_out[base + gi] = reu[k];
+            a.ep_out[base + gi] = rep[k];
+          }
+        }
+      }
+    }
+  }
+}
+
+// tile geometry per dimension: interior and the largest halo of one launch
+struct TileCfg {
+  int tx, ty, tz, hmax;
+};
+constexpr TileCfg kTile1 = {1024, 1, 1, 9};
+constexpr TileCfg kTile2 = {64, 32, 1, 9};
+constexpr TileCfg kTile3 = {32, 8, 8, 2};
+constexpr int kNT = 256;
+
+constexpr int region_max(TileCfg c, int D) {
+  return (c.tx + 2 * c.hmax) * (D >= 2 ? c.ty + 2 * c.hmax : 1) *
+         (D >= 3 ? c.tz + 2 * c.hmax : 1);
+}
+constexpr int ppt_for(TileCfg c, int D) { return (region_max(c, D) + kNT - 1) / kNT; }
+
+template <typename T, bool COMP, int PPT>
+void launch_line(const PropArgs<T>& a, int nt, hipStream_t st) {
+  const size_t smem = sizeof(T) * (size_t)a.nx;
+  switch (nt) {
+    case 64:
+      hipLaunchKernelGGL((k_prop_line<T, COMP, 64, PPT>), dim3(a.nstates), dim3(64), smem, st, a);
+      break;
+    case 128:
+      hipLaunchKernelGGL((k_prop_line<T, COMP, 128, PPT>), dim3(a.nstates), dim3(128), smem, st,
+                         a);
+      break;
+    default:
+      hipLaunchKernelGGL((k_prop_line<T, COMP, 256, PPT>), dim3(a.nstates), dim3(256), smem, st,
+                         a);
+      break;
+  }
+  PW_LAUNCH_CHECK();
+}
+
+template <typename T, bool COMP>
+void dispatch_line(const PropArgs<T>& a, hipStream_t st) {
+  const int n = a.nx;
+  const int nt = n <= 64 ? 64 : (n <= 128 ? 128 : 256);
+  const int ppt = (n + nt - 1) / nt;
+  if (ppt <= 1)
+    launch_line<T, COMP, 1>(a, nt, st);
+  else if (ppt <= 2)
+    launch_line<T, COMP, 2>(a, nt, st);
+  else if (ppt <= 4)
+    launch_line<T, COMP, 4>(a, nt, st);
+  else if (ppt <= 8)
+    launch_line<T, COMP, 8>(a, nt, st);
+  else if (ppt <= 16)
+    launch_line<T, COMP, 16>(a, nt, st);
+  else
+    fail(PW_EINVAL, "1D line longer than 4096 points");
+}
+
+template <typename T, int D, bool COMP>
+void dispatch_tile(PropArgs<T> a, hipStream_t st) {
+  constexpr TileCfg c = D == 1 ? kTile1 : (D == 2 ? kTile2 : kTile3);
+  constexpr int PPT = ppt_for(c, D);
+  const long long blocks = (long long)a.ntx * a.nty * a.ntz * a.nstates;
+  const size_t smem = sizeof(T) * (size_t)a.rx * a.ry * a.rz;
+  hipLaunchKernelGGL((k_prop_tile<T, D, COMP, kNT, PPT>), dim3((unsigned)blocks), dim3(kNT), smem,
+                     st, a);
+  PW_LAUNCH_CHECK();
+}
+
+TileCfg tile_cfg(int dim) { return dim == 1 ? kTile1 : (dim == 2 ? kTile2 : kTile3); }
+
+bool use_line(const Grid& g) { return g.dim == 1 && g.n[0] <= 4096; }
+
+}  // namespace
+
+int steps_per_launch(const Grid& g, bool /*is_double*/) {
+  if (use_line(g)) return 1 << 30;
+  return tile_cfg(g.dim).hmax - 1;
+}
+
+template <typename T>
+void propagate(const Grid& g, const T* c2, const T* u_src, const T* p_src, T* u_dst, T* p_dst,
+               long long sstride, int nstates, int m, T h, bool compensated, StateSet<T> wa,
+               StateSet<T> wb, hipStream_t st) {
+  if (nstates <= 0) return;
+  if (m <= 0) {
+    for (int s = 0; s < nstates; ++s) {
+      PW_HIP(hipMemcpyAsync(u_dst + (long long)s * sstride, u_src + (long long)s * sstride,
+                            sizeof(T) * g.npts(), hipMemcpyDeviceToDevice, st));
+      PW_HIP(hipMemcpyAsync(p_dst + (long long)s * sstride, p_src + (long long)s * sstride,
+                            sizeof(T) * g.npts(), hipMemcpyDeviceToDevice, st));
+    }
+    return;
+  }
+  PropArgs<T> a{};
+  a.c2 = c2;
+  a.sstride = sstride;
+  a.nx = g.n[0];
+  a.ny = g.n[1];
+  a.nz = g.n[2];
+  a.nstates = nstates;
+  a.h = h;
+  a.idx2 = T(1.0 / (g.dx * g.dx));
+  const bool comp = compensated;
+  if (use_line(g)) {
+    a.u_in = u_src;
+    a.p_in = p_src;
+    a.u_out = u_dst;
+    a.p_out = p_dst;
+    a.nsteps = m;
+    a.first = 1;
+    a.last = 1;
+    if (comp) {
+      if constexpr (sizeof(T) == 4) dispatch_line<T, true>(a, st);
+      else fail(PW_EINVAL, "compensation is an FP32 mode");
+    } else {
+      dispatch_line<T, false>(a, st);
+    }
+    return;
+  }
+  const TileCfg c = tile_cfg(g.dim);
+  const int b = c.hmax - 1;
+  const int nl = (m + b - 1) / b;
+  a.tx = std::min(c.tx, a.nx);
+  a.ty = g.dim >= 2 ? std::min(c.ty, a.ny) : 1;
+  a.tz = g.dim >= 3 ? std::min(c.tz, a.nz) : 1;
+  a.ntx = (a.nx + a.tx - 1) / a.tx;
+  a.nty = (a.ny + a.ty - 1) / a.ty;
+  a.ntz = (a.nz + a.tz - 1) / a.tz;
+  if ((long long)a.ntx * a.nty * a.ntz * nstates >= (1LL << 31))
+    fail(PW_EINVAL, "too many tiles for one launch");
+  if (nl > 1 && (wa.u == nullptr || wb.u == nullptr || (comp && (wa.eu == nullptr || wb.eu == nullptr))))
+    fail(PW_EINVAL, "propagation needs scratch state sets");
+  const T* cu = u_src;
+  const T* cp = p_src;
+  const T* ceu = nullptr;
+  const T* cep = nullptr;
+  for (int l = 0; l < nl; ++l) {
+    const int steps = std::min(b, m - l * b);
+    a.first = (l == 0);
+    a.last = (l == nl - 1);
+    a.nsteps = steps;
+    a.H = steps + a.last;
+    a.rx = a.tx + 2 * a.H;
+    a.ry = g.dim >= 2 ? a.ty + 2 * a.H : 1;
+    a.rz = g.dim >= 3 ? a.tz + 2 * a.H : 1;
+    a.u_in = cu;
+    a.p_in = cp;
+    a.eu_in = ceu;
+    a.ep_in = cep;
+    StateSet<T> out;
+    if (a.last) {
+      out.u = u_dst;
+      out.p = p_dst;
+    } else {
+      out = ((nl - 1 - l) % 2 == 1) ? wa : wb;
+    }
+    a.u_out = out.u;
+    a.p_out = out.p;
+    a.eu_out = out.eu;
+    a.ep_out = out.ep;
+    if (comp) {
+      if constexpr (sizeof(T) == 4) {
+        if (g.dim == 1) dispatch_tile<T, 1, true>(a, st);
+        else if (g.dim == 2) dispatch_tile<T, 2, true>(a, st);
+        else dispatch_tile<T, 3, true>(a, st);
+      } else {
+        fail(PW_EINVAL, "compensation is an FP32 mode");
+      }
+    } else {
+      if (g.dim == 1) dispatch_tile<T, 1, false>(a, st);
+      else if (g.dim == 2) dispatch_tile<T, 2, false>(a, st);
+      else dispatch_tile<T, 3, false>(a, st);
+    }
+    cu = out.u;
+    cp = out.p;
+    ceu = out.eu;
+    cep = out.ep;
+  }
+}
+
+template void propagate<float>(const Grid&, const float*, const float*, const float*, float*,
+                               float*, long long, int, int, float, bool, StateSet<float>,
+                               StateSet<float>, hipStream_t);
+template void propagate<double>(const Grid&, const double*, const double*, const double*,
+                                double*, double*, long long, int, int, double, bool,
+                                StateSet<double>, StateSet<double>, hipStream_t);
+
+}  // namespace pw
