@@ -28,7 +28,8 @@ inline unsigned nblocks(long long n, int tb = kTB) { return (unsigned)((n + tb -
 // ---------------------------------------------------------------------------
 // MFMA GEMMs.  Operand layout of v_mfma_f64_16x16x4f64 (64 lanes):
 //   lane l supplies A[m = l%16][k = l/16] and B[k = l/16][n = l%16];
-//   the 16x16 result lives in 4 doubles per lane: D[4*(l/16) + v][l%16].
+//   the 16x16 result lives in 4 doubles per lane: D[4*v + l/16][l%16]
+//   (rows interleaved across the four lane groups).
 // ---------------------------------------------------------------------------
 constexpr int TBM = 64, TBN = 64;
 
@@ -83,7 +84,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn(long long rows, int a, int b, c
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int m = m0 + wm + i * 16 + 4 * (lane / 16) + v;
+        const int m = m0 + wm + i * 16 + 4 * v + lane / 16;
         const int n = n0 + wn + j * 16 + lane % 16;
         if (m < a && n < b) P[m + (long long)n * a] = acc[i][j][v];
       }
@@ -153,7 +154,7 @@ __global__ __launch_bounds__(256) void k_gemm_nn(long long rows, int n, int k, d
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const long long m = m0 + wm + i * 16 + 4 * (lane / 16) + v;
+        const long long m = m0 + wm + i * 16 + 4 * v + lane / 16;
         const int nn = n0 + wn + j * 16 + lane % 16;
         if (m < rows && nn < n) {
           double* c = C + m + (long long)nn * ldc;
