@@ -1,0 +1,242 @@
+"""Benchmark of the MI355X parareal-like wave solver (one GPU).
+
+A step is one full solve of Algorithm 3 (coarse initialisation + K
+iterations: batched fine propagation over all slices, Procrustes corrector,
+corrected sweep, interpolation and update) on the disc2d workload: 2D
+periodic 512^2 fine / 128^2 coarse grid, c = 1 with c = 2 inside a disc of
+radius 0.2, Gaussian pulse (sigma 0.03) at (0.3, 0.5), T = 2, N = 64 slices,
+m_F = 64, m_C = 16, K = 8, FP32 compensated state, FP64 corrector,
+svd tol 1e-13.  Inputs are synthetic and already resident in HBM when the
+timed region starts.
+
+value = fine point-updates of the K batched fine sweeps (K * N * m_F *
+512^2 per step) / wall time of the steps, in Gpoint-updates/s.
+
+Also reported: the roofline of the fine stencil kernel (algorithmic 20 B
+per FP32 point-update: read u, p, c^2, write u, p), the serial GPU fine
+solve and the time to reach 1e-5 energy error against it, the per-phase
+split, and the FP64 oracle timed on the host on a bounded sample.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_UPDATE_F32 = 20
+# HBM bytes per launch of the fine stencil kernel, from the two rocprofv3
+# --pmc runs (FETCH_SIZE, WRITE_SIZE) of `bench.py --traffic-probe`, scaled
+# by the same counters on a 512 MiB copy (profiles/disc2d_fine_stencil_
+# traffic.md).  Valid only for the stencil revision it was measured on.
+TRAFFIC = {"stencil-r2": 582.3e6}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """Oracle fine propagator (numpy FP64, one process) on a bounded sample
+    of the workload: as many slices of the first fine sweep as fit in about
+    `budget_s` seconds."""
+    import numpy as np
+
+    import oracle as O
+    c2 = w.c * w.c
+    dx = 1.0 / w.shape[-1]
+    h = w.T / w.N / w.m_fine
+    u, p = w.u0.copy(), w.p0.copy()
+    t0 = time.perf_counter()
+    slices = 0
+    while time.perf_counter() - t0 < budget_s and slices < w.N:
+        u, p = O.propagate(u, p, c2, h, dx, w.m_fine)
+        slices += 1
+    dt = time.perf_counter() - t0
+    upd = slices * w.m_fine * w.npts
+    return {"value": round(upd / dt / 1e9, 5), "unit": "Gpoint-updates/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"oracle fine propagator F (numpy FP64, 1 thread) on "
+                      f"{slices} of the {w.N} slices of one fine sweep "
+                      f"({slices * w.m_fine} steps of 512^2), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-ttt", action="store_true",
+                    help="skip the time-to-1e-5 study")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only run one fine sweep and one 512 MiB device "
+                         "copy (for rocprofv3 --pmc FETCH_SIZE/WRITE_SIZE)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (--gpus 1); "
+              "multi-GPU sharding is described in DESIGN.md but not built",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1905_00473_amd as pw
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    w = W.disc2d()
+    K = w.K
+    P = pw.Problem.make(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
+                        w.grad_order, w.tol, "f32", True, K)
+    s = pw.Solver(P)
+    s.set_medium(w.c)
+    s.set_initial(w.u0, w.p0)
+    torch.cuda.synchronize()
+    log("context ready")
+    if args.traffic_probe:
+        u = torch.empty((w.N,) + w.shape, dtype=torch.float32, device="cuda")
+        p = torch.empty_like(u)
+        for n in range(w.N):
+            u[n], p[n] = s.state(n)
+        s.propagate(u, p)
+        src = torch.ones(128 * 1024 * 1024, dtype=torch.float32,
+                         device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)  # plain copy: 512 MiB read + 512 MiB written
+        torch.cuda.synchronize()
+        log("traffic probe done: 8 fine launches, one 536870912-byte copy")
+        s.close()
+        return
+
+    # ---- timed region: full solves --------------------------------------
+    for _ in range(args.warmup):
+        s.run(K)
+    torch.cuda.synchronize()
+    log("warmup done")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.run(K)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    upd_step = K * w.N * w.m_fine * w.npts
+    value = upd_step / (ms_step * 1e-3) / 1e9
+    phases = s.timings()
+    rho, ranks = s.residuals()
+    log(f"solve {ms_step:.2f} ms/step")
+
+    # ---- fine stencil kernel: the batched F sweep alone ------------------
+    stencil_rev = pw.lib().pw_version().decode().split()[-1]
+    dt = torch.float32
+    u = torch.empty((w.N,) + w.shape, dtype=dt, device="cuda")
+    p = torch.empty_like(u)
+    for n in range(w.N):
+        u[n], p[n] = s.state(n)
+    uo, po = s.propagate(u, p)  # warm
+    reps = 10
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        s.propagate(u, p)
+    ev1.record()
+    torch.cuda.synchronize()
+    f_ms = ev0.elapsed_time(ev1) / reps
+    steps_per_launch = 8
+    launches = math.ceil(w.m_fine / steps_per_launch)
+    launch_ms = f_ms / launches
+    bytes_per_launch = BYTES_PER_UPDATE_F32 * w.N * w.npts * steps_per_launch
+    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
+    f_gupd = w.N * w.m_fine * w.npts / (f_ms * 1e-3) / 1e9
+    log(f"F sweep {f_ms:.3f} ms ({f_gupd:.1f} Gupd/s)")
+
+    # ---- serial fine and time to 1e-5 -------------------------------------
+    ttt = None
+    serial_ms = None
+    if not args.no_ttt:
+        uf, pf = s.serial_fine(w.N)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            s.serial_fine(w.N)
+        e1.record()
+        torch.cuda.synchronize()
+        serial_ms = e0.elapsed_time(e1) / 3
+        errs = []
+        for k in range(0, K + 1):
+            s.run(k)
+            uN, pN = s.state(w.N)
+            ed, er = s.energy(uN, pN, uf, pf)
+            errs.append(math.sqrt(ed / er) if er > 0 else math.sqrt(ed))
+        log("errors per iteration: " + " ".join(f"{e:.2e}" for e in errs))
+        kstar = next((k for k, e in enumerate(errs) if e <= 1e-5), None)
+        if kstar is not None:
+            ts = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                s.run(kstar)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - a)
+            par_ms = min(ts) * 1e3
+        else:
+            par_ms = None
+        ttt = {"target": 1e-5, "reached_at_iteration": kstar,
+               "parareal_ms": par_ms, "serial_fine_ms": round(serial_ms, 3),
+               "speedup_vs_serial": (round(serial_ms / par_ms, 4)
+                                     if par_ms else None),
+               "energy_error_per_iteration": [float(f"{e:.4e}")
+                                              for e in errs],
+               "plateau": float(f"{min(errs):.4e}")}
+
+    cpu = None if args.no_cpu else cpu_baseline(w)
+
+    out = {
+        "metric": "batched fine-prop Gpoint-updates/s (%HBM roof) + "
+                  "parareal time-to-1e-5 vs serial",
+        "value": round(value, 3),
+        "unit": "Gpoint-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "disc2d: 2D periodic 512^2 fine / 128^2 "
+                               "coarse, disc c=2 in c=1, N=64 slices, "
+                               "m_F=64, m_C=16, K=8, T=2, tol 1e-13",
+                   "state": "f32 compensated", "corrector": "f64",
+                   "step": "one full parareal solve (init + K iterations)"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": TRAFFIC.get(stencil_rev),
+                     "kernel": "k_prop_stream2d<float, true, 8, 0> (fine grid)",
+                     "launch_ms": round(launch_ms, 4),
+                     "algorithmic_bytes_per_launch": bytes_per_launch},
+        "fine_sweep": {"ms": round(f_ms, 4), "gupd_s": round(f_gupd, 2),
+                       "launches": launches},
+        "phases_ms": {k: round(v, 3) for k, v in phases.items()},
+        "rho": [float(f"{r:.4e}") for r in rho],
+        "rank": ranks,
+        "time_to_1e-5": ttt,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
+if __name__ == "__main__":
+    main()

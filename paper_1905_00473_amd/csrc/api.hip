@@ -124,9 +124,11 @@ struct Prob {
   int* counters = nullptr;
   int* rank_dev = nullptr;
   double *M = nullptr, *Bn = nullptr, *Tn = nullptr;
+  RecScratch rs;
   double* ctmp = nullptr;   // complex DFT scratch
   double* itmp = nullptr;   // interpolation scratch
   double* gwork = nullptr;  // split-K partials
+  size_t gwork_elems = 0;
   double* red = nullptr;    // reduction partials
   double* res = nullptr;    // per-iteration [||F - Omega G||^2, ||F||^2]
   OrthScratch os;
@@ -274,7 +276,7 @@ void setup(Prob& pr, const pw_problem& P) {
   pr.H = m.get_n<double>(cap * cap);
   pr.X = m.get_n<double>(cap * cap);
   pr.Y = m.get_n<double>(cap * cap);
-  pr.sig = m.get_n<double>(cap);
+  pr.sig = m.get_n<double>(std::max<long long>(cap, 512));  // also reduction partials
   pr.Hw = m.get_n<double>(cap * cap + 2 * cap + 16);
   pr.Vw = m.get_n<double>(cap * cap);
   pr.counters = m.get_n<int>(64);
@@ -282,16 +284,17 @@ void setup(Prob& pr, const pw_problem& P) {
   pr.M = m.get_n<double>((long long)(pr.rmax + 1) * (pr.rmax + 1));
   pr.Bn = m.get_n<double>((long long)(pr.rmax + 1) * N);
   pr.Tn = m.get_n<double>((long long)(pr.rmax + 1) * N);
+  pr.rs.P0 = m.get_n<double>((long long)(pr.rmax + 1) * (pr.rmax + 1));
+  pr.rs.P1 = m.get_n<double>((long long)(pr.rmax + 1) * (pr.rmax + 1));
+  pr.rs.ta = m.get_n<double>((long long)(pr.rmax + 1) * N);
+  pr.rs.tb = m.get_n<double>((long long)(pr.rmax + 1) * N);
   const int gcols = std::max(N, 1);
   pr.ctmp = m.get_n<double>(4LL * P.dim * Nc * gcols);
   pr.itmp = m.get_n<double>(2LL * (Nf + Nf) * N + 16);
-  // split-K partials: the largest A^T B of the path
-  size_t gw = 0;
-  gw = std::max(gw, gemm_tn_work(rows, (int)cap, N));
-  gw = std::max(gw, gemm_tn_work(rows, N, N));
-  gw = std::max(gw, gemm_tn_work(2 * Nc, pr.rmax + 1, pr.rmax + 1));
-  gw = std::max(gw, gemm_tn_work(2 * Nc, pr.rmax + 1, N));
-  pr.gwork = m.get_n<double>((long long)gw + 16);
+  // split-K partials: bound over every A^T B shape of the path
+  // (a <= cap, b <= max(cap, N))
+  pr.gwork_elems = gemm_tn_work_bound((int)cap, (int)std::max<long long>(cap, N));
+  pr.gwork = m.get_n<double>((long long)pr.gwork_elems);
   pr.red = m.get_n<double>(4096);
   pr.res = m.get_n<double>(2LL * (P.max_iters + 1));
   pr.os.gram = m.get_n<double>((long long)N * N);
@@ -301,6 +304,7 @@ void setup(Prob& pr, const pw_problem& P) {
   pr.os.R1 = m.get_n<double>((long long)N * N);
   pr.os.Q1 = m.get_n<double>(rows * N);
   pr.os.work = pr.gwork;
+  pr.os.work_elems = pr.gwork_elems;
   for (int i = 0; i < 4; ++i) PW_HIP(hipEventCreate(&pr.ev[i]));
 }
 
@@ -322,7 +326,7 @@ template <typename T>
 void prop_fine(Prob& pr, const T* u, const T* p, T* uo, T* po, int n, hipStream_t st) {
   if (n > pr.N) fail(PW_EINVAL, "too many fine states for one batched propagation");
   propagate<T>(pr.gf, tp<T>(pr.c2f), u, p, uo, po, pr.Nf, n, pr.mF, (T)pr.hF, pr.comp,
-               fine_work<T>(pr, 0), fine_work<T>(pr, 1), st);
+               fine_work<T>(pr, 0), fine_work<T>(pr, 1), st, true);
 }
 
 template <typename T>
@@ -335,6 +339,7 @@ void prop_coarse(Prob& pr, const T* u, const T* p, T* uo, T* po, int n, hipStrea
 // FP64 coarse propagation of state columns [u (Nc) ; p (Nc)] (linear C)
 void prop_coarse_cols(Prob& pr, const double* in, double* out, int ncols, hipStream_t st) {
   const long long Nc = pr.Nc;
+  if (ncols > std::max(pr.rmax + 1, pr.N)) fail(PW_EINVAL, "too many coarse columns");
   StateSet<double> a{pr.dw[0], pr.dw[0] + Nc, nullptr, nullptr};
   StateSet<double> b{pr.dw[1], pr.dw[1] + Nc, nullptr, nullptr};
   propagate<double>(pr.gc, pr.c2c_d, in, in + Nc, out, out + Nc, 2 * Nc, ncols, pr.mC, pr.hC,
@@ -366,9 +371,9 @@ void add_inplace(double* a, const double* b, long long n, hipStream_t st) {
 // accumulating the coefficients in C (r x n): X <- X - B (B^T X)
 void project_out(Prob& pr, long long rows, int r, int n, const double* B, double* X, double* C,
                  double* C2, hipStream_t st) {
-  gemm_tn(rows, r, n, 1.0, B, rows, X, rows, 0.0, C, r, pr.gwork, st);
+  gemm_tn(rows, r, n, 1.0, B, rows, X, rows, 0.0, C, r, pr.gwork, pr.gwork_elems, st);
   gemm_nn(rows, n, r, -1.0, B, rows, C, r, 1.0, X, rows, st);
-  gemm_tn(rows, r, n, 1.0, B, rows, X, rows, 0.0, C2, r, pr.gwork, st);
+  gemm_tn(rows, r, n, 1.0, B, rows, X, rows, 0.0, C2, r, pr.gwork, pr.gwork_elems, st);
   gemm_nn(rows, n, r, -1.0, B, rows, C2, r, 1.0, X, rows, st);
   // C += C2 (both r x n, contiguous)
   add_inplace(C, C2, (long long)r * n, st);
@@ -514,7 +519,7 @@ void run_typed(Prob& pr, int K, hipStream_t st) {
       // rho_k: || F - U (V^T G) ||_F / ||F||_F
       const int r = pr.r;
       gemm_tn(rows, r, N, 1.0, pr.Vb[pr.cur], rows, pr.Gm, rows, 0.0, pr.UF, std::max(r, 1),
-              pr.gwork, st);
+              pr.gwork, pr.gwork_elems, st);
       PW_HIP(hipMemcpyAsync(pr.Fp, pr.Fm, sizeof(double) * rows * N, hipMemcpyDeviceToDevice, st));
       gemm_nn(rows, N, r, -1.0, pr.Ub[pr.cur], rows, pr.UF, std::max(r, 1), 1.0, pr.Fp, rows, st);
       frob_norm2(pr.Fp, rows, N, rows, pr.red, pr.res + 2 * (k - 1), st);
@@ -532,9 +537,10 @@ void run_typed(Prob& pr, int K, hipStream_t st) {
                        N - 1, st);
     prop_coarse_cols(pr, pr.Din, pr.Acol, N, st);
     prop_coarse_cols(pr, E, pr.CE, dim, st);
-    gemm_tn(2 * Nc, dim, dim, 1.0, P, 2 * Nc, pr.CE, 2 * Nc, 0.0, pr.M, dim, pr.gwork, st);
-    gemm_tn(2 * Nc, dim, N, 1.0, P, 2 * Nc, pr.Acol, 2 * Nc, 0.0, pr.Bn, dim, pr.gwork, st);
-    recurrence(dim, N, pr.M, pr.Bn, pr.Tn, st);
+    gemm_tn(2 * Nc, dim, dim, 1.0, P, 2 * Nc, pr.CE, 2 * Nc, 0.0, pr.M, dim, pr.gwork, pr.gwork_elems, st);
+    gemm_tn(2 * Nc, dim, N, 1.0, P, 2 * Nc, pr.Acol, 2 * Nc, 0.0, pr.Bn, dim, pr.gwork, pr.gwork_elems, st);
+    if (dim > pr.rmax + 1) fail(PW_EINVAL, "corrector rank exceeds its capacity");
+    recurrence(dim, N, pr.M, pr.Bn, pr.Tn, pr.rs, st);
     gemm_nn(2 * Nc, N, dim, 1.0, E, 2 * Nc, pr.Tn, dim, 0.0, pr.delta, 2 * Nc, st);
     // 4. u^{k+1}_n = v_n + I(delta_n), n = 1..N
     split_cast<T>(pr.delta, 2 * Nc, Nc, N, tp<T>(pr.du_T), tp<T>(pr.dp_T), st);
@@ -663,7 +669,9 @@ extern "C" {
 
 const char* pw_last_error(void) { return g_last_error.c_str(); }
 
-const char* pw_version(void) { return "pwave 0.1 (gfx950)"; }
+// the last word names the revision of the fine stencil kernel (bench.py
+// keys measured HBM traffic on it)
+const char* pw_version(void) { return "pwave 0.2 (gfx950) stencil-r2"; }
 
 int pw_num_problems(const pw_ctx* ctx) { return ctx ? (int)ctx->probs.size() : 0; }
 

@@ -10,9 +10,12 @@
 //  * one-sided (Hestenes) Jacobi SVD of the small core matrix H of
 //    Algorithm 1 with round-robin pair ordering, singular values sorted and
 //    the rank counted on the device;
-//  * the (r+1)-dimensional linear recurrence of the corrected sweep.
+//  * the (r+1)-dimensional linear recurrence of the corrected sweep, as a
+//    doubling scan of matrix-core GEMMs.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "pw_internal.h"
@@ -188,7 +191,7 @@ __device__ __forceinline__ int rr_index(int j, int round, int np) {
   return j == 0 ? 0 : ((j - 1 + round) % (np - 1)) + 1;
 }
 
-__global__ __launch_bounds__(256) void k_sym_eig(int n, double* Ag, int lda, double* Wg,
+__global__ __launch_bounds__(1024) void k_sym_eig(int n, double* Ag, int lda, double* Wg,
                                                   double* lam) {
   __shared__ double A[kEigMax][kEigMax + 1];
   __shared__ double W[kEigMax][kEigMax + 1];
@@ -201,6 +204,12 @@ __global__ __launch_bounds__(256) void k_sym_eig(int n, double* Ag, int lda, dou
     const int i = t % np, j = t / np;
     A[i][j] = (i < n && j < n) ? Ag[i + (long long)j * lda] : 0.0;
     W[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  __shared__ double noise;
+  if (tid == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < n; ++i) tr += fabs(A[i][i]);
+    noise = 2.3e-16 * tr;  // eigenvalues below this are rounding noise
   }
   __syncthreads();
   const int npairs = np / 2;
@@ -219,8 +228,10 @@ __global__ __launch_bounds__(256) void k_sym_eig(int n, double* Ag, int lda, dou
         double c = 1.0, s = 0.0;
         const double apq = A[p][q];
         const double app = A[p][p], aqq = A[q][q];
+        // rotate only above the rounding noise of the entries (~ n eps)
         if (p < n && q < n && apq != 0.0 &&
-            fabs(apq) > 1e-15 * sqrt(fabs(app) * fabs(aqq))) {
+            fabs(apq) > 2.3e-16 * n * sqrt(fabs(app) * fabs(aqq)) &&
+            (fabs(app) > noise || fabs(aqq) > noise)) {
           const double tau = (aqq - app) / (2.0 * apq);
           const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           c = 1.0 / sqrt(1.0 + t * t);
@@ -303,7 +314,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 __global__ __launch_bounds__(256) void k_jacobi_round(int n, int np, int round, double* H,
-                                                       double* V, int* counter) {
+                                                       double* V, int* counter,
+                                                       const double* fro2) {
   const int lane = threadIdx.x & 63;
   const int pair = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (pair >= np / 2) return;
@@ -327,7 +339,13 @@ __global__ __launch_bounds__(256) void k_jacobi_round(int n, int np, int round, 
   al = wave_sum(al);
   be = wave_sum(be);
   ga = wave_sum(ga);
-  if (ga == 0.0 || fabs(ga) <= 1e-15 * sqrt(al * be)) return;
+  // skip pairs already orthogonal to the rounding level of the dot
+  // products (4 sqrt(n) eps, as one-sided Jacobi codes commonly use), and
+  // pairs of two columns that are both rounding noise of H (norm below
+  // eps ||H||_F: they carry singular values below any rank tolerance)
+  const double noise2 = 4.9e-32 * (*fro2);
+  if (ga == 0.0 || fabs(ga) <= 4.5e-16 * sqrt((double)n) * sqrt(al * be)) return;
+  if (al < noise2 && be < noise2) return;
   const double zeta = (be - al) / (2.0 * ga);
   const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
   const double c = 1.0 / sqrt(1.0 + t * t);
@@ -405,44 +423,6 @@ __global__ void k_identity(int n, double* V) {
   V[t] = (t % n == t / n) ? 1.0 : 0.0;
 }
 
-// ---------------------------------------------------------------------------
-// t_1 = b_1; t_n = b_n + M t_{n-1}
-// ---------------------------------------------------------------------------
-constexpr int kRecMax = 8192;
-
-__global__ __launch_bounds__(1024) void k_recurrence(int dim, int N, const double* M,
-                                                      const double* b, double* t) {
-  __shared__ double prev[kRecMax];
-  for (int i = threadIdx.x; i < dim; i += blockDim.x) {
-    prev[i] = b[i];
-    t[i] = b[i];
-  }
-  __syncthreads();
-  for (int s = 1; s < N; ++s) {
-    double nv[kRecMax / 1024];
-#pragma unroll
-    for (int k = 0; k < kRecMax / 1024; ++k) {
-      const int i = threadIdx.x + k * 1024;
-      nv[k] = 0.0;
-      if (i < dim) {
-        double acc = b[(long long)s * dim + i];
-        for (int j = 0; j < dim; ++j) acc += M[i + (long long)j * dim] * prev[j];
-        nv[k] = acc;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kRecMax / 1024; ++k) {
-      const int i = threadIdx.x + k * 1024;
-      if (i < dim) {
-        prev[i] = nv[k];
-        t[(long long)s * dim + i] = nv[k];
-      }
-    }
-    __syncthreads();
-  }
-}
-
 __global__ void k_add_diag(int r, const double* S, double* H, int ldh) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < r) H[i + (long long)i * ldh] += S[i];
@@ -494,7 +474,12 @@ __global__ void k_sum(const double* partials, int nb, double* out) {
   if (threadIdx.x == 0) *out = s[0];
 }
 
-constexpr int kSplitTarget = 2048;
+constexpr int kSplitTarget = 512;
+
+bool debug_jacobi() {
+  static const bool on = getenv("PW_DEBUG_JACOBI") != nullptr;
+  return on;
+}
 constexpr int kTnBK = 32;
 constexpr int kNnBK = 16;
 
@@ -512,10 +497,18 @@ size_t gemm_tn_work(long long rows, int a, int b) {
   return (size_t)tn_splits(rows, a, b) * a * b;
 }
 
+size_t gemm_tn_work_bound(int a_max, int b_max) {
+  // splits <= ceil(target / tiles) <= target / tiles + 1 and
+  // a * b <= tiles * TBM * TBN, so splits * a * b <= target * TBM * TBN + a * b
+  return (size_t)kSplitTarget * TBM * TBN + (size_t)a_max * b_max;
+}
+
 void gemm_tn(long long rows, int a, int b, double alpha, const double* A, long long lda,
              const double* B, long long ldb, double beta, double* C, long long ldc, double* work,
-             hipStream_t st) {
+             size_t work_elems, hipStream_t st) {
   if (a <= 0 || b <= 0) return;
+  if (rows > 0 && gemm_tn_work(rows, a, b) > work_elems)
+    fail(PW_EINVAL, "gemm_tn: split-K scratch too small");
   if (rows <= 0) {
     // empty contraction: C = beta C
     for (int j = 0; j < b; ++j) {
@@ -575,21 +568,21 @@ void gemm_small(int m, int n, int k, double alpha, const double* A, int lda, boo
 void sym_eig(int n, double* A, int lda, double* W, double* lam, hipStream_t st) {
   if (n > kEigMax) fail(PW_EINVAL, "Gram eigen-solver supports at most 64 columns per block");
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_sym_eig, dim3(1), dim3(256), 0, st, n, A, lda, W, lam);
+  hipLaunchKernelGGL(k_sym_eig, dim3(1), dim3(1024), 0, st, n, A, lda, W, lam);
   PW_LAUNCH_CHECK();
 }
 
 void orth(long long rows, int n, const double* A, long long lda, double* Q, long long ldq,
           double* R, OrthScratch s, hipStream_t st) {
   // pass 1: Gram eigenvectors of A
-  gemm_tn(rows, n, n, 1.0, A, lda, A, lda, 0.0, s.gram, n, s.work, st);
+  gemm_tn(rows, n, n, 1.0, A, lda, A, lda, 0.0, s.gram, n, s.work, s.work_elems, st);
   sym_eig(n, s.gram, n, s.W, s.lam, st);
   hipLaunchKernelGGL(k_orth_factors, dim3(1), dim3(kTB), 0, st, n, (const double*)s.W,
                      (const double*)s.lam, 1e-13, 1e-290, s.T, s.R1);
   PW_LAUNCH_CHECK();
   gemm_nn(rows, n, n, 1.0, A, lda, s.T, n, 0.0, s.Q1, rows, st);
   // pass 2: re-orthonormalise Q1 (its Gram is the identity up to rounding)
-  gemm_tn(rows, n, n, 1.0, s.Q1, rows, s.Q1, rows, 0.0, s.gram, n, s.work, st);
+  gemm_tn(rows, n, n, 1.0, s.Q1, rows, s.Q1, rows, 0.0, s.gram, n, s.work, s.work_elems, st);
   sym_eig(n, s.gram, n, s.W, s.lam, st);
   double* R2 = s.gram;  // gram is consumed by sym_eig; reuse as R2
   hipLaunchKernelGGL(k_orth_factors, dim3(1), dim3(kTB), 0, st, n, (const double*)s.W,
@@ -613,15 +606,18 @@ void svd_jacobi(int n, const double* H, double* X, double* Y, double* sig, doubl
   const int maxsweeps = 40;
   PW_HIP(hipMemsetAsync(counters, 0, sizeof(int) * maxsweeps, st));
   const unsigned blocks = (unsigned)((np / 2 + 3) / 4);
+  double* fro2 = Hw + nn + 2 * n + 8;  // scratch slot after the sort workspace
+  frob_norm2(Hw, n, n, n, sig, fro2, st);  // sig used as partials (>= 512 doubles)
   for (int sw = 0; sw < maxsweeps; ++sw) {
     for (int round = 0; round < np - 1; ++round) {
       hipLaunchKernelGGL(k_jacobi_round, dim3(blocks), dim3(256), 0, st, n, np, round, Hw, Vw,
-                         counters + sw);
+                         counters + sw, (const double*)fro2);
       PW_LAUNCH_CHECK();
     }
     int h = 0;
     PW_HIP(hipMemcpyAsync(&h, counters + sw, sizeof(int), hipMemcpyDeviceToHost, st));
     PW_HIP(hipStreamSynchronize(st));
+    if (debug_jacobi()) fprintf(stderr, "[jacobi n=%d] sweep %d: %d rotations\n", n, sw, h);
     if (h == 0) break;
   }
   double* sig_u = Hw + nn;  // Hw has n*n + 2n doubles of room
@@ -636,11 +632,30 @@ void svd_jacobi(int n, const double* H, double* X, double* Y, double* sig, doubl
   PW_LAUNCH_CHECK();
 }
 
-void recurrence(int dim, int N, const double* M, const double* b, double* t, hipStream_t st) {
-  if (dim > kRecMax) fail(PW_EINVAL, "corrector rank too large for the sweep recurrence");
+void recurrence(int dim, int N, const double* M, const double* b, double* t, RecScratch rs,
+                hipStream_t st) {
+  // Hillis-Steele doubling: with t^(0)_n = b_n and P = M,
+  //   t^(l+1)_n = t^(l)_n + P^(2^l) t^(l)_{n - 2^l}   (n >= 2^l)
+  // gives t_n = sum_{j <= n} M^(n-j) b_j after ceil(log2 N) levels; each
+  // level is one matrix-core GEMM (and one squaring of P).
   if (dim <= 0 || N <= 0) return;
-  hipLaunchKernelGGL(k_recurrence, dim3(1), dim3(1024), 0, st, dim, N, M, b, t);
-  PW_LAUNCH_CHECK();
+  const long long dn = (long long)dim * N;
+  double* ta = rs.ta;
+  double* tb = rs.tb;
+  double* P = rs.P0;
+  double* Pn = rs.P1;
+  PW_HIP(hipMemcpyAsync(ta, b, sizeof(double) * dn, hipMemcpyDeviceToDevice, st));
+  PW_HIP(hipMemcpyAsync(P, M, sizeof(double) * dim * dim, hipMemcpyDeviceToDevice, st));
+  for (int s = 1; s < N; s *= 2) {
+    PW_HIP(hipMemcpyAsync(tb, ta, sizeof(double) * dn, hipMemcpyDeviceToDevice, st));
+    gemm_nn(dim, N - s, dim, 1.0, P, dim, ta, dim, 1.0, tb + (long long)s * dim, dim, st);
+    std::swap(ta, tb);
+    if (2 * s < N) {
+      gemm_nn(dim, dim, dim, 1.0, P, dim, P, dim, 0.0, Pn, dim, st);
+      std::swap(P, Pn);
+    }
+  }
+  PW_HIP(hipMemcpyAsync(t, ta, sizeof(double) * dn, hipMemcpyDeviceToDevice, st));
 }
 
 void add_diag(int n, int r, const double* S, double* H, int ldh, hipStream_t st) {

@@ -54,10 +54,12 @@ struct StateSet {
   T* ep = nullptr;
 };
 
+// `fine` only selects which (otherwise identical) kernel instantiation is
+// launched, so that fine- and coarse-grid launches are told apart in traces.
 template <typename T>
 void propagate(const Grid& g, const T* c2, const T* u_src, const T* p_src, T* u_dst, T* p_dst,
                long long sstride, int nstates, int m, T h, bool compensated, StateSet<T> work_a,
-               StateSet<T> work_b, hipStream_t stream);
+               StateSet<T> work_b, hipStream_t stream, bool fine = false);
 
 // largest number of steps one launch of the tiled kernel may take for this
 // grid (the whole propagation when the grid is one periodic line in LDS)
@@ -141,10 +143,15 @@ void energy_pair(const Grid& fine, const T* u, const T* p, const T* uref, const 
 // C (a x b, ldc) = alpha * A^T B + beta * C with A (rows x a, lda),
 // B (rows x b, ldb), column-major.  FP64 MFMA, split over rows, fixed-order
 // reduction.  work: double scratch >= gemm_tn_work(rows, a, b).
+// work needed by one call, and an upper bound over every a <= a_max,
+// b <= b_max (the split count shrinks as the tile count grows, so the
+// per-call need is not monotonic in a or b).  gemm_tn fails if work_elems
+// is too small for the call.
 size_t gemm_tn_work(long long rows, int a, int b);
+size_t gemm_tn_work_bound(int a_max, int b_max);
 void gemm_tn(long long rows, int a, int b, double alpha, const double* A, long long lda,
              const double* B, long long ldb, double beta, double* C, long long ldc, double* work,
-             hipStream_t stream);
+             size_t work_elems, hipStream_t stream);
 
 // C (rows x n, ldc) = alpha * A (rows x k, lda) B (k x n, ldb) + beta * C.
 // FP64 MFMA.  C must not overlap A or B (it may be read when beta != 0).
@@ -173,6 +180,7 @@ struct OrthScratch {
   double* R1 = nullptr;     // n*n
   double* Q1 = nullptr;     // rows*n
   double* work = nullptr;   // gemm_tn work
+  size_t work_elems = 0;
 };
 void orth(long long rows, int n, const double* A, long long lda, double* Q, long long ldq,
           double* R, OrthScratch s, hipStream_t stream);
@@ -180,13 +188,21 @@ void orth(long long rows, int n, const double* A, long long lda, double* Q, long
 // one-sided Jacobi SVD of the n x n matrix H (column-major, ld = n):
 // on return X (n x n, ld n) holds left singular vectors, Y right singular
 // vectors, sig singular values, sorted descending; *rank_dev the number
-// with sig/sig_max > tol.  Scratch: Hw, Vw (n*n each), counters (int).
+// with sig/sig_max > tol.  Scratch: Hw (n*n + 2n + 16), Vw (n*n),
+// counters (40 ints); sig must hold max(n, 512) doubles.
 void svd_jacobi(int n, const double* H, double* X, double* Y, double* sig, double tol,
                 int* rank_dev, double* Hw, double* Vw, int* counters, hipStream_t stream);
 
 // linear recurrence t_1 = b_1, t_n = b_n + M t_{n-1} (t, b: dim x N
-// column-major, M: dim x dim).  One workgroup.
-void recurrence(int dim, int N, const double* M, const double* b, double* t,
+// column-major, M: dim x dim).  Scratch: two dim x dim matrices and two
+// dim x N blocks.
+struct RecScratch {
+  double* P0 = nullptr;
+  double* P1 = nullptr;
+  double* ta = nullptr;
+  double* tb = nullptr;
+};
+void recurrence(int dim, int N, const double* M, const double* b, double* t, RecScratch rs,
                 hipStream_t stream);
 
 // H = [Ua; Ra][Vb; Rb]^T + diag(S, 0): (r+N) x (r+N) helper pieces

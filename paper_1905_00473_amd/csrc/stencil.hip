@@ -7,10 +7,12 @@
 // launch of a slice closes with a half kick.  Between launches of the same
 // slice the carried momentum is the half-step one.
 //
-// Two kernels:
+// Three kernels:
 //  * k_prop_line: a 1D periodic line lives entirely in LDS; all steps of a
 //    propagation run in one launch (no halo).
-//  * k_prop_tile: 2D/3D (and long 1D) grids are cut into tiles; a tile plus
+//  * k_prop_stream2d: 2D grids; each wavefront streams down its columns with
+//    the time steps of a launch pipelined in registers (see below).
+//  * k_prop_tile: 3D (and long 1D) grids are cut into tiles; a tile plus
 //    a halo of H = (steps in this launch) + (closing kick) points is loaded,
 //    every thread keeps u, p, c^2 (and the compensation terms) of its points
 //    in registers, u is mirrored in LDS for the neighbour reads, and the
@@ -265,6 +267,156 @@ __global__ __launch_bounds__(NT) void k_prop_tile(PropArgs<T> a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// 2D streaming kernel with register-pipelined time steps.
+//
+// One wavefront owns 64 consecutive columns x (periodic) and streams down a
+// segment of rows.  The B time steps of a launch are B pipeline stages held
+// in registers: at stream step t stage j turns level-j row t-j into level
+// j+1 row t-j, so a row enters at level 0 (read from memory) and leaves at
+// level B (written to memory).  Each stage keeps a three-row window of its
+// input level; the x neighbours come from the adjacent lanes, so the valid
+// lanes shrink by one per stage and the halo is H = B + 1 columns on each
+// side (the +1 for the closing half kick).  No LDS and no barriers.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Stream2dArgs {
+  const T* u_in;
+  const T* p_in;
+  const T* eu_in;
+  const T* ep_in;
+  T* u_out;
+  T* p_out;
+  T* eu_out;
+  T* ep_out;
+  const T* c2;
+  long long sstride;
+  int nx, ny;
+  int ncb, nseg, Ly;  // column blocks, row segments, rows per segment
+  int nstates;
+  T h, idx2;
+  int nsteps, first, last;
+};
+
+template <typename T>
+__device__ __forceinline__ T lane_up(T v) {  // value of lane - 1
+  return __shfl_up(v, 1, 64);
+}
+template <typename T>
+__device__ __forceinline__ T lane_down(T v) {  // value of lane + 1
+  return __shfl_down(v, 1, 64);
+}
+
+// TAG separates the fine-grid (0) and coarse-grid (1) instantiations in
+// profiles; the code is the same.
+template <typename T, bool COMP, int B, int TAG>
+__global__ __launch_bounds__(256) void k_prop_stream2d(Stream2dArgs<T> a) {
+  constexpr int H = B + 1;
+  constexpr int XV = 64 - 2 * H;  // output columns per wave
+  const int lane = threadIdx.x & 63;
+  const long long nwaves = (long long)a.nstates * a.ncb * a.nseg;
+  const long long nblk = (nwaves + 3) / 4;
+  long long blk = blockIdx.x;
+  if ((nblk & 7) == 0) blk = (blk & 7) * (nblk >> 3) + (blk >> 3);
+  const long long wid = blk * 4 + (threadIdx.x >> 6);
+  if (wid >= nwaves) return;
+  const int cb = (int)(wid % a.ncb);
+  const int seg = (int)((wid / a.ncb) % a.nseg);
+  const int state = (int)(wid / ((long long)a.ncb * a.nseg));
+  const int nx = a.nx, ny = a.ny;
+  const int xl = cb * XV - H + lane;  // logical column of this lane
+  const int gx = wrap_idx(xl, nx);
+  const bool out_lane = lane >= H && lane < 64 - H && (cb * XV + lane - H) < nx;
+  const int Y0 = seg * a.Ly;
+  const int Y1 = min(Y0 + a.Ly, ny);
+  const long long base = (long long)state * a.sstride;
+  const T h = a.h;
+  const int ns = a.nsteps;
+  // stage j window: level-j rows (r-1, r, r+1) with r = t - j
+  T wu[B + 1][3];
+  T wp[B + 1][2], we_u[B + 1][2], we_p[B + 1][2], wk[B + 1][2];
+#pragma unroll
+  for (int j = 0; j <= B; ++j) {
+    wu[j][0] = wu[j][1] = wu[j][2] = T(0);
+    wp[j][0] = wp[j][1] = we_u[j][0] = we_u[j][1] = T(0);
+    we_p[j][0] = we_p[j][1] = wk[j][0] = wk[j][1] = T(0);
+  }
+  for (int t = Y0 - H - 1; t < Y1 + H - 1; ++t) {
+    // level 0, row t+1
+    {
+      const int gy = wrap_idx(t + 1, ny);
+      const long long gi = base + (long long)gy * nx + gx;
+      wu[0][2] = a.u_in[gi];
+      wp[0][1] = a.p_in[gi];
+      wk[0][1] = a.c2[(long long)gy * nx + gx] * a.idx2;
+      if (COMP) {
+        we_u[0][1] = a.first ? T(0) : a.eu_in[gi];
+        we_p[0][1] = a.first ? T(0) : a.ep_in[gi];
+      }
+    }
+    // stages 0..B-1: kick + drift (stages past nsteps pass the row through)
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const T uc = wu[j][1];
+      T un = uc, pn = wp[j][0], eu = we_u[j][0], ep = we_p[j][0];
+      const T kj = wk[j][0];
+      if (j < ns) {
+        const T lap =
+            (lane_up(uc) - T(2) * uc + lane_down(uc)) + (wu[j][0] - T(2) * uc + wu[j][2]);
+        const T w = (j == 0 && a.first) ? h * T(0.5) : h;
+        kadd<T, COMP>(pn, ep, w * (kj * lap));
+        kadd<T, COMP>(un, eu, h * pn);
+      }
+      wu[j + 1][2] = un;
+      wp[j + 1][1] = pn;
+      we_u[j + 1][1] = eu;
+      we_p[j + 1][1] = ep;
+      wk[j + 1][1] = kj;
+      if (j == B - 1 && !a.last) {
+        const int orow = t - j;
+        if (out_lane && orow >= Y0 && orow < Y1) {
+          const long long gi = base + (long long)orow * nx + gx;
+          a.u_out[gi] = un;
+          a.p_out[gi] = pn;
+          if (COMP) {
+            a.eu_out[gi] = eu;
+            a.ep_out[gi] = ep;
+          }
+        }
+      }
+    }
+    // stage B: closing half kick of the slice, then fold and write
+    if (a.last) {
+      const T uc = wu[B][1];
+      const T lap =
+          (lane_up(uc) - T(2) * uc + lane_down(uc)) + (wu[B][0] - T(2) * uc + wu[B][2]);
+      T pn = wp[B][0], ep = we_p[B][0];
+      kadd<T, COMP>(pn, ep, h * T(0.5) * (wk[B][0] * lap));
+      const int orow = t - B;
+      if (out_lane && orow >= Y0 && orow < Y1) {
+        const long long gi = base + (long long)orow * nx + gx;
+        if (COMP) {
+          a.u_out[gi] = uc - we_u[B][0];
+          a.p_out[gi] = pn - ep;
+        } else {
+          a.u_out[gi] = uc;
+          a.p_out[gi] = pn;
+        }
+      }
+    }
+    // advance the windows by one row
+#pragma unroll
+    for (int j = 0; j <= B; ++j) {
+      wu[j][0] = wu[j][1];
+      wu[j][1] = wu[j][2];
+      wp[j][0] = wp[j][1];
+      we_u[j][0] = we_u[j][1];
+      we_p[j][0] = we_p[j][1];
+      wk[j][0] = wk[j][1];
+    }
+  }
+}
+
 // tile geometry per dimension: interior and the largest halo of one launch
 struct TileCfg {
   int tx, ty, tz, hmax;
@@ -329,21 +481,102 @@ void dispatch_tile(PropArgs<T> a, hipStream_t st) {
   PW_LAUNCH_CHECK();
 }
 
+template <typename T>
+constexpr int stream_depth() {
+  return sizeof(T) == 4 ? 8 : 4;
+}
+
+template <typename T, bool COMP>
+void dispatch_stream2d(const Stream2dArgs<T>& a, bool fine, hipStream_t st) {
+  constexpr int B = stream_depth<T>();
+  const long long nwaves = (long long)a.nstates * a.ncb * a.nseg;
+  const long long nblk = (nwaves + 3) / 4;
+  if (nblk >= (1LL << 31)) fail(PW_EINVAL, "too many streams for one launch");
+  if (fine)
+    hipLaunchKernelGGL((k_prop_stream2d<T, COMP, B, 0>), dim3((unsigned)nblk), dim3(256), 0, st,
+                       a);
+  else
+    hipLaunchKernelGGL((k_prop_stream2d<T, COMP, B, 1>), dim3((unsigned)nblk), dim3(256), 0, st,
+                       a);
+  PW_LAUNCH_CHECK();
+}
+
+template <typename T>
+void propagate_stream2d(const Grid& g, const T* c2, const T* u_src, const T* p_src, T* u_dst,
+                        T* p_dst, long long sstride, int nstates, int m, T h, bool comp,
+                        StateSet<T> wa, StateSet<T> wb, bool fine, hipStream_t st) {
+  constexpr int B = stream_depth<T>();
+  constexpr int XV = 64 - 2 * (B + 1);
+  Stream2dArgs<T> a{};
+  a.c2 = c2;
+  a.sstride = sstride;
+  a.nx = g.n[0];
+  a.ny = g.n[1];
+  a.nstates = nstates;
+  a.h = h;
+  a.idx2 = T(1.0 / (g.dx * g.dx));
+  a.ncb = (a.nx + XV - 1) / XV;
+  // enough independent streams to fill the chip; segments of >= 32 rows
+  const long long want = 4096;
+  long long nseg = (want + (long long)nstates * a.ncb - 1) / ((long long)nstates * a.ncb);
+  nseg = std::max(1LL, std::min(nseg, (long long)((a.ny + 31) / 32)));
+  a.Ly = (int)((a.ny + nseg - 1) / nseg);
+  a.nseg = (a.ny + a.Ly - 1) / a.Ly;
+  const int nl = (m + B - 1) / B;
+  if (nl > 1 && (wa.u == nullptr || wb.u == nullptr || (comp && (wa.eu == nullptr || wb.eu == nullptr))))
+    fail(PW_EINVAL, "propagation needs scratch state sets");
+  const T* cu = u_src;
+  const T* cp = p_src;
+  const T* ceu = nullptr;
+  const T* cep = nullptr;
+  for (int l = 0; l < nl; ++l) {
+    a.first = (l == 0);
+    a.last = (l == nl - 1);
+    a.nsteps = std::min(B, m - l * B);
+    a.u_in = cu;
+    a.p_in = cp;
+    a.eu_in = ceu;
+    a.ep_in = cep;
+    StateSet<T> out;
+    if (a.last) {
+      out.u = u_dst;
+      out.p = p_dst;
+    } else {
+      out = ((nl - 1 - l) % 2 == 1) ? wa : wb;
+    }
+    a.u_out = out.u;
+    a.p_out = out.p;
+    a.eu_out = out.eu;
+    a.ep_out = out.ep;
+    if (comp) {
+      if constexpr (sizeof(T) == 4) dispatch_stream2d<T, true>(a, fine, st);
+      else fail(PW_EINVAL, "compensation is an FP32 mode");
+    } else {
+      dispatch_stream2d<T, false>(a, fine, st);
+    }
+    cu = out.u;
+    cp = out.p;
+    ceu = out.eu;
+    cep = out.ep;
+  }
+}
+
 TileCfg tile_cfg(int dim) { return dim == 1 ? kTile1 : (dim == 2 ? kTile2 : kTile3); }
 
 bool use_line(const Grid& g) { return g.dim == 1 && g.n[0] <= 4096; }
 
 }  // namespace
 
-int steps_per_launch(const Grid& g, bool /*is_double*/) {
+int steps_per_launch(const Grid& g, bool is_double) {
   if (use_line(g)) return 1 << 30;
+  if (g.dim == 2) return is_double ? stream_depth<double>() : stream_depth<float>();
   return tile_cfg(g.dim).hmax - 1;
 }
 
 template <typename T>
 void propagate(const Grid& g, const T* c2, const T* u_src, const T* p_src, T* u_dst, T* p_dst,
                long long sstride, int nstates, int m, T h, bool compensated, StateSet<T> wa,
-               StateSet<T> wb, hipStream_t st) {
+               StateSet<T> wb, hipStream_t st, bool fine) {
   if (nstates <= 0) return;
   if (m <= 0) {
     for (int s = 0; s < nstates; ++s) {
@@ -378,6 +611,11 @@ void propagate(const Grid& g, const T* c2, const T* u_src, const T* p_src, T* u_
     } else {
       dispatch_line<T, false>(a, st);
     }
+    return;
+  }
+  if (g.dim == 2) {
+    propagate_stream2d<T>(g, c2, u_src, p_src, u_dst, p_dst, sstride, nstates, m, h, comp, wa, wb,
+                          fine, st);
     return;
   }
   const TileCfg c = tile_cfg(g.dim);
@@ -443,9 +681,9 @@ void propagate(const Grid& g, const T* c2, const T* u_src, const T* p_src, T* u_
 
 template void propagate<float>(const Grid&, const float*, const float*, const float*, float*,
                                float*, long long, int, int, float, bool, StateSet<float>,
-                               StateSet<float>, hipStream_t);
+                               StateSet<float>, hipStream_t, bool);
 template void propagate<double>(const Grid&, const double*, const double*, const double*,
                                 double*, double*, long long, int, int, double, bool,
-                                StateSet<double>, StateSet<double>, hipStream_t);
+                                StateSet<double>, StateSet<double>, hipStream_t, bool);
 
 }  // namespace pw

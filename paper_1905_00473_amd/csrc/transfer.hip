@@ -161,6 +161,85 @@ __global__ void k_interp_axis(const Tin* in, long long sin, Tout* out, long long
   }
 }
 
+// Register-blocked variant for a compile-time ratio R: a thread produces
+// the R phases of RJ consecutive coarse intervals J, so every input value
+// loaded feeds R*RJ accumulators; the polyphase table sits in LDS.
+template <typename Tin, typename Tout, bool FINAL, int R, int RJ>
+__global__ __launch_bounds__(256) void k_interp_axis_rb(const Tin* in, long long sin, Tout* out,
+                                                         long long sout, const Tout* v,
+                                                         const double* tab, int outer, int nc,
+                                                         int inner, int nfields) {
+  extern __shared__ double wt[];
+  for (int t = threadIdx.x; t < R * nc; t += blockDim.x) wt[t] = tab[t];
+  __syncthreads();
+  const int njb = (nc + RJ - 1) / RJ;
+  const long long per = (long long)outer * njb * inner;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= per * nfields) return;
+  const int f = (int)(t / per);
+  long long rr = t - (long long)f * per;
+  const int i = (int)(rr % inner);
+  rr /= inner;
+  const int jb = (int)(rr % njb);
+  const int o = (int)(rr / njb);
+  const int J0 = jb * RJ;
+  const Tin* src = in + (long long)f * sin + (long long)o * nc * inner + i;
+  double acc[RJ][R];
+#pragma unroll
+  for (int a = 0; a < RJ; ++a)
+#pragma unroll
+    for (int s = 0; s < R; ++s) acc[a][s] = 0.0;
+  for (int m = 0; m < nc; ++m) {
+    const double x = (double)src[(long long)m * inner];
+#pragma unroll
+    for (int a = 0; a < RJ; ++a) {
+      int dd = J0 + a - m;
+      if (dd < 0) dd += nc;
+#pragma unroll
+      for (int s = 1; s < R; ++s) acc[a][s] += wt[s * nc + dd] * x;
+    }
+  }
+  const int nf = nc * R;
+#pragma unroll
+  for (int a = 0; a < RJ; ++a) {
+    const int J = J0 + a;
+    if (J >= nc) break;
+    acc[a][0] = (double)src[(long long)J * inner];  // R I = 1 exactly
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      const long long oi = (long long)f * sout + ((long long)o * nf + (long long)J * R + s) * inner + i;
+      if (FINAL) {
+        const double base = v ? (double)v[oi] : 0.0;
+        out[oi] = (Tout)(base + acc[a][s]);
+      } else {
+        out[oi] = (Tout)acc[a][s];
+      }
+    }
+  }
+}
+
+template <typename Tin, typename Tout, bool FINAL>
+void interp_pass(const Tin* in, long long sin, Tout* out, long long sout, const Tout* v,
+                 const double* tab, int outer, int nc, int ratio, int inner, int nfields,
+                 hipStream_t st) {
+  constexpr int RJ = 4;
+  if (ratio == 4 || ratio == 2) {
+    const long long n = (long long)outer * ((nc + RJ - 1) / RJ) * inner * nfields;
+    const size_t smem = sizeof(double) * (size_t)ratio * nc;
+    if (ratio == 4)
+      hipLaunchKernelGGL((k_interp_axis_rb<Tin, Tout, FINAL, 4, RJ>), dim3(nblocks(n)), dim3(kTB),
+                         smem, st, in, sin, out, sout, v, tab, outer, nc, inner, nfields);
+    else
+      hipLaunchKernelGGL((k_interp_axis_rb<Tin, Tout, FINAL, 2, RJ>), dim3(nblocks(n)), dim3(kTB),
+                         smem, st, in, sin, out, sout, v, tab, outer, nc, inner, nfields);
+  } else {
+    const long long n = (long long)outer * nc * ratio * inner * nfields;
+    hipLaunchKernelGGL((k_interp_axis<Tin, Tout, FINAL>), dim3(nblocks(n)), dim3(kTB), 0, st, in,
+                       sin, out, sout, v, tab, outer, nc, ratio, inner, nfields);
+  }
+  PW_LAUNCH_CHECK();
+}
+
 // DFT along one axis of length n with stride `inner`:
 // out[b][o][k][i] = sum_j in[b][o][j][i] * tw[(j*k) mod n] (conj if INV).
 // IN_REAL: input is real, batch b at offset (b/sub)*s_hi + (b%sub)*s_lo.
@@ -447,46 +526,25 @@ void interp_add(const Grid& f, const Grid& c, int ratio, const double* const* ta
   const int fx = f.n[0], fy = f.n[1];
   const int cx = c.n[0], cy = c.n[1], cz = c.n[2];
   if (d == 1) {
-    const long long n = (long long)fx * nfields;
-    hipLaunchKernelGGL((k_interp_axis<T, T, true>), dim3(nblocks(n)), dim3(kTB), 0, st, in, sin,
-                       out, sout, v, tables[0], 1, cx, ratio, 1, nfields);
-    PW_LAUNCH_CHECK();
+    interp_pass<T, T, true>(in, sin, out, sout, v, tables[0], 1, cx, ratio, 1, nfields, st);
     return;
   }
-  // pass x: (cz*cy, cx, 1) -> tmpA (cz*cy, fx, 1)
+  // pass x: (cz*cy, cx, 1) -> tA (cz*cy, fx, 1)
   double* tA = tmp;
   const long long sA = (long long)cz * cy * fx;
   double* tB = tmp + sA * nfields;
-  {
-    const long long n = sA * nfields;
-    hipLaunchKernelGGL((k_interp_axis<T, double, false>), dim3(nblocks(n)), dim3(kTB), 0, st, in,
-                       sin, tA, sA, (const double*)nullptr, tables[0], cz * cy, cx, ratio, 1,
-                       nfields);
-    PW_LAUNCH_CHECK();
-  }
+  interp_pass<T, double, false>(in, sin, tA, sA, (const double*)nullptr, tables[0], cz * cy, cx,
+                                ratio, 1, nfields, st);
   if (d == 2) {
-    const long long n = (long long)fy * fx * nfields;
-    hipLaunchKernelGGL((k_interp_axis<double, T, true>), dim3(nblocks(n)), dim3(kTB), 0, st,
-                       (const double*)tA, sA, out, sout, v, tables[1], 1, cy, ratio, fx, nfields);
-    PW_LAUNCH_CHECK();
+    interp_pass<double, T, true>(tA, sA, out, sout, v, tables[1], 1, cy, ratio, fx, nfields, st);
     return;
   }
   // 3D: pass y: (cz, cy, fx) -> tB (cz, fy, fx); pass z: (1, cz, fy*fx) -> out
   const long long sB = (long long)cz * fy * fx;
-  {
-    const long long n = sB * nfields;
-    hipLaunchKernelGGL((k_interp_axis<double, double, false>), dim3(nblocks(n)), dim3(kTB), 0, st,
-                       (const double*)tA, sA, tB, sB, (const double*)nullptr, tables[1], cz, cy,
-                       ratio, fx, nfields);
-    PW_LAUNCH_CHECK();
-  }
-  {
-    const long long n = (long long)f.n[2] * fy * fx * nfields;
-    hipLaunchKernelGGL((k_interp_axis<double, T, true>), dim3(nblocks(n)), dim3(kTB), 0, st,
-                       (const double*)tB, sB, out, sout, v, tables[2], 1, cz, ratio, fy * fx,
-                       nfields);
-    PW_LAUNCH_CHECK();
-  }
+  interp_pass<double, double, false>(tA, sA, tB, sB, (const double*)nullptr, tables[1], cz, cy,
+                                     ratio, fx, nfields, st);
+  interp_pass<double, T, true>(tB, sB, out, sout, v, tables[2], 1, cz, ratio, fy * fx, nfields,
+                               st);
 }
 
 std::vector<double> dft_table(int n) {
