@@ -272,12 +272,15 @@ __global__ __launch_bounds__(NT) void k_prop_tile(PropArgs<T> a) {
 //
 // One wavefront owns 64 consecutive columns x (periodic) and streams down a
 // segment of rows.  The B time steps of a launch are B pipeline stages held
-// in registers: at stream step t stage j turns level-j row t-j into level
-// j+1 row t-j, so a row enters at level 0 (read from memory) and leaves at
-// level B (written to memory).  Each stage keeps a three-row window of its
-// input level; the x neighbours come from the adjacent lanes, so the valid
-// lanes shrink by one per stage and the halo is H = B + 1 columns on each
-// side (the +1 for the closing half kick).  No LDS and no barriers.
+// in registers: at stream step t stage j turns level-j row t-2j into level
+// j+1 row t-2j.  With this lag of two rows per stage every stage reads only
+// rows produced in the previous stream step, so the B stages of one step
+// are independent of each other.  A row enters at level 0 (read from
+// memory) and leaves at level B (written).  Each stage keeps a three-row
+// window of its input level plus one pending row; the x neighbours come
+// from the adjacent lanes, so the valid lanes shrink by one per stage and
+// the halo is H = B + 1 columns on each side (the +1 for the closing half
+// kick).  No LDS and no barriers.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct Stream2dArgs {
@@ -332,48 +335,54 @@ __global__ __launch_bounds__(256) void k_prop_stream2d(Stream2dArgs<T> a) {
   const long long base = (long long)state * a.sstride;
   const T h = a.h;
   const int ns = a.nsteps;
-  // stage j window: level-j rows (r-1, r, r+1) with r = t - j
-  T wu[B + 1][3];
-  T wp[B + 1][2], we_u[B + 1][2], we_p[B + 1][2], wk[B + 1][2];
+  const bool first = a.first, last = a.last;
+  // stage j window: level-j rows (r-1, r, r+1), r = t - 2j; pending: row
+  // r+2, produced during step t by stage j-1 (or loaded, for j = 0)
+  T wu[B + 1][3], wp[B + 1][2], weu[B + 1][2], wep[B + 1][2], wk[B + 1][2];
+  T qu[B + 1], qp[B + 1], qeu[B + 1], qep[B + 1], qk[B + 1];
 #pragma unroll
   for (int j = 0; j <= B; ++j) {
     wu[j][0] = wu[j][1] = wu[j][2] = T(0);
-    wp[j][0] = wp[j][1] = we_u[j][0] = we_u[j][1] = T(0);
-    we_p[j][0] = we_p[j][1] = wk[j][0] = wk[j][1] = T(0);
+    wp[j][0] = wp[j][1] = weu[j][0] = weu[j][1] = T(0);
+    wep[j][0] = wep[j][1] = wk[j][0] = wk[j][1] = T(0);
+    qu[j] = qp[j] = qeu[j] = qep[j] = qk[j] = T(0);
   }
-  for (int t = Y0 - H - 1; t < Y1 + H - 1; ++t) {
-    // level 0, row t+1
-    {
-      const int gy = wrap_idx(t + 1, ny);
+  const int tout = last ? 2 * B : 2 * (B - 1);  // lag of the written level
+  const int tbeg = Y0 - H - 2;
+  const int tend = Y1 - 1 + tout;  // inclusive
+  for (int t = tbeg; t <= tend; ++t) {
+    // level 0, row t+2 -> pending slot of stage 0
+    if (t + 2 < Y1 + H) {
+      const int gy = wrap_idx(t + 2, ny);
       const long long gi = base + (long long)gy * nx + gx;
-      wu[0][2] = a.u_in[gi];
-      wp[0][1] = a.p_in[gi];
-      wk[0][1] = a.c2[(long long)gy * nx + gx] * a.idx2;
+      qu[0] = a.u_in[gi];
+      qp[0] = a.p_in[gi];
+      qk[0] = a.c2[(long long)gy * nx + gx] * a.idx2;
       if (COMP) {
-        we_u[0][1] = a.first ? T(0) : a.eu_in[gi];
-        we_p[0][1] = a.first ? T(0) : a.ep_in[gi];
+        qeu[0] = first ? T(0) : a.eu_in[gi];
+        qep[0] = first ? T(0) : a.ep_in[gi];
       }
     }
     // stages 0..B-1: kick + drift (stages past nsteps pass the row through)
 #pragma unroll
     for (int j = 0; j < B; ++j) {
       const T uc = wu[j][1];
-      T un = uc, pn = wp[j][0], eu = we_u[j][0], ep = we_p[j][0];
+      T un = uc, pn = wp[j][0], eu = weu[j][0], ep = wep[j][0];
       const T kj = wk[j][0];
       if (j < ns) {
         const T lap =
             (lane_up(uc) - T(2) * uc + lane_down(uc)) + (wu[j][0] - T(2) * uc + wu[j][2]);
-        const T w = (j == 0 && a.first) ? h * T(0.5) : h;
+        const T w = (j == 0 && first) ? h * T(0.5) : h;
         kadd<T, COMP>(pn, ep, w * (kj * lap));
         kadd<T, COMP>(un, eu, h * pn);
       }
-      wu[j + 1][2] = un;
-      wp[j + 1][1] = pn;
-      we_u[j + 1][1] = eu;
-      we_p[j + 1][1] = ep;
-      wk[j + 1][1] = kj;
-      if (j == B - 1 && !a.last) {
-        const int orow = t - j;
+      qu[j + 1] = un;
+      qp[j + 1] = pn;
+      qeu[j + 1] = eu;
+      qep[j + 1] = ep;
+      qk[j + 1] = kj;
+      if (j == B - 1 && !last) {
+        const int orow = t - 2 * j;
         if (out_lane && orow >= Y0 && orow < Y1) {
           const long long gi = base + (long long)orow * nx + gx;
           a.u_out[gi] = un;
@@ -386,17 +395,17 @@ __global__ __launch_bounds__(256) void k_prop_stream2d(Stream2dArgs<T> a) {
       }
     }
     // stage B: closing half kick of the slice, then fold and write
-    if (a.last) {
+    if (last) {
       const T uc = wu[B][1];
       const T lap =
           (lane_up(uc) - T(2) * uc + lane_down(uc)) + (wu[B][0] - T(2) * uc + wu[B][2]);
-      T pn = wp[B][0], ep = we_p[B][0];
+      T pn = wp[B][0], ep = wep[B][0];
       kadd<T, COMP>(pn, ep, h * T(0.5) * (wk[B][0] * lap));
-      const int orow = t - B;
+      const int orow = t - 2 * B;
       if (out_lane && orow >= Y0 && orow < Y1) {
         const long long gi = base + (long long)orow * nx + gx;
         if (COMP) {
-          a.u_out[gi] = uc - we_u[B][0];
+          a.u_out[gi] = uc - weu[B][0];
           a.p_out[gi] = pn - ep;
         } else {
           a.u_out[gi] = uc;
@@ -404,15 +413,20 @@ __global__ __launch_bounds__(256) void k_prop_stream2d(Stream2dArgs<T> a) {
         }
       }
     }
-    // advance the windows by one row
+    // advance every window by one row, taking in the pending row
 #pragma unroll
     for (int j = 0; j <= B; ++j) {
       wu[j][0] = wu[j][1];
       wu[j][1] = wu[j][2];
+      wu[j][2] = qu[j];
       wp[j][0] = wp[j][1];
-      we_u[j][0] = we_u[j][1];
-      we_p[j][0] = we_p[j][1];
+      wp[j][1] = qp[j];
+      weu[j][0] = weu[j][1];
+      weu[j][1] = qeu[j];
+      wep[j][0] = wep[j][1];
+      wep[j][1] = qep[j];
       wk[j][0] = wk[j][1];
+      wk[j][1] = qk[j];
     }
   }
 }
