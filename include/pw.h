@@ -130,6 +130,36 @@ pw_status pw_set_initial(pw_ctx* ctx, int prob, const double* u0,
  */
 pw_status pw_run(pw_ctx* ctx, int prob, int K);
 
+/*
+ * Batching: Algorithm 3 for every problem of the context in lockstep (all
+ * problems 2D, same state dtype and compensation, medium and initial state
+ * set).  Per iteration, the parallel phase of all problems -- the fine
+ * sweeps over all slices of every problem, the restrictions and the coarse
+ * propagations -- is one launch sequence of the multi-problem streaming
+ * kernel (one launch per time block), captured once in a hipGraph and
+ * replayed; the corrector and the sweep then run per problem.  On the first
+ * call an autotuner times the batched fine sweep for each candidate
+ * (pipeline depth 4 or 8 steps, 64/128/256 rows per stream) and keeps the
+ * fastest; with the environment variable PW_TUNE_CACHE naming a file the
+ * choice is cached there across processes.  Results per problem are read
+ * with pw_get_state / pw_get_residuals and equal those of pw_run bit for
+ * bit.  Synchronises once per iteration.
+ */
+pw_status pw_run_batch(pw_ctx* ctx, int K);
+
+/* Time `reps` batched fine sweeps (all slices of all problems, the launch
+ * sequence of pw_run_batch) and return the mean time per sweep in *ms.
+ * Needs a previous pw_run_batch.  Synchronises.                         */
+pw_status pw_batch_fine_sweeps(pw_ctx* ctx, int reps, double* ms);
+
+/* Configuration and timing of the batched runs: chosen pipeline depth and
+ * rows per stream; ms[0..3] = parallel phase, corrector, sweep, total of
+ * the last pw_run_batch; ms[4] = autotuning time; ms[5] = fine sweep time
+ * of the chosen configuration while tuning; ms[6] = 1 if the choice came
+ * from the cache.  Host output.                                         */
+pw_status pw_get_batch_info(pw_ctx* ctx, int* depth, int* rows_per_stream, double* ms,
+                            int cap);
+
 /* Wait for all work on the context stream. */
 pw_status pw_sync(pw_ctx* ctx);
 

@@ -112,6 +112,12 @@ _SIGS = {
                   ctypes.POINTER(ctypes.c_double)],
     "pw_get_timings": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                        ctypes.c_int],
+    "pw_run_batch": [ctypes.c_void_p, ctypes.c_int],
+    "pw_batch_fine_sweeps": [ctypes.c_void_p, ctypes.c_int,
+                             ctypes.POINTER(ctypes.c_double)],
+    "pw_get_batch_info": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
+                          ctypes.POINTER(ctypes.c_int), ctypes.c_void_p,
+                          ctypes.c_int],
 }
 
 #: every symbol include/pw.h declares
@@ -226,6 +232,25 @@ class Solver:
 
     def run(self, K, prob=0):
         _check(lib().pw_run(self._h, prob, int(K)))
+
+    def run_batch(self, K):
+        """Algorithm 3 for all problems of the context in lockstep."""
+        _check(lib().pw_run_batch(self._h, int(K)))
+
+    def batch_fine_sweeps(self, reps=3):
+        ms = ctypes.c_double()
+        _check(lib().pw_batch_fine_sweeps(self._h, int(reps), ctypes.byref(ms)))
+        return ms.value
+
+    def batch_info(self):
+        d, ly = ctypes.c_int(), ctypes.c_int()
+        ms = (ctypes.c_double * 7)()
+        _check(lib().pw_get_batch_info(self._h, ctypes.byref(d),
+                                       ctypes.byref(ly), ms, 7))
+        return dict(depth=d.value, rows_per_stream=ly.value,
+                    parallel=ms[0], corrector=ms[1], sweep=ms[2],
+                    total=ms[3], tune_ms=ms[4], tuned_sweep_ms=ms[5],
+                    from_cache=bool(ms[6]))
 
     def sync(self):
         _check(lib().pw_sync(self._h))

@@ -144,9 +144,44 @@ struct Prob {
 }  // namespace
 }  // namespace pw
 
+namespace pw {
+namespace {
+// Lockstep execution of all problems of a context: the parallel phase of
+// every problem (fine sweep over all slices, restriction, coarse U_n) is
+// one launch sequence of the multi-problem streaming kernel, captured once
+// in a hipGraph and replayed every iteration.
+struct Batch {
+  bool built = false;
+  bool f64 = false, comp = false;
+  MultiPlan<float> F32, C32;
+  MultiPlan<double> F64, C64;
+  void* dF = nullptr;  // device descriptor tables
+  void* dC = nullptr;
+  Buffers mem;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int B = 0, Ly = 0;
+  double tune_ms = 0.0;   // time spent tuning
+  double best_ms = 0.0;   // fine sweep time of the chosen configuration
+  bool from_cache = false;
+  double ms[4] = {0, 0, 0, 0};
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  ~Batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+}  // namespace
+}  // namespace pw
+
 struct pw_ctx {
   hipStream_t stream = nullptr;
   std::vector<std::unique_ptr<pw::Prob>> probs;
+  std::unique_ptr<pw::Batch> batch;
 };
 
 namespace pw {
@@ -290,7 +325,15 @@ void setup(Prob& pr, const pw_problem& P) {
   pr.rs.tb = m.get_n<double>((long long)(pr.rmax + 1) * N);
   const int gcols = std::max(N, 1);
   pr.ctmp = m.get_n<double>(4LL * P.dim * Nc * gcols);
-  pr.itmp = m.get_n<double>(2LL * (Nf + Nf) * N + 16);
+  // interpolation scratch: the partially interpolated fields of one pass
+  // pair (2D: (n_x fine) x (n_y coarse) per field; 3D: also fine x, y by
+  // coarse z), and at least two fine fields for staging inputs
+  long long interp_need = 0;
+  if (P.dim == 2) interp_need = (long long)pr.gc.n[1] * pr.gf.n[0] * N;
+  if (P.dim == 3)
+    interp_need = ((long long)pr.gc.n[2] * pr.gc.n[1] * pr.gf.n[0] +
+                   (long long)pr.gc.n[2] * pr.gf.n[1] * pr.gf.n[0]) * N;
+  pr.itmp = m.get_n<double>(std::max(interp_need, 2 * Nf) + 16);
   // split-K partials: bound over every A^T B shape of the path
   // (a <= cap, b <= max(cap, N))
   pr.gwork_elems = gemm_tn_work_bound((int)cap, (int)std::max<long long>(cap, N));
@@ -472,25 +515,21 @@ void split_cast(const double* delta, long long ld, long long nc, int ncols, T* d
   PW_LAUNCH_CHECK();
 }
 
+// ---- phases of one iteration ---------------------------------------------
+// initialisation: W_0 = R u0, W_n = C W_{n-1}; u^1_n = I W_n
 template <typename T>
-void run_typed(Prob& pr, int K, hipStream_t st) {
+void init_phase(Prob& pr, hipStream_t st) {
   const int N = pr.N;
-  const long long Nf = pr.Nf, Nc = pr.Nc, rows = pr.rows;
+  const long long Nf = pr.Nf, Nc = pr.Nc;
   T* u = tp<T>(pr.u);
   T* p = tp<T>(pr.p);
-  T* v = tp<T>(pr.v);
-  T* vp = tp<T>(pr.vp);
   T* Uc = tp<T>(pr.Uc);
   T* Ucp = tp<T>(pr.Ucp);
   T* Rc = tp<T>(pr.Rc);
   T* Rcp = tp<T>(pr.Rcp);
   reset_corrector(pr);
   for (int i = 0; i < 4; ++i) pr.ms[i] = 0.0;
-  hipEvent_t e0, e1;
-  PW_HIP(hipEventCreate(&e0));
-  PW_HIP(hipEventCreate(&e1));
-  PW_HIP(hipEventRecord(e0, st));
-  // initialisation: W_0 = R u0, W_n = C W_{n-1}; u^1_n = I W_n
+  pr.k_done = 0;
   restrict_fields<T>(pr.gf, pr.ratio, pr.gc, u, Nf, Rc, Nc, 1, st);
   restrict_fields<T>(pr.gf, pr.ratio, pr.gc, p, Nf, Rcp, Nc, 1, st);
   for (int n = 1; n <= N; ++n) {
@@ -502,61 +541,99 @@ void run_typed(Prob& pr, int K, hipStream_t st) {
                 pr.itmp, st);
   interp_add<T>(pr.gf, pr.gc, pr.ratio, pr.itab, Ucp, Nc, (const T*)nullptr, p + Nf, Nf, N,
                 pr.itmp, st);
+}
+
+// restriction of the slice-start states for U_n = C R u^k_{n-1}
+template <typename T>
+void restrict_phase(Prob& pr, hipStream_t st) {
+  restrict_fields<T>(pr.gf, pr.ratio, pr.gc, tp<T>(pr.u), pr.Nf, tp<T>(pr.Rc), pr.Nc, pr.N, st);
+  restrict_fields<T>(pr.gf, pr.ratio, pr.gc, tp<T>(pr.p), pr.Nf, tp<T>(pr.Rcp), pr.Nc, pr.N, st);
+}
+
+// 2. data matrices, Algorithm 1 and the residual rho_k
+template <typename T>
+void corrector_phase(Prob& pr, int k, hipStream_t st) {
+  const int N = pr.N;
+  const long long Nf = pr.Nf, Nc = pr.Nc, rows = pr.rows;
+  energy_columns<T>(pr.gf, pr.ratio, pr.gc, tp<T>(pr.v), tp<T>(pr.vp), Nf, pr.cc, pr.order,
+                    pr.Fm, rows, N, st);
+  energy_columns<T>(pr.gc, 1, pr.gc, tp<T>(pr.Uc), tp<T>(pr.Ucp), Nc, pr.cc, pr.order, pr.Gm,
+                    rows, N, st);
+  update_svd_dev(pr, pr.Fm, pr.Gm, N, st);
+  pr.ranks.push_back(pr.r);
+  // rho_k: || F - U (V^T G) ||_F / ||F||_F
+  const int r = pr.r;
+  gemm_tn(rows, r, N, 1.0, pr.Vb[pr.cur], rows, pr.Gm, rows, 0.0, pr.UF, std::max(r, 1),
+          pr.gwork, pr.gwork_elems, st);
+  PW_HIP(hipMemcpyAsync(pr.Fp, pr.Fm, sizeof(double) * rows * N, hipMemcpyDeviceToDevice, st));
+  gemm_nn(rows, N, r, -1.0, pr.Ub[pr.cur], rows, pr.UF, std::max(r, 1), 1.0, pr.Fp, rows, st);
+  frob_norm2(pr.Fp, rows, N, rows, pr.red, pr.res + 2 * (k - 1), st);
+  frob_norm2(pr.Fm, rows, N, rows, pr.red, pr.res + 2 * (k - 1) + 1, st);
+}
+
+// 3.-4. corrected sweep in corrector coordinates and the update
+template <typename T>
+void sweep_phase(Prob& pr, hipStream_t st) {
+  const int N = pr.N;
+  const long long Nf = pr.Nf, Nc = pr.Nc;
+  T* u = tp<T>(pr.u);
+  T* p = tp<T>(pr.p);
+  T* v = tp<T>(pr.v);
+  T* vp = tp<T>(pr.vp);
+  const int dim = pr.r + 1;
+  const double* E = pr.E[pr.cur];
+  const double* P = pr.Vp[pr.cur];
+  // a_n = C (R v_{n-1} - R u^k_{n-1}), v_0 = u0 -> column 0 is zero
+  fill(pr.Din, 2 * Nc, 0.0, st);
+  if (N > 1)
+    restrict_diff<T>(pr.gf, pr.ratio, pr.gc, v, vp, u + Nf, p + Nf, Nf, pr.Din + 2 * Nc, 2 * Nc,
+                     N - 1, st);
+  prop_coarse_cols(pr, pr.Din, pr.Acol, N, st);
+  prop_coarse_cols(pr, E, pr.CE, dim, st);
+  gemm_tn(2 * Nc, dim, dim, 1.0, P, 2 * Nc, pr.CE, 2 * Nc, 0.0, pr.M, dim, pr.gwork,
+          pr.gwork_elems, st);
+  gemm_tn(2 * Nc, dim, N, 1.0, P, 2 * Nc, pr.Acol, 2 * Nc, 0.0, pr.Bn, dim, pr.gwork,
+          pr.gwork_elems, st);
+  if (dim > pr.rmax + 1) fail(PW_EINVAL, "corrector rank exceeds its capacity");
+  recurrence(dim, N, pr.M, pr.Bn, pr.Tn, pr.rs, st);
+  gemm_nn(2 * Nc, N, dim, 1.0, E, 2 * Nc, pr.Tn, dim, 0.0, pr.delta, 2 * Nc, st);
+  // u^{k+1}_n = v_n + I(delta_n), n = 1..N
+  split_cast<T>(pr.delta, 2 * Nc, Nc, N, tp<T>(pr.du_T), tp<T>(pr.dp_T), st);
+  interp_add<T>(pr.gf, pr.gc, pr.ratio, pr.itab, tp<T>(pr.du_T), Nc, v, u + Nf, Nf, N, pr.itmp,
+                st);
+  interp_add<T>(pr.gf, pr.gc, pr.ratio, pr.itab, tp<T>(pr.dp_T), Nc, vp, p + Nf, Nf, N,
+                pr.itmp, st);
+}
+
+void accumulate_phase_times(Prob& pr) {
+  PW_HIP(hipEventSynchronize(pr.ev[3]));
+  float a = 0, b = 0, c = 0;
+  PW_HIP(hipEventElapsedTime(&a, pr.ev[0], pr.ev[1]));
+  PW_HIP(hipEventElapsedTime(&b, pr.ev[1], pr.ev[2]));
+  PW_HIP(hipEventElapsedTime(&c, pr.ev[2], pr.ev[3]));
+  pr.ms[0] += a;
+  pr.ms[1] += b;
+  pr.ms[2] += c;
+}
+
+template <typename T>
+void run_typed(Prob& pr, int K, hipStream_t st) {
+  hipEvent_t e0, e1;
+  PW_HIP(hipEventCreate(&e0));
+  PW_HIP(hipEventCreate(&e1));
+  PW_HIP(hipEventRecord(e0, st));
+  init_phase<T>(pr, st);
   for (int k = 1; k <= K; ++k) {
     PW_HIP(hipEventRecord(pr.ev[0], st));
-    // 1. parallel phase
-    prop_fine<T>(pr, u, p, v, vp, N, st);
-    restrict_fields<T>(pr.gf, pr.ratio, pr.gc, u, Nf, Rc, Nc, N, st);
-    restrict_fields<T>(pr.gf, pr.ratio, pr.gc, p, Nf, Rcp, Nc, N, st);
-    prop_coarse<T>(pr, Rc, Rcp, Uc, Ucp, N, st);
+    prop_fine<T>(pr, tp<T>(pr.u), tp<T>(pr.p), tp<T>(pr.v), tp<T>(pr.vp), pr.N, st);
+    restrict_phase<T>(pr, st);
+    prop_coarse<T>(pr, tp<T>(pr.Rc), tp<T>(pr.Rcp), tp<T>(pr.Uc), tp<T>(pr.Ucp), pr.N, st);
     PW_HIP(hipEventRecord(pr.ev[1], st));
-    // 2. corrector
-    energy_columns<T>(pr.gf, pr.ratio, pr.gc, v, vp, Nf, pr.cc, pr.order, pr.Fm, rows, N, st);
-    energy_columns<T>(pr.gc, 1, pr.gc, Uc, Ucp, Nc, pr.cc, pr.order, pr.Gm, rows, N, st);
-    update_svd_dev(pr, pr.Fm, pr.Gm, N, st);
-    pr.ranks.push_back(pr.r);
-    {
-      // rho_k: || F - U (V^T G) ||_F / ||F||_F
-      const int r = pr.r;
-      gemm_tn(rows, r, N, 1.0, pr.Vb[pr.cur], rows, pr.Gm, rows, 0.0, pr.UF, std::max(r, 1),
-              pr.gwork, pr.gwork_elems, st);
-      PW_HIP(hipMemcpyAsync(pr.Fp, pr.Fm, sizeof(double) * rows * N, hipMemcpyDeviceToDevice, st));
-      gemm_nn(rows, N, r, -1.0, pr.Ub[pr.cur], rows, pr.UF, std::max(r, 1), 1.0, pr.Fp, rows, st);
-      frob_norm2(pr.Fp, rows, N, rows, pr.red, pr.res + 2 * (k - 1), st);
-      frob_norm2(pr.Fm, rows, N, rows, pr.red, pr.res + 2 * (k - 1) + 1, st);
-    }
+    corrector_phase<T>(pr, k, st);
     PW_HIP(hipEventRecord(pr.ev[2], st));
-    // 3. corrected sweep in corrector coordinates
-    const int dim = pr.r + 1;
-    const double* E = pr.E[pr.cur];
-    const double* P = pr.Vp[pr.cur];
-    // a_n = C (R v_{n-1} - R u^k_{n-1}), v_0 = u0 -> column 0 is zero
-    fill(pr.Din, 2 * Nc, 0.0, st);
-    if (N > 1)
-      restrict_diff<T>(pr.gf, pr.ratio, pr.gc, v, vp, u + Nf, p + Nf, Nf, pr.Din + 2 * Nc, 2 * Nc,
-                       N - 1, st);
-    prop_coarse_cols(pr, pr.Din, pr.Acol, N, st);
-    prop_coarse_cols(pr, E, pr.CE, dim, st);
-    gemm_tn(2 * Nc, dim, dim, 1.0, P, 2 * Nc, pr.CE, 2 * Nc, 0.0, pr.M, dim, pr.gwork, pr.gwork_elems, st);
-    gemm_tn(2 * Nc, dim, N, 1.0, P, 2 * Nc, pr.Acol, 2 * Nc, 0.0, pr.Bn, dim, pr.gwork, pr.gwork_elems, st);
-    if (dim > pr.rmax + 1) fail(PW_EINVAL, "corrector rank exceeds its capacity");
-    recurrence(dim, N, pr.M, pr.Bn, pr.Tn, pr.rs, st);
-    gemm_nn(2 * Nc, N, dim, 1.0, E, 2 * Nc, pr.Tn, dim, 0.0, pr.delta, 2 * Nc, st);
-    // 4. u^{k+1}_n = v_n + I(delta_n), n = 1..N
-    split_cast<T>(pr.delta, 2 * Nc, Nc, N, tp<T>(pr.du_T), tp<T>(pr.dp_T), st);
-    interp_add<T>(pr.gf, pr.gc, pr.ratio, pr.itab, tp<T>(pr.du_T), Nc, v, u + Nf, Nf, N, pr.itmp,
-                  st);
-    interp_add<T>(pr.gf, pr.gc, pr.ratio, pr.itab, tp<T>(pr.dp_T), Nc, vp, p + Nf, Nf, N,
-                  pr.itmp, st);
+    sweep_phase<T>(pr, st);
     PW_HIP(hipEventRecord(pr.ev[3], st));
-    PW_HIP(hipEventSynchronize(pr.ev[3]));
-    float a = 0, b = 0, c = 0;
-    PW_HIP(hipEventElapsedTime(&a, pr.ev[0], pr.ev[1]));
-    PW_HIP(hipEventElapsedTime(&b, pr.ev[1], pr.ev[2]));
-    PW_HIP(hipEventElapsedTime(&c, pr.ev[2], pr.ev[3]));
-    pr.ms[0] += a;
-    pr.ms[1] += b;
-    pr.ms[2] += c;
+    accumulate_phase_times(pr);
     pr.k_done = k;
   }
   PW_HIP(hipEventRecord(e1, st));
@@ -629,6 +706,260 @@ void serial_fine_typed(Prob& pr, int n, T* uo, T* po, hipStream_t st) {
     su = du;
     sp = dp;
   }
+}
+
+// ---------------------------------------------------------------------------
+// batched lockstep driver, hipGraph capture and the autotuner
+// ---------------------------------------------------------------------------
+template <typename T>
+MultiPlan<T>& planF(Batch& b);
+template <>
+MultiPlan<float>& planF<float>(Batch& b) { return b.F32; }
+template <>
+MultiPlan<double>& planF<double>(Batch& b) { return b.F64; }
+template <typename T>
+MultiPlan<T>& planC(Batch& b);
+template <>
+MultiPlan<float>& planC<float>(Batch& b) { return b.C32; }
+template <>
+MultiPlan<double>& planC<double>(Batch& b) { return b.C64; }
+
+template <typename T>
+std::vector<PropJob<T>> fine_jobs(pw_ctx* ctx) {
+  std::vector<PropJob<T>> jobs;
+  for (auto& up : ctx->probs) {
+    Prob& pr = *up;
+    PropJob<T> j;
+    j.g = pr.gf;
+    j.c2 = tp<T>(pr.c2f);
+    j.u_src = tp<T>(pr.u);
+    j.p_src = tp<T>(pr.p);
+    j.u_dst = tp<T>(pr.v);
+    j.p_dst = tp<T>(pr.vp);
+    j.sstride = pr.Nf;
+    j.nstates = pr.N;
+    j.m = pr.mF;
+    j.h = (T)pr.hF;
+    j.wa = fine_work<T>(pr, 0);
+    j.wb = fine_work<T>(pr, 1);
+    jobs.push_back(j);
+  }
+  return jobs;
+}
+
+template <typename T>
+std::vector<PropJob<T>> coarse_jobs(pw_ctx* ctx) {
+  std::vector<PropJob<T>> jobs;
+  for (auto& up : ctx->probs) {
+    Prob& pr = *up;
+    PropJob<T> j;
+    j.g = pr.gc;
+    j.c2 = tp<T>(pr.c2c);
+    j.u_src = tp<T>(pr.Rc);
+    j.p_src = tp<T>(pr.Rcp);
+    j.u_dst = tp<T>(pr.Uc);
+    j.p_dst = tp<T>(pr.Ucp);
+    j.sstride = pr.Nc;
+    j.nstates = pr.N;
+    j.m = pr.mC;
+    j.h = (T)pr.hC;
+    j.wa = coarse_work<T>(pr, 0);
+    j.wb = coarse_work<T>(pr, 1);
+    jobs.push_back(j);
+  }
+  return jobs;
+}
+
+template <typename T>
+void* upload_plan(Batch& b, const MultiPlan<T>& pl, hipStream_t st) {
+  void* d = b.mem.get(sizeof(StreamDesc<T>) * std::max<size_t>(pl.descs.size(), 1));
+  PW_HIP(hipMemcpyAsync(d, pl.descs.data(), sizeof(StreamDesc<T>) * pl.descs.size(),
+                        hipMemcpyHostToDevice, st));
+  PW_HIP(hipStreamSynchronize(st));
+  return d;
+}
+
+std::string tune_key(pw_ctx* ctx, bool f64, bool comp) {
+  hipDeviceProp_t prop;
+  int dev = 0;
+  PW_HIP(hipGetDevice(&dev));
+  PW_HIP(hipGetDeviceProperties(&prop, dev));
+  std::string k = std::string(prop.gcnArchName) + (f64 ? "|f64" : "|f32") + (comp ? "c" : "");
+  std::vector<std::string> items;
+  for (auto& up : ctx->probs) {
+    char buf[96];
+    snprintf(buf, sizeof(buf), "%dx%dN%dm%d", up->gf.n[0], up->gf.n[1], up->N, up->mF);
+    items.push_back(buf);
+  }
+  std::sort(items.begin(), items.end());
+  for (auto& i : items) k += "|" + i;
+  for (auto& ch : k)
+    if (ch == ' ' || ch == ':') ch = '_';
+  return k;
+}
+
+bool tune_lookup(const std::string& key, int* B, int* Ly) {
+  const char* path = getenv("PW_TUNE_CACHE");
+  if (!path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char kb[4096];
+  int b = 0, l = 0;
+  bool found = false;
+  while (fscanf(f, "%4095s %d %d", kb, &b, &l) == 3) {
+    if (key == kb) {
+      *B = b;
+      *Ly = l;
+      found = true;
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+void tune_store(const std::string& key, int B, int Ly) {
+  const char* path = getenv("PW_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "%s %d %d\n", key.c_str(), B, Ly);
+  fclose(f);
+}
+
+// time the batched fine sweep of each candidate (pipeline depth, rows per
+// stream) and keep the fastest
+template <typename T>
+void autotune(pw_ctx* ctx, Batch& b, hipStream_t st) {
+  const std::string key = tune_key(ctx, b.f64, b.comp);
+  int B = 0, Ly = 0;
+  if (tune_lookup(key, &B, &Ly)) {
+    b.B = B;
+    b.Ly = Ly;
+    b.from_cache = true;
+    return;
+  }
+  std::vector<std::pair<int, int>> cands;
+  const int Bs_f[2] = {8, 4};
+  const int Ls[3] = {64, 128, 256};
+  for (int bb : Bs_f) {
+    if (sizeof(T) == 8 && bb != 4) continue;
+    for (int l : Ls) cands.push_back({bb, l});
+  }
+  hipEvent_t e0, e1, t0, t1;
+  PW_HIP(hipEventCreate(&e0));
+  PW_HIP(hipEventCreate(&e1));
+  PW_HIP(hipEventCreate(&t0));
+  PW_HIP(hipEventCreate(&t1));
+  PW_HIP(hipEventRecord(t0, st));
+  const auto jobs = fine_jobs<T>(ctx);
+  double best = 1e30;
+  for (auto c : cands) {
+    MultiPlan<T> pl;
+    pl.B = c.first;
+    pl.Ly = c.second;
+    plan_multi<T>(jobs, pl);
+    Buffers tmp;
+    void* d = tmp.get(sizeof(StreamDesc<T>) * std::max<size_t>(pl.descs.size(), 1));
+    PW_HIP(hipMemcpyAsync(d, pl.descs.data(), sizeof(StreamDesc<T>) * pl.descs.size(),
+                          hipMemcpyHostToDevice, st));
+    run_multi<T>(pl, (const StreamDesc<T>*)d, b.comp, st);  // warm
+    PW_HIP(hipEventRecord(e0, st));
+    for (int r = 0; r < 2; ++r) run_multi<T>(pl, (const StreamDesc<T>*)d, b.comp, st);
+    PW_HIP(hipEventRecord(e1, st));
+    PW_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    PW_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms / 2 < best) {
+      best = ms / 2;
+      b.B = c.first;
+      b.Ly = c.second;
+    }
+  }
+  PW_HIP(hipEventRecord(t1, st));
+  PW_HIP(hipEventSynchronize(t1));
+  float tt = 0;
+  PW_HIP(hipEventElapsedTime(&tt, t0, t1));
+  b.tune_ms = tt;
+  b.best_ms = best;
+  for (hipEvent_t e : {e0, e1, t0, t1}) (void)hipEventDestroy(e);
+  tune_store(key, b.B, b.Ly);
+}
+
+// the parallel phase of every problem: fine sweeps, restrictions, coarse
+// propagations (fixed buffers: graph-capturable)
+template <typename T>
+void batch_parallel_phase(pw_ctx* ctx, Batch& b, hipStream_t st) {
+  run_multi<T>(planF<T>(b), (const StreamDesc<T>*)b.dF, b.comp, st);
+  for (auto& up : ctx->probs) restrict_phase<T>(*up, st);
+  run_multi<T>(planC<T>(b), (const StreamDesc<T>*)b.dC, b.comp, st);
+}
+
+template <typename T>
+void build_batch(pw_ctx* ctx, Batch& b) {
+  hipStream_t st = ctx->stream;
+  autotune<T>(ctx, b, st);
+  MultiPlan<T>& F = planF<T>(b);
+  MultiPlan<T>& C = planC<T>(b);
+  F.B = b.B;
+  F.Ly = b.Ly;
+  plan_multi<T>(fine_jobs<T>(ctx), F);
+  C.B = b.B;
+  C.Ly = b.Ly;
+  plan_multi<T>(coarse_jobs<T>(ctx), C);
+  b.dF = upload_plan<T>(b, F, st);
+  b.dC = upload_plan<T>(b, C, st);
+  PW_HIP(hipStreamCreateWithFlags(&b.cap_stream, hipStreamNonBlocking));
+  PW_HIP(hipStreamBeginCapture(b.cap_stream, hipStreamCaptureModeThreadLocal));
+  try {
+    batch_parallel_phase<T>(ctx, b, b.cap_stream);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(b.cap_stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  PW_HIP(hipStreamEndCapture(b.cap_stream, &b.graph));
+  PW_HIP(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
+  for (auto& e : b.ev) PW_HIP(hipEventCreate(&e));
+  b.built = true;
+}
+
+template <typename T>
+void run_batch_typed(pw_ctx* ctx, int K) {
+  Batch& b = *ctx->batch;
+  hipStream_t st = ctx->stream;
+  if (!b.built) build_batch<T>(ctx, b);
+  for (int i = 0; i < 4; ++i) b.ms[i] = 0.0;
+  hipEvent_t e0, e1;
+  PW_HIP(hipEventCreate(&e0));
+  PW_HIP(hipEventCreate(&e1));
+  PW_HIP(hipEventRecord(e0, st));
+  for (auto& up : ctx->probs) init_phase<T>(*up, st);
+  for (int k = 1; k <= K; ++k) {
+    PW_HIP(hipEventRecord(b.ev[0], st));
+    PW_HIP(hipGraphLaunch(b.exec, st));
+    PW_HIP(hipEventRecord(b.ev[1], st));
+    for (auto& up : ctx->probs) corrector_phase<T>(*up, k, st);
+    PW_HIP(hipEventRecord(b.ev[2], st));
+    for (auto& up : ctx->probs) sweep_phase<T>(*up, st);
+    PW_HIP(hipEventRecord(b.ev[3], st));
+    PW_HIP(hipEventSynchronize(b.ev[3]));
+    float x = 0, y = 0, z = 0;
+    PW_HIP(hipEventElapsedTime(&x, b.ev[0], b.ev[1]));
+    PW_HIP(hipEventElapsedTime(&y, b.ev[1], b.ev[2]));
+    PW_HIP(hipEventElapsedTime(&z, b.ev[2], b.ev[3]));
+    b.ms[0] += x;
+    b.ms[1] += y;
+    b.ms[2] += z;
+    for (auto& up : ctx->probs) up->k_done = k;
+  }
+  PW_HIP(hipEventRecord(e1, st));
+  PW_HIP(hipEventSynchronize(e1));
+  float tot = 0;
+  PW_HIP(hipEventElapsedTime(&tot, e0, e1));
+  b.ms[3] = tot;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
 }
 
 pw_status report(const Error& e) {
@@ -947,6 +1278,68 @@ pw_status pw_energy(pw_ctx* ctx, int prob, const void* u, const void* p, const v
     PW_HIP(hipStreamSynchronize(st));
     if (e_diff) *e_diff = h[0];
     if (e_ref) *e_ref = h[1];
+  });
+}
+
+pw_status pw_run_batch(pw_ctx* ctx, int K) {
+  return guarded([&] {
+    if (!ctx) fail(PW_EINVAL, "null context");
+    const Prob& p0 = *ctx->probs[0];
+    for (auto& up : ctx->probs) {
+      const Prob& pr = *up;
+      if (!pr.have_medium || !pr.have_initial)
+        fail(PW_ESTATE, "set medium and initial state of every problem first");
+      if (pr.gf.dim != 2) fail(PW_EINVAL, "batched runs need 2D problems");
+      if (pr.f64 != p0.f64 || pr.comp != p0.comp)
+        fail(PW_EINVAL, "all problems of a batch need the same state dtype and compensation");
+      if (K < 0 || K > pr.P.max_iters) fail(PW_EINVAL, "K must be in [0, max_iters]");
+    }
+    if (!ctx->batch) {
+      ctx->batch = std::make_unique<Batch>();
+      ctx->batch->f64 = p0.f64;
+      ctx->batch->comp = p0.comp;
+    }
+    if (p0.f64) run_batch_typed<double>(ctx, K);
+    else run_batch_typed<float>(ctx, K);
+  });
+}
+
+pw_status pw_batch_fine_sweeps(pw_ctx* ctx, int reps, double* ms) {
+  return guarded([&] {
+    if (!ctx) fail(PW_EINVAL, "null context");
+    if (!ctx->batch || !ctx->batch->built) fail(PW_ESTATE, "no batched run yet");
+    if (reps < 1) fail(PW_EINVAL, "reps must be >= 1");
+    Batch& b = *ctx->batch;
+    hipStream_t st = ctx->stream;
+    hipEvent_t e0, e1;
+    PW_HIP(hipEventCreate(&e0));
+    PW_HIP(hipEventCreate(&e1));
+    PW_HIP(hipEventRecord(e0, st));
+    for (int r = 0; r < reps; ++r) {
+      if (b.f64) run_multi<double>(b.F64, (const StreamDesc<double>*)b.dF, b.comp, st);
+      else run_multi<float>(b.F32, (const StreamDesc<float>*)b.dF, b.comp, st);
+    }
+    PW_HIP(hipEventRecord(e1, st));
+    PW_HIP(hipEventSynchronize(e1));
+    float t = 0;
+    PW_HIP(hipEventElapsedTime(&t, e0, e1));
+    if (ms) *ms = t / reps;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  });
+}
+
+pw_status pw_get_batch_info(pw_ctx* ctx, int* depth, int* rows_per_stream, double* ms,
+                            int cap) {
+  return guarded([&] {
+    if (!ctx) fail(PW_EINVAL, "null context");
+    if (!ctx->batch || !ctx->batch->built) fail(PW_ESTATE, "no batched run yet");
+    const Batch& b = *ctx->batch;
+    if (depth) *depth = b.B;
+    if (rows_per_stream) *rows_per_stream = b.Ly;
+    const double v[7] = {b.ms[0], b.ms[1], b.ms[2], b.ms[3], b.tune_ms, b.best_ms,
+                         b.from_cache ? 1.0 : 0.0};
+    for (int i = 0; i < 7 && i < cap; ++i) ms[i] = v[i];
   });
 }
 

@@ -65,6 +65,63 @@ void propagate(const Grid& g, const T* c2, const T* u_src, const T* p_src, T* u_
 // grid (the whole propagation when the grid is one periodic line in LDS)
 int steps_per_launch(const Grid& g, bool is_double);
 
+// Streams of one 2D problem in a launch of the streaming kernel: its
+// in/out state sets, grid, and the first global wave index it owns.
+template <typename T>
+struct StreamDesc {
+  const T* u_in;
+  const T* p_in;
+  const T* eu_in;
+  const T* ep_in;
+  T* u_out;
+  T* p_out;
+  T* eu_out;
+  T* ep_out;
+  const T* c2;
+  long long sstride;
+  int nx, ny;
+  int ncb, nseg, Ly;  // column blocks, row segments, rows per segment
+  int nstates;
+  T h, idx2;
+  int nsteps, first, last;
+  long long wave_begin;
+};
+
+// one propagation of a batch: nstates states of one 2D problem by m steps
+template <typename T>
+struct PropJob {
+  Grid g;
+  const T* c2;
+  const T* u_src;
+  const T* p_src;
+  T* u_dst;
+  T* p_dst;
+  long long sstride;
+  int nstates;
+  int m;
+  T h;
+  StateSet<T> wa, wb;
+};
+
+// Launch plan of a multi-problem batched propagation: launch l advances
+// every job that still has steps by one time block of up to B steps.
+// Tunables: B (pipeline depth, 4 or 8) and Ly (target rows per stream).
+template <typename T>
+struct MultiPlan {
+  int B = 8;
+  int Ly = 96;
+  std::vector<int> first_desc;       // per launch: first descriptor index
+  std::vector<int> ndesc;            // per launch: descriptor count
+  std::vector<long long> nwaves;     // per launch
+  std::vector<StreamDesc<T>> descs;  // all launches, host copy
+};
+template <typename T>
+void plan_multi(const std::vector<PropJob<T>>& jobs, MultiPlan<T>& plan);
+// descs_dev: device copy of plan.descs
+template <typename T>
+void run_multi(const MultiPlan<T>& plan, const StreamDesc<T>* descs_dev, bool comp,
+               hipStream_t stream);
+
 // ---------------------------------------------------------------------------
 // grid transfer and energy components (transfer.hip)
 // ---------------------------------------------------------------------------

@@ -282,24 +282,11 @@ __global__ __launch_bounds__(NT) void k_prop_tile(PropArgs<T> a) {
 // the halo is H = B + 1 columns on each side (the +1 for the closing half
 // kick).  No LDS and no barriers.
 // ---------------------------------------------------------------------------
-template <typename T>
-struct Stream2dArgs {
-  const T* u_in;
-  const T* p_in;
-  const T* eu_in;
-  const T* ep_in;
-  T* u_out;
-  T* p_out;
-  T* eu_out;
-  T* ep_out;
-  const T* c2;
-  long long sstride;
-  int nx, ny;
-  int ncb, nseg, Ly;  // column blocks, row segments, rows per segment
-  int nstates;
-  T h, idx2;
-  int nsteps, first, last;
-};
+}  // namespace
+
+// descriptor of one problem's streams in a (possibly multi-problem) launch;
+// declared in pw_internal.h as StreamDesc<T>
+namespace {
 
 template <typename T>
 __device__ __forceinline__ T lane_up(T v) {  // value of lane - 1
@@ -310,19 +297,11 @@ __device__ __forceinline__ T lane_down(T v) {  // value of lane + 1
   return __shfl_down(v, 1, 64);
 }
 
-// TAG separates the fine-grid (0) and coarse-grid (1) instantiations in
-// profiles; the code is the same.
-template <typename T, bool COMP, int B, int TAG>
-__global__ __launch_bounds__(256) void k_prop_stream2d(Stream2dArgs<T> a) {
+// one stream (wavefront) of problem descriptor `a`; wid = local wave index
+template <typename T, bool COMP, int B>
+__device__ __forceinline__ void stream2d_body(const StreamDesc<T>& a, long long wid, int lane) {
   constexpr int H = B + 1;
   constexpr int XV = 64 - 2 * H;  // output columns per wave
-  const int lane = threadIdx.x & 63;
-  const long long nwaves = (long long)a.nstates * a.ncb * a.nseg;
-  const long long nblk = (nwaves + 3) / 4;
-  long long blk = blockIdx.x;
-  if ((nblk & 7) == 0) blk = (blk & 7) * (nblk >> 3) + (blk >> 3);
-  const long long wid = blk * 4 + (threadIdx.x >> 6);
-  if (wid >= nwaves) return;
   const int cb = (int)(wid % a.ncb);
   const int seg = (int)((wid / a.ncb) % a.nseg);
   const int state = (int)(wid / ((long long)a.ncb * a.nseg));
@@ -431,6 +410,42 @@ __global__ __launch_bounds__(256) void k_prop_stream2d(Stream2dArgs<T> a) {
   }
 }
 
+// waves of a launch, remapped so that consecutive blocks of one XCD hold
+// consecutive waves (neighbouring streams share halo rows in one L2)
+__device__ __forceinline__ long long launch_wave(long long nwaves) {
+  const long long nblk = (nwaves + 3) / 4;
+  long long blk = blockIdx.x;
+  if ((nblk & 7) == 0) blk = (blk & 7) * (nblk >> 3) + (blk >> 3);
+  return blk * 4 + (threadIdx.x >> 6);
+}
+
+// single problem; TAG separates the fine-grid (0) and coarse-grid (1)
+// instantiations in profiles, the code is the same
+template <typename T, bool COMP, int B, int TAG>
+__global__ __launch_bounds__(256) void k_prop_stream2d(StreamDesc<T> a) {
+  const long long nwaves = (long long)a.nstates * a.ncb * a.nseg;
+  const long long wid = launch_wave(nwaves);
+  if (wid >= nwaves) return;
+  stream2d_body<T, COMP, B>(a, wid, threadIdx.x & 63);
+}
+
+// many problems of different grids in one launch: wave -> problem through
+// the prefix sums wave_begin of the descriptor table
+template <typename T, bool COMP, int B>
+__global__ __launch_bounds__(256) void k_prop_stream2d_multi(const StreamDesc<T>* descs, int nd,
+                                                             long long nwaves) {
+  const long long wid = launch_wave(nwaves);
+  if (wid >= nwaves) return;
+  int lo = 0, hi = nd - 1;  // last descriptor with wave_begin <= wid
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].wave_begin <= wid) lo = mid;
+    else hi = mid - 1;
+  }
+  const StreamDesc<T> a = descs[lo];
+  stream2d_body<T, COMP, B>(a, wid - a.wave_begin, threadIdx.x & 63);
+}
+
 // tile geometry per dimension: interior and the largest halo of one launch
 struct TileCfg {
   int tx, ty, tz, hmax;
@@ -501,7 +516,7 @@ constexpr int stream_depth() {
 }
 
 template <typename T, bool COMP>
-void dispatch_stream2d(const Stream2dArgs<T>& a, bool fine, hipStream_t st) {
+void dispatch_stream2d(const StreamDesc<T>& a, bool fine, hipStream_t st) {
   constexpr int B = stream_depth<T>();
   const long long nwaves = (long long)a.nstates * a.ncb * a.nseg;
   const long long nblk = (nwaves + 3) / 4;
@@ -521,7 +536,7 @@ void propagate_stream2d(const Grid& g, const T* c2, const T* u_src, const T* p_s
                         StateSet<T> wa, StateSet<T> wb, bool fine, hipStream_t st) {
   constexpr int B = stream_depth<T>();
   constexpr int XV = 64 - 2 * (B + 1);
-  Stream2dArgs<T> a{};
+  StreamDesc<T> a{};
   a.c2 = c2;
   a.sstride = sstride;
   a.nx = g.n[0];
@@ -692,6 +707,122 @@ void propagate(const Grid& g, const T* c2, const T* u_src, const T* p_src, T* u_
     cep = out.ep;
   }
 }
+
+template <typename T>
+void plan_multi(const std::vector<PropJob<T>>& jobs, MultiPlan<T>& plan) {
+  const int B = plan.B;
+  if (B != 4 && B != 8) fail(PW_EINVAL, "pipeline depth must be 4 or 8");
+  if (sizeof(T) == 8 && B != 4) fail(PW_EINVAL, "FP64 streams use depth 4");
+  const int XV = 64 - 2 * (B + 1);
+  plan.first_desc.clear();
+  plan.ndesc.clear();
+  plan.nwaves.clear();
+  plan.descs.clear();
+  int nl = 0;
+  for (const auto& j : jobs) {
+    if (j.g.dim != 2) fail(PW_EINVAL, "batched streams need 2D problems");
+    if (j.m < 1 || j.nstates < 1) fail(PW_EINVAL, "empty job in a batch");
+    nl = std::max(nl, (j.m + B - 1) / B);
+  }
+  for (int l = 0; l < nl; ++l) {
+    plan.first_desc.push_back((int)plan.descs.size());
+    long long waves = 0;
+    for (const auto& j : jobs) {
+      const int njl = (j.m + B - 1) / B;
+      if (l >= njl) continue;
+      if (njl > 1 && (j.wa.u == nullptr || j.wb.u == nullptr))
+        fail(PW_EINVAL, "propagation needs scratch state sets");
+      StreamDesc<T> d{};
+      d.c2 = j.c2;
+      d.sstride = j.sstride;
+      d.nx = j.g.n[0];
+      d.ny = j.g.n[1];
+      d.nstates = j.nstates;
+      d.h = j.h;
+      d.idx2 = T(1.0 / (j.g.dx * j.g.dx));
+      d.ncb = (d.nx + XV - 1) / XV;
+      d.nseg = std::max(1, (d.ny + plan.Ly - 1) / plan.Ly);
+      d.Ly = (d.ny + d.nseg - 1) / d.nseg;
+      d.nseg = (d.ny + d.Ly - 1) / d.Ly;
+      d.first = (l == 0);
+      d.last = (l == njl - 1);
+      d.nsteps = std::min(B, j.m - l * B);
+      // ping-pong: launch l of this job reads what launch l-1 wrote
+      auto set_of = [&](int ll) -> StateSet<T> {
+        StateSet<T> o;
+        if (ll == njl - 1) {
+          o.u = j.u_dst;
+          o.p = j.p_dst;
+        } else {
+          o = ((njl - 1 - ll) % 2 == 1) ? j.wa : j.wb;
+        }
+        return o;
+      };
+      if (l == 0) {
+        d.u_in = j.u_src;
+        d.p_in = j.p_src;
+        d.eu_in = nullptr;
+        d.ep_in = nullptr;
+      } else {
+        const StateSet<T> in = set_of(l - 1);
+        d.u_in = in.u;
+        d.p_in = in.p;
+        d.eu_in = in.eu;
+        d.ep_in = in.ep;
+      }
+      const StateSet<T> out = set_of(l);
+      d.u_out = out.u;
+      d.p_out = out.p;
+      d.eu_out = out.eu;
+      d.ep_out = out.ep;
+      d.wave_begin = waves;
+      waves += (long long)d.nstates * d.ncb * d.nseg;
+      plan.descs.push_back(d);
+    }
+    plan.ndesc.push_back((int)plan.descs.size() - plan.first_desc.back());
+    plan.nwaves.push_back(waves);
+  }
+}
+
+template <typename T>
+void run_multi(const MultiPlan<T>& plan, const StreamDesc<T>* dev, bool comp, hipStream_t st) {
+  for (size_t l = 0; l < plan.nwaves.size(); ++l) {
+    const long long nw = plan.nwaves[l];
+    const long long nblk = (nw + 3) / 4;
+    if (nblk >= (1LL << 31)) fail(PW_EINVAL, "too many streams for one launch");
+    const StreamDesc<T>* d = dev + plan.first_desc[l];
+    const int nd = plan.ndesc[l];
+    if constexpr (sizeof(T) == 4) {
+      if (comp) {
+        if (plan.B == 8)
+          hipLaunchKernelGGL((k_prop_stream2d_multi<T, true, 8>), dim3((unsigned)nblk), dim3(256),
+                             0, st, d, nd, nw);
+        else
+          hipLaunchKernelGGL((k_prop_stream2d_multi<T, true, 4>), dim3((unsigned)nblk), dim3(256),
+                             0, st, d, nd, nw);
+      } else {
+        if (plan.B == 8)
+          hipLaunchKernelGGL((k_prop_stream2d_multi<T, false, 8>), dim3((unsigned)nblk),
+                             dim3(256), 0, st, d, nd, nw);
+        else
+          hipLaunchKernelGGL((k_prop_stream2d_multi<T, false, 4>), dim3((unsigned)nblk),
+                             dim3(256), 0, st, d, nd, nw);
+      }
+    } else {
+      if (comp) fail(PW_EINVAL, "compensation is an FP32 mode");
+      hipLaunchKernelGGL((k_prop_stream2d_multi<T, false, 4>), dim3((unsigned)nblk), dim3(256), 0,
+                         st, d, nd, nw);
+    }
+    PW_LAUNCH_CHECK();
+  }
+}
+
+template void plan_multi<float>(const std::vector<PropJob<float>>&, MultiPlan<float>&);
+template void plan_multi<double>(const std::vector<PropJob<double>>&, MultiPlan<double>&);
+template void run_multi<float>(const MultiPlan<float>&, const StreamDesc<float>*, bool,
+                               hipStream_t);
+template void run_multi<double>(const MultiPlan<double>&, const StreamDesc<double>*, bool,
+                                hipStream_t);
 
 template void propagate<float>(const Grid&, const float*, const float*, const float*, float*,
                                float*, long long, int, int, float, bool, StateSet<float>,

@@ -21,8 +21,12 @@ Workloads (fine grid / coarse grid, unit periodic box):
   N = 32, Courant number <= 0.5 with m_F a multiple of 4 (m_F = 76,
   m_C = 19), K = 6, FP32 compensated state, tol 1e-13.
 
-``scaled(name, ...)`` gives the same recipe on smaller grids / fewer slices
-for tests that must finish in seconds.
+* ``grf2d`` / ``batch2d``  smooth random media c = exp(0.3 g) with random
+  Gaussian pulses; ``batch2d`` draws 32 such problems with fine grids from
+  {256, 384, 512, 768, 1024}^2 (the batched workload).
+
+Every generator takes the grid size, slice count and final time as
+arguments, so tests run the same recipes on grids that finish in seconds.
 """
 
 from __future__ import annotations
@@ -155,5 +159,23 @@ def grf2d(n=64, ratio=4, N=8, K=3, T=0.25, seed=0, dtype="f32",
                     dtype, compensated, c, u0, p0)
 
 
+def batch2d(n_problems=32, sizes=(256, 384, 512, 768, 1024), N=32, K=6,
+            T=1.0, seed=0, dtype="f32", compensated=False):
+    """The batched-problem recipe: n_problems independent 2D problems whose
+    fine grids are drawn uniformly from `sizes` (seed), each with a smooth
+    random medium c = exp(0.3 g) (g a unit Gaussian random field of
+    correlation length 0.1, seed 1000+b) and a random Gaussian pulse
+    (centre ~ U[0,1)^2, sigma ~ U[0.02, 0.05], seed 2000+b); coarse = fine/4,
+    N = 32 slices, Courant number <= 0.5 (m_F a multiple of 4, m_C = m_F/4)."""
+    grids = np.random.default_rng(seed).choice(np.asarray(sizes), n_problems)
+    out = []
+    for b, n in enumerate(grids):
+        w = grf2d(n=int(n), ratio=4, N=N, K=K, T=T, seed=b, dtype=dtype,
+                  compensated=compensated)
+        w.name = f"batch2d[{b}]"
+        out.append(w)
+    return out
+
+
 BY_NAME = {"wave1d": wave1d, "disc2d": disc2d, "layers3d": layers3d,
-           "grf2d": grf2d}
+           "grf2d": grf2d, "batch2d": batch2d}
