@@ -18,3 +18,4 @@ Parity status of every function is listed in the header of `wave.py`.
 """
 
 from .wave import *  # noqa: F401,F403
+from . import adjoint  # noqa: F401

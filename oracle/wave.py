@@ -32,7 +32,7 @@ Parity status (what pins each routine; see tests/test_oracle_pins.py)
 * procrustes, update_svd ................. pinned (brute force over O(2) and
   O(3); the minimum-residual closed form; incremental == direct SVD of the
   explicitly summed correlation matrix; rank identity of Sec. 3.3.1)
-* theta_parareal .......................... pinned (exactness of the first k
+* theta_parareal (and adjoint.py) ......... pinned (exactness of the first k
   slices after k iterations; reduction to textbook parareal with the
   spectral gradient, identical grids and Omega = I; energy preservation of
   the corrected coarse propagator of Sec. 6.3).  The full-loop values on
@@ -369,10 +369,12 @@ class PararealResult:
     rank: list              # rank of Omega^k, k = 1..K
     history: list           # [(u list, p list)] for k = 1..K+1 if kept
     sigma: list             # singular values after each update
+    correctors: list = None  # [(U_k, V_k)] if recorded
 
 
 def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
-                   omega="procrustes", correction=True):
+                   omega="procrustes", correction=True,
+                   record_correctors=False):
     """Algorithm 3 of the paper, step by step.
 
     Initialisation u^1_n = I C R u^1_{n-1}; then K iterations of: parallel
@@ -414,6 +416,7 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
 
     Us = S = Vs = None
     rhos, ranks, sigmas = [], [], []
+    correctors = [] if record_correctors else None
     for _k in range(K):
         v, vp, Uc, Ucp = [None] * (N + 1), [None] * (N + 1), \
             [None] * (N + 1), [None] * (N + 1)
@@ -426,6 +429,8 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
         Gm = np.column_stack([Lam(Uc[n], Ucp[n]) for n in range(1, N + 1)])
         if omega == "procrustes":
             Us, S, Vs = update_svd(Us, S, Vs, Fm, Gm, prob.tol)
+            if record_correctors:
+                correctors.append((Us.copy(), Vs.copy()))
             res = Fm - omega_apply(Us, Vs, Gm)
             ranks.append(len(S))
             sigmas.append(S.copy())
@@ -461,7 +466,8 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
         if keep_history:
             history.append(([x.copy() for x in u], [x.copy() for x in p]))
     return PararealResult(u=u, p=p, rho=rhos, rank=ranks,
-                            history=history, sigma=sigmas)
+                            history=history, sigma=sigmas,
+                            correctors=correctors)
 
 
 def serial_fine(prob: Problem, c, u0, p0):

@@ -1,0 +1,77 @@
+"""Pins of the oracle's misfit gradient (frozen corrector): dot-product
+tests of every hand-written transpose and finite differences of the same
+frozen forward map."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import adjoint as A
+
+
+def _setup(K=2, tol=1e-6, seed=0):
+    rng = np.random.default_rng(seed)
+    n = 32
+    prob = O.Problem((n, n), 4, 0.25, 4, 8, 2, 4, tol)
+    Y, X = np.meshgrid(np.arange(n) / n, np.arange(n) / n, indexing="ij")
+    c = 1.2 + 0.3 * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y)
+    r2 = (X - 0.5) ** 2 + (Y - 0.3) ** 2
+    a = (np.pi * 4.0) ** 2 * r2
+    u0 = (1 - 2 * a) * np.exp(-a)          # Ricker-shaped pulse
+    p0 = np.zeros((n, n))
+    receivers = (n * 24 + np.arange(0, n, 2)).astype(np.int64)
+    data = 0.01 * rng.standard_normal((prob.N, receivers.size))
+    return prob, c, u0, p0, receivers, data
+
+
+def test_forward_frozen_reproduces_algorithm3():
+    prob, c, u0, p0, _, _ = _setup()
+    K = 2
+    res = O.theta_parareal(prob, c, u0, p0, K, record_correctors=True)
+    corr, cc = A.record_correctors(prob, c, u0, p0, K)
+    u, p = A.forward_frozen(prob, c * c, u0, p0, K, corr, cc)
+    for n in range(prob.N + 1):
+        np.testing.assert_allclose(u[n], res.u[n], atol=1e-13)
+        np.testing.assert_allclose(p[n], res.p[n], atol=1e-12)
+
+
+def test_transposes_dot_product():
+    rng = np.random.default_rng(3)
+    prob, c, u0, p0, _, _ = _setup()
+    cs, fs = prob.coarse_shape, prob.shape
+    x = rng.standard_normal(cs)
+    y = rng.standard_normal(fs)
+    assert np.dot(O.interp(x, 4).ravel(), y.ravel()) == pytest.approx(
+        np.dot(x.ravel(), A._interp_T(y, 4, cs).ravel()), rel=1e-12)
+    assert np.dot(O.restrict(y, 4).ravel(), x.ravel()) == pytest.approx(
+        np.dot(y.ravel(), A._restrict_T(x, 4, fs).ravel()), rel=1e-12)
+    # velocity Verlet: <J dx, l> = <dx, J^T l> (linear in the state)
+    c2 = c * c
+    du, dp = rng.standard_normal(fs), rng.standard_normal(fs)
+    lu, lp = rng.standard_normal(fs), rng.standard_normal(fs)
+    ou, op, us = A._prop_store(du, dp, c2, prob.dt_fine, prob.dx_fine, 5)
+    au, ap, _ = A._prop_adjoint(us, lu, lp, c2, prob.dt_fine, prob.dx_fine)
+    lhs = np.sum(ou * lu) + np.sum(op * lp)
+    rhs = np.sum(du * au) + np.sum(dp * ap)
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+@pytest.mark.parametrize("K", [0, 1, 2])
+def test_gradient_matches_finite_differences(K):
+    prob, c, u0, p0, rec, data = _setup()
+    corr, cc = A.record_correctors(prob, c, u0, p0, max(K, 1))
+    c2 = c * c
+    J, g = A.gradient(prob, c2, u0, p0, K, corr, cc, rec, data)
+    rng = np.random.default_rng(11)
+    n = prob.shape[0]
+    Y, X = np.meshgrid(np.arange(n) / n, np.arange(n) / n, indexing="ij")
+    for t in range(3):
+        e = np.cos(2 * np.pi * (rng.integers(1, 4) * X + rng.integers(0, 3) * Y)
+                   + rng.uniform(0, 6)) + 0.3 * rng.standard_normal((n, n))
+        eps = 1e-5
+        def J_at(cc2):
+            u, _ = A.forward_frozen(prob, cc2, u0, p0, K, corr, cc)
+            return A.misfit(u, rec, data)
+        fd = (J_at(c2 + eps * e) - J_at(c2 - eps * e)) / (2 * eps)
+        ad = float(np.sum(g * e))
+        assert ad == pytest.approx(fd, rel=2e-6, abs=1e-12 * abs(J)), (t, ad, fd)
