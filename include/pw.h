@@ -241,8 +241,60 @@ pw_status pw_energy(pw_ctx* ctx, int prob, const void* u, const void* p,
 /* Per-phase device time of the last pw_run in milliseconds, measured with
  * HIP events on the context stream: [0] parallel fine+coarse propagation,
  * [1] creating the corrector (data matrices + Algorithm 1), [2] corrected
- * sweep and update, [3] whole run.  Host output, synchronous.           */
+ * sweep and update, [3] whole run; with cap >= 6 also [4] the last
+ * pw_run_taped / pw_run_frozen and [5] the last pw_backward.  Host output,
+ * synchronous.                                                          */
 pw_status pw_get_timings(pw_ctx* ctx, int prob, double* ms_host, int cap);
+
+/* ---- differentiation with respect to the medium ------------------------
+ * Algorithm 3 is a composition of linear maps of the state whose only
+ * dependence on the medium (besides the corrector) is through c^2 in the
+ * propagators F and C of Sec. 3.1 (C sees the pointwise restriction of
+ * c^2).  Holding the corrector theta^k = I Lambda^dag Omega^k Lambda of
+ * eq. thetarelation fixed at the values a taped run produced (Omega^k from
+ * Algorithm 1 and the c inside Lambda, Lambda^dag), the traces
+ * u^{K+1}_n(x_r), n = 1..N, are differentiable in c^2 and their adjoint is
+ * computed in FP64 by running every step in reverse: velocity Verlet
+ * backwards (the forward trajectory recomputed from checkpoints), the
+ * transposes of the interpolation I and restriction R, and the reduced
+ * sweep recurrence transposed.                                           */
+
+/* Algorithm 3 for K iterations as pw_run, recording a tape on the device:
+ * the slice-start states of every iteration, the corrector pair of every
+ * iteration and the coarse columns of the sweep (about
+ * K*N*Nf*2*sizeof(state) + K*(4+2r)*Nc*8 bytes, owned by the context).
+ * Asynchronous on the context stream except for the rank read-back of
+ * Algorithm 1.                                                          */
+pw_status pw_run_taped(pw_ctx* ctx, int prob, int K);
+
+/* Algorithm 3 for K <= (K of the last pw_run_taped) iterations with the
+ * recorded correctors instead of Algorithm 1 (no data matrices, no SVD),
+ * using the current medium in F, C and R; re-records the states of the
+ * tape.  Residuals are not formed (pw_get_residuals then reports 0
+ * iterations).  PW_ESTATE without a prior taped run.                    */
+pw_status pw_run_frozen(pw_ctx* ctx, int prob, int K);
+
+/* Traces of the current iterate: out[(n-1)*n_rec + r] = u_n(receivers[r])
+ * for n = 1..N, receivers given as flat fine-grid indices (x fastest,
+ * int64, all in [0, Nf) or PW_EINVAL).  on_device applies to receivers
+ * and out (FP64, N x n_rec).  Synchronous.                               */
+pw_status pw_traces(pw_ctx* ctx, int prob, const long long* receivers,
+                    int n_rec, double* out, int on_device);
+
+/* Gradient of J = sum_{n,r} seed[(n-1)*n_rec + r] u^{K+1}_n(receivers[r])
+ * (the vector-Jacobian product of pw_traces) through the last taped or
+ * frozen run, with its correctors held fixed.  grad: Nf doubles on the
+ * fine grid, d J / d c^2 (wrt_velocity = 0) or d J / d c (= 2c dJ/dc^2,
+ * wrt_velocity != 0).  For a misfit 1/2 sum (u - d)^2 pass seed = u - d.
+ * The forward fine and coarse trajectories are recomputed from
+ * checkpoints every `checkpoint_every` steps (<= 0: 64); results do not
+ * depend on it.  on_device applies to receivers, seed and grad.
+ * PW_ESTATE without a tape or after set_medium / set_initial since it was
+ * recorded.  Work buffers (about (2*(N+1) + N*(4 + ckpt)) * Nf * 8 bytes
+ * for ckpt <= m_F) are allocated on first use and kept.  Synchronous.   */
+pw_status pw_backward(pw_ctx* ctx, int prob, const long long* receivers,
+                      int n_rec, const double* seed, double* grad,
+                      int on_device, int wrt_velocity, int checkpoint_every);
 
 #ifdef __cplusplus
 }

@@ -14,7 +14,7 @@ import ctypes
 import os
 
 __all__ = ["Problem", "Solver", "lib", "PwError", "LIB_PATH", "F32", "F64",
-           "FINE", "COARSE"]
+           "FINE", "COARSE", "PararealTraces"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)),
                         "libpwave.so")
@@ -118,6 +118,13 @@ _SIGS = {
     "pw_get_batch_info": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
                           ctypes.POINTER(ctypes.c_int), ctypes.c_void_p,
                           ctypes.c_int],
+    "pw_run_taped": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int],
+    "pw_run_frozen": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int],
+    "pw_traces": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                  ctypes.c_int, ctypes.c_void_p, ctypes.c_int],
+    "pw_backward": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                    ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                    ctypes.c_int, ctypes.c_int, ctypes.c_int],
 }
 
 #: every symbol include/pw.h declares
@@ -278,9 +285,48 @@ class Solver:
         return u, p
 
     def timings(self, prob=0):
-        ms = (ctypes.c_double * 4)()
-        _check(lib().pw_get_timings(self._h, prob, ms, 4))
-        return dict(parallel=ms[0], corrector=ms[1], sweep=ms[2], total=ms[3])
+        ms = (ctypes.c_double * 6)()
+        _check(lib().pw_get_timings(self._h, prob, ms, 6))
+        return dict(parallel=ms[0], corrector=ms[1], sweep=ms[2], total=ms[3],
+                    taped=ms[4], backward=ms[5])
+
+    # -- differentiation --------------------------------------------------------
+    def run_taped(self, K, prob=0):
+        """Algorithm 3 recording the tape the backward pass reads."""
+        _check(lib().pw_run_taped(self._h, prob, int(K)))
+
+    def run_frozen(self, K, prob=0):
+        """Algorithm 3 with the correctors of the last taped run."""
+        _check(lib().pw_run_frozen(self._h, prob, int(K)))
+
+    def _receivers(self, receivers):
+        import torch
+        return torch.as_tensor(receivers).to(device="cuda",
+                                             dtype=torch.int64).contiguous()
+
+    def traces(self, receivers, prob=0):
+        """(N, n_rec) float64: u_n at the receivers (flat fine indices)."""
+        import torch
+        rec = self._receivers(receivers)
+        N = self.problems[prob].n_slices
+        out = torch.empty((N, rec.numel()), dtype=torch.float64, device="cuda")
+        _check(lib().pw_traces(self._h, prob, _ptr(rec), rec.numel(),
+                               _ptr(out), 1))
+        return out
+
+    def backward(self, receivers, seed, wrt="c2", checkpoint_every=64,
+                 prob=0):
+        """Vector-Jacobian product of traces() through the last taped or
+        frozen run: d/d c^2 (wrt="c2") or d/dc (wrt="c") of
+        sum(seed * traces), on the fine grid (float64)."""
+        import torch
+        rec = self._receivers(receivers)
+        sd = self._dev(seed, torch.float64)
+        g = torch.empty(self.shape(prob), dtype=torch.float64, device="cuda")
+        _check(lib().pw_backward(self._h, prob, _ptr(rec), rec.numel(),
+                                 _ptr(sd), _ptr(g), 1, int(wrt == "c"),
+                                 int(checkpoint_every)))
+        return g
 
     def energy(self, u, p, u_ref=None, p_ref=None, prob=0):
         ed, er = ctypes.c_double(), ctypes.c_double()
@@ -349,3 +395,43 @@ class Solver:
         _check(lib().pw_get_corrector(self._h, prob, _ptr(U), _ptr(S), _ptr(V),
                                       r, ctypes.byref(rk)))
         return U[:r], S[:r], V[:r]
+
+
+def _traces_function():
+    import torch
+
+    class _PararealTraces(torch.autograd.Function):
+        """traces = PararealTraces.apply(c, solver, receivers, K, prob):
+        the receiver traces u^{K+1}_n(x_r) (N x n_rec, float64) of
+        Algorithm 3 run on medium c (fine grid, float64 device tensor); the
+        backward pass gives d/dc through the run with its correctors held
+        fixed (pw_backward)."""
+
+        @staticmethod
+        def forward(ctx, c, solver, receivers, K, prob=0):
+            solver.set_medium(c.detach(), prob)
+            solver.run_taped(K, prob)
+            ctx.solver, ctx.receivers, ctx.prob = solver, receivers, prob
+            return solver.traces(receivers, prob)
+
+        @staticmethod
+        def backward(ctx, grad_traces):
+            g = ctx.solver.backward(ctx.receivers, grad_traces.contiguous(),
+                                    wrt="c", prob=ctx.prob)
+            return g, None, None, None, None
+
+    return _PararealTraces
+
+
+class _Lazy:
+    def __init__(self, make):
+        self._make, self._obj = make, None
+
+    def __getattr__(self, name):
+        if self._obj is None:
+            self._obj = self._make()
+        return getattr(self._obj, name)
+
+
+#: torch.autograd.Function over pw_run_taped / pw_traces / pw_backward
+PararealTraces = _Lazy(_traces_function)

@@ -74,6 +74,57 @@ struct Buffers {
   }
 };
 
+// Record of a taped forward run, read by the backward pass: the slice-start
+// states of every iteration, the coarse columns of the reduced sweep and the
+// frozen corrector pair (E_k, P_k) of every iteration.
+struct Tape {
+  std::unique_ptr<Buffers> mem;
+  int Kcap = 0;             // iterations the buffers hold
+  int K = 0;                // iterations of the last taped / frozen run
+  int Kc = 0;               // iterations with recorded correctors
+  long long epoch = -1;     // medium/initial epoch of the recorded run
+  void* us = nullptr;       // Kcap x N fields, state dtype: u^k_n, n = 0..N-1
+  void* ps = nullptr;
+  double* W = nullptr;      // 2Nc x N: initialisation coarse states W_0..W_{N-1}
+  double* Din = nullptr;    // Kcap x (2Nc x N)
+  double* delta = nullptr;  // Kcap x (2Nc x N)
+  double* E = nullptr;      // Kcap x (2Nc x (rmax + 1))
+  double* P = nullptr;
+  std::vector<int> dims;
+  // backward work, allocated on first use
+  std::unique_ptr<Buffers> bw;
+  int bw_ckpt = 0;
+  double *La = nullptr, *Lb = nullptr;   // (N + 1) slots of [u; p] fine adjoints
+  double* Wf = nullptr;                  // N slots of [u; p] widened fine states
+  double *GF = nullptr, *GC = nullptr;   // per-state gradient accumulators
+  double *gc = nullptr, *grad = nullptr, *c2f = nullptr;
+  double *Y = nullptr, *LA = nullptr, *X = nullptr;  // 2Nc x N
+  double *Cn = nullptr, *Cr = nullptr, *Sr = nullptr, *Sn = nullptr, *MT = nullptr;
+  AdjScratch as;
+};
+
+// growable device staging buffer
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void* ensure(size_t b) {
+    if (b <= bytes) return p;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    if (hipMalloc(&p, b) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      fail(PW_ENOMEM, "hipMalloc of a staging buffer failed");
+    }
+    bytes = b;
+    return p;
+  }
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
 struct Prob {
   pw_problem P{};
   Grid gf, gc;
@@ -139,6 +190,11 @@ struct Prob {
   std::vector<int> ranks;
   double ms[4] = {0, 0, 0, 0};
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // adjoint
+  long long epoch = 0;     // bumped by set_medium / set_initial
+  std::unique_ptr<Tape> tape;
+  DevBuf stage_rec, stage_seed, stage_out;
+  double adj_ms[2] = {0, 0};  // last taped forward, last backward
 };
 
 }  // namespace
@@ -573,16 +629,13 @@ void corrector_phase(Prob& pr, int k, hipStream_t st) {
 
 // 3.-4. corrected sweep in corrector coordinates and the update
 template <typename T>
-void sweep_phase(Prob& pr, hipStream_t st) {
+void sweep_core(Prob& pr, const double* E, const double* P, int dim, hipStream_t st) {
   const int N = pr.N;
   const long long Nf = pr.Nf, Nc = pr.Nc;
   T* u = tp<T>(pr.u);
   T* p = tp<T>(pr.p);
   T* v = tp<T>(pr.v);
   T* vp = tp<T>(pr.vp);
-  const int dim = pr.r + 1;
-  const double* E = pr.E[pr.cur];
-  const double* P = pr.Vp[pr.cur];
   // a_n = C (R v_{n-1} - R u^k_{n-1}), v_0 = u0 -> column 0 is zero
   fill(pr.Din, 2 * Nc, 0.0, st);
   if (N > 1)
@@ -603,6 +656,11 @@ void sweep_phase(Prob& pr, hipStream_t st) {
                 st);
   interp_add<T>(pr.gf, pr.gc, pr.ratio, pr.itab, tp<T>(pr.dp_T), Nc, vp, p + Nf, Nf, N,
                 pr.itmp, st);
+}
+
+template <typename T>
+void sweep_phase(Prob& pr, hipStream_t st) {
+  sweep_core<T>(pr, pr.E[pr.cur], pr.Vp[pr.cur], pr.r + 1, st);
 }
 
 void accumulate_phase_times(Prob& pr) {
@@ -706,6 +764,239 @@ void serial_fine_typed(Prob& pr, int n, T* uo, T* po, hipStream_t st) {
     su = du;
     sp = dp;
   }
+}
+
+// ---------------------------------------------------------------------------
+// taped forward, frozen-corrector replay and the backward pass
+// ---------------------------------------------------------------------------
+void ensure_tape(Prob& pr, int K) {
+  if (!pr.tape) pr.tape = std::make_unique<Tape>();
+  Tape& t = *pr.tape;
+  const int Kc = std::max(K, 1);
+  if (t.mem && t.Kcap >= Kc) return;
+  // (re)allocate for Kc iterations; the backward work buffers are kept
+  t.mem.reset();
+  t.mem = std::make_unique<Buffers>();
+  Buffers& m = *t.mem;
+  t.dims.clear();
+  t.K = t.Kc = 0;
+  t.epoch = -1;
+  const long long N = pr.N, Nf = pr.Nf, Nc = pr.Nc;
+  t.Kcap = Kc;
+  t.us = m.get(pr.tsize * Nf * N * Kc);
+  t.ps = m.get(pr.tsize * Nf * N * Kc);
+  t.W = m.get_n<double>(2 * Nc * N);
+  t.Din = m.get_n<double>(2 * Nc * N * Kc);
+  t.delta = m.get_n<double>(2 * Nc * N * Kc);
+  t.E = m.get_n<double>(2 * Nc * (pr.rmax + 1) * Kc);
+  t.P = m.get_n<double>(2 * Nc * (pr.rmax + 1) * Kc);
+}
+
+template <typename T>
+void tape_init_states(Prob& pr, Tape& t, hipStream_t st) {
+  const long long Nc = pr.Nc;
+  const int N = pr.N;
+  // W_0 = R u0 (restricted by the initialisation), W_n = U_n (n >= 1)
+  widen_fields<T>(tp<T>(pr.Rc), Nc, t.W, 2 * Nc, Nc, 1, st);
+  widen_fields<T>(tp<T>(pr.Rcp), Nc, t.W + Nc, 2 * Nc, Nc, 1, st);
+  widen_fields<T>(tp<T>(pr.Uc), Nc, t.W + 2 * Nc, 2 * Nc, Nc, N - 1, st);
+  widen_fields<T>(tp<T>(pr.Ucp), Nc, t.W + 3 * Nc, 2 * Nc, Nc, N - 1, st);
+}
+
+// Algorithm 3 recording the tape.  frozen = false: the corrector of every
+// iteration comes from Algorithm 1 as in pw_run and is recorded; frozen =
+// true: the recorded correctors are replayed (no data matrices, no SVD),
+// with the current medium in F, C and R.
+template <typename T>
+void run_taped_typed(Prob& pr, int K, bool frozen, hipStream_t st) {
+  Tape& t = *pr.tape;
+  const int N = pr.N;
+  const long long Nf = pr.Nf, Nc = pr.Nc;
+  const size_t sbytes = pr.tsize * Nf * N;
+  const long long ecols = 2 * Nc * (pr.rmax + 1);
+  hipEvent_t e0, e1;
+  PW_HIP(hipEventCreate(&e0));
+  PW_HIP(hipEventCreate(&e1));
+  PW_HIP(hipEventRecord(e0, st));
+  init_phase<T>(pr, st);
+  tape_init_states<T>(pr, t, st);
+  if (!frozen) t.dims.assign(K, 0);
+  for (int k = 1; k <= K; ++k) {
+    const int kk = k - 1;
+    PW_HIP(hipMemcpyAsync((char*)t.us + sbytes * kk, pr.u, sbytes, hipMemcpyDeviceToDevice, st));
+    PW_HIP(hipMemcpyAsync((char*)t.ps + sbytes * kk, pr.p, sbytes, hipMemcpyDeviceToDevice, st));
+    prop_fine<T>(pr, tp<T>(pr.u), tp<T>(pr.p), tp<T>(pr.v), tp<T>(pr.vp), N, st);
+    const double* E;
+    const double* P;
+    int dim;
+    if (!frozen) {
+      restrict_phase<T>(pr, st);
+      prop_coarse<T>(pr, tp<T>(pr.Rc), tp<T>(pr.Rcp), tp<T>(pr.Uc), tp<T>(pr.Ucp), N, st);
+      corrector_phase<T>(pr, k, st);
+      E = pr.E[pr.cur];
+      P = pr.Vp[pr.cur];
+      dim = pr.r + 1;
+      PW_HIP(hipMemcpyAsync(t.E + ecols * kk, E, sizeof(double) * 2 * Nc * dim,
+                            hipMemcpyDeviceToDevice, st));
+      PW_HIP(hipMemcpyAsync(t.P + ecols * kk, P, sizeof(double) * 2 * Nc * dim,
+                            hipMemcpyDeviceToDevice, st));
+      t.dims[kk] = dim;
+    } else {
+      E = t.E + ecols * kk;
+      P = t.P + ecols * kk;
+      dim = t.dims[kk];
+    }
+    sweep_core<T>(pr, E, P, dim, st);
+    PW_HIP(hipMemcpyAsync(t.Din + 2 * Nc * N * kk, pr.Din, sizeof(double) * 2 * Nc * N,
+                          hipMemcpyDeviceToDevice, st));
+    PW_HIP(hipMemcpyAsync(t.delta + 2 * Nc * N * kk, pr.delta, sizeof(double) * 2 * Nc * N,
+                          hipMemcpyDeviceToDevice, st));
+    if (!frozen) pr.k_done = k;
+  }
+  PW_HIP(hipEventRecord(e1, st));
+  PW_HIP(hipEventSynchronize(e1));
+  float ms = 0;
+  PW_HIP(hipEventElapsedTime(&ms, e0, e1));
+  pr.adj_ms[0] = ms;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  t.K = K;
+  if (!frozen) t.Kc = K;
+  t.epoch = pr.epoch;
+  if (frozen) {
+    pr.k_done = 0;  // no residuals: the data matrices were not formed
+    pr.ranks.clear();
+  }
+}
+
+void ensure_backward(Prob& pr, int ckpt) {
+  Tape& t = *pr.tape;
+  if (t.bw && t.bw_ckpt == ckpt) return;
+  t.bw.reset();
+  t.bw = std::make_unique<Buffers>();
+  Buffers& m = *t.bw;
+  const long long N = pr.N, Nf = pr.Nf, Nc = pr.Nc;
+  const long long d1 = pr.rmax + 1;
+  t.La = m.get_n<double>((N + 1) * 2 * Nf);
+  t.Lb = m.get_n<double>((N + 1) * 2 * Nf);
+  t.Wf = m.get_n<double>(N * 2 * Nf);
+  t.GF = m.get_n<double>(N * Nf);
+  t.GC = m.get_n<double>(N * Nc);
+  t.gc = m.get_n<double>(Nc);
+  t.grad = m.get_n<double>(Nf);
+  t.c2f = m.get_n<double>(Nf);
+  t.Y = m.get_n<double>(2 * Nc * N);
+  t.LA = m.get_n<double>(2 * Nc * N);
+  t.X = m.get_n<double>(2 * Nc * N);
+  t.Cn = m.get_n<double>(d1 * N);
+  t.Cr = m.get_n<double>(d1 * N);
+  t.Sr = m.get_n<double>(d1 * N);
+  t.Sn = m.get_n<double>(d1 * N);
+  t.MT = m.get_n<double>(d1 * d1);
+  // one time level holds N fine states (>= N coarse columns)
+  const int msteps = std::max(pr.mF, pr.mC);
+  AdjScratch& a = t.as;
+  a.state_elems = N * Nf;
+  a.max_ckpt = (msteps + ckpt - 1) / ckpt;
+  a.max_seg = std::min(ckpt, msteps) + 1;
+  a.ck_u = m.get_n<double>(a.state_elems * a.max_ckpt);
+  a.ck_p = m.get_n<double>(a.state_elems * a.max_ckpt);
+  a.seg = m.get_n<double>(a.state_elems * a.max_seg);
+  a.p_tmp = m.get_n<double>(a.state_elems);
+  a.a_tmp = m.get_n<double>(a.state_elems);
+  a.lp_tmp = m.get_n<double>(a.state_elems);
+  t.bw_ckpt = ckpt;
+}
+
+// d J / d c^2 of J = sum_{n, r} seed[n][r] u^{K+1}_{n+1}(x_r) through the
+// recorded run (frozen correctors), written to t.grad (fine grid, FP64).
+template <typename T>
+void backward_typed(Prob& pr, const long long* rec, int nrec, const double* seed, int ckpt,
+                    hipStream_t st) {
+  Tape& t = *pr.tape;
+  const int N = pr.N, K = t.K;
+  const long long Nf = pr.Nf, Nc = pr.Nc;
+  const long long F2 = 2 * Nf, C2 = 2 * Nc;
+  const long long ecols = C2 * (pr.rmax + 1);
+  const Grid& gf = pr.gf;
+  const Grid& gc = pr.gc;
+  hipEvent_t e0, e1;
+  PW_HIP(hipEventCreate(&e0));
+  PW_HIP(hipEventCreate(&e1));
+  PW_HIP(hipEventRecord(e0, st));
+  mul_fields(pr.cf, pr.cf, t.c2f, Nf, 1.0, st);
+  fill(t.La, (N + 1) * F2, 0.0, st);
+  fill(t.Lb, (N + 1) * F2, 0.0, st);
+  fill(t.GF, (long long)N * Nf, 0.0, st);
+  fill(t.GC, (long long)N * Nc, 0.0, st);
+  // slot n of A holds the adjoint of the state u_n ([u; p], n = 0..N)
+  double* A = t.La;
+  double* B = t.Lb;
+  receiver_scatter(seed, rec, nrec, N, A + F2, F2, st);
+  for (int k = K; k >= 1; --k) {
+    const int kk = k - 1;
+    const double* E = t.E + ecols * kk;
+    const double* P = t.P + ecols * kk;
+    const int dim = t.dims[kk];
+    const double* Din = t.Din + C2 * N * kk;
+    const double* dl = t.delta + C2 * N * kk;
+    // adjoint of u^{k+1}_n = v_n + I E t_n: y_n = I^T L_n, c_n = E^T y_n
+    interp_transpose(gf, gc, pr.ratio, pr.itab, A + F2, F2, t.Y, C2, N, pr.itmp, st);
+    interp_transpose(gf, gc, pr.ratio, pr.itab, A + F2 + Nf, F2, t.Y + Nc, C2, N, pr.itmp, st);
+    gemm_tn(C2, dim, N, 1.0, E, C2, t.Y, C2, 0.0, t.Cn, dim, pr.gwork, pr.gwork_elems, st);
+    // t_n = P^T a_n + M t_{n-1}, M = P^T C E: s_n = c_n + M^T s_{n+1}
+    prop_coarse_cols(pr, E, pr.CE, dim, st);
+    gemm_tn(C2, dim, dim, 1.0, pr.CE, C2, P, C2, 0.0, t.MT, dim, pr.gwork, pr.gwork_elems, st);
+    reverse_cols(dim, N, t.Cn, dim, t.Cr, dim, st);
+    recurrence(dim, N, t.MT, t.Cr, t.Sr, pr.rs, st);
+    reverse_cols(dim, N, t.Sr, dim, t.Sn, dim, st);
+    // adjoint of a_n: P s_n
+    gemm_nn(C2, N, dim, 1.0, P, C2, t.Sn, dim, 0.0, t.LA, C2, st);
+    // C acts on x_n = Din_n + delta_{n-1} (a_n and the C E t_{n-1} of M)
+    copy_fields(Din, C2 * N, t.X, C2 * N, C2 * N, 1, st);
+    add_inplace(t.X + C2, dl, C2 * (N - 1), st);
+    vv_adjoint(gc, pr.c2c_d, t.X, t.X + Nc, C2, t.LA, t.LA + Nc, C2, t.GC, Nc, N, pr.mC, pr.hC,
+               ckpt, t.as, st);
+    // LA column n now holds the adjoint of Din_{n+1} = R v_n - R u^k_n
+    restrict_transpose_add(gf, pr.ratio, gc, t.LA + C2, C2, A + F2, F2, 1.0, N - 1, st);
+    restrict_transpose_add(gf, pr.ratio, gc, t.LA + C2 + Nc, C2, A + F2 + Nf, F2, 1.0, N - 1,
+                           st);
+    // v_n = F u^k_{n-1}
+    widen_fields<T>(tp<T>(t.us) + Nf * N * kk, Nf, t.Wf, F2, Nf, N, st);
+    widen_fields<T>(tp<T>(t.ps) + Nf * N * kk, Nf, t.Wf + Nf, F2, Nf, N, st);
+    vv_adjoint(gf, t.c2f, t.Wf, t.Wf + Nf, F2, A + F2, A + F2 + Nf, F2, t.GF, Nf, N, pr.mF, pr.hF,
+               ckpt, t.as, st);
+    // slot n of A: adjoint of u^k_{n-1} through F; shift into B and add the
+    // -R^T part of Din
+    copy_fields(A + 2 * F2, F2, B + F2, F2, F2, N - 1, st);
+    restrict_transpose_add(gf, pr.ratio, gc, t.LA + C2, C2, B + F2, F2, -1.0, N - 1, st);
+    restrict_transpose_add(gf, pr.ratio, gc, t.LA + C2 + Nc, C2, B + F2 + Nf, F2, -1.0, N - 1,
+                           st);
+    fill(B + (long long)N * F2, F2, 0.0, st);
+    std::swap(A, B);
+  }
+  // initialisation u^1_n = I W_n, W_n = C W_{n-1}
+  interp_transpose(gf, gc, pr.ratio, pr.itab, A + F2, F2, t.Y, C2, N, pr.itmp, st);
+  interp_transpose(gf, gc, pr.ratio, pr.itab, A + F2 + Nf, F2, t.Y + Nc, C2, N, pr.itmp, st);
+  double* lam = t.LA;
+  fill(lam, C2, 0.0, st);
+  for (int n = N; n >= 1; --n) {
+    add_inplace(lam, t.Y + C2 * (n - 1), C2, st);
+    const double* Wn = t.W + C2 * (n - 1);
+    vv_adjoint(gc, pr.c2c_d, Wn, Wn + Nc, C2, lam, lam + Nc, C2, t.GC, Nc, 1, pr.mC, pr.hC, ckpt,
+               t.as, st);
+  }
+  // the gradient: fine accumulators + R^T of the coarse ones
+  sum_fields(t.GC, Nc, N, t.gc, Nc, false, st);
+  sum_fields(t.GF, Nf, N, t.grad, Nf, false, st);
+  restrict_transpose_add(gf, pr.ratio, gc, t.gc, Nc, t.grad, Nf, 1.0, 1, st);
+  PW_HIP(hipEventRecord(e1, st));
+  PW_HIP(hipEventSynchronize(e1));
+  float ms = 0;
+  PW_HIP(hipEventElapsedTime(&ms, e0, e1));
+  pr.adj_ms[1] = ms;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
 }
 
 // ---------------------------------------------------------------------------
@@ -1067,6 +1358,7 @@ pw_status pw_set_medium(pw_ctx* ctx, int prob, const double* c, int on_device) {
     else set_medium_typed<float>(pr, st);
     PW_HIP(hipStreamSynchronize(st));
     pr.have_medium = true;
+    ++pr.epoch;
   });
 }
 
@@ -1084,6 +1376,7 @@ pw_status pw_set_initial(pw_ctx* ctx, int prob, const double* u0, const double* 
     else set_initial_typed<float>(pr, du, dp, st);
     PW_HIP(hipStreamSynchronize(st));
     pr.have_initial = true;
+    ++pr.epoch;
     pr.k_done = 0;
     reset_corrector(pr);
   });
@@ -1347,6 +1640,112 @@ pw_status pw_get_timings(pw_ctx* ctx, int prob, double* ms, int cap) {
   return guarded([&] {
     Prob& pr = get_prob(ctx, prob);
     for (int i = 0; i < 4 && i < cap; ++i) ms[i] = pr.ms[i];
+    for (int i = 0; i < 2 && i + 4 < cap; ++i) ms[i + 4] = pr.adj_ms[i];
+  });
+}
+
+// ---- adjoint ---------------------------------------------------------------
+pw_status pw_run_taped(pw_ctx* ctx, int prob, int K) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (!pr.have_medium || !pr.have_initial) fail(PW_ESTATE, "set medium and initial state first");
+    if (K < 0 || K > pr.P.max_iters) fail(PW_EINVAL, "K must be in [0, max_iters]");
+    ensure_tape(pr, K);
+    if (pr.f64) run_taped_typed<double>(pr, K, false, ctx->stream);
+    else run_taped_typed<float>(pr, K, false, ctx->stream);
+  });
+}
+
+pw_status pw_run_frozen(pw_ctx* ctx, int prob, int K) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (!pr.have_medium || !pr.have_initial) fail(PW_ESTATE, "set medium and initial state first");
+    if (!pr.tape || K < 0 || K > pr.tape->Kc)
+      fail(PW_ESTATE, "run_frozen needs correctors recorded by pw_run_taped for K iterations");
+    if (pr.f64) run_taped_typed<double>(pr, K, true, ctx->stream);
+    else run_taped_typed<float>(pr, K, true, ctx->stream);
+  });
+}
+
+// receivers: checked on the host (copied there first when on the device)
+const long long* stage_receivers(Prob& pr, const long long* rec, int nrec, int on_device,
+                                 hipStream_t st) {
+  if (nrec < 0) fail(PW_EINVAL, "negative receiver count");
+  if (nrec == 0) return nullptr;
+  if (!rec) fail(PW_EINVAL, "null receivers");
+  std::vector<long long> h((size_t)nrec);
+  if (on_device) {
+    PW_HIP(hipMemcpyAsync(h.data(), rec, sizeof(long long) * nrec, hipMemcpyDeviceToHost, st));
+    PW_HIP(hipStreamSynchronize(st));
+  } else {
+    std::memcpy(h.data(), rec, sizeof(long long) * nrec);
+  }
+  for (long long x : h)
+    if (x < 0 || x >= pr.Nf) fail(PW_EINVAL, "receiver index outside the fine grid");
+  if (on_device) return rec;
+  long long* d = (long long*)pr.stage_rec.ensure(sizeof(long long) * nrec);
+  PW_HIP(hipMemcpyAsync(d, h.data(), sizeof(long long) * nrec, hipMemcpyHostToDevice, st));
+  PW_HIP(hipStreamSynchronize(st));
+  return d;
+}
+
+pw_status pw_traces(pw_ctx* ctx, int prob, const long long* receivers, int n_rec, double* out,
+                    int on_device) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    hipStream_t st = ctx->stream;
+    const long long* rec = stage_receivers(pr, receivers, n_rec, on_device, st);
+    if (n_rec == 0) return;
+    if (!out) fail(PW_EINVAL, "null output");
+    const long long n = (long long)pr.N * n_rec;
+    double* dst = on_device ? out : (double*)pr.stage_out.ensure(sizeof(double) * n);
+    const size_t off = pr.tsize * pr.Nf;  // fields n = 1..N
+    if (pr.f64)
+      receiver_values<double>((const double*)((const char*)pr.u + off), pr.Nf, rec, n_rec, pr.N,
+                              dst, st);
+    else
+      receiver_values<float>((const float*)((const char*)pr.u + off), pr.Nf, rec, n_rec, pr.N,
+                             dst, st);
+    if (!on_device) {
+      PW_HIP(hipMemcpyAsync(out, dst, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+      PW_HIP(hipStreamSynchronize(st));
+    }
+  });
+}
+
+pw_status pw_backward(pw_ctx* ctx, int prob, const long long* receivers, int n_rec,
+                      const double* seed, double* grad, int on_device, int wrt_velocity,
+                      int checkpoint_every) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    hipStream_t st = ctx->stream;
+    if (!pr.tape || pr.tape->epoch < 0)
+      fail(PW_ESTATE, "pw_backward needs a run by pw_run_taped or pw_run_frozen");
+    if (pr.tape->epoch != pr.epoch)
+      fail(PW_ESTATE, "medium or initial state changed since the taped run");
+    if (!grad) fail(PW_EINVAL, "null gradient output");
+    const int ckpt = checkpoint_every > 0 ? checkpoint_every : 64;
+    const long long* rec = stage_receivers(pr, receivers, n_rec, on_device, st);
+    const long long ns = (long long)pr.N * n_rec;
+    const double* sd = nullptr;
+    if (n_rec > 0) {
+      if (!seed) fail(PW_EINVAL, "null seed");
+      sd = (const double*)stage_in(seed, ns, on_device, pr,
+                                   (double*)pr.stage_seed.ensure(sizeof(double) * ns), st);
+    }
+    ensure_backward(pr, ckpt);
+    if (pr.f64) backward_typed<double>(pr, rec, n_rec, sd, ckpt, st);
+    else backward_typed<float>(pr, rec, n_rec, sd, ckpt, st);
+    Tape& t = *pr.tape;
+    double* g = t.grad;
+    if (wrt_velocity) {
+      // d J / d c = 2 c d J / d c^2
+      mul_fields(pr.cf, t.grad, t.Wf, pr.Nf, 2.0, st);
+      g = t.Wf;
+    }
+    PW_HIP(hipMemcpyAsync(grad, g, sizeof(double) * pr.Nf,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    PW_HIP(hipStreamSynchronize(st));
   });
 }
 

@@ -270,4 +270,61 @@ void fill(double* p, long long n, double v, hipStream_t stream);
 void frob_norm2(const double* A, long long rows, int cols, long long lda, double* partials,
                 double* out, hipStream_t stream);
 
+// ---------------------------------------------------------------------------
+// adjoint building blocks (adjoint.hip), FP64
+// ---------------------------------------------------------------------------
+// Scratch of vv_adjoint: one "time level" holds ns states of np points
+// (state_elems >= ns * np).  ck_u / ck_p: max_ckpt levels (checkpoints);
+// seg: max_seg levels (displacements of one recomputed segment);
+// p_tmp, a_tmp, lp_tmp: one level each.
+struct AdjScratch {
+  long long state_elems = 0;
+  int max_ckpt = 0, max_seg = 0;
+  double* ck_u = nullptr;
+  double* ck_p = nullptr;
+  double* seg = nullptr;
+  double* p_tmp = nullptr;
+  double* a_tmp = nullptr;
+  double* lp_tmp = nullptr;
+};
+
+// Reverse of m velocity-Verlet steps (size h, medium c2) of ns states whose
+// inputs are (u0, p0) (state s at offset s * s0).  (lu, lp) hold the adjoint
+// of the outputs on entry and of the inputs on return (stride sl);
+// gacc[s * sg + J] += d J / d c2(J) of state s.  The forward trajectory is
+// recomputed from checkpoints taken every `ckpt` steps.
+void vv_adjoint(const Grid& g, const double* c2, const double* u0, const double* p0,
+                long long s0, double* lu, double* lp, long long sl, double* gacc, long long sg,
+                int ns, int m, double h, int ckpt, const AdjScratch& sc, hipStream_t stream);
+
+template <typename T>
+void widen_fields(const T* in, long long si, double* out, long long so, long long np, int ns,
+                  hipStream_t stream);
+void copy_fields(const double* in, long long si, double* out, long long so, long long np, int ns,
+                 hipStream_t stream);
+// transpose of interp (without the added base field): fine fields -> coarse
+void interp_transpose(const Grid& fine, const Grid& coarse, int ratio,
+                      const double* const* tables, const double* in, long long sin, double* out,
+                      long long sout, int nfields, double* tmp, hipStream_t stream);
+// out[fine node ratio * J] += scale * in[J] (transpose of the restriction)
+void restrict_transpose_add(const Grid& fine, int ratio, const Grid& coarse, const double* in,
+                            long long sin, double* out, long long sout, double scale,
+                            int nfields, hipStream_t stream);
+// out[J] (+)= sum over ns fields in[s * si + J], summed in field order
+void sum_fields(const double* in, long long si, int ns, double* out, long long np, bool acc,
+                hipStream_t stream);
+// res[n][r] = u_n(rec[r]) - data[n][r] (data may be null: zero)
+template <typename T>
+void receiver_values(const T* u, long long su, const long long* rec, int nrec, int nst,
+                     double* out, hipStream_t stream);
+// lam[n * sl + rec[r]] += seed[n][r], receivers handled in order (no atomics)
+void receiver_scatter(const double* seed, const long long* rec, int nrec, int nst, double* lam,
+                      long long sl, hipStream_t stream);
+// dst column j = src column (n - 1 - j), m rows
+void reverse_cols(int m, int n, const double* src, long long lds, double* dst, long long ldd,
+                  hipStream_t stream);
+// out[J] = scale * a[J] * b[J]
+void mul_fields(const double* a, const double* b, double* out, long long n, double scale,
+                hipStream_t stream);
+
 }  // namespace pw

@@ -1,0 +1,196 @@
+"""Parity of the HIP adjoint (pw_run_taped / pw_run_frozen / pw_traces /
+pw_backward) with the FP64 oracle's hand-written adjoint of Algorithm 3 with
+frozen correctors, plus finite differences through the GPU's own frozen
+forward, checkpoint-interval invariance and the autograd Function.
+
+Gates (FP64 state): traces to 1e-12 absolute (values are O(0.1)); J to
+1e-10 relative; gradient max-abs error <= 1e-8 * max |oracle gradient|.
+The two sides compute the correctors independently (same Algorithm 1, other
+rounding); with svd_tol 1e-6 the kept directions have sigma_i / sigma_1 >=
+1e-6, where rounding moves Omega by ~eps * 1e6 ~ 1e-10 relative.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from oracle import adjoint as A
+from tests.gpu_helpers import to_np
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "2d": dict(shape=(32, 32), ratio=4, m_fine=8, m_coarse=2),
+    "1d": dict(shape=(64,), ratio=4, m_fine=16, m_coarse=4),
+    "3d": dict(shape=(16, 16, 16), ratio=2, m_fine=8, m_coarse=2),
+    # 2D, several tiles and a ragged tail on both axes, N = 6 slices
+    "2d_ragged": dict(shape=(40, 72), ratio=4, N=6, m_fine=12, m_coarse=3,
+                      T=0.375),
+}
+
+
+def _solver(w, K, dtype="f64", compensated=False):
+    import paper_1905_00473_amd as pw
+    P = pw.Problem.make(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
+                        w.grad_order, w.tol, dtype, compensated, max(K, 1))
+    s = pw.Solver(P)
+    s.set_medium(w.c)
+    if dtype == "f32":
+        u0 = w.u0.astype(np.float32).astype(np.float64)
+    else:
+        u0 = w.u0
+    s.set_initial(u0, w.p0)
+    return s, u0
+
+
+def _oracle(w, u0, K, rec, data):
+    Q = O.Problem(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
+                  w.grad_order, w.tol)
+    corr, cc = A.record_correctors(Q, w.c, u0, w.p0, max(K, 1))
+    J, g = A.gradient(Q, w.c * w.c, u0, w.p0, K, corr, cc, rec, data)
+    u, _ = A.forward_frozen(Q, w.c * w.c, u0, w.p0, K, corr, cc)
+    tr = np.stack([u[n].ravel()[rec] for n in range(1, w.N + 1)])
+    return J, g, tr, [c[0].shape[1] for c in corr[:K]]
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("K", [0, 1, 2])
+def test_backward_matches_oracle(case, K):
+    kw = dict(CASES[case])
+    w, rec, data = W.misfit_case(K=K, **kw)
+    print(f"adjoint parity {case} K={K} shape={w.shape}", flush=True)
+    s, u0 = _solver(w, K)
+    s.run_taped(K)
+    tr = to_np(s.traces(rec))
+    J_ref, g_ref, tr_ref, ranks_ref = _oracle(w, u0, K, rec, data)
+    _, ranks = s.residuals()
+    assert list(ranks) == ranks_ref
+    np.testing.assert_allclose(tr, tr_ref, rtol=0, atol=1e-12)
+    seed = tr - data
+    J = 0.5 * float(np.sum(seed * seed))
+    assert J == pytest.approx(J_ref, rel=1e-10)
+    g = to_np(s.backward(rec, seed, wrt="c2"))
+    err = np.abs(g - g_ref).max()
+    assert err <= 1e-8 * np.abs(g_ref).max(), (err, np.abs(g_ref).max())
+    # d/dc = 2 c d/dc^2
+    gc = to_np(s.backward(rec, seed, wrt="c"))
+    np.testing.assert_allclose(gc, 2 * w.c * g, rtol=1e-14, atol=0)
+    s.close()
+
+
+def test_checkpoint_interval_does_not_change_the_gradient():
+    w, rec, data = W.misfit_case(K=2, **CASES["2d_ragged"])
+    s, _ = _solver(w, 2)
+    s.run_taped(2)
+    seed = to_np(s.traces(rec)) - data
+    g64 = to_np(s.backward(rec, seed, checkpoint_every=64))
+    for ck in (1, 3, 5, 12):
+        g = to_np(s.backward(rec, seed, checkpoint_every=ck))
+        assert np.array_equal(g, g64), ck
+    s.close()
+
+
+def test_frozen_replay_reproduces_the_taped_run():
+    w, rec, _ = W.misfit_case(K=2, **CASES["2d"])
+    s, _ = _solver(w, 2)
+    s.run_taped(2)
+    a = to_np(s.traces(rec))
+    u2a, p2a = s.state(w.N)
+    s.run_frozen(2)
+    b = to_np(s.traces(rec))
+    u2b, p2b = s.state(w.N)
+    assert np.array_equal(a, b)
+    assert np.array_equal(to_np(u2a), to_np(u2b))
+    assert np.array_equal(to_np(p2a), to_np(p2b))
+    s.close()
+
+
+@pytest.mark.parametrize("case", ["2d", "3d"])
+def test_gradient_matches_gpu_finite_differences(case):
+    """Central differences of J through pw_run_frozen (the GPU's own frozen
+    forward) against <grad, e> for random directions e."""
+    K = 2
+    w, rec, data = W.misfit_case(K=K, **CASES[case])
+    s, _ = _solver(w, K)
+    s.run_taped(K)
+    seed = to_np(s.traces(rec)) - data
+    J0 = 0.5 * float(np.sum(seed * seed))
+    g = to_np(s.backward(rec, seed, wrt="c2"))
+    rng = np.random.default_rng(7)
+    c2 = w.c * w.c
+    for t in range(2):
+        e = rng.standard_normal(w.shape)
+        eps = 1e-5
+
+        def J_at(x):
+            s.set_medium(np.sqrt(x))
+            s.run_frozen(K)
+            d = to_np(s.traces(rec)) - data
+            return 0.5 * float(np.sum(d * d))
+
+        fd = (J_at(c2 + eps * e) - J_at(c2 - eps * e)) / (2 * eps)
+        ad = float(np.sum(g * e))
+        assert ad == pytest.approx(fd, rel=1e-6, abs=1e-12 * J0), (t, ad, fd)
+    s.close()
+
+
+def test_fp32_compensated_gradient_close_to_oracle():
+    """FP32 compensated states, FP64 adjoint: the gradient follows the
+    FP64 oracle to the accuracy of the FP32 trajectory."""
+    K = 2
+    w, rec, data = W.misfit_case(K=K, **CASES["2d"])
+    s, u0 = _solver(w, K, dtype="f32", compensated=True)
+    s.run_taped(K)
+    seed = to_np(s.traces(rec)) - data
+    g = to_np(s.backward(rec, seed))
+    _, g_ref, _, _ = _oracle(w, u0, K, rec, data)
+    err = np.abs(g - g_ref).max()
+    assert err <= 1e-4 * np.abs(g_ref).max(), (err, np.abs(g_ref).max())
+    s.close()
+
+
+def test_autograd_function():
+    import torch
+    import paper_1905_00473_amd as pw
+    K = 1
+    w, rec, data = W.misfit_case(K=K, **CASES["2d"])
+    s, u0 = _solver(w, K)
+    c = torch.tensor(w.c, dtype=torch.float64, device="cuda",
+                     requires_grad=True)
+    d = torch.tensor(data, dtype=torch.float64, device="cuda")
+    tr = pw.PararealTraces.apply(c, s, rec, K)
+    loss = 0.5 * ((tr - d) ** 2).sum()
+    loss.backward()
+    J_ref, g_ref, _, _ = _oracle(w, u0, K, rec, data)
+    assert float(loss.detach()) == pytest.approx(J_ref, rel=1e-10)
+    gc = to_np(c.grad)
+    ref = 2 * w.c * g_ref
+    assert np.abs(gc - ref).max() <= 1e-8 * np.abs(ref).max()
+    s.close()
+
+
+def test_backward_call_order_and_argument_errors():
+    import paper_1905_00473_amd as pw
+    w, rec, data = W.misfit_case(K=1, **CASES["2d"])
+    s, _ = _solver(w, 1)
+    seed = np.zeros((w.N, rec.size))
+    with pytest.raises(pw.PwError, match="PW_ESTATE"):
+        s.backward(rec, seed)
+    with pytest.raises(pw.PwError, match="PW_ESTATE"):
+        s.run_frozen(1)
+    s.run_taped(1)
+    with pytest.raises(pw.PwError, match="PW_EINVAL"):
+        s.traces(np.array([w.npts], dtype=np.int64))
+    with pytest.raises(pw.PwError, match="PW_EINVAL"):
+        s.backward(np.array([-1], dtype=np.int64), np.zeros((w.N, 1)))
+    with pytest.raises(pw.PwError, match="PW_ESTATE"):
+        s.run_frozen(2)
+    s.set_medium(w.c)
+    with pytest.raises(pw.PwError, match="PW_ESTATE"):
+        s.backward(rec, seed)
+    # a frozen replay makes the tape current again
+    s.run_frozen(1)
+    g = to_np(s.backward(rec, seed))
+    assert np.all(g == 0.0)
+    s.close()

@@ -6,22 +6,15 @@ import numpy as np
 import pytest
 
 import oracle as O
+import workloads as W
 from oracle import adjoint as A
 
 
 def _setup(K=2, tol=1e-6, seed=0):
-    rng = np.random.default_rng(seed)
-    n = 32
-    prob = O.Problem((n, n), 4, 0.25, 4, 8, 2, 4, tol)
-    Y, X = np.meshgrid(np.arange(n) / n, np.arange(n) / n, indexing="ij")
-    c = 1.2 + 0.3 * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y)
-    r2 = (X - 0.5) ** 2 + (Y - 0.3) ** 2
-    a = (np.pi * 4.0) ** 2 * r2
-    u0 = (1 - 2 * a) * np.exp(-a)          # Ricker-shaped pulse
-    p0 = np.zeros((n, n))
-    receivers = (n * 24 + np.arange(0, n, 2)).astype(np.int64)
-    data = 0.01 * rng.standard_normal((prob.N, receivers.size))
-    return prob, c, u0, p0, receivers, data
+    w, receivers, data = W.misfit_case(K=K, tol=tol, seed=seed)
+    prob = O.Problem(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
+                     w.grad_order, w.tol)
+    return prob, w.c, w.u0, w.p0, receivers, data
 
 
 def test_forward_frozen_reproduces_algorithm3():
@@ -75,3 +68,28 @@ def test_gradient_matches_finite_differences(K):
         fd = (J_at(c2 + eps * e) - J_at(c2 - eps * e)) / (2 * eps)
         ad = float(np.sum(g * e))
         assert ad == pytest.approx(fd, rel=2e-6, abs=1e-12 * abs(J)), (t, ad, fd)
+
+
+@pytest.mark.parametrize("shape,ratio,m_fine,m_coarse", [
+    ((64,), 4, 16, 4), ((16, 16, 16), 2, 8, 2)])
+def test_gradient_fd_1d_3d(shape, ratio, m_fine, m_coarse):
+    """The same finite-difference pin on a 1D and a 3D grid (the transposes
+    of the separable interpolation along every axis)."""
+    K = 1
+    w, rec, data = W.misfit_case(shape, ratio=ratio, K=K, m_fine=m_fine,
+                                 m_coarse=m_coarse)
+    prob = O.Problem(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
+                     w.grad_order, w.tol)
+    corr, cc = A.record_correctors(prob, w.c, w.u0, w.p0, K)
+    c2 = w.c * w.c
+    J, g = A.gradient(prob, c2, w.u0, w.p0, K, corr, cc, rec, data)
+    e = np.random.default_rng(5).standard_normal(shape)
+    eps = 1e-5
+
+    def J_at(cc2):
+        u, _ = A.forward_frozen(prob, cc2, w.u0, w.p0, K, corr, cc)
+        return A.misfit(u, rec, data)
+
+    fd = (J_at(c2 + eps * e) - J_at(c2 - eps * e)) / (2 * eps)
+    assert float(np.sum(g * e)) == pytest.approx(fd, rel=2e-6,
+                                                 abs=1e-12 * abs(J))

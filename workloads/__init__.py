@@ -21,6 +21,13 @@ Workloads (fine grid / coarse grid, unit periodic box):
   N = 32, Courant number <= 0.5 with m_F a multiple of 4 (m_F = 76,
   m_C = 19), K = 6, FP32 compensated state, tol 1e-13.
 
+* ``misfit_case`` small receiver-misfit problems in 1D/2D/3D (smooth
+  medium, Ricker-shaped initial pulse, a line of receivers, random data)
+  and ``misfit2d`` the full-size one: 512^2 / 128^2, c = 1 + 2 s with s a
+  min-max normalised Gaussian random field (correlation 0.1, seed 0),
+  Ricker-shaped pulse of peak frequency 10 at (0.5, 0.1), 128 receivers
+  at x = (i + 1/2)/128, y = 0.9 (nearest nodes), T = 1, N = 32, m_F = 96,
+  m_C = 24, K = 4; target medium for the data: the same recipe, seed 1.
 * ``grf2d`` / ``batch2d``  smooth random media c = exp(0.3 g) with random
   Gaussian pulses; ``batch2d`` draws 32 such problems with fine grids from
   {256, 384, 512, 768, 1024}^2 (the batched workload).
@@ -177,5 +184,77 @@ def batch2d(n_problems=32, sizes=(256, 384, 512, 768, 1024), N=32, K=6,
     return out
 
 
+def ricker_pulse(shape, centre, freq):
+    """(1 - 2 a) exp(-a), a = (pi f r)^2, r the periodic distance to
+    `centre` (given in numpy axis order)."""
+    grids = _axes(shape)
+    r2 = np.zeros(shape)
+    for g, x0 in zip(grids, centre):
+        d = (g - x0 + 0.5) % 1.0 - 0.5
+        r2 = r2 + d * d
+    a = (np.pi * freq) ** 2 * r2
+    return (1.0 - 2.0 * a) * np.exp(-a)
+
+
+def misfit_case(shape=(32, 32), ratio=4, N=4, K=2, T=0.25, m_fine=8,
+                m_coarse=2, tol=1e-6, seed=0, dtype="f64"):
+    """A small receiver-misfit problem: c = 1.2 + 0.3 prod_axes
+    sin/cos(2 pi x), Ricker-shaped initial pulse (peak frequency 4) at
+    0.3 along the first numpy axis and 0.5 along the others, receivers
+    every second node along x at 3/4 of every other axis, data
+    0.01 * N(0, 1) of shape (N, n_receivers) (seed).
+    Returns (Workload, receivers (int64 flat fine indices), data)."""
+    shape = tuple(int(n) for n in shape)
+    grids = _axes(shape)
+    prod = np.ones(shape)
+    for i, g in enumerate(grids):
+        prod = prod * (np.sin(2 * np.pi * g) if i % 2 == 0
+                       else np.cos(2 * np.pi * g))
+    c = 1.2 + 0.3 * prod
+    centre = [0.3] + [0.5] * (len(shape) - 1)
+    u0 = ricker_pulse(shape, centre, 4.0)
+    p0 = np.zeros(shape)
+    nx = shape[-1]
+    base = 0
+    stride = 1
+    for ax in range(len(shape) - 1, -1, -1):
+        if ax != len(shape) - 1:
+            base += (3 * shape[ax] // 4) * stride
+        stride *= shape[ax]
+    receivers = (base + np.arange(0, nx, 2)).astype(np.int64)
+    data = 0.01 * np.random.default_rng(seed).standard_normal(
+        (N, receivers.size))
+    w = Workload("misfit_case", shape, ratio, T, N, m_fine, m_coarse, K, tol,
+                 4, dtype, False, c, u0, p0)
+    return w, receivers, data
+
+
+def misfit_medium(shape, seed):
+    """c = 1 + 2 s, s a min-max normalised Gaussian random field of
+    correlation length 0.1 (seed)."""
+    g = smooth_random_field(shape, 0.1, seed)
+    s = (g - g.min()) / (g.max() - g.min())
+    return 1.0 + 2.0 * s
+
+
+def misfit2d(n=512, ratio=4, N=32, K=4, T=1.0, dtype="f32",
+             compensated=True, n_receivers=128):
+    """The full-size receiver-misfit workload (medium seed 0; the data are
+    traces for the target medium misfit_medium(shape, 1)).
+    Returns (Workload, receivers, target medium)."""
+    shape = (n, n)
+    c = misfit_medium(shape, 0)
+    target = misfit_medium(shape, 1)
+    u0 = ricker_pulse(shape, (0.1, 0.5), 10.0)
+    p0 = np.zeros(shape)
+    m_f = _steps_for_courant(3.0, n, T / N)
+    xs = np.floor((np.arange(n_receivers) + 0.5) / n_receivers * n + 0.5)
+    y = int(np.floor(0.9 * n + 0.5))
+    receivers = (y * n + xs.astype(np.int64)).astype(np.int64)
+    w = Workload("misfit2d", shape, ratio, T, N, m_f, m_f // 4, K, 1e-13, 4,
+                 dtype, compensated, c, u0, p0)
+    return w, receivers, target
+
+
 BY_NAME = {"wave1d": wave1d, "disc2d": disc2d, "layers3d": layers3d,
-           "grf2d": grf2d, "batch2d": batch2d}
+           "grf2d": grf2d, "batch2d": batch2d, "misfit2d": misfit2d}
