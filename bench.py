@@ -102,6 +102,74 @@ def batch_measurement(pw, W, torch):
     return out
 
 
+def serial_traces(pw, torch, w, c, receivers):
+    """Receiver traces u_n(x_r), n = 1..N, of the serial fine solution on
+    medium c (the synthetic data of the misfit workload)."""
+    P = pw.Problem.make(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
+                        w.grad_order, w.tol, "f64", False, 1)
+    s = pw.Solver(P)
+    s.set_medium(c)
+    s.set_initial(w.u0, w.p0)
+    u, p = s.state(0)
+    u, p = u[None].contiguous(), p[None].contiguous()
+    rec = torch.as_tensor(receivers, device="cuda")
+    out = []
+    for _ in range(w.N):
+        u, p = s.propagate(u, p)
+        out.append(u.reshape(-1)[rec])
+    d = torch.stack(out).double().contiguous()
+    s.close()
+    return d
+
+
+def adjoint_measurement(pw, W, torch, reps=3):
+    """Gradient of the receiver misfit with respect to c^2 (misfit2d
+    recipe): taped forward (Algorithm 3, FP32 compensated states) + traces
+    + backward (FP64 adjoint, checkpoints every 64 fine steps)."""
+    w, rec, target = W.misfit2d()
+    data = serial_traces(pw, torch, w, target, rec)
+    P = pw.Problem.make(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
+                        w.grad_order, w.tol, w.dtype, w.compensated, w.K)
+    s = pw.Solver(P)
+    s.set_medium(w.c)
+    s.set_initial(w.u0, w.p0)
+    recd = torch.as_tensor(rec, device="cuda")
+
+    def once():
+        s.run_taped(w.K)
+        tr = s.traces(recd)
+        seed = tr - data
+        g = s.backward(recd, seed, wrt="c2", checkpoint_every=64)
+        return 0.5 * float((seed * seed).sum()), g
+
+    J, g = once()  # allocates the tape and the work buffers
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        once()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    tm = s.timings()
+    fwd_upd = w.K * w.N * w.m_fine * w.npts
+    log(f"adjoint: gradient {ms:.1f} ms (taped forward {tm['taped']:.1f}, "
+        f"backward {tm['backward']:.1f})")
+    out = {"workload": "misfit2d: 2D periodic 512^2 / 128^2, c = 1 + 2 s "
+                       "(GRF, seed 0), N=32, m_F=96, m_C=24, K=4, 128 "
+                       "receivers, data from the serial fine solve on the "
+                       "seed-1 medium",
+           "forward_state": "f32 compensated", "adjoint": "f64",
+           "checkpoint_every": 64,
+           "gradient_ms": round(ms, 2),
+           "taped_forward_ms": round(tm["taped"], 2),
+           "backward_ms": round(tm["backward"], 2),
+           "backward_over_forward": round(tm["backward"] / tm["taped"], 3),
+           "fine_updates_forward": fwd_upd,
+           "J": float(f"{J:.6e}"),
+           "grad_norm": float(f"{float(g.norm()):.6e}")}
+    s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +180,10 @@ def main():
                     help="skip the time-to-1e-5 study")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 32-problem batched measurement")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the misfit-gradient measurement")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the misfit-gradient measurement (profiling)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run one fine sweep and one 512 MiB device "
                          "copy (for rocprofv3 --pmc FETCH_SIZE/WRITE_SIZE)")
@@ -129,6 +201,9 @@ def main():
     import workloads as W
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.adjoint_only:
+        print(json.dumps(adjoint_measurement(pw, W, torch)), flush=True)
+        return
     w = W.disc2d()
     K = w.K
     P = pw.Problem.make(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
@@ -240,6 +315,8 @@ def main():
     del u, p
     torch.cuda.empty_cache()
     batched = None if args.no_batch else batch_measurement(pw, W, torch)
+    torch.cuda.empty_cache()
+    adjoint = None if args.no_adjoint else adjoint_measurement(pw, W, torch)
 
     cpu = None if args.no_cpu else cpu_baseline(w)
 
@@ -276,6 +353,7 @@ def main():
         "rank": ranks,
         "time_to_1e-5": ttt,
         "batched": batched,
+        "adjoint": adjoint,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

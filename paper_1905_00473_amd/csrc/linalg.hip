@@ -365,6 +365,241 @@ __global__ __launch_bounds__(256) void k_jacobi_round(int n, int np, int round, 
   if (lane == 0) atomicAdd(counter, 1);
 }
 
+// Block one-sided Jacobi: columns are grouped in blocks of kJB; one launch
+// is one round of the round-robin over blocks and one workgroup handles one
+// block pair (16 columns).  The workgroup forms the 16 x 16 Gram matrix of
+// its columns on the matrix cores, runs one cyclic sweep of two-sided
+// rotations on it (the rotation of every pair from the current Gram
+// entries, with the same relative threshold and noise rule as the column
+// version), and applies the accumulated 16 x 16 rotation to the 16 columns
+// of H and V.
+constexpr int kJB = 8;
+constexpr int kJC = 2 * kJB;
+
+__device__ __forceinline__ void pair_rotation(const double* G, int i, int partner, bool valid,
+                                              double thr, double noise2, double* a, double* b,
+                                              bool* rot) {
+  *a = 1.0;
+  *b = 0.0;
+  *rot = false;
+  if (!valid) return;
+  const int p = min(i, partner), q = max(i, partner);
+  const double al = G[p * kJC + p], be = G[q * kJC + q], ga = G[p * kJC + q];
+  if (ga == 0.0 || fabs(ga) <= thr * sqrt(al * be)) return;
+  if (fmin(al, be) < noise2) return;
+  const double zeta = (be - al) / (2.0 * ga);
+  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double c = 1.0 / sqrt(1.0 + t * t);
+  const double s = c * t;
+  // column p <- c p - s q ; column q <- s p + c q
+  *a = c;
+  *b = (i == p) ? -s : s;
+  *rot = true;
+}
+
+// rows of one staged block column (the block path takes n <= kJRows)
+constexpr int kJRows = 1024;
+constexpr int kJLd = kJRows + 1;  // odd stride: the 16 columns fall in distinct LDS banks
+
+__global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round, double* H,
+                                                      double* V, int* counter,
+                                                      const double* fro2) {
+  constexpr int RPT = kJRows / 256;  // staged rows per thread and column
+  constexpr int VT = 8;              // V tiles per wave prefetched at the start
+  __shared__ double Hs[kJC * kJLd];
+  __shared__ double Gp[4][kJC * kJC];
+  __shared__ double G[2][kJC * kJC];
+  __shared__ double W[2][kJC * kJC];
+  __shared__ double ca[kJC], cb[kJC];
+  __shared__ signed char part[kJC - 1][kJC];
+  __shared__ int nrot;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  int bp = rr_index(blockIdx.x, round, npb);
+  int bq = rr_index(npb - 1 - blockIdx.x, round, npb);
+  if (bp > bq) {
+    const int t = bp;
+    bp = bq;
+    bq = t;
+  }
+  const int nb = (n + kJB - 1) / kJB;
+  if (bq >= nb) return;  // paired with the padding block
+  auto gcol = [&](int c) { return c < kJB ? bp * kJB + c : bq * kJB + (c - kJB); };
+  // V operands of the first VT row tiles of this wave (see step 3), loaded
+  // now so that their latency overlaps steps 1 and 2
+  double va[VT][4];
+#pragma unroll
+  for (int u = 0; u < VT; ++u) {
+    const int ra = 16 * (wave + 4 * u) + (lane & 15);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int gk = gcol(4 * t + (lane >> 4));
+      va[u][t] = (ra < n && gk < n) ? V[(long long)gk * n + ra] : 0.0;
+    }
+  }
+  // stage the 16 columns of H (all loads of a thread in flight together);
+  // padding columns beyond n are zero
+  {
+    double v[kJC][RPT];
+#pragma unroll
+    for (int c = 0; c < kJC; ++c) {
+      const int gc = gcol(c);
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const int row = tid + 256 * r;
+        v[c][r] = (gc < n && row < n) ? H[(long long)gc * n + row] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kJC; ++c)
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const int row = tid + 256 * r;
+        if (row < n) Hs[c * kJLd + row] = v[c][r];
+      }
+  }
+  // round-robin partners of the inner sweep
+  if (tid < (kJC - 1) * (kJC / 2)) {
+    const int r = tid / (kJC / 2), g = tid % (kJC / 2);
+    const int a = rr_index(g, r, kJC), b = rr_index(kJC - 1 - g, r, kJC);
+    part[r][a] = (signed char)b;
+    part[r][b] = (signed char)a;
+  }
+  if (tid == 0) nrot = 0;
+  __syncthreads();
+  // 1. Gram matrix D = B^T B of the staged block B (n x 16) on the matrix
+  //    cores, rows split over the 4 waves.  Operand lane l: A[l%16][l/16] =
+  //    B^T[l%16][k0 + l/16] = B[k0 + l/16][l%16], the same value for both.
+  {
+    v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+    const double* col = Hs + (lane & 15) * kJLd + (lane >> 4);
+    for (int k0 = 4 * wave; k0 < n; k0 += 16) {
+      const double x = (k0 + (lane >> 4) < n) ? col[k0] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, acc, 0, 0, 0);
+    }
+    for (int v = 0; v < 4; ++v) Gp[wave][(4 * v + (lane >> 4)) * kJC + (lane & 15)] = acc[v];
+  }
+  __syncthreads();
+  const int i = tid / kJC, j = tid % kJC;  // this thread's Gram / rotation entry
+  G[0][tid] = Gp[0][tid] + Gp[1][tid] + Gp[2][tid] + Gp[3][tid];
+  W[0][tid] = (i == j) ? 1.0 : 0.0;
+  __syncthreads();
+  // 2. one cyclic sweep of rotations on the Gram matrix; the rotation of
+  //    each pair is formed once (threads 0..7) and read by all
+  const double noise2 = 4.9e-32 * (*fro2);
+  const double thr2 = 4.5e-16 * 4.5e-16 * (double)n;
+  int cur = 0;
+  for (int r = 0; r < kJC - 1; ++r) {
+    const double* Gc = G[cur];
+    if (tid < kJC / 2) {
+      int p = rr_index(tid, r, kJC), q = rr_index(kJC - 1 - tid, r, kJC);
+      if (p > q) {
+        const int t = p;
+        p = q;
+        q = t;
+      }
+      double c = 1.0, sn = 0.0;
+      bool rot = false;
+      if (gcol(q) < n) {
+        const double al = Gc[p * kJC + p], be = Gc[q * kJC + q], ga = Gc[p * kJC + q];
+        if (ga != 0.0 && ga * ga > thr2 * (al * be) && fmin(al, be) >= noise2) {
+          // tan of the angle: t = sgn(d) g / (|d| + sqrt(d^2 + g^2)), d = be - al,
+          // g = 2 ga (the smaller root of t^2 + 2 zeta t - 1 = 0, zeta = d / g);
+          // the hardware reciprocal square root and reciprocal seeds are
+          // refined by Newton steps to full double precision
+          const double d = be - al, g = 2.0 * ga;
+          const double x = fma(d, d, g * g);
+          double y = __builtin_amdgcn_rsq(x);
+          y = y * fma(-0.5 * x * y, y, 1.5);
+          y = y * fma(-0.5 * x * y, y, 1.5);
+          const double m = fabs(d) + x * y;  // |d| + sqrt(d^2 + g^2)
+          double z = __builtin_amdgcn_rcp(m);
+          z = z * fma(-m, z, 2.0);
+          z = z * fma(-m, z, 2.0);
+          const double t = (d >= 0.0 ? g : -g) * z;
+          const double u = fma(t, t, 1.0);
+          double w = __builtin_amdgcn_rsq(u);
+          w = w * fma(-0.5 * u * w, w, 1.5);
+          w = w * fma(-0.5 * u * w, w, 1.5);
+          c = w;
+          sn = w * t;
+          rot = true;
+        }
+      }
+      // column p <- c p - s q ; column q <- s p + c q
+      ca[p] = c;
+      cb[p] = -sn;
+      ca[q] = c;
+      cb[q] = sn;
+      if (rot) atomicAdd(&nrot, 1);
+    }
+    __syncthreads();
+    const int pi = part[r][i], pj = part[r][j];
+    const double ai = ca[i], bi = cb[i], aj = ca[j], bj = cb[j];
+    // G' = J^T G J entrywise, W' = W J
+    const double gn = ai * aj * Gc[i * kJC + j] + ai * bj * Gc[i * kJC + pj] +
+                      bi * aj * Gc[pi * kJC + j] + bi * bj * Gc[pi * kJC + pj];
+    const double* Wc = W[cur];
+    const double wn = aj * Wc[i * kJC + j] + bj * Wc[i * kJC + pj];
+    G[cur ^ 1][tid] = gn;
+    W[cur ^ 1][tid] = wn;
+    cur ^= 1;
+    __syncthreads();
+  }
+  if (nrot == 0) return;
+  // 3. H(:, cols) <- B W (B staged), V(:, cols) <- V(:, cols) W, in 16-row
+  //    tiles on the matrix cores: A[i][k] = X[tile + i][4t + k] (lane l:
+  //    i = l%16, k = l/16), B[k][c] = W[4t + k][c] (held in four registers),
+  //    D[4v + l/16][l%16] = (X W)[tile + 4v + l/16][l%16].
+  const double* Wf = W[cur];
+  double bw[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) bw[t] = Wf[(4 * t + (lane >> 4)) * kJC + (lane & 15)];
+  const int gout = gcol(lane & 15);
+  auto store = [&](double* X, int tile, const v4d& acc) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = tile + 4 * v + (lane >> 4);
+      if (row < n && gout < n) X[(long long)gout * n + row] = acc[v];
+    }
+  };
+  for (int tile = 16 * wave; tile < n; tile += 64) {
+    const int ra = tile + (lane & 15);
+    v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int k = 4 * t + (lane >> 4);
+      const double a = (ra < n) ? Hs[k * kJLd + ra] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bw[t], acc, 0, 0, 0);
+    }
+    store(H, tile, acc);
+  }
+#pragma unroll
+  for (int u = 0; u < VT; ++u) {
+    const int tile = 16 * (wave + 4 * u);
+    if (tile < n) {
+      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va[u][t], bw[t], acc, 0, 0, 0);
+      store(V, tile, acc);
+    }
+  }
+  for (int tile = 16 * (wave + 4 * VT); tile < n; tile += 64) {
+    const int ra = tile + (lane & 15);
+    double a[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int gk = gcol(4 * t + (lane >> 4));
+      a[t] = (ra < n && gk < n) ? V[(long long)gk * n + ra] : 0.0;
+    }
+    v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], bw[t], acc, 0, 0, 0);
+    store(V, tile, acc);
+  }
+  if (tid == 0) atomicAdd(counter, nrot);
+}
+
 __global__ void k_col_norms(int n, const double* H, double* sig) {
   const int lane = threadIdx.x & 63;
   const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -599,6 +834,17 @@ void svd_jacobi(int n, const double* H, double* X, double* Y, double* sig, doubl
     return;
   }
   const long long nn = (long long)n * n;
+  if (const char* dump = getenv("PW_DUMP_H")) {
+    // debugging aid: append (n, H column-major) to the named file
+    std::vector<double> h((size_t)nn);
+    PW_HIP(hipMemcpyAsync(h.data(), H, sizeof(double) * nn, hipMemcpyDeviceToHost, st));
+    PW_HIP(hipStreamSynchronize(st));
+    if (FILE* f = fopen(dump, "ab")) {
+      fwrite(&n, sizeof(int), 1, f);
+      fwrite(h.data(), sizeof(double), (size_t)nn, f);
+      fclose(f);
+    }
+  }
   PW_HIP(hipMemcpyAsync(Hw, H, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
   hipLaunchKernelGGL(k_identity, dim3(nblocks(nn)), dim3(kTB), 0, st, n, Vw);
   PW_LAUNCH_CHECK();
@@ -608,11 +854,23 @@ void svd_jacobi(int n, const double* H, double* X, double* Y, double* sig, doubl
   const unsigned blocks = (unsigned)((np / 2 + 3) / 4);
   double* fro2 = Hw + nn + 2 * n + 8;  // scratch slot after the sort workspace
   frob_norm2(Hw, n, n, n, sig, fro2, st);  // sig used as partials (>= 512 doubles)
+  // block version from two block pairs up (columns in blocks of kJB)
+  const int nb = (n + kJB - 1) / kJB;
+  const int npb = nb + (nb & 1);
+  const bool blocked = n >= 2 * kJC && n <= kJRows && !getenv("PW_JACOBI_COLUMNS");
   for (int sw = 0; sw < maxsweeps; ++sw) {
-    for (int round = 0; round < np - 1; ++round) {
-      hipLaunchKernelGGL(k_jacobi_round, dim3(blocks), dim3(256), 0, st, n, np, round, Hw, Vw,
-                         counters + sw, (const double*)fro2);
-      PW_LAUNCH_CHECK();
+    if (blocked) {
+      for (int round = 0; round < npb - 1; ++round) {
+        hipLaunchKernelGGL(k_jacobi_block, dim3(npb / 2), dim3(256), 0, st, n, npb, round, Hw, Vw,
+                           counters + sw, (const double*)fro2);
+        PW_LAUNCH_CHECK();
+      }
+    } else {
+      for (int round = 0; round < np - 1; ++round) {
+        hipLaunchKernelGGL(k_jacobi_round, dim3(blocks), dim3(256), 0, st, n, np, round, Hw, Vw,
+                           counters + sw, (const double*)fro2);
+        PW_LAUNCH_CHECK();
+      }
     }
     int h = 0;
     PW_HIP(hipMemcpyAsync(&h, counters + sw, sizeof(int), hipMemcpyDeviceToHost, st));

@@ -194,3 +194,34 @@ def test_backward_call_order_and_argument_errors():
     g = to_np(s.backward(rec, seed))
     assert np.all(g == 0.0)
     s.close()
+
+
+def test_full_size_gradient_directional_fd():
+    """At the full misfit workload size (512^2, N = 32, m_F = 96, 128
+    receivers; FP64 states, K = 2, checkpoints every 64 steps) the oracle
+    cannot run; the property checked is <grad, e> = central difference of J
+    through the GPU's frozen forward, for a smooth random direction e."""
+    K = 2
+    w, rec, _ = W.misfit2d(K=K, dtype="f64", compensated=False)
+    print(f"full-size adjoint {w.shape} N={w.N} m_F={w.m_fine}", flush=True)
+    data = 0.01 * np.random.default_rng(3).standard_normal((w.N, rec.size))
+    s, _ = _solver(w, K)
+    s.run_taped(K)
+    seed = to_np(s.traces(rec)) - data
+    J0 = 0.5 * float(np.sum(seed * seed))
+    g = to_np(s.backward(rec, seed, wrt="c2", checkpoint_every=64))
+    assert np.all(np.isfinite(g)) and np.abs(g).max() > 0
+    e = W.smooth_random_field(w.shape, 0.05, 7)
+    c2 = w.c * w.c
+    eps = 1e-4
+
+    def J_at(x):
+        s.set_medium(np.sqrt(x))
+        s.run_frozen(K)
+        d = to_np(s.traces(rec)) - data
+        return 0.5 * float(np.sum(d * d))
+
+    fd = (J_at(c2 + eps * e) - J_at(c2 - eps * e)) / (2 * eps)
+    ad = float(np.sum(g * e))
+    assert ad == pytest.approx(fd, rel=1e-5, abs=1e-12 * J0), (ad, fd)
+    s.close()
