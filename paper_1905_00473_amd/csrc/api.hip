@@ -397,10 +397,9 @@ void setup(Prob& pr, const pw_problem& P) {
   pr.red = m.get_n<double>(4096);
   pr.res = m.get_n<double>(2LL * (P.max_iters + 1));
   pr.os.gram = m.get_n<double>((long long)N * N);
-  pr.os.W = m.get_n<double>((long long)N * N);
-  pr.os.lam = m.get_n<double>(N);
   pr.os.T = m.get_n<double>((long long)N * N);
   pr.os.R1 = m.get_n<double>((long long)N * N);
+  pr.os.R2 = m.get_n<double>((long long)N * N);
   pr.os.Q1 = m.get_n<double>(rows * N);
   pr.os.work = pr.gwork;
   pr.os.work_elems = pr.gwork_elems;

@@ -185,123 +185,113 @@ __global__ void k_gemm_small(int m, int n, int k, double alpha, const double* A,
 // cyclic Jacobi eigen-decomposition of a symmetric n x n matrix (n <= 64)
 // in one workgroup; round-robin ordering, n/2 disjoint rotations per round
 // ---------------------------------------------------------------------------
-constexpr int kEigMax = 64;
+constexpr int kCholMax = 64;
 
 __device__ __forceinline__ int rr_index(int j, int round, int np) {
   return j == 0 ? 0 : ((j - 1 + round) % (np - 1)) + 1;
 }
 
-__global__ __launch_bounds__(1024) void k_sym_eig(int n, double* Ag, int lda, double* Wg,
-                                                  double* lam) {
-  __shared__ double A[kEigMax][kEigMax + 1];
-  __shared__ double W[kEigMax][kEigMax + 1];
-  __shared__ double cs[kEigMax / 2][2];
-  __shared__ int pq[kEigMax / 2][2];
-  __shared__ int nrot;
+// Truncated pivoted Cholesky of the Gram matrix G = A^T A (n x n, n <= 64)
+// in one workgroup, and the two factors of the orthonormalisation
+// Q = A T, A ~ Q R:  with P G P^T = L L^T truncated at rank k (the pivot
+// steps stop when the largest remaining diagonal entry is <= rel times the
+// largest diagonal of G, or <= abs_thr), R = L^T P^T (rows k.. zero) and
+// T = P [L_11^{-T}; 0] (columns k.. zero).  T and R are column-major n x n.
+__global__ __launch_bounds__(1024) void k_pchol_factors(int n, const double* Gg, double rel,
+                                                        double abs_thr, double* T, double* R) {
+  __shared__ double A[kCholMax][kCholMax + 1];   // trailing Gram matrix
+  __shared__ double Rm[kCholMax][kCholMax + 1];  // rows of L^T, pivoted column order
+  __shared__ double X[kCholMax][kCholMax + 1];   // inverse of the leading k x k block
+  __shared__ int perm[kCholMax];
+  __shared__ int piv_s, stop_s;
+  __shared__ double d0_s;
   const int tid = threadIdx.x;
-  const int np = (n + 1) & ~1;
-  for (int t = tid; t < np * np; t += blockDim.x) {
-    const int i = t % np, j = t / np;
-    A[i][j] = (i < n && j < n) ? Ag[i + (long long)j * lda] : 0.0;
-    W[i][j] = (i == j) ? 1.0 : 0.0;
+  const int lane = tid & 63, x = tid & 63, y = tid >> 6;
+  for (int m = 0; m < 4; ++m) {
+    const int k = y + 16 * m;
+    A[x][k] = (x < n && k < n) ? Gg[x + (long long)k * n] : 0.0;
+    Rm[x][k] = 0.0;
+    X[x][k] = 0.0;
   }
-  __shared__ double noise;
-  if (tid == 0) {
-    double tr = 0.0;
-    for (int i = 0; i < n; ++i) tr += fabs(A[i][i]);
-    noise = 2.3e-16 * tr;  // eigenvalues below this are rounding noise
-  }
+  if (tid < kCholMax) perm[tid] = tid;
   __syncthreads();
-  const int npairs = np / 2;
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    if (tid == 0) nrot = 0;
+  int rank = n;
+  for (int j = 0; j < n; ++j) {
+    if (tid < 64) {
+      // pivot: largest remaining diagonal entry (lowest index on ties)
+      double v = (lane >= j && lane < n) ? A[lane][lane] : -1.0;
+      int idx = lane;
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(v, off, 64);
+        const int oi = __shfl_xor(idx, off, 64);
+        if (ov > v || (ov == v && oi < idx)) {
+          v = ov;
+          idx = oi;
+        }
+      }
+      if (lane == 0) {
+        if (j == 0) d0_s = v;
+        const double d0 = j == 0 ? v : d0_s;
+        piv_s = idx;
+        stop_s = (!(v > rel * d0) || !(v > abs_thr)) ? 1 : 0;
+      }
+    }
     __syncthreads();
-    for (int round = 0; round < np - 1; ++round) {
-      if (tid < npairs) {
-        int p = rr_index(tid, round, np);
-        int q = rr_index(np - 1 - tid, round, np);
-        if (p > q) {
-          const int tmp = p;
-          p = q;
-          q = tmp;
-        }
-        double c = 1.0, s = 0.0;
-        const double apq = A[p][q];
-        const double app = A[p][p], aqq = A[q][q];
-        // rotate only above the rounding noise of the entries (~ n eps)
-        if (p < n && q < n && apq != 0.0 &&
-            fabs(apq) > 2.3e-16 * n * sqrt(fabs(app) * fabs(aqq)) &&
-            (fabs(app) > noise || fabs(aqq) > noise)) {
-          const double tau = (aqq - app) / (2.0 * apq);
-          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + t * t);
-          s = t * c;
-          atomicAdd(&nrot, 1);
-        }
-        cs[tid][0] = c;
-        cs[tid][1] = s;
-        pq[tid][0] = p;
-        pq[tid][1] = q;
+    if (stop_s) {
+      rank = j;
+      break;
+    }
+    const int pv = piv_s;
+    if (pv != j) {
+      if (tid < n) {
+        const double t = A[j][tid];
+        A[j][tid] = A[pv][tid];
+        A[pv][tid] = t;
       }
       __syncthreads();
-      // columns: A <- A J, W <- W J
-      for (int t = tid; t < npairs * np; t += blockDim.x) {
-        const int k = t / np, r = t % np;
-        const double c = cs[k][0], s = cs[k][1];
-        if (s != 0.0) {
-          const int p = pq[k][0], q = pq[k][1];
-          const double ap = A[r][p], aq = A[r][q];
-          A[r][p] = c * ap - s * aq;
-          A[r][q] = s * ap + c * aq;
-          const double wp = W[r][p], wq = W[r][q];
-          W[r][p] = c * wp - s * wq;
-          W[r][q] = s * wp + c * wq;
-        }
+      if (tid < n) {
+        const double t = A[tid][j];
+        A[tid][j] = A[tid][pv];
+        A[tid][pv] = t;
       }
-      __syncthreads();
-      // rows: A <- J^T A
-      for (int t = tid; t < npairs * np; t += blockDim.x) {
-        const int k = t / np, r = t % np;
-        const double c = cs[k][0], s = cs[k][1];
-        if (s != 0.0) {
-          const int p = pq[k][0], q = pq[k][1];
-          const double ap = A[p][r], aq = A[q][r];
-          A[p][r] = c * ap - s * aq;
-          A[q][r] = s * ap + c * aq;
-        }
+      if (tid < j) {
+        const double t = Rm[tid][j];
+        Rm[tid][j] = Rm[tid][pv];
+        Rm[tid][pv] = t;
+      }
+      if (tid == 0) {
+        const int t = perm[j];
+        perm[j] = perm[pv];
+        perm[pv] = t;
       }
       __syncthreads();
     }
-    if (nrot == 0) break;
+    const double r = sqrt(A[j][j]);
+    if (tid >= j && tid < n) Rm[j][tid] = (tid == j) ? r : A[j][tid] / r;
+    __syncthreads();
+    for (int m = 0; m < 4; ++m) {
+      const int k = y + 16 * m;
+      if (x > j && x < n && k > j && k < n) A[x][k] -= Rm[j][x] * Rm[j][k];
+    }
     __syncthreads();
   }
-  for (int t = tid; t < n * n; t += blockDim.x) {
-    const int i = t % n, j = t / n;
-    Wg[i + (long long)j * n] = W[i][j];
-  }
-  for (int i = tid; i < n; i += blockDim.x) lam[i] = A[i][i];
-}
-
-// T = W diag(kappa) with kappa_i = 1/sqrt(lam_i) for kept directions and
-// R = diag(sqrt(lam_i)) W^T (rows of dropped directions zero); a direction
-// is kept when lam_i > thr * max(lam) (rel) and lam_i > abs_thr.
-__global__ void k_orth_factors(int n, const double* W, const double* lam, double rel,
-                               double abs_thr, double* T, double* R) {
-  __shared__ double lmax;
-  if (threadIdx.x == 0) {
-    double m = 0.0;
-    for (int i = 0; i < n; ++i) m = fmax(m, lam[i]);
-    lmax = m;
+  // X = (leading rank x rank block of L^T)^{-1}, one column per thread
+  if (tid < rank) {
+    const int b = tid;
+    X[b][b] = 1.0 / Rm[b][b];
+    for (int a = b - 1; a >= 0; --a) {
+      double s = 0.0;
+      for (int c = a + 1; c <= b; ++c) s += Rm[a][c] * X[c][b];
+      X[a][b] = -s / Rm[a][a];
+    }
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
-    const int i = t % n, j = t / n;  // element (i, j)
-    const double lj = lam[j];
-    const bool keepj = lj > rel * lmax && lj > abs_thr;
-    T[i + j * n] = keepj ? W[i + j * n] / sqrt(lj) : 0.0;
-    const double li = lam[i];
-    const bool keepi = li > rel * lmax && li > abs_thr;
-    R[i + j * n] = keepi ? sqrt(li) * W[j + i * n] : 0.0;
+  for (int m = 0; m < 4; ++m) {
+    const int b = y + 16 * m, a = x;
+    if (a < n && b < n) {
+      T[perm[a] + (long long)b * n] = (a < rank && b < rank) ? X[a][b] : 0.0;
+      R[a + (long long)perm[b] * n] = (a < rank) ? Rm[a][b] : 0.0;
+    }
   }
 }
 
@@ -450,12 +440,13 @@ __global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round,
         v[c][r] = (gc < n && row < n) ? H[(long long)gc * n + row] : 0.0;
       }
     }
+    const int n64 = (n + 63) & ~63;
 #pragma unroll
     for (int c = 0; c < kJC; ++c)
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
         const int row = tid + 256 * r;
-        if (row < n) Hs[c * kJLd + row] = v[c][r];
+        if (row < n64) Hs[c * kJLd + row] = v[c][r];
       }
   }
   // round-robin partners of the inner sweep
@@ -471,23 +462,36 @@ __global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round,
   //    cores, rows split over the 4 waves.  Operand lane l: A[l%16][l/16] =
   //    B^T[l%16][k0 + l/16] = B[k0 + l/16][l%16], the same value for both.
   {
-    v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+    // rows beyond n are zero in the staged block up to the next multiple
+    // of 64 (cleared above), so full groups of four steps need no test
+    v4d acc0 = v4d{0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
     const double* col = Hs + (lane & 15) * kJLd + (lane >> 4);
-    for (int k0 = 4 * wave; k0 < n; k0 += 16) {
-      const double x = (k0 + (lane >> 4) < n) ? col[k0] : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, acc, 0, 0, 0);
+    for (int k0 = 4 * wave; k0 < n; k0 += 64) {
+      const double x0 = col[k0], x1 = col[k0 + 16], x2 = col[k0 + 32], x3 = col[k0 + 48];
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, x0, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, x1, acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x2, x2, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x3, x3, acc1, 0, 0, 0);
     }
-    for (int v = 0; v < 4; ++v) Gp[wave][(4 * v + (lane >> 4)) * kJC + (lane & 15)] = acc[v];
+    for (int v = 0; v < 4; ++v)
+      Gp[wave][(4 * v + (lane >> 4)) * kJC + (lane & 15)] = acc0[v] + acc1[v];
   }
   __syncthreads();
-  const int i = tid / kJC, j = tid % kJC;  // this thread's Gram / rotation entry
   G[0][tid] = Gp[0][tid] + Gp[1][tid] + Gp[2][tid] + Gp[3][tid];
-  W[0][tid] = (i == j) ? 1.0 : 0.0;
+  W[0][tid] = (tid / kJC == tid % kJC) ? 1.0 : 0.0;
   __syncthreads();
   // 2. one cyclic sweep of rotations on the Gram matrix; the rotation of
-  //    each pair is formed once (threads 0..7) and read by all
+  //    each pair is formed once (threads 0..7) and read by all.  The
+  //    partners of this thread's row and column index in the 15 rounds are
+  //    packed four bits each into one register.
   const double noise2 = 4.9e-32 * (*fro2);
   const double thr2 = 4.5e-16 * 4.5e-16 * (double)n;
+  const int i = tid / kJC, j = tid % kJC;  // this thread's Gram / rotation entry
+  unsigned long long packi = 0, packj = 0;
+  for (int r = 0; r < kJC - 1; ++r) {
+    packi |= (unsigned long long)part[r][i] << (4 * r);
+    packj |= (unsigned long long)part[r][j] << (4 * r);
+  }
   int cur = 0;
   for (int r = 0; r < kJC - 1; ++r) {
     const double* Gc = G[cur];
@@ -534,15 +538,14 @@ __global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round,
       if (rot) atomicAdd(&nrot, 1);
     }
     __syncthreads();
-    const int pi = part[r][i], pj = part[r][j];
+    const int pi = (int)((packi >> (4 * r)) & 15), pj = (int)((packj >> (4 * r)) & 15);
+    const double* Wc = W[cur];
+    const double g0 = Gc[i * kJC + j], g1 = Gc[i * kJC + pj], g2 = Gc[pi * kJC + j],
+                 g3 = Gc[pi * kJC + pj], w0 = Wc[i * kJC + j], w1 = Wc[i * kJC + pj];
     const double ai = ca[i], bi = cb[i], aj = ca[j], bj = cb[j];
     // G' = J^T G J entrywise, W' = W J
-    const double gn = ai * aj * Gc[i * kJC + j] + ai * bj * Gc[i * kJC + pj] +
-                      bi * aj * Gc[pi * kJC + j] + bi * bj * Gc[pi * kJC + pj];
-    const double* Wc = W[cur];
-    const double wn = aj * Wc[i * kJC + j] + bj * Wc[i * kJC + pj];
-    G[cur ^ 1][tid] = gn;
-    W[cur ^ 1][tid] = wn;
+    G[cur ^ 1][tid] = ai * aj * g0 + ai * bj * g1 + bi * aj * g2 + bi * bj * g3;
+    W[cur ^ 1][tid] = aj * w0 + bj * w1;
     cur ^= 1;
     __syncthreads();
   }
@@ -800,31 +803,26 @@ void gemm_small(int m, int n, int k, double alpha, const double* A, int lda, boo
   PW_LAUNCH_CHECK();
 }
 
-void sym_eig(int n, double* A, int lda, double* W, double* lam, hipStream_t st) {
-  if (n > kEigMax) fail(PW_EINVAL, "Gram eigen-solver supports at most 64 columns per block");
+void pchol_factors(int n, const double* G, double rel, double abs_thr, double* T, double* R,
+                   hipStream_t st) {
+  if (n > kCholMax) fail(PW_EINVAL, "the orthonormalisation supports at most 64 columns");
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_sym_eig, dim3(1), dim3(1024), 0, st, n, A, lda, W, lam);
+  hipLaunchKernelGGL(k_pchol_factors, dim3(1), dim3(1024), 0, st, n, G, rel, abs_thr, T, R);
   PW_LAUNCH_CHECK();
 }
 
 void orth(long long rows, int n, const double* A, long long lda, double* Q, long long ldq,
           double* R, OrthScratch s, hipStream_t st) {
-  // pass 1: Gram eigenvectors of A
+  // pass 1: truncated pivoted Cholesky QR of A
   gemm_tn(rows, n, n, 1.0, A, lda, A, lda, 0.0, s.gram, n, s.work, s.work_elems, st);
-  sym_eig(n, s.gram, n, s.W, s.lam, st);
-  hipLaunchKernelGGL(k_orth_factors, dim3(1), dim3(kTB), 0, st, n, (const double*)s.W,
-                     (const double*)s.lam, 1e-13, 1e-290, s.T, s.R1);
-  PW_LAUNCH_CHECK();
+  pchol_factors(n, s.gram, 1e-13, 1e-290, s.T, s.R1, st);
   gemm_nn(rows, n, n, 1.0, A, lda, s.T, n, 0.0, s.Q1, rows, st);
-  // pass 2: re-orthonormalise Q1 (its Gram is the identity up to rounding)
+  // pass 2: the same on Q1 (its Gram is the identity up to rounding on the
+  // kept columns, zero on the dropped ones)
   gemm_tn(rows, n, n, 1.0, s.Q1, rows, s.Q1, rows, 0.0, s.gram, n, s.work, s.work_elems, st);
-  sym_eig(n, s.gram, n, s.W, s.lam, st);
-  double* R2 = s.gram;  // gram is consumed by sym_eig; reuse as R2
-  hipLaunchKernelGGL(k_orth_factors, dim3(1), dim3(kTB), 0, st, n, (const double*)s.W,
-                     (const double*)s.lam, 0.0, 0.25, s.T, R2);
-  PW_LAUNCH_CHECK();
+  pchol_factors(n, s.gram, 0.0, 0.25, s.T, s.R2, st);
   gemm_nn(rows, n, n, 1.0, s.Q1, rows, s.T, n, 0.0, Q, ldq, st);
-  gemm_small(n, n, n, 1.0, R2, n, false, s.R1, n, false, 0.0, R, n, st);
+  gemm_small(n, n, n, 1.0, s.R2, n, false, s.R1, n, false, 0.0, R, n, st);
 }
 
 void svd_jacobi(int n, const double* H, double* X, double* Y, double* sig, double tol,

@@ -221,20 +221,15 @@ void gemm_small(int m, int n, int k, double alpha, const double* A, int lda, boo
                 const double* B, int ldb, bool tb, double beta, double* C, int ldc,
                 hipStream_t stream);
 
-// symmetric eigen-decomposition of n x n (n <= 128) A (in place destroyed):
-// W (n x n, column eigenvectors), lam (n), cyclic Jacobi in one workgroup.
-void sym_eig(int n, double* A, int lda, double* W, double* lam, hipStream_t stream);
-
-// Orthonormalisation for truncated QR (two passes of the eigenvector
-// orthonormalisation of the Gram matrix): A (rows x n) = Q R approximately;
-// Q (rows x n, ldq), R (n x n). Directions whose Gram eigenvalue is below
-// rel_tol * max are dropped (zero Q column, zero R row).
+// Orthonormalisation for the truncated QR of Algorithm 1 (two passes of
+// pivoted Cholesky QR): A (rows x n, n <= 64) = Q R approximately; Q (rows x
+// n, ldq), R (n x n).  Directions whose pivot is below 1e-13 times the
+// largest diagonal of A^T A are dropped (zero Q column, zero R row).
 struct OrthScratch {
   double* gram = nullptr;   // n*n
-  double* W = nullptr;      // n*n
-  double* lam = nullptr;    // n
   double* T = nullptr;      // n*n
   double* R1 = nullptr;     // n*n
+  double* R2 = nullptr;     // n*n
   double* Q1 = nullptr;     // rows*n
   double* work = nullptr;   // gemm_tn work
   size_t work_elems = 0;
