@@ -166,6 +166,90 @@ __global__ __launch_bounds__(256) void k_gemm_nn(long long rows, int n, int k, d
       }
 }
 
+// Large C = alpha A B + beta C (A: rows x k, B: k x n, column-major):
+// 128 x 128 tiles, 4 waves of 64 x 64.  The MFMA computes tiles of C^T
+// (operand a from B, operand b from A) so that in the result layout
+// D[4v + l/16][l%16] the lane index l%16 runs along the rows of C and each
+// group of 16 lanes stores 128 contiguous bytes.  The next k-step's global
+// loads are issued before the current step's MFMAs (two LDS buffers).
+constexpr int GBM = 128, GBN = 128, GBK = 16, GPAD = 4;
+
+__global__ __launch_bounds__(256) void k_gemm_nn_big(long long rows, int n, int k, double alpha,
+                                                      const double* A, long long lda,
+                                                      const double* B, long long ldb, double beta,
+                                                      double* C, long long ldc) {
+  __shared__ double As[2][GBK][GBM + GPAD];
+  __shared__ double Bs[2][GBK][GBN + GPAD];
+  const long long m0 = (long long)blockIdx.x * GBM;
+  const int n0 = blockIdx.y * GBN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+  v4d acc[4][4];  // [n sub-tile][m sub-tile]
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+  // loader coordinates: A tile 128 x 16 (8 per thread), B tile 16 x 128
+  const int am = tid & 127, ak = tid >> 7;  // k = ak + 2 q
+  const int bk = tid & 15, bn = tid >> 4;   // n = bn + 16 q
+  double ra[8], rb[8];
+  auto load = [&](int k0) {
+    const long long r = m0 + am;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int kk = k0 + ak + 2 * q;
+      ra[q] = (r < rows && kk < k) ? A[r + (long long)kk * lda] : 0.0;
+      const int nn = n0 + bn + 16 * q;
+      rb[q] = (k0 + bk < k && nn < n) ? B[(k0 + bk) + (long long)nn * ldb] : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      As[buf][ak + 2 * q][am] = ra[q];
+      Bs[buf][bk][bn + 16 * q] = rb[q];
+    }
+  };
+  load(0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < k; k0 += GBK) {
+    const bool more = k0 + GBK < k;
+    if (more) load(k0 + GBK);
+#pragma unroll
+    for (int kk = 0; kk < GBK; kk += 4) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = Bs[buf][kk + (lane >> 4)][wn + 16 * i + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = As[buf][kk + (lane >> 4)][wm + 16 * j + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  // acc[i][j][v] = C[m0 + wm + 16 j + l%16][n0 + wn + 16 i + 4 v + l/16]
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const long long m = m0 + wm + 16 * j + (lane & 15);
+        const int nn = n0 + wn + 16 * i + 4 * v + (lane >> 4);
+        if (m < rows && nn < n) {
+          double* c = C + m + (long long)nn * ldc;
+          *c = beta == 0.0 ? alpha * acc[i][j][v] : alpha * acc[i][j][v] + beta * (*c);
+        }
+      }
+}
+
 __global__ void k_gemm_small(int m, int n, int k, double alpha, const double* A, int lda, int ta,
                              const double* B, int ldb, int tb, double beta, double* C, int ldc) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -785,6 +869,13 @@ void gemm_nn(long long rows, int n, int k, double alpha, const double* A, long l
         PW_LAUNCH_CHECK();
       }
     }
+    return;
+  }
+  if (n > TBN && rows >= GBM && !getenv("PW_GEMM_SMALL_TILES")) {
+    dim3 grid((unsigned)((rows + GBM - 1) / GBM), (n + GBN - 1) / GBN);
+    hipLaunchKernelGGL(k_gemm_nn_big, grid, dim3(256), 0, st, rows, n, k, alpha, A, lda, B, ldb,
+                       beta, C, ldc);
+    PW_LAUNCH_CHECK();
     return;
   }
   dim3 grid((unsigned)((rows + TBM - 1) / TBM), (n + TBN - 1) / TBN);
