@@ -1,8 +1,9 @@
 // Adjoint building blocks for d J / d c^2 through Algorithm 3 with the
 // phase corrector held fixed:
-//  * reverse velocity Verlet (Sec. 3.1 scheme run backwards) with the c^2
-//    gradient accumulated per state, the forward displacements recomputed
-//    from checkpoints taken every `ckpt` steps;
+//  * reverse velocity Verlet (Sec. 3.1 scheme run backwards, in leapfrog
+//    form: the two half kicks that meet at a level are one kick) with the
+//    c^2 gradient accumulated per state, the forward displacements
+//    recomputed from checkpoints taken every `ckpt` steps;
 //  * transposes of the trigonometric interpolation and of the pointwise
 //    restriction;
 //  * the receiver misfit and its seed.
@@ -25,89 +26,139 @@ struct G3 {
 };
 inline G3 g3(const Grid& g) { return G3{g.dim, g.n[0], g.n[1], g.n[2], 1.0 / (g.dx * g.dx)}; }
 
-__device__ __forceinline__ int wrapi(int g, int n) {
-  g %= n;
-  return g < 0 ? g + n : g;
+// Launch geometry of the per-point kernels: a 1D grid of blocks of kTB
+// points along x.  Blocks are dispatched round-robin over the 8 XCDs, each
+// with its own L2; block L is given the logical block (L % 8) * per + L / 8
+// so that every XCD sweeps a contiguous range of rows and finds the
+// neighbouring rows of its stencils in its own L2.  Logical blocks run
+// x-block fastest, then y, z and the state; coordinates need one division
+// chain per block, none per thread.
+constexpr int kXcd = 8;
+struct Pt {
+  int x, y, z, s;
+  long long J;  // index within the state
+  bool ok;
+};
+__device__ __forceinline__ Pt point(const G3& g, int nxb, long long nblk) {
+  Pt p;
+  const long long per = (nblk + kXcd - 1) / kXcd;
+  const long long L = (long long)(blockIdx.x % kXcd) * per + blockIdx.x / kXcd;
+  p.ok = L < nblk;
+  long long r = L;
+  const int xb = (int)(r % nxb);
+  r /= nxb;
+  p.y = (int)(r % g.ny);
+  r /= g.ny;
+  p.z = (int)(r % g.nz);
+  p.s = (int)(r / g.nz);
+  p.x = xb * kTB + threadIdx.x;
+  p.ok = p.ok && p.x < g.nx;
+  p.J = (long long)p.x + (long long)g.nx * ((long long)p.y + (long long)g.ny * p.z);
+  return p;
+}
+struct PtLaunch {
+  dim3 grid;
+  int nxb;
+  long long nblk;
+};
+PtLaunch pt_launch(const G3& g, int ns) {
+  PtLaunch l;
+  l.nxb = (g.nx + kTB - 1) / kTB;
+  l.nblk = (long long)l.nxb * g.ny * g.nz * ns;
+  const long long per = (l.nblk + kXcd - 1) / kXcd;
+  l.grid = dim3((unsigned)(per * kXcd));
+  return l;
 }
 
-// periodic CD2 Laplacian of f at point J (f: one field)
-__device__ __forceinline__ double lap_at(const double* f, long long J, const G3& g) {
-  const int x = (int)(J % g.nx);
-  const int y = (int)((J / g.nx) % g.ny);
-  const int z = (int)(J / ((long long)g.nx * g.ny));
-  const double c = f[J];
-  auto at = [&](int xx, int yy, int zz) {
-    return f[(long long)xx + (long long)g.nx * ((long long)yy + (long long)g.ny * zz)];
-  };
-  double s = at(wrapi(x + 1, g.nx), y, z) - 2.0 * c + at(wrapi(x - 1, g.nx), y, z);
-  if (g.dim >= 2) s += at(x, wrapi(y + 1, g.ny), z) - 2.0 * c + at(x, wrapi(y - 1, g.ny), z);
-  if (g.dim >= 3) s += at(x, y, wrapi(z + 1, g.nz)) - 2.0 * c + at(x, y, wrapi(z - 1, g.nz));
-  return s * g.idx2;
+// periodic neighbour offsets of a point (up to 6), relative to it
+struct Nbr {
+  long long off[6];
+  int cnt;
+};
+__device__ __forceinline__ Nbr neighbours(const Pt& p, const G3& g) {
+  Nbr nb;
+  const long long sy = g.nx, sz = (long long)g.nx * g.ny;
+  nb.off[0] = p.x + 1 < g.nx ? 1 : 1 - g.nx;
+  nb.off[1] = p.x > 0 ? -1 : g.nx - 1;
+  nb.cnt = 2;
+  if (g.dim >= 2) {
+    nb.off[2] = p.y + 1 < g.ny ? sy : sy - (long long)g.ny * sy;
+    nb.off[3] = p.y > 0 ? -sy : (long long)g.ny * sy - sy;
+    nb.cnt = 4;
+  }
+  if (g.dim >= 3) {
+    nb.off[4] = p.z + 1 < g.nz ? sz : sz - (long long)g.nz * sz;
+    nb.off[5] = p.z > 0 ? -sz : (long long)g.nz * sz - sz;
+    nb.cnt = 6;
+  }
+  return nb;
 }
 
-// c^2 * lambda of a field, staged for the adjoint Laplacian
-__global__ void k_mul_c2(const double* c2, const double* l, long long sl, double* out,
-                         long long so, long long np, int ns) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= np * ns) return;
-  const int s = (int)(t / np);
-  const long long J = t - (long long)s * np;
-  out[(long long)s * so + J] = c2[J] * l[(long long)s * sl + J];
+// CD2 Laplacian of field f at J (f points at J's field)
+__device__ __forceinline__ double lap_nb(const double* f, long long J, const Nbr& nb, double idx2) {
+  double s = -(double)nb.cnt * f[J];
+  for (int k = 0; k < nb.cnt; ++k) s += f[J + nb.off[k]];
+  return s * idx2;
 }
 
-// forward half kick + drift: ph = p + h/2 c2 Lap u ; u_next = u + h ph
-__global__ void k_fwd_kick_drift(const double* u, long long su, double* p, long long sp,
-                                 double* un, long long sun, const double* c2, double h, G3 g,
-                                 long long np, int ns) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= np * ns) return;
-  const int s = (int)(t / np);
-  const long long J = t - (long long)s * np;
-  const double* us = u + (long long)s * su;
-  double pv = p[(long long)s * sp + J] + 0.5 * h * (c2[J] * lap_at(us, J, g));
-  p[(long long)s * sp + J] = pv;
-  un[(long long)s * sun + J] = us[J] + h * pv;
+// Forward recomputation, leapfrog form of velocity Verlet: the state
+// carried between steps is (u_i, p_{i-1/2}); one step is the kick at level
+// i with weight w (h/2 at level 0, h after) and the drift:
+//   p <- p + w c2 Lap u_i,  u_{i+1} = u_i + h p.
+__global__ void k_fwd_step(const double* u, long long su, double* p, long long sp, double* un,
+                           long long sun, const double* c2, double w, double h, G3 g, int nxb,
+                           long long nblk) {
+  const Pt q = point(g, nxb, nblk);
+  if (!q.ok) return;
+  const Nbr nb = neighbours(q, g);
+  const long long J = q.J;
+  const double* us = u + (long long)q.s * su;
+  double* ps = p + (long long)q.s * sp;
+  const double pv = ps[J] + w * (c2[J] * lap_nb(us, J, nb, g.idx2));
+  ps[J] = pv;
+  un[(long long)q.s * sun + J] = us[J] + h * pv;
 }
 
-// forward closing half kick: p += h/2 c2 Lap u
-__global__ void k_fwd_kick(const double* u, long long su, double* p, long long sp,
-                           const double* c2, double h, G3 g, long long np, int ns) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= np * ns) return;
-  const int s = (int)(t / np);
-  const long long J = t - (long long)s * np;
-  p[(long long)s * sp + J] += 0.5 * h * (c2[J] * lap_at(u + (long long)s * su, J, g));
+// Reverse of the closing half kick at level m (p_m = p_{m-1/2} + h/2 c2 Lap u_m):
+//   lu += w Lap(c2 lp),  g += w lp Lap u_m   (w = h/2)
+__global__ void k_adj_kick(double* lu, const double* lp, long long sl, const double* u,
+                           long long su, double* gacc, long long sg, const double* c2, double w,
+                           G3 g, int nxb, long long nblk) {
+  const Pt q = point(g, nxb, nblk);
+  if (!q.ok) return;
+  const Nbr nb = neighbours(q, g);
+  const long long J = q.J;
+  const double* l = lp + (long long)q.s * sl;
+  double a = -(double)nb.cnt * c2[J] * l[J];
+  for (int k = 0; k < nb.cnt; ++k) a += c2[J + nb.off[k]] * l[J + nb.off[k]];
+  lu[(long long)q.s * sl + J] += w * a * g.idx2;
+  gacc[(long long)q.s * sg + J] += w * l[J] * lap_nb(u + (long long)q.s * su, J, nb, g.idx2);
 }
 
-// reverse of the second half kick and the drift of a step:
-//   lu += h/2 Lap(c2 lp);  g += h/2 lp Lap(u_next);  lp_new = lp + h lu
-// a = c2 lp (staged); u1 = displacement after the drift
-__global__ void k_adj_kick2_drift(const double* a, long long sa, double* lu, long long slu,
-                                  const double* lp, long long slp, double* lpn, long long slpn,
-                                  const double* u1, long long su1, double* gacc, long long sg,
-                                  double h, G3 g, long long np, int ns) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= np * ns) return;
-  const int s = (int)(t / np);
-  const long long J = t - (long long)s * np;
-  const double lpv = lp[(long long)s * slp + J];
-  const double luv = lu[(long long)s * slu + J] + 0.5 * h * lap_at(a + (long long)s * sa, J, g);
-  lu[(long long)s * slu + J] = luv;
-  gacc[(long long)s * sg + J] += 0.5 * h * lpv * lap_at(u1 + (long long)s * su1, J, g);
-  lpn[(long long)s * slpn + J] = lpv + h * luv;
-}
-
-// reverse of the first half kick: lu += h/2 Lap(c2 lp); g += h/2 lp Lap(u0)
-__global__ void k_adj_kick1(const double* a, long long sa, double* lu, long long slu,
-                            const double* lp, long long slp, const double* u0, long long su0,
-                            double* gacc, long long sg, double h, G3 g, long long np, int ns) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= np * ns) return;
-  const int s = (int)(t / np);
-  const long long J = t - (long long)s * np;
-  lu[(long long)s * slu + J] += 0.5 * h * lap_at(a + (long long)s * sa, J, g);
-  gacc[(long long)s * sg + J] +=
-      0.5 * h * lp[(long long)s * slp + J] * lap_at(u0 + (long long)s * su0, J, g);
+// One reverse leapfrog step, from level i+1 to level i: the reverse drift
+// lp' = lp + h lu (pointwise, formed at J and its neighbours), then the
+// reverse kick at level i with weight w:
+//   lu' = lu + w Lap(c2 lp'),  g += w lp' Lap u_i.
+// (lu, lp) and (lu', lp') are distinct buffers.
+__global__ void k_adj_step(const double* lu, const double* lp, long long sl, double* lu2,
+                           double* lp2, long long sl2, const double* u, long long su,
+                           double* gacc, long long sg, const double* c2, double w, double h,
+                           G3 g, int nxb, long long nblk) {
+  const Pt q = point(g, nxb, nblk);
+  if (!q.ok) return;
+  const Nbr nb = neighbours(q, g);
+  const long long J = q.J;
+  const double* lus = lu + (long long)q.s * sl;
+  const double* lps = lp + (long long)q.s * sl;
+  const double lpc = fma(h, lus[J], lps[J]);
+  double a = -(double)nb.cnt * c2[J] * lpc;
+  for (int k = 0; k < nb.cnt; ++k) {
+    const long long o = J + nb.off[k];
+    a += c2[o] * fma(h, lus[o], lps[o]);
+  }
+  lu2[(long long)q.s * sl2 + J] = lus[J] + w * a * g.idx2;
+  lp2[(long long)q.s * sl2 + J] = lpc;
+  gacc[(long long)q.s * sg + J] += w * lpc * lap_nb(u + (long long)q.s * su, J, nb, g.idx2);
 }
 
 template <typename T>
@@ -242,41 +293,38 @@ void vv_adjoint(const Grid& grid, const double* c2, const double* u0, const doub
   if (ckpt < 1) fail(PW_EINVAL, "checkpoint interval must be >= 1");
   const long long np = grid.npts();
   const G3 g = g3(grid);
-  const unsigned nb = nblocks(np * ns);
+  const PtLaunch pl = pt_launch(g, ns);
+  const dim3 gr = pl.grid;
   const int nseg = (m + ckpt - 1) / ckpt;
   if ((long long)ns * np > sc.state_elems) fail(PW_EINVAL, "adjoint scratch too small");
   if (nseg > sc.max_ckpt) fail(PW_EINVAL, "too many checkpoints for the adjoint scratch");
   if (std::min(m, ckpt) + 1 > sc.max_seg) fail(PW_EINVAL, "checkpoint segment too long");
   const long long S = sc.state_elems;  // stride of one stored time level
-  // forward pass: checkpoints (u, p) at the start of every segment
+  auto wk = [&](int level) { return level == 0 ? 0.5 * h : h; };
+  // forward pass: checkpoints (u_i, p_{i-1/2}) at the start of every
+  // segment (p_{-1/2} = p_0, with the half kick at level 0)
   copy_fields(u0, s0, sc.ck_u, np, np, ns, st);
   copy_fields(p0, s0, sc.ck_p, np, np, ns, st);
-  double* cu = sc.ck_u;
-  double* cp = sc.ck_p;
   for (int seg = 0; seg + 1 < nseg; ++seg) {
+    const double* cu = sc.ck_u + seg * S;
     double* nu = sc.ck_u + (seg + 1) * S;
     double* npp = sc.ck_p + (seg + 1) * S;
-    copy_fields(cp, np, npp, np, np, ns, st);
-    // ckpt steps from (cu, cp) into (nu, npp), ping-ponging u in the
-    // segment store
+    copy_fields(sc.ck_p + seg * S, np, npp, np, np, ns, st);
     const double* src = cu;
     for (int i = 0; i < ckpt; ++i) {
       double* dst = (i == ckpt - 1) ? nu : sc.seg + (long long)(i % 2) * S;
-      hipLaunchKernelGGL(k_fwd_kick_drift, dim3(nb), dim3(kTB), 0, st, src, np, npp, np, dst, np,
-                         c2, h, g, np, ns);
-      hipLaunchKernelGGL(k_fwd_kick, dim3(nb), dim3(kTB), 0, st, (const double*)dst, np, npp, np,
-                         c2, h, g, np, ns);
+      hipLaunchKernelGGL(k_fwd_step, gr, dim3(kTB), 0, st, src, np, npp, np, dst, np, c2,
+                         wk(seg * ckpt + i), h, g, pl.nxb, pl.nblk);
       PW_LAUNCH_CHECK();
       src = dst;
     }
-    cu = nu;
-    cp = npp;
   }
-  // reverse over the segments: recompute the displacements, step back.
-  // The adjoint momentum ping-pongs between lp (stride sl) and lp_tmp
-  // (stride np).
+  // reverse over the segments.  (lu, lp) ping-pong between the caller's
+  // arrays (stride sl) and scratch (stride np).
+  double* lua = lu;
   double* lpa = lp;
   long long sa = sl;
+  double* lub = sc.a_tmp;
   double* lpb = sc.lp_tmp;
   long long sb = np;
   for (int seg = nseg - 1; seg >= 0; --seg) {
@@ -286,34 +334,34 @@ void vv_adjoint(const Grid& grid, const double* c2, const double* u0, const doub
     copy_fields(sc.ck_u + seg * S, np, sc.seg, np, np, ns, st);
     copy_fields(sc.ck_p + seg * S, np, sc.p_tmp, np, np, ns, st);
     for (int i = 0; i < len; ++i) {
-      const double* src = sc.seg + (long long)i * S;
-      double* dst = sc.seg + (long long)(i + 1) * S;
-      hipLaunchKernelGGL(k_fwd_kick_drift, dim3(nb), dim3(kTB), 0, st, src, np, sc.p_tmp, np, dst,
-                         np, c2, h, g, np, ns);
-      hipLaunchKernelGGL(k_fwd_kick, dim3(nb), dim3(kTB), 0, st, (const double*)dst, np,
-                         sc.p_tmp, np, c2, h, g, np, ns);
+      hipLaunchKernelGGL(k_fwd_step, gr, dim3(kTB), 0, st,
+                         (const double*)(sc.seg + (long long)i * S), np, sc.p_tmp, np,
+                         sc.seg + (long long)(i + 1) * S, np, c2, wk(i0 + i), h, g, pl.nxb,
+                         pl.nblk);
+      PW_LAUNCH_CHECK();
+    }
+    if (seg == nseg - 1) {
+      // closing half kick at level m
+      hipLaunchKernelGGL(k_adj_kick, gr, dim3(kTB), 0, st, lua, (const double*)lpa, sa,
+                         (const double*)(sc.seg + (long long)len * S), np, gacc, sg, c2, 0.5 * h,
+                         g, pl.nxb, pl.nblk);
       PW_LAUNCH_CHECK();
     }
     for (int i = len - 1; i >= 0; --i) {
-      const double* ui = sc.seg + (long long)i * S;
-      const double* ui1 = sc.seg + (long long)(i + 1) * S;
-      // second half kick + drift
-      hipLaunchKernelGGL(k_mul_c2, dim3(nb), dim3(kTB), 0, st, c2, (const double*)lpa, sa,
-                         sc.a_tmp, np, np, ns);
-      hipLaunchKernelGGL(k_adj_kick2_drift, dim3(nb), dim3(kTB), 0, st, (const double*)sc.a_tmp,
-                         np, lu, sl, (const double*)lpa, sa, lpb, sb, ui1, np, gacc, sg, h, g, np,
-                         ns);
-      // first half kick
-      hipLaunchKernelGGL(k_mul_c2, dim3(nb), dim3(kTB), 0, st, c2, (const double*)lpb, sb,
-                         sc.a_tmp, np, np, ns);
-      hipLaunchKernelGGL(k_adj_kick1, dim3(nb), dim3(kTB), 0, st, (const double*)sc.a_tmp, np, lu,
-                         sl, (const double*)lpb, sb, ui, np, gacc, sg, h, g, np, ns);
+      hipLaunchKernelGGL(k_adj_step, gr, dim3(kTB), 0, st, (const double*)lua,
+                         (const double*)lpa, sa, lub, lpb, sb,
+                         (const double*)(sc.seg + (long long)i * S), np, gacc, sg, c2,
+                         wk(i0 + i), h, g, pl.nxb, pl.nblk);
       PW_LAUNCH_CHECK();
+      std::swap(lua, lub);
       std::swap(lpa, lpb);
       std::swap(sa, sb);
     }
   }
-  if (lpa != lp) copy_fields(lpa, sa, lp, sl, np, ns, st);
+  if (lua != lu) {
+    copy_fields(lua, sa, lu, sl, np, ns, st);
+    copy_fields(lpa, sa, lp, sl, np, ns, st);
+  }
 }
 
 void interp_transpose(const Grid& f, const Grid& c, int ratio, const double* const* tables,

@@ -906,7 +906,10 @@ void orth(long long rows, int n, const double* A, long long lda, double* Q, long
           double* R, OrthScratch s, hipStream_t st) {
   // pass 1: truncated pivoted Cholesky QR of A
   gemm_tn(rows, n, n, 1.0, A, lda, A, lda, 0.0, s.gram, n, s.work, s.work_elems, st);
-  pchol_factors(n, s.gram, 1e-13, 1e-290, s.T, s.R1, st);
+  // truncation at 1e-15 of the largest Gram diagonal: residual directions
+  // down to ~3e-8 of the largest singular value are kept (the Gram matrix
+  // resolves directions only down to ~sqrt(eps) of it)
+  pchol_factors(n, s.gram, 1e-15, 1e-290, s.T, s.R1, st);
   gemm_nn(rows, n, n, 1.0, A, lda, s.T, n, 0.0, s.Q1, rows, st);
   // pass 2: the same on Q1 (its Gram is the identity up to rounding on the
   // kept columns, zero on the dropped ones)

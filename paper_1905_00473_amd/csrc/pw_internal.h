@@ -223,7 +223,7 @@ void gemm_small(int m, int n, int k, double alpha, const double* A, int lda, boo
 
 // Orthonormalisation for the truncated QR of Algorithm 1 (two passes of
 // pivoted Cholesky QR): A (rows x n, n <= 64) = Q R approximately; Q (rows x
-// n, ldq), R (n x n).  Directions whose pivot is below 1e-13 times the
+// n, ldq), R (n x n).  Directions whose pivot is below 1e-15 times the
 // largest diagonal of A^T A are dropped (zero Q column, zero R row).
 struct OrthScratch {
   double* gram = nullptr;   // n*n

@@ -28,6 +28,8 @@ Workloads (fine grid / coarse grid, unit periodic box):
   Ricker-shaped pulse of peak frequency 10 at (0.5, 0.1), 128 receivers
   at x = (i + 1/2)/128, y = 0.9 (nearest nodes), T = 1, N = 32, m_F = 96,
   m_C = 24, K = 4; target medium for the data: the same recipe, seed 1.
+* ``random_pulses`` seeded Gaussian-pulse states (test inputs of the
+  propagators at full size).
 * ``grf2d`` / ``batch2d``  smooth random media c = exp(0.3 g) with random
   Gaussian pulses; ``batch2d`` draws 32 such problems with fine grids from
   {256, 384, 512, 768, 1024}^2 (the batched workload).
@@ -194,6 +196,28 @@ def ricker_pulse(shape, centre, freq):
         r2 = r2 + d * d
     a = (np.pi * freq) ** 2 * r2
     return (1.0 - 2.0 * a) * np.exp(-a)
+
+
+def random_pulses(shape, n, seed, sigma=(0.02, 0.05)):
+    """n seeded states (u, p) of Gaussian pulses at random centres with
+    widths drawn from `sigma` (the batched-problem recipe's pulse), p a
+    second pulse of random amplitude; periodic distances."""
+    rng = np.random.default_rng(seed)
+    grids = _axes(shape)
+    us, ps = [], []
+    for _ in range(n):
+        fields = []
+        for _ in range(2):
+            x0 = rng.uniform(0, 1, size=len(shape))
+            s = rng.uniform(*sigma)
+            r2 = np.zeros(shape)
+            for g, c in zip(grids, x0):
+                d = (g - c + 0.5) % 1.0 - 0.5
+                r2 = r2 + d * d
+            fields.append(np.exp(-r2 / (2 * s * s)))
+        us.append(fields[0])
+        ps.append(rng.uniform(-2, 2) * fields[1])
+    return np.stack(us), np.stack(ps)
 
 
 def misfit_case(shape=(32, 32), ratio=4, N=4, K=2, T=0.25, m_fine=8,
