@@ -39,19 +39,20 @@ struct Pt {
   long long J;  // index within the state
   bool ok;
 };
-__device__ __forceinline__ Pt point(const G3& g, int nxb, long long nblk) {
+// (logical block counts stay below 2^31: 32-bit decoding)
+__device__ __forceinline__ Pt point(const G3& g, int nxb, int nblk) {
   Pt p;
-  const long long per = (nblk + kXcd - 1) / kXcd;
-  const long long L = (long long)(blockIdx.x % kXcd) * per + blockIdx.x / kXcd;
+  const int per = (nblk + kXcd - 1) / kXcd;
+  const int L = (int)(blockIdx.x % kXcd) * per + (int)(blockIdx.x / kXcd);
   p.ok = L < nblk;
-  long long r = L;
-  const int xb = (int)(r % nxb);
+  int r = L;
+  const int xb = r % nxb;
   r /= nxb;
-  p.y = (int)(r % g.ny);
+  p.y = r % g.ny;
   r /= g.ny;
-  p.z = (int)(r % g.nz);
-  p.s = (int)(r / g.nz);
-  p.x = xb * kTB + threadIdx.x;
+  p.z = r % g.nz;
+  p.s = r / g.nz;
+  p.x = xb * kTB + (int)threadIdx.x;
   p.ok = p.ok && p.x < g.nx;
   p.J = (long long)p.x + (long long)g.nx * ((long long)p.y + (long long)g.ny * p.z);
   return p;
@@ -59,45 +60,49 @@ __device__ __forceinline__ Pt point(const G3& g, int nxb, long long nblk) {
 struct PtLaunch {
   dim3 grid;
   int nxb;
-  long long nblk;
+  int nblk;
 };
 PtLaunch pt_launch(const G3& g, int ns) {
   PtLaunch l;
   l.nxb = (g.nx + kTB - 1) / kTB;
-  l.nblk = (long long)l.nxb * g.ny * g.nz * ns;
-  const long long per = (l.nblk + kXcd - 1) / kXcd;
-  l.grid = dim3((unsigned)(per * kXcd));
+  const long long nblk = (long long)l.nxb * g.ny * g.nz * ns;
+  if (nblk >= (1LL << 31) - kXcd) fail(PW_EINVAL, "adjoint launch too large");
+  l.nblk = (int)nblk;
+  const int per = (l.nblk + kXcd - 1) / kXcd;
+  l.grid = dim3((unsigned)per * kXcd);
   return l;
 }
 
-// periodic neighbour offsets of a point (up to 6), relative to it
+// periodic neighbour offsets of a point (2 D of them), relative to it
+template <int D>
 struct Nbr {
-  long long off[6];
-  int cnt;
+  long long off[2 * D];
 };
-__device__ __forceinline__ Nbr neighbours(const Pt& p, const G3& g) {
-  Nbr nb;
-  const long long sy = g.nx, sz = (long long)g.nx * g.ny;
+template <int D>
+__device__ __forceinline__ Nbr<D> neighbours(const Pt& p, const G3& g) {
+  Nbr<D> nb;
   nb.off[0] = p.x + 1 < g.nx ? 1 : 1 - g.nx;
   nb.off[1] = p.x > 0 ? -1 : g.nx - 1;
-  nb.cnt = 2;
-  if (g.dim >= 2) {
+  if (D >= 2) {
+    const long long sy = g.nx;
     nb.off[2] = p.y + 1 < g.ny ? sy : sy - (long long)g.ny * sy;
     nb.off[3] = p.y > 0 ? -sy : (long long)g.ny * sy - sy;
-    nb.cnt = 4;
   }
-  if (g.dim >= 3) {
+  if (D >= 3) {
+    const long long sz = (long long)g.nx * g.ny;
     nb.off[4] = p.z + 1 < g.nz ? sz : sz - (long long)g.nz * sz;
     nb.off[5] = p.z > 0 ? -sz : (long long)g.nz * sz - sz;
-    nb.cnt = 6;
   }
   return nb;
 }
 
 // CD2 Laplacian of field f at J (f points at J's field)
-__device__ __forceinline__ double lap_nb(const double* f, long long J, const Nbr& nb, double idx2) {
-  double s = -(double)nb.cnt * f[J];
-  for (int k = 0; k < nb.cnt; ++k) s += f[J + nb.off[k]];
+template <int D>
+__device__ __forceinline__ double lap_nb(const double* f, long long J, const Nbr<D>& nb,
+                                         double idx2) {
+  double s = -2.0 * D * f[J];
+#pragma unroll
+  for (int k = 0; k < 2 * D; ++k) s += f[J + nb.off[k]];
   return s * idx2;
 }
 
@@ -105,34 +110,37 @@ __device__ __forceinline__ double lap_nb(const double* f, long long J, const Nbr
 // carried between steps is (u_i, p_{i-1/2}); one step is the kick at level
 // i with weight w (h/2 at level 0, h after) and the drift:
 //   p <- p + w c2 Lap u_i,  u_{i+1} = u_i + h p.
+template <int D>
 __global__ void k_fwd_step(const double* u, long long su, double* p, long long sp, double* un,
                            long long sun, const double* c2, double w, double h, G3 g, int nxb,
-                           long long nblk) {
+                           int nblk) {
   const Pt q = point(g, nxb, nblk);
   if (!q.ok) return;
-  const Nbr nb = neighbours(q, g);
+  const Nbr<D> nb = neighbours<D>(q, g);
   const long long J = q.J;
   const double* us = u + (long long)q.s * su;
   double* ps = p + (long long)q.s * sp;
-  const double pv = ps[J] + w * (c2[J] * lap_nb(us, J, nb, g.idx2));
+  const double pv = ps[J] + w * (c2[J] * lap_nb<D>(us, J, nb, g.idx2));
   ps[J] = pv;
   un[(long long)q.s * sun + J] = us[J] + h * pv;
 }
 
 // Reverse of the closing half kick at level m (p_m = p_{m-1/2} + h/2 c2 Lap u_m):
 //   lu += w Lap(c2 lp),  g += w lp Lap u_m   (w = h/2)
+template <int D>
 __global__ void k_adj_kick(double* lu, const double* lp, long long sl, const double* u,
                            long long su, double* gacc, long long sg, const double* c2, double w,
-                           G3 g, int nxb, long long nblk) {
+                           G3 g, int nxb, int nblk) {
   const Pt q = point(g, nxb, nblk);
   if (!q.ok) return;
-  const Nbr nb = neighbours(q, g);
+  const Nbr<D> nb = neighbours<D>(q, g);
   const long long J = q.J;
   const double* l = lp + (long long)q.s * sl;
-  double a = -(double)nb.cnt * c2[J] * l[J];
-  for (int k = 0; k < nb.cnt; ++k) a += c2[J + nb.off[k]] * l[J + nb.off[k]];
+  double a = -2.0 * D * c2[J] * l[J];
+#pragma unroll
+  for (int k = 0; k < 2 * D; ++k) a += c2[J + nb.off[k]] * l[J + nb.off[k]];
   lu[(long long)q.s * sl + J] += w * a * g.idx2;
-  gacc[(long long)q.s * sg + J] += w * l[J] * lap_nb(u + (long long)q.s * su, J, nb, g.idx2);
+  gacc[(long long)q.s * sg + J] += w * l[J] * lap_nb<D>(u + (long long)q.s * su, J, nb, g.idx2);
 }
 
 // One reverse leapfrog step, from level i+1 to level i: the reverse drift
@@ -140,25 +148,27 @@ __global__ void k_adj_kick(double* lu, const double* lp, long long sl, const dou
 // reverse kick at level i with weight w:
 //   lu' = lu + w Lap(c2 lp'),  g += w lp' Lap u_i.
 // (lu, lp) and (lu', lp') are distinct buffers.
+template <int D>
 __global__ void k_adj_step(const double* lu, const double* lp, long long sl, double* lu2,
                            double* lp2, long long sl2, const double* u, long long su,
                            double* gacc, long long sg, const double* c2, double w, double h,
-                           G3 g, int nxb, long long nblk) {
+                           G3 g, int nxb, int nblk) {
   const Pt q = point(g, nxb, nblk);
   if (!q.ok) return;
-  const Nbr nb = neighbours(q, g);
+  const Nbr<D> nb = neighbours<D>(q, g);
   const long long J = q.J;
   const double* lus = lu + (long long)q.s * sl;
   const double* lps = lp + (long long)q.s * sl;
   const double lpc = fma(h, lus[J], lps[J]);
-  double a = -(double)nb.cnt * c2[J] * lpc;
-  for (int k = 0; k < nb.cnt; ++k) {
+  double a = -2.0 * D * c2[J] * lpc;
+#pragma unroll
+  for (int k = 0; k < 2 * D; ++k) {
     const long long o = J + nb.off[k];
     a += c2[o] * fma(h, lus[o], lps[o]);
   }
   lu2[(long long)q.s * sl2 + J] = lus[J] + w * a * g.idx2;
   lp2[(long long)q.s * sl2 + J] = lpc;
-  gacc[(long long)q.s * sg + J] += w * lpc * lap_nb(u + (long long)q.s * su, J, nb, g.idx2);
+  gacc[(long long)q.s * sg + J] += w * lpc * lap_nb<D>(u + (long long)q.s * su, J, nb, g.idx2);
 }
 
 template <typename T>
@@ -286,7 +296,8 @@ void copy_fields(const double* in, long long si, double* out, long long so, long
   PW_LAUNCH_CHECK();
 }
 
-void vv_adjoint(const Grid& grid, const double* c2, const double* u0, const double* p0,
+template <int D>
+void vv_adjoint_d(const Grid& grid, const double* c2, const double* u0, const double* p0,
                 long long s0, double* lu, double* lp, long long sl, double* gacc, long long sg,
                 int ns, int m, double h, int ckpt, const AdjScratch& sc, hipStream_t st) {
   if (ns == 0 || m == 0) return;
@@ -313,7 +324,7 @@ void vv_adjoint(const Grid& grid, const double* c2, const double* u0, const doub
     const double* src = cu;
     for (int i = 0; i < ckpt; ++i) {
       double* dst = (i == ckpt - 1) ? nu : sc.seg + (long long)(i % 2) * S;
-      hipLaunchKernelGGL(k_fwd_step, gr, dim3(kTB), 0, st, src, np, npp, np, dst, np, c2,
+      hipLaunchKernelGGL(k_fwd_step<D>, gr, dim3(kTB), 0, st, src, np, npp, np, dst, np, c2,
                          wk(seg * ckpt + i), h, g, pl.nxb, pl.nblk);
       PW_LAUNCH_CHECK();
       src = dst;
@@ -334,7 +345,7 @@ void vv_adjoint(const Grid& grid, const double* c2, const double* u0, const doub
     copy_fields(sc.ck_u + seg * S, np, sc.seg, np, np, ns, st);
     copy_fields(sc.ck_p + seg * S, np, sc.p_tmp, np, np, ns, st);
     for (int i = 0; i < len; ++i) {
-      hipLaunchKernelGGL(k_fwd_step, gr, dim3(kTB), 0, st,
+      hipLaunchKernelGGL(k_fwd_step<D>, gr, dim3(kTB), 0, st,
                          (const double*)(sc.seg + (long long)i * S), np, sc.p_tmp, np,
                          sc.seg + (long long)(i + 1) * S, np, c2, wk(i0 + i), h, g, pl.nxb,
                          pl.nblk);
@@ -342,13 +353,13 @@ void vv_adjoint(const Grid& grid, const double* c2, const double* u0, const doub
     }
     if (seg == nseg - 1) {
       // closing half kick at level m
-      hipLaunchKernelGGL(k_adj_kick, gr, dim3(kTB), 0, st, lua, (const double*)lpa, sa,
+      hipLaunchKernelGGL(k_adj_kick<D>, gr, dim3(kTB), 0, st, lua, (const double*)lpa, sa,
                          (const double*)(sc.seg + (long long)len * S), np, gacc, sg, c2, 0.5 * h,
                          g, pl.nxb, pl.nblk);
       PW_LAUNCH_CHECK();
     }
     for (int i = len - 1; i >= 0; --i) {
-      hipLaunchKernelGGL(k_adj_step, gr, dim3(kTB), 0, st, (const double*)lua,
+      hipLaunchKernelGGL(k_adj_step<D>, gr, dim3(kTB), 0, st, (const double*)lua,
                          (const double*)lpa, sa, lub, lpb, sb,
                          (const double*)(sc.seg + (long long)i * S), np, gacc, sg, c2,
                          wk(i0 + i), h, g, pl.nxb, pl.nblk);
@@ -362,6 +373,17 @@ void vv_adjoint(const Grid& grid, const double* c2, const double* u0, const doub
     copy_fields(lua, sa, lu, sl, np, ns, st);
     copy_fields(lpa, sa, lp, sl, np, ns, st);
   }
+}
+
+void vv_adjoint(const Grid& grid, const double* c2, const double* u0, const double* p0,
+                long long s0, double* lu, double* lp, long long sl, double* gacc, long long sg,
+                int ns, int m, double h, int ckpt, const AdjScratch& sc, hipStream_t st) {
+  if (grid.dim == 1)
+    vv_adjoint_d<1>(grid, c2, u0, p0, s0, lu, lp, sl, gacc, sg, ns, m, h, ckpt, sc, st);
+  else if (grid.dim == 2)
+    vv_adjoint_d<2>(grid, c2, u0, p0, s0, lu, lp, sl, gacc, sg, ns, m, h, ckpt, sc, st);
+  else
+    vv_adjoint_d<3>(grid, c2, u0, p0, s0, lu, lp, sl, gacc, sg, ns, m, h, ckpt, sc, st);
 }
 
 void interp_transpose(const Grid& f, const Grid& c, int ratio, const double* const* tables,
