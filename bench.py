@@ -34,7 +34,7 @@ BYTES_PER_UPDATE_F32 = 20
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) of `bench.py --traffic-probe`, scaled
 # by the same counters on a 512 MiB copy (profiles/disc2d_fine_stencil_
 # traffic.md).  Valid only for the stencil revision it was measured on.
-TRAFFIC = {"stencil-r3": 576.5e6}
+TRAFFIC = {"stencil-r3": 577.0e6}
 
 
 def log(msg):
@@ -184,6 +184,8 @@ def main():
                     help="skip the misfit-gradient measurement")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the misfit-gradient measurement (profiling)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the 32-problem batched measurement (profiling)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run one fine sweep and one 512 MiB device "
                          "copy (for rocprofv3 --pmc FETCH_SIZE/WRITE_SIZE)")
@@ -203,6 +205,9 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     if args.adjoint_only:
         print(json.dumps(adjoint_measurement(pw, W, torch)), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps(batch_measurement(pw, W, torch)), flush=True)
         return
     w = W.disc2d()
     K = w.K
