@@ -39,3 +39,45 @@ def test_problem_struct_layout():
     assert ctypes.sizeof(pw.Problem) == 72
     assert pw.Problem.T.offset == 24
     assert pw.Problem.svd_tol.offset == 48
+
+
+def _create(P):
+    h = ctypes.c_void_p()
+    arr = (pw.Problem * 1)(P)
+    st = pw.lib().pw_create(arr, 1, None, ctypes.byref(h))
+    return st, pw.lib().pw_last_error().decode()
+
+
+def test_invalid_problems_rejected_before_any_device_work():
+    """Argument validation of pw_create runs on the host before any device
+    allocation (these calls make no GPU call)."""
+    good = dict(shape=(40, 40), ratio=4, T=0.25, N=4, m_fine=8, m_coarse=2)
+    cases = []
+
+    def mk(**kw):
+        a = dict(good)
+        a.update(kw)
+        return pw.Problem.make(a["shape"], a["ratio"], a["T"], a["N"],
+                               a["m_fine"], a["m_coarse"],
+                               a.get("order", 4), a.get("tol", 1e-10),
+                               a.get("dtype", "f64"), a.get("comp", False),
+                               a.get("max_iters", 2))
+    cases.append((mk(ratio=3), "ratio must divide"))
+    cases.append((mk(shape=(16, 16)), "at least 5 points"))
+    cases.append((mk(T=0.0), "T must be positive"))
+    cases.append((mk(N=0), "slice/step"))
+    cases.append((mk(N=65), "at most 64 slices"))
+    cases.append((mk(order=3), "grad_order"))
+    cases.append((mk(tol=0.0), "svd_tol"))
+    cases.append((mk(comp=True), "compensation"))
+    cases.append((mk(max_iters=0), "max_iters"))
+    bad_dim = mk()
+    bad_dim.dim = 4
+    cases.append((bad_dim, "dim must be"))
+    bad_axis = mk()
+    bad_axis.n_fine[2] = 3
+    cases.append((bad_axis, "unused axes"))
+    for P, msg in cases:
+        st, err = _create(P)
+        assert st == -1, (msg, st, err)
+        assert msg in err, (msg, err)
