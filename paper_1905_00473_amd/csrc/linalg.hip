@@ -105,6 +105,25 @@ __global__ void k_reduce_splits(const double* part, int nsplit, int a, int b, do
   *c = beta == 0.0 ? alpha * s : alpha * s + beta * (*c);
 }
 
+// many splits: one wave per output element; lane l adds partials l, l+64,
+// ... and the wave sums its lanes in a fixed order
+__global__ __launch_bounds__(256) void k_reduce_splits_wave(const double* part, int nsplit, int a,
+                                                            int b, double alpha, double beta,
+                                                            double* C, long long ldc) {
+  const long long t = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const long long ab = (long long)a * b;
+  if (t >= ab) return;
+  double s = 0.0;
+  for (int k = lane; k < nsplit; k += 64) s += part[(long long)k * ab + t];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) {
+    const int m = (int)(t % a), n = (int)(t / a);
+    double* c = C + m + (long long)n * ldc;
+    *c = beta == 0.0 ? alpha * s : alpha * s + beta * (*c);
+  }
+}
+
 template <int BK>
 __global__ __launch_bounds__(256) void k_gemm_nn(long long rows, int n, int k, double alpha,
                                                   const double* A, long long lda, const double* B,
@@ -851,8 +870,12 @@ void gemm_tn(long long rows, int a, int b, double alpha, const double* A, long l
                      rps);
   PW_LAUNCH_CHECK();
   const long long ab = (long long)a * b;
-  hipLaunchKernelGGL(k_reduce_splits, dim3(nblocks(ab)), dim3(kTB), 0, st, (const double*)work, ns,
-                     a, b, alpha, beta, C, ldc);
+  if (ns >= 32)
+    hipLaunchKernelGGL(k_reduce_splits_wave, dim3((unsigned)((ab + 3) / 4)), dim3(256), 0, st,
+                       (const double*)work, ns, a, b, alpha, beta, C, ldc);
+  else
+    hipLaunchKernelGGL(k_reduce_splits, dim3(nblocks(ab)), dim3(kTB), 0, st, (const double*)work,
+                       ns, a, b, alpha, beta, C, ldc);
   PW_LAUNCH_CHECK();
 }
 
@@ -982,8 +1005,57 @@ void svd_jacobi(int n, const double* H, double* X, double* Y, double* sig, doubl
   PW_LAUNCH_CHECK();
 }
 
+// one step of the serial recurrence: t_n = b_n + M t_{n-1} (M: dim x dim,
+// column-major).  A workgroup owns 64 rows (lane = row); its 16 waves sum
+// interleaved column groups with four independent accumulators each, and
+// the partial sums are combined in a fixed order through LDS.
+constexpr int kRecWaves = 16;
+__global__ __launch_bounds__(64 * kRecWaves) void k_rec_step(int dim, const double* M,
+                                                              const double* tprev,
+                                                              const double* b, double* t) {
+  __shared__ double part[kRecWaves][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = blockIdx.x * 64 + lane;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (row < dim) {
+    int j = wave;
+    for (; j + 3 * kRecWaves < dim; j += 4 * kRecWaves) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int jj = j + k * kRecWaves;
+        acc[k] = fma(M[row + (long long)jj * dim], tprev[jj], acc[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {  // at most three columns remain
+      const int jj = j + k * kRecWaves;
+      if (jj < dim) acc[k] = fma(M[row + (long long)jj * dim], tprev[jj], acc[k]);
+    }
+  }
+  part[wave][lane] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  __syncthreads();
+  if (wave == 0 && row < dim) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kRecWaves; ++w) s += part[w][lane];
+    t[row] = b[row] + s;
+  }
+}
+
 void recurrence(int dim, int N, const double* M, const double* b, double* t, RecScratch rs,
                 hipStream_t st) {
+  if (dim > 64 && N > 1) {
+    // large dim: N - 1 matrix-vector steps cost less than the doubling
+    // scan's log2(N) dim x dim products
+    PW_HIP(hipMemcpyAsync(t, b, sizeof(double) * dim, hipMemcpyDeviceToDevice, st));
+    for (int n = 1; n < N; ++n) {
+      hipLaunchKernelGGL(k_rec_step, dim3((dim + 63) / 64), dim3(64 * kRecWaves), 0, st, dim, M,
+                         (const double*)(t + (long long)(n - 1) * dim),
+                         b + (long long)n * dim, t + (long long)n * dim);
+      PW_LAUNCH_CHECK();
+    }
+    return;
+  }
   // Hillis-Steele doubling: with t^(0)_n = b_n and P = M,
   //   t^(l+1)_n = t^(l)_n + P^(2^l) t^(l)_{n - 2^l}   (n >= 2^l)
   // gives t_n = sum_{j <= n} M^(n-j) b_j after ceil(log2 N) levels; each

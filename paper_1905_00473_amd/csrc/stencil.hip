@@ -545,10 +545,15 @@ void propagate_stream2d(const Grid& g, const T* c2, const T* u_src, const T* p_s
   a.h = h;
   a.idx2 = T(1.0 / (g.dx * g.dx));
   a.ncb = (a.nx + XV - 1) / XV;
-  // enough independent streams to fill the chip; segments of >= 32 rows
+  // enough independent streams to fill the chip; segments of >= 32 rows,
+  // or >= 8 rows when even that leaves fewer than 256 streams (one small
+  // state: each stream is a serial chain of row steps, so shorter segments
+  // finish sooner although they repeat more halo rows)
   const long long want = 4096;
-  long long nseg = (want + (long long)nstates * a.ncb - 1) / ((long long)nstates * a.ncb);
-  nseg = std::max(1LL, std::min(nseg, (long long)((a.ny + 31) / 32)));
+  const long long lanes = (long long)nstates * a.ncb;
+  long long nseg = (want + lanes - 1) / lanes;
+  const long long minrows = lanes * ((a.ny + 31) / 32) < 256 ? 8 : 32;
+  nseg = std::max(1LL, std::min(nseg, (long long)((a.ny + minrows - 1) / minrows)));
   a.Ly = (int)((a.ny + nseg - 1) / nseg);
   a.nseg = (a.ny + a.Ly - 1) / a.Ly;
   const int nl = (m + B - 1) / B;
