@@ -269,6 +269,85 @@ __global__ __launch_bounds__(256) void k_gemm_nn_big(long long rows, int n, int 
       }
 }
 
+// Large split-K partial of C = A^T B (A: rows x a, B: rows x b,
+// column-major): 128 x 128 tiles of the a x b result, rows split over
+// blockIdx.z; each partial goes to part[z] (a x b, column-major).  Same
+// structure as k_gemm_nn_big: tiles of C^T on the matrix cores (operand a
+// from B, operand b from A) for contiguous stores, next k-step prefetched.
+__global__ __launch_bounds__(256) void k_gemm_tn_big(long long rows, int a, int b,
+                                                      const double* A, long long lda,
+                                                      const double* B, long long ldb,
+                                                      double* part, long long rows_per_split) {
+  __shared__ double As[2][GBK][GBM + GPAD];
+  __shared__ double Bs[2][GBK][GBN + GPAD];
+  const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
+  const long long r0 = (long long)blockIdx.z * rows_per_split;
+  const long long r1 = std::min(rows, r0 + rows_per_split);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+  v4d acc[4][4];  // [n sub-tile][m sub-tile]
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+  // loader: 16 rows x 128 columns of A and of B, 8 values each per thread
+  const int lk = tid & 15, lc = tid >> 4;  // column = lc + 16 q
+  double ra[8], rb[8];
+  auto load = [&](long long k0) {
+    const long long r = k0 + lk;
+    const bool ok = r < r1;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int c = lc + 16 * q;
+      ra[q] = (ok && m0 + c < a) ? A[r + (long long)(m0 + c) * lda] : 0.0;
+      rb[q] = (ok && n0 + c < b) ? B[r + (long long)(n0 + c) * ldb] : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      As[buf][lk][lc + 16 * q] = ra[q];
+      Bs[buf][lk][lc + 16 * q] = rb[q];
+    }
+  };
+  load(r0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (long long k0 = r0; k0 < r1; k0 += GBK) {
+    const bool more = k0 + GBK < r1;
+    if (more) load(k0 + GBK);
+#pragma unroll
+    for (int kk = 0; kk < GBK; kk += 4) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = Bs[buf][kk + (lane >> 4)][wn + 16 * i + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = As[buf][kk + (lane >> 4)][wm + 16 * j + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  double* P = part + (long long)blockIdx.z * a * b;
+  // acc[i][j][v] = C[m0 + wm + 16 j + l%16][n0 + wn + 16 i + 4 v + l/16]
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wm + 16 * j + (lane & 15);
+        const int n = n0 + wn + 16 * i + 4 * v + (lane >> 4);
+        if (m < a && n < b) P[m + (long long)n * a] = acc[i][j][v];
+      }
+}
+
 __global__ void k_gemm_small(int m, int n, int k, double alpha, const double* A, int lda, int ta,
                              const double* B, int ldb, int tb, double beta, double* C, int ldc) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -824,10 +903,20 @@ bool debug_jacobi() {
 constexpr int kTnBK = 32;
 constexpr int kNnBK = 16;
 
+// large results use the 128 x 128 tile kernel with about kBigTarget
+// workgroups (the scratch bound below covers both schemes)
+constexpr int kBigTarget = 256;
+bool tn_big(long long rows, int a, int b) {
+  return a > TBM && b > TBN && rows >= GBM && !getenv("PW_GEMM_SMALL_TILES");
+}
+
 int tn_splits(long long rows, int a, int b) {
-  const long long tiles = (long long)((a + TBM - 1) / TBM) * ((b + TBN - 1) / TBN);
-  long long s = (kSplitTarget + tiles - 1) / tiles;
-  const long long maxs = (rows + kTnBK - 1) / kTnBK;
+  const bool big = tn_big(rows, a, b);
+  const int bm = big ? GBM : TBM, bn = big ? GBN : TBN, bk = big ? GBK : kTnBK;
+  const long long tiles = (long long)((a + bm - 1) / bm) * ((b + bn - 1) / bn);
+  const long long target = big ? kBigTarget : kSplitTarget;
+  long long s = (target + tiles - 1) / tiles;
+  const long long maxs = (rows + bk - 1) / bk;
   s = std::max(1LL, std::min(s, maxs));
   return (int)s;
 }
@@ -840,8 +929,10 @@ size_t gemm_tn_work(long long rows, int a, int b) {
 
 size_t gemm_tn_work_bound(int a_max, int b_max) {
   // splits <= ceil(target / tiles) <= target / tiles + 1 and
-  // a * b <= tiles * TBM * TBN, so splits * a * b <= target * TBM * TBN + a * b
-  return (size_t)kSplitTarget * TBM * TBN + (size_t)a_max * b_max;
+  // a * b <= tiles * BM * BN, so splits * a * b <= target * BM * BN + a * b
+  // for either tile scheme
+  return std::max((size_t)kSplitTarget * TBM * TBN, (size_t)kBigTarget * GBM * GBN) +
+         (size_t)a_max * b_max;
 }
 
 void gemm_tn(long long rows, int a, int b, double alpha, const double* A, long long lda,
@@ -861,13 +952,21 @@ void gemm_tn(long long rows, int a, int b, double alpha, const double* A, long l
     }
     return;
   }
+  const bool big = tn_big(rows, a, b);
   const int splits = tn_splits(rows, a, b);
+  const int bk = big ? GBK : kTnBK;
   long long rps = (rows + splits - 1) / splits;
-  rps = (rps + kTnBK - 1) / kTnBK * kTnBK;
+  rps = (rps + bk - 1) / bk * bk;
   const int ns = (int)((rows + rps - 1) / rps);
-  dim3 grid((a + TBM - 1) / TBM, (b + TBN - 1) / TBN, ns);
-  hipLaunchKernelGGL((k_gemm_tn<kTnBK>), grid, dim3(256), 0, st, rows, a, b, A, lda, B, ldb, work,
-                     rps);
+  if (big) {
+    dim3 grid((a + GBM - 1) / GBM, (b + GBN - 1) / GBN, ns);
+    hipLaunchKernelGGL(k_gemm_tn_big, grid, dim3(256), 0, st, rows, a, b, A, lda, B, ldb, work,
+                       rps);
+  } else {
+    dim3 grid((a + TBM - 1) / TBM, (b + TBN - 1) / TBN, ns);
+    hipLaunchKernelGGL((k_gemm_tn<kTnBK>), grid, dim3(256), 0, st, rows, a, b, A, lda, B, ldb,
+                       work, rps);
+  }
   PW_LAUNCH_CHECK();
   const long long ab = (long long)a * b;
   if (ns >= 32)
