@@ -585,6 +585,7 @@ __global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round,
   __shared__ double ca[kJC], cb[kJC];
   __shared__ signed char part[kJC - 1][kJC];
   __shared__ int nrot;
+  __shared__ int any_rot;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   int bp = rr_index(blockIdx.x, round, npb);
@@ -661,13 +662,27 @@ __global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round,
   __syncthreads();
   G[0][tid] = Gp[0][tid] + Gp[1][tid] + Gp[2][tid] + Gp[3][tid];
   W[0][tid] = (tid / kJC == tid % kJC) ? 1.0 : 0.0;
+  if (tid == 0) any_rot = 0;
   __syncthreads();
+  // a pair is rotated only if it is above the threshold in the current
+  // Gram matrix; if no pair of the fresh one is, the sweep below would
+  // leave everything unchanged: skip it
+  const double noise2 = 4.9e-32 * (*fro2);
+  const double thr2 = 4.5e-16 * 4.5e-16 * (double)n;
+  {
+    const int pi_ = tid / kJC, pj_ = tid % kJC;
+    if (pi_ < pj_ && gcol(pj_) < n) {
+      const double al = G[0][pi_ * kJC + pi_], be = G[0][pj_ * kJC + pj_];
+      const double ga = G[0][pi_ * kJC + pj_];
+      if (ga != 0.0 && ga * ga > thr2 * (al * be) && fmin(al, be) >= noise2) any_rot = 1;
+    }
+  }
+  __syncthreads();
+  if (any_rot == 0) return;
   // 2. one cyclic sweep of rotations on the Gram matrix; the rotation of
   //    each pair is formed once (threads 0..7) and read by all.  The
   //    partners of this thread's row and column index in the 15 rounds are
   //    packed four bits each into one register.
-  const double noise2 = 4.9e-32 * (*fro2);
-  const double thr2 = 4.5e-16 * 4.5e-16 * (double)n;
   const int i = tid / kJC, j = tid % kJC;  // this thread's Gram / rotation entry
   unsigned long long packi = 0, packj = 0;
   for (int r = 0; r < kJC - 1; ++r) {
