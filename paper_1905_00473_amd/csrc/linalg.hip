@@ -582,7 +582,6 @@ __global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round,
   __shared__ double Gp[4][kJC * kJC];
   __shared__ double G[2][kJC * kJC];
   __shared__ double W[2][kJC * kJC];
-  __shared__ double ca[kJC], cb[kJC];
   __shared__ signed char part[kJC - 1][kJC];
   __shared__ int nrot;
   __shared__ int any_rot;
@@ -679,73 +678,67 @@ __global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round,
   }
   __syncthreads();
   if (any_rot == 0) return;
-  // 2. one cyclic sweep of rotations on the Gram matrix; the rotation of
-  //    each pair is formed once (threads 0..7) and read by all.  The
-  //    partners of this thread's row and column index in the 15 rounds are
-  //    packed four bits each into one register.
+  // 2. one cyclic sweep of rotations on the Gram matrix.  Thread (i, j)
+  //    forms the rotation of column j's pair (the threads that share a pair
+  //    compute it from the same entries, so they agree bit for bit) and takes
+  //    the one of column i from lane (i mod 4, i) of its own wave, which formed
+  //    it: no second barrier per round.  The partners of this thread's row
+  //    and column index in the 15 rounds are packed four bits each into one
+  //    register.
   const int i = tid / kJC, j = tid % kJC;  // this thread's Gram / rotation entry
+  const int src_i = (lane & ~(kJC - 1)) | i;
   unsigned long long packi = 0, packj = 0;
   for (int r = 0; r < kJC - 1; ++r) {
     packi |= (unsigned long long)part[r][i] << (4 * r);
     packj |= (unsigned long long)part[r][j] << (4 * r);
   }
-  int cur = 0;
+  int cur = 0, myrot = 0;
   for (int r = 0; r < kJC - 1; ++r) {
     const double* Gc = G[cur];
-    if (tid < kJC / 2) {
-      int p = rr_index(tid, r, kJC), q = rr_index(kJC - 1 - tid, r, kJC);
-      if (p > q) {
-        const int t = p;
-        p = q;
-        q = t;
-      }
-      double c = 1.0, sn = 0.0;
-      bool rot = false;
-      if (gcol(q) < n) {
-        const double al = Gc[p * kJC + p], be = Gc[q * kJC + q], ga = Gc[p * kJC + q];
-        if (ga != 0.0 && ga * ga > thr2 * (al * be) && fmin(al, be) >= noise2) {
-          // tan of the angle: t = sgn(d) g / (|d| + sqrt(d^2 + g^2)), d = be - al,
-          // g = 2 ga (the smaller root of t^2 + 2 zeta t - 1 = 0, zeta = d / g);
-          // the hardware reciprocal square root and reciprocal seeds are
-          // refined by Newton steps to full double precision
-          const double d = be - al, g = 2.0 * ga;
-          const double x = fma(d, d, g * g);
-          double y = __builtin_amdgcn_rsq(x);
-          y = y * fma(-0.5 * x * y, y, 1.5);
-          y = y * fma(-0.5 * x * y, y, 1.5);
-          const double m = fabs(d) + x * y;  // |d| + sqrt(d^2 + g^2)
-          double z = __builtin_amdgcn_rcp(m);
-          z = z * fma(-m, z, 2.0);
-          z = z * fma(-m, z, 2.0);
-          const double t = (d >= 0.0 ? g : -g) * z;
-          const double u = fma(t, t, 1.0);
-          double w = __builtin_amdgcn_rsq(u);
-          w = w * fma(-0.5 * u * w, w, 1.5);
-          w = w * fma(-0.5 * u * w, w, 1.5);
-          c = w;
-          sn = w * t;
-          rot = true;
-        }
-      }
-      // column p <- c p - s q ; column q <- s p + c q
-      ca[p] = c;
-      cb[p] = -sn;
-      ca[q] = c;
-      cb[q] = sn;
-      if (rot) atomicAdd(&nrot, 1);
-    }
-    __syncthreads();
-    const int pi = (int)((packi >> (4 * r)) & 15), pj = (int)((packj >> (4 * r)) & 15);
     const double* Wc = W[cur];
+    const int pi = (int)((packi >> (4 * r)) & 15), pj = (int)((packj >> (4 * r)) & 15);
+    const int lo = j < pj ? j : pj, hi = j < pj ? pj : j;
     const double g0 = Gc[i * kJC + j], g1 = Gc[i * kJC + pj], g2 = Gc[pi * kJC + j],
                  g3 = Gc[pi * kJC + pj], w0 = Wc[i * kJC + j], w1 = Wc[i * kJC + pj];
-    const double ai = ca[i], bi = cb[i], aj = ca[j], bj = cb[j];
+    const double al = Gc[lo * (kJC + 1)], be = Gc[hi * (kJC + 1)], ga = Gc[lo * kJC + hi];
+    // the pair (lo, hi) is rotated only if it is above the threshold
+    const bool rot = (gcol(hi) < n) & (ga != 0.0) & (ga * ga > thr2 * (al * be)) &
+                     (fmin(al, be) >= noise2);
+    // the rotation angle phi with tan 2 phi = g / d (|phi| <= pi/4), d = be - al,
+    // g = 2 ga: with rho = sqrt(d^2 + g^2), cos 2 phi = |d| / rho, so
+    // c = cos phi = sqrt(h), h = (1 + |d| / rho) / 2 in [1/2, 1], and
+    // s = sin phi = sgn(d) g / (2 rho c).  Two reciprocal square roots,
+    // 1 / rho and 1 / sqrt(h), each seeded by the hardware instruction and
+    // refined by two Newton steps to full double precision (c^2 + s^2 = 1
+    // to rounding needs both).  Branch-free: the values formed for a pair
+    // that is not rotated are discarded.
+    const double d = be - al, g = 2.0 * ga;
+    const double xx = fma(d, d, g * g);
+    const double hxx = 0.5 * xx;
+    double rr = __builtin_amdgcn_rsq(xx);
+    rr = fma(rr, fma(-hxx * rr, rr, 0.5), rr);
+    rr = fma(rr, fma(-hxx * rr, rr, 0.5), rr);
+    const double h = fma(0.5 * fabs(d), rr, 0.5);
+    const double hh = 0.5 * h;
+    const double sg = (d >= 0.0 ? 0.5 : -0.5) * g * rr;  // sgn(d) g / (2 rho)
+    double w = __builtin_amdgcn_rsq(h);
+    w = fma(w, fma(-hh * w, w, 0.5), w);
+    w = fma(w, fma(-hh * w, w, 0.5), w);
+    const double cs = h * w, sn = sg * w;
+    // column x of the pair (p, q), p < q: x' = a x + b y with
+    // column p <- c p - s q, column q <- s p + c q
+    const double aj = rot ? cs : 1.0;
+    const double bj = rot ? (j == lo ? -sn : sn) : 0.0;
+    const double ai = __shfl(aj, src_i, 64), bi = __shfl(bj, src_i, 64);
+    if (rot && i == j && j == lo) ++myrot;  // one counting thread per pair
     // G' = J^T G J entrywise, W' = W J
     G[cur ^ 1][tid] = ai * aj * g0 + ai * bj * g1 + bi * aj * g2 + bi * bj * g3;
     W[cur ^ 1][tid] = aj * w0 + bj * w1;
     cur ^= 1;
     __syncthreads();
   }
+  if (myrot) atomicAdd(&nrot, myrot);
+  __syncthreads();
   if (nrot == 0) return;
   // 3. H(:, cols) <- B W (B staged), V(:, cols) <- V(:, cols) W, in 16-row
   //    tiles on the matrix cores: A[i][k] = X[tile + i][4t + k] (lane l:
