@@ -703,28 +703,24 @@ __global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round,
     const double al = Gc[lo * (kJC + 1)], be = Gc[hi * (kJC + 1)], ga = Gc[lo * kJC + hi];
     // the pair (lo, hi) is rotated only if it is above the threshold
     const bool rot = (gcol(hi) < n) & (ga != 0.0) & (ga * ga > thr2 * (al * be)) &
-                     (fmin(al, be) >= noise2);
-    // the rotation angle phi with tan 2 phi = g / d (|phi| <= pi/4), d = be - al,
-    // g = 2 ga: with rho = sqrt(d^2 + g^2), cos 2 phi = |d| / rho, so
-    // c = cos phi = sqrt(h), h = (1 + |d| / rho) / 2 in [1/2, 1], and
-    // s = sin phi = sgn(d) g / (2 rho c).  Two reciprocal square roots,
-    // 1 / rho and 1 / sqrt(h), each seeded by the hardware instruction and
-    // refined by two Newton steps to full double precision (c^2 + s^2 = 1
-    // to rounding needs both).  Branch-free: the values formed for a pair
-    // that is not rotated are discarded.
+                     (al >= noise2) & (be >= noise2);
+    // tan of the angle: t = sgn(d) g / (|d| + sqrt(d^2 + g^2)), d = be - al,
+    // g = 2 ga (the smaller root of t^2 + 2 zeta t - 1 = 0, zeta = d / g),
+    // from the hardware reciprocal square root and reciprocal alone: an
+    // angle off by a relative 1e-5 still reduces the pair's inner product by
+    // that factor, and the sweep count does not change.  The rotation stays
+    // orthogonal to rounding whatever t is: c = 1 / sqrt(1 + t^2) is refined
+    // by two Newton steps to full double precision and s = c t.  Branch-free:
+    // the values formed for a pair that is not rotated are discarded.
     const double d = be - al, g = 2.0 * ga;
     const double xx = fma(d, d, g * g);
-    const double hxx = 0.5 * xx;
-    double rr = __builtin_amdgcn_rsq(xx);
-    rr = fma(rr, fma(-hxx * rr, rr, 0.5), rr);
-    rr = fma(rr, fma(-hxx * rr, rr, 0.5), rr);
-    const double h = fma(0.5 * fabs(d), rr, 0.5);
-    const double hh = 0.5 * h;
-    const double sg = (d >= 0.0 ? 0.5 : -0.5) * g * rr;  // sgn(d) g / (2 rho)
-    double w = __builtin_amdgcn_rsq(h);
-    w = fma(w, fma(-hh * w, w, 0.5), w);
-    w = fma(w, fma(-hh * w, w, 0.5), w);
-    const double cs = h * w, sn = sg * w;
+    const double m = fma(xx, __builtin_amdgcn_rsq(xx), fabs(d));  // |d| + sqrt(d^2 + g^2)
+    const double t = (d >= 0.0 ? g : -g) * __builtin_amdgcn_rcp(m);
+    const double u = fma(t, t, 1.0), hu = 0.5 * u;
+    double w = __builtin_amdgcn_rsq(u);
+    w = fma(w, fma(-hu * w, w, 0.5), w);
+    w = fma(w, fma(-hu * w, w, 0.5), w);
+    const double cs = w, sn = w * t;
     // column x of the pair (p, q), p < q: x' = a x + b y with
     // column p <- c p - s q, column q <- s p + c q
     const double aj = rot ? cs : 1.0;
@@ -732,8 +728,8 @@ __global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round,
     const double ai = __shfl(aj, src_i, 64), bi = __shfl(bj, src_i, 64);
     if (rot && i == j && j == lo) ++myrot;  // one counting thread per pair
     // G' = J^T G J entrywise, W' = W J
-    G[cur ^ 1][tid] = ai * aj * g0 + ai * bj * g1 + bi * aj * g2 + bi * bj * g3;
-    W[cur ^ 1][tid] = aj * w0 + bj * w1;
+    G[cur ^ 1][tid] = ai * fma(bj, g1, aj * g0) + bi * fma(bj, g3, aj * g2);
+    W[cur ^ 1][tid] = fma(bj, w1, aj * w0);
     cur ^= 1;
     __syncthreads();
   }
