@@ -34,61 +34,94 @@ inline unsigned nblocks(long long n, int tb = kTB) { return (unsigned)((n + tb -
 //   the 16x16 result lives in 4 doubles per lane: D[4*v + l/16][l%16]
 //   (rows interleaved across the four lane groups).
 // ---------------------------------------------------------------------------
+// Tile sizes: 64 x 64 (4 waves of 32 x 32) for narrow results, 128 x 128
+// (4 waves of 64 x 64) for wide ones; BK rows of the contraction per step.
 constexpr int TBM = 64, TBN = 64;
+constexpr int GBM = 128, GBN = 128;
+constexpr int GBK = 16, GPAD = 4;
 
-template <int BK>
-__global__ __launch_bounds__(256) void k_gemm_tn(long long rows, int a, int b, const double* A,
+// Split-K partial of C = A^T B (A: rows x a, B: rows x b, column-major):
+// TM x TN tiles of the a x b result, rows split over blockIdx.z; each
+// partial goes to part[z] (a x b, column-major).  The matrix cores compute
+// tiles of C^T (operand a from B, operand b from A), so that in the result
+// layout D[4v + l/16][l%16] the lane index l%16 runs along the rows of C and
+// each group of 16 lanes stores 128 contiguous bytes.  The next step's global
+// loads are issued before the current step's MFMAs (two LDS buffers).
+template <int TM, int TN, int BK>
+__global__ __launch_bounds__(256, 2) void k_gemm_tn(long long rows, int a, int b, const double* A,
                                                   long long lda, const double* B, long long ldb,
                                                   double* part, long long rows_per_split) {
-  __shared__ double As[BK][TBM + 1];
-  __shared__ double Bs[BK][TBN + 1];
-  const int m0 = blockIdx.x * TBM, n0 = blockIdx.y * TBN;
+  constexpr int SJ = TM / 32, SI = TN / 32;  // 16 x 16 sub-tiles per wave along m, n
+  constexpr int CS = 256 / BK;               // columns per loader pass
+  constexpr int QA = TM / CS, QB = TN / CS;  // loads per thread per step
+  __shared__ double As[2][BK][TM + GPAD];
+  __shared__ double Bs[2][BK][TN + GPAD];
+  const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
   const long long r0 = (long long)blockIdx.z * rows_per_split;
   const long long r1 = std::min(rows, r0 + rows_per_split);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-  v4d acc[2][2];
+  const int wm = (wave & 1) * (TM / 2), wn = (wave >> 1) * (TN / 2);
+  v4d acc[SI][SJ];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < SI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
-  const int kk_ld = tid % BK;
-  const int cc_ld = tid / BK;
-  constexpr int CSTEP = 256 / BK;
-  for (long long k0 = r0; k0 < r1; k0 += BK) {
-    const long long r = k0 + kk_ld;
-    const bool rok = r < r1;
+    for (int j = 0; j < SJ; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int lk = tid % BK, lc = tid / BK;  // row lk of the step, columns lc + CS q
+  double ra[QA], rb[QB];
+  auto load = [&](long long k0) {
+    const long long r = k0 + lk;
+    const bool ok = r < r1;
 #pragma unroll
-    for (int j = 0; j < TBM / CSTEP; ++j) {
-      const int cc = cc_ld + CSTEP * j;
-      As[kk_ld][cc] = (rok && m0 + cc < a) ? A[r + (long long)(m0 + cc) * lda] : 0.0;
-      Bs[kk_ld][cc] = (rok && n0 + cc < b) ? B[r + (long long)(n0 + cc) * ldb] : 0.0;
+    for (int q = 0; q < QA; ++q) {
+      const int c = lc + CS * q;
+      ra[q] = (ok && m0 + c < a) ? A[r + (long long)(m0 + c) * lda] : 0.0;
     }
-    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int c = lc + CS * q;
+      rb[q] = (ok && n0 + c < b) ? B[r + (long long)(n0 + c) * ldb] : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < QA; ++q) As[buf][lk][lc + CS * q] = ra[q];
+#pragma unroll
+    for (int q = 0; q < QB; ++q) Bs[buf][lk][lc + CS * q] = rb[q];
+  };
+  load(r0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (long long k0 = r0; k0 < r1; k0 += BK) {
+    const bool more = k0 + BK < r1;
+    if (more) load(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      double av[2], bv[2];
+      double av[SI], bv[SJ];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) av[i] = As[kk + lane / 16][wm + i * 16 + lane % 16];
+      for (int i = 0; i < SI; ++i) av[i] = Bs[buf][kk + (lane >> 4)][wn + 16 * i + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) bv[j] = Bs[kk + lane / 16][wn + j * 16 + lane % 16];
+      for (int j = 0; j < SJ; ++j) bv[j] = As[buf][kk + (lane >> 4)][wm + 16 * j + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < SI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < SJ; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
+    if (more) store(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
   double* P = part + (long long)blockIdx.z * a * b;
+  // acc[i][j][v] = C[m0 + wm + 16 j + l%16][n0 + wn + 16 i + 4 v + l/16]
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < SI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < SJ; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int m = m0 + wm + i * 16 + 4 * v + lane / 16;
-        const int n = n0 + wn + j * 16 + lane % 16;
+        const int m = m0 + wm + 16 * j + (lane & 15);
+        const int n = n0 + wn + 16 * i + 4 * v + (lane >> 4);
         if (m < a && n < b) P[m + (long long)n * a] = acc[i][j][v];
       }
 }
@@ -124,129 +157,68 @@ __global__ __launch_bounds__(256) void k_reduce_splits_wave(const double* part, 
   }
 }
 
-template <int BK>
-__global__ __launch_bounds__(256) void k_gemm_nn(long long rows, int n, int k, double alpha,
+// C = alpha A B + beta C (A: rows x k, B: k x n, column-major): TM x TN
+// tiles of C, 4 waves of TM/2 x TN/2, C^T tiles on the matrix cores for
+// contiguous stores and the next k-step prefetched, as in k_gemm_tn.
+template <int TM, int TN, int BK>
+__global__ __launch_bounds__(256, 2) void k_gemm_nn(long long rows, int n, int k, double alpha,
                                                   const double* A, long long lda, const double* B,
                                                   long long ldb, double beta, double* C,
                                                   long long ldc) {
-  __shared__ double As[BK][TBM + 1];
-  __shared__ double Bs[BK][TBN + 1];
-  const long long m0 = (long long)blockIdx.x * TBM;
-  const int n0 = blockIdx.y * TBN;
+  constexpr int SJ = TM / 32, SI = TN / 32;
+  constexpr int KA = 256 / TM, QA = BK / KA;  // A: row am, k = ak + KA q
+  constexpr int NB = 256 / BK, QB = TN / NB;  // B: k = bk, column bn + NB q
+  __shared__ double As[2][BK][TM + GPAD];
+  __shared__ double Bs[2][BK][TN + GPAD];
+  const long long m0 = (long long)blockIdx.x * TM;
+  const int n0 = blockIdx.y * TN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-  v4d acc[2][2];
+  const int wm = (wave & 1) * (TM / 2), wn = (wave >> 1) * (TN / 2);
+  v4d acc[SI][SJ];  // [n sub-tile][m sub-tile]
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < SI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
-  const int am = tid % TBM, ak = tid / TBM;  // A tile: 64 rows x BK
-  const int bk = tid % BK, bn = tid / BK;    // B tile: BK x 64
-  for (int k0 = 0; k0 < k; k0 += BK) {
-#pragma unroll
-    for (int j = 0; j < BK / (256 / TBM); ++j) {
-      const int kk = ak + (256 / TBM) * j;
-      const long long r = m0 + am;
-      As[kk][am] = (r < rows && k0 + kk < k) ? A[r + (long long)(k0 + kk) * lda] : 0.0;
-    }
-#pragma unroll
-    for (int j = 0; j < TBN / (256 / BK); ++j) {
-      const int nn = bn + (256 / BK) * j;
-      Bs[bk][nn] = (k0 + bk < k && n0 + nn < n) ? B[(k0 + bk) + (long long)(n0 + nn) * ldb] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      double av[2], bv[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) av[i] = As[kk + lane / 16][wm + i * 16 + lane % 16];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) bv[j] = Bs[kk + lane / 16][wn + j * 16 + lane % 16];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const long long m = m0 + wm + i * 16 + 4 * v + lane / 16;
-        const int nn = n0 + wn + j * 16 + lane % 16;
-        if (m < rows && nn < n) {
-          double* c = C + m + (long long)nn * ldc;
-          *c = beta == 0.0 ? alpha * acc[i][j][v] : alpha * acc[i][j][v] + beta * (*c);
-        }
-      }
-}
-
-// Large C = alpha A B + beta C (A: rows x k, B: k x n, column-major):
-// 128 x 128 tiles, 4 waves of 64 x 64.  The MFMA computes tiles of C^T
-// (operand a from B, operand b from A) so that in the result layout
-// D[4v + l/16][l%16] the lane index l%16 runs along the rows of C and each
-// group of 16 lanes stores 128 contiguous bytes.  The next k-step's global
-// loads are issued before the current step's MFMAs (two LDS buffers).
-constexpr int GBM = 128, GBN = 128, GBK = 16, GPAD = 4;
-
-__global__ __launch_bounds__(256) void k_gemm_nn_big(long long rows, int n, int k, double alpha,
-                                                      const double* A, long long lda,
-                                                      const double* B, long long ldb, double beta,
-                                                      double* C, long long ldc) {
-  __shared__ double As[2][GBK][GBM + GPAD];
-  __shared__ double Bs[2][GBK][GBN + GPAD];
-  const long long m0 = (long long)blockIdx.x * GBM;
-  const int n0 = blockIdx.y * GBN;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
-  v4d acc[4][4];  // [n sub-tile][m sub-tile]
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
-  // loader coordinates: A tile 128 x 16 (8 per thread), B tile 16 x 128
-  const int am = tid & 127, ak = tid >> 7;  // k = ak + 2 q
-  const int bk = tid & 15, bn = tid >> 4;   // n = bn + 16 q
-  double ra[8], rb[8];
+    for (int j = 0; j < SJ; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int am = tid % TM, ak = tid / TM;
+  const int bk = tid % BK, bn = tid / BK;
+  double ra[QA], rb[QB];
   auto load = [&](int k0) {
     const long long r = m0 + am;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int kk = k0 + ak + 2 * q;
+    for (int q = 0; q < QA; ++q) {
+      const int kk = k0 + ak + KA * q;
       ra[q] = (r < rows && kk < k) ? A[r + (long long)kk * lda] : 0.0;
-      const int nn = n0 + bn + 16 * q;
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int nn = n0 + bn + NB * q;
       rb[q] = (k0 + bk < k && nn < n) ? B[(k0 + bk) + (long long)nn * ldb] : 0.0;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      As[buf][ak + 2 * q][am] = ra[q];
-      Bs[buf][bk][bn + 16 * q] = rb[q];
-    }
+    for (int q = 0; q < QA; ++q) As[buf][ak + KA * q][am] = ra[q];
+#pragma unroll
+    for (int q = 0; q < QB; ++q) Bs[buf][bk][bn + NB * q] = rb[q];
   };
   load(0);
   store(0);
   __syncthreads();
   int buf = 0;
-  for (int k0 = 0; k0 < k; k0 += GBK) {
-    const bool more = k0 + GBK < k;
-    if (more) load(k0 + GBK);
+  for (int k0 = 0; k0 < k; k0 += BK) {
+    const bool more = k0 + BK < k;
+    if (more) load(k0 + BK);
 #pragma unroll
-    for (int kk = 0; kk < GBK; kk += 4) {
-      double av[4], bv[4];
+    for (int kk = 0; kk < BK; kk += 4) {
+      double av[SI], bv[SJ];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = Bs[buf][kk + (lane >> 4)][wn + 16 * i + (lane & 15)];
+      for (int i = 0; i < SI; ++i) av[i] = Bs[buf][kk + (lane >> 4)][wn + 16 * i + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = As[buf][kk + (lane >> 4)][wm + 16 * j + (lane & 15)];
+      for (int j = 0; j < SJ; ++j) bv[j] = As[buf][kk + (lane >> 4)][wm + 16 * j + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < SI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < SJ; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
     if (more) store(buf ^ 1);
@@ -255,9 +227,9 @@ __global__ __launch_bounds__(256) void k_gemm_nn_big(long long rows, int n, int 
   }
   // acc[i][j][v] = C[m0 + wm + 16 j + l%16][n0 + wn + 16 i + 4 v + l/16]
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < SI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < SJ; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const long long m = m0 + wm + 16 * j + (lane & 15);
@@ -266,85 +238,6 @@ __global__ __launch_bounds__(256) void k_gemm_nn_big(long long rows, int n, int 
           double* c = C + m + (long long)nn * ldc;
           *c = beta == 0.0 ? alpha * acc[i][j][v] : alpha * acc[i][j][v] + beta * (*c);
         }
-      }
-}
-
-// Large split-K partial of C = A^T B (A: rows x a, B: rows x b,
-// column-major): 128 x 128 tiles of the a x b result, rows split over
-// blockIdx.z; each partial goes to part[z] (a x b, column-major).  Same
-// structure as k_gemm_nn_big: tiles of C^T on the matrix cores (operand a
-// from B, operand b from A) for contiguous stores, next k-step prefetched.
-__global__ __launch_bounds__(256) void k_gemm_tn_big(long long rows, int a, int b,
-                                                      const double* A, long long lda,
-                                                      const double* B, long long ldb,
-                                                      double* part, long long rows_per_split) {
-  __shared__ double As[2][GBK][GBM + GPAD];
-  __shared__ double Bs[2][GBK][GBN + GPAD];
-  const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
-  const long long r0 = (long long)blockIdx.z * rows_per_split;
-  const long long r1 = std::min(rows, r0 + rows_per_split);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
-  v4d acc[4][4];  // [n sub-tile][m sub-tile]
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
-  // loader: 16 rows x 128 columns of A and of B, 8 values each per thread
-  const int lk = tid & 15, lc = tid >> 4;  // column = lc + 16 q
-  double ra[8], rb[8];
-  auto load = [&](long long k0) {
-    const long long r = k0 + lk;
-    const bool ok = r < r1;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int c = lc + 16 * q;
-      ra[q] = (ok && m0 + c < a) ? A[r + (long long)(m0 + c) * lda] : 0.0;
-      rb[q] = (ok && n0 + c < b) ? B[r + (long long)(n0 + c) * ldb] : 0.0;
-    }
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      As[buf][lk][lc + 16 * q] = ra[q];
-      Bs[buf][lk][lc + 16 * q] = rb[q];
-    }
-  };
-  load(r0);
-  store(0);
-  __syncthreads();
-  int buf = 0;
-  for (long long k0 = r0; k0 < r1; k0 += GBK) {
-    const bool more = k0 + GBK < r1;
-    if (more) load(k0 + GBK);
-#pragma unroll
-    for (int kk = 0; kk < GBK; kk += 4) {
-      double av[4], bv[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = Bs[buf][kk + (lane >> 4)][wn + 16 * i + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = As[buf][kk + (lane >> 4)][wm + 16 * j + (lane & 15)];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
-    }
-    if (more) store(buf ^ 1);
-    __syncthreads();
-    buf ^= 1;
-  }
-  double* P = part + (long long)blockIdx.z * a * b;
-  // acc[i][j][v] = C[m0 + wm + 16 j + l%16][n0 + wn + 16 i + 4 v + l/16]
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int m = m0 + wm + 16 * j + (lane & 15);
-        const int n = n0 + wn + 16 * i + 4 * v + (lane >> 4);
-        if (m < a && n < b) P[m + (long long)n * a] = acc[i][j][v];
       }
 }
 
@@ -904,8 +797,6 @@ bool debug_jacobi() {
   static const bool on = getenv("PW_DEBUG_JACOBI") != nullptr;
   return on;
 }
-constexpr int kTnBK = 32;
-constexpr int kNnBK = 16;
 
 // large results use the 128 x 128 tile kernel with about kBigTarget
 // workgroups (the scratch bound below covers both schemes)
@@ -916,7 +807,7 @@ bool tn_big(long long rows, int a, int b) {
 
 int tn_splits(long long rows, int a, int b) {
   const bool big = tn_big(rows, a, b);
-  const int bm = big ? GBM : TBM, bn = big ? GBN : TBN, bk = big ? GBK : kTnBK;
+  const int bm = big ? GBM : TBM, bn = big ? GBN : TBN, bk = GBK;
   const long long tiles = (long long)((a + bm - 1) / bm) * ((b + bn - 1) / bn);
   const long long target = big ? kBigTarget : kSplitTarget;
   long long s = (target + tiles - 1) / tiles;
@@ -958,18 +849,17 @@ void gemm_tn(long long rows, int a, int b, double alpha, const double* A, long l
   }
   const bool big = tn_big(rows, a, b);
   const int splits = tn_splits(rows, a, b);
-  const int bk = big ? GBK : kTnBK;
   long long rps = (rows + splits - 1) / splits;
-  rps = (rps + bk - 1) / bk * bk;
+  rps = (rps + GBK - 1) / GBK * GBK;
   const int ns = (int)((rows + rps - 1) / rps);
   if (big) {
     dim3 grid((a + GBM - 1) / GBM, (b + GBN - 1) / GBN, ns);
-    hipLaunchKernelGGL(k_gemm_tn_big, grid, dim3(256), 0, st, rows, a, b, A, lda, B, ldb, work,
-                       rps);
+    hipLaunchKernelGGL((k_gemm_tn<GBM, GBN, GBK>), grid, dim3(256), 0, st, rows, a, b, A, lda, B,
+                       ldb, work, rps);
   } else {
     dim3 grid((a + TBM - 1) / TBM, (b + TBN - 1) / TBN, ns);
-    hipLaunchKernelGGL((k_gemm_tn<kTnBK>), grid, dim3(256), 0, st, rows, a, b, A, lda, B, ldb,
-                       work, rps);
+    hipLaunchKernelGGL((k_gemm_tn<TBM, TBN, GBK>), grid, dim3(256), 0, st, rows, a, b, A, lda, B,
+                       ldb, work, rps);
   }
   PW_LAUNCH_CHECK();
   const long long ab = (long long)a * b;
@@ -999,14 +889,14 @@ void gemm_nn(long long rows, int n, int k, double alpha, const double* A, long l
   }
   if (n > TBN && rows >= GBM && !getenv("PW_GEMM_SMALL_TILES")) {
     dim3 grid((unsigned)((rows + GBM - 1) / GBM), (n + GBN - 1) / GBN);
-    hipLaunchKernelGGL(k_gemm_nn_big, grid, dim3(256), 0, st, rows, n, k, alpha, A, lda, B, ldb,
-                       beta, C, ldc);
+    hipLaunchKernelGGL((k_gemm_nn<GBM, GBN, GBK>), grid, dim3(256), 0, st, rows, n, k, alpha, A,
+                       lda, B, ldb, beta, C, ldc);
     PW_LAUNCH_CHECK();
     return;
   }
   dim3 grid((unsigned)((rows + TBM - 1) / TBM), (n + TBN - 1) / TBN);
-  hipLaunchKernelGGL((k_gemm_nn<kNnBK>), grid, dim3(256), 0, st, rows, n, k, alpha, A, lda, B, ldb,
-                     beta, C, ldc);
+  hipLaunchKernelGGL((k_gemm_nn<TBM, TBN, GBK>), grid, dim3(256), 0, st, rows, n, k, alpha, A,
+                     lda, B, ldb, beta, C, ldc);
   PW_LAUNCH_CHECK();
 }
 
