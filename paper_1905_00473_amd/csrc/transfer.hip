@@ -291,6 +291,99 @@ __global__ void k_dft_axis(const void* inp, long long s_hi, long long s_lo, int 
   }
 }
 
+// The same transform for a power-of-two length n <= kFftTile by the
+// radix-2 Stockham algorithm (self-sorting, out of place between two LDS
+// buffers): a workgroup takes kFftTile / n consecutive lines, loads them
+// with consecutive lanes on consecutive addresses (along the line when it
+// is contiguous, across lines otherwise), runs the log2(n) butterfly stages
+// in LDS and writes the lines back the same way.  Stage s combines
+// transforms of length ns = 2^s: for butterfly j < n/2, k = j mod ns,
+// v0 = a[j], v1 = a[j + n/2] w^(k n / (2 ns)), and b[2 ns (j / ns) + k] =
+// v0 + v1, b[... + ns] = v0 - v1 (w the n-th root of unity of the table,
+// conjugated for the inverse).  O(n log n) operations per line instead of
+// O(n^2); the result is in natural order.
+constexpr int kFftTile = 2048;  // complex values per workgroup
+
+template <bool IN_REAL, bool OUT_REAL, bool INV>
+__global__ __launch_bounds__(256) void k_fft_axis(const void* inp, long long s_hi, long long s_lo,
+                                                  int sub, long long s_in_c, void* outp,
+                                                  long long s_out, const double2* tw, int outer,
+                                                  int n, int log2n, int inner, int nbatch,
+                                                  double scale) {
+  __shared__ double2 buf[2][kFftTile];
+  const int L = kFftTile / n;  // lines of this workgroup
+  const int nlines = nbatch * outer * inner;
+  const int l0 = blockIdx.x * L;
+  const int tid = threadIdx.x;
+  // element e of the tile: (line, j); lanes run along j for contiguous lines
+  auto coords = [&](int e, int& line, int& j) {
+    if (inner == 1) {
+      line = e >> log2n;
+      j = e & (n - 1);
+    } else {
+      line = e % L;
+      j = e / L;
+    }
+  };
+  auto offset = [&](int gl, int& b) -> long long {
+    const int i = gl % inner;
+    const int bo = gl / inner;
+    const int o = bo % outer;
+    b = bo / outer;
+    return (long long)o * n * inner + i;
+  };
+  for (int e = tid; e < kFftTile; e += 256) {
+    int line, j;
+    coords(e, line, j);
+    const int gl = l0 + line;
+    double2 v = make_double2(0.0, 0.0);
+    if (gl < nlines) {
+      int b;
+      const long long off = offset(gl, b) + (long long)j * inner;
+      if (IN_REAL) {
+        v.x = ((const double*)inp)[(long long)(b / sub) * s_hi + (long long)(b % sub) * s_lo + off];
+      } else {
+        v = ((const double2*)inp)[(long long)b * s_in_c + off];
+      }
+    }
+    buf[0][line * n + j] = v;
+  }
+  __syncthreads();
+  const int half = n >> 1;
+  int cur = 0;
+  for (int s = 0; s < log2n; ++s) {
+    const int ns = 1 << s;
+    const double2* a = buf[cur];
+    double2* o = buf[cur ^ 1];
+    for (int e = tid; e < kFftTile / 2; e += 256) {
+      const int line = e / half, j = e - line * half;
+      const int k = j & (ns - 1);
+      const double2 w = tw[k << (log2n - 1 - s)];
+      const double wy = INV ? -w.y : w.y;
+      const double2 v0 = a[line * n + j], x1 = a[line * n + j + half];
+      const double2 v1 = make_double2(x1.x * w.x - x1.y * wy, x1.x * wy + x1.y * w.x);
+      const int d = line * n + ((j - k) << 1) + k;
+      o[d] = make_double2(v0.x + v1.x, v0.y + v1.y);
+      o[d + ns] = make_double2(v0.x - v1.x, v0.y - v1.y);
+    }
+    cur ^= 1;
+    __syncthreads();
+  }
+  for (int e = tid; e < kFftTile; e += 256) {
+    int line, j;
+    coords(e, line, j);
+    const int gl = l0 + line;
+    if (gl >= nlines) continue;
+    int b;
+    const long long oi = offset(gl, b) + (long long)j * inner;
+    const double2 v = buf[cur][line * n + j];
+    if (OUT_REAL)
+      ((double*)outp)[(long long)b * s_out + oi] = v.x * scale;
+    else
+      ((double2*)outp)[(long long)b * s_out + oi] = v;
+  }
+}
+
 __device__ __forceinline__ double wavenumber(int k, int n, double len) {
   const int f = (k < (n + 1) / 2) ? k : k - n;
   return 2.0 * 3.14159265358979323846 * (double)f / len;
@@ -558,6 +651,29 @@ std::vector<double> dft_table(int n) {
   return tw;
 }
 
+// one transform pass along an axis of length n: the FFT for powers of two
+// up to kFftTile, the direct sum otherwise
+template <bool IN_REAL, bool OUT_REAL, bool INV>
+void dft_pass(const void* in, long long s_hi, long long s_lo, int sub, long long s_in_c,
+              void* out, long long s_out, const double* tw, int outer, int n, int inner,
+              int nbatch, double scale, hipStream_t st) {
+  int log2n = 0;
+  while ((1 << log2n) < n) ++log2n;
+  if (n >= 2 && (1 << log2n) == n && n <= kFftTile) {
+    const long long lines = (long long)nbatch * outer * inner;
+    const int L = kFftTile / n;
+    hipLaunchKernelGGL((k_fft_axis<IN_REAL, OUT_REAL, INV>), dim3((unsigned)((lines + L - 1) / L)),
+                       dim3(256), 0, st, in, s_hi, s_lo, sub, s_in_c, out, s_out,
+                       (const double2*)tw, outer, n, log2n, inner, nbatch, scale);
+  } else {
+    const long long total = (long long)outer * n * inner * nbatch;
+    hipLaunchKernelGGL((k_dft_axis<IN_REAL, OUT_REAL, INV>), dim3(nblocks(total)), dim3(kTB), 0,
+                       st, in, s_hi, s_lo, sub, s_in_c, out, s_out, (const double2*)tw, outer, n,
+                       inner, nbatch, scale);
+  }
+  PW_LAUNCH_CHECK();
+}
+
 void grad2func_cols(const Grid& c, const double* const* dft, const double* q, long long ldq,
                     const double* sums, double* w, long long ldw, int ncols, double* ctmp,
                     hipStream_t st) {
@@ -569,29 +685,16 @@ void grad2func_cols(const Grid& c, const double* const* dft, const double* q, lo
   double2* B = A + nc * d * ncols;
   const int nb = d * ncols;
   // forward x (real in): batch b = col*d + a
-  {
-    const long long n = nc * nb;
-    hipLaunchKernelGGL((k_dft_axis<true, false, false>), dim3(nblocks(n)), dim3(kTB), 0, st,
-                       (const void*)q, ldq, nc, d, 0LL, (void*)A, nc, (const double2*)dft[0],
-                       ny * nz, nx, 1, nb, 1.0);
-    PW_LAUNCH_CHECK();
-  }
+  dft_pass<true, false, false>(q, ldq, nc, d, 0LL, A, nc, dft[0], ny * nz, nx, 1, nb, 1.0, st);
   double2* cur = A;
   double2* oth = B;
   if (d >= 2) {
-    const long long n = nc * nb;
-    hipLaunchKernelGGL((k_dft_axis<false, false, false>), dim3(nblocks(n)), dim3(kTB), 0, st,
-                       (const void*)cur, 0LL, 0LL, 1, nc, (void*)oth, nc, (const double2*)dft[1],
-                       nz, ny, nx, nb, 1.0);
-    PW_LAUNCH_CHECK();
+    dft_pass<false, false, false>(cur, 0LL, 0LL, 1, nc, oth, nc, dft[1], nz, ny, nx, nb, 1.0, st);
     std::swap(cur, oth);
   }
   if (d >= 3) {
-    const long long n = nc * nb;
-    hipLaunchKernelGGL((k_dft_axis<false, false, false>), dim3(nblocks(n)), dim3(kTB), 0, st,
-                       (const void*)cur, 0LL, 0LL, 1, nc, (void*)oth, nc, (const double2*)dft[2],
-                       1, nz, nx * ny, nb, 1.0);
-    PW_LAUNCH_CHECK();
+    dft_pass<false, false, false>(cur, 0LL, 0LL, 1, nc, oth, nc, dft[2], 1, nz, nx * ny, nb, 1.0,
+                                  st);
     std::swap(cur, oth);
   }
   {
@@ -603,35 +706,21 @@ void grad2func_cols(const Grid& c, const double* const* dft, const double* q, lo
   }
   // inverse passes; the last one writes the real part / nc into w
   const double scale = 1.0 / (double)nc;
-  const long long n = nc * ncols;
   if (d == 1) {
-    hipLaunchKernelGGL((k_dft_axis<false, true, true>), dim3(nblocks(n)), dim3(kTB), 0, st,
-                       (const void*)cur, 0LL, 0LL, 1, nc, (void*)w, ldw, (const double2*)dft[0], 1,
-                       nx, 1, ncols, scale);
-    PW_LAUNCH_CHECK();
+    dft_pass<false, true, true>(cur, 0LL, 0LL, 1, nc, w, ldw, dft[0], 1, nx, 1, ncols, scale, st);
     return;
   }
-  hipLaunchKernelGGL((k_dft_axis<false, false, true>), dim3(nblocks(n)), dim3(kTB), 0, st,
-                     (const void*)cur, 0LL, 0LL, 1, nc, (void*)oth, nc, (const double2*)dft[0],
-                     ny * nz, nx, 1, ncols, 1.0);
-  PW_LAUNCH_CHECK();
+  dft_pass<false, false, true>(cur, 0LL, 0LL, 1, nc, oth, nc, dft[0], ny * nz, nx, 1, ncols, 1.0,
+                               st);
   std::swap(cur, oth);
   if (d == 2) {
-    hipLaunchKernelGGL((k_dft_axis<false, true, true>), dim3(nblocks(n)), dim3(kTB), 0, st,
-                       (const void*)cur, 0LL, 0LL, 1, nc, (void*)w, ldw, (const double2*)dft[1],
-                       nz, ny, nx, ncols, scale);
-    PW_LAUNCH_CHECK();
+    dft_pass<false, true, true>(cur, 0LL, 0LL, 1, nc, w, ldw, dft[1], nz, ny, nx, ncols, scale, st);
     return;
   }
-  hipLaunchKernelGGL((k_dft_axis<false, false, true>), dim3(nblocks(n)), dim3(kTB), 0, st,
-                     (const void*)cur, 0LL, 0LL, 1, nc, (void*)oth, nc, (const double2*)dft[1], nz,
-                     ny, nx, ncols, 1.0);
-  PW_LAUNCH_CHECK();
+  dft_pass<false, false, true>(cur, 0LL, 0LL, 1, nc, oth, nc, dft[1], nz, ny, nx, ncols, 1.0, st);
   std::swap(cur, oth);
-  hipLaunchKernelGGL((k_dft_axis<false, true, true>), dim3(nblocks(n)), dim3(kTB), 0, st,
-                     (const void*)cur, 0LL, 0LL, 1, nc, (void*)w, ldw, (const double2*)dft[2], 1,
-                     nz, nx * ny, ncols, scale);
-  PW_LAUNCH_CHECK();
+  dft_pass<false, true, true>(cur, 0LL, 0LL, 1, nc, w, ldw, dft[2], 1, nz, nx * ny, ncols, scale,
+                              st);
 }
 
 void lambda_adjoint_cols(const Grid& c, const double* in, long long ldi, const double* cc,
