@@ -170,11 +170,24 @@ def test_interp_add_parity(dim, dtype):
 # ---------------------------------------------------------------------------
 # Lambda^dag (Algorithm 2)
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("dim", [1, 2, 3])
-def test_grad2func_parity(dim):
+G2F_CASES = {
+    # coarse axes of power-of-two length go through the FFT, the others
+    # through the direct transform
+    "1d_fft": lambda: W.wave1d(),
+    "2d_direct": lambda: W.disc2d(n=72, N=4, K=2, T=0.25),
+    "2d_fft": lambda: W.disc2d(n=128, N=4, K=2, T=0.25),
+    "2d_mixed": lambda: W.misfit_case((40, 64), ratio=4, N=4, K=1, m_fine=16,
+                                      m_coarse=4)[0],
+    "3d_direct": lambda: W.layers3d(n=40, N=4, K=2, T=0.06),
+    "3d_fft": lambda: W.layers3d(n=32, N=4, K=2, T=0.06),
+}
+
+
+@pytest.mark.parametrize("case", list(G2F_CASES))
+def test_grad2func_parity(case):
     import torch
-    w = {1: lambda: W.wave1d(), 2: lambda: W.disc2d(n=72, N=4, K=2, T=0.25),
-         3: lambda: W.layers3d(n=40, N=4, K=2, T=0.06)}[dim]()
+    w = G2F_CASES[case]()
+    dim = len(w.shape)
     s, Q = _solver(w, dtype="f64")
     rng = np.random.default_rng(5)
     n = 3
