@@ -189,12 +189,37 @@ __global__ __launch_bounds__(256) void k_interp_axis_rb(const Tin* in, long long
   for (int a = 0; a < RJ; ++a)
 #pragma unroll
     for (int s = 0; s < R; ++s) acc[a][s] = 0.0;
-  for (int m = 0; m < nc; ++m) {
+  // acc[a][s] += w_s[(J0 + a - m) mod nc] x_m.  Over RJ consecutive m the
+  // index J0 + a - m takes 2 RJ - 1 values, so a block of RJ inputs needs
+  // 2 RJ - 1 weights per phase from LDS instead of RJ^2.
+  int m = 0;
+  for (; m + RJ <= nc; m += RJ) {
+    double x[RJ];
+#pragma unroll
+    for (int u = 0; u < RJ; ++u) x[u] = (double)src[(long long)(m + u) * inner];
+#pragma unroll
+    for (int s = 1; s < R; ++s) {
+      double w[2 * RJ - 1];  // w[k] = w_s[(J0 - m + k - (RJ - 1)) mod nc]
+#pragma unroll
+      for (int k = 0; k < 2 * RJ - 1; ++k) {
+        int dd = J0 - m + k - (RJ - 1);
+        dd += dd < 0 ? nc : 0;
+        dd -= dd >= nc ? nc : 0;
+        w[k] = wt[s * nc + dd];
+      }
+#pragma unroll
+      for (int u = 0; u < RJ; ++u)
+#pragma unroll
+        for (int a = 0; a < RJ; ++a) acc[a][s] += w[a - u + RJ - 1] * x[u];
+    }
+  }
+  for (; m < nc; ++m) {
     const double x = (double)src[(long long)m * inner];
 #pragma unroll
     for (int a = 0; a < RJ; ++a) {
       int dd = J0 + a - m;
       if (dd < 0) dd += nc;
+      if (dd >= nc) dd -= nc;
 #pragma unroll
       for (int s = 1; s < R; ++s) acc[a][s] += wt[s * nc + dd] * x;
     }
