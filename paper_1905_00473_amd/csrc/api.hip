@@ -179,10 +179,16 @@ struct Prob {
   double* ctmp = nullptr;   // complex DFT scratch
   double* itmp = nullptr;   // interpolation scratch
   double* gwork = nullptr;  // split-K partials
+  double* gwork2 = nullptr; // split-K partials of the G branch of Algorithm 1
   size_t gwork_elems = 0;
   double* red = nullptr;    // reduction partials
   double* res = nullptr;    // per-iteration [||F - Omega G||^2, ||F||^2]
-  OrthScratch os;
+  OrthScratch os, os2;  // orthonormalisation scratch of the F and the G branch
+  // Algorithm 1 treats the F-side and the G-side data independently up to
+  // the core matrix: the G branch runs on a second stream, forked from and
+  // joined to the caller's stream with events
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   int cur = 0;    // which of the ping-pong corrector buffers is current
   int r = 0;      // current rank
   int k_done = 0;
@@ -195,6 +201,13 @@ struct Prob {
   std::unique_ptr<Tape> tape;
   DevBuf stage_rec, stage_seed, stage_out;
   double adj_ms[2] = {0, 0};  // last taped forward, last backward
+  ~Prob() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    if (join_ev) (void)hipEventDestroy(join_ev);
+    if (side) (void)hipStreamDestroy(side);
+  }
 };
 
 }  // namespace
@@ -403,7 +416,18 @@ void setup(Prob& pr, const pw_problem& P) {
   pr.os.Q1 = m.get_n<double>(rows * N);
   pr.os.work = pr.gwork;
   pr.os.work_elems = pr.gwork_elems;
+  pr.gwork2 = m.get_n<double>((long long)pr.gwork_elems);
+  pr.os2.gram = m.get_n<double>((long long)N * N);
+  pr.os2.T = m.get_n<double>((long long)N * N);
+  pr.os2.R1 = m.get_n<double>((long long)N * N);
+  pr.os2.R2 = m.get_n<double>((long long)N * N);
+  pr.os2.Q1 = m.get_n<double>(rows * N);
+  pr.os2.work = pr.gwork2;
+  pr.os2.work_elems = pr.gwork_elems;
   for (int i = 0; i < 4; ++i) PW_HIP(hipEventCreate(&pr.ev[i]));
+  PW_HIP(hipStreamCreateWithFlags(&pr.side, hipStreamNonBlocking));
+  PW_HIP(hipEventCreateWithFlags(&pr.fork_ev, hipEventDisableTiming));
+  PW_HIP(hipEventCreateWithFlags(&pr.join_ev, hipEventDisableTiming));
 }
 
 // ---------------------------------------------------------------------------
@@ -468,10 +492,10 @@ void add_inplace(double* a, const double* b, long long n, hipStream_t st) {
 // remove the components along basis B (rows x r) from X (rows x n) twice,
 // accumulating the coefficients in C (r x n): X <- X - B (B^T X)
 void project_out(Prob& pr, long long rows, int r, int n, const double* B, double* X, double* C,
-                 double* C2, hipStream_t st) {
-  gemm_tn(rows, r, n, 1.0, B, rows, X, rows, 0.0, C, r, pr.gwork, pr.gwork_elems, st);
+                 double* C2, double* work, hipStream_t st) {
+  gemm_tn(rows, r, n, 1.0, B, rows, X, rows, 0.0, C, r, work, pr.gwork_elems, st);
   gemm_nn(rows, n, r, -1.0, B, rows, C, r, 1.0, X, rows, st);
-  gemm_tn(rows, r, n, 1.0, B, rows, X, rows, 0.0, C2, r, pr.gwork, pr.gwork_elems, st);
+  gemm_tn(rows, r, n, 1.0, B, rows, X, rows, 0.0, C2, r, work, pr.gwork_elems, st);
   gemm_nn(rows, n, r, -1.0, B, rows, C2, r, 1.0, X, rows, st);
   // C += C2 (both r x n, contiguous)
   add_inplace(C, C2, (long long)r * n, st);
@@ -485,19 +509,28 @@ void update_svd_dev(Prob& pr, const double* F, const double* G, int ncols, hipSt
   double* U = pr.Ub[cur];
   double* V = pr.Vb[cur];
   int n;
+  // the G branch (projection and orthonormalisation of the G-side data)
+  // runs on the side stream between the fork and the join
+  PW_HIP(hipEventRecord(pr.fork_ev, st));
+  PW_HIP(hipStreamWaitEvent(pr.side, pr.fork_ev, 0));
   if (r == 0) {
     orth(rows, ncols, F, rows, U, rows, pr.RF, pr.os, st);
-    orth(rows, ncols, G, rows, V, rows, pr.RG, pr.os, st);
+    orth(rows, ncols, G, rows, V, rows, pr.RG, pr.os2, pr.side);
+    PW_HIP(hipEventRecord(pr.join_ev, pr.side));
+    PW_HIP(hipStreamWaitEvent(st, pr.join_ev, 0));
     gemm_small(ncols, ncols, ncols, 1.0, pr.RF, ncols, false, pr.RG, ncols, true, 0.0, pr.H,
                ncols, st);
     n = ncols;
   } else {
     PW_HIP(hipMemcpyAsync(pr.Fp, F, sizeof(double) * rows * ncols, hipMemcpyDeviceToDevice, st));
-    PW_HIP(hipMemcpyAsync(pr.Gp, G, sizeof(double) * rows * ncols, hipMemcpyDeviceToDevice, st));
-    project_out(pr, rows, r, ncols, U, pr.Fp, pr.UF, pr.UF2, st);
-    project_out(pr, rows, r, ncols, V, pr.Gp, pr.VG, pr.VG2, st);
+    PW_HIP(hipMemcpyAsync(pr.Gp, G, sizeof(double) * rows * ncols, hipMemcpyDeviceToDevice,
+                          pr.side));
+    project_out(pr, rows, r, ncols, U, pr.Fp, pr.UF, pr.UF2, pr.gwork, st);
+    project_out(pr, rows, r, ncols, V, pr.Gp, pr.VG, pr.VG2, pr.gwork2, pr.side);
     orth(rows, ncols, pr.Fp, rows, U + rows * r, rows, pr.RF, pr.os, st);
-    orth(rows, ncols, pr.Gp, rows, V + rows * r, rows, pr.RG, pr.os, st);
+    orth(rows, ncols, pr.Gp, rows, V + rows * r, rows, pr.RG, pr.os2, pr.side);
+    PW_HIP(hipEventRecord(pr.join_ev, pr.side));
+    PW_HIP(hipStreamWaitEvent(st, pr.join_ev, 0));
     n = r + ncols;
     // Af = [UF; RF], Bg = [VG; RG] ((r + ncols) x ncols)
     copy_block(r, ncols, pr.UF, r, pr.Af, n, st);
