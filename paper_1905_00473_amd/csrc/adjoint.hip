@@ -143,32 +143,51 @@ __global__ void k_adj_kick(double* lu, const double* lp, long long sl, const dou
   gacc[(long long)q.s * sg + J] += w * l[J] * lap_nb<D>(u + (long long)q.s * su, J, nb, g.idx2);
 }
 
-// One reverse leapfrog step, from level i+1 to level i: the reverse drift
-// lp' = lp + h lu (pointwise, formed at J and its neighbours), then the
-// reverse kick at level i with weight w:
+// One reverse leapfrog step, from level i+1 to level i, for all ns states
+// of a point in one thread: the reverse drift lp' = lp + h lu (pointwise,
+// formed at J and its neighbours), then the reverse kick at level i with
+// weight w:
 //   lu' = lu + w Lap(c2 lp'),  g += w lp' Lap u_i.
-// (lu, lp) and (lu', lp') are distinct buffers.
+// (lu, lp) and (lu', lp') are distinct buffers.  A thread takes the
+// states kAdjGroup q .. kAdjGroup q + kAdjGroup - 1 of a point: their c^2
+// gradient contributions are summed in a register and added once to field
+// q of gacc (the caller sums the fields of gacc).  Per point and state this
+// moves 40 B (read lu, lp, u; write lu', lp') plus 16 B per group, instead
+// of the 64 B of one thread per state, whose gradient accumulator is read
+// and written per state.
+constexpr int kAdjGroup = 8;
+
 template <int D>
-__global__ void k_adj_step(const double* lu, const double* lp, long long sl, double* lu2,
-                           double* lp2, long long sl2, const double* u, long long su,
-                           double* gacc, long long sg, const double* c2, double w, double h,
-                           G3 g, int nxb, int nblk) {
-  const Pt q = point(g, nxb, nblk);
+__global__ void k_adj_step_grp(const double* lu, const double* lp, long long sl, double* lu2,
+                               double* lp2, long long sl2, const double* u, long long su,
+                               double* gacc, long long sg, const double* c2, double w, double h,
+                               G3 g, int nxb, int nblk, int ns) {
+  const Pt q = point(g, nxb, nblk);  // q.s: state group
   if (!q.ok) return;
   const Nbr<D> nb = neighbours<D>(q, g);
   const long long J = q.J;
-  const double* lus = lu + (long long)q.s * sl;
-  const double* lps = lp + (long long)q.s * sl;
-  const double lpc = fma(h, lus[J], lps[J]);
-  double a = -2.0 * D * c2[J] * lpc;
+  const double cc = c2[J];
+  double cn[2 * D];
 #pragma unroll
-  for (int k = 0; k < 2 * D; ++k) {
-    const long long o = J + nb.off[k];
-    a += c2[o] * fma(h, lus[o], lps[o]);
+  for (int k = 0; k < 2 * D; ++k) cn[k] = c2[J + nb.off[k]];
+  double gsum = 0.0;
+  const int s1 = min(ns, (q.s + 1) * kAdjGroup);
+#pragma unroll 2
+  for (int s = q.s * kAdjGroup; s < s1; ++s) {
+    const double* lus = lu + (long long)s * sl;
+    const double* lps = lp + (long long)s * sl;
+    const double lpc = fma(h, lus[J], lps[J]);
+    double a = -2.0 * D * cc * lpc;
+#pragma unroll
+    for (int k = 0; k < 2 * D; ++k) {
+      const long long o = J + nb.off[k];
+      a += cn[k] * fma(h, lus[o], lps[o]);
+    }
+    lu2[(long long)s * sl2 + J] = lus[J] + w * a * g.idx2;
+    lp2[(long long)s * sl2 + J] = lpc;
+    gsum += w * lpc * lap_nb<D>(u + (long long)s * su, J, nb, g.idx2);
   }
-  lu2[(long long)q.s * sl2 + J] = lus[J] + w * a * g.idx2;
-  lp2[(long long)q.s * sl2 + J] = lpc;
-  gacc[(long long)q.s * sg + J] += w * lpc * lap_nb<D>(u + (long long)q.s * su, J, nb, g.idx2);
+  gacc[(long long)q.s * sg + J] += gsum;
 }
 
 template <typename T>
@@ -305,6 +324,7 @@ void vv_adjoint_d(const Grid& grid, const double* c2, const double* u0, const do
   const long long np = grid.npts();
   const G3 g = g3(grid);
   const PtLaunch pl = pt_launch(g, ns);
+  const PtLaunch pg = pt_launch(g, (ns + kAdjGroup - 1) / kAdjGroup);  // per state group
   const dim3 gr = pl.grid;
   const int nseg = (m + ckpt - 1) / ckpt;
   if ((long long)ns * np > sc.state_elems) fail(PW_EINVAL, "adjoint scratch too small");
@@ -359,10 +379,10 @@ void vv_adjoint_d(const Grid& grid, const double* c2, const double* u0, const do
       PW_LAUNCH_CHECK();
     }
     for (int i = len - 1; i >= 0; --i) {
-      hipLaunchKernelGGL(k_adj_step<D>, gr, dim3(kTB), 0, st, (const double*)lua,
+      hipLaunchKernelGGL(k_adj_step_grp<D>, pg.grid, dim3(kTB), 0, st, (const double*)lua,
                          (const double*)lpa, sa, lub, lpb, sb,
                          (const double*)(sc.seg + (long long)i * S), np, gacc, sg, c2,
-                         wk(i0 + i), h, g, pl.nxb, pl.nblk);
+                         wk(i0 + i), h, g, pg.nxb, pg.nblk, ns);
       PW_LAUNCH_CHECK();
       std::swap(lua, lub);
       std::swap(lpa, lpb);

@@ -286,7 +286,9 @@ struct AdjScratch {
 // Reverse of m velocity-Verlet steps (size h, medium c2) of ns states whose
 // inputs are (u0, p0) (state s at offset s * s0).  (lu, lp) hold the adjoint
 // of the outputs on entry and of the inputs on return (stride sl);
-// gacc[s * sg + J] += d J / d c2(J) of state s.  The forward trajectory is
+// the ns fields gacc[s * sg + J] receive d J / d c2(J) of the ns states:
+// only their sum over s is defined (states 8q .. 8q+7 add their
+// contributions of a reverse step to field q).  The forward trajectory is
 // recomputed from checkpoints taken every `ckpt` steps.
 void vv_adjoint(const Grid& g, const double* c2, const double* u0, const double* p0,
                 long long s0, double* lu, double* lp, long long sl, double* gacc, long long sg,
