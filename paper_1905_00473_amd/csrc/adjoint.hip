@@ -337,6 +337,16 @@ void vv_adjoint_d(const Grid& grid, const double* c2, const double* u0, const do
   copy_fields(u0, s0, sc.ck_u, np, np, ns, st);
   copy_fields(p0, s0, sc.ck_p, np, np, ns, st);
   for (int seg = 0; seg + 1 < nseg; ++seg) {
+    if (D == 2) {
+      // the streaming propagator, levels into the segment store
+      const double* pf = leapfrog_levels2d(grid, c2, sc.ck_u + seg * S, sc.ck_p + seg * S,
+                                           sc.p_tmp, sc.p_tmp2, np, ns, ckpt, h, seg == 0, sc.seg,
+                                           S, st);
+      copy_fields(sc.seg + (long long)(ckpt - 1) * S, np, sc.ck_u + (seg + 1) * S, np, np, ns,
+                  st);
+      copy_fields(pf, np, sc.ck_p + (seg + 1) * S, np, np, ns, st);
+      continue;
+    }
     const double* cu = sc.ck_u + seg * S;
     double* nu = sc.ck_u + (seg + 1) * S;
     double* npp = sc.ck_p + (seg + 1) * S;
@@ -363,13 +373,18 @@ void vv_adjoint_d(const Grid& grid, const double* c2, const double* u0, const do
     const int len = std::min(ckpt, m - i0);
     // displacements u_{i0} .. u_{i0+len} in the segment store
     copy_fields(sc.ck_u + seg * S, np, sc.seg, np, np, ns, st);
-    copy_fields(sc.ck_p + seg * S, np, sc.p_tmp, np, np, ns, st);
-    for (int i = 0; i < len; ++i) {
-      hipLaunchKernelGGL(k_fwd_step<D>, gr, dim3(kTB), 0, st,
-                         (const double*)(sc.seg + (long long)i * S), np, sc.p_tmp, np,
-                         sc.seg + (long long)(i + 1) * S, np, c2, wk(i0 + i), h, g, pl.nxb,
-                         pl.nblk);
-      PW_LAUNCH_CHECK();
+    if (D == 2) {
+      leapfrog_levels2d(grid, c2, sc.ck_u + seg * S, sc.ck_p + seg * S, sc.p_tmp, sc.p_tmp2, np,
+                        ns, len, h, i0 == 0, sc.seg + S, S, st);
+    } else {
+      copy_fields(sc.ck_p + seg * S, np, sc.p_tmp, np, np, ns, st);
+      for (int i = 0; i < len; ++i) {
+        hipLaunchKernelGGL(k_fwd_step<D>, gr, dim3(kTB), 0, st,
+                           (const double*)(sc.seg + (long long)i * S), np, sc.p_tmp, np,
+                           sc.seg + (long long)(i + 1) * S, np, c2, wk(i0 + i), h, g, pl.nxb,
+                           pl.nblk);
+        PW_LAUNCH_CHECK();
+      }
     }
     if (seg == nseg - 1) {
       // closing half kick at level m

@@ -935,6 +935,7 @@ void ensure_backward(Prob& pr, int ckpt) {
   a.ck_p = m.get_n<double>(a.state_elems * a.max_ckpt);
   a.seg = m.get_n<double>(a.state_elems * a.max_seg);
   a.p_tmp = m.get_n<double>(a.state_elems);
+  a.p_tmp2 = m.get_n<double>(a.state_elems);
   a.a_tmp = m.get_n<double>(a.state_elems);
   a.lp_tmp = m.get_n<double>(a.state_elems);
   t.bw_ckpt = ckpt;

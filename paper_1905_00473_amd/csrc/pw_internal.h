@@ -85,6 +85,10 @@ struct StreamDesc {
   T h, idx2;
   int nsteps, first, last;
   long long wave_begin;
+  // optional: u of every level produced by the launch, level j + 1 of the
+  // launch at lv_out + j * lv_stride (state s at offset s * sstride)
+  T* lv_out;
+  long long lv_stride;
 };
 
 // one propagation of a batch: nstates states of one 2D problem by m steps
@@ -271,7 +275,7 @@ void frob_norm2(const double* A, long long rows, int cols, long long lda, double
 // Scratch of vv_adjoint: one "time level" holds ns states of np points
 // (state_elems >= ns * np).  ck_u / ck_p: max_ckpt levels (checkpoints);
 // seg: max_seg levels (displacements of one recomputed segment);
-// p_tmp, a_tmp, lp_tmp: one level each.
+// p_tmp, p_tmp2, a_tmp, lp_tmp: one level each.
 struct AdjScratch {
   long long state_elems = 0;
   int max_ckpt = 0, max_seg = 0;
@@ -279,9 +283,22 @@ struct AdjScratch {
   double* ck_p = nullptr;
   double* seg = nullptr;
   double* p_tmp = nullptr;
+  double* p_tmp2 = nullptr;
   double* a_tmp = nullptr;
   double* lp_tmp = nullptr;
 };
+
+// Leapfrog form of m velocity-Verlet steps of nstates 2D FP64 states
+// (stride sstride), the state carried being (u_i, p_{i-1/2}): from
+// (u_src, p_src) at level i0, every step kicks (weight h/2 if it is level 0
+// of the trajectory, `level0`, else h) and drifts; u of levels i0+1..i0+m
+// goes to lv + (k - 1) lv_stride, k = 1..m.  p ping-pongs between pa and pb
+// (both distinct from p_src); the returned pointer holds p_{i0+m-1/2}.
+// No closing half kick.
+const double* leapfrog_levels2d(const Grid& g, const double* c2, const double* u_src,
+                                const double* p_src, double* pa, double* pb, long long sstride,
+                                int nstates, int m, double h, bool level0, double* lv,
+                                long long lv_stride, hipStream_t stream);
 
 // Reverse of m velocity-Verlet steps (size h, medium c2) of ns states whose
 // inputs are (u0, p0) (state s at offset s * s0).  (lu, lp) hold the adjoint

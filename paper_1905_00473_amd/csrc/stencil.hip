@@ -360,6 +360,11 @@ __device__ __forceinline__ void stream2d_body(const StreamDesc<T>& a, long long 
       qeu[j + 1] = eu;
       qep[j + 1] = ep;
       qk[j + 1] = kj;
+      if (a.lv_out != nullptr && j < ns) {
+        const int orow = t - 2 * j;
+        if (out_lane && orow >= Y0 && orow < Y1)
+          a.lv_out[(long long)j * a.lv_stride + base + (long long)orow * nx + gx] = un;
+      }
       if (j == B - 1 && !last) {
         const int orow = t - 2 * j;
         if (out_lane && orow >= Y0 && orow < Y1) {
@@ -530,20 +535,12 @@ void dispatch_stream2d(const StreamDesc<T>& a, bool fine, hipStream_t st) {
   PW_LAUNCH_CHECK();
 }
 
+// streams of a 2D launch: column blocks of XV output columns, row segments
+// sized so that about 4096 streams fill the chip
 template <typename T>
-void propagate_stream2d(const Grid& g, const T* c2, const T* u_src, const T* p_src, T* u_dst,
-                        T* p_dst, long long sstride, int nstates, int m, T h, bool comp,
-                        StateSet<T> wa, StateSet<T> wb, bool fine, hipStream_t st) {
+void stream_geometry(StreamDesc<T>& a, int nstates) {
   constexpr int B = stream_depth<T>();
   constexpr int XV = 64 - 2 * (B + 1);
-  StreamDesc<T> a{};
-  a.c2 = c2;
-  a.sstride = sstride;
-  a.nx = g.n[0];
-  a.ny = g.n[1];
-  a.nstates = nstates;
-  a.h = h;
-  a.idx2 = T(1.0 / (g.dx * g.dx));
   a.ncb = (a.nx + XV - 1) / XV;
   // enough independent streams to fill the chip; segments of >= 32 rows,
   // or >= 8 rows when even that leaves fewer than 256 streams (one small
@@ -556,6 +553,22 @@ void propagate_stream2d(const Grid& g, const T* c2, const T* u_src, const T* p_s
   nseg = std::max(1LL, std::min(nseg, (long long)((a.ny + minrows - 1) / minrows)));
   a.Ly = (int)((a.ny + nseg - 1) / nseg);
   a.nseg = (a.ny + a.Ly - 1) / a.Ly;
+}
+
+template <typename T>
+void propagate_stream2d(const Grid& g, const T* c2, const T* u_src, const T* p_src, T* u_dst,
+                        T* p_dst, long long sstride, int nstates, int m, T h, bool comp,
+                        StateSet<T> wa, StateSet<T> wb, bool fine, hipStream_t st) {
+  constexpr int B = stream_depth<T>();
+  StreamDesc<T> a{};
+  a.c2 = c2;
+  a.sstride = sstride;
+  a.nx = g.n[0];
+  a.ny = g.n[1];
+  a.nstates = nstates;
+  a.h = h;
+  a.idx2 = T(1.0 / (g.dx * g.dx));
+  stream_geometry(a, nstates);
   const int nl = (m + B - 1) / B;
   if (nl > 1 && (wa.u == nullptr || wb.u == nullptr || (comp && (wa.eu == nullptr || wb.eu == nullptr))))
     fail(PW_EINVAL, "propagation needs scratch state sets");
@@ -600,6 +613,42 @@ TileCfg tile_cfg(int dim) { return dim == 1 ? kTile1 : (dim == 2 ? kTile2 : kTil
 bool use_line(const Grid& g) { return g.dim == 1 && g.n[0] <= 4096; }
 
 }  // namespace
+
+const double* leapfrog_levels2d(const Grid& g, const double* c2, const double* u_src,
+                                const double* p_src, double* pa, double* pb, long long sstride,
+                                int nstates, int m, double h, bool level0, double* lv,
+                                long long lv_stride, hipStream_t st) {
+  if (g.dim != 2) fail(PW_EINVAL, "leapfrog_levels2d: 2D grids only");
+  if (nstates <= 0 || m <= 0) return p_src;
+  if (pa == p_src || pb == p_src || pa == pb) fail(PW_EINVAL, "leapfrog_levels2d: p buffers alias");
+  constexpr int B = stream_depth<double>();
+  StreamDesc<double> a{};
+  a.c2 = c2;
+  a.sstride = sstride;
+  a.nx = g.n[0];
+  a.ny = g.n[1];
+  a.nstates = nstates;
+  a.h = h;
+  a.idx2 = 1.0 / (g.dx * g.dx);
+  stream_geometry(a, nstates);
+  a.lv_stride = lv_stride;
+  a.last = 0;  // leapfrog form: no closing half kick
+  const int nl = (m + B - 1) / B;
+  const double* cp = p_src;
+  for (int l = 0; l < nl; ++l) {
+    a.first = (level0 && l == 0) ? 1 : 0;
+    a.nsteps = std::min(B, m - l * B);
+    a.u_in = l == 0 ? u_src : lv + (long long)(l * B - 1) * lv_stride;
+    a.p_in = cp;
+    double* po = (l % 2 == 0) ? pa : pb;
+    a.u_out = lv + (long long)(l * B + a.nsteps - 1) * lv_stride;
+    a.p_out = po;
+    a.lv_out = lv + (long long)(l * B) * lv_stride;
+    dispatch_stream2d<double, false>(a, true, st);
+    cp = po;
+  }
+  return cp;
+}
 
 int steps_per_launch(const Grid& g, bool is_double) {
   if (use_line(g)) return 1 << 30;
