@@ -236,6 +236,100 @@ __global__ void k_interp_T_axis(const double* in, long long sin, double* out, lo
   out[(long long)f * sout + ((long long)o * nc + m) * inner + i] = acc;
 }
 
+// Register-blocked variant for a compile-time ratio R: a thread produces RM
+// consecutive coarse outputs m, so every fine value loaded feeds RM
+// accumulators; over RM consecutive J the weight index J - m takes 2 RM - 1
+// values per phase, read from LDS once per block.  The terms of each output
+// are added in the order of k_interp_T_axis (J ascending, s ascending).
+template <int R, int RM>
+__global__ __launch_bounds__(256) void k_interp_T_axis_rb(const double* in, long long sin,
+                                                          double* out, long long sout,
+                                                          const double* tab, int outer, int nc,
+                                                          int inner, int nfields) {
+  extern __shared__ double wt[];
+  for (int t = threadIdx.x; t < R * nc; t += blockDim.x) wt[t] = tab[t];
+  __syncthreads();
+  const int nmb = (nc + RM - 1) / RM;
+  const long long per = (long long)outer * nmb * inner;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= per * nfields) return;
+  const int f = (int)(t / per);
+  long long rr = t - (long long)f * per;
+  const int i = (int)(rr % inner);
+  rr /= inner;
+  const int mb = (int)(rr % nmb);
+  const int o = (int)(rr / nmb);
+  const int m0 = mb * RM;
+  const double* src = in + (long long)f * sin + (long long)o * nc * R * inner + i;
+  double acc[RM];
+#pragma unroll
+  for (int a = 0; a < RM; ++a)
+    acc[a] = (m0 + a < nc) ? src[(long long)R * (m0 + a) * inner] : 0.0;
+  int J = 0;
+  for (; J + RM <= nc; J += RM) {
+    double x[RM][R];
+#pragma unroll
+    for (int u = 0; u < RM; ++u)
+#pragma unroll
+      for (int s = 1; s < R; ++s) x[u][s] = src[((long long)R * (J + u) + s) * inner];
+    double w[R][2 * RM - 1];  // w[s][k] = w_s[(J - m0 + k - (RM - 1)) mod nc]
+#pragma unroll
+    for (int s = 1; s < R; ++s)
+#pragma unroll
+      for (int k = 0; k < 2 * RM - 1; ++k) {
+        // J - m0 + k - (RM - 1) lies in (-nc - RM, nc): at most two wraps
+        int d = J - m0 + k - (RM - 1);
+        d += d < 0 ? nc : 0;
+        d += d < 0 ? nc : 0;
+        w[s][k] = wt[s * nc + d];
+      }
+#pragma unroll
+    for (int u = 0; u < RM; ++u)
+#pragma unroll
+      for (int s = 1; s < R; ++s)
+#pragma unroll
+        for (int a = 0; a < RM; ++a) acc[a] += w[s][u - a + RM - 1] * x[u][s];
+  }
+  for (; J < nc; ++J) {
+#pragma unroll
+    for (int s = 1; s < R; ++s) {
+      const double x = src[((long long)R * J + s) * inner];
+#pragma unroll
+      for (int a = 0; a < RM; ++a) {
+        int d = (J - m0 - a) % nc;
+        d += d < 0 ? nc : 0;
+        acc[a] += wt[s * nc + d] * x;
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < RM; ++a)
+    if (m0 + a < nc) out[(long long)f * sout + ((long long)o * nc + m0 + a) * inner + i] = acc[a];
+}
+
+// one transposed interpolation pass: fine (outer, nc*ratio, inner) ->
+// coarse (outer, nc, inner)
+void interp_T_pass(const double* in, long long sin, double* out, long long sout,
+                   const double* tab, int outer, int nc, int ratio, int inner, int nfields,
+                   hipStream_t st) {
+  constexpr int RM = 4;
+  if (ratio == 4 || ratio == 2) {
+    const long long n = (long long)outer * ((nc + RM - 1) / RM) * inner * nfields;
+    const size_t smem = sizeof(double) * (size_t)ratio * nc;
+    if (ratio == 4)
+      hipLaunchKernelGGL((k_interp_T_axis_rb<4, RM>), dim3(nblocks(n)), dim3(kTB), smem, st, in,
+                         sin, out, sout, tab, outer, nc, inner, nfields);
+    else
+      hipLaunchKernelGGL((k_interp_T_axis_rb<2, RM>), dim3(nblocks(n)), dim3(kTB), smem, st, in,
+                         sin, out, sout, tab, outer, nc, inner, nfields);
+  } else {
+    const long long n = (long long)outer * nc * inner * nfields;
+    hipLaunchKernelGGL(k_interp_T_axis, dim3(nblocks(n)), dim3(kTB), 0, st, in, sin, out, sout,
+                       tab, outer, nc, ratio, inner, nfields);
+  }
+  PW_LAUNCH_CHECK();
+}
+
 // fine[ratio J] += scale * coarse[J] (transpose of the restriction)
 __global__ void k_restrict_T_add(const double* c, long long sc, double* f, long long sf, G3 cg,
                                  int ratio, int fnx, int fny, double scale, int nfields) {
@@ -426,41 +520,28 @@ void interp_transpose(const Grid& f, const Grid& c, int ratio, const double* con
                       double* tmp, hipStream_t st) {
   if (nfields == 0) return;
   const int d = f.dim;
-  const int fx = f.n[0], fy = f.n[1], fz = f.n[2];
+  const int fx = f.n[0], fy = f.n[1];
   const int cx = c.n[0], cy = c.n[1], cz = c.n[2];
   if (d == 1) {
-    const long long n = (long long)cx * nfields;
-    hipLaunchKernelGGL(k_interp_T_axis, dim3(nblocks(n)), dim3(kTB), 0, st, in, sin, out, sout,
-                       tables[0], 1, cx, ratio, 1, nfields);
-    PW_LAUNCH_CHECK();
+    interp_T_pass(in, sin, out, sout, tables[0], 1, cx, ratio, 1, nfields, st);
     return;
   }
   if (d == 2) {
     // y transpose: (1, fy, fx) -> tmp (1, cy, fx); x transpose: (cy, fx, 1) -> out
     const long long sA = (long long)cy * fx;
-    hipLaunchKernelGGL(k_interp_T_axis, dim3(nblocks(sA * nfields)), dim3(kTB), 0, st, in, sin,
-                       tmp, sA, tables[1], 1, cy, ratio, fx, nfields);
-    hipLaunchKernelGGL(k_interp_T_axis, dim3(nblocks((long long)cy * cx * nfields)), dim3(kTB), 0,
-                       st, (const double*)tmp, sA, out, sout, tables[0], cy, cx, ratio, 1,
-                       nfields);
-    PW_LAUNCH_CHECK();
+    interp_T_pass(in, sin, tmp, sA, tables[1], 1, cy, ratio, fx, nfields, st);
+    interp_T_pass(tmp, sA, out, sout, tables[0], cy, cx, ratio, 1, nfields, st);
     return;
   }
   // 3D: z: (1, fz, fy*fx) -> A (1, cz, fy*fx); y: (cz, fy, fx) -> B (cz, cy, fx);
   // x: (cz*cy, fx, 1) -> out
-  (void)fz;
   const long long sA = (long long)cz * fy * fx;
   const long long sB = (long long)cz * cy * fx;
   double* A = tmp;
   double* B = tmp + sA * nfields;
-  hipLaunchKernelGGL(k_interp_T_axis, dim3(nblocks(sA * nfields)), dim3(kTB), 0, st, in, sin, A,
-                     sA, tables[2], 1, cz, ratio, fy * fx, nfields);
-  hipLaunchKernelGGL(k_interp_T_axis, dim3(nblocks(sB * nfields)), dim3(kTB), 0, st,
-                     (const double*)A, sA, B, sB, tables[1], cz, cy, ratio, fx, nfields);
-  hipLaunchKernelGGL(k_interp_T_axis, dim3(nblocks((long long)cz * cy * cx * nfields)),
-                     dim3(kTB), 0, st, (const double*)B, sB, out, sout, tables[0], cz * cy, cx,
-                     ratio, 1, nfields);
-  PW_LAUNCH_CHECK();
+  interp_T_pass(in, sin, A, sA, tables[2], 1, cz, ratio, fy * fx, nfields, st);
+  interp_T_pass(A, sA, B, sB, tables[1], cz, cy, ratio, fx, nfields, st);
+  interp_T_pass(B, sB, out, sout, tables[0], cz * cy, cx, ratio, 1, nfields, st);
 }
 
 void restrict_transpose_add(const Grid& f, int ratio, const Grid& c, const double* in,

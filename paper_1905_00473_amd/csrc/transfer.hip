@@ -217,9 +217,8 @@ __global__ __launch_bounds__(256) void k_interp_axis_rb(const Tin* in, long long
     const double x = (double)src[(long long)m * inner];
 #pragma unroll
     for (int a = 0; a < RJ; ++a) {
-      int dd = J0 + a - m;
+      int dd = (J0 + a - m) % nc;  // J0 + a may pass nc (discarded outputs)
       if (dd < 0) dd += nc;
-      if (dd >= nc) dd -= nc;
 #pragma unroll
       for (int s = 1; s < R; ++s) acc[a][s] += wt[s * nc + dd] * x;
     }
