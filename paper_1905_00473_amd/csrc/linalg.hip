@@ -480,8 +480,15 @@ __global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round,
   __shared__ int any_rot;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  int bp = rr_index(blockIdx.x, round, npb);
-  int bq = rr_index(npb - 1 - blockIdx.x, round, npb);
+  // blocks are dispatched round-robin over the 8 XCDs; pair indices are
+  // given to them in contiguous chunks per XCD, so that a column block,
+  // which moves to a neighbouring pair index from one round to the next,
+  // mostly stays in the same XCD's L2
+  const int np2 = npb / 2, per = (np2 + 7) / 8;
+  const int pair = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (pair >= np2) return;
+  int bp = rr_index(pair, round, npb);
+  int bq = rr_index(npb - 1 - pair, round, npb);
   if (bp > bq) {
     const int t = bp;
     bp = bq;
@@ -969,7 +976,8 @@ void svd_jacobi(int n, const double* H, double* X, double* Y, double* sig, doubl
   for (int sw = 0; sw < maxsweeps; ++sw) {
     if (blocked) {
       for (int round = 0; round < npb - 1; ++round) {
-        hipLaunchKernelGGL(k_jacobi_block, dim3(npb / 2), dim3(256), 0, st, n, npb, round, Hw, Vw,
+        hipLaunchKernelGGL(k_jacobi_block, dim3(8 * ((npb / 2 + 7) / 8)), dim3(256), 0, st, n, npb,
+                           round, Hw, Vw,
                            counters + sw, (const double*)fro2);
         PW_LAUNCH_CHECK();
       }
