@@ -520,9 +520,8 @@ constexpr int stream_depth() {
   return sizeof(T) == 4 ? 8 : 4;
 }
 
-template <typename T, bool COMP>
+template <typename T, bool COMP, int B = stream_depth<T>()>
 void dispatch_stream2d(const StreamDesc<T>& a, bool fine, hipStream_t st) {
-  constexpr int B = stream_depth<T>();
   const long long nwaves = (long long)a.nstates * a.ncb * a.nseg;
   const long long nblk = (nwaves + 3) / 4;
   if (nblk >= (1LL << 31)) fail(PW_EINVAL, "too many streams for one launch");
@@ -537,29 +536,27 @@ void dispatch_stream2d(const StreamDesc<T>& a, bool fine, hipStream_t st) {
 
 // streams of a 2D launch: column blocks of XV output columns, row segments
 // sized so that about 4096 streams fill the chip
-template <typename T>
+template <typename T, int B = stream_depth<T>()>
 void stream_geometry(StreamDesc<T>& a, int nstates) {
-  constexpr int B = stream_depth<T>();
   constexpr int XV = 64 - 2 * (B + 1);
   a.ncb = (a.nx + XV - 1) / XV;
   // enough independent streams to fill the chip; segments of >= 32 rows,
-  // or >= 8 rows when even that leaves fewer than 256 streams (one small
-  // state: each stream is a serial chain of row steps, so shorter segments
-  // finish sooner although they repeat more halo rows)
+  // or of >= 2 B rows when even that leaves fewer than 256 streams (one
+  // small state: each stream is a serial chain of row steps, so shorter
+  // segments finish sooner although they repeat more halo rows)
   const long long want = 4096;
   const long long lanes = (long long)nstates * a.ncb;
   long long nseg = (want + lanes - 1) / lanes;
-  const long long minrows = lanes * ((a.ny + 31) / 32) < 256 ? 8 : 32;
+  const long long minrows = lanes * ((a.ny + 31) / 32) < 256 ? B : 32;
   nseg = std::max(1LL, std::min(nseg, (long long)((a.ny + minrows - 1) / minrows)));
   a.Ly = (int)((a.ny + nseg - 1) / nseg);
   a.nseg = (a.ny + a.Ly - 1) / a.Ly;
 }
 
-template <typename T>
-void propagate_stream2d(const Grid& g, const T* c2, const T* u_src, const T* p_src, T* u_dst,
-                        T* p_dst, long long sstride, int nstates, int m, T h, bool comp,
-                        StateSet<T> wa, StateSet<T> wb, bool fine, hipStream_t st) {
-  constexpr int B = stream_depth<T>();
+template <typename T, int B>
+void propagate_stream2d_b(const Grid& g, const T* c2, const T* u_src, const T* p_src, T* u_dst,
+                          T* p_dst, long long sstride, int nstates, int m, T h, bool comp,
+                          StateSet<T> wa, StateSet<T> wb, bool fine, hipStream_t st) {
   StreamDesc<T> a{};
   a.c2 = c2;
   a.sstride = sstride;
@@ -568,7 +565,7 @@ void propagate_stream2d(const Grid& g, const T* c2, const T* u_src, const T* p_s
   a.nstates = nstates;
   a.h = h;
   a.idx2 = T(1.0 / (g.dx * g.dx));
-  stream_geometry(a, nstates);
+  stream_geometry<T, B>(a, nstates);
   const int nl = (m + B - 1) / B;
   if (nl > 1 && (wa.u == nullptr || wb.u == nullptr || (comp && (wa.eu == nullptr || wb.eu == nullptr))))
     fail(PW_EINVAL, "propagation needs scratch state sets");
@@ -596,16 +593,37 @@ void propagate_stream2d(const Grid& g, const T* c2, const T* u_src, const T* p_s
     a.eu_out = out.eu;
     a.ep_out = out.ep;
     if (comp) {
-      if constexpr (sizeof(T) == 4) dispatch_stream2d<T, true>(a, fine, st);
+      if constexpr (sizeof(T) == 4) dispatch_stream2d<T, true, B>(a, fine, st);
       else fail(PW_EINVAL, "compensation is an FP32 mode");
     } else {
-      dispatch_stream2d<T, false>(a, fine, st);
+      dispatch_stream2d<T, false, B>(a, fine, st);
     }
     cu = out.u;
     cp = out.p;
     ceu = out.eu;
     cep = out.ep;
   }
+}
+
+// FP32 states of a launch too small to fill the chip (a few small states,
+// as in the serial chain of coarse propagations) take 4 time steps per
+// launch instead of 8: each stream is then a chain of about half as many
+// row steps (half the stages, half the halo rows, shorter segments)
+template <typename T>
+void propagate_stream2d(const Grid& g, const T* c2, const T* u_src, const T* p_src, T* u_dst,
+                        T* p_dst, long long sstride, int nstates, int m, T h, bool comp,
+                        StateSet<T> wa, StateSet<T> wb, bool fine, hipStream_t st) {
+  if constexpr (sizeof(T) == 4) {
+    constexpr int XV = 64 - 2 * (stream_depth<T>() + 1);
+    const long long lanes = (long long)nstates * ((g.n[0] + XV - 1) / XV);
+    if (lanes * ((g.n[1] + 31) / 32) < 256) {
+      propagate_stream2d_b<T, 4>(g, c2, u_src, p_src, u_dst, p_dst, sstride, nstates, m, h, comp,
+                                 wa, wb, fine, st);
+      return;
+    }
+  }
+  propagate_stream2d_b<T, stream_depth<T>()>(g, c2, u_src, p_src, u_dst, p_dst, sstride, nstates,
+                                             m, h, comp, wa, wb, fine, st);
 }
 
 TileCfg tile_cfg(int dim) { return dim == 1 ? kTile1 : (dim == 2 ? kTile2 : kTile3); }
