@@ -298,7 +298,7 @@ __device__ __forceinline__ T lane_down(T v) {  // value of lane + 1
 }
 
 // one stream (wavefront) of problem descriptor `a`; wid = local wave index
-template <typename T, bool COMP, int B>
+template <typename T, bool COMP, int B, bool LV = false>
 __device__ __forceinline__ void stream2d_body(const StreamDesc<T>& a, long long wid, int lane) {
   constexpr int H = B + 1;
   constexpr int XV = 64 - 2 * H;  // output columns per wave
@@ -360,7 +360,7 @@ __device__ __forceinline__ void stream2d_body(const StreamDesc<T>& a, long long 
       qeu[j + 1] = eu;
       qep[j + 1] = ep;
       qk[j + 1] = kj;
-      if (a.lv_out != nullptr && j < ns) {
+      if (LV && j < ns) {
         const int orow = t - 2 * j;
         if (out_lane && orow >= Y0 && orow < Y1)
           a.lv_out[(long long)j * a.lv_stride + base + (long long)orow * nx + gx] = un;
@@ -432,6 +432,16 @@ __global__ __launch_bounds__(256) void k_prop_stream2d(StreamDesc<T> a) {
   const long long wid = launch_wave(nwaves);
   if (wid >= nwaves) return;
   stream2d_body<T, COMP, B>(a, wid, threadIdx.x & 63);
+}
+
+// the same with every produced level of u written to a.lv_out (the forward
+// recomputation of the adjoint)
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_prop_stream2d_levels(StreamDesc<T> a) {
+  const long long nwaves = (long long)a.nstates * a.ncb * a.nseg;
+  const long long wid = launch_wave(nwaves);
+  if (wid >= nwaves) return;
+  stream2d_body<T, false, B, true>(a, wid, threadIdx.x & 63);
 }
 
 // many problems of different grids in one launch: wave -> problem through
@@ -662,7 +672,11 @@ const double* leapfrog_levels2d(const Grid& g, const double* c2, const double* u
     a.u_out = lv + (long long)(l * B + a.nsteps - 1) * lv_stride;
     a.p_out = po;
     a.lv_out = lv + (long long)(l * B) * lv_stride;
-    dispatch_stream2d<double, false>(a, true, st);
+    const long long nwaves = (long long)a.nstates * a.ncb * a.nseg;
+    if ((nwaves + 3) / 4 >= (1LL << 31)) fail(PW_EINVAL, "too many streams for one launch");
+    hipLaunchKernelGGL((k_prop_stream2d_levels<double, B>), dim3((unsigned)((nwaves + 3) / 4)),
+                       dim3(256), 0, st, a);
+    PW_LAUNCH_CHECK();
     cp = po;
   }
   return cp;
