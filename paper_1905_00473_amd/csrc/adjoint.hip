@@ -20,6 +20,9 @@ namespace {
 constexpr int kTB = 256;
 inline unsigned nblocks(long long n, int tb = kTB) { return (unsigned)((n + tb - 1) / tb); }
 
+__device__ __forceinline__ double lane_dn(double v) { return __shfl_down(v, 1, 64); }  // lane + 1
+__device__ __forceinline__ double lane_upv(double v) { return __shfl_up(v, 1, 64); }   // lane - 1
+
 struct G3 {
   int dim, nx, ny, nz;
   double idx2;
@@ -188,6 +191,164 @@ __global__ void k_adj_step_grp(const double* lu, const double* lp, long long sl,
     gsum += w * lpc * lap_nb<D>(u + (long long)s * su, J, nb, g.idx2);
   }
   gacc[(long long)q.s * sg + J] += gsum;
+}
+
+// Reverse leapfrog steps in 2D as a row stream, RB steps per launch
+// (pipeline stages held in registers, as in the forward streaming
+// propagator): one wavefront owns 64 - 2 RB output columns of one state
+// (RB halo lanes on each side, the x neighbours from the adjacent lanes) and
+// walks down a segment of rows.  Stage j performs reverse step top - j on
+// the row r = t - 2j of stream step t: from (lu, lp) at level top - j + 1,
+//   lp' = lp + h lu,  lu' = lu + w Lap(c2 lp'),  g += w lp' Lap u_{top-j},
+// reading u of its level from the segment store and its input rows from the
+// stage before (stage 0 from memory).  g is read at stage 0, carried through
+// the stages and written after the last, so the contributions are added in
+// the order of one launch per step.  Per point and step: 8 B of u, plus
+// 48 B per launch (lu, lp in and out, g in and out).
+constexpr int kAdjRB = 4;
+
+struct AdjStreamDesc {
+  const double* lu_in;
+  const double* lp_in;
+  long long s_in;
+  double* lu_out;
+  double* lp_out;
+  long long s_out;
+  const double* useg;  // level 0 of the segment store
+  long long s_lev, s_u;  // stride of a level, of a state within a level
+  double* gacc;
+  long long sg;
+  const double* c2;
+  double h, idx2;
+  double w[kAdjRB];
+  int top, nsteps;
+  int nx, ny, ncb, nseg, Ly, nstates;
+};
+
+__global__ __launch_bounds__(256) void k_adj_stream2d(AdjStreamDesc a) {
+  constexpr int B = kAdjRB;
+  constexpr int H = B;
+  constexpr int XV = 64 - 2 * H;
+  const long long nwaves = (long long)a.nstates * a.ncb * a.nseg;
+  // blocks of one XCD take consecutive waves (neighbouring segments share
+  // halo rows in that XCD's L2)
+  const long long nblk = (nwaves + 3) / 4;
+  long long blk = blockIdx.x;
+  if ((nblk & 7) == 0) blk = (blk & 7) * (nblk >> 3) + (blk >> 3);
+  const long long wid = blk * 4 + (threadIdx.x >> 6);
+  if (wid >= nwaves) return;
+  const int lane = threadIdx.x & 63;
+  const int cb = (int)(wid % a.ncb);
+  const int seg = (int)((wid / a.ncb) % a.nseg);
+  const int st = (int)(wid / ((long long)a.ncb * a.nseg));
+  const int nx = a.nx, ny = a.ny;
+  int gx = (cb * XV - H + lane) % nx;
+  if (gx < 0) gx += nx;
+  const bool out_lane = lane >= H && lane < 64 - H && (cb * XV + lane - H) < nx;
+  const int Y0 = seg * a.Ly;
+  const int Y1 = min(Y0 + a.Ly, ny);
+  auto rowidx = [&](int y) -> long long {
+    int r = y % ny;
+    if (r < 0) r += ny;
+    return (long long)r * nx + gx;
+  };
+  const double* lui = a.lu_in + (long long)st * a.s_in;
+  const double* lpi = a.lp_in + (long long)st * a.s_in;
+  double* gs = a.gacc + (long long)st * a.sg;
+  const double* ul[B];
+#pragma unroll
+  for (int j = 0; j < B; ++j)
+    ul[j] = a.useg + (long long)(j < a.nsteps ? a.top - j : a.top) * a.s_lev +
+            (long long)st * a.s_u;
+  // stage j: windows of its input level, rows (r-1, r, r+1) of q = c2 lp'
+  // and of u (its own level); rows (r, r+1) of lu, lp' and the carried g;
+  // pending row r+2 (from stage j-1, or loaded for j = 0)
+  double wq[B][3], wu[B][3], wl[B][2], wp[B][2], wg[B][2];
+  double pl[B], pp[B], pg[B];
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    wq[j][0] = wq[j][1] = wq[j][2] = 0.0;
+    wu[j][0] = wu[j][1] = wu[j][2] = 0.0;
+    wl[j][0] = wl[j][1] = wp[j][0] = wp[j][1] = wg[j][0] = wg[j][1] = 0.0;
+    pl[j] = pp[j] = pg[j] = 0.0;
+  }
+  const int tbeg = Y0 - H - 2;
+  const int tend = Y1 - 1 + 2 * (B - 1);
+  for (int t = tbeg; t <= tend; ++t) {
+    // input level, row t+2 -> pending slot of stage 0
+    if (t + 2 < Y1 + H) {
+      const long long gi = rowidx(t + 2);
+      pl[0] = lui[gi];
+      pp[0] = lpi[gi];
+      pg[0] = (t + 2 >= Y0 && t + 2 < Y1) ? gs[gi] : 0.0;
+    }
+    // every stage takes its pending row into its windows (lp', q) and
+    // loads the same row of its u level; then processes its centre row
+    double ol[B], op[B], og[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const int r = t - 2 * j;
+      const double lc = wl[j][0], pc = wp[j][0], gc = wg[j][0];
+      double lo = lc, po = pc, go = gc;
+      if (j < a.nsteps) {
+        const double uc = wu[j][1];
+        const double qc = wq[j][1];
+        // neighbours in the order x+1, x-1, y+1, y-1
+        double aa = -2.0 * 2 * qc;
+        aa += lane_dn(qc);
+        aa += lane_upv(qc);
+        aa += wq[j][2];
+        aa += wq[j][0];
+        double lu_ = -2.0 * 2 * uc;
+        lu_ += lane_dn(uc);
+        lu_ += lane_upv(uc);
+        lu_ += wu[j][2];
+        lu_ += wu[j][0];
+        lo = lc + a.w[j] * aa * a.idx2;
+        go = gc + a.w[j] * pc * (lu_ * a.idx2);
+      }
+      (void)r;
+      ol[j] = lo;
+      op[j] = po;
+      og[j] = go;
+    }
+    // outputs: stage j's row goes to stage j+1 (the last stage writes)
+#pragma unroll
+    for (int j = 0; j + 1 < B; ++j) {
+      pl[j + 1] = ol[j];
+      pp[j + 1] = op[j];
+      pg[j + 1] = og[j];
+    }
+    {
+      const int orow = t - 2 * (B - 1);
+      if (out_lane && orow >= Y0 && orow < Y1) {
+        const long long gi = (long long)orow * nx + gx;
+        a.lu_out[(long long)st * a.s_out + gi] = ol[B - 1];
+        a.lp_out[(long long)st * a.s_out + gi] = op[B - 1];
+        gs[gi] = og[B - 1];
+      }
+    }
+    // advance every window by one row, taking in the pending row: lp' and
+    // q = c2 lp' of the incoming row (pointwise), and the same row of u
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const int rin = t + 2 - 2 * j;  // row of the pending slot of stage j
+      const long long gi = rowidx(rin);
+      const double lpn = (j < a.nsteps) ? fma(a.h, pl[j], pp[j]) : pp[j];
+      wq[j][0] = wq[j][1];
+      wq[j][1] = wq[j][2];
+      wq[j][2] = a.c2[gi] * lpn;
+      wu[j][0] = wu[j][1];
+      wu[j][1] = wu[j][2];
+      wu[j][2] = ul[j][gi];
+      wl[j][0] = wl[j][1];
+      wl[j][1] = pl[j];
+      wp[j][0] = wp[j][1];
+      wp[j][1] = lpn;
+      wg[j][0] = wg[j][1];
+      wg[j][1] = pg[j];
+    }
+  }
 }
 
 template <typename T>
@@ -487,15 +648,61 @@ void vv_adjoint_d(const Grid& grid, const double* c2, const double* u0, const do
                          g, pl.nxb, pl.nblk);
       PW_LAUNCH_CHECK();
     }
-    for (int i = len - 1; i >= 0; --i) {
-      hipLaunchKernelGGL(k_adj_step_grp<D>, pg.grid, dim3(kTB), 0, st, (const double*)lua,
-                         (const double*)lpa, sa, lub, lpb, sb,
-                         (const double*)(sc.seg + (long long)i * S), np, gacc, sg, c2,
-                         wk(i0 + i), h, g, pg.nxb, pg.nblk, ns);
-      PW_LAUNCH_CHECK();
-      std::swap(lua, lub);
-      std::swap(lpa, lpb);
-      std::swap(sa, sb);
+    if (D == 2 && (long long)ns * np >= (1LL << 18)) {
+      // kAdjRB reverse steps per launch (launches too small to fill the
+      // chip, such as one coarse state, keep one step per launch: a stream
+      // is a serial chain of row steps)
+      AdjStreamDesc d{};
+      d.useg = sc.seg;
+      d.s_lev = S;
+      d.s_u = np;
+      d.gacc = gacc;
+      d.sg = sg;
+      d.c2 = c2;
+      d.h = h;
+      d.idx2 = g.idx2;
+      d.nx = g.nx;
+      d.ny = g.ny;
+      d.nstates = ns;
+      d.ncb = (g.nx + (64 - 2 * kAdjRB) - 1) / (64 - 2 * kAdjRB);
+      {
+        // about 4096 streams, segments of at least 16 rows
+        const long long lanes = (long long)ns * d.ncb;
+        long long nsg = (4096 + lanes - 1) / lanes;
+        nsg = std::max(1LL, std::min(nsg, (long long)((g.ny + 15) / 16)));
+        d.Ly = (int)((g.ny + nsg - 1) / nsg);
+        d.nseg = (g.ny + d.Ly - 1) / d.Ly;
+      }
+      const long long nw = (long long)ns * d.ncb * d.nseg;
+      if ((nw + 3) / 4 >= (1LL << 31)) fail(PW_EINVAL, "adjoint launch too large");
+      for (int i = len - 1; i >= 0;) {
+        d.top = i;
+        d.nsteps = std::min(kAdjRB, i + 1);
+        for (int j = 0; j < kAdjRB; ++j) d.w[j] = j < d.nsteps ? wk(i0 + i - j) : 0.0;
+        d.lu_in = lua;
+        d.lp_in = lpa;
+        d.s_in = sa;
+        d.lu_out = lub;
+        d.lp_out = lpb;
+        d.s_out = sb;
+        hipLaunchKernelGGL(k_adj_stream2d, dim3((unsigned)((nw + 3) / 4)), dim3(256), 0, st, d);
+        PW_LAUNCH_CHECK();
+        std::swap(lua, lub);
+        std::swap(lpa, lpb);
+        std::swap(sa, sb);
+        i -= d.nsteps;
+      }
+    } else {
+      for (int i = len - 1; i >= 0; --i) {
+        hipLaunchKernelGGL(k_adj_step_grp<D>, pg.grid, dim3(kTB), 0, st, (const double*)lua,
+                           (const double*)lpa, sa, lub, lpb, sb,
+                           (const double*)(sc.seg + (long long)i * S), np, gacc, sg, c2,
+                           wk(i0 + i), h, g, pg.nxb, pg.nblk, ns);
+        PW_LAUNCH_CHECK();
+        std::swap(lua, lub);
+        std::swap(lpa, lpb);
+        std::swap(sa, sb);
+      }
     }
   }
   if (lua != lu) {
