@@ -27,6 +27,10 @@ CASES = {
     # 2D, several tiles and a ragged tail on both axes, N = 6 slices
     "2d_ragged": dict(shape=(40, 72), ratio=4, N=6, m_fine=12, m_coarse=3,
                       T=0.375),
+    # 2D with N * points = 2^18: the fine reverse steps run as row streams,
+    # four steps per launch
+    "2d_stream": dict(shape=(128, 128), ratio=4, N=16, m_fine=32, m_coarse=8,
+                      T=0.5),
 }
 
 
@@ -79,8 +83,9 @@ def test_backward_matches_oracle(case, K):
     s.close()
 
 
-def test_checkpoint_interval_does_not_change_the_gradient():
-    w, rec, data = W.misfit_case(K=2, **CASES["2d_ragged"])
+@pytest.mark.parametrize("case", ["2d_ragged", "2d_stream"])
+def test_checkpoint_interval_does_not_change_the_gradient(case):
+    w, rec, data = W.misfit_case(K=2, **CASES[case])
     s, _ = _solver(w, 2)
     s.run_taped(2)
     seed = to_np(s.traces(rec)) - data
