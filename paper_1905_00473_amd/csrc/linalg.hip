@@ -637,19 +637,21 @@ __global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round,
   __syncthreads();
   if (nrot == 0) return;
   // 3. H(:, cols) <- B W (B staged), V(:, cols) <- V(:, cols) W, in 16-row
-  //    tiles on the matrix cores: A[i][k] = X[tile + i][4t + k] (lane l:
-  //    i = l%16, k = l/16), B[k][c] = W[4t + k][c] (held in four registers),
-  //    D[4v + l/16][l%16] = (X W)[tile + 4v + l/16][l%16].
+  //    tiles on the matrix cores, computed transposed, (X W)^T = W^T X^T:
+  //    operand A[i][k] = W^T[i][4t + k] = W[4t + k][i] (lane l: i = l%16,
+  //    k = l/16; held in four registers), operand B[k][j] = X[tile + j][4t + k],
+  //    D[4v + l/16][l%16] = (X W)[tile + l%16][4v + l/16]: the 16 lanes of a
+  //    group store 16 consecutive rows of one column (128 contiguous bytes).
   const double* Wf = W[cur];
   double bw[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) bw[t] = Wf[(4 * t + (lane >> 4)) * kJC + (lane & 15)];
-  const int gout = gcol(lane & 15);
   auto store = [&](double* X, int tile, const v4d& acc) {
+    const int row = tile + (lane & 15);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int row = tile + 4 * v + (lane >> 4);
-      if (row < n && gout < n) X[(long long)gout * n + row] = acc[v];
+      const int gc = gcol(4 * v + (lane >> 4));
+      if (row < n && gc < n) X[(long long)gc * n + row] = acc[v];
     }
   };
   for (int tile = 16 * wave; tile < n; tile += 64) {
@@ -659,7 +661,7 @@ __global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round,
     for (int t = 0; t < 4; ++t) {
       const int k = 4 * t + (lane >> 4);
       const double a = (ra < n) ? Hs[k * kJLd + ra] : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bw[t], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bw[t], a, acc, 0, 0, 0);
     }
     store(H, tile, acc);
   }
@@ -669,7 +671,7 @@ __global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round,
     if (tile < n) {
       v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int t = 0; t < 4; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va[u][t], bw[t], acc, 0, 0, 0);
+      for (int t = 0; t < 4; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bw[t], va[u][t], acc, 0, 0, 0);
       store(V, tile, acc);
     }
   }
@@ -683,7 +685,7 @@ __global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round,
     }
     v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], bw[t], acc, 0, 0, 0);
+    for (int t = 0; t < 4; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bw[t], a[t], acc, 0, 0, 0);
     store(V, tile, acc);
   }
   if (tid == 0) atomicAdd(counter, nrot);
