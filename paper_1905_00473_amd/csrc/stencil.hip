@@ -24,6 +24,8 @@
 // slice and folded into the state at the slice end.
 #include <algorithm>
 
+#include <cstdlib>
+
 #include "pw_internal.h"
 
 namespace pw {
@@ -550,11 +552,18 @@ template <typename T, int B = stream_depth<T>()>
 void stream_geometry(StreamDesc<T>& a, int nstates) {
   constexpr int XV = 64 - 2 * (B + 1);
   a.ncb = (a.nx + XV - 1) / XV;
-  // enough independent streams to fill the chip; segments of >= 32 rows,
-  // or of >= 2 B rows when even that leaves fewer than 256 streams (one
-  // small state: each stream is a serial chain of row steps, so shorter
-  // segments finish sooner although they repeat more halo rows)
-  const long long want = 4096;
+  // enough independent streams to fill the chip once at the kernel's
+  // occupancy (256 CUs x 4 SIMDs x 3 waves for the 8-step FP32 kernel, 4
+  // waves otherwise): a whole number of workgroups per CU, no tail;
+  // segments of >= 32 rows, or of >= B rows when even that leaves fewer
+  // than 256 streams (one small state: each stream is a serial chain of row
+  // steps, so shorter segments finish sooner although they repeat more halo
+  // rows)
+  static const long long want_env = [] {
+    const char* e = getenv("PW_STREAM_TARGET");  // tuning override
+    return e ? atoll(e) : 0LL;
+  }();
+  const long long want = want_env > 0 ? want_env : (sizeof(T) == 4 && B == 8 ? 3072 : 4096);
   const long long lanes = (long long)nstates * a.ncb;
   long long nseg = (want + lanes - 1) / lanes;
   const long long minrows = lanes * ((a.ny + 31) / 32) < 256 ? B : 32;
