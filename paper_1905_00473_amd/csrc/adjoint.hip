@@ -11,6 +11,7 @@
 // widened when read.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "pw_internal.h"
 
@@ -666,9 +667,15 @@ void vv_adjoint_d(const Grid& grid, const double* c2, const double* u0, const do
       d.nstates = ns;
       d.ncb = (g.nx + (64 - 2 * kAdjRB) - 1) / (64 - 2 * kAdjRB);
       {
-        // about 4096 streams, segments of at least 16 rows
+        // about 1920 streams (measured best on 32 states of 512^2: longer
+        // segments repeat fewer halo rows), segments of at least 16 rows
+        static const long long want_env = [] {
+          const char* e = getenv("PW_ADJ_STREAMS");  // tuning override
+          return e ? atoll(e) : 0LL;
+        }();
+        const long long want = want_env > 0 ? want_env : 1920;
         const long long lanes = (long long)ns * d.ncb;
-        long long nsg = (4096 + lanes - 1) / lanes;
+        long long nsg = (want + lanes - 1) / lanes;
         nsg = std::max(1LL, std::min(nsg, (long long)((g.ny + 15) / 16)));
         d.Ly = (int)((g.ny + nsg - 1) / nsg);
         d.nseg = (g.ny + d.Ly - 1) / d.Ly;

@@ -549,7 +549,7 @@ void dispatch_stream2d(const StreamDesc<T>& a, bool fine, hipStream_t st) {
 // streams of a 2D launch: column blocks of XV output columns, row segments
 // sized so that about 4096 streams fill the chip
 template <typename T, int B = stream_depth<T>()>
-void stream_geometry(StreamDesc<T>& a, int nstates) {
+void stream_geometry(StreamDesc<T>& a, int nstates, long long want_default = 0) {
   constexpr int XV = 64 - 2 * (B + 1);
   a.ncb = (a.nx + XV - 1) / XV;
   // enough independent streams to fill the chip once at the kernel's
@@ -563,7 +563,9 @@ void stream_geometry(StreamDesc<T>& a, int nstates) {
     const char* e = getenv("PW_STREAM_TARGET");  // tuning override
     return e ? atoll(e) : 0LL;
   }();
-  const long long want = want_env > 0 ? want_env : (sizeof(T) == 4 && B == 8 ? 3072 : 4096);
+  const long long want =
+      want_env > 0 ? want_env
+                   : (want_default > 0 ? want_default : (sizeof(T) == 4 && B == 8 ? 3072 : 4096));
   const long long lanes = (long long)nstates * a.ncb;
   long long nseg = (want + lanes - 1) / lanes;
   const long long minrows = lanes * ((a.ny + 31) / 32) < 256 ? B : 32;
@@ -667,7 +669,7 @@ const double* leapfrog_levels2d(const Grid& g, const double* c2, const double* u
   a.nstates = nstates;
   a.h = h;
   a.idx2 = 1.0 / (g.dx * g.dx);
-  stream_geometry(a, nstates);
+  stream_geometry(a, nstates, 3072);  // measured best for the level-writing kernel
   a.lv_stride = lv_stride;
   a.last = 0;  // leapfrog form: no closing half kick
   const int nl = (m + B - 1) / B;
