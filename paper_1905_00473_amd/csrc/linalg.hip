@@ -810,8 +810,13 @@ bool debug_jacobi() {
 // large results use the 128 x 128 tile kernel with about kBigTarget
 // workgroups (the scratch bound below covers both schemes)
 constexpr int kBigTarget = 256;
+bool small_tiles_forced() {
+  static const bool on = getenv("PW_GEMM_SMALL_TILES") != nullptr;
+  return on;
+}
+
 bool tn_big(long long rows, int a, int b) {
-  return a > TBM && b > TBN && rows >= GBM && !getenv("PW_GEMM_SMALL_TILES");
+  return a > TBM && b > TBN && rows >= GBM && !small_tiles_forced();
 }
 
 int tn_splits(long long rows, int a, int b) {
@@ -896,7 +901,7 @@ void gemm_nn(long long rows, int n, int k, double alpha, const double* A, long l
     }
     return;
   }
-  if (n > TBN && rows >= GBM && !getenv("PW_GEMM_SMALL_TILES")) {
+  if (n > TBN && rows >= GBM && !small_tiles_forced()) {
     dim3 grid((unsigned)((rows + GBM - 1) / GBM), (n + GBN - 1) / GBN);
     hipLaunchKernelGGL((k_gemm_nn<GBM, GBN, GBK>), grid, dim3(256), 0, st, rows, n, k, alpha, A,
                        lda, B, ldb, beta, C, ldc);
