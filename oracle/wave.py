@@ -384,8 +384,10 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
     u^{k+1}_n = v_n + I[real(grad2func(q, sum w) - grad2func(q~, sum U_n)),
     c (p - p~)].  Slice indices n = 0..N with u^k_0 = u0.
 
-    ``omega='identity'`` uses Omega = I (Sec. 6.2); ``correction=False``
-    drops the parareal-style additive term (Sec. 6.3).
+    ``omega='identity'`` uses Omega = I (Sec. 6.2); ``omega='plain'`` is
+    the plain parareal method of eq. plainparareal with the coarse
+    propagator I C R (no energy components, no Lambda^dag);
+    ``correction=False`` drops the parareal-style additive term (Sec. 6.3).
     """
     r = prob.ratio
     N = prob.N
@@ -427,6 +429,8 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
         Fm = np.column_stack([Lam(restrict(v[n], r), restrict(vp[n], r))
                               for n in range(1, N + 1)])
         Gm = np.column_stack([Lam(Uc[n], Ucp[n]) for n in range(1, N + 1)])
+        if omega not in ("procrustes", "identity", "plain"):
+            raise ValueError(omega)
         if omega == "procrustes":
             Us, S, Vs = update_svd(Us, S, Vs, Fm, Gm, prob.tol)
             if record_correctors:
@@ -448,6 +452,15 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
         pn = [p[0]] + [None] * N
         for n in range(1, N + 1):            # the serial sweep
             w, wp = Cprop(restrict(un[n - 1], r), restrict(pn[n - 1], r))
+            if omega == "plain":
+                # eq. plainparareal: I C R u^{k+1}_{n-1} + F u^k_{n-1}
+                #                    - I C R u^k_{n-1}
+                if correction:
+                    un[n] = v[n] + interp(w - Uc[n], r)
+                    pn[n] = vp[n] + interp(wp - Ucp[n], r)
+                else:
+                    un[n], pn[n] = interp(w, r), interp(wp, r)
+                continue
             zq = Om(Lam(w, wp))
             q, pq = split_components(zq, cshape)
             q1 = grad2func(q, np.sum(w), dxc)

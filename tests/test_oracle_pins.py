@@ -437,3 +437,68 @@ def test_p12_theta_keeps_energy():
         e_w = O.energy(w, wp, c, dx, "spectral")
         e_t = O.energy(a, b, c, dx, "spectral")
         assert e_t == pytest.approx(e_w - 0.5 * n * dx * qbar ** 2, rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Comparator variants of Sec. 6: plain parareal (eq. plainparareal) and the
+# iteration without the parareal-style correction (Sec. 6.3)
+# ---------------------------------------------------------------------------
+def _variant_problem(m_coarse):
+    n = 45
+    x = np.arange(n) / n
+    prob = O.Problem((n,), 1, 0.6, 6, 20, m_coarse, "spectral", 1e-14)
+    c = 1 + 0.2 * np.cos(2 * np.pi * x)
+    u0 = np.exp(-(x - 0.5) ** 2 / 0.08 ** 2)
+    return prob, c, u0, np.zeros(n)
+
+
+def test_plain_variant_is_eq_plainparareal():
+    """Coarse grid = fine grid (I = R = identity): omega='plain' is the
+    textbook recursion of eq. plainparareal."""
+    prob, c, u0, p0 = _variant_problem(5)
+    dx, c2 = prob.dx_fine, c * c
+    res = O.theta_parareal(prob, c, u0, p0, K=3, omega="plain")
+    v = _plain_parareal(
+        lambda s: O.propagate(s[0], s[1], c2, prob.dt_fine, dx, 20),
+        lambda s: O.propagate(s[0], s[1], c2, prob.dt_coarse, dx, 5),
+        (u0, p0), prob.N, 3)
+    for m in range(prob.N + 1):
+        np.testing.assert_allclose(res.u[m], v[m][0], atol=1e-13)
+        np.testing.assert_allclose(res.p[m], v[m][1], atol=1e-12)
+
+
+@pytest.mark.parametrize("omega", ["plain", "procrustes"])
+def test_variants_exact_after_one_iteration_when_c_equals_f(omega):
+    """With C = F (same grid, same steps) plain parareal is exact after one
+    iteration; so is the phase-corrected coarse propagation without the
+    additive correction, since Omega acts as the identity on the span of
+    the data (F^1 = G^1) and the spectral Lambda^dag Lambda is the identity
+    for odd n."""
+    prob, c, u0, p0 = _variant_problem(20)
+    ref_u, ref_p = O.serial_fine(prob, c, u0, p0)
+    res = O.theta_parareal(prob, c, u0, p0, K=1, omega=omega,
+                           correction=(omega == "plain"))
+    for m in range(prob.N + 1):
+        np.testing.assert_allclose(res.u[m], ref_u[m], atol=1e-10)
+        np.testing.assert_allclose(res.p[m], ref_p[m], atol=1e-9)
+
+
+def test_no_correction_identity_is_serial_coarse():
+    """Without the additive correction and with Omega = I the iteration is
+    the serial coarse propagation (Lambda^dag Lambda = 1 for the spectral
+    gradient at odd n; coarse grid = fine grid)."""
+    prob, c, u0, p0 = _variant_problem(5)
+    dx, c2 = prob.dx_fine, c * c
+    res = O.theta_parareal(prob, c, u0, p0, K=2, omega="identity",
+                           correction=False)
+    w = (u0, p0)
+    for m in range(1, prob.N + 1):
+        w = O.propagate(w[0], w[1], c2, prob.dt_coarse, dx, 5)
+        np.testing.assert_allclose(res.u[m], w[0], atol=1e-12)
+        np.testing.assert_allclose(res.p[m], w[1], atol=1e-11)
+
+
+def test_unknown_variant_raises():
+    prob, c, u0, p0 = _variant_problem(5)
+    with pytest.raises(ValueError):
+        O.theta_parareal(prob, c, u0, p0, K=1, omega="bogus")
