@@ -14,8 +14,10 @@ value = fine point-updates of the K batched fine sweeps (K * N * m_F *
 
 Also reported: the roofline of the fine stencil kernel (algorithmic 20 B
 per FP32 point-update: read u, p, c^2, write u, p), the serial GPU fine
-solve and the time to reach 1e-5 energy error against it, the per-phase
-split, and the FP64 oracle timed on the host on a bounded sample.
+solve and the time to reach 1e-5 energy error against it, the comparator
+iterations of Sec. 6 (Omega = I, no parareal-style correction, plain
+parareal: error per iteration and time), the per-phase split, and the FP64
+oracle timed on the host on a bounded sample.
 """
 
 import argparse
@@ -170,6 +172,37 @@ def adjoint_measurement(pw, W, torch, reps=3):
     return out
 
 
+def variants_measurement(s, w, K, uf, pf, torch):
+    """The comparator iterations of Sec. 6 on the same workload: energy
+    error of the last slice after k = 0..K iterations and the time of a
+    K-iteration run, for Omega = I, no parareal-style correction and plain
+    parareal, beside Algorithm 3."""
+    out = {}
+    for name in ("omega_one", "no_correction", "plain"):
+        s.set_variant(name)
+        errs = []
+        for k in range(0, K + 1):
+            s.run(k)
+            uN, pN = s.state(w.N)
+            ed, er = s.energy(uN, pN, uf, pf)
+            e = math.sqrt(ed / er) if er > 0 else math.sqrt(ed)
+            errs.append(float(f"{e:.4e}") if math.isfinite(e) else None)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        s.run(K)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - a) * 1e3
+        rho, _ = s.residuals()
+        out[name] = {"energy_error_per_iteration": errs,
+                     "ms_K_iterations": round(ms, 3),
+                     "rho": [float(f"{r:.4e}") if math.isfinite(r) else None
+                             for r in rho]}
+        log(f"variant {name}: {ms:.1f} ms, errors "
+            + " ".join("nan" if e is None else f"{e:.2e}" for e in errs))
+    s.set_variant("theta")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +211,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttt", action="store_true",
                     help="skip the time-to-1e-5 study")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the comparator iterations of Sec. 6")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 32-problem batched measurement")
     ap.add_argument("--no-adjoint", action="store_true",
@@ -278,6 +313,7 @@ def main():
     # ---- serial fine and time to 1e-5 -------------------------------------
     ttt = None
     serial_ms = None
+    variants = None
     if not args.no_ttt:
         uf, pf = s.serial_fine(w.N)
         torch.cuda.synchronize()
@@ -322,6 +358,13 @@ def main():
                        "stagnates instead of converging to the fine solution "
                        "(conclusions; 2D inclusion experiment), which is what "
                        "this workload shows"}
+        if not args.no_variants:
+            variants = variants_measurement(s, w, K, uf, pf, torch)
+            variants["theta"] = {
+                "energy_error_per_iteration": ttt[
+                    "energy_error_per_iteration"],
+                "ms_K_iterations": round(ms_step, 3),
+                "rho": [float(f"{r:.4e}") for r in rho]}
 
     s.close()
     del u, p
@@ -364,6 +407,7 @@ def main():
         "rho": [float(f"{r:.4e}") for r in rho],
         "rank": ranks,
         "time_to_1e-5": ttt,
+        "variants": variants,
         "batched": batched,
         "adjoint": adjoint,
         "cpu_baseline": cpu,

@@ -131,6 +131,36 @@ pw_status pw_set_initial(pw_ctx* ctx, int prob, const double* u0,
 pw_status pw_run(pw_ctx* ctx, int prob, int K);
 
 /*
+ * Comparator iterations of Sec. 6, run by pw_run in place of Algorithm 3
+ * (the coarse initialisation and the batched fine step are the same):
+ *   PW_VARIANT_THETA          Algorithm 3 as above (the default);
+ *   PW_VARIANT_OMEGA_ONE      Omega = I in eq. thetarelation (Sec. 6.2):
+ *                             u^{k+1}_n = v_n + I Lambda^dag Lambda
+ *                             C (R u^{k+1}_{n-1} - R u^k_{n-1});
+ *                             rho_k = ||F^k - G^k|| / ||F^k||, rank = rows;
+ *   PW_VARIANT_NO_CORRECTION  the phase-corrected coarse propagation
+ *                             without the parareal-style correction
+ *                             (Sec. 6.3): u^{k+1}_n = I Lambda^dag Omega^k
+ *                             Lambda C R u^{k+1}_{n-1}, with Omega^k from
+ *                             Algorithm 1 on the same data as Algorithm 3;
+ *   PW_VARIANT_PLAIN          plain parareal, eq. plainparareal with the
+ *                             coarse propagator I C R; rho_k and rank as
+ *                             for PW_VARIANT_OMEGA_ONE.
+ * The Omega = I and plain sweeps are serial chains of N coarse
+ * propagations (no reduced recurrence).  Applies to pw_run only:
+ * pw_run_batch, pw_run_taped and pw_run_frozen return PW_EINVAL for a
+ * problem whose variant is not PW_VARIANT_THETA.  Resets the iteration.
+ * PW_EINVAL for an unknown variant.
+ */
+typedef enum {
+  PW_VARIANT_THETA = 0,
+  PW_VARIANT_OMEGA_ONE = 1,
+  PW_VARIANT_NO_CORRECTION = 2,
+  PW_VARIANT_PLAIN = 3
+} pw_variant;
+pw_status pw_set_variant(pw_ctx* ctx, int prob, int variant);
+
+/*
  * Batching: Algorithm 3 for every problem of the context in lockstep (all
  * problems 2D, same state dtype and compensation, medium and initial state
  * set).  Per iteration, the parallel phase of all problems -- the fine

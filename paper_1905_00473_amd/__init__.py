@@ -70,6 +70,9 @@ class Problem(ctypes.Structure):
         return p
 
 
+#: comparator iterations of Sec. 6 selectable with Solver.set_variant
+VARIANTS = {"theta": 0, "omega_one": 1, "no_correction": 2, "plain": 3}
+
 _LIB = None
 
 _SIGS = {
@@ -82,6 +85,7 @@ _SIGS = {
     "pw_set_initial": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                        ctypes.c_void_p, ctypes.c_int],
     "pw_run": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int],
+    "pw_set_variant": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int],
     "pw_get_state": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
     "pw_get_residuals": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
@@ -239,6 +243,12 @@ class Solver:
 
     def run(self, K, prob=0):
         _check(lib().pw_run(self._h, prob, int(K)))
+
+    def set_variant(self, variant, prob=0):
+        """Iteration run by `run`: 'theta' (Algorithm 3), 'omega_one'
+        (Omega = I), 'no_correction' or 'plain' (plain parareal)."""
+        v = VARIANTS.get(variant, variant)
+        _check(lib().pw_set_variant(self._h, prob, int(v)))
 
     def run_batch(self, K):
         """Algorithm 3 for all problems of the context in lockstep."""

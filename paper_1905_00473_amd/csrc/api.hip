@@ -189,6 +189,8 @@ struct Prob {
   // joined to the caller's stream with events
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  int variant = PW_VARIANT_THETA;  // iteration run by pw_run
+  double* vsum = nullptr;          // column sum of the Omega = I chain
   int cur = 0;    // which of the ping-pong corrector buffers is current
   int r = 0;      // current rank
   int k_done = 0;
@@ -408,6 +410,7 @@ void setup(Prob& pr, const pw_problem& P) {
   pr.gwork_elems = gemm_tn_work_bound((int)cap, (int)std::max<long long>(cap, N));
   pr.gwork = m.get_n<double>((long long)pr.gwork_elems);
   pr.red = m.get_n<double>(4096);
+  pr.vsum = m.get_n<double>(16);
   pr.res = m.get_n<double>(2LL * (P.max_iters + 1));
   pr.os.gram = m.get_n<double>((long long)N * N);
   pr.os.T = m.get_n<double>((long long)N * N);
@@ -546,8 +549,8 @@ void update_svd_dev(Prob& pr, const double* F, const double* G, int ncols, hipSt
   rn = std::min(rn, pr.rmax);
   // new columns of E and P for the sweep: Lambda^dag of Q_F, Lambda^T of Q_G
   const long long Nc = pr.Nc;
-  lambda_dag_cols(pr.gc, pr.dtab, U + rows * r, rows, pr.cc, pr.E[cur] + 2 * Nc * r, 2 * Nc,
-                  ncols, pr.ctmp, st);
+  lambda_dag_cols(pr.gc, pr.dtab, U + rows * r, rows, pr.cc, nullptr, pr.E[cur] + 2 * Nc * r,
+                  2 * Nc, ncols, pr.ctmp, st);
   lambda_adjoint_cols(pr.gc, V + rows * r, rows, pr.cc, pr.order, pr.Vp[cur] + 2 * Nc * r, 2 * Nc,
                       ncols, st);
   // rotate: [U Q_F] X(:, 1:rn) etc.
@@ -659,21 +662,22 @@ void corrector_phase(Prob& pr, int k, hipStream_t st) {
   frob_norm2(pr.Fm, rows, N, rows, pr.red, pr.res + 2 * (k - 1) + 1, st);
 }
 
-// 3.-4. corrected sweep in corrector coordinates and the update
+// a_n = R v_{n-1} - R u^k_{n-1} (double coarse columns), v_0 = u0 -> column 0
+// is zero
 template <typename T>
-void sweep_core(Prob& pr, const double* E, const double* P, int dim, hipStream_t st) {
-  const int N = pr.N;
+void sweep_inputs(Prob& pr, hipStream_t st) {
   const long long Nf = pr.Nf, Nc = pr.Nc;
-  T* u = tp<T>(pr.u);
-  T* p = tp<T>(pr.p);
-  T* v = tp<T>(pr.v);
-  T* vp = tp<T>(pr.vp);
-  // a_n = C (R v_{n-1} - R u^k_{n-1}), v_0 = u0 -> column 0 is zero
   fill(pr.Din, 2 * Nc, 0.0, st);
-  if (N > 1)
-    restrict_diff<T>(pr.gf, pr.ratio, pr.gc, v, vp, u + Nf, p + Nf, Nf, pr.Din + 2 * Nc, 2 * Nc,
-                     N - 1, st);
-  prop_coarse_cols(pr, pr.Din, pr.Acol, N, st);
+  if (pr.N > 1)
+    restrict_diff<T>(pr.gf, pr.ratio, pr.gc, tp<T>(pr.v), tp<T>(pr.vp), tp<T>(pr.u) + Nf,
+                     tp<T>(pr.p) + Nf, Nf, pr.Din + 2 * Nc, 2 * Nc, pr.N - 1, st);
+}
+
+// delta_n = E t_n with t_n = P^T Acol_n + (P^T C E) t_{n-1}, t_0 = 0: the
+// serial sweep in corrector coordinates (Acol already formed)
+void corrector_chain(Prob& pr, const double* E, const double* P, int dim, hipStream_t st) {
+  const int N = pr.N;
+  const long long Nc = pr.Nc;
   prop_coarse_cols(pr, E, pr.CE, dim, st);
   gemm_tn(2 * Nc, dim, dim, 1.0, P, 2 * Nc, pr.CE, 2 * Nc, 0.0, pr.M, dim, pr.gwork,
           pr.gwork_elems, st);
@@ -682,17 +686,131 @@ void sweep_core(Prob& pr, const double* E, const double* P, int dim, hipStream_t
   if (dim > pr.rmax + 1) fail(PW_EINVAL, "corrector rank exceeds its capacity");
   recurrence(dim, N, pr.M, pr.Bn, pr.Tn, pr.rs, st);
   gemm_nn(2 * Nc, N, dim, 1.0, E, 2 * Nc, pr.Tn, dim, 0.0, pr.delta, 2 * Nc, st);
-  // u^{k+1}_n = v_n + I(delta_n), n = 1..N
+}
+
+// u^{k+1}_n = v_n + I(delta_n) (add_v) or I(delta_n), n = 1..N
+template <typename T>
+void sweep_update(Prob& pr, bool add_v, hipStream_t st) {
+  const int N = pr.N;
+  const long long Nf = pr.Nf, Nc = pr.Nc;
+  const T* v = add_v ? tp<T>(pr.v) : nullptr;
+  const T* vp = add_v ? tp<T>(pr.vp) : nullptr;
   split_cast<T>(pr.delta, 2 * Nc, Nc, N, tp<T>(pr.du_T), tp<T>(pr.dp_T), st);
-  interp_add<T>(pr.gf, pr.gc, pr.ratio, pr.itab, tp<T>(pr.du_T), Nc, v, u + Nf, Nf, N, pr.itmp,
-                st);
-  interp_add<T>(pr.gf, pr.gc, pr.ratio, pr.itab, tp<T>(pr.dp_T), Nc, vp, p + Nf, Nf, N,
+  interp_add<T>(pr.gf, pr.gc, pr.ratio, pr.itab, tp<T>(pr.du_T), Nc, v, tp<T>(pr.u) + Nf, Nf, N,
                 pr.itmp, st);
+  interp_add<T>(pr.gf, pr.gc, pr.ratio, pr.itab, tp<T>(pr.dp_T), Nc, vp, tp<T>(pr.p) + Nf, Nf, N,
+                pr.itmp, st);
+}
+
+// 3.-4. corrected sweep in corrector coordinates and the update:
+// delta_n = Lambda^dag Omega Lambda C (a_n + delta_{n-1}) (R I = 1)
+template <typename T>
+void sweep_core(Prob& pr, const double* E, const double* P, int dim, hipStream_t st) {
+  sweep_inputs<T>(pr, st);
+  prop_coarse_cols(pr, pr.Din, pr.Acol, pr.N, st);
+  corrector_chain(pr, E, P, dim, st);
+  sweep_update<T>(pr, true, st);
+}
+
+// ---- comparator iterations of Sec. 6 -----------------------------------
+__global__ void k_add_cols(const double* a, const double* b, double* out, long long n) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  out[t] = b ? a[t] + b[t] : a[t];
+}
+__global__ void k_sub_cols(const double* a, const double* b, double* out, long long n) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  out[t] = a[t] - b[t];
+}
+// out[0] = sum of x[0..n) (one workgroup, fixed summation order)
+__global__ __launch_bounds__(256) void k_col_sum(const double* x, long long n, double* out) {
+  __shared__ double part[256];
+  double acc = 0.0;
+  for (long long i = threadIdx.x; i < n; i += 256) acc += x[i];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = part[0];
+}
+
+void add_cols(const double* a, const double* b, double* out, long long n, hipStream_t st) {
+  hipLaunchKernelGGL(k_add_cols, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, out,
+                     n);
+  PW_LAUNCH_CHECK();
+}
+
+// rho_k = ||F^k - G^k|| / ||F^k|| for the iterations without a fitted
+// corrector (Omega = I, plain); the rank reported is the row count
+template <typename T>
+void residual_identity_phase(Prob& pr, int k, hipStream_t st) {
+  const int N = pr.N;
+  const long long Nf = pr.Nf, Nc = pr.Nc, rows = pr.rows;
+  energy_columns<T>(pr.gf, pr.ratio, pr.gc, tp<T>(pr.v), tp<T>(pr.vp), Nf, pr.cc, pr.order,
+                    pr.Fm, rows, N, st);
+  energy_columns<T>(pr.gc, 1, pr.gc, tp<T>(pr.Uc), tp<T>(pr.Ucp), Nc, pr.cc, pr.order, pr.Gm,
+                    rows, N, st);
+  pr.ranks.push_back((int)rows);
+  const long long n = rows * N;
+  hipLaunchKernelGGL(k_sub_cols, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                     (const double*)pr.Fm, (const double*)pr.Gm, pr.Fp, n);
+  PW_LAUNCH_CHECK();
+  frob_norm2(pr.Fp, rows, N, rows, pr.red, pr.res + 2 * (k - 1), st);
+  frob_norm2(pr.Fm, rows, N, rows, pr.red, pr.res + 2 * (k - 1) + 1, st);
+}
+
+// Omega = I (project) or plain parareal: the serial chain
+// delta_n = Pi C (a_n + delta_{n-1}), delta_1 = 0, with Pi = Lambda^dag
+// Lambda (Omega = I) or the identity (plain); then u^{k+1}_n = v_n + I delta_n
+template <typename T>
+void sweep_serial_chain(Prob& pr, bool project, hipStream_t st) {
+  const int N = pr.N;
+  const long long Nc = pr.Nc, C2 = 2 * Nc, rows = pr.rows;
+  sweep_inputs<T>(pr, st);
+  for (int n = 1; n <= N; ++n) {
+    double* x = pr.Acol + C2 * (n - 1);
+    double* dn = pr.delta + C2 * (n - 1);
+    add_cols(pr.Din + C2 * (n - 1), n > 1 ? pr.delta + C2 * (n - 2) : nullptr, x, C2, st);
+    if (!project) {
+      prop_coarse_cols(pr, x, dn, 1, st);
+      continue;
+    }
+    prop_coarse_cols(pr, x, pr.CE, 1, st);
+    energy_columns<double>(pr.gc, 1, pr.gc, pr.CE, pr.CE + Nc, C2, pr.cc, pr.order, pr.Fp, rows,
+                           1, st);
+    hipLaunchKernelGGL(k_col_sum, dim3(1), dim3(256), 0, st, (const double*)pr.CE, Nc, pr.vsum);
+    PW_LAUNCH_CHECK();
+    lambda_dag_cols(pr.gc, pr.dtab, pr.Fp, rows, pr.cc, pr.vsum, dn, C2, 1, pr.ctmp, st);
+  }
+  sweep_update<T>(pr, true, st);
+}
+
+// Sec. 6.3: u^{k+1}_n = I Lambda^dag Omega Lambda C R u^{k+1}_{n-1}; with
+// u^{k+1}_{n-1} = I delta_{n-1} (n >= 2) and R I = 1 this is the chain
+// delta_n = Lambda^dag Omega Lambda C delta_{n-1}, delta_0 = R u0, i.e. the
+// corrector-coordinate recurrence with Acol = [C R u0, 0, ..., 0]
+template <typename T>
+void sweep_no_correction(Prob& pr, hipStream_t st) {
+  const long long Nc = pr.Nc, C2 = 2 * Nc;
+  cast_to_double<T>(tp<T>(pr.Rc), pr.Din, Nc, st);
+  cast_to_double<T>(tp<T>(pr.Rcp), pr.Din + Nc, Nc, st);
+  if (pr.N > 1) fill(pr.Acol + C2, C2 * (pr.N - 1), 0.0, st);
+  prop_coarse_cols(pr, pr.Din, pr.Acol, 1, st);
+  corrector_chain(pr, pr.E[pr.cur], pr.Vp[pr.cur], pr.r + 1, st);
+  sweep_update<T>(pr, false, st);
 }
 
 template <typename T>
 void sweep_phase(Prob& pr, hipStream_t st) {
-  sweep_core<T>(pr, pr.E[pr.cur], pr.Vp[pr.cur], pr.r + 1, st);
+  switch (pr.variant) {
+    case PW_VARIANT_OMEGA_ONE: sweep_serial_chain<T>(pr, true, st); break;
+    case PW_VARIANT_PLAIN: sweep_serial_chain<T>(pr, false, st); break;
+    case PW_VARIANT_NO_CORRECTION: sweep_no_correction<T>(pr, st); break;
+    default: sweep_core<T>(pr, pr.E[pr.cur], pr.Vp[pr.cur], pr.r + 1, st);
+  }
 }
 
 void accumulate_phase_times(Prob& pr) {
@@ -719,7 +837,10 @@ void run_typed(Prob& pr, int K, hipStream_t st) {
     restrict_phase<T>(pr, st);
     prop_coarse<T>(pr, tp<T>(pr.Rc), tp<T>(pr.Rcp), tp<T>(pr.Uc), tp<T>(pr.Ucp), pr.N, st);
     PW_HIP(hipEventRecord(pr.ev[1], st));
-    corrector_phase<T>(pr, k, st);
+    if (pr.variant == PW_VARIANT_OMEGA_ONE || pr.variant == PW_VARIANT_PLAIN)
+      residual_identity_phase<T>(pr, k, st);
+    else
+      corrector_phase<T>(pr, k, st);
     PW_HIP(hipEventRecord(pr.ev[2], st));
     sweep_phase<T>(pr, st);
     PW_HIP(hipEventRecord(pr.ev[3], st));
@@ -1425,6 +1546,17 @@ pw_status pw_run(pw_ctx* ctx, int prob, int K) {
   });
 }
 
+pw_status pw_set_variant(pw_ctx* ctx, int prob, int variant) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (variant < PW_VARIANT_THETA || variant > PW_VARIANT_PLAIN)
+      fail(PW_EINVAL, "unknown variant");
+    pr.variant = variant;
+    pr.k_done = 0;
+    reset_corrector(pr);
+  });
+}
+
 pw_status pw_get_state(pw_ctx* ctx, int prob, int n, void* u, void* p, int on_device) {
   return guarded([&] {
     Prob& pr = get_prob(ctx, prob);
@@ -1616,6 +1748,8 @@ pw_status pw_run_batch(pw_ctx* ctx, int K) {
       if (!pr.have_medium || !pr.have_initial)
         fail(PW_ESTATE, "set medium and initial state of every problem first");
       if (pr.gf.dim != 2) fail(PW_EINVAL, "batched runs need 2D problems");
+      if (pr.variant != PW_VARIANT_THETA)
+        fail(PW_EINVAL, "batched runs execute Algorithm 3 only (a problem has a variant set)");
       if (pr.f64 != p0.f64 || pr.comp != p0.comp)
         fail(PW_EINVAL, "all problems of a batch need the same state dtype and compensation");
       if (K < 0 || K > pr.P.max_iters) fail(PW_EINVAL, "K must be in [0, max_iters]");
@@ -1682,6 +1816,8 @@ pw_status pw_run_taped(pw_ctx* ctx, int prob, int K) {
   return guarded([&] {
     Prob& pr = get_prob(ctx, prob);
     if (!pr.have_medium || !pr.have_initial) fail(PW_ESTATE, "set medium and initial state first");
+    if (pr.variant != PW_VARIANT_THETA)
+      fail(PW_EINVAL, "taped runs differentiate Algorithm 3 only (a variant is set)");
     if (K < 0 || K > pr.P.max_iters) fail(PW_EINVAL, "K must be in [0, max_iters]");
     ensure_tape(pr, K);
     if (pr.f64) run_taped_typed<double>(pr, K, false, ctx->stream);
@@ -1693,6 +1829,8 @@ pw_status pw_run_frozen(pw_ctx* ctx, int prob, int K) {
   return guarded([&] {
     Prob& pr = get_prob(ctx, prob);
     if (!pr.have_medium || !pr.have_initial) fail(PW_ESTATE, "set medium and initial state first");
+    if (pr.variant != PW_VARIANT_THETA)
+      fail(PW_EINVAL, "taped runs differentiate Algorithm 3 only (a variant is set)");
     if (!pr.tape || K < 0 || K > pr.tape->Kc)
       fail(PW_ESTATE, "run_frozen needs correctors recorded by pw_run_taped for K iterations");
     if (pr.f64) run_taped_typed<double>(pr, K, true, ctx->stream);

@@ -182,10 +182,11 @@ void grad2func_cols(const Grid& coarse, const double* const* dft, const double* 
 void lambda_adjoint_cols(const Grid& coarse, const double* in, long long ldi, const double* cc,
                          int order, double* out, long long ldo, int ncols, hipStream_t stream);
 
-// B'-columns from corrector columns: out_u = grad2func(q, 0), out_p = cc * p.
+// Lambda^dag of energy-component columns: out_u = grad2func(q, sums[col])
+// (sums null: all zero), out_p = cc * p.
 void lambda_dag_cols(const Grid& coarse, const double* const* dft, const double* in,
-                     long long ldi, const double* cc, double* out, long long ldo, int ncols,
-                     double* ctmp, hipStream_t stream);
+                     long long ldi, const double* cc, const double* sums, double* out,
+                     long long ldo, int ncols, double* ctmp, hipStream_t stream);
 
 // set column `col` of a 2*Nc-row matrix to [val_u * 1 ; 0]
 void set_dc_column(double* mat, long long ld, int col, long long nc, double val,

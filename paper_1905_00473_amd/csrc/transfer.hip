@@ -757,10 +757,10 @@ void lambda_adjoint_cols(const Grid& c, const double* in, long long ldi, const d
 }
 
 void lambda_dag_cols(const Grid& c, const double* const* dft, const double* in, long long ldi,
-                     const double* cc, double* out, long long ldo, int ncols, double* ctmp,
-                     hipStream_t st) {
+                     const double* cc, const double* sums, double* out, long long ldo, int ncols,
+                     double* ctmp, hipStream_t st) {
   if (ncols == 0) return;
-  grad2func_cols(c, dft, in, ldi, nullptr, out, ldo, ncols, ctmp, st);
+  grad2func_cols(c, dft, in, ldi, sums, out, ldo, ncols, ctmp, st);
   const long long n = c.npts() * ncols;
   hipLaunchKernelGGL(k_scale_p, dim3(nblocks(n)), dim3(kTB), 0, st, in, ldi, c.dim, cc, out, ldo,
                      c.npts(), ncols);
