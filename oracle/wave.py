@@ -374,7 +374,7 @@ class PararealResult:
 
 def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
                    omega="procrustes", correction=True,
-                   record_correctors=False):
+                   record_correctors=False, sample_cols=None):
     """Algorithm 3 of the paper, step by step.
 
     Initialisation u^1_n = I C R u^1_{n-1}; then K iterations of: parallel
@@ -388,6 +388,11 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
     the plain parareal method of eq. plainparareal with the coarse
     propagator I C R (no energy components, no Lambda^dag);
     ``correction=False`` drops the parareal-style additive term (Sec. 6.3).
+
+    ``sample_cols``: random subsampling of the data matrices (Sec. 6.5).
+    Entry k-1 lists the columns (0-based, column j holds slice j+1) of
+    F^k and G^k that Algorithm 1 receives in iteration k; the draw is an
+    input.  rho_k is still measured on all N columns.
     """
     r = prob.ratio
     N = prob.N
@@ -432,7 +437,16 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
         if omega not in ("procrustes", "identity", "plain"):
             raise ValueError(omega)
         if omega == "procrustes":
-            Us, S, Vs = update_svd(Us, S, Vs, Fm, Gm, prob.tol)
+            if sample_cols is None:
+                Fs, Gs = Fm, Gm
+            else:
+                cols = np.asarray(sample_cols[_k], dtype=np.int64)
+                if (cols.size == 0 or cols.min() < 0 or cols.max() >= N
+                        or np.unique(cols).size != cols.size):
+                    raise ValueError("sample columns must be distinct "
+                                     "indices in [0, N)")
+                Fs, Gs = Fm[:, cols], Gm[:, cols]
+            Us, S, Vs = update_svd(Us, S, Vs, Fs, Gs, prob.tol)
             if record_correctors:
                 correctors.append((Us.copy(), Vs.copy()))
             res = Fm - omega_apply(Us, Vs, Gm)

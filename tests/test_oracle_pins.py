@@ -502,3 +502,74 @@ def test_unknown_variant_raises():
     prob, c, u0, p0 = _variant_problem(5)
     with pytest.raises(ValueError):
         O.theta_parareal(prob, c, u0, p0, K=1, omega="bogus")
+
+
+# ---------------------------------------------------------------------------
+# Random subsampling of the data matrices (Sec. 6.5): Algorithm 1 receives
+# only the sampled slice columns of F^k and G^k
+# ---------------------------------------------------------------------------
+def _subsample_problem():
+    n = 48
+    x = np.arange(n) / n
+    prob = O.Problem((n,), 2, 1.0, 8, 16, 4, 4, 1e-14)
+    c = 1 + 0.3 * np.cos(2 * np.pi * x)
+    u0 = np.exp(-(x - 0.4) ** 2 / 0.07 ** 2)
+    return prob, c, u0, np.zeros(n)
+
+
+def test_subsample_single_column_is_rank_one_closed_form():
+    """One iteration with the single column j: M = F_j G_j^T has rank one,
+    so Omega = (F_j / |F_j|)(G_j / |G_j|)^T.  F_j and G_j are built here
+    from the primitives (eqs. matrixF, matrixG on the coarse
+    initialisation u^1)."""
+    prob, c, u0, p0 = _subsample_problem()
+    r = prob.ratio
+    cc = O.restrict(c, r)
+    j = 5
+    res = O.theta_parareal(prob, c, u0, p0, K=1, sample_cols=[[j]],
+                           record_correctors=True)
+    U, V = res.correctors[0]
+    assert U.shape[1] == 1 and res.rank == [1]
+    W, Wp = O.restrict(u0, r), O.restrict(p0, r)
+    for _ in range(j):                   # u^1_j = I (C R)^j u0 on the fine grid
+        W, Wp = O.propagate(W, Wp, cc * cc, prob.dt_coarse, prob.dx_coarse,
+                            prob.m_coarse)
+    uj, pj = O.interp(W, r), O.interp(Wp, r)
+    v, vp = O.propagate(uj, pj, c * c, prob.dt_fine, prob.dx_fine, prob.m_fine)
+    Fj = O.energy_components(O.restrict(v, r), O.restrict(vp, r), cc,
+                             prob.dx_coarse, prob.grad_order)
+    Gw, Gwp = O.propagate(O.restrict(uj, r), O.restrict(pj, r), cc * cc,
+                          prob.dt_coarse, prob.dx_coarse, prob.m_coarse)
+    Gj = O.energy_components(Gw, Gwp, cc, prob.dx_coarse, prob.grad_order)
+    expect = np.outer(Fj / np.linalg.norm(Fj), Gj / np.linalg.norm(Gj))
+    np.testing.assert_allclose(U @ V.T, expect, atol=1e-12)
+
+
+def test_subsample_is_a_set_and_all_columns_is_the_default():
+    """M = sum F_S G_S^T does not depend on the order of the sampled
+    columns; sampling every column is the unsampled iteration."""
+    prob, c, u0, p0 = _subsample_problem()
+    rng = np.random.default_rng(3)
+    S = [np.sort(rng.choice(prob.N, 4, replace=False)) for _ in range(3)]
+    a = O.theta_parareal(prob, c, u0, p0, K=3, sample_cols=S,
+                         record_correctors=True)
+    b = O.theta_parareal(prob, c, u0, p0, K=3,
+                         sample_cols=[s[::-1].copy() for s in S],
+                         record_correctors=True)
+    for (Ua, Va), (Ub, Vb) in zip(a.correctors, b.correctors):
+        np.testing.assert_allclose(Ua @ Va.T, Ub @ Vb.T, atol=1e-10)
+    assert a.rank == b.rank
+    full = O.theta_parareal(prob, c, u0, p0, K=2,
+                            sample_cols=[rng.permutation(prob.N)
+                                         for _ in range(2)])
+    ref = O.theta_parareal(prob, c, u0, p0, K=2)
+    assert full.rank == ref.rank
+    for n in range(prob.N + 1):
+        np.testing.assert_allclose(full.u[n], ref.u[n], atol=1e-10)
+
+
+@pytest.mark.parametrize("bad", [[[]], [[0, 0]], [[8]], [[-1]]])
+def test_subsample_rejects_bad_columns(bad):
+    prob, c, u0, p0 = _subsample_problem()
+    with pytest.raises(ValueError):
+        O.theta_parareal(prob, c, u0, p0, K=1, sample_cols=bad)
