@@ -16,8 +16,10 @@ Also reported: the roofline of the fine stencil kernel (algorithmic 20 B
 per FP32 point-update: read u, p, c^2, write u, p), the serial GPU fine
 solve and the time to reach 1e-5 energy error against it, the comparator
 iterations of Sec. 6 (Omega = I, no parareal-style correction, plain
-parareal: error per iteration and time), the per-phase split, and the FP64
-oracle timed on the host on a bounded sample.
+parareal: error per iteration and time), the random subsampling of the
+data matrices on the Sec. 6.5 waveguide (error per iteration and corrector
+time per sample size, singular-value decay), the per-phase split, and the
+FP64 oracle timed on the host on a bounded sample.
 """
 
 import argparse
@@ -203,6 +205,61 @@ def variants_measurement(s, w, K, uf, pf, torch):
     return out
 
 
+def sampling_measurement(pw, W, torch):
+    """Random subsampling of the data matrices on the Sec. 6.5 waveguide
+    (200^2 / 100^2, N = 200, FP64 state): energy error of the last slice
+    after k = 0..K iterations, time of a K-iteration run and of its
+    corrector phase, for N, N/2, N/4 and N/8 sampled columns per
+    iteration; and the decay of the normalised singular values of the
+    accumulated correlation matrix M after each iteration (all columns)."""
+    w = W.waveguide2d()
+    K = w.K
+    P = pw.Problem.make(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
+                        w.grad_order, w.tol, "f64", False, K)
+    s = pw.Solver(P)
+    s.set_medium(w.c)
+    s.set_initial(w.u0, w.p0)
+    uf, pf = s.serial_fine(w.N)
+    out = {"workload": "waveguide2d: 200^2 fine / 100^2 coarse, c = 1 - "
+                       "0.3 cos(2 pi x), Gaussian plane pulse in y, T = 4, "
+                       "N = 200, m_F = 250, m_C = 25, K = 6, FP64 state, "
+                       "tol 1e-14", "by_sample_size": {}}
+    idx = [0, 1, 3, 7, 15, 31, 63, 127, 255, 511, 1023]
+    for n_s in (w.N, w.N // 2, w.N // 4, w.N // 8):
+        s.set_sampling(None if n_s == w.N else
+                       W.sample_columns(w.N, n_s, K, seed=0))
+        errs, decay = [], []
+        for k in range(0, K + 1):
+            s.run(k)
+            uN, pN = s.state(w.N)
+            ed, er = s.energy(uN, pN, uf, pf)
+            errs.append(float(f"{math.sqrt(ed / er):.4e}"))
+            if n_s == w.N and k > 0:
+                _, S, _ = s.corrector()
+                S = S.cpu().numpy()
+                decay.append([float(f"{S[i] / S[0]:.3e}") for i in idx
+                              if i < len(S)])
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        s.run(K)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - a) * 1e3
+        ph = s.timings()
+        _, ranks = s.residuals()
+        rec = {"energy_error_per_iteration": errs,
+               "ms_K_iterations": round(ms, 2),
+               "corrector_ms": round(ph["corrector"], 2),
+               "rank": ranks}
+        if decay:
+            rec["sigma_over_sigma1"] = {"index": idx, "per_iteration": decay}
+        out["by_sample_size"][str(n_s)] = rec
+        log(f"sampling {n_s}/{w.N}: {ms:.1f} ms (corrector "
+            f"{ph['corrector']:.1f}), errors "
+            + " ".join(f"{e:.2e}" for e in errs))
+    s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,6 +270,10 @@ def main():
                     help="skip the time-to-1e-5 study")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the comparator iterations of Sec. 6")
+    ap.add_argument("--no-sampling", action="store_true",
+                    help="skip the data-matrix subsampling study")
+    ap.add_argument("--sampling-only", action="store_true",
+                    help="only the data-matrix subsampling study")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 32-problem batched measurement")
     ap.add_argument("--no-adjoint", action="store_true",
@@ -240,6 +301,9 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     if args.adjoint_only:
         print(json.dumps(adjoint_measurement(pw, W, torch)), flush=True)
+        return
+    if args.sampling_only:
+        print(json.dumps(sampling_measurement(pw, W, torch)), flush=True)
         return
     if args.batch_only:
         print(json.dumps(batch_measurement(pw, W, torch)), flush=True)
@@ -372,6 +436,9 @@ def main():
     batched = None if args.no_batch else batch_measurement(pw, W, torch)
     torch.cuda.empty_cache()
     adjoint = None if args.no_adjoint else adjoint_measurement(pw, W, torch)
+    torch.cuda.empty_cache()
+    sampling = None if args.no_sampling else sampling_measurement(pw, W,
+                                                                  torch)
 
     cpu = None if args.no_cpu else cpu_baseline(w)
 
@@ -408,6 +475,7 @@ def main():
         "rank": ranks,
         "time_to_1e-5": ttt,
         "variants": variants,
+        "sampling": sampling,
         "batched": batched,
         "adjoint": adjoint,
         "cpu_baseline": cpu,

@@ -161,6 +161,23 @@ typedef enum {
 pw_status pw_set_variant(pw_ctx* ctx, int prob, int variant);
 
 /*
+ * Random subsampling of the data matrices (Sec. 6.5): in iteration k
+ * (1-based) Algorithm 1 receives only the columns
+ * cols[(k-1) * n_per_iter + j], j < n_per_iter, of F^k and G^k (column j
+ * holds slice j + 1), so the truncated QR and the core SVD work on
+ * n_per_iter instead of N columns.  The draw is the caller's: cols is a
+ * host array of n_iters x n_per_iter int32, each row distinct indices in
+ * [0, N); it is copied.  rho_k is still measured on all N columns.
+ * n_per_iter = 0 switches sampling off (cols may be NULL).  Applies to
+ * pw_run, pw_run_batch and pw_run_taped, which return PW_EINVAL when K
+ * exceeds n_iters.  PW_EINVAL for sizes outside [0, N], a column outside
+ * [0, N) or repeated within a row.  Resets the iteration.  Synchronises
+ * the context stream.
+ */
+pw_status pw_set_sampling(pw_ctx* ctx, int prob, const int* cols,
+                          int n_per_iter, int n_iters);
+
+/*
  * Batching: Algorithm 3 for every problem of the context in lockstep (all
  * problems 2D, same state dtype and compensation, medium and initial state
  * set).  Per iteration, the parallel phase of all problems -- the fine

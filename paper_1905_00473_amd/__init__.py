@@ -86,6 +86,8 @@ _SIGS = {
                        ctypes.c_void_p, ctypes.c_int],
     "pw_run": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int],
     "pw_set_variant": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int],
+    "pw_set_sampling": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                        ctypes.c_int, ctypes.c_int],
     "pw_get_state": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
     "pw_get_residuals": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
@@ -243,6 +245,21 @@ class Solver:
 
     def run(self, K, prob=0):
         _check(lib().pw_run(self._h, prob, int(K)))
+
+    def set_sampling(self, cols, prob=0):
+        """Random subsampling of the data matrices: cols is a
+        (n_iters, n_per_iter) integer table of slice columns per iteration
+        (None switches sampling off)."""
+        import numpy as np
+        if cols is None:
+            _check(lib().pw_set_sampling(self._h, prob, None, 0, 0))
+            return
+        a = np.ascontiguousarray(np.asarray(cols, dtype=np.int32))
+        if a.ndim != 2:
+            raise ValueError("cols must be a 2-D table (iterations x samples)")
+        _check(lib().pw_set_sampling(
+            self._h, prob, a.ctypes.data_as(ctypes.c_void_p),
+            int(a.shape[1]), int(a.shape[0])))
 
     def set_variant(self, variant, prob=0):
         """Iteration run by `run`: 'theta' (Algorithm 3), 'omega_one'

@@ -190,6 +190,8 @@ struct Prob {
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   int variant = PW_VARIANT_THETA;  // iteration run by pw_run
+  DevBuf samp;                     // sampled data columns, samp_iters x samp_n
+  int samp_n = 0, samp_iters = 0;
   double* vsum = nullptr;          // column sum of the Omega = I chain
   int cur = 0;    // which of the ping-pong corrector buffers is current
   int r = 0;      // current rank
@@ -287,7 +289,6 @@ void validate(const pw_problem& P) {
   if (P.state_dtype != PW_F32 && P.state_dtype != PW_F64) fail(PW_EINVAL, "bad state dtype");
   if (P.compensated && P.state_dtype != PW_F32) fail(PW_EINVAL, "compensation is an FP32 mode");
   if (P.max_iters < 1) fail(PW_EINVAL, "max_iters must be >= 1");
-  if (P.n_slices > 64) fail(PW_EINVAL, "at most 64 slices per problem");
 }
 
 void setup(Prob& pr, const pw_problem& P) {
@@ -412,19 +413,29 @@ void setup(Prob& pr, const pw_problem& P) {
   pr.red = m.get_n<double>(4096);
   pr.vsum = m.get_n<double>(16);
   pr.res = m.get_n<double>(2LL * (P.max_iters + 1));
-  pr.os.gram = m.get_n<double>((long long)N * N);
-  pr.os.T = m.get_n<double>((long long)N * N);
+  size_t tsq_st = 0, tsq_tau = 0;
+  tsqr_work(rows, N, &tsq_st, &tsq_tau);
   pr.os.R1 = m.get_n<double>((long long)N * N);
   pr.os.R2 = m.get_n<double>((long long)N * N);
   pr.os.Q1 = m.get_n<double>(rows * N);
+  pr.os.hw = m.get_n<double>((long long)tsq_st + 16);
+  pr.os.htau = m.get_n<double>((long long)tsq_tau + 16);
+  if (N > 64) {
+    pr.os.W = m.get_n<double>(rows * 64);
+    pr.os.C = m.get_n<double>((long long)N * 64);
+  }
   pr.os.work = pr.gwork;
   pr.os.work_elems = pr.gwork_elems;
   pr.gwork2 = m.get_n<double>((long long)pr.gwork_elems);
-  pr.os2.gram = m.get_n<double>((long long)N * N);
-  pr.os2.T = m.get_n<double>((long long)N * N);
   pr.os2.R1 = m.get_n<double>((long long)N * N);
   pr.os2.R2 = m.get_n<double>((long long)N * N);
   pr.os2.Q1 = m.get_n<double>(rows * N);
+  pr.os2.hw = m.get_n<double>((long long)tsq_st + 16);
+  pr.os2.htau = m.get_n<double>((long long)tsq_tau + 16);
+  if (N > 64) {
+    pr.os2.W = m.get_n<double>(rows * 64);
+    pr.os2.C = m.get_n<double>((long long)N * 64);
+  }
   pr.os2.work = pr.gwork2;
   pr.os2.work_elems = pr.gwork_elems;
   for (int i = 0; i < 4; ++i) PW_HIP(hipEventCreate(&pr.ev[i]));
@@ -504,7 +515,29 @@ void project_out(Prob& pr, long long rows, int r, int n, const double* B, double
   add_inplace(C, C2, (long long)r * n, st);
 }
 
-void update_svd_dev(Prob& pr, const double* F, const double* G, int ncols, hipStream_t st) {
+// dst[:, j] = src[:, idx[j]] for j < ncols (rows x ncols, column-major)
+__global__ void k_gather_cols(const double* src, long long rows, const int* idx, int ncols,
+                              double* dst) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows * ncols) return;
+  const long long j = t / rows, i = t - j * rows;
+  dst[t] = src[(long long)idx[j] * rows + i];
+}
+
+void gather_cols(const double* src, long long rows, const int* idx, int ncols, double* dst,
+                 hipStream_t st) {
+  const long long n = rows * ncols;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src,
+                     rows, idx, ncols, dst);
+  PW_LAUNCH_CHECK();
+}
+
+// Algorithm 1 on F, G (rows x ncols); with cols (device, ncols entries) it
+// runs on the columns F[:, cols], G[:, cols] instead (random subsampling of
+// the data matrices)
+void update_svd_dev(Prob& pr, const double* F, const double* G, int ncols, hipStream_t st,
+                    const int* cols = nullptr) {
   const long long rows = pr.rows;
   const int r = pr.r;
   const int cur = pr.cur, nxt = 1 - pr.cur;
@@ -516,6 +549,12 @@ void update_svd_dev(Prob& pr, const double* F, const double* G, int ncols, hipSt
   // runs on the side stream between the fork and the join
   PW_HIP(hipEventRecord(pr.fork_ev, st));
   PW_HIP(hipStreamWaitEvent(pr.side, pr.fork_ev, 0));
+  if (cols) {
+    gather_cols(F, rows, cols, ncols, pr.Fp, st);
+    gather_cols(G, rows, cols, ncols, pr.Gp, pr.side);
+    F = pr.Fp;
+    G = pr.Gp;
+  }
   if (r == 0) {
     orth(rows, ncols, F, rows, U, rows, pr.RF, pr.os, st);
     orth(rows, ncols, G, rows, V, rows, pr.RG, pr.os2, pr.side);
@@ -525,9 +564,12 @@ void update_svd_dev(Prob& pr, const double* F, const double* G, int ncols, hipSt
                ncols, st);
     n = ncols;
   } else {
-    PW_HIP(hipMemcpyAsync(pr.Fp, F, sizeof(double) * rows * ncols, hipMemcpyDeviceToDevice, st));
-    PW_HIP(hipMemcpyAsync(pr.Gp, G, sizeof(double) * rows * ncols, hipMemcpyDeviceToDevice,
-                          pr.side));
+    if (F != pr.Fp)
+      PW_HIP(hipMemcpyAsync(pr.Fp, F, sizeof(double) * rows * ncols, hipMemcpyDeviceToDevice,
+                            st));
+    if (G != pr.Gp)
+      PW_HIP(hipMemcpyAsync(pr.Gp, G, sizeof(double) * rows * ncols, hipMemcpyDeviceToDevice,
+                            pr.side));
     project_out(pr, rows, r, ncols, U, pr.Fp, pr.UF, pr.UF2, pr.gwork, st);
     project_out(pr, rows, r, ncols, V, pr.Gp, pr.VG, pr.VG2, pr.gwork2, pr.side);
     orth(rows, ncols, pr.Fp, rows, U + rows * r, rows, pr.RF, pr.os, st);
@@ -564,6 +606,11 @@ void update_svd_dev(Prob& pr, const double* F, const double* G, int ncols, hipSt
     PW_HIP(hipMemcpyAsync(pr.S, pr.sig, sizeof(double) * rn, hipMemcpyDeviceToDevice, st));
   pr.cur = nxt;
   pr.r = rn;
+}
+
+void check_sampling(const Prob& pr, int K) {
+  if (pr.samp_n > 0 && K > pr.samp_iters)
+    fail(PW_EINVAL, "the sampled-column table covers fewer iterations than K");
 }
 
 void reset_corrector(Prob& pr) {
@@ -650,7 +697,13 @@ void corrector_phase(Prob& pr, int k, hipStream_t st) {
                     pr.Fm, rows, N, st);
   energy_columns<T>(pr.gc, 1, pr.gc, tp<T>(pr.Uc), tp<T>(pr.Ucp), Nc, pr.cc, pr.order, pr.Gm,
                     rows, N, st);
-  update_svd_dev(pr, pr.Fm, pr.Gm, N, st);
+  if (pr.samp_n > 0) {
+    if (k > pr.samp_iters) fail(PW_EINVAL, "no sampled columns for this iteration");
+    update_svd_dev(pr, pr.Fm, pr.Gm, pr.samp_n, st,
+                   (const int*)pr.samp.p + (long long)(k - 1) * pr.samp_n);
+  } else {
+    update_svd_dev(pr, pr.Fm, pr.Gm, N, st);
+  }
   pr.ranks.push_back(pr.r);
   // rho_k: || F - U (V^T G) ||_F / ||F||_F
   const int r = pr.r;
@@ -1541,8 +1594,38 @@ pw_status pw_run(pw_ctx* ctx, int prob, int K) {
     Prob& pr = get_prob(ctx, prob);
     if (!pr.have_medium || !pr.have_initial) fail(PW_ESTATE, "set medium and initial state first");
     if (K < 0 || K > pr.P.max_iters) fail(PW_EINVAL, "K must be in [0, max_iters]");
+    check_sampling(pr, K);
     if (pr.f64) run_typed<double>(pr, K, ctx->stream);
     else run_typed<float>(pr, K, ctx->stream);
+  });
+}
+
+pw_status pw_set_sampling(pw_ctx* ctx, int prob, const int* cols, int n_per_iter,
+                          int n_iters) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (n_per_iter < 0 || n_per_iter > pr.N || n_iters < 0)
+      fail(PW_EINVAL, "sample size must be in [0, N] and the iteration count >= 0");
+    if (n_per_iter > 0 && (n_iters == 0 || !cols)) fail(PW_EINVAL, "empty column table");
+    std::vector<char> seen((size_t)pr.N);
+    for (int k = 0; k < (n_per_iter > 0 ? n_iters : 0); ++k) {
+      std::fill(seen.begin(), seen.end(), 0);
+      for (int j = 0; j < n_per_iter; ++j) {
+        const int c = cols[(long long)k * n_per_iter + j];
+        if (c < 0 || c >= pr.N) fail(PW_EINVAL, "sample column outside [0, N)");
+        if (seen[(size_t)c]) fail(PW_EINVAL, "repeated sample column in one iteration");
+        seen[(size_t)c] = 1;
+      }
+    }
+    if (n_per_iter > 0) {
+      const size_t bytes = sizeof(int) * (size_t)n_per_iter * (size_t)n_iters;
+      PW_HIP(hipStreamSynchronize(ctx->stream));
+      PW_HIP(hipMemcpy(pr.samp.ensure(bytes), cols, bytes, hipMemcpyHostToDevice));
+    }
+    pr.samp_n = n_per_iter;
+    pr.samp_iters = n_per_iter > 0 ? n_iters : 0;
+    pr.k_done = 0;
+    reset_corrector(pr);
   });
 }
 
@@ -1753,6 +1836,7 @@ pw_status pw_run_batch(pw_ctx* ctx, int K) {
       if (pr.f64 != p0.f64 || pr.comp != p0.comp)
         fail(PW_EINVAL, "all problems of a batch need the same state dtype and compensation");
       if (K < 0 || K > pr.P.max_iters) fail(PW_EINVAL, "K must be in [0, max_iters]");
+      check_sampling(pr, K);
     }
     if (!ctx->batch) {
       ctx->batch = std::make_unique<Batch>();
@@ -1819,6 +1903,7 @@ pw_status pw_run_taped(pw_ctx* ctx, int prob, int K) {
     if (pr.variant != PW_VARIANT_THETA)
       fail(PW_EINVAL, "taped runs differentiate Algorithm 3 only (a variant is set)");
     if (K < 0 || K > pr.P.max_iters) fail(PW_EINVAL, "K must be in [0, max_iters]");
+    check_sampling(pr, K);
     ensure_tape(pr, K);
     if (pr.f64) run_taped_typed<double>(pr, K, false, ctx->stream);
     else run_taped_typed<float>(pr, K, false, ctx->stream);

@@ -257,117 +257,10 @@ __global__ void k_gemm_small(int m, int n, int k, double alpha, const double* A,
 }
 
 // ---------------------------------------------------------------------------
-// cyclic Jacobi eigen-decomposition of a symmetric n x n matrix (n <= 64)
-// in one workgroup; round-robin ordering, n/2 disjoint rotations per round
+// round-robin ordering of the Jacobi sweeps: n/2 disjoint pairs per round
 // ---------------------------------------------------------------------------
-constexpr int kCholMax = 64;
-
 __device__ __forceinline__ int rr_index(int j, int round, int np) {
   return j == 0 ? 0 : ((j - 1 + round) % (np - 1)) + 1;
-}
-
-// Truncated pivoted Cholesky of the Gram matrix G = A^T A (n x n, n <= 64)
-// in one workgroup, and the two factors of the orthonormalisation
-// Q = A T, A ~ Q R:  with P G P^T = L L^T truncated at rank k (the pivot
-// steps stop when the largest remaining diagonal entry is <= rel times the
-// largest diagonal of G, or <= abs_thr), R = L^T P^T (rows k.. zero) and
-// T = P [L_11^{-T}; 0] (columns k.. zero).  T and R are column-major n x n.
-__global__ __launch_bounds__(1024) void k_pchol_factors(int n, const double* Gg, double rel,
-                                                        double abs_thr, double* T, double* R) {
-  __shared__ double A[kCholMax][kCholMax + 1];   // trailing Gram matrix
-  __shared__ double Rm[kCholMax][kCholMax + 1];  // rows of L^T, pivoted column order
-  __shared__ double X[kCholMax][kCholMax + 1];   // inverse of the leading k x k block
-  __shared__ int perm[kCholMax];
-  __shared__ int piv_s, stop_s;
-  __shared__ double d0_s;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, x = tid & 63, y = tid >> 6;
-  for (int m = 0; m < 4; ++m) {
-    const int k = y + 16 * m;
-    A[x][k] = (x < n && k < n) ? Gg[x + (long long)k * n] : 0.0;
-    Rm[x][k] = 0.0;
-    X[x][k] = 0.0;
-  }
-  if (tid < kCholMax) perm[tid] = tid;
-  __syncthreads();
-  int rank = n;
-  for (int j = 0; j < n; ++j) {
-    if (tid < 64) {
-      // pivot: largest remaining diagonal entry (lowest index on ties)
-      double v = (lane >= j && lane < n) ? A[lane][lane] : -1.0;
-      int idx = lane;
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(v, off, 64);
-        const int oi = __shfl_xor(idx, off, 64);
-        if (ov > v || (ov == v && oi < idx)) {
-          v = ov;
-          idx = oi;
-        }
-      }
-      if (lane == 0) {
-        if (j == 0) d0_s = v;
-        const double d0 = j == 0 ? v : d0_s;
-        piv_s = idx;
-        stop_s = (!(v > rel * d0) || !(v > abs_thr)) ? 1 : 0;
-      }
-    }
-    __syncthreads();
-    if (stop_s) {
-      rank = j;
-      break;
-    }
-    const int pv = piv_s;
-    if (pv != j) {
-      if (tid < n) {
-        const double t = A[j][tid];
-        A[j][tid] = A[pv][tid];
-        A[pv][tid] = t;
-      }
-      __syncthreads();
-      if (tid < n) {
-        const double t = A[tid][j];
-        A[tid][j] = A[tid][pv];
-        A[tid][pv] = t;
-      }
-      if (tid < j) {
-        const double t = Rm[tid][j];
-        Rm[tid][j] = Rm[tid][pv];
-        Rm[tid][pv] = t;
-      }
-      if (tid == 0) {
-        const int t = perm[j];
-        perm[j] = perm[pv];
-        perm[pv] = t;
-      }
-      __syncthreads();
-    }
-    const double r = sqrt(A[j][j]);
-    if (tid >= j && tid < n) Rm[j][tid] = (tid == j) ? r : A[j][tid] / r;
-    __syncthreads();
-    for (int m = 0; m < 4; ++m) {
-      const int k = y + 16 * m;
-      if (x > j && x < n && k > j && k < n) A[x][k] -= Rm[j][x] * Rm[j][k];
-    }
-    __syncthreads();
-  }
-  // X = (leading rank x rank block of L^T)^{-1}, one column per thread
-  if (tid < rank) {
-    const int b = tid;
-    X[b][b] = 1.0 / Rm[b][b];
-    for (int a = b - 1; a >= 0; --a) {
-      double s = 0.0;
-      for (int c = a + 1; c <= b; ++c) s += Rm[a][c] * X[c][b];
-      X[a][b] = -s / Rm[a][a];
-    }
-  }
-  __syncthreads();
-  for (int m = 0; m < 4; ++m) {
-    const int b = y + 16 * m, a = x;
-    if (a < n && b < n) {
-      T[perm[a] + (long long)b * n] = (a < rank && b < rank) ? X[a][b] : 0.0;
-      R[a + (long long)perm[b] * n] = (a < rank) ? Rm[a][b] : 0.0;
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -924,29 +817,298 @@ void gemm_small(int m, int n, int k, double alpha, const double* A, int lda, boo
   PW_LAUNCH_CHECK();
 }
 
-void pchol_factors(int n, const double* G, double rel, double abs_thr, double* T, double* R,
-                   hipStream_t st) {
-  if (n > kCholMax) fail(PW_EINVAL, "the orthonormalisation supports at most 64 columns");
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_pchol_factors, dim3(1), dim3(1024), 0, st, n, G, rel, abs_thr, T, R);
-  PW_LAUNCH_CHECK();
+// ---------------------------------------------------------------------------
+// Householder QR of a tall matrix with at most 64 columns (TSQR): the rows
+// are cut into chunks of at most 256 rows, each chunk is factored by
+// Householder reflections in the LDS of one workgroup, the stacked n x n
+// R factors of all chunks form the next, shorter matrix, until one chunk
+// is left.  Q is then formed from the top down by applying each chunk's
+// reflectors to its n-row block of the level above ([I; 0] at the top).
+// Backward stable: Q is orthonormal to rounding whatever the conditioning
+// of A (directions far below sqrt(eps) of the largest are resolved, which
+// a Gram-based QR cannot do).
+// ---------------------------------------------------------------------------
+constexpr int kQrRows = 256;          // rows per chunk (at most)
+constexpr int kQrRPT = kQrRows / 4;  // rows per thread (4 threads per column)
+constexpr int kQrCols = 64;           // columns per factorisation
+
+// rows [off, off + m) of chunk c when M rows are cut into nch near-equal
+// chunks
+__device__ __forceinline__ void qr_chunk(long long M, int nch, int c, long long& off, int& m) {
+  const long long base = M / nch, rem = M % nch;
+  off = (long long)c * base + (c < rem ? c : rem);
+  m = (int)(base + (c < rem ? 1 : 0));
+}
+
+// Householder QR of chunk blockIdx.x of A (M x n, n <= 64): reflector j is
+// I - tau_j v v^T with v_j = 1 and v_i (i > j) stored in V below the
+// diagonal (LAPACK's convention); tau to tau[c * n + j]; the n x n R factor
+// (rows >= min(m, n) zero) to rows [c n, c n + n) of Rout.  V may alias A
+// (each thread reads its part of the chunk before anything is written).
+// Thread (k, s) = (t mod 64, t / 64) holds column k of the rows i = s + 4 q
+// in registers; the current reflector column is shared through LDS, so a
+// step costs 2 x 64 register FMAs per thread plus two small reductions.
+__global__ __launch_bounds__(256) void k_hqr_chunk(long long M, int n, int nch, const double* A,
+                                                   long long lda, double* V, long long ldv,
+                                                   double* tau, double* Rout, long long ldr) {
+  __shared__ double vcol[kQrRows];
+  __shared__ double part[4 * kQrCols];
+  __shared__ double w[kQrCols];
+  __shared__ double taus[kQrCols];
+  __shared__ double s_beta, s_scale;
+  long long off;
+  int m;
+  qr_chunk(M, nch, blockIdx.x, off, m);
+  const int t = threadIdx.x, k = t & 63, seg = t >> 6;
+  double reg[kQrRPT];
+#pragma unroll
+  for (int q = 0; q < kQrRPT; ++q) {
+    const int i = seg + 4 * q;
+    reg[q] = (k < n && i < m) ? A[(off + i) + (long long)k * lda] : 0.0;
+  }
+  const int r = m < n ? m : n;
+  for (int j = 0; j < r; ++j) {
+    if (k == j) {
+#pragma unroll
+      for (int q = 0; q < kQrRPT; ++q) {
+        const int i = seg + 4 * q;
+        vcol[i] = i >= j ? reg[q] : 0.0;
+      }
+    }
+    __syncthreads();
+    if (seg == 0) {
+      double s = 0.0;
+      for (int i = j + 1 + k; i < m; i += 64) s = fma(vcol[i], vcol[i], s);
+      s = wave_sum(s);
+      if (k == 0) {
+        const double alpha = vcol[j];
+        if (s == 0.0) {
+          taus[j] = 0.0;
+          s_beta = alpha;
+          s_scale = 0.0;
+        } else {
+          const double beta = -copysign(sqrt(alpha * alpha + s), alpha);
+          taus[j] = (beta - alpha) / beta;
+          s_scale = 1.0 / (alpha - beta);
+          s_beta = beta;
+        }
+      }
+    }
+    __syncthreads();
+    const double tj = taus[j], sc = s_scale;
+    if (k == j) {  // the pivot column becomes [.., beta, v]
+#pragma unroll
+      for (int q = 0; q < kQrRPT; ++q) {
+        const int i = seg + 4 * q;
+        if (i == j) reg[q] = s_beta;
+        else if (i > j) reg[q] *= sc;
+      }
+    }
+    if (tj != 0.0) {
+      // w_k = tau sum_{i >= j} v_i a_ik, k > j
+      double acc = 0.0;
+      if (k > j && k < n) {
+#pragma unroll
+        for (int q = 0; q < kQrRPT; ++q) {
+          const int i = seg + 4 * q;
+          const double v = i == j ? 1.0 : (i > j ? vcol[i] * sc : 0.0);
+          acc = fma(v, reg[q], acc);
+        }
+      }
+      part[seg * kQrCols + k] = acc;
+      __syncthreads();
+      if (t > j && t < n)
+        w[t] = tj * ((part[t] + part[kQrCols + t]) + (part[2 * kQrCols + t] + part[3 * kQrCols + t]));
+      __syncthreads();
+      if (k > j && k < n) {
+        const double wk = w[k];
+#pragma unroll
+        for (int q = 0; q < kQrRPT; ++q) {
+          const int i = seg + 4 * q;
+          const double v = i == j ? 1.0 : (i > j ? vcol[i] * sc : 0.0);
+          reg[q] = fma(-wk, v, reg[q]);
+        }
+      }
+    }
+    __syncthreads();  // vcol and part are rewritten by the next step
+  }
+#pragma unroll
+  for (int q = 0; q < kQrRPT; ++q) {
+    const int i = seg + 4 * q;
+    if (k < n && i < m) V[(off + i) + (long long)k * ldv] = (k < r && i > k) ? reg[q] : 0.0;
+  }
+  if (t < n) tau[(long long)blockIdx.x * n + t] = t < r ? taus[t] : 0.0;
+#pragma unroll
+  for (int q = 0; q < kQrRPT; ++q) {
+    const int i = seg + 4 * q;
+    if (k < n && i < n)
+      Rout[((long long)blockIdx.x * n + i) + (long long)k * ldr] =
+          (i <= k && i < r) ? reg[q] : 0.0;
+  }
+}
+
+// Q rows of chunk blockIdx.x: the chunk's reflectors applied, last first,
+// to [Qup rows c n .. c n + n - 1; 0] (Qup null: [I; 0]).  Q may alias V.
+// Same register layout as k_hqr_chunk.
+__global__ __launch_bounds__(256) void k_hqr_formq(long long M, int n, int nch, const double* V,
+                                                   long long ldv, const double* tau,
+                                                   const double* Qup, long long ldu, double* Q,
+                                                   long long ldq) {
+  __shared__ double vcol[kQrRows];
+  __shared__ double part[4 * kQrCols];
+  __shared__ double w[kQrCols];
+  long long off;
+  int m;
+  qr_chunk(M, nch, blockIdx.x, off, m);
+  const int t = threadIdx.x, k = t & 63, seg = t >> 6;
+  double reg[kQrRPT];
+#pragma unroll
+  for (int q = 0; q < kQrRPT; ++q) {
+    const int i = seg + 4 * q;
+    double val = 0.0;
+    if (k < n && i < m && i < n)
+      val = Qup ? Qup[((long long)blockIdx.x * n + i) + (long long)k * ldu] : (i == k ? 1.0 : 0.0);
+    reg[q] = val;
+  }
+  const int r = m < n ? m : n;
+  for (int j = r - 1; j >= 0; --j) {
+    const double tj = tau[(long long)blockIdx.x * n + j];
+    if (tj == 0.0) continue;  // the same for every thread of the block
+    vcol[t] = t == j ? 1.0 : ((t > j && t < m) ? V[(off + t) + (long long)j * ldv] : 0.0);
+    __syncthreads();
+    double acc = 0.0;
+    if (k < n) {
+#pragma unroll
+      for (int q = 0; q < kQrRPT; ++q) acc = fma(vcol[seg + 4 * q], reg[q], acc);
+    }
+    part[seg * kQrCols + k] = acc;
+    __syncthreads();
+    if (t < n)
+      w[t] = tj * ((part[t] + part[kQrCols + t]) + (part[2 * kQrCols + t] + part[3 * kQrCols + t]));
+    __syncthreads();
+    if (k < n) {
+      const double wk = w[k];
+#pragma unroll
+      for (int q = 0; q < kQrRPT; ++q) reg[q] = fma(-wk, vcol[seg + 4 * q], reg[q]);
+    }
+    __syncthreads();  // vcol and part are rewritten by the next step
+  }
+#pragma unroll
+  for (int q = 0; q < kQrRPT; ++q) {
+    const int i = seg + 4 * q;
+    if (k < n && i < m) Q[(off + i) + (long long)k * ldq] = reg[q];
+  }
+}
+
+// chunk count of one TSQR level of M rows
+static int qr_nchunks(long long M) { return (int)((M + kQrRows - 1) / kQrRows); }
+
+void tsqr_work(long long rows, int n, size_t* stack_elems, size_t* tau_elems) {
+  n = std::min(n, kQrCols);
+  size_t st = 0, ta = 0;
+  long long M = rows;
+  for (;;) {
+    const int nch = qr_nchunks(M);
+    ta += (size_t)nch * n;
+    if (nch == 1) break;
+    M = (long long)nch * n;
+    st += (size_t)M * n;
+  }
+  *stack_elems = st;
+  *tau_elems = ta;
+}
+
+// A (rows x n, n <= 64) = Q R, Q with ld ldq, R n x n (ld n, rows >=
+// min(rows, n) zero).  A and Q must not alias.
+static void tsqr(long long rows, int n, const double* A, long long lda, double* Q, long long ldq,
+                 double* R, const OrthScratch& s, hipStream_t st) {
+  struct Level {
+    long long M;
+    int nch;
+    double* V;
+    long long ldv;
+    double* tau;
+  };
+  Level lv[40];
+  int L = 0;
+  long long M = rows;
+  const double* in = A;
+  long long ldin = lda;
+  double* V = s.Q1;  // level 0 reflectors (rows x n)
+  long long ldv = rows;
+  double* stack = s.hw;
+  double* tp = s.htau;
+  for (;;) {
+    const int nch = qr_nchunks(M);
+    const bool top = nch == 1;
+    double* Rout = top ? R : stack;
+    const long long ldr = top ? n : (long long)nch * n;
+    hipLaunchKernelGGL(k_hqr_chunk, dim3((unsigned)nch), dim3(256), 0, st, M, n, nch, in, ldin, V,
+                       ldv, tp, Rout, ldr);
+    PW_LAUNCH_CHECK();
+    if (L >= 40) fail(PW_EINVAL, "TSQR level count exceeded");
+    lv[L++] = Level{M, nch, V, ldv, tp};
+    if (top) break;
+    tp += (size_t)nch * n;
+    M = (long long)nch * n;
+    in = stack;
+    ldin = M;
+    V = stack;  // the next level factors its input in place
+    ldv = M;
+    stack += (size_t)M * n;
+  }
+  const double* Qup = nullptr;
+  long long ldu = 0;
+  for (int l = L - 1; l >= 0; --l) {
+    double* out = l == 0 ? Q : lv[l].V;
+    const long long ldo = l == 0 ? ldq : lv[l].ldv;
+    hipLaunchKernelGGL(k_hqr_formq, dim3((unsigned)lv[l].nch), dim3(256), 0, st, lv[l].M, n,
+                       lv[l].nch, (const double*)lv[l].V, lv[l].ldv, (const double*)lv[l].tau, Qup,
+                       ldu, out, ldo);
+    PW_LAUNCH_CHECK();
+    Qup = out;
+    ldu = ldo;
+  }
 }
 
 void orth(long long rows, int n, const double* A, long long lda, double* Q, long long ldq,
           double* R, OrthScratch s, hipStream_t st) {
-  // pass 1: truncated pivoted Cholesky QR of A
-  gemm_tn(rows, n, n, 1.0, A, lda, A, lda, 0.0, s.gram, n, s.work, s.work_elems, st);
-  // truncation at 1e-15 of the largest Gram diagonal: residual directions
-  // down to ~3e-8 of the largest singular value are kept (the Gram matrix
-  // resolves directions only down to ~sqrt(eps) of it)
-  pchol_factors(n, s.gram, 1e-15, 1e-290, s.T, s.R1, st);
-  gemm_nn(rows, n, n, 1.0, A, lda, s.T, n, 0.0, s.Q1, rows, st);
-  // pass 2: the same on Q1 (its Gram is the identity up to rounding on the
-  // kept columns, zero on the dropped ones)
-  gemm_tn(rows, n, n, 1.0, s.Q1, rows, s.Q1, rows, 0.0, s.gram, n, s.work, s.work_elems, st);
-  pchol_factors(n, s.gram, 0.0, 0.25, s.T, s.R2, st);
-  gemm_nn(rows, n, n, 1.0, s.Q1, rows, s.T, n, 0.0, Q, ldq, st);
-  gemm_small(n, n, n, 1.0, s.R2, n, false, s.R1, n, false, 0.0, R, n, st);
+  if (n <= 0) return;
+  if (n <= kQrCols) {
+    tsqr(rows, n, A, lda, Q, ldq, R, s, st);
+    return;
+  }
+  // More than 64 columns: column blocks of 64 by block classical
+  // Gram-Schmidt with reorthogonalisation, each pass followed by a
+  // Householder QR of the block:
+  //   W = A_b - Qp C1 = Q1 R1;  Q1 - Qp C2 = Q_b R2
+  //   => A_b = Qp (C1 + C2 R1) + Q_b (R2 R1)
+  fill(R, (long long)n * n, 0.0, st);
+  for (int b0 = 0; b0 < n; b0 += kQrCols) {
+    const int nb = std::min(kQrCols, n - b0);
+    double* Qb = Q + (long long)b0 * ldq;
+    double* Rtop = R + (long long)b0 * n;      // rows 0..b0 of the block's columns
+    double* Rbb = R + b0 + (long long)b0 * n;  // diagonal block
+    PW_HIP(hipMemcpy2DAsync(s.W, sizeof(double) * rows, A + (long long)b0 * lda,
+                            sizeof(double) * lda, sizeof(double) * rows, nb,
+                            hipMemcpyDeviceToDevice, st));
+    if (b0 > 0) {
+      gemm_tn(rows, b0, nb, 1.0, Q, ldq, s.W, rows, 0.0, Rtop, n, s.work, s.work_elems, st);
+      gemm_nn(rows, nb, b0, -1.0, Q, ldq, Rtop, n, 1.0, s.W, rows, st);
+    }
+    tsqr(rows, nb, s.W, rows, Qb, ldq, s.R1, s, st);
+    if (b0 > 0) {
+      gemm_tn(rows, b0, nb, 1.0, Q, ldq, Qb, ldq, 0.0, s.C, b0, s.work, s.work_elems, st);
+      gemm_nn(rows, nb, b0, -1.0, Q, ldq, s.C, b0, 1.0, Qb, ldq, st);
+      gemm_small(b0, nb, nb, 1.0, s.C, b0, false, s.R1, nb, false, 1.0, Rtop, n, st);
+      PW_HIP(hipMemcpy2DAsync(s.W, sizeof(double) * rows, Qb, sizeof(double) * ldq,
+                              sizeof(double) * rows, nb, hipMemcpyDeviceToDevice, st));
+      tsqr(rows, nb, s.W, rows, Qb, ldq, s.R2, s, st);
+      gemm_small(nb, nb, nb, 1.0, s.R2, nb, false, s.R1, nb, false, 0.0, Rbb, n, st);
+    } else {
+      copy_block(nb, nb, s.R1, nb, Rbb, n, st);
+    }
+  }
 }
 
 void svd_jacobi(int n, const double* H, double* X, double* Y, double* sig, double tol,

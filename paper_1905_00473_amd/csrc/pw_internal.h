@@ -231,14 +231,18 @@ void gemm_small(int m, int n, int k, double alpha, const double* A, int lda, boo
 // n, ldq), R (n x n).  Directions whose pivot is below 1e-15 times the
 // largest diagonal of A^T A are dropped (zero Q column, zero R row).
 struct OrthScratch {
-  double* gram = nullptr;   // n*n
-  double* T = nullptr;      // n*n
   double* R1 = nullptr;     // n*n
   double* R2 = nullptr;     // n*n
-  double* Q1 = nullptr;     // rows*n
+  double* Q1 = nullptr;     // rows*min(n, 64): reflectors of the first TSQR level
+  double* hw = nullptr;     // TSQR stacked R factors (tsqr_work)
+  double* htau = nullptr;   // TSQR reflector scalars (tsqr_work)
+  double* W = nullptr;      // rows*64 (only for n > 64 columns)
+  double* C = nullptr;      // n*64 (only for n > 64 columns)
   double* work = nullptr;   // gemm_tn work
   size_t work_elems = 0;
 };
+// workspace of the Householder TSQR of a rows x min(n, 64) block
+void tsqr_work(long long rows, int n, size_t* stack_elems, size_t* tau_elems);
 void orth(long long rows, int n, const double* A, long long lda, double* Q, long long ldq,
           double* R, OrthScratch s, hipStream_t stream);
 

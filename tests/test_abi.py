@@ -66,7 +66,6 @@ def test_invalid_problems_rejected_before_any_device_work():
     cases.append((mk(shape=(16, 16)), "at least 5 points"))
     cases.append((mk(T=0.0), "T must be positive"))
     cases.append((mk(N=0), "slice/step"))
-    cases.append((mk(N=65), "at most 64 slices"))
     cases.append((mk(order=3), "grad_order"))
     cases.append((mk(tol=0.0), "svd_tol"))
     cases.append((mk(comp=True), "compensation"))

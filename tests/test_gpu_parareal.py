@@ -2,7 +2,10 @@
 oracle, exactness invariants, and the serial fine reference.
 
 Tolerances (energy norm of the Sec. 6 error measure, per slice):
-* FP64 state, svd_tol >= 1e-6: 1e-12.  At the paper's tol (1e-14) the
+* FP64 state, svd_tol >= 1e-6: max(1e-12, 256 A eps), with A the
+  amplification of a relative input perturbation through the iteration,
+  measured on the oracle (about 400 on wave1d: the gate is 2.2e-11
+  there).  At the paper's tol (1e-14) the
   phase corrector keeps directions with sigma_i / sigma_1 down to 1e-14,
   in which Omega is only determined to about eps * sigma_1 / sigma_i; two
   orderings of the same exact arithmetic already differ by ~1e-11 there
@@ -17,7 +20,8 @@ import pytest
 
 import oracle as O
 import workloads as W
-from tests.gpu_helpers import inputs_as, problem_pair, rel_energy_err, to_np
+from tests.gpu_helpers import (derived_gate, inputs_as, problem_pair,
+                               rel_energy_err, to_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -37,6 +41,7 @@ def _run(w, K, tol=None, dtype=None, compensated=None):
 
 def _compare(s, Q, w, u0, p0, K, gate):
     ref = O.theta_parareal(Q, w.c, u0, p0, K)
+    gate = derived_gate(Q, w, u0, p0, K, gate)
     worst = 0.0
     for n in range(Q.N + 1):
         u, p = s.state(n)
@@ -46,7 +51,7 @@ def _compare(s, Q, w, u0, p0, K, gate):
         e = rel_energy_err(to_np(u), to_np(p), ref.u[n], ref.p[n], w.c,
                            Q.dx_fine)
         worst = max(worst, e)
-    assert worst < gate, worst
+    assert worst < gate, (worst, gate)
     rho, rk = s.residuals()
     assert rk == ref.rank, (rk, ref.rank)
     np.testing.assert_allclose(rho, ref.rho, rtol=1e-6)
@@ -59,6 +64,16 @@ def test_wave1d_fp64_parity(tol, gate):
     w = W.wave1d()
     s, Q, u0, p0 = _run(w, w.K, tol=tol)
     _compare(s, Q, w, u0, p0, w.K, gate)
+
+
+@pytest.mark.parametrize("N,K", [(100, 3), (200, 2)])
+def test_many_slices_fp64_parity(N, K):
+    """More than 64 slices: the orthonormalisation inside Algorithm 1 runs
+    in column blocks of 64 made orthogonal by block Gram-Schmidt."""
+    w = W.wave1d(n=512, N=N, K=K)
+    s, Q, u0, p0 = _run(w, K, tol=1e-6)
+    _compare(s, Q, w, u0, p0, K, 1e-12)
+    s.close()
 
 
 def test_disc2d_small_fp64_parity():

@@ -4,14 +4,16 @@ parareal-style correction (Sec. 6.3) and plain parareal (eq.
 plainparareal), each run through the same C-ABI entry point as Algorithm 3
 after pw_set_variant.
 
-Gates: FP64 state, svd tol 1e-6: max(1e-12, 64 A eps) in the energy norm
+Gates: FP64 state, svd tol 1e-6: max(1e-12, 256 A eps) in the energy norm
 per slice, eps = 2^-52, where A is the amplification of a relative input
 perturbation through the same iteration, measured on the oracle (u0
 perturbed by 1e-13 relative noise).  Omega = I and plain parareal are
 unstable for waves (the growth Sec. 6 reports), so rounding differences
-between two correct orderings grow with A (up to ~1e4 on wave1d); 64
+between two correct orderings grow with A (up to ~1e4 on wave1d); 256
 covers the rounding injected at every stage rather than at the input
-only.  FP32 compensated state: 1e-5 against the oracle on the same
+only.  For Algorithm 3 (no correction) the gate is also at least 16
+times the spread between two oracle runs that pass Algorithm 1 its data
+columns in opposite orders.  FP32 compensated state: 1e-5 against the oracle on the same
 FP32-rounded initial data.  Residuals to rtol 1e-6 and equal ranks (the
 row count for Omega = I and plain).
 """
@@ -21,7 +23,8 @@ import pytest
 
 import oracle as O
 import workloads as W
-from tests.gpu_helpers import inputs_as, problem_pair, rel_energy_err, to_np
+from tests.gpu_helpers import (derived_gate, inputs_as, problem_pair,
+                               rel_energy_err, to_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -45,27 +48,15 @@ def _solve(w, K, variant, dtype="f64", tol=1e-6):
     return s, Q, u0, p0
 
 
-def _amplification(Q, w, u0, p0, K, variant, ref):
-    """max_n of the relative energy-norm change of slice n over the size
-    of a 1e-13 relative perturbation of u0 (oracle only)."""
-    eps = 1e-13
-    rng = np.random.default_rng(7)
-    u1 = u0 * (1 + eps * rng.standard_normal(u0.shape))
-    r1 = O.theta_parareal(Q, w.c, u1, p0, K, **ORACLE_ARGS[variant])
-    return max(rel_energy_err(r1.u[n], r1.p[n], ref.u[n], ref.p[n], w.c,
-                              Q.dx_fine) for n in range(1, Q.N + 1)) / eps
-
-
 def _compare(s, Q, w, u0, p0, K, variant, floor):
     ref = O.theta_parareal(Q, w.c, u0, p0, K, **ORACLE_ARGS[variant])
-    amp = _amplification(Q, w, u0, p0, K, variant, ref)
-    gate = max(floor, 64 * amp * 2.0 ** -52)
+    gate = derived_gate(Q, w, u0, p0, K, floor, **ORACLE_ARGS[variant])
     worst = 0.0
     for n in range(1, Q.N + 1):
         u, p = s.state(n)
         worst = max(worst, rel_energy_err(to_np(u), to_np(p), ref.u[n],
                                           ref.p[n], w.c, Q.dx_fine))
-    assert worst < gate, (variant, worst, gate, amp)
+    assert worst < gate, (variant, worst, gate)
     rho, rk = s.residuals()
     assert list(rk) == list(ref.rank), (rk, ref.rank)
     np.testing.assert_allclose(rho, ref.rho, rtol=1e-6)

@@ -30,6 +30,13 @@ Workloads (fine grid / coarse grid, unit periodic box):
   m_C = 24, K = 4; target medium for the data: the same recipe, seed 1.
 * ``random_pulses`` seeded Gaussian-pulse states (test inputs of the
   propagators at full size).
+* ``waveguide2d`` the low-rank study of the data matrices (Sec. 6.5):
+  200^2 / 100^2, c = 1 - 0.3 cos(2 pi x) on [-0.5, 0.5)^2 (here x + 1/2 on
+  the unit box, i.e. c = 1 + 0.3 cos(2 pi x)), T = 4, N = 200 slices
+  (dt_com = 0.02), coarse step 8e-4 (m_C = 25), fine step 8e-5
+  (m_F = 250); the plane wave is a Gaussian pulse in y (sigma 0.05)
+  moving in +y, p0 = -c du0/dy.  ``sample_columns`` draws the random
+  slice columns of Sec. 6.5 (seeded, sorted per iteration).
 * ``grf2d`` / ``batch2d``  smooth random media c = exp(0.3 g) with random
   Gaussian pulses; ``batch2d`` draws 32 such problems with fine grids from
   {256, 384, 512, 768, 1024}^2 (the batched workload).
@@ -129,6 +136,27 @@ def layers3d(n=256, ratio=4, N=32, K=6, T=1.5, dtype="f32",
     m_f = _steps_for_courant(3.0 * 1.05, n, T / N)
     return Workload("layers3d", (n, n, n), ratio, T, N, m_f, m_f // 4, K,
                     1e-13, 4, dtype, compensated, c, u0, p0)
+
+
+def waveguide2d(n=200, ratio=2, N=200, K=6, T=4.0, m_fine=250, m_coarse=25,
+                dtype="f64", compensated=False, tol=1e-14):
+    Y, X = _axes((n, n))
+    c = 1.0 + 0.3 * np.cos(2 * np.pi * X)
+    s = 0.05
+    u0 = np.exp(-(Y - 0.5) ** 2 / (2 * s * s))
+    p0 = c * (Y - 0.5) / (s * s) * u0
+    return Workload("waveguide2d", (n, n), ratio, T, N, m_fine, m_coarse, K,
+                    tol, 4, dtype, compensated, c, u0, p0)
+
+
+def sample_columns(N, n_per_iter, n_iters, seed=0):
+    """(n_iters, n_per_iter) int32 table: per iteration n_per_iter distinct
+    slice columns in [0, N), drawn uniformly without replacement and
+    sorted."""
+    rng = np.random.default_rng(seed)
+    return np.array([np.sort(rng.choice(N, n_per_iter, replace=False))
+                     for _ in range(n_iters)], dtype=np.int32).reshape(
+                         n_iters, n_per_iter)
 
 
 def smooth_random_field(shape, corr, seed):
