@@ -415,6 +415,10 @@ void setup(Prob& pr, const pw_problem& P) {
   pr.res = m.get_n<double>(2LL * (P.max_iters + 1));
   size_t tsq_st = 0, tsq_tau = 0;
   tsqr_work(rows, N, &tsq_st, &tsq_tau);
+  pr.os.gram = m.get_n<double>(64LL * 64);
+  pr.os.T = m.get_n<double>(64LL * 64);
+  pr.os.info = m.get_n<double>(16);
+  pr.os.gram_enough = !pr.f64;
   pr.os.R1 = m.get_n<double>((long long)N * N);
   pr.os.R2 = m.get_n<double>((long long)N * N);
   pr.os.Q1 = m.get_n<double>(rows * N);
@@ -427,6 +431,10 @@ void setup(Prob& pr, const pw_problem& P) {
   pr.os.work = pr.gwork;
   pr.os.work_elems = pr.gwork_elems;
   pr.gwork2 = m.get_n<double>((long long)pr.gwork_elems);
+  pr.os2.gram = m.get_n<double>(64LL * 64);
+  pr.os2.T = m.get_n<double>(64LL * 64);
+  pr.os2.info = m.get_n<double>(16);
+  pr.os2.gram_enough = !pr.f64;
   pr.os2.R1 = m.get_n<double>((long long)N * N);
   pr.os2.R2 = m.get_n<double>((long long)N * N);
   pr.os2.Q1 = m.get_n<double>(rows * N);
@@ -556,8 +564,12 @@ void update_svd_dev(Prob& pr, const double* F, const double* G, int ncols, hipSt
     G = pr.Gp;
   }
   if (r == 0) {
-    orth(rows, ncols, F, rows, U, rows, pr.RF, pr.os, st);
-    orth(rows, ncols, G, rows, V, rows, pr.RG, pr.os2, pr.side);
+    orth_begin(rows, ncols, F, rows, pr.os, st);
+    orth_begin(rows, ncols, G, rows, pr.os2, pr.side);
+    const bool cf = orth_choose(rows, ncols, pr.os, st);
+    const bool cg = orth_choose(rows, ncols, pr.os2, pr.side);
+    orth_finish(rows, ncols, F, rows, U, rows, pr.RF, pr.os, cf, st);
+    orth_finish(rows, ncols, G, rows, V, rows, pr.RG, pr.os2, cg, pr.side);
     PW_HIP(hipEventRecord(pr.join_ev, pr.side));
     PW_HIP(hipStreamWaitEvent(st, pr.join_ev, 0));
     gemm_small(ncols, ncols, ncols, 1.0, pr.RF, ncols, false, pr.RG, ncols, true, 0.0, pr.H,
@@ -572,8 +584,12 @@ void update_svd_dev(Prob& pr, const double* F, const double* G, int ncols, hipSt
                             pr.side));
     project_out(pr, rows, r, ncols, U, pr.Fp, pr.UF, pr.UF2, pr.gwork, st);
     project_out(pr, rows, r, ncols, V, pr.Gp, pr.VG, pr.VG2, pr.gwork2, pr.side);
-    orth(rows, ncols, pr.Fp, rows, U + rows * r, rows, pr.RF, pr.os, st);
-    orth(rows, ncols, pr.Gp, rows, V + rows * r, rows, pr.RG, pr.os2, pr.side);
+    orth_begin(rows, ncols, pr.Fp, rows, pr.os, st);
+    orth_begin(rows, ncols, pr.Gp, rows, pr.os2, pr.side);
+    const bool cf = orth_choose(rows, ncols, pr.os, st);
+    const bool cg = orth_choose(rows, ncols, pr.os2, pr.side);
+    orth_finish(rows, ncols, pr.Fp, rows, U + rows * r, rows, pr.RF, pr.os, cf, st);
+    orth_finish(rows, ncols, pr.Gp, rows, V + rows * r, rows, pr.RG, pr.os2, cg, pr.side);
     PW_HIP(hipEventRecord(pr.join_ev, pr.side));
     PW_HIP(hipStreamWaitEvent(st, pr.join_ev, 0));
     n = r + ncols;

@@ -263,6 +263,118 @@ __device__ __forceinline__ int rr_index(int j, int round, int np) {
   return j == 0 ? 0 : ((j - 1 + round) % (np - 1)) + 1;
 }
 
+constexpr int kCholMax = 64;
+
+// Truncated pivoted Cholesky of the Gram matrix G = A^T A (n x n, n <= 64)
+// in one workgroup, and the two factors of the orthonormalisation
+// Q = A T, A ~ Q R:  with P G P^T = L L^T truncated at rank k (the pivot
+// steps stop when the largest remaining diagonal entry is <= rel times the
+// largest diagonal of G, or <= abs_thr), R = L^T P^T (rows k.. zero) and
+// T = P [L_11^{-T}; 0] (columns k.. zero).  T and R are column-major n x n.
+__global__ __launch_bounds__(1024) void k_pchol_factors(int n, const double* Gg, double rel,
+                                                        double abs_thr, double* T, double* R,
+                                                        double* info) {
+  __shared__ double A[kCholMax][kCholMax + 1];   // trailing Gram matrix
+  __shared__ double Rm[kCholMax][kCholMax + 1];  // rows of L^T, pivoted column order
+  __shared__ double X[kCholMax][kCholMax + 1];   // inverse of the leading k x k block
+  __shared__ int perm[kCholMax];
+  __shared__ int piv_s, stop_s;
+  __shared__ double d0_s;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, x = tid & 63, y = tid >> 6;
+  for (int m = 0; m < 4; ++m) {
+    const int k = y + 16 * m;
+    A[x][k] = (x < n && k < n) ? Gg[x + (long long)k * n] : 0.0;
+    Rm[x][k] = 0.0;
+    X[x][k] = 0.0;
+  }
+  if (tid < kCholMax) perm[tid] = tid;
+  __syncthreads();
+  int rank = n;
+  for (int j = 0; j < n; ++j) {
+    if (tid < 64) {
+      // pivot: largest remaining diagonal entry (lowest index on ties)
+      double v = (lane >= j && lane < n) ? A[lane][lane] : -1.0;
+      int idx = lane;
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(v, off, 64);
+        const int oi = __shfl_xor(idx, off, 64);
+        if (ov > v || (ov == v && oi < idx)) {
+          v = ov;
+          idx = oi;
+        }
+      }
+      if (lane == 0) {
+        if (j == 0) d0_s = v;
+        const double d0 = j == 0 ? v : d0_s;
+        piv_s = idx;
+        stop_s = (!(v > rel * d0) || !(v > abs_thr)) ? 1 : 0;
+      }
+    }
+    __syncthreads();
+    if (stop_s) {
+      rank = j;
+      break;
+    }
+    const int pv = piv_s;
+    if (pv != j) {
+      if (tid < n) {
+        const double t = A[j][tid];
+        A[j][tid] = A[pv][tid];
+        A[pv][tid] = t;
+      }
+      __syncthreads();
+      if (tid < n) {
+        const double t = A[tid][j];
+        A[tid][j] = A[tid][pv];
+        A[tid][pv] = t;
+      }
+      if (tid < j) {
+        const double t = Rm[tid][j];
+        Rm[tid][j] = Rm[tid][pv];
+        Rm[tid][pv] = t;
+      }
+      if (tid == 0) {
+        const int t = perm[j];
+        perm[j] = perm[pv];
+        perm[pv] = t;
+      }
+      __syncthreads();
+    }
+    const double r = sqrt(A[j][j]);
+    if (tid >= j && tid < n) Rm[j][tid] = (tid == j) ? r : A[j][tid] / r;
+    __syncthreads();
+    for (int m = 0; m < 4; ++m) {
+      const int k = y + 16 * m;
+      if (x > j && x < n && k > j && k < n) A[x][k] -= Rm[j][x] * Rm[j][k];
+    }
+    __syncthreads();
+  }
+  // info: [kept rank, smallest kept pivot / largest diagonal]
+  if (info && tid == 0) {
+    info[0] = (double)rank;
+    info[1] = rank > 0 && d0_s > 0.0 ? (Rm[rank - 1][rank - 1] * Rm[rank - 1][rank - 1]) / d0_s : 0.0;
+  }
+  // X = (leading rank x rank block of L^T)^{-1}, one column per thread
+  if (tid < rank) {
+    const int b = tid;
+    X[b][b] = 1.0 / Rm[b][b];
+    for (int a = b - 1; a >= 0; --a) {
+      double s = 0.0;
+      for (int c = a + 1; c <= b; ++c) s += Rm[a][c] * X[c][b];
+      X[a][b] = -s / Rm[a][a];
+    }
+  }
+  __syncthreads();
+  for (int m = 0; m < 4; ++m) {
+    const int b = y + 16 * m, a = x;
+    if (a < n && b < n) {
+      T[perm[a] + (long long)b * n] = (a < rank && b < rank) ? X[a][b] : 0.0;
+      R[a + (long long)perm[b] * n] = (a < rank) ? Rm[a][b] : 0.0;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // one-sided Jacobi SVD: one launch per round of disjoint column pairs
 // ---------------------------------------------------------------------------
@@ -842,20 +954,21 @@ __device__ __forceinline__ void qr_chunk(long long M, int nch, int c, long long&
 
 // Householder QR of chunk blockIdx.x of A (M x n, n <= 64): reflector j is
 // I - tau_j v v^T with v_j = 1 and v_i (i > j) stored in V below the
-// diagonal (LAPACK's convention); tau to tau[c * n + j]; the n x n R factor
-// (rows >= min(m, n) zero) to rows [c n, c n + n) of Rout.  V may alias A
-// (each thread reads its part of the chunk before anything is written).
-// Thread (k, s) = (t mod 64, t / 64) holds column k of the rows i = s + 4 q
-// in registers; the current reflector column is shared through LDS, so a
-// step costs 2 x 64 register FMAs per thread plus two small reductions.
+// diagonal (LAPACK's convention; V is zero elsewhere); tau to
+// tau[c * n + j]; the n x n R factor (rows >= min(m, n) zero) to rows
+// [c n, c n + n) of Rout.  V may alias A (the chunk is read completely
+// before anything is written).  Thread (k, s) = (t mod 64, t / 64) holds
+// column k of the rows i = s + 4 q in registers; wave 0 finishes each
+// reflector in LDS (kept there until the end), so a step costs 2 x 64
+// register FMAs per thread and no global memory access.
 __global__ __launch_bounds__(256) void k_hqr_chunk(long long M, int n, int nch, const double* A,
                                                    long long lda, double* V, long long ldv,
                                                    double* tau, double* Rout, long long ldr) {
-  __shared__ double vcol[kQrRows];
+  __shared__ double vs[kQrCols * kQrRows];  // reflector j in vs[j * kQrRows + i]
   __shared__ double part[4 * kQrCols];
   __shared__ double w[kQrCols];
   __shared__ double taus[kQrCols];
-  __shared__ double s_beta, s_scale;
+  __shared__ double betas[kQrCols];
   long long off;
   int m;
   qr_chunk(M, nch, blockIdx.x, off, m);
@@ -868,6 +981,7 @@ __global__ __launch_bounds__(256) void k_hqr_chunk(long long M, int n, int nch, 
   }
   const int r = m < n ? m : n;
   for (int j = 0; j < r; ++j) {
+    double* vcol = vs + j * kQrRows;
     if (k == j) {
 #pragma unroll
       for (int q = 0; q < kQrRPT; ++q) {
@@ -877,45 +991,34 @@ __global__ __launch_bounds__(256) void k_hqr_chunk(long long M, int n, int nch, 
     }
     __syncthreads();
     if (seg == 0) {
+      // every lane of wave 0 forms the reflector (beta, tau, 1 / (alpha -
+      // beta)) from the butterfly sum, then finishes its four entries of v
       double s = 0.0;
       for (int i = j + 1 + k; i < m; i += 64) s = fma(vcol[i], vcol[i], s);
       s = wave_sum(s);
+      const double alpha = vcol[j];
+      double beta = alpha, tj = 0.0, sc = 0.0;
+      if (s != 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + s), alpha);
+        tj = (beta - alpha) / beta;
+        sc = 1.0 / (alpha - beta);
+      }
+      for (int i = k; i < kQrRows; i += 64) vcol[i] = i == j ? 1.0 : (i > j ? vcol[i] * sc : 0.0);
       if (k == 0) {
-        const double alpha = vcol[j];
-        if (s == 0.0) {
-          taus[j] = 0.0;
-          s_beta = alpha;
-          s_scale = 0.0;
-        } else {
-          const double beta = -copysign(sqrt(alpha * alpha + s), alpha);
-          taus[j] = (beta - alpha) / beta;
-          s_scale = 1.0 / (alpha - beta);
-          s_beta = beta;
-        }
+        taus[j] = tj;
+        betas[j] = beta;
       }
     }
     __syncthreads();
-    const double tj = taus[j], sc = s_scale;
-    if (k == j) {  // the pivot column becomes [.., beta, v]
-#pragma unroll
-      for (int q = 0; q < kQrRPT; ++q) {
-        const int i = seg + 4 * q;
-        if (i == j) reg[q] = s_beta;
-        else if (i > j) reg[q] *= sc;
-      }
-    }
+    const double tj = taus[j];
     if (tj != 0.0) {
       // w_k = tau sum_{i >= j} v_i a_ik, k > j
-      double acc = 0.0;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};  // four independent FMA chains
       if (k > j && k < n) {
 #pragma unroll
-        for (int q = 0; q < kQrRPT; ++q) {
-          const int i = seg + 4 * q;
-          const double v = i == j ? 1.0 : (i > j ? vcol[i] * sc : 0.0);
-          acc = fma(v, reg[q], acc);
-        }
+        for (int q = 0; q < kQrRPT; ++q) acc[q & 3] = fma(vcol[seg + 4 * q], reg[q], acc[q & 3]);
       }
-      part[seg * kQrCols + k] = acc;
+      part[seg * kQrCols + k] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
       __syncthreads();
       if (t > j && t < n)
         w[t] = tj * ((part[t] + part[kQrCols + t]) + (part[2 * kQrCols + t] + part[3 * kQrCols + t]));
@@ -923,44 +1026,44 @@ __global__ __launch_bounds__(256) void k_hqr_chunk(long long M, int n, int nch, 
       if (k > j && k < n) {
         const double wk = w[k];
 #pragma unroll
-        for (int q = 0; q < kQrRPT; ++q) {
-          const int i = seg + 4 * q;
-          const double v = i == j ? 1.0 : (i > j ? vcol[i] * sc : 0.0);
-          reg[q] = fma(-wk, v, reg[q]);
-        }
+        for (int q = 0; q < kQrRPT; ++q) reg[q] = fma(-wk, vcol[seg + 4 * q], reg[q]);
       }
+      __syncthreads();  // part is rewritten by the next step
     }
-    __syncthreads();  // vcol and part are rewritten by the next step
   }
-#pragma unroll
-  for (int q = 0; q < kQrRPT; ++q) {
-    const int i = seg + 4 * q;
-    if (k < n && i < m) V[(off + i) + (long long)k * ldv] = (k < r && i > k) ? reg[q] : 0.0;
-  }
+  for (int k2 = 0; k2 < n; ++k2)
+    if (t < m) V[(off + t) + (long long)k2 * ldv] = (k2 < r && t > k2) ? vs[k2 * kQrRows + t] : 0.0;
   if (t < n) tau[(long long)blockIdx.x * n + t] = t < r ? taus[t] : 0.0;
 #pragma unroll
   for (int q = 0; q < kQrRPT; ++q) {
     const int i = seg + 4 * q;
-    if (k < n && i < n)
-      Rout[((long long)blockIdx.x * n + i) + (long long)k * ldr] =
-          (i <= k && i < r) ? reg[q] : 0.0;
+    if (k < n && i < n) {
+      double val = 0.0;
+      if (i < r && i < k) val = reg[q];
+      else if (i < r && i == k) val = betas[i];
+      Rout[((long long)blockIdx.x * n + i) + (long long)k * ldr] = val;
+    }
   }
 }
 
 // Q rows of chunk blockIdx.x: the chunk's reflectors applied, last first,
-// to [Qup rows c n .. c n + n - 1; 0] (Qup null: [I; 0]).  Q may alias V.
-// Same register layout as k_hqr_chunk.
+// to [Qup rows c n .. c n + n - 1; 0] (Qup null: [I; 0]).  Q may alias V
+// (the reflectors are staged in LDS first).  Same register layout as
+// k_hqr_chunk.
 __global__ __launch_bounds__(256) void k_hqr_formq(long long M, int n, int nch, const double* V,
                                                    long long ldv, const double* tau,
                                                    const double* Qup, long long ldu, double* Q,
                                                    long long ldq) {
-  __shared__ double vcol[kQrRows];
+  __shared__ double vs[kQrCols * kQrRows];
   __shared__ double part[4 * kQrCols];
   __shared__ double w[kQrCols];
   long long off;
   int m;
   qr_chunk(M, nch, blockIdx.x, off, m);
   const int t = threadIdx.x, k = t & 63, seg = t >> 6;
+  const int r = m < n ? m : n;
+  for (int j = 0; j < r; ++j)
+    vs[j * kQrRows + t] = t == j ? 1.0 : ((t > j && t < m) ? V[(off + t) + (long long)j * ldv] : 0.0);
   double reg[kQrRPT];
 #pragma unroll
   for (int q = 0; q < kQrRPT; ++q) {
@@ -970,18 +1073,17 @@ __global__ __launch_bounds__(256) void k_hqr_formq(long long M, int n, int nch, 
       val = Qup ? Qup[((long long)blockIdx.x * n + i) + (long long)k * ldu] : (i == k ? 1.0 : 0.0);
     reg[q] = val;
   }
-  const int r = m < n ? m : n;
+  __syncthreads();
   for (int j = r - 1; j >= 0; --j) {
     const double tj = tau[(long long)blockIdx.x * n + j];
     if (tj == 0.0) continue;  // the same for every thread of the block
-    vcol[t] = t == j ? 1.0 : ((t > j && t < m) ? V[(off + t) + (long long)j * ldv] : 0.0);
-    __syncthreads();
-    double acc = 0.0;
+    const double* vcol = vs + j * kQrRows;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};  // four independent FMA chains
     if (k < n) {
 #pragma unroll
-      for (int q = 0; q < kQrRPT; ++q) acc = fma(vcol[seg + 4 * q], reg[q], acc);
+      for (int q = 0; q < kQrRPT; ++q) acc[q & 3] = fma(vcol[seg + 4 * q], reg[q], acc[q & 3]);
     }
-    part[seg * kQrCols + k] = acc;
+    part[seg * kQrCols + k] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     __syncthreads();
     if (t < n)
       w[t] = tj * ((part[t] + part[kQrCols + t]) + (part[2 * kQrCols + t] + part[3 * kQrCols + t]));
@@ -991,7 +1093,7 @@ __global__ __launch_bounds__(256) void k_hqr_formq(long long M, int n, int nch, 
 #pragma unroll
       for (int q = 0; q < kQrRPT; ++q) reg[q] = fma(-wk, vcol[seg + 4 * q], reg[q]);
     }
-    __syncthreads();  // vcol and part are rewritten by the next step
+    __syncthreads();  // part is rewritten by the next step
   }
 #pragma unroll
   for (int q = 0; q < kQrRPT; ++q) {
@@ -1071,9 +1173,55 @@ static void tsqr(long long rows, int n, const double* A, long long lda, double* 
   }
 }
 
-void orth(long long rows, int n, const double* A, long long lda, double* Q, long long ldq,
-          double* R, OrthScratch s, hipStream_t st) {
+void pchol_factors(int n, const double* G, double rel, double abs_thr, double* T, double* R,
+                   double* info, hipStream_t st) {
+  if (n > kCholMax) fail(PW_EINVAL, "a Cholesky QR block holds at most 64 columns");
   if (n <= 0) return;
+  hipLaunchKernelGGL(k_pchol_factors, dim3(1), dim3(1024), 0, st, n, G, rel, abs_thr, T, R, info);
+  PW_LAUNCH_CHECK();
+}
+
+// Two ways to factor A = Q R inside Algorithm 1.  Cholesky QR twice
+// (Gram matrix, pivoted Cholesky, Q = A T, repeated on Q) costs a few
+// GEMMs and is as accurate as Householder QR when A is well conditioned
+// (kappa(A) below about 1 / sqrt(11 (rows n + n^2) eps)); beyond that its
+// Gram matrix loses the small directions, and the Householder TSQR above
+// is used.  orth_begin forms the Gram matrix and its pivoted Cholesky
+// factor (with a report of the smallest pivot), orth_choose reads the
+// report (synchronising the stream), orth_finish completes either method.
+// With FP32 states the data carry rounding of ~6e-8 of their size, so
+// the truncation of Cholesky QR at ~3e-8 loses nothing and it is always
+// used (gram_enough).
+void orth_begin(long long rows, int n, const double* A, long long lda, const OrthScratch& s,
+                hipStream_t st) {
+  if (n <= 0 || n > kCholMax) return;
+  gemm_tn(rows, n, n, 1.0, A, lda, A, lda, 0.0, s.gram, n, s.work, s.work_elems, st);
+  pchol_factors(n, s.gram, 1e-15, 1e-290, s.T, s.R1, s.info, st);
+}
+
+bool orth_choose(long long rows, int n, const OrthScratch& s, hipStream_t st) {
+  if (n <= 0 || n > kCholMax) return false;
+  if (s.gram_enough) return true;
+  double h[2] = {0.0, 0.0};
+  PW_HIP(hipMemcpyAsync(h, s.info, sizeof(h), hipMemcpyDeviceToHost, st));
+  PW_HIP(hipStreamSynchronize(st));
+  const double thr = 11.0 * ((double)rows * n + (double)n * n) * 2.220446049250313e-16;
+  // kept rank n and sigma_min^2 / sigma_max^2 (the smallest pivot ratio)
+  // at least 100 thr: Cholesky QR twice is backward stable there
+  return (int)h[0] == n && h[1] > 100.0 * thr;
+}
+
+void orth_finish(long long rows, int n, const double* A, long long lda, double* Q, long long ldq,
+                 double* R, const OrthScratch& s, bool cholqr, hipStream_t st) {
+  if (n <= 0) return;
+  if (cholqr) {
+    gemm_nn(rows, n, n, 1.0, A, lda, s.T, n, 0.0, s.Q1, rows, st);
+    gemm_tn(rows, n, n, 1.0, s.Q1, rows, s.Q1, rows, 0.0, s.gram, n, s.work, s.work_elems, st);
+    pchol_factors(n, s.gram, 0.0, 0.25, s.T, s.R2, nullptr, st);
+    gemm_nn(rows, n, n, 1.0, s.Q1, rows, s.T, n, 0.0, Q, ldq, st);
+    gemm_small(n, n, n, 1.0, s.R2, n, false, s.R1, n, false, 0.0, R, n, st);
+    return;
+  }
   if (n <= kQrCols) {
     tsqr(rows, n, A, lda, Q, ldq, R, s, st);
     return;
@@ -1109,6 +1257,13 @@ void orth(long long rows, int n, const double* A, long long lda, double* Q, long
       copy_block(nb, nb, s.R1, nb, Rbb, n, st);
     }
   }
+}
+
+void orth(long long rows, int n, const double* A, long long lda, double* Q, long long ldq,
+          double* R, OrthScratch s, hipStream_t st) {
+  orth_begin(rows, n, A, lda, s, st);
+  const bool c = orth_choose(rows, n, s, st);
+  orth_finish(rows, n, A, lda, Q, ldq, R, s, c, st);
 }
 
 void svd_jacobi(int n, const double* H, double* X, double* Y, double* sig, double tol,

@@ -231,6 +231,13 @@ void gemm_small(int m, int n, int k, double alpha, const double* A, int lda, boo
 // n, ldq), R (n x n).  Directions whose pivot is below 1e-15 times the
 // largest diagonal of A^T A are dropped (zero Q column, zero R row).
 struct OrthScratch {
+  double* gram = nullptr;   // n*n (n <= 64)
+  double* T = nullptr;      // n*n (n <= 64)
+  double* info = nullptr;   // 2: pivoted Cholesky report
+  // accept the Gram-based truncation at ~sqrt(eps) of the largest
+  // direction whatever the conditioning (data from FP32 states, whose own
+  // rounding is larger than that)
+  bool gram_enough = false;
   double* R1 = nullptr;     // n*n
   double* R2 = nullptr;     // n*n
   double* Q1 = nullptr;     // rows*min(n, 64): reflectors of the first TSQR level
@@ -245,6 +252,16 @@ struct OrthScratch {
 void tsqr_work(long long rows, int n, size_t* stack_elems, size_t* tau_elems);
 void orth(long long rows, int n, const double* A, long long lda, double* Q, long long ldq,
           double* R, OrthScratch s, hipStream_t stream);
+// the same in three steps, so that two factorisations on two streams can
+// be started before either stream is synchronised: orth_begin enqueues
+// the Gram matrix and its pivoted Cholesky factor, orth_choose
+// synchronises the stream and returns whether Cholesky QR is accurate
+// enough, orth_finish enqueues the chosen method
+void orth_begin(long long rows, int n, const double* A, long long lda, const OrthScratch& s,
+                hipStream_t stream);
+bool orth_choose(long long rows, int n, const OrthScratch& s, hipStream_t stream);
+void orth_finish(long long rows, int n, const double* A, long long lda, double* Q, long long ldq,
+                 double* R, const OrthScratch& s, bool cholqr, hipStream_t stream);
 
 // one-sided Jacobi SVD of the n x n matrix H (column-major, ld = n):
 // on return X (n x n, ld n) holds left singular vectors, Y right singular
