@@ -79,7 +79,7 @@ typedef struct {
   int n_slices;        /* N coupling intervals                               */
   int m_fine;          /* fine steps per interval                            */
   int m_coarse;        /* coarse steps per interval                          */
-  int grad_order;      /* order of the central gradient nabla_h: 2 or 4      */
+  int grad_order;      /* order of the central gradient nabla_h: 2, 4, 6, 8  */
   double svd_tol;      /* relative rank tolerance of Algorithm 1 (> 0)       */
   int state_dtype;     /* pw_dtype of u, p                                   */
   int compensated;     /* FP32 only: compensated (Kahan) accumulation in F/C */

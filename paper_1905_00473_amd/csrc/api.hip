@@ -284,7 +284,8 @@ void validate(const pw_problem& P) {
   }
   if (!(P.T > 0)) fail(PW_EINVAL, "T must be positive");
   if (P.n_slices < 1 || P.m_fine < 1 || P.m_coarse < 1) fail(PW_EINVAL, "bad slice/step counts");
-  if (P.grad_order != 2 && P.grad_order != 4) fail(PW_EINVAL, "grad_order must be 2 or 4");
+  if (P.grad_order != 2 && P.grad_order != 4 && P.grad_order != 6 && P.grad_order != 8)
+    fail(PW_EINVAL, "grad_order must be 2, 4, 6 or 8");
   if (!(P.svd_tol > 0)) fail(PW_EINVAL, "svd_tol must be positive");
   if (P.state_dtype != PW_F32 && P.state_dtype != PW_F64) fail(PW_EINVAL, "bad state dtype");
   if (P.compensated && P.state_dtype != PW_F32) fail(PW_EINVAL, "compensation is an FP32 mode");

@@ -1,7 +1,7 @@
 // Grid transfer and energy components:
 //  * restriction R (pointwise, coarse node J = fine node ratio*J, Sec. 3.1)
 //  * energy components Lambda[U, P] = [nabla_h U ; P / c] (eqs. matrixF /
-//    matrixG) with the central gradient of order 2 or 4
+//    matrixG) with the central gradient of order 2, 4, 6 or 8
 //  * trigonometric interpolation I (the Fourier interpolation of Sec. 6)
 //    evaluated as a separable polyphase convolution with the periodic
 //    Dirichlet-type kernel of the zero-padded spectrum, the Nyquist
@@ -34,8 +34,21 @@ struct GridArg {
 
 inline GridArg garg(const Grid& g) { return GridArg{g.dim, g.n[0], g.n[1], g.n[2], g.dx}; }
 
-// central first difference of order 2 or 4 along axis `ax` at coarse point
-// (X, Y, Z) of a field sampled at fine index ratio * coarse index
+// weight b_j of f(x + j h) - f(x - j h) in the central first difference of
+// order 2m = order (j = 1..m): b_j = 2 (-1)^(j+1) (m!)^2 / (j (m-j)! (m+j)!),
+// the coefficients of the Taylor-matched antisymmetric stencil
+__device__ __forceinline__ double fd_weight(int order, int j) {
+  switch (order) {
+    case 2: return 0.5;
+    case 4: return j == 1 ? 2.0 / 3.0 : -1.0 / 12.0;
+    case 6: return j == 1 ? 3.0 / 4.0 : (j == 2 ? -3.0 / 20.0 : 1.0 / 60.0);
+    default:  // 8
+      return j == 1 ? 4.0 / 5.0 : (j == 2 ? -1.0 / 5.0 : (j == 3 ? 4.0 / 105.0 : -1.0 / 280.0));
+  }
+}
+
+// central first difference of order 2, 4, 6 or 8 along axis `ax` at coarse
+// point (X, Y, Z) of a field sampled at fine index ratio * coarse index
 template <typename T>
 __device__ __forceinline__ double grad_at(const T* f, int ax, int X, int Y, int Z, const GridArg& c,
                                           int ratio, int fnx, int fny, int order) {
@@ -48,12 +61,8 @@ __device__ __forceinline__ double grad_at(const T* f, int ax, int X, int Y, int 
         (long long)x * ratio + (long long)fnx * ((long long)y * ratio + (long long)fny * z * ratio);
     return (double)f[gi];
   };
-  double d;
-  if (order == 4) {
-    d = (2.0 / 3.0) * (val(1) - val(-1)) + (-1.0 / 12.0) * (val(2) - val(-2));
-  } else {
-    d = 0.5 * (val(1) - val(-1));
-  }
+  double d = 0.0;
+  for (int j = 1; j <= order / 2; ++j) d += fd_weight(order, j) * (val(j) - val(-j));
   return d / c.dx;
 }
 
@@ -502,8 +511,8 @@ __global__ void k_energy_pair(const T* u, const T* p, const T* ur, const T* pr, 
           const long long gi = (long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z);
           return (double)u[gi] - (double)ur[gi];
         };
-        double d = order == 4 ? (2.0 / 3.0) * (val(1) - val(-1)) + (-1.0 / 12.0) * (val(2) - val(-2))
-                              : 0.5 * (val(1) - val(-1));
+        double d = 0.0;
+        for (int j = 1; j <= order / 2; ++j) d += fd_weight(order, j) * (val(j) - val(-j));
         d /= g.dx;
         a0 += d * d;
         const double e = grad_at(ur, a, X, Y, Z, g, 1, g.nx, g.ny, order);

@@ -67,6 +67,7 @@ def test_invalid_problems_rejected_before_any_device_work():
     cases.append((mk(T=0.0), "T must be positive"))
     cases.append((mk(N=0), "slice/step"))
     cases.append((mk(order=3), "grad_order"))
+    cases.append((mk(order=10), "grad_order"))
     cases.append((mk(tol=0.0), "svd_tol"))
     cases.append((mk(comp=True), "compensation"))
     cases.append((mk(max_iters=0), "max_iters"))
