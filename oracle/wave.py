@@ -68,7 +68,9 @@ class Problem:
     nodes overlap with the fine grid nodes").  ``T``: final time, ``N``:
     number of coupling intervals of length dt_com = T/N.  ``m_fine`` /
     ``m_coarse``: steps per interval of F and C (Sec. 3.1).  ``length``: box
-    length L per axis.
+    length L per axis.  ``interp``: the interpolation I, trigonometric
+    (the interpft of Sec. 6) or periodic piecewise linear (one of the
+    lower-order interpolants the numerical examples of Sec. 7 also use).
     """
 
     shape: tuple
@@ -80,6 +82,7 @@ class Problem:
     grad_order: object = 4
     tol: float = 1e-14
     length: float = 1.0
+    interp: str = "trig"    # I: "trig" (interpft) or "linear"
 
     @property
     def dim(self):
@@ -174,17 +177,35 @@ def _interp_axis(U, ratio, ax):
     return np.moveaxis(out, -1, ax)
 
 
-def interp(U, ratio):
-    """Trigonometric (Fourier) interpolation I from the coarse to the fine
-    grid, one axis at a time: the coarse spectrum is zero-padded, the
-    Nyquist coefficient of an even length is split between +n/2 and -n/2,
-    and the real part of the inverse transform is returned (the `interpft`
-    interpolation of Sec. 6)."""
+def _interp_axis_linear(U, ratio, ax):
+    # fine node ratio*J + s lies at J + s/ratio in coarse units, between
+    # coarse nodes J and J + 1 (periodic)
+    A = np.moveaxis(U, ax, -1)
+    n = A.shape[-1]
+    out = np.zeros(A.shape[:-1] + (n * ratio,))
+    for J in range(n):
+        for s in range(ratio):
+            t = s / ratio
+            out[..., J * ratio + s] = (1.0 - t) * A[..., J] + t * A[..., (J + 1) % n]
+    return np.moveaxis(out, -1, ax)
+
+
+def interp(U, ratio, kind="trig"):
+    """Interpolation I from the coarse to the fine grid, one axis at a time.
+    ``kind='trig'``: trigonometric (Fourier) interpolation: the coarse
+    spectrum is zero-padded, the Nyquist coefficient of an even length is
+    split between +n/2 and -n/2, and the real part of the inverse transform
+    is returned (the `interpft` interpolation of Sec. 6).
+    ``kind='linear'``: periodic piecewise-linear interpolation between
+    neighbouring coarse nodes."""
+    if kind not in ("trig", "linear"):
+        raise ValueError(kind)
     out = np.asarray(U, dtype=np.float64)
     if ratio == 1:
         return np.array(out, copy=True)
     for ax in range(out.ndim):
-        out = _interp_axis(out, ratio, ax)
+        out = (_interp_axis(out, ratio, ax) if kind == "trig"
+               else _interp_axis_linear(out, ratio, ax))
     return out
 
 
@@ -395,6 +416,7 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
     input.  rho_k is still measured on all N columns.
     """
     r = prob.ratio
+    ik = prob.interp
     N = prob.N
     cf = np.asarray(c, dtype=np.float64)
     cc = restrict(cf, r)
@@ -417,7 +439,7 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
     p = [np.array(p0, dtype=np.float64)] + [None] * N
     for n in range(1, N + 1):
         W, Wp = Cprop(restrict(u[n - 1], r), restrict(p[n - 1], r))
-        u[n], p[n] = interp(W, r), interp(Wp, r)
+        u[n], p[n] = interp(W, r, ik), interp(Wp, r, ik)
     history = [([x.copy() for x in u], [x.copy() for x in p])] \
         if keep_history else []
 
@@ -470,10 +492,10 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
                 # eq. plainparareal: I C R u^{k+1}_{n-1} + F u^k_{n-1}
                 #                    - I C R u^k_{n-1}
                 if correction:
-                    un[n] = v[n] + interp(w - Uc[n], r)
-                    pn[n] = vp[n] + interp(wp - Ucp[n], r)
+                    un[n] = v[n] + interp(w - Uc[n], r, ik)
+                    pn[n] = vp[n] + interp(wp - Ucp[n], r, ik)
                 else:
-                    un[n], pn[n] = interp(w, r), interp(wp, r)
+                    un[n], pn[n] = interp(w, r, ik), interp(wp, r, ik)
                 continue
             zq = Om(Lam(w, wp))
             q, pq = split_components(zq, cshape)
@@ -484,11 +506,11 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
                 qt1 = grad2func(qt, np.sum(Uc[n]), dxc)
                 du = q1 - qt1
                 dp = cc * (pq - pt)
-                un[n] = v[n] + interp(du, r)
-                pn[n] = vp[n] + interp(dp, r)
+                un[n] = v[n] + interp(du, r, ik)
+                pn[n] = vp[n] + interp(dp, r, ik)
             else:
-                un[n] = interp(q1, r)
-                pn[n] = interp(cc * pq, r)
+                un[n] = interp(q1, r, ik)
+                pn[n] = interp(cc * pq, r, ik)
         u, p = un, pn
         if keep_history:
             history.append(([x.copy() for x in u], [x.copy() for x in p]))

@@ -573,3 +573,55 @@ def test_subsample_rejects_bad_columns(bad):
     prob, c, u0, p0 = _subsample_problem()
     with pytest.raises(ValueError):
         O.theta_parareal(prob, c, u0, p0, K=1, sample_cols=bad)
+
+
+# ---------------------------------------------------------------------------
+# Periodic piecewise-linear I (a lower-order interpolant the numerical
+# examples of Sec. 7 use beside interpft)
+# ---------------------------------------------------------------------------
+def _np_interp_periodic(U, ratio):
+    # library routine on the periodic extension of the coarse samples
+    n = U.size
+    xc = np.arange(n + 1)
+    xf = np.arange(n * ratio) / ratio
+    return np.interp(xf, xc, np.append(U, U[0]))
+
+
+@pytest.mark.parametrize("n,ratio", [(7, 3), (12, 4), (5, 2)])
+def test_linear_interp_matches_library_and_restricts(n, ratio):
+    rng = np.random.default_rng(n * ratio)
+    U = rng.standard_normal(n)
+    f = O.interp(U, ratio, "linear")
+    np.testing.assert_allclose(f, _np_interp_periodic(U, ratio), atol=1e-14)
+    assert np.array_equal(O.restrict(f, ratio), U)          # R I = 1
+    # 2D: separable, each axis against the library routine
+    V = rng.standard_normal((n + 1, n))
+    g = O.interp(V, ratio, "linear")
+    ref = np.array([_np_interp_periodic(row, ratio) for row in V])
+    ref = np.array([_np_interp_periodic(col, ratio) for col in ref.T]).T
+    np.testing.assert_allclose(g, ref, atol=1e-13)
+    assert np.array_equal(O.restrict(g, ratio), V)
+
+
+def test_linear_interp_exactness_bitwise():
+    """The exactness of converged slices does not depend on I."""
+    n = 48
+    x = np.arange(n) / n
+    prob = O.Problem((n,), 4, 0.5, 6, 24, 6, 4, 1e-14, interp="linear")
+    c = 1 + 0.3 * np.sin(2 * np.pi * x)
+    u0 = np.exp(-(x - 0.5) ** 2 / 0.1 ** 2)
+    us, ps = O.serial_fine(prob, c, u0, np.zeros(n))
+    res = O.theta_parareal(prob, c, u0, np.zeros(n), K=3, keep_history=True)
+    for k, (hu, hp) in enumerate(res.history):
+        for m in range(0, k + 1):
+            assert np.array_equal(hu[m], us[m]) and np.array_equal(hp[m],
+                                                                   ps[m])
+    # and linear I really differs from interpft here
+    res_t = O.theta_parareal(O.Problem((n,), 4, 0.5, 6, 24, 6, 4, 1e-14), c,
+                             u0, np.zeros(n), K=1)
+    assert np.abs(res.history[1][0][-1] - res_t.u[-1]).max() > 1e-6
+
+
+def test_unknown_interp_raises():
+    with pytest.raises(ValueError):
+        O.interp(np.ones(4), 2, "cubic")
