@@ -85,7 +85,15 @@ typedef struct {
   int compensated;     /* FP32 only: compensated (Kahan) accumulation in F/C */
   int max_iters;       /* largest K that pw_run will be asked for (sizes the
                           corrector bases: rank <= max_iters * n_slices)     */
+  int interp;          /* pw_interp: the interpolation I (0 = trigonometric) */
 } pw_problem;
+
+/* The interpolation I from the coarse to the fine grid: trigonometric
+ * (the interpft of Sec. 6, the default) or periodic piecewise linear (one
+ * of the lower-order interpolants used in the numerical examples of
+ * Sec. 7).  Both satisfy R I = 1.  Taped runs (differentiation) support
+ * the trigonometric one only.                                           */
+typedef enum { PW_INTERP_TRIG = 0, PW_INTERP_LINEAR = 1 } pw_interp;
 
 typedef struct pw_ctx pw_ctx;
 

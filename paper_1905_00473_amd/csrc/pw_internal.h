@@ -157,6 +157,8 @@ void restrict_fields(const Grid& fine, int ratio, const Grid& coarse, const T* i
 // polyphase weights of trigonometric interpolation along one axis:
 // table[s * nc + d], s in [0, ratio), d in [0, nc) (host-built)
 std::vector<double> trig_interp_table(int nc, int ratio);
+// the same layout for periodic piecewise-linear interpolation
+std::vector<double> linear_interp_table(int nc, int ratio);
 
 // u_out[s] = (v ? v[s] : 0) + I(in[s]) on the fine grid, fields of type T.
 // tmp: double scratch of nfields * (fine points) * 2 elements.

@@ -643,6 +643,19 @@ std::vector<double> trig_interp_table(int nc, int ratio) {
   return tab;
 }
 
+// polyphase weights of periodic piecewise-linear interpolation in the same
+// layout: fine node ratio J + s takes 1 - s/ratio of coarse node J (d = 0)
+// and s/ratio of coarse node J + 1 (d = nc - 1)
+std::vector<double> linear_interp_table(int nc, int ratio) {
+  std::vector<double> tab((size_t)nc * ratio, 0.0);
+  for (int s = 0; s < ratio; ++s) {
+    const double t = (double)s / ratio;
+    tab[(size_t)s * nc] += 1.0 - t;
+    tab[(size_t)s * nc + (size_t)(nc - 1)] += t;
+  }
+  return tab;
+}
+
 template <typename T>
 void interp_add(const Grid& f, const Grid& c, int ratio, const double* const* tables, const T* in,
                 long long sin, const T* v, T* out, long long sout, int nfields, double* tmp,

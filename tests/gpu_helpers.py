@@ -8,7 +8,8 @@ import numpy as np
 import oracle as O
 
 
-def problem_pair(w, max_iters=None, tol=None, dtype=None, compensated=None):
+def problem_pair(w, max_iters=None, tol=None, dtype=None, compensated=None,
+                 interp="trig"):
     """(pw.Problem, oracle.Problem) for a workloads.Workload."""
     import paper_1905_00473_amd as pw
     dt = dtype or w.dtype
@@ -16,9 +17,9 @@ def problem_pair(w, max_iters=None, tol=None, dtype=None, compensated=None):
     t = w.tol if tol is None else tol
     P = pw.Problem.make(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
                         w.grad_order, t, dt, comp and dt == "f32",
-                        max_iters or w.K)
+                        max_iters or w.K, interp)
     Q = O.Problem(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
-                  w.grad_order, t)
+                  w.grad_order, t, interp=interp)
     return P, Q
 
 

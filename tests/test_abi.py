@@ -68,6 +68,9 @@ def test_invalid_problems_rejected_before_any_device_work():
     cases.append((mk(N=0), "slice/step"))
     cases.append((mk(order=3), "grad_order"))
     cases.append((mk(order=10), "grad_order"))
+    bad_interp = mk()
+    bad_interp.interp = 2
+    cases.append((bad_interp, "interp"))
     cases.append((mk(tol=0.0), "svd_tol"))
     cases.append((mk(comp=True), "compensation"))
     cases.append((mk(max_iters=0), "max_iters"))
