@@ -69,8 +69,9 @@ class Problem:
     number of coupling intervals of length dt_com = T/N.  ``m_fine`` /
     ``m_coarse``: steps per interval of F and C (Sec. 3.1).  ``length``: box
     length L per axis.  ``interp``: the interpolation I, trigonometric
-    (the interpft of Sec. 6) or periodic piecewise linear (one of the
-    lower-order interpolants the numerical examples of Sec. 7 also use).
+    (the interpft of Sec. 6), periodic piecewise linear, or local cubic
+    (4-point Lagrange): lower-order interpolants of the kind the numerical
+    examples of Sec. 7 also use.
     """
 
     shape: tuple
@@ -82,7 +83,7 @@ class Problem:
     grad_order: object = 4
     tol: float = 1e-14
     length: float = 1.0
-    interp: str = "trig"    # I: "trig" (interpft) or "linear"
+    interp: str = "trig"    # I: "trig" (interpft), "linear" or "cubic"
 
     @property
     def dim(self):
@@ -190,6 +191,26 @@ def _interp_axis_linear(U, ratio, ax):
     return np.moveaxis(out, -1, ax)
 
 
+def _cubic_weights(t):
+    # 4-point Lagrange weights of the nodes -1, 0, 1, 2 at t in [0, 1)
+    return ((-t * (t - 1) * (t - 2) / 6.0, (t + 1) * (t - 1) * (t - 2) / 2.0,
+             -(t + 1) * t * (t - 2) / 2.0, (t + 1) * t * (t - 1) / 6.0))
+
+
+def _interp_axis_cubic(U, ratio, ax):
+    # fine node ratio*J + s at J + s/ratio: the cubic through the coarse
+    # nodes J - 1 .. J + 2 (periodic)
+    A = np.moveaxis(U, ax, -1)
+    n = A.shape[-1]
+    out = np.zeros(A.shape[:-1] + (n * ratio,))
+    for J in range(n):
+        for s in range(ratio):
+            w = _cubic_weights(s / ratio)
+            out[..., J * ratio + s] = sum(w[k] * A[..., (J + k - 1) % n]
+                                          for k in range(4))
+    return np.moveaxis(out, -1, ax)
+
+
 def interp(U, ratio, kind="trig"):
     """Interpolation I from the coarse to the fine grid, one axis at a time.
     ``kind='trig'``: trigonometric (Fourier) interpolation: the coarse
@@ -197,15 +218,17 @@ def interp(U, ratio, kind="trig"):
     split between +n/2 and -n/2, and the real part of the inverse transform
     is returned (the `interpft` interpolation of Sec. 6).
     ``kind='linear'``: periodic piecewise-linear interpolation between
-    neighbouring coarse nodes."""
-    if kind not in ("trig", "linear"):
+    neighbouring coarse nodes.  ``kind='cubic'``: local cubic (4-point
+    Lagrange) interpolation through the coarse nodes J - 1 .. J + 2."""
+    if kind not in ("trig", "linear", "cubic"):
         raise ValueError(kind)
     out = np.asarray(U, dtype=np.float64)
     if ratio == 1:
         return np.array(out, copy=True)
     for ax in range(out.ndim):
-        out = (_interp_axis(out, ratio, ax) if kind == "trig"
-               else _interp_axis_linear(out, ratio, ax))
+        f = {"trig": _interp_axis, "linear": _interp_axis_linear,
+             "cubic": _interp_axis_cubic}[kind]
+        out = f(out, ratio, ax)
     return out
 
 

@@ -624,4 +624,44 @@ def test_linear_interp_exactness_bitwise():
 
 def test_unknown_interp_raises():
     with pytest.raises(ValueError):
-        O.interp(np.ones(4), 2, "cubic")
+        O.interp(np.ones(4), 2, "spline")
+
+
+def test_cubic_interp_reproduces_cubics_and_restricts():
+    """Local cubic I: exact for a cubic polynomial wherever the 4-point
+    stencil does not wrap, R I = 1, each weight set against the library's
+    Lagrange polynomial, and fourth-order convergence on a smooth periodic
+    function."""
+    from scipy.interpolate import lagrange
+    n, r = 12, 4
+    X = np.arange(n, dtype=float)
+    poly = np.poly1d([0.3, -1.1, 0.7, 2.0])
+    f = O.interp(poly(X), r, "cubic")
+    xf = np.arange(n * r) / r
+    inner = (xf >= 1) & (xf < n - 2)
+    np.testing.assert_allclose(f[inner], poly(xf[inner]), atol=1e-11)
+    rng = np.random.default_rng(1)
+    U = rng.standard_normal(n)
+    g = O.interp(U, r, "cubic")
+    assert np.array_equal(O.restrict(g, r), U)
+    for J in (0, 5, n - 1):
+        L = lagrange(np.array([-1.0, 0.0, 1.0, 2.0]),
+                     U[[(J - 1) % n, J, (J + 1) % n, (J + 2) % n]])
+        for s in range(r):
+            assert abs(g[J * r + s] - L(s / r)) < 1e-12
+    errs = []
+    for m in (16, 32, 64):
+        xc = np.arange(m) / m
+        xf = np.arange(m * r) / (m * r)
+        errs.append(np.abs(O.interp(np.sin(2 * np.pi * xc), r, "cubic")
+                           - np.sin(2 * np.pi * xf)).max())
+    assert 14 < errs[0] / errs[1] < 18 and 14 < errs[1] / errs[2] < 18, errs
+
+
+def test_cubic_interp_2d_separable():
+    rng = np.random.default_rng(2)
+    V = rng.standard_normal((6, 7))
+    g = O.interp(V, 3, "cubic")
+    ref = np.array([O.interp(row, 3, "cubic") for row in V])
+    ref = np.array([O.interp(col, 3, "cubic") for col in ref.T]).T
+    np.testing.assert_allclose(g, ref, atol=1e-13)
