@@ -89,11 +89,12 @@ typedef struct {
 } pw_problem;
 
 /* The interpolation I from the coarse to the fine grid: trigonometric
- * (the interpft of Sec. 6, the default) or periodic piecewise linear (one
- * of the lower-order interpolants used in the numerical examples of
- * Sec. 7).  Both satisfy R I = 1.  Taped runs (differentiation) support
- * the trigonometric one only.                                           */
-typedef enum { PW_INTERP_TRIG = 0, PW_INTERP_LINEAR = 1 } pw_interp;
+ * (the interpft of Sec. 6, the default), periodic piecewise linear, or
+ * local cubic (4-point Lagrange through the coarse nodes J-1 .. J+2):
+ * lower-order interpolants of the kind used in the numerical examples of
+ * Sec. 7.  All satisfy R I = 1.  Taped runs (differentiation) support the
+ * trigonometric one only.                                               */
+typedef enum { PW_INTERP_TRIG = 0, PW_INTERP_LINEAR = 1, PW_INTERP_CUBIC = 2 } pw_interp;
 
 typedef struct pw_ctx pw_ctx;
 

@@ -53,8 +53,8 @@ class Problem(ctypes.Structure):
     def make(cls, shape, ratio, T, N, m_fine, m_coarse, grad_order=4,
              tol=1e-14, dtype="f64", compensated=False, max_iters=8,
              interp="trig"):
-        """shape: fine grid in numpy order (x last); interp: "trig" or
-        "linear"."""
+        """shape: fine grid in numpy order (x last); interp: "trig",
+        "linear" or "cubic"."""
         p = cls()
         p.dim = len(shape)
         xyz = list(reversed(shape)) + [1] * (3 - len(shape))
@@ -70,7 +70,7 @@ class Problem(ctypes.Structure):
         p.state_dtype = F64 if dtype in ("f64", "float64", F64) else F32
         p.compensated = int(bool(compensated))
         p.max_iters = int(max_iters)
-        p.interp = {"trig": 0, "linear": 1}.get(interp, interp)
+        p.interp = {"trig": 0, "linear": 1, "cubic": 2}.get(interp, interp)
         return p
 
 

@@ -290,8 +290,8 @@ void validate(const pw_problem& P) {
   if (P.state_dtype != PW_F32 && P.state_dtype != PW_F64) fail(PW_EINVAL, "bad state dtype");
   if (P.compensated && P.state_dtype != PW_F32) fail(PW_EINVAL, "compensation is an FP32 mode");
   if (P.max_iters < 1) fail(PW_EINVAL, "max_iters must be >= 1");
-  if (P.interp != PW_INTERP_TRIG && P.interp != PW_INTERP_LINEAR)
-    fail(PW_EINVAL, "interp must be PW_INTERP_TRIG or PW_INTERP_LINEAR");
+  if (P.interp != PW_INTERP_TRIG && P.interp != PW_INTERP_LINEAR && P.interp != PW_INTERP_CUBIC)
+    fail(PW_EINVAL, "interp must be PW_INTERP_TRIG, PW_INTERP_LINEAR or PW_INTERP_CUBIC");
 }
 
 void setup(Prob& pr, const pw_problem& P) {
@@ -331,9 +331,9 @@ void setup(Prob& pr, const pw_problem& P) {
   pr.c2c = m.get(ts * Nc);
   pr.c2c_d = m.get_n<double>(Nc);
   for (int a = 0; a < P.dim; ++a) {
-    std::vector<double> t = P.interp == PW_INTERP_LINEAR
-                                ? linear_interp_table(pr.gc.n[a], P.ratio)
-                                : trig_interp_table(pr.gc.n[a], P.ratio);
+    std::vector<double> t = P.interp == PW_INTERP_LINEAR  ? linear_interp_table(pr.gc.n[a], P.ratio)
+                            : P.interp == PW_INTERP_CUBIC ? cubic_interp_table(pr.gc.n[a], P.ratio)
+                                                          : trig_interp_table(pr.gc.n[a], P.ratio);
     pr.itab[a] = m.get_n<double>((long long)t.size());
     PW_HIP(hipMemcpy(pr.itab[a], t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice));
     std::vector<double> d = dft_table(pr.gc.n[a]);

@@ -159,6 +159,8 @@ void restrict_fields(const Grid& fine, int ratio, const Grid& coarse, const T* i
 std::vector<double> trig_interp_table(int nc, int ratio);
 // the same layout for periodic piecewise-linear interpolation
 std::vector<double> linear_interp_table(int nc, int ratio);
+// and for local cubic (4-point Lagrange) interpolation
+std::vector<double> cubic_interp_table(int nc, int ratio);
 
 // u_out[s] = (v ? v[s] : 0) + I(in[s]) on the fine grid, fields of type T.
 // tmp: double scratch of nfields * (fine points) * 2 elements.

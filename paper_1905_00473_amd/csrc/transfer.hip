@@ -656,6 +656,21 @@ std::vector<double> linear_interp_table(int nc, int ratio) {
   return tab;
 }
 
+// the same layout for local cubic interpolation: fine node ratio J + s
+// (t = s / ratio) takes the 4-point Lagrange weights of coarse nodes
+// J - 1, J, J + 1, J + 2, i.e. d = 1, 0, nc - 1, nc - 2 (nc >= 4)
+std::vector<double> cubic_interp_table(int nc, int ratio) {
+  std::vector<double> tab((size_t)nc * ratio, 0.0);
+  for (int s = 0; s < ratio; ++s) {
+    const double t = (double)s / ratio;
+    const double w[4] = {-t * (t - 1.0) * (t - 2.0) / 6.0, (t + 1.0) * (t - 1.0) * (t - 2.0) / 2.0,
+                         -(t + 1.0) * t * (t - 2.0) / 2.0, (t + 1.0) * t * (t - 1.0) / 6.0};
+    const int dd[4] = {1, 0, nc - 1, nc - 2};
+    for (int k = 0; k < 4; ++k) tab[(size_t)s * nc + (size_t)dd[k]] += w[k];
+  }
+  return tab;
+}
+
 template <typename T>
 void interp_add(const Grid& f, const Grid& c, int ratio, const double* const* tables, const T* in,
                 long long sin, const T* v, T* out, long long sout, int nfields, double* tmp,

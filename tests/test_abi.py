@@ -69,7 +69,7 @@ def test_invalid_problems_rejected_before_any_device_work():
     cases.append((mk(order=3), "grad_order"))
     cases.append((mk(order=10), "grad_order"))
     bad_interp = mk()
-    bad_interp.interp = 2
+    bad_interp.interp = 3
     cases.append((bad_interp, "interp"))
     cases.append((mk(tol=0.0), "svd_tol"))
     cases.append((mk(comp=True), "compensation"))
