@@ -79,7 +79,8 @@ typedef struct {
   int n_slices;        /* N coupling intervals                               */
   int m_fine;          /* fine steps per interval                            */
   int m_coarse;        /* coarse steps per interval                          */
-  int grad_order;      /* order of the central gradient nabla_h: 2, 4, 6, 8  */
+  int grad_order;      /* nabla_h: central difference of order 2, 4, 6 or 8,
+                          or 0 for the Fourier (spectral) derivative         */
   double svd_tol;      /* relative rank tolerance of Algorithm 1 (> 0)       */
   int state_dtype;     /* pw_dtype of u, p                                   */
   int compensated;     /* FP32 only: compensated (Kahan) accumulation in F/C */
@@ -287,9 +288,11 @@ pw_status pw_get_corrector(pw_ctx* ctx, int prob, double* U, double* S,
                            double* V, int cap, int* rank);
 
 /* Discrete wave energy (eq. discrete-wave-energy) on the fine grid with
- * the fine medium and the context's gradient order, of the difference
- * [u - u_ref, p - p_ref] and of [u_ref, p_ref], in double (synchronous;
- * results to host).  u_ref may be NULL (then the energy of [u, p]).     */
+ * the fine medium and the context's gradient order (the fourth-order
+ * central difference for a context with the spectral gradient), of the
+ * difference [u - u_ref, p - p_ref] and of [u_ref, p_ref], in double
+ * (synchronous; results to host).  u_ref may be NULL (then the energy of
+ * [u, p]).                                                              */
 pw_status pw_energy(pw_ctx* ctx, int prob, const void* u, const void* p,
                     const void* u_ref, const void* p_ref, double* e_diff,
                     double* e_ref);

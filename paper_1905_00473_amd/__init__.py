@@ -65,7 +65,7 @@ class Problem(ctypes.Structure):
         p.n_slices = int(N)
         p.m_fine = int(m_fine)
         p.m_coarse = int(m_coarse)
-        p.grad_order = int(grad_order)
+        p.grad_order = 0 if grad_order == "spectral" else int(grad_order)
         p.svd_tol = float(tol)
         p.state_dtype = F64 if dtype in ("f64", "float64", F64) else F32
         p.compensated = int(bool(compensated))

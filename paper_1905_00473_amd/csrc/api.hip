@@ -193,6 +193,7 @@ struct Prob {
   DevBuf samp;                     // sampled data columns, samp_iters x samp_n
   int samp_n = 0, samp_iters = 0;
   double* vsum = nullptr;          // column sum of the Omega = I chain
+  SpecScratch spec;                // spectral gradient (grad_order 0)
   int cur = 0;    // which of the ping-pong corrector buffers is current
   int r = 0;      // current rank
   int k_done = 0;
@@ -284,8 +285,9 @@ void validate(const pw_problem& P) {
   }
   if (!(P.T > 0)) fail(PW_EINVAL, "T must be positive");
   if (P.n_slices < 1 || P.m_fine < 1 || P.m_coarse < 1) fail(PW_EINVAL, "bad slice/step counts");
-  if (P.grad_order != 2 && P.grad_order != 4 && P.grad_order != 6 && P.grad_order != 8)
-    fail(PW_EINVAL, "grad_order must be 2, 4, 6 or 8");
+  if (P.grad_order != 0 && P.grad_order != 2 && P.grad_order != 4 && P.grad_order != 6 &&
+      P.grad_order != 8)
+    fail(PW_EINVAL, "grad_order must be 2, 4, 6, 8 or 0 (spectral)");
   if (!(P.svd_tol > 0)) fail(PW_EINVAL, "svd_tol must be positive");
   if (P.state_dtype != PW_F32 && P.state_dtype != PW_F64) fail(PW_EINVAL, "bad state dtype");
   if (P.compensated && P.state_dtype != PW_F32) fail(PW_EINVAL, "compensation is an FP32 mode");
@@ -417,6 +419,13 @@ void setup(Prob& pr, const pw_problem& P) {
   pr.gwork = m.get_n<double>((long long)pr.gwork_elems);
   pr.red = m.get_n<double>(4096);
   pr.vsum = m.get_n<double>(16);
+  if (pr.order == 0) {
+    pr.spec.dft = pr.dtab;
+    pr.spec.cols = N;
+    pr.spec.ctmp = m.get_n<double>(4LL * (P.dim + 1) * Nc * N);
+    pr.spec.rtmp = m.get_n<double>((long long)P.dim * Nc * N);
+    pr.spec.ures = m.get_n<double>(Nc * N);
+  }
   pr.res = m.get_n<double>(2LL * (P.max_iters + 1));
   size_t tsq_st = 0, tsq_tau = 0;
   tsqr_work(rows, N, &tsq_st, &tsq_tau);
@@ -615,7 +624,7 @@ void update_svd_dev(Prob& pr, const double* F, const double* G, int ncols, hipSt
   lambda_dag_cols(pr.gc, pr.dtab, U + rows * r, rows, pr.cc, nullptr, pr.E[cur] + 2 * Nc * r,
                   2 * Nc, ncols, pr.ctmp, st);
   lambda_adjoint_cols(pr.gc, V + rows * r, rows, pr.cc, pr.order, pr.Vp[cur] + 2 * Nc * r, 2 * Nc,
-                      ncols, st);
+                      ncols, st, &pr.spec);
   // rotate: [U Q_F] X(:, 1:rn) etc.
   gemm_nn(rows, rn, n, 1.0, U, rows, pr.X, n, 0.0, pr.Ub[nxt], rows, st);
   gemm_nn(rows, rn, n, 1.0, V, rows, pr.Y, n, 0.0, pr.Vb[nxt], rows, st);
@@ -715,9 +724,9 @@ void corrector_phase(Prob& pr, int k, hipStream_t st) {
   const int N = pr.N;
   const long long Nf = pr.Nf, Nc = pr.Nc, rows = pr.rows;
   energy_columns<T>(pr.gf, pr.ratio, pr.gc, tp<T>(pr.v), tp<T>(pr.vp), Nf, pr.cc, pr.order,
-                    pr.Fm, rows, N, st);
+                    pr.Fm, rows, N, st, &pr.spec);
   energy_columns<T>(pr.gc, 1, pr.gc, tp<T>(pr.Uc), tp<T>(pr.Ucp), Nc, pr.cc, pr.order, pr.Gm,
-                    rows, N, st);
+                    rows, N, st, &pr.spec);
   if (pr.samp_n > 0) {
     if (k > pr.samp_iters) fail(PW_EINVAL, "no sampled columns for this iteration");
     update_svd_dev(pr, pr.Fm, pr.Gm, pr.samp_n, st,
@@ -824,9 +833,9 @@ void residual_identity_phase(Prob& pr, int k, hipStream_t st) {
   const int N = pr.N;
   const long long Nf = pr.Nf, Nc = pr.Nc, rows = pr.rows;
   energy_columns<T>(pr.gf, pr.ratio, pr.gc, tp<T>(pr.v), tp<T>(pr.vp), Nf, pr.cc, pr.order,
-                    pr.Fm, rows, N, st);
+                    pr.Fm, rows, N, st, &pr.spec);
   energy_columns<T>(pr.gc, 1, pr.gc, tp<T>(pr.Uc), tp<T>(pr.Ucp), Nc, pr.cc, pr.order, pr.Gm,
-                    rows, N, st);
+                    rows, N, st, &pr.spec);
   pr.ranks.push_back((int)rows);
   const long long n = rows * N;
   hipLaunchKernelGGL(k_sub_cols, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
@@ -854,7 +863,7 @@ void sweep_serial_chain(Prob& pr, bool project, hipStream_t st) {
     }
     prop_coarse_cols(pr, x, pr.CE, 1, st);
     energy_columns<double>(pr.gc, 1, pr.gc, pr.CE, pr.CE + Nc, C2, pr.cc, pr.order, pr.Fp, rows,
-                           1, st);
+                           1, st, &pr.spec);
     hipLaunchKernelGGL(k_col_sum, dim3(1), dim3(256), 0, st, (const double*)pr.CE, Nc, pr.vsum);
     PW_LAUNCH_CHECK();
     lambda_dag_cols(pr.gc, pr.dtab, pr.Fp, rows, pr.cc, pr.vsum, dn, C2, 1, pr.ctmp, st);
@@ -1743,10 +1752,10 @@ pw_status pw_energy_components(pw_ctx* ctx, int prob, int grid, const void* u, c
     const long long ss = src.npts();
     if (pr.f64)
       energy_columns<double>(src, ratio, pr.gc, (const double*)u, (const double*)p, ss, pr.cc,
-                             pr.order, out, pr.rows, n_states, ctx->stream);
+                             pr.order, out, pr.rows, n_states, ctx->stream, &pr.spec);
     else
       energy_columns<float>(src, ratio, pr.gc, (const float*)u, (const float*)p, ss, pr.cc,
-                            pr.order, out, pr.rows, n_states, ctx->stream);
+                            pr.order, out, pr.rows, n_states, ctx->stream, &pr.spec);
   });
 }
 
@@ -1831,10 +1840,12 @@ pw_status pw_energy(pw_ctx* ctx, int prob, const void* u, const void* p, const v
     double* res = pr.red + 4000;
     if (pr.f64)
       energy_pair<double>(pr.gf, (const double*)u, (const double*)p, (const double*)u_ref,
-                          (const double*)p_ref, pr.cf, pr.order, pr.red, res, st);
+                          (const double*)p_ref, pr.cf, pr.order ? pr.order : 4, pr.red, res,
+                          st);
     else
       energy_pair<float>(pr.gf, (const float*)u, (const float*)p, (const float*)u_ref,
-                         (const float*)p_ref, pr.cf, pr.order, pr.red, res, st);
+                         (const float*)p_ref, pr.cf, pr.order ? pr.order : 4, pr.red, res,
+                         st);
     double h[2] = {0, 0};
     PW_HIP(hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, st));
     PW_HIP(hipStreamSynchronize(st));

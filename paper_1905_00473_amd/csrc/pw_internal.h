@@ -129,12 +129,37 @@ void run_multi(const MultiPlan<T>& plan, const StreamDesc<T>* descs_dev, bool co
 // ---------------------------------------------------------------------------
 // grid transfer and energy components (transfer.hip)
 // ---------------------------------------------------------------------------
+// Scratch of the spectral (Fourier) gradient on the coarse grid, for up to
+// `cols` fields: DFT tables per axis, complex work of 4 (d + 1) points
+// x cols doubles, real work of d points x cols, restricted fields of
+// points x cols.
+struct SpecScratch {
+  const double* const* dft = nullptr;
+  double* ctmp = nullptr;
+  double* rtmp = nullptr;
+  double* ures = nullptr;
+  int cols = 0;
+};
+
+// out[col * ldo + a * np + J] = D_a in_col (the Fourier derivative
+// real(ifft(i xi_a fft(in)))) for a < d, columns of np points, ld ldi
+void spectral_grad_cols(const Grid& grid, const SpecScratch& sp, const double* in,
+                        long long ldi, int ncols, double* out, long long ldo,
+                        hipStream_t stream);
+// out[col * ldo + J] = -sum_a D_a q_a, q_a = in[col * ldi + a * np ..]
+// (the transpose of the Fourier gradient, which is skew-symmetric)
+void spectral_div_cols(const Grid& grid, const SpecScratch& sp, const double* in,
+                       long long ldi, int ncols, double* out, long long ldo,
+                       hipStream_t stream);
+
 // out[:, s] = Lambda R [u_s, p_s] (double columns, rows = (d+1) * coarse
-// points).  `ratio` = 1 when u, p already live on the coarse grid.
+// points).  `ratio` = 1 when u, p already live on the coarse grid.  order
+// 0 = spectral gradient (needs sp).
 template <typename T>
 void energy_columns(const Grid& fine_or_coarse, int ratio, const Grid& coarse, const T* u,
                     const T* p, long long sstride, const double* cc, int order, double* out,
-                    long long ldo, int nstates, hipStream_t stream);
+                    long long ldo, int nstates, hipStream_t stream,
+                    const SpecScratch* sp = nullptr);
 
 // out[:, s] = [R(a_u - b_u) ; R(a_p - b_p)] as double coarse states
 // (column length 2 * coarse points, leading dimension ldo).  Column s uses
@@ -184,7 +209,8 @@ void grad2func_cols(const Grid& coarse, const double* const* dft, const double* 
 // out_u = -sum_a grad_a(q_a) (gradient order `order`), out_p = p / cc.
 // in: rows (d+1)*Nc, ld ldi; out: 2*Nc rows, ld ldo.
 void lambda_adjoint_cols(const Grid& coarse, const double* in, long long ldi, const double* cc,
-                         int order, double* out, long long ldo, int ncols, hipStream_t stream);
+                         int order, double* out, long long ldo, int ncols, hipStream_t stream,
+                         const SpecScratch* sp = nullptr);
 
 // Lambda^dag of energy-component columns: out_u = grad2func(q, sums[col])
 // (sums null: all zero), out_p = cc * p.

@@ -66,10 +66,12 @@ __device__ __forceinline__ double grad_at(const T* f, int ax, int X, int Y, int 
   return d / c.dx;
 }
 
+// order 0 (spectral gradient): the gradient rows are left to the caller
+// and the restricted u goes to ures (nstates x coarse points) instead
 template <typename T>
 __global__ void k_energy_columns(const T* u, const T* p, long long sstride, GridArg c, int ratio,
                                  int fnx, int fny, const double* cc, int order, double* out,
-                                 long long ldo, int nstates) {
+                                 long long ldo, int nstates, double* ures) {
   const long long nc = (long long)c.nx * c.ny * c.nz;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nc * nstates) return;
@@ -81,9 +83,14 @@ __global__ void k_energy_columns(const T* u, const T* p, long long sstride, Grid
   const T* us = u + (long long)s * sstride;
   const T* ps = p + (long long)s * sstride;
   double* o = out + (long long)s * ldo;
-  for (int a = 0; a < c.dim; ++a) o[a * nc + J] = grad_at(us, a, X, Y, Z, c, ratio, fnx, fny, order);
   const long long gi =
       (long long)X * ratio + (long long)fnx * ((long long)Y * ratio + (long long)fny * Z * ratio);
+  if (order > 0) {
+    for (int a = 0; a < c.dim; ++a)
+      o[a * nc + J] = grad_at(us, a, X, Y, Z, c, ratio, fnx, fny, order);
+  } else {
+    ures[(long long)s * nc + J] = (double)us[gi];
+  }
   o[c.dim * nc + J] = (double)ps[gi] / cc[J];
 }
 
@@ -577,12 +584,15 @@ constexpr int kEnergyBlocks = 1024;
 template <typename T>
 void energy_columns(const Grid& src, int ratio, const Grid& c, const T* u, const T* p,
                     long long sstride, const double* cc, int order, double* out, long long ldo,
-                    int nstates, hipStream_t st) {
+                    int nstates, hipStream_t st, const SpecScratch* sp) {
   const long long n = c.npts() * nstates;
   if (n == 0) return;
+  if (order == 0 && !sp) fail(PW_EINVAL, "spectral gradient without its scratch");
   hipLaunchKernelGGL((k_energy_columns<T>), dim3(nblocks(n)), dim3(kTB), 0, st, u, p, sstride,
-                     garg(c), ratio, src.n[0], src.n[1], cc, order, out, ldo, nstates);
+                     garg(c), ratio, src.n[0], src.n[1], cc, order, out, ldo, nstates,
+                     order == 0 ? sp->ures : (double*)nullptr);
   PW_LAUNCH_CHECK();
+  if (order == 0) spectral_grad_cols(c, *sp, sp->ures, c.npts(), nstates, out, ldo, st);
 }
 
 template <typename T>
@@ -735,6 +745,138 @@ void dft_pass(const void* in, long long s_hi, long long s_lo, int sub, long long
   PW_LAUNCH_CHECK();
 }
 
+// G[(col d + a) np + J] = i xi_a S[col np + J]
+__global__ void k_spec_grad_mul(const double2* S, GridArg c, double2* G, int ncols) {
+  const long long nc = (long long)c.nx * c.ny * c.nz;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nc * ncols) return;
+  const int col = (int)(t / nc);
+  const long long J = t - (long long)col * nc;
+  const int X = (int)(J % c.nx);
+  const int Y = (int)((J / c.nx) % c.ny);
+  const int Z = (int)(J / ((long long)c.nx * c.ny));
+  const double xi[3] = {wavenumber(X, c.nx, c.nx * c.dx), wavenumber(Y, c.ny, c.ny * c.dx),
+                        wavenumber(Z, c.nz, c.nz * c.dx)};
+  const double2 s = S[t];
+  for (int a = 0; a < c.dim; ++a)
+    G[((long long)col * c.dim + a) * nc + J] = make_double2(-xi[a] * s.y, xi[a] * s.x);
+}
+
+// S[col np + J] = -i sum_a xi_a Q[(col d + a) np + J]
+__global__ void k_spec_div_mul(const double2* Q, GridArg c, double2* S, int ncols) {
+  const long long nc = (long long)c.nx * c.ny * c.nz;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nc * ncols) return;
+  const int col = (int)(t / nc);
+  const long long J = t - (long long)col * nc;
+  const int X = (int)(J % c.nx);
+  const int Y = (int)((J / c.nx) % c.ny);
+  const int Z = (int)(J / ((long long)c.nx * c.ny));
+  const double xi[3] = {wavenumber(X, c.nx, c.nx * c.dx), wavenumber(Y, c.ny, c.ny * c.dx),
+                        wavenumber(Z, c.nz, c.nz * c.dx)};
+  double sr = 0.0, si = 0.0;
+  for (int a = 0; a < c.dim; ++a) {
+    const double2 q = Q[((long long)col * c.dim + a) * nc + J];
+    sr += xi[a] * q.x;
+    si += xi[a] * q.y;
+  }
+  S[t] = make_double2(si, -sr);  // -i (sr + i si)
+}
+
+// out[col * ldo + a * np + J] = r[(col d + a) np + J]
+__global__ void k_spec_scatter(const double* r, int d, long long nc, int ncols, double* out,
+                               long long ldo) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nc * d * ncols) return;
+  const long long b = t / nc, J = t - b * nc;
+  const int col = (int)(b / d), a = (int)(b % d);
+  out[(long long)col * ldo + (long long)a * nc + J] = r[t];
+}
+
+// forward transform of nb real fields (batch b at (b / sub) s_hi + (b % sub)
+// s_lo) into the complex spectrum; returns the buffer holding it
+static double2* spec_forward(const Grid& c, const double* const* dft, const void* in,
+                             long long s_hi, long long s_lo, int sub, int nb, double2* A,
+                             double2* B, hipStream_t st) {
+  const long long nc = c.npts();
+  const int nx = c.n[0], ny = c.n[1], nz = c.n[2];
+  dft_pass<true, false, false>(in, s_hi, s_lo, sub, 0LL, A, nc, dft[0], ny * nz, nx, 1, nb, 1.0, st);
+  double2* cur = A;
+  double2* oth = B;
+  if (c.dim >= 2) {
+    dft_pass<false, false, false>(cur, 0LL, 0LL, 1, nc, oth, nc, dft[1], nz, ny, nx, nb, 1.0, st);
+    std::swap(cur, oth);
+  }
+  if (c.dim >= 3) {
+    dft_pass<false, false, false>(cur, 0LL, 0LL, 1, nc, oth, nc, dft[2], 1, nz, nx * ny, nb, 1.0,
+                                  st);
+    std::swap(cur, oth);
+  }
+  return cur;
+}
+
+// inverse transform of nb spectra in `cur` (work buffer `oth`), real part
+// / np written to out, batch b at b * s_out
+static void spec_inverse_real(const Grid& c, const double* const* dft, double2* cur,
+                              double2* oth, int nb, double* out, long long s_out,
+                              hipStream_t st) {
+  const long long nc = c.npts();
+  const int nx = c.n[0], ny = c.n[1], nz = c.n[2];
+  const double scale = 1.0 / (double)nc;
+  if (c.dim == 1) {
+    dft_pass<false, true, true>(cur, 0LL, 0LL, 1, nc, out, s_out, dft[0], 1, nx, 1, nb, scale, st);
+    return;
+  }
+  dft_pass<false, false, true>(cur, 0LL, 0LL, 1, nc, oth, nc, dft[0], ny * nz, nx, 1, nb, 1.0, st);
+  std::swap(cur, oth);
+  if (c.dim == 2) {
+    dft_pass<false, true, true>(cur, 0LL, 0LL, 1, nc, out, s_out, dft[1], nz, ny, nx, nb, scale,
+                                st);
+    return;
+  }
+  dft_pass<false, false, true>(cur, 0LL, 0LL, 1, nc, oth, nc, dft[1], nz, ny, nx, nb, 1.0, st);
+  std::swap(cur, oth);
+  dft_pass<false, true, true>(cur, 0LL, 0LL, 1, nc, out, s_out, dft[2], 1, nz, nx * ny, nb, scale,
+                              st);
+}
+
+void spectral_grad_cols(const Grid& c, const SpecScratch& sp, const double* in, long long ldi,
+                        int ncols, double* out, long long ldo, hipStream_t st) {
+  if (ncols == 0) return;
+  if (ncols > sp.cols) fail(PW_EINVAL, "too many columns for the spectral gradient scratch");
+  const int d = c.dim;
+  const long long nc = c.npts();
+  double2* A = (double2*)sp.ctmp;          // ncols spectra
+  double2* B = A + nc * ncols;             // ncols
+  double2* G = B + nc * ncols;             // ncols * d
+  double2* G2 = G + nc * ncols * d;        // ncols * d
+  double2* S = spec_forward(c, sp.dft, in, ldi, 0LL, 1, ncols, A, B, st);
+  hipLaunchKernelGGL(k_spec_grad_mul, dim3(nblocks(nc * ncols)), dim3(kTB), 0, st,
+                     (const double2*)S, garg(c), G, ncols);
+  PW_LAUNCH_CHECK();
+  spec_inverse_real(c, sp.dft, G, G2, ncols * d, sp.rtmp, nc, st);
+  hipLaunchKernelGGL(k_spec_scatter, dim3(nblocks(nc * d * ncols)), dim3(kTB), 0, st,
+                     (const double*)sp.rtmp, d, nc, ncols, out, ldo);
+  PW_LAUNCH_CHECK();
+}
+
+void spectral_div_cols(const Grid& c, const SpecScratch& sp, const double* in, long long ldi,
+                       int ncols, double* out, long long ldo, hipStream_t st) {
+  if (ncols == 0) return;
+  if (ncols > sp.cols) fail(PW_EINVAL, "too many columns for the spectral gradient scratch");
+  const int d = c.dim;
+  const long long nc = c.npts();
+  double2* A = (double2*)sp.ctmp;          // ncols * d spectra
+  double2* B = A + nc * ncols * d;         // ncols * d
+  double2* S = B + nc * ncols * d;         // ncols
+  double2* S2 = S + nc * ncols;            // ncols
+  double2* Q = spec_forward(c, sp.dft, in, ldi, nc, d, ncols * d, A, B, st);
+  hipLaunchKernelGGL(k_spec_div_mul, dim3(nblocks(nc * ncols)), dim3(kTB), 0, st,
+                     (const double2*)Q, garg(c), S, ncols);
+  PW_LAUNCH_CHECK();
+  spec_inverse_real(c, sp.dft, S, S2, ncols, out, ldo, st);
+}
+
 void grad2func_cols(const Grid& c, const double* const* dft, const double* q, long long ldq,
                     const double* sums, double* w, long long ldw, int ncols, double* ctmp,
                     hipStream_t st) {
@@ -785,12 +927,15 @@ void grad2func_cols(const Grid& c, const double* const* dft, const double* q, lo
 }
 
 void lambda_adjoint_cols(const Grid& c, const double* in, long long ldi, const double* cc,
-                         int order, double* out, long long ldo, int ncols, hipStream_t st) {
+                         int order, double* out, long long ldo, int ncols, hipStream_t st,
+                         const SpecScratch* sp) {
   const long long n = c.npts() * ncols;
   if (n == 0) return;
+  if (order == 0 && !sp) fail(PW_EINVAL, "spectral gradient without its scratch");
   hipLaunchKernelGGL(k_lambda_adjoint, dim3(nblocks(n)), dim3(kTB), 0, st, in, ldi, garg(c), cc,
                      order, out, ldo, ncols);
   PW_LAUNCH_CHECK();
+  if (order == 0) spectral_div_cols(c, *sp, in, ldi, ncols, out, ldo, st);
 }
 
 void lambda_dag_cols(const Grid& c, const double* const* dft, const double* in, long long ldi,
@@ -824,7 +969,8 @@ void energy_pair(const Grid& f, const T* u, const T* p, const T* ur, const T* pr
 
 #define PW_INST(T)                                                                              \
   template void energy_columns<T>(const Grid&, int, const Grid&, const T*, const T*, long long, \
-                                  const double*, int, double*, long long, int, hipStream_t);   \
+                                  const double*, int, double*, long long, int, hipStream_t,    \
+                                  const SpecScratch*);                                         \
   template void restrict_diff<T>(const Grid&, int, const Grid&, const T*, const T*, const T*,   \
                                  const T*, long long, double*, long long, int, hipStream_t);   \
   template void restrict_fields<T>(const Grid&, int, const Grid&, const T*, long long, T*,      \

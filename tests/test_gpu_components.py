@@ -101,7 +101,7 @@ def test_batched_equals_single_bitwise():
 # ---------------------------------------------------------------------------
 # restriction + energy components (eqs. matrixF / matrixG)
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("order", [2, 4, 6, 8])
+@pytest.mark.parametrize("order", [2, 4, 6, 8, "spectral"])
 @pytest.mark.parametrize("dim", [1, 2, 3])
 def test_energy_components_parity(dim, order):
     import paper_1905_00473_amd as pw

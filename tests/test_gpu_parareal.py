@@ -76,6 +76,18 @@ def test_many_slices_fp64_parity(N, K):
     s.close()
 
 
+@pytest.mark.parametrize("order", [8, "spectral"])
+def test_disc2d_small_fp64_gradient_orders(order):
+    """Algorithm 3 with the 8th-order and the Fourier gradient (Sec. 6.4):
+    Lambda, its transpose in the sweep coordinates and the corrector."""
+    w = W.disc2d(n=96, ratio=4, N=8, K=3, T=0.5, dtype="f64",
+                 compensated=False)
+    w.grad_order = order
+    s, Q, u0, p0 = _run(w, 3, tol=1e-6)
+    _compare(s, Q, w, u0, p0, 3, 1e-12)
+    s.close()
+
+
 def test_disc2d_small_fp64_parity():
     w = W.disc2d(n=96, ratio=4, N=8, K=3, T=0.5, dtype="f64",
                  compensated=False)

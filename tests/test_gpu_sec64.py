@@ -14,7 +14,8 @@ FP64 state.
   the oracle's residuals.
 * Column 3, max over the slices of ||grad2func(nabla_h U) - U|| / ||U||
   on the serial fine solution: gate 0.5 % against the printed value (the
-  oracle's own agreement).
+  oracle's own agreement); for the spectral gradient, whose printed value
+  1.8e-12 is rounding, below 1e-11.
 """
 
 import os
@@ -54,7 +55,7 @@ def _setup(order, K):
     return P, Q, np.ones(n), u0, np.zeros(n)
 
 
-@pytest.mark.parametrize("order", [2, 4, 6, 8])
+@pytest.mark.parametrize("order", [2, 4, 6, 8, "spectral"])
 def test_printed_mean_residual(order):
     import paper_1905_00473_amd as pw
     print(f"sec6.4 residual order={order}", flush=True)
@@ -73,7 +74,7 @@ def test_printed_mean_residual(order):
     s.close()
 
 
-@pytest.mark.parametrize("order", [2, 4, 6, 8])
+@pytest.mark.parametrize("order", [2, 4, 6, 8, "spectral"])
 def test_printed_reconstruction_error(order):
     import paper_1905_00473_amd as pw
     import torch
@@ -91,5 +92,10 @@ def test_printed_reconstruction_error(order):
         e = torch.linalg.norm(w[0] - u) / torch.linalg.norm(u)
         worst = max(worst, float(e))
     printed = _table()[order][1]
-    assert abs(worst - printed) / printed < 5e-3, (order, worst, printed)
+    if order == "spectral":
+        # the printed 1.8e-12 is rounding: the Fourier gradient loses only
+        # the Nyquist mode, which these fields do not carry
+        assert worst < 1e-11, worst
+    else:
+        assert abs(worst - printed) / printed < 5e-3, (order, worst, printed)
     s.close()
