@@ -1259,12 +1259,6 @@ void orth_finish(long long rows, int n, const double* A, long long lda, double* 
   }
 }
 
-void orth(long long rows, int n, const double* A, long long lda, double* Q, long long ldq,
-          double* R, OrthScratch s, hipStream_t st) {
-  orth_begin(rows, n, A, lda, s, st);
-  const bool c = orth_choose(rows, n, s, st);
-  orth_finish(rows, n, A, lda, Q, ldq, R, s, c, st);
-}
 
 void svd_jacobi(int n, const double* H, double* X, double* Y, double* sig, double tol,
                 int* rank_dev, double* Hw, double* Vw, int* counters, hipStream_t st) {

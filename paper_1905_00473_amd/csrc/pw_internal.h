@@ -280,13 +280,12 @@ struct OrthScratch {
 };
 // workspace of the Householder TSQR of a rows x min(n, 64) block
 void tsqr_work(long long rows, int n, size_t* stack_elems, size_t* tau_elems);
-void orth(long long rows, int n, const double* A, long long lda, double* Q, long long ldq,
-          double* R, OrthScratch s, hipStream_t stream);
-// the same in three steps, so that two factorisations on two streams can
-// be started before either stream is synchronised: orth_begin enqueues
-// the Gram matrix and its pivoted Cholesky factor, orth_choose
-// synchronises the stream and returns whether Cholesky QR is accurate
-// enough, orth_finish enqueues the chosen method
+// A (rows x n) = Q R inside Algorithm 1 (Q with ld ldq, R n x n), in
+// three steps so that two factorisations on two streams can be started
+// before either stream is synchronised: orth_begin enqueues the Gram
+// matrix and its pivoted Cholesky factor, orth_choose synchronises the
+// stream and returns whether Cholesky QR is accurate enough, orth_finish
+// enqueues the chosen method (Cholesky QR twice or Householder TSQR)
 void orth_begin(long long rows, int n, const double* A, long long lda, const OrthScratch& s,
                 hipStream_t stream);
 bool orth_choose(long long rows, int n, const OrthScratch& s, hipStream_t stream);

@@ -99,3 +99,34 @@ def test_batch_rejects_mixed_problems():
     s = _solver([w2, w1], 1)
     with pytest.raises(pw.PwError):
         s.run_batch(1)
+
+
+def test_batch_with_sampling_equals_single_runs(tmp_path, monkeypatch):
+    """Random subsampling set on some problems of a batch: each problem
+    still equals its own single-problem run with the same table bit for
+    bit; a variant other than Algorithm 3 is refused by batched runs."""
+    import paper_1905_00473_amd as pw
+    import torch
+    monkeypatch.setenv("PW_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    ws = _batch_workloads()
+    K = 2
+    tables = [W.sample_columns(ws[0].N, 3, K, seed=4), None,
+              W.sample_columns(ws[2].N, 5, K, seed=6)]
+    sb = _solver(ws, K)
+    for i, t in enumerate(tables):
+        sb.set_sampling(t, prob=i)
+    sb.run_batch(K)
+    for i, w in enumerate(ws):
+        s1 = _solver([w], K)
+        s1.set_sampling(tables[i])
+        s1.run(K)
+        for n in range(w.N + 1):
+            ub, pb = sb.state(n, prob=i)
+            u1, p1 = s1.state(n)
+            assert torch.equal(ub, u1) and torch.equal(pb, p1), (i, n)
+        assert sb.residuals(prob=i) == s1.residuals()
+        s1.close()
+    sb.set_variant("plain", prob=1)
+    with pytest.raises(pw.PwError, match="Algorithm 3 only"):
+        sb.run_batch(K)
+    sb.close()
