@@ -232,3 +232,46 @@ def test_update_svd_parity(tol):
                                    atol=1e-9 * np.max(np.abs(G)))
         ortho = to_np(Ug) @ to_np(Ug).T
         np.testing.assert_allclose(ortho, np.eye(r), atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# the orthonormalisation inside Algorithm 1 at awkward shapes: Householder
+# TSQR chunking (rows below, at and just above one chunk of 256, many
+# chunks), more than 64 columns (blocked), fewer rows than columns
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("nc,ncols", [(50, 7), (128, 64), (129, 64),
+                                      (2500, 33), (70, 65), (300, 130),
+                                      (6, 24)])
+def test_update_svd_qr_shapes(nc, ncols):
+    """1D problems with rows = 2 nc; data with a steep spectrum (so the
+    FP64 path takes the Householder TSQR), two updates against the oracle:
+    singular values 1e-9, Omega-action on the data 1e-9 of its size, U
+    orthonormal to 1e-12."""
+    import paper_1905_00473_amd as pw
+    import torch
+    print(f"qr shapes nc={nc} ncols={ncols}", flush=True)
+    rows = 2 * nc
+    m_c = int(np.ceil(2 * nc / ncols))       # c dt / dx <= 1/2 on one grid
+    P = pw.Problem.make((nc,), 1, 1.0, ncols, 4 * m_c, m_c, 4, 1e-6, "f64",
+                        False, 2)
+    s = pw.Solver(P)
+    s.set_medium(np.ones(nc))
+    rng = np.random.default_rng(nc + ncols)
+    U = S = V = None
+    k = min(rows, 40)
+    for it in range(2):
+        basis = rng.standard_normal((rows, k)) * (0.55 ** np.arange(k))
+        F = basis @ rng.standard_normal((k, ncols))
+        G = F + 0.05 * (basis @ rng.standard_normal((k, ncols)))
+        U, S, V = O.update_svd(U, S, V, F, G, 1e-6)
+        r = s.update_svd(torch.tensor(F.T.copy(), device="cuda"),
+                         torch.tensor(G.T.copy(), device="cuda"),
+                         reset=(it == 0))
+        Ug, Sg, Vg = s.corrector()
+        assert r == len(S), (it, r, len(S))
+        np.testing.assert_allclose(to_np(Sg), S, rtol=1e-9, atol=1e-12 * S[0])
+        Ug, Vg = to_np(Ug).T, to_np(Vg).T
+        d = np.abs(Ug @ (Vg.T @ G) - U @ (V.T @ G)).max() / np.abs(G).max()
+        assert d < 1e-9, (it, d)
+        np.testing.assert_allclose(Ug.T @ Ug, np.eye(r), atol=1e-12)
+    s.close()
