@@ -19,7 +19,8 @@ iterations of Sec. 6 (Omega = I, no parareal-style correction, plain
 parareal: error per iteration and time), the random subsampling of the
 data matrices on the Sec. 6.5 waveguide (error per iteration and corrector
 time per sample size, singular-value decay), the Sec. 6.4 gradient-order
-table recomputed on the GPU beside the printed values, the per-phase
+table recomputed on the GPU beside the printed values, the comparisons of
+Secs. 6.2 / 6.3 on the paper's 1D setup, the per-phase
 split, and the FP64 oracle timed on the host on a bounded sample.
 """
 
@@ -297,6 +298,53 @@ def gradient_order_measurement(pw, torch):
     return out
 
 
+def sec6_comparator_measurement(pw, torch, K=8):
+    """The comparisons of Secs. 6.2 and 6.3 on the paper's own 1D setup
+    (100 points on [-0.5, 0.5), c = 1, one grid, dt/dx = 0.5, dt/dt_fine =
+    20, dt_com = 0.05, interpft, tol 1e-14, FP64): the energy error at T
+    after k = 1..K iterations of Algorithm 3 against Omega = I with the
+    second-order gradient for T = 2.5, 5, 10 (Sec. 6.2), and against the
+    iteration without the parareal-style correction with the fourth-order
+    gradient for T = 10 (Sec. 6.3)."""
+    import numpy as np
+    n = 100
+    x = -0.5 + np.arange(n) / n
+    u0 = np.cos(10 * np.pi * x) * np.exp(-100 * x ** 2)
+
+    def errors(T, order, variant):
+        N = int(round(T / 0.05))
+        P = pw.Problem.make((n,), 1, T, N, 200, 10, order, 1e-14, "f64",
+                            False, K)
+        s = pw.Solver(P)
+        s.set_medium(np.ones(n))
+        s.set_initial(u0, np.zeros(n))
+        s.set_variant(variant)
+        uf, pf = s.serial_fine(N)
+        out = []
+        for k in range(1, K + 1):
+            s.run(k)
+            uN, pN = s.state(N)
+            ed, er = s.energy(uN, pN, uf, pf)
+            e = math.sqrt(ed / er)
+            out.append(float(f"{e:.3e}") if math.isfinite(e) else None)
+        s.close()
+        return out
+
+    res = {"sec6_2_omega_one": {}, "sec6_3_no_correction": {}}
+    for T in (2.5, 5.0, 10.0):
+        res["sec6_2_omega_one"][str(T)] = {
+            "theta": errors(T, 2, "theta"),
+            "omega_one": errors(T, 2, "omega_one")}
+    res["sec6_3_no_correction"]["10.0"] = {
+        "theta": errors(10.0, 4, "theta"),
+        "no_correction": errors(10.0, 4, "no_correction")}
+    for key, d in res.items():
+        for T, v in d.items():
+            log(f"{key} T={T}: " + "; ".join(
+                f"{name} {v[name][-1]}" for name in v))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -307,6 +355,8 @@ def main():
                     help="skip the time-to-1e-5 study")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the comparator iterations of Sec. 6")
+    ap.add_argument("--no-sec6", action="store_true",
+                    help="skip the Secs. 6.2 / 6.3 comparisons")
     ap.add_argument("--no-table", action="store_true",
                     help="skip the Sec. 6.4 gradient-order table")
     ap.add_argument("--no-sampling", action="store_true",
@@ -479,6 +529,7 @@ def main():
     sampling = None if args.no_sampling else sampling_measurement(pw, W,
                                                                   torch)
     table = None if args.no_table else gradient_order_measurement(pw, torch)
+    sec6 = None if args.no_sec6 else sec6_comparator_measurement(pw, torch)
 
     cpu = None if args.no_cpu else cpu_baseline(w)
 
@@ -517,6 +568,7 @@ def main():
         "variants": variants,
         "sampling": sampling,
         "gradient_order_table": table,
+        "sec6_comparators": sec6,
         "batched": batched,
         "adjoint": adjoint,
         "cpu_baseline": cpu,
