@@ -1231,9 +1231,15 @@ void orth_finish(long long rows, int n, const double* A, long long lda, double* 
   // Householder QR of the block:
   //   W = A_b - Qp C1 = Q1 R1;  Q1 - Qp C2 = Q_b R2
   //   => A_b = Qp (C1 + C2 R1) + Q_b (R2 R1)
+  // With fewer rows than columns only the first m = rows columns are
+  // factored that way (their Q, noise directions included, is a complete
+  // orthonormal basis); the remaining columns get R = Q^T A and zero Q
+  // columns, as an economy Householder QR of a wide matrix gives.
+  const int m = (int)std::min<long long>(rows, n);
+  if (m < n && ldq != rows) fail(PW_EINVAL, "wide orthonormalisation needs ldq = rows");
   fill(R, (long long)n * n, 0.0, st);
-  for (int b0 = 0; b0 < n; b0 += kQrCols) {
-    const int nb = std::min(kQrCols, n - b0);
+  for (int b0 = 0; b0 < m; b0 += kQrCols) {
+    const int nb = std::min(kQrCols, m - b0);
     double* Qb = Q + (long long)b0 * ldq;
     double* Rtop = R + (long long)b0 * n;      // rows 0..b0 of the block's columns
     double* Rbb = R + b0 + (long long)b0 * n;  // diagonal block
@@ -1256,6 +1262,11 @@ void orth_finish(long long rows, int n, const double* A, long long lda, double* 
     } else {
       copy_block(nb, nb, s.R1, nb, Rbb, n, st);
     }
+  }
+  if (m < n) {
+    gemm_tn(rows, m, n - m, 1.0, Q, ldq, A + (long long)m * lda, lda, 0.0, R + (long long)m * n,
+            n, s.work, s.work_elems, st);
+    fill(Q + (long long)m * ldq, (long long)(n - m) * ldq, 0.0, st);
   }
 }
 

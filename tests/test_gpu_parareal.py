@@ -88,6 +88,32 @@ def test_disc2d_small_fp64_gradient_orders(order):
     s.close()
 
 
+def test_more_slices_than_rows():
+    """The Sec. 6 setup at T = 15: 300 slices, 2 x 100 data rows, so the
+    data matrices are wide (the QR inside Algorithm 1 factors only as many
+    columns as there are rows)."""
+    import paper_1905_00473_amd as pw
+    n, T, N, K = 100, 15.0, 300, 2
+    x = -0.5 + np.arange(n) / n
+    u0 = np.cos(10 * np.pi * x) * np.exp(-100 * x ** 2)
+    p0 = np.zeros(n)
+    c = np.ones(n)
+    P = pw.Problem.make((n,), 1, T, N, 200, 10, 2, 1e-14, "f64", False, K)
+    Q = O.Problem((n,), 1, T, N, 200, 10, 2, 1e-14)
+    s = pw.Solver(P)
+    s.set_medium(c)
+    s.set_initial(u0, p0)
+    s.run(K)
+    ref = O.theta_parareal(Q, c, u0, p0, K)
+    worst = max(rel_energy_err(to_np(s.state(k)[0]), to_np(s.state(k)[1]),
+                               ref.u[k], ref.p[k], c, Q.dx_fine, 2)
+                for k in range(1, N + 1))
+    assert worst < 1e-9, worst
+    _, rk = s.residuals()
+    assert list(rk) == list(ref.rank)
+    s.close()
+
+
 def test_disc2d_small_fp64_parity():
     w = W.disc2d(n=96, ratio=4, N=8, K=3, T=0.5, dtype="f64",
                  compensated=False)
