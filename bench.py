@@ -303,7 +303,8 @@ def sec6_comparator_measurement(pw, torch, K=8):
     (100 points on [-0.5, 0.5), c = 1, one grid, dt/dx = 0.5, dt/dt_fine =
     20, dt_com = 0.05, interpft, tol 1e-14, FP64): the energy error at T
     after k = 1..K iterations of Algorithm 3 against Omega = I with the
-    second-order gradient for T = 2.5, 5, 10 (Sec. 6.2), and against the
+    second-order gradient for T = 2.5, 5, 10, 50 (Sec. 6.2; 1000 slices
+    for T = 50), and against the
     iteration without the parareal-style correction with the fourth-order
     gradient for T = 10 (Sec. 6.3)."""
     import numpy as np
@@ -331,7 +332,7 @@ def sec6_comparator_measurement(pw, torch, K=8):
         return out
 
     res = {"sec6_2_omega_one": {}, "sec6_3_no_correction": {}}
-    for T in (2.5, 5.0, 10.0):
+    for T in (2.5, 5.0, 10.0, 50.0):
         res["sec6_2_omega_one"][str(T)] = {
             "theta": errors(T, 2, "theta"),
             "omega_one": errors(T, 2, "omega_one")}
