@@ -88,6 +88,20 @@ def test_disc2d_small_fp64_gradient_orders(order):
     s.close()
 
 
+def test_many_slices_fp32():
+    """100 slices with the FP32 compensated state (Cholesky QR for the
+    data blocks, blocked beyond 64 columns)."""
+    w = W.wave1d(n=512, N=100, K=2)
+    s, Q, u0, p0 = _run(w, 2, tol=1e-6, dtype="f32", compensated=True)
+    ref = O.theta_parareal(Q, w.c, u0, p0, 2)
+    for n in range(1, Q.N + 1, 7):
+        u, p = s.state(n)
+        e = rel_energy_err(to_np(u), to_np(p), ref.u[n], ref.p[n], w.c,
+                           Q.dx_fine)
+        assert e < 1e-5, (n, e)
+    s.close()
+
+
 def test_more_slices_than_rows():
     """The Sec. 6 setup at T = 15: 300 slices, 2 x 100 data rows, so the
     data matrices are wide (the QR inside Algorithm 1 factors only as many
