@@ -76,6 +76,17 @@ def test_many_slices_fp64_parity(N, K):
     s.close()
 
 
+def test_layers3d_small_spectral_fp64():
+    """Algorithm 3 with the Fourier gradient in 3D (non-power-of-two coarse
+    axes: the direct DFT passes)."""
+    w = W.layers3d(n=48, ratio=4, N=4, K=2, T=0.1, dtype="f64",
+                   compensated=False)
+    w.grad_order = "spectral"
+    s, Q, u0, p0 = _run(w, 2, tol=1e-6)
+    _compare(s, Q, w, u0, p0, 2, 1e-12)
+    s.close()
+
+
 @pytest.mark.parametrize("order", [8, "spectral"])
 def test_disc2d_small_fp64_gradient_orders(order):
     """Algorithm 3 with the 8th-order and the Fourier gradient (Sec. 6.4):

@@ -127,3 +127,26 @@ def test_sampling_errors():
         s.run(3)
     s.run(2)
     s.close()
+
+
+def test_sampled_fp32():
+    """Subsampling with the FP32 compensated state, 1e-5 against the
+    oracle fed the same table and the same FP32-rounded initial data."""
+    import paper_1905_00473_amd as pw
+    from tests.gpu_helpers import inputs_as
+    w = W.disc2d(n=96, ratio=4, N=8, K=3, T=0.5)
+    cols = W.sample_columns(w.N, 4, 3, seed=13)
+    P, Q = problem_pair(w, max_iters=3, tol=1e-6, dtype="f32")
+    s = pw.Solver(P)
+    u0, p0 = inputs_as(w, "f32")
+    s.set_medium(w.c)
+    s.set_initial(u0, p0)
+    s.set_sampling(cols)
+    s.run(3)
+    ref = O.theta_parareal(Q, w.c, u0, p0, 3, sample_cols=list(cols))
+    for n in range(1, Q.N + 1):
+        u, p = s.state(n)
+        e = rel_energy_err(to_np(u), to_np(p), ref.u[n], ref.p[n], w.c,
+                           Q.dx_fine)
+        assert e < 1e-5, (n, e)
+    s.close()

@@ -138,3 +138,19 @@ def test_variant_errors():
     with pytest.raises(pw.PwError, match="Algorithm 3 only"):
         s.run_taped(1)
     s.close()
+
+
+@pytest.mark.parametrize("variant", list(ORACLE_ARGS))
+def test_disc2d_small_fp32(variant):
+    """The comparators with the FP32 compensated state: 1e-5 in the energy
+    norm relative to the oracle's result (run on the same FP32-rounded
+    initial data), the FP32 gate of Algorithm 3."""
+    w = W.disc2d(n=96, ratio=4, N=8, K=3, T=0.5)
+    s, Q, u0, p0 = _solve(w, 3, variant, dtype="f32")
+    ref = O.theta_parareal(Q, w.c, u0, p0, 3, **ORACLE_ARGS[variant])
+    for n in range(1, Q.N + 1):
+        u, p = s.state(n)
+        e = rel_energy_err(to_np(u), to_np(p), ref.u[n], ref.p[n], w.c,
+                           Q.dx_fine)
+        assert e < 1e-5, (variant, n, e)
+    s.close()
