@@ -377,8 +377,8 @@ def main():
                          "copy (for rocprofv3 --pmc FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus 1); "
-              "multi-GPU sharding is described in DESIGN.md but not built",
+        print("bench.py: runs on one GPU only (--gpus 1); sharding the "
+              "slices over several GPUs is not implemented",
               file=sys.stderr)
         sys.exit(2)
 
