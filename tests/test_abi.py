@@ -84,3 +84,15 @@ def test_invalid_problems_rejected_before_any_device_work():
         st, err = _create(P)
         assert st == -1, (msg, st, err)
         assert msg in err, (msg, err)
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU; asked for more it says so and exits 2."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"),
+                        "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
