@@ -34,10 +34,12 @@ __all__ = ["record_correctors", "forward_frozen", "misfit", "gradient",
            "theta_matrix"]
 
 
-def record_correctors(prob, c, u0, p0, K):
+def record_correctors(prob, c, u0, p0, K, sample_cols=None):
     """Run Algorithm 3 once and return the correctors [(U_k, V_k)] and the
-    coarse medium used inside Lambda / Lambda^dag."""
-    res = O.theta_parareal(prob, c, u0, p0, K, record_correctors=True)
+    coarse medium used inside Lambda / Lambda^dag (``sample_cols``: the
+    subsampling table of the run, see theta_parareal)."""
+    res = O.theta_parareal(prob, c, u0, p0, K, record_correctors=True,
+                           sample_cols=sample_cols)
     return res.correctors, O.restrict(np.asarray(c, float), prob.ratio)
 
 

@@ -251,3 +251,42 @@ def test_full_size_gradient_directional_fd():
     ad = float(np.sum(g * e))
     assert ad == pytest.approx(fd, rel=1e-5, abs=1e-12 * J0), (ad, fd)
     s.close()
+
+
+def _parity_with(w, K, rec, data, setup, oracle_kwargs):
+    """Taped run + backward on the GPU after `setup(solver)`, against the
+    adjoint oracle with correctors recorded the same way."""
+    s, u0 = _solver(w, K)
+    setup(s)
+    s.run_taped(K)
+    tr = to_np(s.traces(rec))
+    Q = O.Problem(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
+                  w.grad_order, w.tol)
+    corr, cc = A.record_correctors(Q, w.c, u0, w.p0, max(K, 1),
+                                   **oracle_kwargs)
+    J_ref, g_ref = A.gradient(Q, w.c * w.c, u0, w.p0, K, corr, cc, rec, data)
+    u, _ = A.forward_frozen(Q, w.c * w.c, u0, w.p0, K, corr, cc)
+    tr_ref = np.stack([u[n].ravel()[rec] for n in range(1, w.N + 1)])
+    np.testing.assert_allclose(tr, tr_ref, rtol=0, atol=1e-12)
+    seed = tr - data
+    g = to_np(s.backward(rec, seed, wrt="c2"))
+    err = np.abs(g - g_ref).max()
+    assert err <= 1e-8 * np.abs(g_ref).max(), (err, np.abs(g_ref).max())
+    s.close()
+
+
+def test_backward_with_sampling_matches_oracle():
+    """Taped run with random subsampling of the data matrices."""
+    K = 2
+    w, rec, data = W.misfit_case(K=K, **CASES["2d_ragged"])
+    cols = W.sample_columns(w.N, 3, K, seed=17)
+    _parity_with(w, K, rec, data, lambda s: s.set_sampling(cols),
+                 dict(sample_cols=list(cols)))
+
+
+def test_backward_spectral_gradient_matches_oracle():
+    """Taped run with the Fourier gradient inside Lambda."""
+    K = 2
+    w, rec, data = W.misfit_case(K=K, **CASES["2d"])
+    w.grad_order = "spectral"
+    _parity_with(w, K, rec, data, lambda s: None, {})
