@@ -356,6 +356,8 @@ def main():
                     help="skip the time-to-1e-5 study")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the comparator iterations of Sec. 6")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the FP32-vs-FP64 comparison of the solve")
     ap.add_argument("--no-sec6", action="store_true",
                     help="skip the Secs. 6.2 / 6.3 comparisons")
     ap.add_argument("--no-table", action="store_true",
@@ -438,6 +440,39 @@ def main():
     phases = s.timings()
     rho, ranks = s.residuals()
     log(f"solve {ms_step:.2f} ms/step")
+
+    # ---- precision: the FP32 solve against the FP64 path ------------------
+    # (the FP64 GPU path matches the FP64 oracle to 1e-12 in the parity
+    # tests; at this size it stands in for the oracle, which takes minutes)
+    precision = None
+    if not args.no_precision:
+        P64 = pw.Problem.make(w.shape, w.ratio, w.T, w.N, w.m_fine,
+                              w.m_coarse, w.grad_order, w.tol, "f64", False,
+                              K)
+        s64 = pw.Solver(P64)
+        s64.set_medium(w.c)
+        s64.set_initial(w.u0.astype(np.float32).astype(np.float64),
+                        w.p0.astype(np.float32).astype(np.float64))
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        s64.run(K)
+        torch.cuda.synchronize()
+        ms64 = (time.perf_counter() - a) * 1e3
+        errs = {}
+        for n in (1, w.N // 2, w.N):
+            u32, p32 = s.state(n)
+            u64, p64 = s64.state(n)
+            ed, er = s64.energy(u32.double(), p32.double(), u64, p64)
+            errs[str(n)] = float(f"{math.sqrt(ed / er):.3e}")
+        precision = {"fp32_vs_fp64_energy_error_at_slice": errs,
+                     "fp64_solve_ms": round(ms64, 2),
+                     "note": "FP32 compensated solve against the FP64 path "
+                             "from the same FP32-rounded initial data, "
+                             "energy norm relative to the FP64 result"}
+        log(f"FP32 vs FP64 energy error at slices 1, N/2, N: {errs}; "
+            f"FP64 solve {ms64:.1f} ms")
+        s64.close()
+        torch.cuda.empty_cache()
 
     # ---- fine stencil kernel: the batched F sweep alone ------------------
     stencil_rev = pw.lib().pw_version().decode().split()[-1]
@@ -563,6 +598,7 @@ def main():
         "fine_sweep": {"ms": round(f_ms, 4), "gupd_s": round(f_gupd, 2),
                        "launches": launches},
         "phases_ms": {k: round(v, 3) for k, v in phases.items()},
+        "precision": precision,
         "rho": [float(f"{r:.4e}") for r in rho],
         "rank": ranks,
         "time_to_1e-5": ttt,
