@@ -80,6 +80,7 @@ __global__ __launch_bounds__(NT) void k_prop_line(PropArgs<T> a) {
   T* su = reinterpret_cast<T*>(smem_raw);
   const int tid = threadIdx.x;
   const int n = a.nx;
+  T* se = su + n;  // COMP: the displacement's compensation term
   const long long base = (long long)blockIdx.x * a.sstride;
   T ru[PPT], rp[PPT], rc[PPT], reu[PPT], rep[PPT];
 #pragma unroll
@@ -95,6 +96,7 @@ __global__ __launch_bounds__(NT) void k_prop_line(PropArgs<T> a) {
         rep[k] = a.ep_in[base + i];
       }
       su[i] = ru[k];
+      if (COMP) se[i] = reu[k];
     }
   }
   __syncthreads();
@@ -106,7 +108,8 @@ __global__ __launch_bounds__(NT) void k_prop_line(PropArgs<T> a) {
       if (i < n) {
         const int im = i == 0 ? n - 1 : i - 1;
         const int ip = i == n - 1 ? 0 : i + 1;
-        const T lap = su[ip] - T(2) * ru[k] + su[im];
+        T lap = su[ip] - T(2) * ru[k] + su[im];
+        if (COMP) lap -= se[ip] - T(2) * reu[k] + se[im];  // second difference of u - e
         kadd<T, COMP>(rp[k], rep[k], w * (rc[k] * (lap * a.idx2)));
         kadd<T, COMP>(ru[k], reu[k], a.h * rp[k]);
       }
@@ -115,7 +118,10 @@ __global__ __launch_bounds__(NT) void k_prop_line(PropArgs<T> a) {
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
       const int i = tid + k * NT;
-      if (i < n) su[i] = ru[k];
+      if (i < n) {
+        su[i] = ru[k];
+        if (COMP) se[i] = reu[k];
+      }
     }
     __syncthreads();
   }
@@ -127,7 +133,8 @@ __global__ __launch_bounds__(NT) void k_prop_line(PropArgs<T> a) {
       if (i < n) {
         const int im = i == 0 ? n - 1 : i - 1;
         const int ip = i == n - 1 ? 0 : i + 1;
-        const T lap = su[ip] - T(2) * ru[k] + su[im];
+        T lap = su[ip] - T(2) * ru[k] + su[im];
+        if (COMP) lap -= se[ip] - T(2) * reu[k] + se[im];
         kadd<T, COMP>(rp[k], rep[k], w * (rc[k] * (lap * a.idx2)));
       }
     }
@@ -177,6 +184,7 @@ __global__ __launch_bounds__(NT) void k_prop_tile(PropArgs<T> a) {
   const int rx = a.rx, ry = a.ry, rz = a.rz;
   const int RN = rx * ry * rz;
   const int sy = rx, sz = rx * ry;
+  T* se = su + RN;  // COMP: the displacement's compensation term
   const long long base = (long long)state * a.sstride;
 
   T ru[PPT], rp[PPT], rc[PPT], reu[PPT], rep[PPT];
@@ -205,6 +213,7 @@ __global__ __launch_bounds__(NT) void k_prop_tile(PropArgs<T> a) {
         rep[k] = a.ep_in[base + gi];
       }
       su[i] = ru[k];
+      if (COMP) se[i] = reu[k];
     }
   }
   __syncthreads();
@@ -218,6 +227,13 @@ __global__ __launch_bounds__(NT) void k_prop_tile(PropArgs<T> a) {
         T lap = su[i + 1] - T(2) * uc + su[i - 1];
         if (D >= 2) lap += su[i + sy] - T(2) * uc + su[i - sy];
         if (D >= 3) lap += su[i + sz] - T(2) * uc + su[i - sz];
+        if (COMP) {  // second difference of u - e
+          const T ec = reu[k];
+          T le = se[i + 1] - T(2) * ec + se[i - 1];
+          if (D >= 2) le += se[i + sy] - T(2) * ec + se[i - sy];
+          if (D >= 3) le += se[i + sz] - T(2) * ec + se[i - sz];
+          lap -= le;
+        }
         kadd<T, COMP>(rp[k], rep[k], w * (rc[k] * (lap * a.idx2)));
       }
     }
@@ -233,7 +249,10 @@ __global__ __launch_bounds__(NT) void k_prop_tile(PropArgs<T> a) {
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
       const int i = tid + k * NT;
-      if (i < RN) su[i] = ru[k];
+      if (i < RN) {
+        su[i] = ru[k];
+        if (COMP) se[i] = reu[k];
+      }
     }
     __syncthreads();
   }
@@ -319,12 +338,14 @@ __device__ __forceinline__ void stream2d_body(const StreamDesc<T>& a, long long 
   const bool first = a.first, last = a.last;
   // stage j window: level-j rows (r-1, r, r+1), r = t - 2j; pending: row
   // r+2, produced during step t by stage j-1 (or loaded, for j = 0)
-  T wu[B + 1][3], wp[B + 1][2], weu[B + 1][2], wep[B + 1][2], wk[B + 1][2];
+  // weu holds rows (r-1, r, r+1) like wu: with COMP the second difference
+  // is taken of u - e, the compensated displacement
+  T wu[B + 1][3], wp[B + 1][2], weu[B + 1][3], wep[B + 1][2], wk[B + 1][2];
   T qu[B + 1], qp[B + 1], qeu[B + 1], qep[B + 1], qk[B + 1];
 #pragma unroll
   for (int j = 0; j <= B; ++j) {
     wu[j][0] = wu[j][1] = wu[j][2] = T(0);
-    wp[j][0] = wp[j][1] = weu[j][0] = weu[j][1] = T(0);
+    wp[j][0] = wp[j][1] = weu[j][0] = weu[j][1] = weu[j][2] = T(0);
     wep[j][0] = wep[j][1] = wk[j][0] = wk[j][1] = T(0);
     qu[j] = qp[j] = qeu[j] = qep[j] = qk[j] = T(0);
   }
@@ -348,11 +369,14 @@ __device__ __forceinline__ void stream2d_body(const StreamDesc<T>& a, long long 
 #pragma unroll
     for (int j = 0; j < B; ++j) {
       const T uc = wu[j][1];
-      T un = uc, pn = wp[j][0], eu = weu[j][0], ep = wep[j][0];
+      T un = uc, pn = wp[j][0], eu = weu[j][1], ep = wep[j][0];
       const T kj = wk[j][0];
       if (j < ns) {
-        const T lap =
+        T lap =
             (lane_up(uc) - T(2) * uc + lane_down(uc)) + (wu[j][0] - T(2) * uc + wu[j][2]);
+        if (COMP)
+          lap -= (lane_up(eu) - T(2) * eu + lane_down(eu)) +
+                 (weu[j][0] - T(2) * eu + weu[j][2]);
         const T w = (j == 0 && first) ? h * T(0.5) : h;
         kadd<T, COMP>(pn, ep, w * (kj * lap));
         kadd<T, COMP>(un, eu, h * pn);
@@ -383,15 +407,17 @@ __device__ __forceinline__ void stream2d_body(const StreamDesc<T>& a, long long 
     // stage B: closing half kick of the slice, then fold and write
     if (last) {
       const T uc = wu[B][1];
-      const T lap =
-          (lane_up(uc) - T(2) * uc + lane_down(uc)) + (wu[B][0] - T(2) * uc + wu[B][2]);
+      const T ec = weu[B][1];
+      T lap = (lane_up(uc) - T(2) * uc + lane_down(uc)) + (wu[B][0] - T(2) * uc + wu[B][2]);
+      if (COMP)
+        lap -= (lane_up(ec) - T(2) * ec + lane_down(ec)) + (weu[B][0] - T(2) * ec + weu[B][2]);
       T pn = wp[B][0], ep = wep[B][0];
       kadd<T, COMP>(pn, ep, h * T(0.5) * (wk[B][0] * lap));
       const int orow = t - 2 * B;
       if (out_lane && orow >= Y0 && orow < Y1) {
         const long long gi = base + (long long)orow * nx + gx;
         if (COMP) {
-          a.u_out[gi] = uc - weu[B][0];
+          a.u_out[gi] = uc - ec;
           a.p_out[gi] = pn - ep;
         } else {
           a.u_out[gi] = uc;
@@ -408,7 +434,8 @@ __device__ __forceinline__ void stream2d_body(const StreamDesc<T>& a, long long 
       wp[j][0] = wp[j][1];
       wp[j][1] = qp[j];
       weu[j][0] = weu[j][1];
-      weu[j][1] = qeu[j];
+      weu[j][1] = weu[j][2];
+      weu[j][2] = qeu[j];
       wep[j][0] = wep[j][1];
       wep[j][1] = qep[j];
       wk[j][0] = wk[j][1];
@@ -480,7 +507,7 @@ constexpr int ppt_for(TileCfg c, int D) { return (region_max(c, D) + kNT - 1) / 
 
 template <typename T, bool COMP, int PPT>
 void launch_line(const PropArgs<T>& a, int nt, hipStream_t st) {
-  const size_t smem = sizeof(T) * (size_t)a.nx;
+  const size_t smem = sizeof(T) * (size_t)a.nx * (COMP ? 2 : 1);
   switch (nt) {
     case 64:
       hipLaunchKernelGGL((k_prop_line<T, COMP, 64, PPT>), dim3(a.nstates), dim3(64), smem, st, a);
@@ -521,7 +548,7 @@ void dispatch_tile(PropArgs<T> a, hipStream_t st) {
   constexpr TileCfg c = D == 1 ? kTile1 : (D == 2 ? kTile2 : kTile3);
   constexpr int PPT = ppt_for(c, D);
   const long long blocks = (long long)a.ntx * a.nty * a.ntz * a.nstates;
-  const size_t smem = sizeof(T) * (size_t)a.rx * a.ry * a.rz;
+  const size_t smem = sizeof(T) * (size_t)a.rx * a.ry * a.rz * (COMP ? 2 : 1);
   hipLaunchKernelGGL((k_prop_tile<T, D, COMP, kNT, PPT>), dim3((unsigned)blocks), dim3(kNT), smem,
                      st, a);
   PW_LAUNCH_CHECK();
