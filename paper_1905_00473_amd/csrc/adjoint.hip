@@ -21,8 +21,8 @@ namespace {
 constexpr int kTB = 256;
 inline unsigned nblocks(long long n, int tb = kTB) { return (unsigned)((n + tb - 1) / tb); }
 
-__device__ __forceinline__ double lane_dn(double v) { return __shfl_down(v, 1, 64); }  // lane + 1
-__device__ __forceinline__ double lane_upv(double v) { return __shfl_up(v, 1, 64); }   // lane - 1
+__device__ __forceinline__ double lane_dn(double v) { return lane_shift<0x130>(v); }   // lane + 1
+__device__ __forceinline__ double lane_upv(double v) { return lane_shift<0x138>(v); }  // lane - 1
 
 struct G3 {
   int dim, nx, ny, nz;

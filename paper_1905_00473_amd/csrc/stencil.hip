@@ -309,23 +309,6 @@ __global__ __launch_bounds__(NT) void k_prop_tile(PropArgs<T> a) {
 // declared in pw_internal.h as StreamDesc<T>
 namespace {
 
-// x neighbours through the DPP wavefront shifts (wave_shr:1 = 0x138 reads
-// lane - 1, wave_shl:1 = 0x130 reads lane + 1): a modifier of a VALU move
-// instead of an LDS-crossbar permute and its lane-index arithmetic.  Lanes
-// 0 and 63 read 0; they are halo lanes of every stage.  All 64 lanes are
-// active wherever these are called.
-template <int CTRL>
-__device__ __forceinline__ float lane_shift(float v) {
-  return __builtin_bit_cast(
-      float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
-}
-template <int CTRL>
-__device__ __forceinline__ double lane_shift(double v) {
-  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
-  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-}
 template <typename T>
 __device__ __forceinline__ T lane_up(T v) {  // value of lane - 1
   return lane_shift<0x138>(v);
