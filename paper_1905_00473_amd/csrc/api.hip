@@ -391,8 +391,8 @@ void setup(Prob& pr, const pw_problem& P) {
   pr.X = m.get_n<double>(cap * cap);
   pr.Y = m.get_n<double>(cap * cap);
   pr.sig = m.get_n<double>(std::max<long long>(cap, 512));  // also reduction partials
-  pr.Hw = m.get_n<double>(cap * cap + 2 * cap + 16);
-  pr.Vw = m.get_n<double>(cap * cap);
+  pr.Hw = m.get_n<double>(2 * cap * cap + 3 * cap + 32);
+  pr.Vw = m.get_n<double>(2 * cap * cap);
   pr.counters = m.get_n<int>(64);
   pr.rank_dev = m.get_n<int>(4);
   pr.M = m.get_n<double>((long long)(pr.rmax + 1) * (pr.rmax + 1));

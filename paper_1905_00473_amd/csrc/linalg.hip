@@ -473,7 +473,7 @@ constexpr int kJLd = kJRows + 1;  // odd stride: the 16 columns fall in distinct
 
 __global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round, double* H,
                                                       double* V, int* counter,
-                                                      const double* fro2) {
+                                                      const double* fro2, double* cnorm2) {
   constexpr int RPT = kJRows / 256;  // staged rows per thread and column
   constexpr int VT = 8;              // V tiles per wave prefetched at the start
   __shared__ double Hs[kJC * kJLd];
@@ -567,6 +567,12 @@ __global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round,
   G[0][tid] = Gp[0][tid] + Gp[1][tid] + Gp[2][tid] + Gp[3][tid];
   W[0][tid] = (tid / kJC == tid % kJC) ? 1.0 : 0.0;
   if (tid == 0) any_rot = 0;
+  // squared norms of the block's columns, for the ordering of the next sweep
+  // (the diagonal of G, summed in the same order)
+  if (tid < kJC && gcol(tid) < n) {
+    const int d = tid * (kJC + 1);
+    cnorm2[gcol(tid)] = Gp[0][d] + Gp[1][d] + Gp[2][d] + Gp[3][d];
+  }
   __syncthreads();
   // a pair is rotated only if it is above the threshold in the current
   // Gram matrix; if no pair of the fresh one is, the sweep below would
@@ -641,6 +647,8 @@ __global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round,
   if (myrot) atomicAdd(&nrot, myrot);
   __syncthreads();
   if (nrot == 0) return;
+  // the rotated columns' squared norms: the diagonal of the rotated Gram
+  if (tid < kJC && gcol(tid) < n) cnorm2[gcol(tid)] = G[cur][tid * (kJC + 1)];
   // 3. H(:, cols) <- B W (B staged), V(:, cols) <- V(:, cols) W, in 16-row
   //    tiles on the matrix cores, computed transposed, (X W)^T = W^T X^T:
   //    operand A[i][k] = W^T[i][4t + k] = W[4t + k][i] (lane l: i = l%16,
@@ -694,6 +702,36 @@ __global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round,
     store(V, tile, acc);
   }
   if (tid == 0) atomicAdd(counter, nrot);
+}
+
+// column order of the next sweep: descending norm, ties by index (one
+// workgroup; n <= kJRows).  perm[k] = the column that goes to position k.
+__global__ __launch_bounds__(1024) void k_norm_order(int n, const double* nrm, int* perm) {
+  __shared__ double v[kJRows];
+  // NaN sorts last, so that the ranks always form a permutation
+  for (int c = threadIdx.x; c < n; c += 1024) v[c] = nrm[c] == nrm[c] ? nrm[c] : -1.0;
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += 1024) {
+    const double x = v[c];
+    int rank = 0;
+    for (int k = 0; k < n; ++k) rank += (v[k] > x) | ((v[k] == x) & (k < c));
+    perm[rank] = c;
+  }
+}
+
+// Hd(:, k) = Hs(:, perm[k]) and Vd(:, k) = Vs(:, perm[k]) (n x n, column-major)
+__global__ void k_gather_cols2(int n, const int* perm, const double* Hs, double* Hd,
+                               const double* Vs, double* Vd) {
+  const long long nn = (long long)n * n;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nn;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(e / n), i = (int)(e % n);
+    const int pk = perm[k];
+    const bool ok = (unsigned)pk < (unsigned)n;
+    const long long src = (long long)(ok ? pk : 0) * n + i;
+    Hd[e] = ok ? Hs[src] : 0.0;
+    Vd[e] = ok ? Vs[src] : 0.0;
+  }
 }
 
 __global__ void k_col_norms(int n, const double* H, double* sig) {
@@ -1289,30 +1327,55 @@ void svd_jacobi(int n, const double* H, double* X, double* Y, double* sig, doubl
       fclose(f);
     }
   }
-  PW_HIP(hipMemcpyAsync(Hw, H, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
-  hipLaunchKernelGGL(k_identity, dim3(nblocks(nn)), dim3(kTB), 0, st, n, Vw);
+  // workspace: Hw = two n x n buffers, then n + n (sort) + 8 + 8 (norm of H)
+  // + n (column norms) doubles; Vw = two n x n buffers.  The block version
+  // gathers the columns of H and V into the other buffer before each sweep.
+  double* Hc = Hw;
+  double* Hn = Hw + nn;
+  double* Vc = Vw;
+  double* Vn = Vw + nn;
+  double* ws = Hw + 2 * nn;
+  double* sig_u = ws;
+  int* pos = (int*)(sig_u + n);
+  double* fro2 = ws + 2 * n + 8;
+  double* cnorm2 = ws + 2 * n + 16;
+  PW_HIP(hipMemcpyAsync(Hc, H, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL(k_identity, dim3(nblocks(nn)), dim3(kTB), 0, st, n, Vc);
   PW_LAUNCH_CHECK();
   const int np = (n + 1) & ~1;
   const int maxsweeps = 40;
   PW_HIP(hipMemsetAsync(counters, 0, sizeof(int) * maxsweeps, st));
   const unsigned blocks = (unsigned)((np / 2 + 3) / 4);
-  double* fro2 = Hw + nn + 2 * n + 8;  // scratch slot after the sort workspace
-  frob_norm2(Hw, n, n, n, sig, fro2, st);  // sig used as partials (>= 512 doubles)
+  frob_norm2(Hc, n, n, n, sig, fro2, st);  // sig used as partials (>= 512 doubles)
   // block version from two block pairs up (columns in blocks of kJB)
   const int nb = (n + kJB - 1) / kJB;
   const int npb = nb + (nb & 1);
   const bool blocked = n >= 2 * kJC && n <= kJRows && !getenv("PW_JACOBI_COLUMNS");
+  if (blocked) {
+    hipLaunchKernelGGL(k_col_norms, dim3((n + 3) / 4), dim3(256), 0, st, n, (const double*)Hc,
+                       cnorm2);
+    PW_LAUNCH_CHECK();
+  }
   for (int sw = 0; sw < maxsweeps; ++sw) {
     if (blocked) {
+      // each sweep visits the columns in descending order of their norms
+      // (blocks of similar norms), which saves sweeps; the same permutation
+      // of the columns of H and V keeps H0 V = H
+      hipLaunchKernelGGL(k_norm_order, dim3(1), dim3(1024), 0, st, n, (const double*)cnorm2, pos);
+      PW_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_gather_cols2, dim3(std::min(nblocks(nn), 2048u)), dim3(kTB), 0, st, n,
+                         (const int*)pos, (const double*)Hc, Hn, (const double*)Vc, Vn);
+      PW_LAUNCH_CHECK();
+      std::swap(Hc, Hn);
+      std::swap(Vc, Vn);
       for (int round = 0; round < npb - 1; ++round) {
         hipLaunchKernelGGL(k_jacobi_block, dim3(8 * ((npb / 2 + 7) / 8)), dim3(256), 0, st, n, npb,
-                           round, Hw, Vw,
-                           counters + sw, (const double*)fro2);
+                           round, Hc, Vc, counters + sw, (const double*)fro2, cnorm2);
         PW_LAUNCH_CHECK();
       }
     } else {
       for (int round = 0; round < np - 1; ++round) {
-        hipLaunchKernelGGL(k_jacobi_round, dim3(blocks), dim3(256), 0, st, n, np, round, Hw, Vw,
+        hipLaunchKernelGGL(k_jacobi_round, dim3(blocks), dim3(256), 0, st, n, np, round, Hc, Vc,
                            counters + sw, (const double*)fro2);
         PW_LAUNCH_CHECK();
       }
@@ -1323,15 +1386,13 @@ void svd_jacobi(int n, const double* H, double* X, double* Y, double* sig, doubl
     if (debug_jacobi()) fprintf(stderr, "[jacobi n=%d] sweep %d: %d rotations\n", n, sw, h);
     if (h == 0) break;
   }
-  double* sig_u = Hw + nn;  // Hw has n*n + 2n doubles of room
-  int* pos = (int*)(sig_u + n);
-  hipLaunchKernelGGL(k_col_norms, dim3((n + 3) / 4), dim3(256), 0, st, n, (const double*)Hw, sig_u);
+  hipLaunchKernelGGL(k_col_norms, dim3((n + 3) / 4), dim3(256), 0, st, n, (const double*)Hc, sig_u);
   PW_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_sort_rank, dim3(1), dim3(1024), 0, st, n, (const double*)sig_u, pos, tol,
                      rank_dev, sig);
   PW_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_scatter_svd, dim3(nblocks(nn)), dim3(kTB), 0, st, n, (const double*)Hw,
-                     (const double*)Vw, (const int*)pos, (const double*)sig_u, X, Y);
+  hipLaunchKernelGGL(k_scatter_svd, dim3(nblocks(nn)), dim3(kTB), 0, st, n, (const double*)Hc,
+                     (const double*)Vc, (const int*)pos, (const double*)sig_u, X, Y);
   PW_LAUNCH_CHECK();
 }
 

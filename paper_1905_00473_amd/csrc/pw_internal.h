@@ -295,7 +295,7 @@ void orth_finish(long long rows, int n, const double* A, long long lda, double* 
 // one-sided Jacobi SVD of the n x n matrix H (column-major, ld = n):
 // on return X (n x n, ld n) holds left singular vectors, Y right singular
 // vectors, sig singular values, sorted descending; *rank_dev the number
-// with sig/sig_max > tol.  Scratch: Hw (n*n + 2n + 16), Vw (n*n),
+// with sig/sig_max > tol.  Scratch: Hw (2 n*n + 3n + 16), Vw (2 n*n),
 // counters (40 ints); sig must hold max(n, 512) doubles.
 void svd_jacobi(int n, const double* H, double* X, double* Y, double* sig, double tol,
                 int* rank_dev, double* Hw, double* Vw, int* counters, hipStream_t stream);
