@@ -280,3 +280,40 @@ def test_update_svd_qr_shapes(nc, ncols):
         np.testing.assert_allclose(Ug.T @ Ug, np.eye(r),
                                    atol=1e-12 if rows >= ncols else 1e-10)
     s.close()
+
+
+def test_update_svd_tied_norms():
+    """Algorithm 1 when the core matrix has columns of equal norm (the SVD
+    orders every sweep by column norm, ties by index): data F = G = 2 Q_k
+    with orthonormal Q_k give a core 4 I (every norm tied, no rotation),
+    then a random update mixes the tied block.  Against the oracle as
+    above: singular values 1e-9, Omega-action 1e-9, U orthonormal 1e-12."""
+    import paper_1905_00473_amd as pw
+    import torch
+    nc, ncols = 64, 48
+    rows = 2 * nc
+    m_c = int(np.ceil(2 * nc / ncols))
+    P = pw.Problem.make((nc,), 1, 1.0, ncols, 4 * m_c, m_c, 4, 1e-6, "f64",
+                        False, 3)
+    s = pw.Solver(P)
+    s.set_medium(np.ones(nc))
+    rng = np.random.default_rng(11)
+    Qm, _ = np.linalg.qr(rng.standard_normal((rows, rows)))
+    data = [2.0 * Qm[:, :ncols], 2.0 * Qm[:, ncols:2 * ncols]]
+    basis = rng.standard_normal((rows, 30)) * (0.6 ** np.arange(30))
+    data.append(basis @ rng.standard_normal((30, ncols)))
+    U = S = V = None
+    for it, F in enumerate(data):
+        G = F if it < 2 else F + 0.05 * (basis @ rng.standard_normal((30, ncols)))
+        U, S, V = O.update_svd(U, S, V, F, G, 1e-6)
+        r = s.update_svd(torch.tensor(F.T.copy(), device="cuda"),
+                         torch.tensor(G.T.copy(), device="cuda"),
+                         reset=(it == 0))
+        Ug, Sg, Vg = s.corrector()
+        assert r == len(S), (it, r, len(S))
+        np.testing.assert_allclose(to_np(Sg), S, rtol=1e-9, atol=1e-12 * S[0])
+        Ug, Vg = to_np(Ug).T, to_np(Vg).T
+        d = np.abs(Ug @ (Vg.T @ G) - U @ (V.T @ G)).max() / np.abs(G).max()
+        assert d < 1e-9, (it, d)
+        np.testing.assert_allclose(Ug.T @ Ug, np.eye(r), atol=1e-12)
+    s.close()
