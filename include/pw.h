@@ -87,6 +87,9 @@ typedef struct {
   int max_iters;       /* largest K that pw_run will be asked for (sizes the
                           corrector bases: rank <= max_iters * n_slices)     */
   int interp;          /* pw_interp: the interpolation I (0 = trigonometric) */
+  int keep_history;    /* 1: keep every iterate u^k_n, k = 1..max_iters+1, on
+                          the device for pw_get_iterate ((max_iters + 1) N
+                          fine states); 0: only the current one         */
 } pw_problem;
 
 /* The interpolation I from the coarse to the fine grid: trigonometric
@@ -130,15 +133,37 @@ pw_status pw_set_initial(pw_ctx* ctx, int prob, const double* u0,
 
 /*
  * Algorithm 3 (eq. thetarelation): the coarse initialisation
- * u^1_n = I C R u^1_{n-1} followed by K iterations of: F on all slices in
- * one batched launch, the data matrices F^k = [Lambda R v_n],
+ * u^1_n = I C R u^1_{n-1} followed by up to K iterations of: F on all
+ * slices in one batched launch, the data matrices F^k = [Lambda R v_n],
  * G^k = [Lambda C R u^k_{n-1}], the incremental Procrustes SVD of
  * Algorithm 1, the corrected sweep over n and the update
- * u^{k+1}_n = v_n + I delta_n.  K <= max_iters.  Runs on the context
- * stream; synchronises once per iteration to read the new rank.  Each
- * call restarts from u0 (the iteration count and corrector are reset).
+ * u^{k+1}_n = v_n + I delta_n.  K <= max_iters.  Each call restarts from
+ * u0 (the iteration count and corrector are reset).
+ *
+ * Stopping rule (the "while tolerance not met" of Algorithm 3, which the
+ * paper leaves open): with stop_tol > 0 the run ends after the first
+ * iteration k whose change max_n sqrt(E(u^{k+1}_n - u^k_n) / E(u^{k+1}_n))
+ * (discrete energy on the fine grid, FP64) is <= stop_tol; that costs one
+ * energy reduction per slice and one host synchronisation per iteration.
+ * stop_tol = 0 runs exactly K iterations.  *k_done (may be NULL) receives
+ * the number of iterations run; the current iterate is then u^{k_done+1}.
+ * Runs on the context stream; synchronises once per iteration to read the
+ * new rank of Algorithm 1 and once per Jacobi sweep of its core SVD.
  */
-pw_status pw_run(pw_ctx* ctx, int prob, int K);
+pw_status pw_run(pw_ctx* ctx, int prob, int K, double stop_tol, int* k_done);
+
+/*
+ * Resume Algorithm 3 from the current iterate and corrector (left by
+ * pw_run, pw_run_batch, pw_continue, pw_load or overwritten with
+ * pw_set_iterate / pw_set_corrector) for up to K more iterations,
+ * numbered k_done + 1, ...; k_done + K <= max_iters.  update_corrector = 1:
+ * each iteration updates the corrector with Algorithm 1 on its data, as
+ * pw_run does; 0: the current corrector Omega = U~ V~^T is held fixed (no
+ * data matrices, no SVD; the iteration's residual is reported as NaN).
+ * stop_tol and *k_done as for pw_run.  PW_ESTATE without an iterate.
+ */
+pw_status pw_continue(pw_ctx* ctx, int prob, int K, int update_corrector, double stop_tol,
+                      int* k_done);
 
 /*
  * Comparator iterations of Sec. 6, run by pw_run in place of Algorithm 3
@@ -226,12 +251,52 @@ pw_status pw_sync(pw_ctx* ctx);
 pw_status pw_get_state(pw_ctx* ctx, int prob, int n, void* u, void* p,
                        int on_device);
 
+/* Iterate u^k_n of the last run (eq. (2) / Algorithm 3 notation: k = 1 is
+ * the coarse initialisation, k = k_done + 1 the current iterate), n = 0..N
+ * (u^k_0 = u0), into caller buffers of n_points elements of the state
+ * dtype.  k < k_done + 1 needs keep_history = 1 (PW_EINVAL otherwise).
+ * PW_ESTATE before the first run.  on_device as for pw_get_state.      */
+pw_status pw_get_iterate(pw_ctx* ctx, int prob, int k, int n, void* u, void* p,
+                         int on_device);
+
+/* Overwrite slice n = 1..N of the current iterate u^{k_done+1}_n with the
+ * double fields u, p (fine grid, rounded to the state dtype), e.g. to
+ * resume from iterates computed elsewhere.  PW_ESTATE before the first
+ * run.  Synchronous.                                                    */
+pw_status pw_set_iterate(pw_ctx* ctx, int prob, int n, const double* u, const double* p,
+                         int on_device);
+
+/* Replace the corrector of Algorithm 1 by U~ (rows x rank), S~ (rank),
+ * V~ (rows x rank), double, column-major, with orthonormal columns (the
+ * caller's responsibility); Omega = U~ V~^T then acts in the sweep.  rank
+ * <= min(max_iters * N, rows).  Synchronous.                           */
+pw_status pw_set_corrector(pw_ctx* ctx, int prob, const double* U, const double* S,
+                           const double* V, int rank, int on_device);
+
 /* Per-iteration diagnostics of the last pw_run, k = 1..K: relative
  * Procrustes residual rho_k = ||F^k - Omega^k G^k||_F / ||F^k||_F
  * (Sec. 6.4) and the rank of Omega^k (Algorithm 1).  cap = array length;
  * returns the number of iterations in *count.  Host output, synchronous. */
 pw_status pw_get_residuals(pw_ctx* ctx, int prob, double* rho_host,
                            int* rank_host, int cap, int* count);
+
+/* Per-iteration record of the last run (FP64, host), PW_DIAG_STRIDE values
+ * per iteration k = 1..k_done at out[(k-1) * PW_DIAG_STRIDE + i]:
+ *   i = 0  rho_k = ||F^k - Omega^k G^k||_F / ||F^k||_F (Sec. 6.4)
+ *   i = 1  rank of Omega^k (Algorithm 1)
+ *   i = 2  ||F^k||_F^2 over all N columns
+ *   i = 3  ||F^k_in||_F^2, i = 4  ||G^k_in||_F^2: the columns that entered
+ *          Algorithm 1 (all N unless subsampled)
+ *   i = 5  trace of S~^k (sum of the retained singular values)
+ *   i = 6  r^2_min = sum_{j<=k} (||F^j_in||^2 + ||G^j_in||^2) - 2 tr S~^k,
+ *          the minimum residual of the accumulated Procrustes problem of
+ *          Sec. 3.3 (exact without truncation; reported as computed)
+ *   i = 7  the stopping measure of pw_run (NaN unless stop_tol > 0)
+ * Iterations without a fitted corrector (comparators, frozen corrector)
+ * report 0 or NaN where a value does not exist.  cap = iterations the
+ * array holds; *count = k_done.                                          */
+#define PW_DIAG_STRIDE 8
+pw_status pw_get_diagnostics(pw_ctx* ctx, int prob, double* out, int cap, int* count);
 
 /* Serial fine reference u(t_n) = F^n [u0, p0] (Sec. 6: computed serially
  * with the fine propagator) written to caller device buffers u_dev, p_dev
@@ -297,6 +362,27 @@ pw_status pw_energy(pw_ctx* ctx, int prob, const void* u, const void* p,
                     const void* u_ref, const void* p_ref, double* e_diff,
                     double* e_ref);
 
+/* Error measures of the Sec. 6 preamble on the fine grid, FP64 (host,
+ * synchronous): out[0] = E([u - u_ref, p - p_ref]), out[1] = E([u_ref,
+ * p_ref]) (as pw_energy), out[2] = sum (u - u_ref)^2, out[3] = sum u_ref^2
+ * over the grid points (the l2 error of the displacement is
+ * sqrt(out[2] / out[3])).  u_ref may be NULL (then out[0] = E([u, p]),
+ * out[2] = sum u^2, out[1] = out[3] = 0).                              */
+pw_status pw_error_norms(pw_ctx* ctx, int prob, const void* u, const void* p,
+                         const void* u_ref, const void* p_ref, double* out);
+
+/* Checkpoint of the whole context: per problem the medium, u0, the current
+ * iterate, kept history, corrector (U~, S~, V~ and the sweep columns),
+ * per-iteration records, comparator variant and sampling table, written to
+ * the file `path` (host byte order, format tag PWCKPT01).  pw_load restores
+ * it into a context created with the same problem descriptions (PW_EINVAL
+ * otherwise, or for a damaged file; the state is then unspecified until the
+ * next set_* / run), after which pw_continue resumes the iteration exactly
+ * where pw_save left it (bit for bit).  Tapes of taped runs are not saved.
+ * Synchronous.                                                          */
+pw_status pw_save(pw_ctx* ctx, const char* path);
+pw_status pw_load(pw_ctx* ctx, const char* path);
+
 /* Per-phase device time of the last pw_run in milliseconds, measured with
  * HIP events on the context stream: [0] parallel fine+coarse propagation,
  * [1] creating the corrector (data matrices + Algorithm 1), [2] corrected
@@ -332,6 +418,11 @@ pw_status pw_run_taped(pw_ctx* ctx, int prob, int K);
  * tape.  Residuals are not formed (pw_get_residuals then reports 0
  * iterations).  PW_ESTATE without a prior taped run.                    */
 pw_status pw_run_frozen(pw_ctx* ctx, int prob, int K);
+
+/* Serial number of the tape: bumped by every pw_run_taped and
+ * pw_run_frozen, so a caller that keeps a gradient graph can tell whether
+ * the tape pw_backward will read is still the one its forward recorded. */
+pw_status pw_get_tape_id(pw_ctx* ctx, int prob, long long* id);
 
 /* Traces of the current iterate: out[(n-1)*n_rec + r] = u_n(receivers[r])
  * for n = 1..N, receivers given as flat fine-grid indices (x fastest,

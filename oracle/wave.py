@@ -356,7 +356,7 @@ def _rank(sig, tol):
     return int(np.sum(sig / np.max(sig) > tol))
 
 
-def update_svd(U, S, V, F, G, tol):
+def update_svd(U, S, V, F, G, tol, svd=None):
     """Algorithm 1: truncated SVD of M_new = U diag(S) V^T + F G^T.
 
     With S empty (first call): reduced QR of F and G, SVD of R_F R_G^T,
@@ -365,14 +365,17 @@ def update_svd(U, S, V, F, G, tol):
     Gram-Schmidt re-orthogonalisation pass against U / V, exact no-op in
     exact arithmetic), SVD of H = [U_F; R_F][V_G; R_G]^T + diag(S, 0),
     truncation, and the rotated bases [U Q_F] X_h, [V Q_G] Y_h.
-    Returns (U_new, S_new, V_new).
+    Returns (U_new, S_new, V_new).  ``svd``: the SVD routine (default
+    numpy.linalg.svd, LAPACK's divide and conquer); another backward-stable
+    driver gives the same exact arithmetic with other rounding.
     """
+    svd = svd or np.linalg.svd
     F = np.asarray(F, dtype=np.float64)
     G = np.asarray(G, dtype=np.float64)
     if S is None or len(S) == 0:
         QF, RF = _reduced_qr(F)
         QG, RG = _reduced_qr(G)
-        X, sig, Yt = np.linalg.svd(RF @ RG.T)
+        X, sig, Yt = svd(RF @ RG.T)
         r = _rank(sig, tol)
         return QF @ X[:, :r], sig[:r].copy(), QG @ Yt.T[:, :r]
     UF = U.T @ F
@@ -390,7 +393,7 @@ def update_svd(U, S, V, F, G, tol):
     H = np.vstack([UF, RF]) @ np.vstack([VG, RG]).T
     r0 = len(S)
     H[:r0, :r0] += np.diag(S)
-    X, sig, Yt = np.linalg.svd(H)
+    X, sig, Yt = svd(H)
     r = _rank(sig, tol)
     Un = np.hstack([U, QF]) @ X[:, :r]
     Vn = np.hstack([V, QG]) @ Yt.T[:, :r]
@@ -414,11 +417,13 @@ class PararealResult:
     history: list           # [(u list, p list)] for k = 1..K+1 if kept
     sigma: list             # singular values after each update
     correctors: list = None  # [(U_k, V_k)] if recorded
+    data_norms: list = None  # [(||F^k||^2, ||F^k_in||^2, ||G^k_in||^2)]
 
 
 def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
                    omega="procrustes", correction=True,
-                   record_correctors=False, sample_cols=None):
+                   record_correctors=False, sample_cols=None, pmap=None,
+                   svd=None):
     """Algorithm 3 of the paper, step by step.
 
     Initialisation u^1_n = I C R u^1_{n-1}; then K iterations of: parallel
@@ -437,6 +442,13 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
     Entry k-1 lists the columns (0-based, column j holds slice j+1) of
     F^k and G^k that Algorithm 1 receives in iteration k; the draw is an
     input.  rho_k is still measured on all N columns.
+
+    ``pmap``: how the parallel loop of Algorithm 3 (the parfor over slices)
+    is executed: a function with the signature of ``itertools.starmap``
+    applied to ``propagate`` and one argument tuple per slice (e.g. a
+    process pool's ``starmap``); None runs the slices one after another.
+    Every slice is computed by the same ``propagate`` call either way.
+    ``svd``: the SVD routine of Algorithm 1 (see update_svd).
     """
     r = prob.ratio
     ik = prob.interp
@@ -467,13 +479,20 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
         if keep_history else []
 
     Us = S = Vs = None
-    rhos, ranks, sigmas = [], [], []
+    rhos, ranks, sigmas, norms = [], [], [], []
     correctors = [] if record_correctors else None
     for _k in range(K):
         v, vp, Uc, Ucp = [None] * (N + 1), [None] * (N + 1), \
             [None] * (N + 1), [None] * (N + 1)
+        if pmap is not None:                # the parallel loop (parfor)
+            out = list(pmap(propagate,
+                            [(u[n - 1], p[n - 1], c2f, hf, dxf, prob.m_fine)
+                             for n in range(1, N + 1)]))
+            for n in range(1, N + 1):
+                v[n], vp[n] = out[n - 1]
         for n in range(1, N + 1):           # the parallel loop
-            v[n], vp[n] = Fprop(u[n - 1], p[n - 1])
+            if pmap is None:
+                v[n], vp[n] = Fprop(u[n - 1], p[n - 1])
             Uc[n], Ucp[n] = Cprop(restrict(u[n - 1], r),
                                   restrict(p[n - 1], r))
         Fm = np.column_stack([Lam(restrict(v[n], r), restrict(vp[n], r))
@@ -491,13 +510,16 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
                     raise ValueError("sample columns must be distinct "
                                      "indices in [0, N)")
                 Fs, Gs = Fm[:, cols], Gm[:, cols]
-            Us, S, Vs = update_svd(Us, S, Vs, Fs, Gs, prob.tol)
+            norms.append((float(np.sum(Fm * Fm)), float(np.sum(Fs * Fs)),
+                          float(np.sum(Gs * Gs))))
+            Us, S, Vs = update_svd(Us, S, Vs, Fs, Gs, prob.tol, svd)
             if record_correctors:
                 correctors.append((Us.copy(), Vs.copy()))
             res = Fm - omega_apply(Us, Vs, Gm)
             ranks.append(len(S))
             sigmas.append(S.copy())
         else:
+            norms.append((float(np.sum(Fm * Fm)), 0.0, 0.0))
             res = Fm - Gm
             ranks.append(Fm.shape[0])
             sigmas.append(np.zeros(0))
@@ -539,7 +561,7 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
             history.append(([x.copy() for x in u], [x.copy() for x in p]))
     return PararealResult(u=u, p=p, rho=rhos, rank=ranks,
                             history=history, sigma=sigmas,
-                            correctors=correctors)
+                            correctors=correctors, data_norms=norms)
 
 
 def serial_fine(prob: Problem, c, u0, p0):

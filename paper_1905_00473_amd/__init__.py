@@ -14,7 +14,7 @@ import ctypes
 import os
 
 __all__ = ["Problem", "Solver", "lib", "PwError", "LIB_PATH", "F32", "F64",
-           "FINE", "COARSE", "PararealTraces"]
+           "FINE", "COARSE", "PararealTraces", "require", "DIAG_FIELDS"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)),
                         "libpwave.so")
@@ -47,14 +47,15 @@ class Problem(ctypes.Structure):
         ("compensated", ctypes.c_int),
         ("max_iters", ctypes.c_int),
         ("interp", ctypes.c_int),
+        ("keep_history", ctypes.c_int),
     ]
 
     @classmethod
     def make(cls, shape, ratio, T, N, m_fine, m_coarse, grad_order=4,
              tol=1e-14, dtype="f64", compensated=False, max_iters=8,
-             interp="trig"):
+             interp="trig", keep_history=False):
         """shape: fine grid in numpy order (x last); interp: "trig",
-        "linear" or "cubic"."""
+        "linear" or "cubic"; keep_history: keep every iterate u^k_n."""
         p = cls()
         p.dim = len(shape)
         xyz = list(reversed(shape)) + [1] * (3 - len(shape))
@@ -71,6 +72,7 @@ class Problem(ctypes.Structure):
         p.compensated = int(bool(compensated))
         p.max_iters = int(max_iters)
         p.interp = {"trig": 0, "linear": 1, "cubic": 2}.get(interp, interp)
+        p.keep_history = int(bool(keep_history))
         return p
 
 
@@ -88,7 +90,27 @@ _SIGS = {
                       ctypes.c_int],
     "pw_set_initial": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                        ctypes.c_void_p, ctypes.c_int],
-    "pw_run": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int],
+    "pw_run": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+               ctypes.POINTER(ctypes.c_int)],
+    "pw_continue": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                    ctypes.c_double, ctypes.POINTER(ctypes.c_int)],
+    "pw_get_iterate": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                       ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                       ctypes.c_int],
+    "pw_set_iterate": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
+    "pw_set_corrector": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                         ctypes.c_int],
+    "pw_get_diagnostics": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                           ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
+    "pw_error_norms": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                       ctypes.c_void_p],
+    "pw_save": [ctypes.c_void_p, ctypes.c_char_p],
+    "pw_load": [ctypes.c_void_p, ctypes.c_char_p],
+    "pw_get_tape_id": [ctypes.c_void_p, ctypes.c_int,
+                       ctypes.POINTER(ctypes.c_longlong)],
     "pw_set_variant": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int],
     "pw_set_sampling": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                         ctypes.c_int, ctypes.c_int],
@@ -174,6 +196,31 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+#: values per iteration of Solver.diagnostics (PW_DIAG_STRIDE)
+DIAG_STRIDE = 8
+DIAG_FIELDS = ("rho", "rank", "F2", "F_in2", "G_in2", "trace_S", "r2_min",
+               "change")
+
+
+def require(t, dtype, shape, name):
+    """Check a tensor handed to the C ABI: a CUDA (HIP) tensor of the given
+    torch dtype and shape, contiguous.  Raises ValueError before any device
+    work (the library reads and writes exactly the sizes the problem
+    implies, so a mismatch would read or write out of bounds)."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: expected a device (cuda) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    return t
+
+
 class Solver:
     """A context of one or more wave problems on the current CUDA (HIP)
     device and stream."""
@@ -247,8 +294,79 @@ class Solver:
         a, b = self._dev(u0, torch.float64), self._dev(p0, torch.float64)
         _check(lib().pw_set_initial(self._h, prob, _ptr(a), _ptr(b), 1))
 
-    def run(self, K, prob=0):
-        _check(lib().pw_run(self._h, prob, int(K)))
+    def run(self, K, prob=0, stop_tol=0.0):
+        """Algorithm 3 from u0: coarse initialisation and up to K
+        iterations (stop_tol > 0: stop once the change of the iterate falls
+        to stop_tol).  Returns the number of iterations run."""
+        kd = ctypes.c_int()
+        _check(lib().pw_run(self._h, prob, int(K), float(stop_tol),
+                            ctypes.byref(kd)))
+        return kd.value
+
+    def resume(self, K, update_corrector=True, stop_tol=0.0, prob=0):
+        """Continue Algorithm 3 from the current iterate for up to K more
+        iterations (update_corrector=False holds the corrector fixed).
+        Returns k_done after the call."""
+        kd = ctypes.c_int()
+        _check(lib().pw_continue(self._h, prob, int(K),
+                                 int(bool(update_corrector)),
+                                 float(stop_tol), ctypes.byref(kd)))
+        return kd.value
+
+    def iterate(self, k, n, prob=0):
+        """u^k_n, p^k_n of the last run (k = 1: coarse initialisation)."""
+        import torch
+        u = torch.empty(self.shape(prob), dtype=self.dtype(prob), device="cuda")
+        p = torch.empty_like(u)
+        _check(lib().pw_get_iterate(self._h, prob, int(k), int(n), _ptr(u),
+                                    _ptr(p), 1))
+        return u, p
+
+    def set_iterate(self, n, u, p, prob=0):
+        """Overwrite slice n (1..N) of the current iterate (float64 fields)."""
+        import torch
+        a, b = self._dev(u, torch.float64), self._dev(p, torch.float64)
+        require(a, torch.float64, self.shape(prob), "u")
+        require(b, torch.float64, self.shape(prob), "p")
+        _check(lib().pw_set_iterate(self._h, prob, int(n), _ptr(a), _ptr(b), 1))
+
+    def set_corrector(self, U, S, V, prob=0):
+        """Replace the corrector: U, V (rank, rows), S (rank,) float64, rows
+        of U and V the singular vectors."""
+        import torch
+        U = self._dev(U, torch.float64)
+        V = self._dev(V, torch.float64)
+        S = self._dev(S, torch.float64).reshape(-1)
+        r = int(S.numel())
+        require(U, torch.float64, (r, self.rows(prob)), "U")
+        require(V, torch.float64, (r, self.rows(prob)), "V")
+        _check(lib().pw_set_corrector(self._h, prob, _ptr(U), _ptr(S), _ptr(V),
+                                      r, 1))
+
+    def diagnostics(self, prob=0, cap=256):
+        """Per-iteration record: a list of dicts with the DIAG_FIELDS."""
+        buf = (ctypes.c_double * (DIAG_STRIDE * cap))()
+        cnt = ctypes.c_int()
+        _check(lib().pw_get_diagnostics(self._h, prob, buf, cap,
+                                        ctypes.byref(cnt)))
+        out = []
+        for k in range(min(cnt.value, cap)):
+            row = buf[DIAG_STRIDE * k:DIAG_STRIDE * (k + 1)]
+            d = dict(zip(DIAG_FIELDS, row))
+            d["rank"] = int(d["rank"])
+            out.append(d)
+        return out
+
+    def save(self, path):
+        _check(lib().pw_save(self._h, os.fsencode(path)))
+
+    def load(self, path):
+        _check(lib().pw_load(self._h, os.fsencode(path)))
+
+    def tape_id(self, prob=0):
+        v = ctypes.c_longlong()
+        _check(lib().pw_get_tape_id(self._h, prob, ctypes.byref(v)))
+        return v.value
 
     def set_sampling(self, cols, prob=0):
         """Random subsampling of the data matrices: cols is a
@@ -359,17 +477,45 @@ class Solver:
                                  int(checkpoint_every)))
         return g
 
+    def _state_args(self, prob, **fields):
+        sh, dt = self.shape(prob), self.dtype(prob)
+        for name, t in fields.items():
+            if t is not None:
+                require(t, dt, sh, name)
+
     def energy(self, u, p, u_ref=None, p_ref=None, prob=0):
+        self._state_args(prob, u=u, p=p, u_ref=u_ref, p_ref=p_ref)
+        if (u_ref is None) != (p_ref is None):
+            raise ValueError("u_ref and p_ref go together")
         ed, er = ctypes.c_double(), ctypes.c_double()
         _check(lib().pw_energy(self._h, prob, _ptr(u), _ptr(p), _ptr(u_ref),
                                _ptr(p_ref), ctypes.byref(ed),
                                ctypes.byref(er)))
         return ed.value, er.value
 
+    def error_norms(self, u, p, u_ref=None, p_ref=None, prob=0):
+        """dict: energy error sqrt(E(d)/E(ref)), l2 error of u, and the raw
+        sums E(d), E(ref), sum (u-u_ref)^2, sum u_ref^2."""
+        import math
+        self._state_args(prob, u=u, p=p, u_ref=u_ref, p_ref=p_ref)
+        if (u_ref is None) != (p_ref is None):
+            raise ValueError("u_ref and p_ref go together")
+        out = (ctypes.c_double * 4)()
+        _check(lib().pw_error_norms(self._h, prob, _ptr(u), _ptr(p),
+                                    _ptr(u_ref), _ptr(p_ref), out))
+        e, e0, d2, r2 = out[0], out[1], out[2], out[3]
+        return dict(energy=math.sqrt(e / e0) if e0 > 0 else math.sqrt(e),
+                    l2=math.sqrt(d2 / r2) if r2 > 0 else math.sqrt(d2),
+                    E_diff=e, E_ref=e0, l2_diff2=d2, l2_ref2=r2)
+
     # -- building blocks (parity checks) --------------------------------------
     def propagate(self, u, p, grid=FINE, prob=0):
         """u, p: (n_states, *grid) tensors of the state dtype."""
         import torch
+        sh = self.shape(prob) if grid == FINE else self.coarse_shape(prob)
+        n = int(u.shape[0]) if getattr(u, "dim", lambda: 0)() > 0 else 0
+        require(u, self.dtype(prob), (n,) + sh, "u")
+        require(p, self.dtype(prob), (n,) + sh, "p")
         uo, po = torch.empty_like(u), torch.empty_like(p)
         _check(lib().pw_propagate(self._h, prob, grid, _ptr(u), _ptr(p),
                                   _ptr(uo), _ptr(po), int(u.shape[0])))
@@ -377,7 +523,10 @@ class Solver:
 
     def energy_components(self, u, p, grid=FINE, prob=0):
         import torch
-        n = int(u.shape[0])
+        n = int(u.shape[0]) if getattr(u, "dim", lambda: 0)() > 0 else 0
+        sh = self.shape(prob) if grid == FINE else self.coarse_shape(prob)
+        require(u, self.dtype(prob), (n,) + sh, "u")
+        require(p, self.dtype(prob), (n,) + sh, "p")
         out = torch.empty((n, self.rows(prob)), dtype=torch.float64,
                           device="cuda")
         _check(lib().pw_energy_components(self._h, prob, grid, _ptr(u),
@@ -386,8 +535,16 @@ class Solver:
 
     def interp_add(self, du, dp, v=None, vp=None, prob=0):
         import torch
-        n = int(du.shape[0])
+        n = int(du.shape[0]) if getattr(du, "dim", lambda: 0)() > 0 else 0
+        cs = (n,) + self.coarse_shape(prob)
+        require(du, torch.float64, cs, "du")
+        require(dp, torch.float64, cs, "dp")
         shp = (n,) + self.shape(prob)
+        if (v is None) != (vp is None):
+            raise ValueError("v and vp go together")
+        if v is not None:
+            require(v, self.dtype(prob), shp, "v")
+            require(vp, self.dtype(prob), shp, "vp")
         uo = torch.empty(shp, dtype=self.dtype(prob), device="cuda")
         po = torch.empty_like(uo)
         _check(lib().pw_interp_add(self._h, prob, _ptr(du), _ptr(dp), _ptr(v),
@@ -395,8 +552,14 @@ class Solver:
         return uo, po
 
     def grad2func(self, q, sums=None, prob=0):
+        import math
         import torch
-        n = int(q.shape[0])
+        n = int(q.shape[0]) if getattr(q, "dim", lambda: 0)() > 0 else 0
+        d = self.problems[prob].dim
+        nc = math.prod(self.coarse_shape(prob))
+        require(q, torch.float64, (n, d * nc), "q")
+        if sums is not None:
+            require(sums, torch.float64, (n,), "sums")
         w = torch.empty((n,) + self.coarse_shape(prob), dtype=torch.float64,
                         device="cuda")
         _check(lib().pw_grad2func(self._h, prob, _ptr(q), _ptr(sums), _ptr(w),
@@ -405,6 +568,10 @@ class Solver:
 
     def update_svd(self, F, G, reset=False, prob=0):
         """F, G: (n_cols, rows) float64 device tensors (column j = row j)."""
+        import torch
+        n = int(F.shape[0]) if getattr(F, "dim", lambda: 0)() > 0 else 0
+        require(F, torch.float64, (n, self.rows(prob)), "F")
+        require(G, torch.float64, (n, self.rows(prob)), "G")
         rk = ctypes.c_int()
         _check(lib().pw_update_svd(self._h, prob, _ptr(F), _ptr(G),
                                    int(F.shape[0]), int(bool(reset)),
@@ -443,10 +610,16 @@ def _traces_function():
             solver.set_medium(c.detach(), prob)
             solver.run_taped(K, prob)
             ctx.solver, ctx.receivers, ctx.prob = solver, receivers, prob
+            # the tape this graph's backward must read
+            ctx.tape_id = solver.tape_id(prob)
             return solver.traces(receivers, prob)
 
         @staticmethod
         def backward(ctx, grad_traces):
+            if ctx.solver.tape_id(ctx.prob) != ctx.tape_id:
+                raise PwError(-5, "the solver ran another taped forward since "
+                                  "this graph was recorded; its tape is gone "
+                                  "(use one Solver per live graph)")
             g = ctx.solver.backward(ctx.receivers, grad_traces.contiguous(),
                                     wrt="c", prob=ctx.prob)
             return g, None, None, None, None

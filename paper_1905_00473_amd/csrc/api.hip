@@ -50,6 +50,13 @@ namespace {
 
 thread_local std::string g_last_error;
 
+// per-iteration device record: [0] ||F - Omega G||_F^2, [1] ||F||_F^2 (all N
+// columns), [2] ||F_in||_F^2, [3] ||G_in||_F^2 (the columns entering
+// Algorithm 1), [4] trace of S~ after the update
+constexpr int kRes = 5;
+// values per iteration returned by pw_get_diagnostics
+constexpr int kPwDiag = 8;
+
 struct Buffers {
   std::vector<void*> ptrs;
   void* get(size_t bytes) {
@@ -198,9 +205,18 @@ struct Prob {
   int r = 0;      // current rank
   int k_done = 0;
   bool have_medium = false, have_initial = false;
+  bool have_iterate = false;  // u^{k_done+1}_n exists (after a run, a continue or a load)
   std::vector<int> ranks;
+  // iterate history (keep_history): level k-1 holds u^k_n, n = 1..N
+  // ((max_iters + 1) levels of N fields; u^k_0 = u0 for every k)
+  void *hist_u = nullptr, *hist_p = nullptr;
+  DevBuf prev;                 // u^k_n, n = 1..N, for the stopping rule without history
+  double* chg = nullptr;       // device: N x 4 energy sums of u^{k+1}_n - u^k_n
+  std::vector<double> change;  // per iteration: max_n sqrt(E(u^{k+1}_n - u^k_n) / E(u^{k+1}_n))
+  long long tape_serial = 0;   // bumped by every taped or frozen run
   double ms[4] = {0, 0, 0, 0};
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<hipEvent_t> pev;  // per-iteration phase events (4 per iteration)
   // adjoint
   long long epoch = 0;     // bumped by set_medium / set_initial
   std::unique_ptr<Tape> tape;
@@ -208,6 +224,8 @@ struct Prob {
   double adj_ms[2] = {0, 0};  // last taped forward, last backward
   ~Prob() {
     for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& e : pev)
       if (e) (void)hipEventDestroy(e);
     if (fork_ev) (void)hipEventDestroy(fork_ev);
     if (join_ev) (void)hipEventDestroy(join_ev);
@@ -294,6 +312,7 @@ void validate(const pw_problem& P) {
   if (P.max_iters < 1) fail(PW_EINVAL, "max_iters must be >= 1");
   if (P.interp != PW_INTERP_TRIG && P.interp != PW_INTERP_LINEAR && P.interp != PW_INTERP_CUBIC)
     fail(PW_EINVAL, "interp must be PW_INTERP_TRIG, PW_INTERP_LINEAR or PW_INTERP_CUBIC");
+  if (P.keep_history != 0 && P.keep_history != 1) fail(PW_EINVAL, "keep_history must be 0 or 1");
 }
 
 void setup(Prob& pr, const pw_problem& P) {
@@ -417,7 +436,7 @@ void setup(Prob& pr, const pw_problem& P) {
   // (a <= cap, b <= max(cap, N))
   pr.gwork_elems = gemm_tn_work_bound((int)cap, (int)std::max<long long>(cap, N));
   pr.gwork = m.get_n<double>((long long)pr.gwork_elems);
-  pr.red = m.get_n<double>(4096);
+  pr.red = m.get_n<double>(kEnergyPartials + 16);
   pr.vsum = m.get_n<double>(16);
   if (pr.order == 0) {
     pr.spec.dft = pr.dtab;
@@ -426,7 +445,12 @@ void setup(Prob& pr, const pw_problem& P) {
     pr.spec.rtmp = m.get_n<double>((long long)P.dim * Nc * N);
     pr.spec.ures = m.get_n<double>(Nc * N);
   }
-  pr.res = m.get_n<double>(2LL * (P.max_iters + 1));
+  pr.res = m.get_n<double>((long long)kRes * (P.max_iters + 1));
+  pr.chg = m.get_n<double>(4LL * N);
+  if (P.keep_history) {
+    pr.hist_u = m.get(ts * Nf * N * (size_t)(P.max_iters + 1));
+    pr.hist_p = m.get(ts * Nf * N * (size_t)(P.max_iters + 1));
+  }
   size_t tsq_st = 0, tsq_tau = 0;
   tsqr_work(rows, N, &tsq_st, &tsq_tau);
   pr.os.gram = m.get_n<double>(64LL * 64);
@@ -559,7 +583,7 @@ void gather_cols(const double* src, long long rows, const int* idx, int ncols, d
 // runs on the columns F[:, cols], G[:, cols] instead (random subsampling of
 // the data matrices)
 void update_svd_dev(Prob& pr, const double* F, const double* G, int ncols, hipStream_t st,
-                    const int* cols = nullptr) {
+                    const int* cols = nullptr, double* norms = nullptr) {
   const long long rows = pr.rows;
   const int r = pr.r;
   const int cur = pr.cur, nxt = 1 - pr.cur;
@@ -576,6 +600,11 @@ void update_svd_dev(Prob& pr, const double* F, const double* G, int ncols, hipSt
     gather_cols(G, rows, cols, ncols, pr.Gp, pr.side);
     F = pr.Fp;
     G = pr.Gp;
+  }
+  if (norms) {
+    // ||F_in||^2 and ||G_in||^2 (own partial buffers on the two streams)
+    frob_norm2(F, rows, ncols, rows, pr.red, norms, st);
+    frob_norm2(G, rows, ncols, rows, pr.red + 1024, norms + 1, pr.side);
   }
   if (r == 0) {
     orth_begin(rows, ncols, F, rows, pr.os, st);
@@ -698,6 +727,7 @@ void init_phase(Prob& pr, hipStream_t st) {
   reset_corrector(pr);
   for (int i = 0; i < 4; ++i) pr.ms[i] = 0.0;
   pr.k_done = 0;
+  pr.change.clear();
   restrict_fields<T>(pr.gf, pr.ratio, pr.gc, u, Nf, Rc, Nc, 1, st);
   restrict_fields<T>(pr.gf, pr.ratio, pr.gc, p, Nf, Rcp, Nc, 1, st);
   for (int n = 1; n <= N; ++n) {
@@ -727,12 +757,13 @@ void corrector_phase(Prob& pr, int k, hipStream_t st) {
                     pr.Fm, rows, N, st, &pr.spec);
   energy_columns<T>(pr.gc, 1, pr.gc, tp<T>(pr.Uc), tp<T>(pr.Ucp), Nc, pr.cc, pr.order, pr.Gm,
                     rows, N, st, &pr.spec);
+  double* rk = pr.res + (long long)kRes * (k - 1);
   if (pr.samp_n > 0) {
     if (k > pr.samp_iters) fail(PW_EINVAL, "no sampled columns for this iteration");
     update_svd_dev(pr, pr.Fm, pr.Gm, pr.samp_n, st,
-                   (const int*)pr.samp.p + (long long)(k - 1) * pr.samp_n);
+                   (const int*)pr.samp.p + (long long)(k - 1) * pr.samp_n, rk + 2);
   } else {
-    update_svd_dev(pr, pr.Fm, pr.Gm, N, st);
+    update_svd_dev(pr, pr.Fm, pr.Gm, N, st, nullptr, rk + 2);
   }
   pr.ranks.push_back(pr.r);
   // rho_k: || F - U (V^T G) ||_F / ||F||_F
@@ -741,8 +772,9 @@ void corrector_phase(Prob& pr, int k, hipStream_t st) {
           pr.gwork, pr.gwork_elems, st);
   PW_HIP(hipMemcpyAsync(pr.Fp, pr.Fm, sizeof(double) * rows * N, hipMemcpyDeviceToDevice, st));
   gemm_nn(rows, N, r, -1.0, pr.Ub[pr.cur], rows, pr.UF, std::max(r, 1), 1.0, pr.Fp, rows, st);
-  frob_norm2(pr.Fp, rows, N, rows, pr.red, pr.res + 2 * (k - 1), st);
-  frob_norm2(pr.Fm, rows, N, rows, pr.red, pr.res + 2 * (k - 1) + 1, st);
+  frob_norm2(pr.Fp, rows, N, rows, pr.red, rk, st);
+  frob_norm2(pr.Fm, rows, N, rows, pr.red, rk + 1, st);
+  vec_sum(pr.S, r, rk + 4, st);
 }
 
 // a_n = R v_{n-1} - R u^k_{n-1} (double coarse columns), v_0 = u0 -> column 0
@@ -841,8 +873,10 @@ void residual_identity_phase(Prob& pr, int k, hipStream_t st) {
   hipLaunchKernelGGL(k_sub_cols, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                      (const double*)pr.Fm, (const double*)pr.Gm, pr.Fp, n);
   PW_LAUNCH_CHECK();
-  frob_norm2(pr.Fp, rows, N, rows, pr.red, pr.res + 2 * (k - 1), st);
-  frob_norm2(pr.Fm, rows, N, rows, pr.red, pr.res + 2 * (k - 1) + 1, st);
+  double* rk = pr.res + (long long)kRes * (k - 1);
+  frob_norm2(pr.Fp, rows, N, rows, pr.red, rk, st);
+  frob_norm2(pr.Fm, rows, N, rows, pr.red, rk + 1, st);
+  fill(rk + 2, 3, 0.0, st);
 }
 
 // Omega = I (project) or plain parareal: the serial chain
@@ -896,40 +930,157 @@ void sweep_phase(Prob& pr, hipStream_t st) {
   }
 }
 
-void accumulate_phase_times(Prob& pr) {
-  PW_HIP(hipEventSynchronize(pr.ev[3]));
-  float a = 0, b = 0, c = 0;
-  PW_HIP(hipEventElapsedTime(&a, pr.ev[0], pr.ev[1]));
-  PW_HIP(hipEventElapsedTime(&b, pr.ev[1], pr.ev[2]));
-  PW_HIP(hipEventElapsedTime(&c, pr.ev[2], pr.ev[3]));
-  pr.ms[0] += a;
-  pr.ms[1] += b;
-  pr.ms[2] += c;
+// u^k_n, n = 1..N, of the current iterate into history level k - 1
+void store_history(Prob& pr, int k, hipStream_t st) {
+  if (!pr.hist_u) return;
+  const size_t fb = pr.tsize * pr.Nf;
+  const size_t bytes = fb * pr.N;
+  PW_HIP(hipMemcpyAsync((char*)pr.hist_u + bytes * (k - 1), (const char*)pr.u + fb, bytes,
+                        hipMemcpyDeviceToDevice, st));
+  PW_HIP(hipMemcpyAsync((char*)pr.hist_p + bytes * (k - 1), (const char*)pr.p + fb, bytes,
+                        hipMemcpyDeviceToDevice, st));
+}
+
+// the previous iterate u^k_n, n = 1..N, for the stopping rule (the history
+// level when kept, else a copy taken before the iteration)
+const void* prev_iterate(Prob& pr, int k, bool p_field) {
+  const size_t bytes = pr.tsize * pr.Nf * pr.N;
+  if (pr.hist_u) return (const char*)(p_field ? pr.hist_p : pr.hist_u) + bytes * (k - 1);
+  return (const char*)pr.prev.p + (p_field ? bytes : 0);
+}
+
+// stopping measure of iteration k (u^{k+1} current, u^k previous):
+// max_n sqrt(E(u^{k+1}_n - u^k_n) / E(u^{k+1}_n)) on the fine grid, FP64
+// reductions on the device, one read-back
+template <typename T>
+double change_measure(Prob& pr, int k, hipStream_t st) {
+  const int N = pr.N;
+  const long long Nf = pr.Nf;
+  const T* ua = tp<T>((void*)prev_iterate(pr, k, false));
+  const T* pa = tp<T>((void*)prev_iterate(pr, k, true));
+  const T* ub = tp<T>(pr.u) + Nf;
+  const T* pb = tp<T>(pr.p) + Nf;
+  const int order = pr.order ? pr.order : 4;
+  for (int n = 0; n < N; ++n)
+    energy_pair<T>(pr.gf, ua + n * Nf, pa + n * Nf, ub + n * Nf, pb + n * Nf, pr.cf, order,
+                   pr.red, pr.chg + 4 * n, st);
+  std::vector<double> h(4 * (size_t)N);
+  PW_HIP(hipMemcpyAsync(h.data(), pr.chg, sizeof(double) * 4 * N, hipMemcpyDeviceToHost, st));
+  PW_HIP(hipStreamSynchronize(st));
+  double worst = 0.0;
+  for (int n = 0; n < N; ++n) {
+    const double e = h[4 * n], e0 = h[4 * n + 1];
+    const double c = e0 > 0 ? std::sqrt(e / e0) : std::sqrt(e);
+    if (!(c <= worst)) worst = c;  // NaN propagates
+  }
+  return worst;
+}
+
+// phase events of one iteration (4 per iteration, created on first use);
+// read once at the end of a run
+hipEvent_t* phase_events(Prob& pr, int k) {
+  const size_t need = 4 * (size_t)k;
+  while (pr.pev.size() < need) {
+    hipEvent_t e;
+    PW_HIP(hipEventCreate(&e));
+    pr.pev.push_back(e);
+  }
+  return pr.pev.data() + 4 * (size_t)(k - 1);
+}
+
+void accumulate_phase_times(Prob& pr, int k_first, int k_last) {
+  if (k_last < k_first) return;
+  PW_HIP(hipEventSynchronize(phase_events(pr, k_last)[3]));
+  for (int k = k_first; k <= k_last; ++k) {
+    hipEvent_t* ev = phase_events(pr, k);
+    float a = 0, b = 0, c = 0;
+    PW_HIP(hipEventElapsedTime(&a, ev[0], ev[1]));
+    PW_HIP(hipEventElapsedTime(&b, ev[1], ev[2]));
+    PW_HIP(hipEventElapsedTime(&c, ev[2], ev[3]));
+    pr.ms[0] += a;
+    pr.ms[1] += b;
+    pr.ms[2] += c;
+  }
+}
+
+// iteration k of the selected iteration: parallel phase, corrector (update:
+// Algorithm 1 on the new data; otherwise the current corrector is kept and
+// no data matrices are formed), sweep and update
+template <typename T>
+void iteration(Prob& pr, int k, bool update, hipStream_t st) {
+  hipEvent_t* ev = phase_events(pr, k);
+  PW_HIP(hipEventRecord(ev[0], st));
+  prop_fine<T>(pr, tp<T>(pr.u), tp<T>(pr.p), tp<T>(pr.v), tp<T>(pr.vp), pr.N, st);
+  restrict_phase<T>(pr, st);
+  prop_coarse<T>(pr, tp<T>(pr.Rc), tp<T>(pr.Rcp), tp<T>(pr.Uc), tp<T>(pr.Ucp), pr.N, st);
+  PW_HIP(hipEventRecord(ev[1], st));
+  if (pr.variant == PW_VARIANT_OMEGA_ONE || pr.variant == PW_VARIANT_PLAIN) {
+    residual_identity_phase<T>(pr, k, st);
+  } else if (update) {
+    corrector_phase<T>(pr, k, st);
+  } else {
+    pr.ranks.push_back(pr.r);
+    fill(pr.res + (long long)kRes * (k - 1), kRes, std::nan(""), st);
+  }
+  PW_HIP(hipEventRecord(ev[2], st));
+  sweep_phase<T>(pr, st);
+  PW_HIP(hipEventRecord(ev[3], st));
+}
+
+// iterations k_done + 1 .. k_done + K; with stop_tol > 0 the run ends after
+// the first iteration whose change measure is <= stop_tol
+template <typename T>
+void run_iterations(Prob& pr, int K, bool update, double stop_tol, hipStream_t st) {
+  const int k0 = pr.k_done;
+  const bool stop_rule = stop_tol > 0;
+  const size_t fb = pr.tsize * pr.Nf;
+  const size_t bytes = fb * pr.N;
+  int k = k0;
+  while (k < k0 + K) {
+    ++k;
+    if (stop_rule && !pr.hist_u) {
+      char* d = (char*)pr.prev.ensure(2 * bytes);
+      PW_HIP(hipMemcpyAsync(d, (const char*)pr.u + fb, bytes, hipMemcpyDeviceToDevice, st));
+      PW_HIP(hipMemcpyAsync(d + bytes, (const char*)pr.p + fb, bytes, hipMemcpyDeviceToDevice,
+                            st));
+    }
+    iteration<T>(pr, k, update, st);
+    pr.k_done = k;
+    store_history(pr, k + 1, st);
+    const double chg = stop_rule ? change_measure<T>(pr, k, st) : std::nan("");
+    pr.change.push_back(chg);
+    if (stop_rule && chg <= stop_tol) break;
+  }
+  accumulate_phase_times(pr, k0 + 1, k);
 }
 
 template <typename T>
-void run_typed(Prob& pr, int K, hipStream_t st) {
+void run_typed(Prob& pr, int K, double stop_tol, hipStream_t st) {
   hipEvent_t e0, e1;
   PW_HIP(hipEventCreate(&e0));
   PW_HIP(hipEventCreate(&e1));
   PW_HIP(hipEventRecord(e0, st));
   init_phase<T>(pr, st);
-  for (int k = 1; k <= K; ++k) {
-    PW_HIP(hipEventRecord(pr.ev[0], st));
-    prop_fine<T>(pr, tp<T>(pr.u), tp<T>(pr.p), tp<T>(pr.v), tp<T>(pr.vp), pr.N, st);
-    restrict_phase<T>(pr, st);
-    prop_coarse<T>(pr, tp<T>(pr.Rc), tp<T>(pr.Rcp), tp<T>(pr.Uc), tp<T>(pr.Ucp), pr.N, st);
-    PW_HIP(hipEventRecord(pr.ev[1], st));
-    if (pr.variant == PW_VARIANT_OMEGA_ONE || pr.variant == PW_VARIANT_PLAIN)
-      residual_identity_phase<T>(pr, k, st);
-    else
-      corrector_phase<T>(pr, k, st);
-    PW_HIP(hipEventRecord(pr.ev[2], st));
-    sweep_phase<T>(pr, st);
-    PW_HIP(hipEventRecord(pr.ev[3], st));
-    accumulate_phase_times(pr);
-    pr.k_done = k;
-  }
+  pr.have_iterate = true;
+  store_history(pr, 1, st);
+  run_iterations<T>(pr, K, true, stop_tol, st);
+  PW_HIP(hipEventRecord(e1, st));
+  PW_HIP(hipEventSynchronize(e1));
+  float tot = 0;
+  PW_HIP(hipEventElapsedTime(&tot, e0, e1));
+  pr.ms[3] = tot;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
+template <typename T>
+void continue_typed(Prob& pr, int K, bool update, double stop_tol, hipStream_t st) {
+  hipEvent_t e0, e1;
+  PW_HIP(hipEventCreate(&e0));
+  PW_HIP(hipEventCreate(&e1));
+  for (int i = 0; i < 4; ++i) pr.ms[i] = 0.0;
+  PW_HIP(hipEventRecord(e0, st));
+  run_iterations<T>(pr, K, update, stop_tol, st);
   PW_HIP(hipEventRecord(e1, st));
   PW_HIP(hipEventSynchronize(e1));
   float tot = 0;
@@ -1055,6 +1206,8 @@ void run_taped_typed(Prob& pr, int K, bool frozen, hipStream_t st) {
   PW_HIP(hipEventCreate(&e1));
   PW_HIP(hipEventRecord(e0, st));
   init_phase<T>(pr, st);
+  pr.have_iterate = true;
+  ++pr.tape_serial;
   tape_init_states<T>(pr, t, st);
   if (!frozen) t.dims.assign(K, 0);
   for (int k = 1; k <= K; ++k) {
@@ -1087,7 +1240,10 @@ void run_taped_typed(Prob& pr, int K, bool frozen, hipStream_t st) {
                           hipMemcpyDeviceToDevice, st));
     PW_HIP(hipMemcpyAsync(t.delta + 2 * Nc * N * kk, pr.delta, sizeof(double) * 2 * Nc * N,
                           hipMemcpyDeviceToDevice, st));
-    if (!frozen) pr.k_done = k;
+    if (!frozen) {
+      pr.k_done = k;
+      pr.change.push_back(std::nan(""));
+    }
   }
   PW_HIP(hipEventRecord(e1, st));
   PW_HIP(hipEventSynchronize(e1));
@@ -1102,6 +1258,8 @@ void run_taped_typed(Prob& pr, int K, bool frozen, hipStream_t st) {
   if (frozen) {
     pr.k_done = 0;  // no residuals: the data matrices were not formed
     pr.ranks.clear();
+    pr.change.clear();
+    pr.have_iterate = false;  // the state is a frozen replay, not an iterate to continue
   }
 }
 
@@ -1462,7 +1620,11 @@ void run_batch_typed(pw_ctx* ctx, int K) {
   PW_HIP(hipEventCreate(&e0));
   PW_HIP(hipEventCreate(&e1));
   PW_HIP(hipEventRecord(e0, st));
-  for (auto& up : ctx->probs) init_phase<T>(*up, st);
+  for (auto& up : ctx->probs) {
+    init_phase<T>(*up, st);
+    up->have_iterate = true;
+    store_history(*up, 1, st);
+  }
   for (int k = 1; k <= K; ++k) {
     PW_HIP(hipEventRecord(b.ev[0], st));
     PW_HIP(hipGraphLaunch(b.exec, st));
@@ -1479,7 +1641,11 @@ void run_batch_typed(pw_ctx* ctx, int K) {
     b.ms[0] += x;
     b.ms[1] += y;
     b.ms[2] += z;
-    for (auto& up : ctx->probs) up->k_done = k;
+    for (auto& up : ctx->probs) {
+      up->k_done = k;
+      up->change.push_back(std::nan(""));
+      store_history(*up, k + 1, st);
+    }
   }
   PW_HIP(hipEventRecord(e1, st));
   PW_HIP(hipEventSynchronize(e1));
@@ -1489,6 +1655,12 @@ void run_batch_typed(pw_ctx* ctx, int K) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
 }
+
+}  // namespace
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
 
 pw_status report(const Error& e) {
   g_last_error = e.msg;
@@ -1517,6 +1689,190 @@ const void* stage_in(const double* src, long long n, int on_device, Prob& pr, do
   if (on_device) return src;
   PW_HIP(hipMemcpyAsync(scratch, src, sizeof(double) * n, hipMemcpyHostToDevice, st));
   return scratch;
+}
+
+// E = [Lambda^dag_u U~ , DC] and P = [Lambda^T V~ , DC] of the current
+// corrector, formed directly from U~ and V~ (in chunks of at most N columns,
+// the capacity of the transform scratch)
+void rebuild_sweep_columns(Prob& pr, hipStream_t st) {
+  const long long rows = pr.rows, Nc = pr.Nc;
+  const int r = pr.r, cur = pr.cur;
+  for (int j0 = 0; j0 < r; j0 += pr.N) {
+    const int nc = std::min(pr.N, r - j0);
+    lambda_dag_cols(pr.gc, pr.dtab, pr.Ub[cur] + rows * j0, rows, pr.cc, nullptr,
+                    pr.E[cur] + 2 * Nc * j0, 2 * Nc, nc, pr.ctmp, st);
+    lambda_adjoint_cols(pr.gc, pr.Vb[cur] + rows * j0, rows, pr.cc, pr.order,
+                        pr.Vp[cur] + 2 * Nc * j0, 2 * Nc, nc, st, &pr.spec);
+  }
+  set_dc_column(pr.E[cur], 2 * Nc, r, Nc, 1.0 / (double)Nc, st);
+  set_dc_column(pr.Vp[cur], 2 * Nc, r, Nc, 1.0, st);
+}
+
+// ---- checkpoint files ---------------------------------------------------
+// Layout (host byte order): "PWCKPT01", int32 number of problems, then per
+// problem: its pw_problem fields as 16 int64 / double slots, int32 flags
+// [have_medium, have_initial, have_iterate, variant, k_done, r, cur,
+// samp_n, samp_iters, n_ranks, n_change, history levels, 0, 0, 0, 0], then
+// the blocks that exist: c (Nf doubles); u0, p0 (state dtype); the current
+// iterate n = 1..N; the history levels; ranks; change; the per-iteration
+// record; U~, V~ (rows x r), S~ (r), E, P (2 Nc x (r + 1)); the sampling table.
+constexpr char kCkptMagic[9] = "PWCKPT01";
+
+void problem_slots(const pw_problem& P, double* d) {
+  const double v[16] = {(double)P.dim, (double)P.n_fine[0], (double)P.n_fine[1],
+                        (double)P.n_fine[2], (double)P.ratio, P.T, (double)P.n_slices,
+                        (double)P.m_fine, (double)P.m_coarse, (double)P.grad_order, P.svd_tol,
+                        (double)P.state_dtype, (double)P.compensated, (double)P.max_iters,
+                        (double)P.interp, (double)P.keep_history};
+  std::memcpy(d, v, sizeof(v));
+}
+
+struct File {
+  FILE* f = nullptr;
+  ~File() {
+    if (f) fclose(f);
+  }
+};
+
+void wr(FILE* f, const void* x, size_t bytes) {
+  if (bytes && fwrite(x, 1, bytes, f) != bytes) fail(PW_EINVAL, "checkpoint write failed");
+}
+void rd(FILE* f, void* x, size_t bytes) {
+  if (bytes && fread(x, 1, bytes, f) != bytes)
+    fail(PW_EINVAL, "checkpoint file truncated or unreadable");
+}
+void wr_dev(FILE* f, const void* d, size_t bytes, hipStream_t st) {
+  if (!bytes) return;
+  std::vector<char> h(bytes);
+  PW_HIP(hipMemcpyAsync(h.data(), d, bytes, hipMemcpyDeviceToHost, st));
+  PW_HIP(hipStreamSynchronize(st));
+  wr(f, h.data(), bytes);
+}
+void rd_dev(FILE* f, void* d, size_t bytes, hipStream_t st) {
+  if (!bytes) return;
+  std::vector<char> h(bytes);
+  rd(f, h.data(), bytes);
+  PW_HIP(hipMemcpyAsync(d, h.data(), bytes, hipMemcpyHostToDevice, st));
+  PW_HIP(hipStreamSynchronize(st));
+}
+
+void save_problem(FILE* f, Prob& pr, hipStream_t st) {
+  double slots[16];
+  problem_slots(pr.P, slots);
+  wr(f, slots, sizeof(slots));
+  const int levels = pr.hist_u && pr.have_iterate ? pr.k_done + 1 : 0;
+  const int32_t fl[16] = {pr.have_medium, pr.have_initial, pr.have_iterate, pr.variant,
+                          pr.k_done, pr.r, pr.cur, pr.samp_n, pr.samp_iters,
+                          (int32_t)pr.ranks.size(), (int32_t)pr.change.size(), levels, 0, 0, 0,
+                          0};
+  wr(f, fl, sizeof(fl));
+  const size_t fb = pr.tsize * pr.Nf;
+  const long long rows = pr.rows, Nc = pr.Nc;
+  if (pr.have_medium) wr_dev(f, pr.cf, sizeof(double) * pr.Nf, st);
+  if (pr.have_initial) {
+    wr_dev(f, pr.u, fb, st);
+    wr_dev(f, pr.p, fb, st);
+  }
+  if (pr.have_iterate) {
+    wr_dev(f, (char*)pr.u + fb, fb * pr.N, st);
+    wr_dev(f, (char*)pr.p + fb, fb * pr.N, st);
+  }
+  for (int l = 0; l < levels; ++l) {
+    wr_dev(f, (char*)pr.hist_u + fb * pr.N * l, fb * pr.N, st);
+    wr_dev(f, (char*)pr.hist_p + fb * pr.N * l, fb * pr.N, st);
+  }
+  wr(f, pr.ranks.data(), sizeof(int) * pr.ranks.size());
+  wr(f, pr.change.data(), sizeof(double) * pr.change.size());
+  wr_dev(f, pr.res, sizeof(double) * kRes * pr.k_done, st);
+  if (pr.r > 0) {
+    wr_dev(f, pr.Ub[pr.cur], sizeof(double) * rows * pr.r, st);
+    wr_dev(f, pr.Vb[pr.cur], sizeof(double) * rows * pr.r, st);
+    wr_dev(f, pr.S, sizeof(double) * pr.r, st);
+  }
+  wr_dev(f, pr.E[pr.cur], sizeof(double) * 2 * Nc * (pr.r + 1), st);
+  wr_dev(f, pr.Vp[pr.cur], sizeof(double) * 2 * Nc * (pr.r + 1), st);
+  if (pr.samp_n > 0) wr_dev(f, pr.samp.p, sizeof(int) * (size_t)pr.samp_n * pr.samp_iters, st);
+}
+
+template <typename T>
+void load_medium_typed(Prob& pr, hipStream_t st) {
+  set_medium_typed<T>(pr, st);
+}
+
+void load_problem(FILE* f, Prob& pr, hipStream_t st) {
+  double slots[16], mine[16];
+  rd(f, slots, sizeof(slots));
+  problem_slots(pr.P, mine);
+  if (std::memcmp(slots, mine, sizeof(slots)) != 0)
+    fail(PW_EINVAL, "checkpoint was written for a different problem description");
+  int32_t fl[16];
+  rd(f, fl, sizeof(fl));
+  const bool have_medium = fl[0], have_initial = fl[1], have_iterate = fl[2];
+  const int k_done = fl[4], r = fl[5], cur = fl[6], samp_n = fl[7], samp_iters = fl[8];
+  const int n_ranks = fl[9], n_change = fl[10], levels = fl[11];
+  if (fl[3] < PW_VARIANT_THETA || fl[3] > PW_VARIANT_PLAIN || k_done < 0 ||
+      k_done > pr.P.max_iters || r < 0 || r > pr.rmax || (cur != 0 && cur != 1) || samp_n < 0 ||
+      samp_n > pr.N || samp_iters < 0 || n_ranks < 0 || n_ranks > pr.P.max_iters ||
+      n_change < 0 || n_change > pr.P.max_iters || levels < 0 ||
+      levels > (pr.hist_u ? k_done + 1 : 0) || (have_iterate && !have_initial) ||
+      (!have_medium && (have_iterate || r > 0)))
+    fail(PW_EINVAL, "inconsistent checkpoint header");
+  const size_t fb = pr.tsize * pr.Nf;
+  const long long rows = pr.rows, Nc = pr.Nc;
+  if (have_medium) {
+    std::vector<double> c((size_t)pr.Nf);
+    rd(f, c.data(), sizeof(double) * c.size());
+    for (double x : c)
+      if (!(x > 0.0) || !std::isfinite(x)) fail(PW_EINVAL, "checkpoint medium not positive");
+    PW_HIP(hipMemcpyAsync(pr.cf, c.data(), sizeof(double) * c.size(), hipMemcpyHostToDevice, st));
+    if (pr.f64) load_medium_typed<double>(pr, st);
+    else load_medium_typed<float>(pr, st);
+    PW_HIP(hipStreamSynchronize(st));
+  }
+  if (have_initial) {
+    rd_dev(f, pr.u, fb, st);
+    rd_dev(f, pr.p, fb, st);
+  }
+  if (have_iterate) {
+    rd_dev(f, (char*)pr.u + fb, fb * pr.N, st);
+    rd_dev(f, (char*)pr.p + fb, fb * pr.N, st);
+  }
+  for (int l = 0; l < levels; ++l) {
+    rd_dev(f, (char*)pr.hist_u + fb * pr.N * l, fb * pr.N, st);
+    rd_dev(f, (char*)pr.hist_p + fb * pr.N * l, fb * pr.N, st);
+  }
+  std::vector<int> ranks((size_t)n_ranks);
+  rd(f, ranks.data(), sizeof(int) * ranks.size());
+  std::vector<double> change((size_t)n_change);
+  rd(f, change.data(), sizeof(double) * change.size());
+  rd_dev(f, pr.res, sizeof(double) * kRes * k_done, st);
+  if (r > 0) {
+    rd_dev(f, pr.Ub[cur], sizeof(double) * rows * r, st);
+    rd_dev(f, pr.Vb[cur], sizeof(double) * rows * r, st);
+    rd_dev(f, pr.S, sizeof(double) * r, st);
+  }
+  rd_dev(f, pr.E[cur], sizeof(double) * 2 * Nc * (r + 1), st);
+  rd_dev(f, pr.Vp[cur], sizeof(double) * 2 * Nc * (r + 1), st);
+  if (samp_n > 0) {
+    const size_t bytes = sizeof(int) * (size_t)samp_n * samp_iters;
+    std::vector<int> tab((size_t)samp_n * samp_iters);
+    rd(f, tab.data(), bytes);
+    for (int x : tab)
+      if (x < 0 || x >= pr.N) fail(PW_EINVAL, "checkpoint sampling table out of range");
+    PW_HIP(hipMemcpy(pr.samp.ensure(bytes), tab.data(), bytes, hipMemcpyHostToDevice));
+  }
+  pr.have_medium = have_medium;
+  pr.have_initial = have_initial;
+  pr.have_iterate = have_iterate;
+  pr.variant = fl[3];
+  pr.k_done = k_done;
+  pr.r = r;
+  pr.cur = cur;
+  pr.samp_n = samp_n;
+  pr.samp_iters = samp_n > 0 ? samp_iters : 0;
+  pr.ranks = ranks;
+  pr.change = change;
+  ++pr.epoch;  // a recorded tape no longer matches
 }
 
 }  // namespace
@@ -1615,18 +1971,38 @@ pw_status pw_set_initial(pw_ctx* ctx, int prob, const double* u0, const double* 
     pr.have_initial = true;
     ++pr.epoch;
     pr.k_done = 0;
+    pr.have_iterate = false;
+    pr.change.clear();
     reset_corrector(pr);
   });
 }
 
-pw_status pw_run(pw_ctx* ctx, int prob, int K) {
+pw_status pw_run(pw_ctx* ctx, int prob, int K, double stop_tol, int* k_done) {
   return guarded([&] {
     Prob& pr = get_prob(ctx, prob);
     if (!pr.have_medium || !pr.have_initial) fail(PW_ESTATE, "set medium and initial state first");
     if (K < 0 || K > pr.P.max_iters) fail(PW_EINVAL, "K must be in [0, max_iters]");
+    if (!(stop_tol >= 0)) fail(PW_EINVAL, "stop_tol must be >= 0");
     check_sampling(pr, K);
-    if (pr.f64) run_typed<double>(pr, K, ctx->stream);
-    else run_typed<float>(pr, K, ctx->stream);
+    if (pr.f64) run_typed<double>(pr, K, stop_tol, ctx->stream);
+    else run_typed<float>(pr, K, stop_tol, ctx->stream);
+    if (k_done) *k_done = pr.k_done;
+  });
+}
+
+pw_status pw_continue(pw_ctx* ctx, int prob, int K, int update_corrector, double stop_tol,
+                      int* k_done) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (!pr.have_medium || !pr.have_iterate)
+      fail(PW_ESTATE, "pw_continue needs an iterate (pw_run, pw_run_batch or pw_load first)");
+    if (K < 0 || pr.k_done + K > pr.P.max_iters)
+      fail(PW_EINVAL, "k_done + K must not exceed max_iters");
+    if (!(stop_tol >= 0)) fail(PW_EINVAL, "stop_tol must be >= 0");
+    if (update_corrector) check_sampling(pr, pr.k_done + K);
+    if (pr.f64) continue_typed<double>(pr, K, update_corrector != 0, stop_tol, ctx->stream);
+    else continue_typed<float>(pr, K, update_corrector != 0, stop_tol, ctx->stream);
+    if (k_done) *k_done = pr.k_done;
   });
 }
 
@@ -1655,6 +2031,8 @@ pw_status pw_set_sampling(pw_ctx* ctx, int prob, const int* cols, int n_per_iter
     pr.samp_n = n_per_iter;
     pr.samp_iters = n_per_iter > 0 ? n_iters : 0;
     pr.k_done = 0;
+    pr.have_iterate = false;
+    pr.change.clear();
     reset_corrector(pr);
   });
 }
@@ -1666,6 +2044,8 @@ pw_status pw_set_variant(pw_ctx* ctx, int prob, int variant) {
       fail(PW_EINVAL, "unknown variant");
     pr.variant = variant;
     pr.k_done = 0;
+    pr.have_iterate = false;
+    pr.change.clear();
     reset_corrector(pr);
   });
 }
@@ -1685,18 +2065,133 @@ pw_status pw_get_state(pw_ctx* ctx, int prob, int n, void* u, void* p, int on_de
   });
 }
 
+pw_status pw_get_iterate(pw_ctx* ctx, int prob, int k, int n, void* u, void* p, int on_device) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (!pr.have_iterate) fail(PW_ESTATE, "no iterate: run first");
+    if (k < 1 || k > pr.k_done + 1) fail(PW_EINVAL, "k must be in [1, k_done + 1]");
+    if (n < 0 || n > pr.N) fail(PW_EINVAL, "slice index out of range");
+    if (!u || !p) fail(PW_EINVAL, "null output");
+    const size_t fb = pr.tsize * pr.Nf;
+    const char *su, *sp;
+    if (n == 0 || k == pr.k_done + 1) {
+      su = (const char*)pr.u + fb * n;
+      sp = (const char*)pr.p + fb * n;
+    } else {
+      if (!pr.hist_u) fail(PW_EINVAL, "earlier iterates need keep_history = 1");
+      const size_t lvl = fb * pr.N * (size_t)(k - 1);
+      su = (const char*)pr.hist_u + lvl + fb * (n - 1);
+      sp = (const char*)pr.hist_p + lvl + fb * (n - 1);
+    }
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    PW_HIP(hipMemcpyAsync(u, su, fb, kind, ctx->stream));
+    PW_HIP(hipMemcpyAsync(p, sp, fb, kind, ctx->stream));
+    if (!on_device) PW_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+pw_status pw_set_iterate(pw_ctx* ctx, int prob, int n, const double* u, const double* p,
+                         int on_device) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (!pr.have_iterate) fail(PW_ESTATE, "no iterate to overwrite: run first");
+    if (n < 1 || n > pr.N) fail(PW_EINVAL, "n must be in [1, N] (slice 0 is u0)");
+    if (!u || !p) fail(PW_EINVAL, "null input");
+    hipStream_t st = ctx->stream;
+    const long long Nf = pr.Nf;
+    const double* du = (const double*)stage_in(u, Nf, on_device, pr, pr.itmp, st);
+    const double* dp = (const double*)stage_in(p, Nf, on_device, pr, pr.itmp + Nf, st);
+    const size_t fb = pr.tsize * Nf;
+    if (pr.f64) {
+      cast_from_double<double>(du, (double*)((char*)pr.u + fb * n), Nf, st);
+      cast_from_double<double>(dp, (double*)((char*)pr.p + fb * n), Nf, st);
+    } else {
+      cast_from_double<float>(du, (float*)((char*)pr.u + fb * n), Nf, st);
+      cast_from_double<float>(dp, (float*)((char*)pr.p + fb * n), Nf, st);
+    }
+    if (pr.hist_u) {
+      // the current iterate's history level follows it
+      const size_t lvl = fb * pr.N * (size_t)pr.k_done + fb * (n - 1);
+      PW_HIP(hipMemcpyAsync((char*)pr.hist_u + lvl, (char*)pr.u + fb * n, fb,
+                            hipMemcpyDeviceToDevice, st));
+      PW_HIP(hipMemcpyAsync((char*)pr.hist_p + lvl, (char*)pr.p + fb * n, fb,
+                            hipMemcpyDeviceToDevice, st));
+    }
+    PW_HIP(hipStreamSynchronize(st));
+  });
+}
+
+pw_status pw_set_corrector(pw_ctx* ctx, int prob, const double* U, const double* S,
+                           const double* V, int rank, int on_device) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (!pr.have_medium) fail(PW_ESTATE, "set the medium first");
+    if (rank < 0 || rank > pr.rmax) fail(PW_EINVAL, "rank must be in [0, min(max_iters N, rows)]");
+    if (rank > 0 && (!U || !S || !V)) fail(PW_EINVAL, "null corrector input");
+    hipStream_t st = ctx->stream;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const size_t vb = sizeof(double) * (size_t)pr.rows * rank;
+    if (rank > 0) {
+      PW_HIP(hipMemcpyAsync(pr.Ub[pr.cur], U, vb, kind, st));
+      PW_HIP(hipMemcpyAsync(pr.Vb[pr.cur], V, vb, kind, st));
+      PW_HIP(hipMemcpyAsync(pr.S, S, sizeof(double) * rank, kind, st));
+    }
+    pr.r = rank;
+    rebuild_sweep_columns(pr, st);
+    PW_HIP(hipStreamSynchronize(st));
+  });
+}
+
+pw_status pw_get_diagnostics(pw_ctx* ctx, int prob, double* out, int cap, int* count) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    const int K = pr.k_done;
+    std::vector<double> h((size_t)kRes * std::max(K, 1));
+    if (K > 0) {
+      PW_HIP(hipMemcpyAsync(h.data(), pr.res, sizeof(double) * kRes * K, hipMemcpyDeviceToHost,
+                            ctx->stream));
+      PW_HIP(hipStreamSynchronize(ctx->stream));
+    }
+    double in2 = 0.0;  // sum over iterations of ||F_in||^2 + ||G_in||^2
+    for (int k = 0; k < K; ++k) {
+      const double* r = h.data() + (size_t)kRes * k;
+      in2 += r[2] + r[3];
+      if (k >= cap) continue;
+      double* o = out + (size_t)kPwDiag * k;
+      o[0] = r[1] > 0 ? std::sqrt(r[0] / r[1]) : (std::isnan(r[0]) ? r[0] : 0.0);
+      o[1] = k < (int)pr.ranks.size() ? pr.ranks[(size_t)k] : 0;
+      o[2] = r[1];
+      o[3] = r[2];
+      o[4] = r[3];
+      o[5] = r[4];
+      o[6] = in2 - 2.0 * r[4];
+      o[7] = k < (int)pr.change.size() ? pr.change[(size_t)k] : std::nan("");
+    }
+    if (count) *count = K;
+  });
+}
+
+pw_status pw_get_tape_id(pw_ctx* ctx, int prob, long long* id) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (!id) fail(PW_EINVAL, "null output");
+    *id = pr.tape_serial;
+  });
+}
+
 pw_status pw_get_residuals(pw_ctx* ctx, int prob, double* rho, int* rank, int cap, int* count) {
   return guarded([&] {
     Prob& pr = get_prob(ctx, prob);
     const int K = pr.k_done;
-    std::vector<double> h(2 * (size_t)std::max(K, 1));
+    std::vector<double> h((size_t)kRes * std::max(K, 1));
     if (K > 0) {
-      PW_HIP(hipMemcpyAsync(h.data(), pr.res, sizeof(double) * 2 * K, hipMemcpyDeviceToHost,
+      PW_HIP(hipMemcpyAsync(h.data(), pr.res, sizeof(double) * kRes * K, hipMemcpyDeviceToHost,
                             ctx->stream));
       PW_HIP(hipStreamSynchronize(ctx->stream));
     }
     for (int k = 0; k < K && k < cap; ++k) {
-      if (rho) rho[k] = h[2 * k + 1] > 0 ? std::sqrt(h[2 * k] / h[2 * k + 1]) : 0.0;
+      const double* rr = h.data() + (size_t)kRes * k;
+      if (rho) rho[k] = rr[1] > 0 ? std::sqrt(rr[0] / rr[1]) : (std::isnan(rr[0]) ? rr[0] : 0.0);
       if (rank) rank[k] = k < (int)pr.ranks.size() ? pr.ranks[k] : 0;
     }
     if (count) *count = K;
@@ -1830,27 +2325,83 @@ pw_status pw_get_corrector(pw_ctx* ctx, int prob, double* U, double* S, double* 
   });
 }
 
+// energy and l2 sums of [u - u_ref, p - p_ref] and [u_ref, p_ref] on the
+// fine grid (host output h[0..3], see energy_pair)
+void energy_sums(pw_ctx* ctx, Prob& pr, const void* u, const void* p, const void* u_ref,
+                 const void* p_ref, double* h) {
+  if (!pr.have_medium) fail(PW_ESTATE, "set the medium first");
+  if (!u || !p || (u_ref && !p_ref)) fail(PW_EINVAL, "bad arguments");
+  hipStream_t st = ctx->stream;
+  double* res = pr.red + kEnergyPartials;
+  const int order = pr.order ? pr.order : 4;
+  if (pr.f64)
+    energy_pair<double>(pr.gf, (const double*)u, (const double*)p, (const double*)u_ref,
+                        (const double*)p_ref, pr.cf, order, pr.red, res, st);
+  else
+    energy_pair<float>(pr.gf, (const float*)u, (const float*)p, (const float*)u_ref,
+                       (const float*)p_ref, pr.cf, order, pr.red, res, st);
+  PW_HIP(hipMemcpyAsync(h, res, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+  PW_HIP(hipStreamSynchronize(st));
+}
+
 pw_status pw_energy(pw_ctx* ctx, int prob, const void* u, const void* p, const void* u_ref,
                     const void* p_ref, double* e_diff, double* e_ref) {
   return guarded([&] {
     Prob& pr = get_prob(ctx, prob);
-    if (!pr.have_medium) fail(PW_ESTATE, "set the medium first");
-    if (!u || !p || (u_ref && !p_ref)) fail(PW_EINVAL, "bad arguments");
-    hipStream_t st = ctx->stream;
-    double* res = pr.red + 4000;
-    if (pr.f64)
-      energy_pair<double>(pr.gf, (const double*)u, (const double*)p, (const double*)u_ref,
-                          (const double*)p_ref, pr.cf, pr.order ? pr.order : 4, pr.red, res,
-                          st);
-    else
-      energy_pair<float>(pr.gf, (const float*)u, (const float*)p, (const float*)u_ref,
-                         (const float*)p_ref, pr.cf, pr.order ? pr.order : 4, pr.red, res,
-                         st);
-    double h[2] = {0, 0};
-    PW_HIP(hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, st));
-    PW_HIP(hipStreamSynchronize(st));
+    double h[4] = {0, 0, 0, 0};
+    energy_sums(ctx, pr, u, p, u_ref, p_ref, h);
     if (e_diff) *e_diff = h[0];
     if (e_ref) *e_ref = h[1];
+  });
+}
+
+pw_status pw_error_norms(pw_ctx* ctx, int prob, const void* u, const void* p, const void* u_ref,
+                         const void* p_ref, double* out) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (!out) fail(PW_EINVAL, "null output");
+    energy_sums(ctx, pr, u, p, u_ref, p_ref, out);
+  });
+}
+
+pw_status pw_save(pw_ctx* ctx, const char* path) {
+  return guarded([&] {
+    if (!ctx) fail(PW_EINVAL, "null context");
+    if (!path) fail(PW_EINVAL, "null path");
+    File fh;
+    fh.f = fopen(path, "wb");
+    if (!fh.f) fail(PW_EINVAL, std::string("cannot open checkpoint for writing: ") + path);
+    wr(fh.f, kCkptMagic, 8);
+    const int32_t np = (int32_t)ctx->probs.size();
+    wr(fh.f, &np, sizeof(np));
+    PW_HIP(hipStreamSynchronize(ctx->stream));
+    for (auto& up : ctx->probs) save_problem(fh.f, *up, ctx->stream);
+    if (fclose(fh.f) != 0) {
+      fh.f = nullptr;
+      fail(PW_EINVAL, "checkpoint write failed");
+    }
+    fh.f = nullptr;
+  });
+}
+
+pw_status pw_load(pw_ctx* ctx, const char* path) {
+  return guarded([&] {
+    if (!ctx) fail(PW_EINVAL, "null context");
+    if (!path) fail(PW_EINVAL, "null path");
+    File fh;
+    fh.f = fopen(path, "rb");
+    if (!fh.f) fail(PW_EINVAL, std::string("cannot open checkpoint: ") + path);
+    char magic[8];
+    rd(fh.f, magic, 8);
+    if (std::memcmp(magic, kCkptMagic, 8) != 0) fail(PW_EINVAL, "not a pwave checkpoint");
+    int32_t np = 0;
+    rd(fh.f, &np, sizeof(np));
+    if (np != (int32_t)ctx->probs.size())
+      fail(PW_EINVAL, "checkpoint holds a different number of problems");
+    PW_HIP(hipStreamSynchronize(ctx->stream));
+    for (auto& up : ctx->probs) load_problem(fh.f, *up, ctx->stream);
+    char extra;
+    if (fread(&extra, 1, 1, fh.f) != 0) fail(PW_EINVAL, "trailing bytes in checkpoint");
   });
 }
 

@@ -845,11 +845,6 @@ __global__ void k_sum(const double* partials, int nb, double* out) {
 
 constexpr int kSplitTarget = 512;
 
-bool debug_jacobi() {
-  static const bool on = getenv("PW_DEBUG_JACOBI") != nullptr;
-  return on;
-}
-
 // large results use the 128 x 128 tile kernel with about kBigTarget
 // workgroups (the scratch bound below covers both schemes)
 constexpr int kBigTarget = 256;
@@ -1316,17 +1311,6 @@ void svd_jacobi(int n, const double* H, double* X, double* Y, double* sig, doubl
     return;
   }
   const long long nn = (long long)n * n;
-  if (const char* dump = getenv("PW_DUMP_H")) {
-    // debugging aid: append (n, H column-major) to the named file
-    std::vector<double> h((size_t)nn);
-    PW_HIP(hipMemcpyAsync(h.data(), H, sizeof(double) * nn, hipMemcpyDeviceToHost, st));
-    PW_HIP(hipStreamSynchronize(st));
-    if (FILE* f = fopen(dump, "ab")) {
-      fwrite(&n, sizeof(int), 1, f);
-      fwrite(h.data(), sizeof(double), (size_t)nn, f);
-      fclose(f);
-    }
-  }
   // workspace: Hw = two n x n buffers, then n + n (sort) + 8 + 8 (norm of H)
   // + n (column norms) doubles; Vw = two n x n buffers.  The block version
   // gathers the columns of H and V into the other buffer before each sweep.
@@ -1383,7 +1367,6 @@ void svd_jacobi(int n, const double* H, double* X, double* Y, double* sig, doubl
     int h = 0;
     PW_HIP(hipMemcpyAsync(&h, counters + sw, sizeof(int), hipMemcpyDeviceToHost, st));
     PW_HIP(hipStreamSynchronize(st));
-    if (debug_jacobi()) fprintf(stderr, "[jacobi n=%d] sweep %d: %d rotations\n", n, sw, h);
     if (h == 0) break;
   }
   hipLaunchKernelGGL(k_col_norms, dim3((n + 3) / 4), dim3(256), 0, st, n, (const double*)Hc, sig_u);
@@ -1489,6 +1472,11 @@ void copy_block(int m, int n, const double* src, long long lds, double* dst, lon
 void fill(double* p, long long n, double v, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill, dim3(nblocks(n)), dim3(kTB), 0, st, p, n, v);
+  PW_LAUNCH_CHECK();
+}
+
+void vec_sum(const double* x, int n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(kTB), 0, st, x, n, out);
   PW_LAUNCH_CHECK();
 }
 

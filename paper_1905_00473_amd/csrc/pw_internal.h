@@ -223,11 +223,18 @@ void set_dc_column(double* mat, long long ld, int col, long long nc, double val,
                    hipStream_t stream);
 
 // energy of fine-grid state differences (double partials on device, reduced
-// on device in a fixed order).  result[0] = E(u - uref), result[1] = E(uref)
+// on device in a fixed order).  result[0] = E(u - uref), result[1] = E(uref),
+// result[2] = sum (u - uref)^2, result[3] = sum uref^2 (uref null: the
+// energy and the sum of squares of [u, p]).  partials: kEnergyPartials
+// doubles, every one written by each call.
 template <typename T>
 void energy_pair(const Grid& fine, const T* u, const T* p, const T* uref, const T* pref,
                  const double* cfine, int order, double* partials, double* result,
                  hipStream_t stream);
+constexpr int kEnergyPartials = 4096;
+
+// message of the last failing ABI call on this thread (pw_last_error)
+void set_last_error(const std::string& msg);
 
 // ---------------------------------------------------------------------------
 // dense linear algebra (linalg.hip)
@@ -317,6 +324,8 @@ void add_diag(int n, int r, const double* S, double* H, int ldh, hipStream_t str
 void copy_block(int m, int n, const double* src, long long lds, double* dst, long long ldd,
                 hipStream_t stream);
 void fill(double* p, long long n, double v, hipStream_t stream);
+// out[0] = x[0] + ... + x[n-1] (one workgroup, fixed order; n = 0 gives 0)
+void vec_sum(const double* x, int n, double* out, hipStream_t stream);
 void frob_norm2(const double* A, long long rows, int cols, long long lda, double* partials,
                 double* out, hipStream_t stream);
 

@@ -494,14 +494,15 @@ __global__ void k_set_dc(double* mat, long long ld, int col, long long nc, doubl
   mat[(long long)col * ld + t] = t < nc ? val : 0.0;
 }
 
-// per-block partial sums of |grad_h(u-uref)|^2 + (p-pref)^2 / c^2 and of the
-// same for (uref, pref); the final sum is taken by k_finish_pair
+// per-block partial sums of |grad_h(u-uref)|^2 + (p-pref)^2 / c^2, of the
+// same for (uref, pref), and of (u-uref)^2 and uref^2 (the l2 error of the
+// displacement); the final sums are taken by k_finish_pair
 template <typename T>
 __global__ void k_energy_pair(const T* u, const T* p, const T* ur, const T* pr, const double* cf,
                               GridArg g, int order, double* partials) {
-  __shared__ double s0[kTB], s1[kTB];
+  __shared__ double s0[kTB], s1[kTB], s2[kTB], s3[kTB];
   const long long np = (long long)g.nx * g.ny * g.nz;
-  double a0 = 0.0, a1 = 0.0;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   for (long long J = (long long)blockIdx.x * blockDim.x + threadIdx.x; J < np;
        J += (long long)gridDim.x * blockDim.x) {
     const int X = (int)(J % g.nx);
@@ -534,46 +535,56 @@ __global__ void k_energy_pair(const T* u, const T* p, const T* ur, const T* pr, 
       const double dp = (double)p[J] - (double)pr[J];
       a0 += dp * dp / c2;
       a1 += (double)pr[J] * (double)pr[J] / c2;
+      const double du = (double)u[J] - (double)ur[J];
+      a2 += du * du;
+      a3 += (double)ur[J] * (double)ur[J];
     } else {
       a0 += (double)p[J] * (double)p[J] / c2;
+      a2 += (double)u[J] * (double)u[J];
     }
   }
   s0[threadIdx.x] = a0;
   s1[threadIdx.x] = a1;
+  s2[threadIdx.x] = a2;
+  s3[threadIdx.x] = a3;
   __syncthreads();
   for (int w = kTB / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) {
       s0[threadIdx.x] += s0[threadIdx.x + w];
       s1[threadIdx.x] += s1[threadIdx.x + w];
+      s2[threadIdx.x] += s2[threadIdx.x + w];
+      s3[threadIdx.x] += s3[threadIdx.x + w];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x] = s0[0];
-    partials[2 * blockIdx.x + 1] = s1[0];
+    partials[4 * blockIdx.x] = s0[0];
+    partials[4 * blockIdx.x + 1] = s1[0];
+    partials[4 * blockIdx.x + 2] = s2[0];
+    partials[4 * blockIdx.x + 3] = s3[0];
   }
 }
 
+// result = [E(u - uref), E(uref), sum (u - uref)^2, sum uref^2]: the
+// energies carry the factor 1/2 dx^d of the discrete energy, the l2 sums
+// are plain sums over the grid points
 __global__ void k_finish_pair(const double* partials, int nb, double scale, double* result) {
-  __shared__ double s0[kTB], s1[kTB];
-  double a0 = 0.0, a1 = 0.0;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-    a0 += partials[2 * i];
-    a1 += partials[2 * i + 1];
-  }
-  s0[threadIdx.x] = a0;
-  s1[threadIdx.x] = a1;
+  __shared__ double s[4][kTB];
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < nb; i += blockDim.x)
+    for (int q = 0; q < 4; ++q) a[q] += partials[4 * i + q];
+  for (int q = 0; q < 4; ++q) s[q][threadIdx.x] = a[q];
   __syncthreads();
   for (int w = kTB / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      s0[threadIdx.x] += s0[threadIdx.x + w];
-      s1[threadIdx.x] += s1[threadIdx.x + w];
-    }
+    if ((int)threadIdx.x < w)
+      for (int q = 0; q < 4; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    result[0] = 0.5 * scale * s0[0];
-    result[1] = 0.5 * scale * s1[0];
+    result[0] = 0.5 * scale * s[0][0];
+    result[1] = 0.5 * scale * s[1][0];
+    result[2] = s[2][0];
+    result[3] = s[3][0];
   }
 }
 
@@ -966,6 +977,8 @@ void energy_pair(const Grid& f, const T* u, const T* p, const T* ur, const T* pr
                      kEnergyBlocks, scale, result);
   PW_LAUNCH_CHECK();
 }
+
+static_assert(4 * kEnergyBlocks == kEnergyPartials, "energy partial layout");
 
 #define PW_INST(T)                                                                              \
   template void energy_columns<T>(const Grid&, int, const Grid&, const T*, const T*, long long, \

@@ -1,7 +1,9 @@
 """Shared helpers of the GPU parity tests: build a solver and the matching
 oracle problem from one seeded workload."""
 
+import contextlib
 import math
+import os
 
 import numpy as np
 
@@ -87,3 +89,64 @@ def derived_gate(Q, w, u0, p0, K, floor=1e-12, **oracle_kwargs):
                256 * amplification(Q, w, u0, p0, K, **oracle_kwargs)
                * 2.0 ** -52,
                16 * ordering_spread(Q, w, u0, p0, K, **oracle_kwargs))
+
+
+def state_errors(u, p, ur, pr, c, dx, order=4):
+    """(energy, l2, max) relative differences of a state against a
+    reference: the Sec. 6 energy norm (blind to a constant shift of u), the
+    l2 norm of the displacement and its largest pointwise difference
+    relative to the largest reference value."""
+    e = rel_energy_err(u, p, ur, pr, c, dx, order)
+    l2 = O.l2_error(u, ur)
+    m = float(np.max(np.abs(u - ur)) / max(np.max(np.abs(ur)), 1e-300))
+    return e, l2, m
+
+
+@contextlib.contextmanager
+def oracle_pool(n=None):
+    """The parfor of Algorithm 3 for the oracle: a process pool (started by
+    a fork server, so the workers hold no GPU state) whose starmap runs the
+    oracle's propagate on all slices of an iteration at once."""
+    import multiprocessing as mp
+    n = n or max(1, min(16, os.cpu_count() or 1))
+    ctx = mp.get_context("forkserver")
+    with ctx.Pool(n) as pool:
+        yield pool.starmap
+
+
+def derived_gates(Q, w, u0, p0, K, ref, pmap=None, floor=1e-12,
+                  **oracle_kwargs):
+    """Per-norm gates (energy, l2, max; see state_errors) for an FP64
+    end-to-end comparison, each max(floor, 256 A eps, 16 S, 16 D) with,
+    from three more oracle runs:
+    A  the amplification of a 1e-13 relative perturbation of u0;
+    S  the spread of Algorithm 1 over the order of its data columns;
+    D  the spread over the SVD routine of Algorithm 1 (LAPACK's QR-iteration
+       driver in place of divide and conquer): both drivers are backward
+       stable, so D is how far a correct SVD may move the iteration through
+       the singular directions the truncation keeps but the data determine
+       only to eps sigma_1 / sigma_i.
+    ``ref`` is the oracle run the GPU is compared with."""
+    import functools
+
+    import scipy.linalg
+    eps_in = 1e-13
+    rng = np.random.default_rng(7)
+    u1 = u0 * (1 + eps_in * rng.standard_normal(np.shape(u0)))
+    runs = {"A": O.theta_parareal(Q, w.c, u1, p0, K, pmap=pmap,
+                                  **oracle_kwargs)}
+    cols = [np.arange(Q.N)[::-1].copy() for _ in range(K)]
+    runs["S"] = O.theta_parareal(Q, w.c, u0, p0, K, pmap=pmap,
+                                 sample_cols=cols, **oracle_kwargs)
+    svd = functools.partial(scipy.linalg.svd, lapack_driver="gesvd")
+    runs["D"] = O.theta_parareal(Q, w.c, u0, p0, K, pmap=pmap, svd=svd,
+                                 **oracle_kwargs)
+    spread = {}
+    for key, r in runs.items():
+        spread[key] = np.max([state_errors(r.u[n], r.p[n], ref.u[n], ref.p[n],
+                                           w.c, Q.dx_fine)
+                              for n in range(1, Q.N + 1)], axis=0)
+    gates = np.maximum.reduce([np.full(3, floor),
+                               256 * spread["A"] / eps_in * 2.0 ** -52,
+                               16 * spread["S"], 16 * spread["D"]])
+    return gates, spread

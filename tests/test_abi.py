@@ -35,8 +35,8 @@ def test_version_and_error_string():
 
 def test_problem_struct_layout():
     # int dim, int n[3], int ratio, double T, int N, mF, mC, order,
-    # double tol, int dtype, comp, max_iters
-    assert ctypes.sizeof(pw.Problem) == 72
+    # double tol, int dtype, comp, max_iters, interp, keep_history
+    assert ctypes.sizeof(pw.Problem) == 80
     assert pw.Problem.T.offset == 24
     assert pw.Problem.svd_tol.offset == 48
 
@@ -96,3 +96,23 @@ def test_bench_refuses_several_gpus():
                        timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_binding_argument_checks_run_before_any_device_work():
+    """The binding's tensor checks (dtype, device, shape, contiguity) reject
+    a mismatched tensor with ValueError; a CPU tensor is refused here, on a
+    host without a GPU, before any library call."""
+    import pytest
+    import torch
+    t = torch.zeros((2, 3), dtype=torch.float64)
+    with pytest.raises(ValueError, match="device"):
+        pw.require(t, torch.float64, (2, 3), "u")
+    with pytest.raises(ValueError, match="torch tensor"):
+        pw.require([1.0], torch.float64, (1,), "u")
+
+
+def test_keep_history_flag_validated():
+    P = pw.Problem.make((40, 40), 4, 0.25, 4, 8, 2)
+    P.keep_history = 2
+    st, msg = _create(P)
+    assert st == -1 and "keep_history" in msg

@@ -197,7 +197,7 @@ def grf2d(n=64, ratio=4, N=8, K=3, T=0.25, seed=0, dtype="f32",
 
 
 def batch2d(n_problems=32, sizes=(256, 384, 512, 768, 1024), N=32, K=6,
-            T=1.0, seed=0, dtype="f32", compensated=False):
+            T=1.0, seed=0, dtype="f32", compensated=True):
     """The batched-problem recipe: n_problems independent 2D problems whose
     fine grids are drawn uniformly from `sizes` (seed), each with a smooth
     random medium c = exp(0.3 g) (g a unit Gaussian random field of
