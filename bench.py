@@ -41,19 +41,36 @@ BYTES_PER_UPDATE_F32 = 20
 # by the same counters on a 512 MiB copy (profiles/disc2d_fine_stencil_
 # traffic.md).  Valid only for the stencil revision it was measured on.
 TRAFFIC = {"stencil-r6": 563.7e6}
+# the same for the 3D stencil (layers3d) and the multi-problem 2D kernel
+# (batch2d), per launch, keyed by the revision they were measured on
+TRAFFIC3D = {}
+TRAFFIC_BATCH = {}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, budget_s=15.0):
-    """Oracle fine propagator (numpy FP64, one process) on a bounded sample
-    of the workload: as many slices of the first fine sweep as fit in about
-    `budget_s` seconds."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, budget_s=8.0):
+    """The oracle's fine propagator (numpy FP64) on a bounded sample of the
+    workload's first fine sweep, timed two ways: one process, and a process
+    pool over slices with one worker per host core (the parfor of Algorithm
+    3).  The pool leg is the reported value."""
     import numpy as np
 
     import oracle as O
+    from tests.gpu_helpers import oracle_pool
     c2 = w.c * w.c
     dx = 1.0 / w.shape[-1]
     h = w.T / w.N / w.m_fine
@@ -63,27 +80,54 @@ def cpu_baseline(w, budget_s=15.0):
     while time.perf_counter() - t0 < budget_s and slices < w.N:
         u, p = O.propagate(u, p, c2, h, dx, w.m_fine)
         slices += 1
-    dt = time.perf_counter() - t0
-    upd = slices * w.m_fine * w.npts
-    return {"value": round(upd / dt / 1e9, 5), "unit": "Gpoint-updates/s",
-            "cores": 1, "kind": "oracle",
-            "sample": f"oracle fine propagator F (numpy FP64, 1 thread) on "
-                      f"{slices} of the {w.N} slices of one fine sweep "
-                      f"({slices * w.m_fine} steps of 512^2), {dt:.1f} s"}
+    dt1 = time.perf_counter() - t0
+    one = slices * w.m_fine * w.npts / dt1 / 1e9
+    cores = max(1, min(os.cpu_count() or 1, 64))
+    # the pool propagates as many independent states as it has workers,
+    # repeated while the budget lasts (the same state: the work per slice
+    # does not depend on the data)
+    states = [(w.u0, w.p0, c2, h, dx, w.m_fine)] * cores
+    with oracle_pool(cores) as pm:
+        list(pm(O.propagate, states[:1]))  # start the workers
+        t0 = time.perf_counter()
+        done = 0
+        while time.perf_counter() - t0 < budget_s or done == 0:
+            list(pm(O.propagate, states))
+            done += cores
+        dtp = time.perf_counter() - t0
+    pool = done * w.m_fine * w.npts / dtp / 1e9
+    model = cpu_model()
+    return {"value": round(pool, 5), "unit": "Gpoint-updates/s",
+            "cores": cores, "kind": "oracle",
+            "cpu_model": model,
+            "single_process": {"value": round(one, 5), "cores": 1,
+                               "sample": f"{slices} slices in {dt1:.1f} s"},
+            "sample": f"oracle fine propagator F (numpy FP64) on "
+                      f"{w.shape[0]}^{len(w.shape)} states of the "
+                      f"{w.name} workload, {w.m_fine} steps per slice: "
+                      f"{done} slice propagations on a pool of {cores} "
+                      f"processes in {dtp:.1f} s ({model})"}
 
 
-def batch_measurement(pw, W, torch):
-    """32 independent 2D problems of uneven grids (batch2d recipe): build
-    the batch (autotune + hipGraph capture) with one batched iteration, then
-    time the batched fine sweep over all slices of all problems."""
-    ws = W.batch2d()
+def batch_context(pw, W, K):
+    ws = W.batch2d(K=K)
     probs = [pw.Problem.make(w.shape, w.ratio, w.T, w.N, w.m_fine,
                              w.m_coarse, w.grad_order, w.tol, w.dtype,
-                             w.compensated, 1) for w in ws]
+                             w.compensated, K) for w in ws]
     sb = pw.Solver(probs)
     for i, w in enumerate(ws):
         sb.set_medium(w.c, prob=i)
         sb.set_initial(w.u0, w.p0, prob=i)
+    return ws, sb
+
+
+def batch_measurement(pw, W, torch):
+    """32 independent 2D problems of uneven grids (batch2d recipe, FP32
+    compensated): build the batch (autotune + hipGraph capture) with one
+    batched iteration, time the batched fine sweep over all slices of all
+    problems, then the full K = 6 batched solve."""
+    K = 6
+    ws, sb = batch_context(pw, W, K)
     log("batch context ready")
     t0 = time.perf_counter()
     sb.run_batch(1)
@@ -93,19 +137,194 @@ def batch_measurement(pw, W, torch):
     upd = sum(w.updates_per_sweep() for w in ws)
     gupd = upd / (ms * 1e-3) / 1e9
     log(f"batched fine sweep {ms:.2f} ms ({gupd:.1f} Gupd/s)")
+    solve_ms = solve_time(sb, K, reps=2, run=lambda: sb.run_batch(K))
+    info_k = sb.batch_info()
+    log(f"batched K={K} solve {solve_ms:.1f} ms")
+    depth = info["depth"]
+    # one sweep = ceil(m_F / depth) launches per problem, all problems in one
+    # launch sequence: the launch count of the longest problem
+    launches = max(math.ceil(w.m_fine / depth) for w in ws)
+    launch_ms = ms / launches
+    bpl = BYTES_PER_UPDATE_F32 * upd / launches
+    rev = pw.lib().pw_version().decode().split()[-1]
     grids = sorted({w.shape[0] for w in ws})
     out = {"workload": "batch2d: 32 problems, fine grids from "
-                       f"{grids} (seed 0), N=32, FP32",
+                       f"{grids} (seed 0), N=32, K={K}, FP32 compensated",
            "updates_per_sweep": upd, "fine_sweep_ms": round(ms, 3),
            "gupd_s": round(gupd, 2),
            "hbm_frac_algorithmic": round(gupd * BYTES_PER_UPDATE_F32 / HBM_PEAK_GBS, 4),
-           "depth": info["depth"], "rows_per_stream": info["rows_per_stream"],
+           "roofline": roofline_stencil(
+               f"k_prop_stream2d_multi<float, true, {depth}> (mean launch "
+               f"of a sweep, {launches} launches)", launch_ms, int(bpl),
+               TRAFFIC_BATCH.get(rev)),
+           "depth": depth, "rows_per_stream": info["rows_per_stream"],
            "tune_ms": round(info["tune_ms"], 1),
            "first_batched_iteration_s": round(t_iter, 3),
-           "phases_ms": {k: round(info[k], 3) for k in
+           "solve_ms": round(solve_ms, 1),
+           "solve_gupd_s": round(K * upd / (solve_ms * 1e-3) / 1e9, 2),
+           "phases_ms": {k: round(info_k[k], 3) for k in
                          ("parallel", "corrector", "sweep", "total")}}
     sb.close()
     return out
+
+
+def stream_time(fn, reps=3):
+    """Mean time of fn() in ms from HIP events on torch's current stream (the
+    library's context stream)."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def solve_time(s, K, reps=3, run=None):
+    """Best wall time (ms) of a K-iteration solve, synchronised."""
+    import torch
+    run = run or (lambda: s.run(K))
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        run()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - a)
+    return min(ts) * 1e3
+
+
+def errors_to_serial(s, w, uf, pf):
+    """Energy error of slice N against the serial fine solution after
+    k = 0..K iterations, from the iterate history of the last run."""
+    errs = []
+    for k in range(1, w.K + 2):
+        uN, pN = s.iterate(k, w.N)
+        nm = s.error_norms(uN, pN, uf, pf)
+        errs.append(nm["energy"])
+    return errs
+
+
+def ttt_record(errs, serial_ms, par_ms_fn):
+    kstar = next((k for k, e in enumerate(errs) if e <= 1e-5), None)
+    par_ms = par_ms_fn(kstar) if kstar is not None else None
+    return {"target": 1e-5, "reached_at_iteration": kstar,
+            "parareal_ms": round(par_ms, 3) if par_ms else None,
+            "serial_fine_ms": round(serial_ms, 3),
+            "speedup_vs_serial": (round(serial_ms / par_ms, 4)
+                                  if par_ms else None),
+            "energy_error_per_iteration": [float(f"{e:.4e}") for e in errs],
+            "plateau": float(f"{min(errs):.4e}")}
+
+
+def roofline_stencil(name, launch_ms, bytes_per_launch, traffic):
+    """Roofline object of a stencil kernel: achieved = algorithmic bytes per
+    launch / launch time against the HBM peak; traffic = counter bytes per
+    launch (profiles/), with the measured DRAM fraction beside it."""
+    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
+    out = {"bound": "hbm", "achieved": round(achieved, 1),
+           "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "traffic": traffic, "kernel": name,
+           "launch_ms": round(launch_ms, 4),
+           "algorithmic_bytes_per_launch": bytes_per_launch}
+    if traffic:
+        out["hbm_frac_measured"] = round(
+            traffic / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    return out
+
+
+def layers3d_measurement(pw, W, torch):
+    """The 3D layered workload at full size (256^3 / 64^3, N = 32, m_F =
+    76, K = 6, FP32 compensated state): one batched fine sweep timed on its
+    own (events), the full solve, the serial fine solve and the energy
+    error of slice N after k iterations against it."""
+    w = W.layers3d()
+    K = w.K
+    P = pw.Problem.make(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
+                        w.grad_order, w.tol, "f32", True, K,
+                        keep_history=True)
+    s = pw.Solver(P)
+    s.set_medium(w.c)
+    s.set_initial(w.u0, w.p0)
+    log("layers3d context ready")
+    s.run(0)
+    u = torch.empty((w.N,) + w.shape, dtype=torch.float32, device="cuda")
+    p = torch.empty_like(u)
+    for n in range(w.N):
+        u[n], p[n] = s.state(n)
+    s.propagate(u, p)  # warm
+    f_ms = stream_time(lambda: s.propagate(u, p), reps=2)
+    del u, p
+    torch.cuda.empty_cache()
+    upd = w.N * w.m_fine * w.npts
+    f_gupd = upd / (f_ms * 1e-3) / 1e9
+    launches, spl = s.launch_plan(w.N)
+    launch_ms = f_ms / launches
+    bpl = BYTES_PER_UPDATE_F32 * w.N * w.npts * spl
+    rev = pw.lib().pw_version().decode().split()[-1]
+    roof = roofline_stencil(f"3D fine stencil ({spl} step(s) per launch)",
+                            launch_ms, bpl, TRAFFIC3D.get(rev))
+    log(f"layers3d F sweep {f_ms:.1f} ms ({f_gupd:.1f} Gupd/s)")
+    solve_ms = solve_time(s, K, reps=1, run=lambda: s.run(K))
+    phases = s.timings()
+    uf, pf = s.serial_fine(w.N)
+    serial_ms = stream_time(lambda: s.serial_fine(w.N), reps=1)
+    errs = errors_to_serial(s, w, uf, pf)
+    ttt = ttt_record(errs, serial_ms,
+                     lambda k: solve_time(s, k, reps=1, run=lambda: s.run(k)))
+    log(f"layers3d solve {solve_ms:.0f} ms, serial fine {serial_ms:.0f} ms, "
+        "errors " + " ".join(f"{e:.2e}" for e in errs))
+    rho, ranks = s.residuals()
+    out = {"workload": "layers3d: 3D periodic 256^3 fine / 64^3 coarse, "
+                       "layered c 1.0/1.5/2.2/3.0 x (1 + 0.05 U[-1,1]) (seed "
+                       "0), Gaussian sigma 0.04 at the centre, T=1.5, N=32, "
+                       f"m_F={w.m_fine}, m_C={w.m_coarse}, K={K}, FP32 "
+                       "compensated state, FP64 corrector, tol 1e-13",
+           "fine_sweep_ms": round(f_ms, 3), "gupd_s": round(f_gupd, 2),
+           "hbm_frac_algorithmic": round(f_gupd * BYTES_PER_UPDATE_F32
+                                         / HBM_PEAK_GBS, 4),
+           "roofline": roof,
+           "solve_ms": round(solve_ms, 1),
+           "solve_gupd_s": round(K * upd / (solve_ms * 1e-3) / 1e9, 2),
+           "phases_ms": {k: round(v, 2) for k, v in phases.items()},
+           "rank": ranks, "rho": [float(f"{r:.4e}") for r in rho],
+           "time_to_1e-5": ttt}
+    s.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def wave1d_measurement(pw, W, torch):
+    """The 1D workload (256 / 64 points, N = 16, K = 6, FP64, tol 1e-14):
+    time to reach an energy error of 1e-5 at T against the serial fine
+    solve, both on the GPU."""
+    w = W.wave1d()
+    K = w.K
+    P = pw.Problem.make(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
+                        w.grad_order, w.tol, "f64", False, K,
+                        keep_history=True)
+    s = pw.Solver(P)
+    s.set_medium(w.c)
+    s.set_initial(w.u0, w.p0)
+    s.run(K)
+    uf, pf = s.serial_fine(w.N)
+    s.serial_fine(w.N)
+    serial_ms = stream_time(lambda: s.serial_fine(w.N), reps=5)
+    errs = errors_to_serial(s, w, uf, pf)
+    ttt = ttt_record(errs, serial_ms,
+                     lambda k: solve_time(s, k, reps=5, run=lambda: s.run(k)))
+    s.run(K)
+    ttt["phases_ms_K_iterations"] = {k: round(v, 3)
+                                     for k, v in s.timings().items()}
+    log(f"wave1d: serial {serial_ms:.3f} ms, parareal to 1e-5 "
+        f"{ttt['parareal_ms']} ms at k={ttt['reached_at_iteration']}")
+    s.close()
+    return {"workload": "wave1d: 1D periodic 256 / 64 points, c = 1 + 0.2 "
+                        "sin 2 pi x, N=16, m_F=32, m_C=8, K=6, FP64, tol "
+                        "1e-14", "time_to_1e-5": ttt}
 
 
 def serial_traces(pw, torch, w, c, receivers):
@@ -346,6 +565,37 @@ def sec6_comparator_measurement(pw, torch, K=8):
     return res
 
 
+def traffic_probe(pw, W, torch, which):
+    """One batched fine sweep of the batch2d or layers3d workload and one
+    512 MiB device copy (the copy scales the rocprofv3 counters)."""
+    if which == "batch":
+        ws, sb = batch_context(pw, W, 1)
+        sb.run_batch(1)
+        torch.cuda.synchronize()
+        sb.batch_fine_sweeps(1)
+        sb.close()
+    else:
+        w = W.layers3d()
+        P = pw.Problem.make(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
+                            w.grad_order, w.tol, "f32", True, 1)
+        s = pw.Solver(P)
+        s.set_medium(w.c)
+        s.set_initial(w.u0, w.p0)
+        s.run(0)
+        u = torch.empty((w.N,) + w.shape, dtype=torch.float32, device="cuda")
+        p = torch.empty_like(u)
+        for n in range(w.N):
+            u[n], p[n] = s.state(n)
+        s.propagate(u, p)
+        s.close()
+    src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"traffic probe ({which}) done: one fine sweep, one 536870912-byte "
+        "copy")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -374,9 +624,16 @@ def main():
                     help="only the misfit-gradient measurement (profiling)")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the 32-problem batched measurement (profiling)")
-    ap.add_argument("--traffic-probe", action="store_true",
-                    help="only run one fine sweep and one 512 MiB device "
-                         "copy (for rocprofv3 --pmc FETCH_SIZE/WRITE_SIZE)")
+    ap.add_argument("--layers-only", action="store_true",
+                    help="only the 3D layered workload (profiling)")
+    ap.add_argument("--no-layers", action="store_true",
+                    help="skip the 3D layered workload")
+    ap.add_argument("--no-wave1d", action="store_true",
+                    help="skip the 1D time-to-1e-5 study")
+    ap.add_argument("--traffic-probe", nargs="?", const="disc2d",
+                    choices=["disc2d", "batch", "layers3d"],
+                    help="only run one fine sweep of the workload and one "
+                         "512 MiB device copy (for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: runs on one GPU only (--gpus 1); sharding the "
@@ -399,6 +656,12 @@ def main():
         return
     if args.batch_only:
         print(json.dumps(batch_measurement(pw, W, torch)), flush=True)
+        return
+    if args.layers_only:
+        print(json.dumps(layers3d_measurement(pw, W, torch)), flush=True)
+        return
+    if args.traffic_probe in ("batch", "layers3d"):
+        traffic_probe(pw, W, torch, args.traffic_probe)
         return
     w = W.disc2d()
     K = w.K
@@ -491,8 +754,7 @@ def main():
     ev1.record()
     torch.cuda.synchronize()
     f_ms = ev0.elapsed_time(ev1) / reps
-    steps_per_launch = 8
-    launches = math.ceil(w.m_fine / steps_per_launch)
+    launches, steps_per_launch = s.launch_plan(w.N)
     launch_ms = f_ms / launches
     bytes_per_launch = BYTES_PER_UPDATE_F32 * w.N * w.npts * steps_per_launch
     achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
@@ -564,6 +826,8 @@ def main():
     torch.cuda.empty_cache()
     sampling = None if args.no_sampling else sampling_measurement(pw, W,
                                                                   torch)
+    layers = None if args.no_layers else layers3d_measurement(pw, W, torch)
+    wave1d = None if args.no_wave1d else wave1d_measurement(pw, W, torch)
     table = None if args.no_table else gradient_order_measurement(pw, torch)
     sec6 = None if args.no_sec6 else sec6_comparator_measurement(pw, torch)
 
@@ -607,6 +871,8 @@ def main():
         "gradient_order_table": table,
         "sec6_comparators": sec6,
         "batched": batched,
+        "layers3d": layers,
+        "wave1d": wave1d,
         "adjoint": adjoint,
         "cpu_baseline": cpu,
     }

@@ -419,6 +419,12 @@ pw_status pw_run_taped(pw_ctx* ctx, int prob, int K);
  * iterations).  PW_ESTATE without a prior taped run.                    */
 pw_status pw_run_frozen(pw_ctx* ctx, int prob, int K);
 
+/* Launch plan of one propagation F (grid = PW_FINE) or C (PW_COARSE) of
+ * n_states states in one batch: the number of kernel launches and the time
+ * steps each launch takes (the last one may take fewer).  Host only.     */
+pw_status pw_launch_plan(pw_ctx* ctx, int prob, int grid, int n_states, int* launches,
+                         int* steps_per_launch);
+
 /* Serial number of the tape: bumped by every pw_run_taped and
  * pw_run_frozen, so a caller that keeps a gradient graph can tell whether
  * the tape pw_backward will read is still the one its forward recorded. */

@@ -423,7 +423,7 @@ class PararealResult:
 def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
                    omega="procrustes", correction=True,
                    record_correctors=False, sample_cols=None, pmap=None,
-                   svd=None):
+                   svd=None, sweep="literal"):
     """Algorithm 3 of the paper, step by step.
 
     Initialisation u^1_n = I C R u^1_{n-1}; then K iterations of: parallel
@@ -449,6 +449,12 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
     process pool's ``starmap``); None runs the slices one after another.
     Every slice is computed by the same ``propagate`` call either way.
     ``svd``: the SVD routine of Algorithm 1 (see update_svd).
+
+    ``sweep``: "literal" applies Omega and grad2func to both terms of the
+    correction, as Algorithm 3 writes it; "difference" applies them once
+    to the difference Lambda(w - U_n), with the sum of w - U_n as the mean
+    (the same linear map, another rounding; used only to measure how much
+    rounding alone moves the iteration).
     """
     r = prob.ratio
     ik = prob.interp
@@ -541,6 +547,13 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
                     pn[n] = vp[n] + interp(wp - Ucp[n], r, ik)
                 else:
                     un[n], pn[n] = interp(w, r, ik), interp(wp, r, ik)
+                continue
+            if correction and sweep == "difference":
+                zd = Om(Lam(w - Uc[n], wp - Ucp[n]))
+                qd, pd = split_components(zd, cshape)
+                un[n] = v[n] + interp(grad2func(qd, np.sum(w - Uc[n]), dxc),
+                                      r, ik)
+                pn[n] = vp[n] + interp(cc * pd, r, ik)
                 continue
             zq = Om(Lam(w, wp))
             q, pq = split_components(zq, cshape)

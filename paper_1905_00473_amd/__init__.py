@@ -111,6 +111,9 @@ _SIGS = {
     "pw_load": [ctypes.c_void_p, ctypes.c_char_p],
     "pw_get_tape_id": [ctypes.c_void_p, ctypes.c_int,
                        ctypes.POINTER(ctypes.c_longlong)],
+    "pw_launch_plan": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                       ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                       ctypes.POINTER(ctypes.c_int)],
     "pw_set_variant": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int],
     "pw_set_sampling": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                         ctypes.c_int, ctypes.c_int],
@@ -362,6 +365,13 @@ class Solver:
 
     def load(self, path):
         _check(lib().pw_load(self._h, os.fsencode(path)))
+
+    def launch_plan(self, n_states, grid=FINE, prob=0):
+        """(launches, steps per launch) of one propagation of n_states."""
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _check(lib().pw_launch_plan(self._h, prob, grid, int(n_states),
+                                    ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def tape_id(self, prob=0):
         v = ctypes.c_longlong()

@@ -25,12 +25,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <memory>
 #include <new>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "pw_internal.h"
@@ -54,6 +57,8 @@ thread_local std::string g_last_error;
 // columns), [2] ||F_in||_F^2, [3] ||G_in||_F^2 (the columns entering
 // Algorithm 1), [4] trace of S~ after the update
 constexpr int kRes = 5;
+// host threads driving the per-problem corrector and sweep of a batch
+constexpr int kBatchThreads = 8;
 // values per iteration returned by pw_get_diagnostics
 constexpr int kPwDiag = 8;
 
@@ -195,6 +200,10 @@ struct Prob {
   // the core matrix: the G branch runs on a second stream, forked from and
   // joined to the caller's stream with events
   hipStream_t side = nullptr;
+  // batched runs: this problem's corrector and sweep run on its own stream,
+  // concurrently with the other problems' (joined with done_ev)
+  hipStream_t own = nullptr;
+  hipEvent_t done_ev = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   int variant = PW_VARIANT_THETA;  // iteration run by pw_run
   DevBuf samp;                     // sampled data columns, samp_iters x samp_n
@@ -230,6 +239,8 @@ struct Prob {
     if (fork_ev) (void)hipEventDestroy(fork_ev);
     if (join_ev) (void)hipEventDestroy(join_ev);
     if (side) (void)hipStreamDestroy(side);
+    if (own) (void)hipStreamDestroy(own);
+    if (done_ev) (void)hipEventDestroy(done_ev);
   }
 };
 
@@ -259,7 +270,9 @@ struct Batch {
   bool from_cache = false;
   double ms[4] = {0, 0, 0, 0};
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t fork_ev = nullptr;  // end of the parallel phase (problem streams wait on it)
   ~Batch() {
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -486,6 +499,8 @@ void setup(Prob& pr, const pw_problem& P) {
   pr.os2.work_elems = pr.gwork_elems;
   for (int i = 0; i < 4; ++i) PW_HIP(hipEventCreate(&pr.ev[i]));
   PW_HIP(hipStreamCreateWithFlags(&pr.side, hipStreamNonBlocking));
+  PW_HIP(hipStreamCreateWithFlags(&pr.own, hipStreamNonBlocking));
+  PW_HIP(hipEventCreateWithFlags(&pr.done_ev, hipEventDisableTiming));
   PW_HIP(hipEventCreateWithFlags(&pr.fork_ev, hipEventDisableTiming));
   PW_HIP(hipEventCreateWithFlags(&pr.join_ev, hipEventDisableTiming));
 }
@@ -1607,7 +1622,57 @@ void build_batch(pw_ctx* ctx, Batch& b) {
   PW_HIP(hipStreamEndCapture(b.cap_stream, &b.graph));
   PW_HIP(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
   for (auto& e : b.ev) PW_HIP(hipEventCreate(&e));
+  PW_HIP(hipEventCreateWithFlags(&b.fork_ev, hipEventDisableTiming));
   b.built = true;
+}
+
+// The corrector (data matrices, Algorithm 1) and the corrected sweep of
+// every problem of a batch, after the batched parallel phase enqueued on
+// `st`: each problem runs on its own stream, driven by one of a few host
+// threads, so that the problems' chains of small launches and the host
+// synchronisations inside Algorithm 1 (the rank read-back, the Jacobi
+// convergence test) overlap across problems.  The context stream then
+// waits for every problem.
+template <typename T>
+void concurrent_serial_phase(pw_ctx* ctx, int k, hipStream_t st) {
+  const int np = (int)ctx->probs.size();
+  hipEvent_t start = ctx->batch->fork_ev;
+  PW_HIP(hipEventRecord(start, st));
+  std::atomic<int> next{0};
+  std::vector<Error> errs;
+  std::mutex mu;
+  auto worker = [&] {
+    for (;;) {
+      const int i = next.fetch_add(1);
+      if (i >= np) return;
+      Prob& pr = *ctx->probs[(size_t)i];
+      try {
+        PW_HIP(hipStreamWaitEvent(pr.own, start, 0));
+        corrector_phase<T>(pr, k, pr.own);
+        sweep_phase<T>(pr, pr.own);
+        PW_HIP(hipEventRecord(pr.done_ev, pr.own));
+      } catch (const Error& e) {
+        std::lock_guard<std::mutex> lock(mu);
+        errs.push_back(e);
+        next.store(np);
+      } catch (const std::exception& e) {
+        std::lock_guard<std::mutex> lock(mu);
+        errs.push_back(Error{PW_EINVAL, e.what()});
+        next.store(np);
+      }
+    }
+  };
+  const int nt = std::max(1, std::min(np, kBatchThreads));
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
+  worker();
+  for (auto& th : pool) th.join();
+  if (!errs.empty()) {
+    // let every problem stream drain before reporting
+    for (auto& up : ctx->probs) (void)hipStreamSynchronize(up->own);
+    throw errs.front();
+  }
+  for (auto& up : ctx->probs) PW_HIP(hipStreamWaitEvent(st, up->done_ev, 0));
 }
 
 template <typename T>
@@ -1629,9 +1694,8 @@ void run_batch_typed(pw_ctx* ctx, int K) {
     PW_HIP(hipEventRecord(b.ev[0], st));
     PW_HIP(hipGraphLaunch(b.exec, st));
     PW_HIP(hipEventRecord(b.ev[1], st));
-    for (auto& up : ctx->probs) corrector_phase<T>(*up, k, st);
+    concurrent_serial_phase<T>(ctx, k, st);
     PW_HIP(hipEventRecord(b.ev[2], st));
-    for (auto& up : ctx->probs) sweep_phase<T>(*up, st);
     PW_HIP(hipEventRecord(b.ev[3], st));
     PW_HIP(hipEventSynchronize(b.ev[3]));
     float x = 0, y = 0, z = 0;
@@ -2168,6 +2232,20 @@ pw_status pw_get_diagnostics(pw_ctx* ctx, int prob, double* out, int cap, int* c
       o[7] = k < (int)pr.change.size() ? pr.change[(size_t)k] : std::nan("");
     }
     if (count) *count = K;
+  });
+}
+
+pw_status pw_launch_plan(pw_ctx* ctx, int prob, int grid, int n_states, int* launches,
+                         int* steps_per_launch) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (grid != PW_FINE && grid != PW_COARSE) fail(PW_EINVAL, "bad grid");
+    if (n_states < 1) fail(PW_EINVAL, "n_states must be >= 1");
+    int l = 0, b = 0;
+    if (grid == PW_FINE) launch_plan(pr.gf, pr.f64, n_states, pr.mF, &l, &b);
+    else launch_plan(pr.gc, pr.f64, n_states, pr.mC, &l, &b);
+    if (launches) *launches = l;
+    if (steps_per_launch) *steps_per_launch = b;
   });
 }
 

@@ -64,6 +64,9 @@ void propagate(const Grid& g, const T* c2, const T* u_src, const T* p_src, T* u_
 // largest number of steps one launch of the tiled kernel may take for this
 // grid (the whole propagation when the grid is one periodic line in LDS)
 int steps_per_launch(const Grid& g, bool is_double);
+// launches and time steps per launch that propagate() takes for nstates
+// states and m steps on grid g
+void launch_plan(const Grid& g, bool is_double, int nstates, int m, int* launches, int* spl);
 
 // Streams of one 2D problem in a launch of the streaming kernel: its
 // in/out state sets, grid, and the first global wave index it owns.

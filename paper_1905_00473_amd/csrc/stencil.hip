@@ -490,6 +490,230 @@ __global__ __launch_bounds__(256) void k_prop_stream2d_multi(const StreamDesc<T>
   stream2d_body<T, COMP, B>(a, wid - a.wave_begin, threadIdx.x & 63);
 }
 
+// ---------------------------------------------------------------------------
+// 3D streaming kernel with register-pipelined time steps.
+//
+// A workgroup of WY waves owns a 64 (x) by WY*R (y) block of columns and
+// streams it along z through a segment of planes.  Wave w holds rows
+// w*R .. w*R+R-1 of the block, lane l column l, one value per row in
+// registers.  As in the 2D kernel the B time steps of a launch are B
+// pipeline stages: at stream step t stage j turns level-j plane t-2j into
+// level j+1 plane t-2j from its window of three level-j planes (the z
+// neighbours), so the stages of one step are independent.  The x neighbours
+// come from the adjacent lanes (DPP wavefront shifts), the y neighbours from
+// the wave's own rows or, for its first and last row, from the waves above
+// and below through LDS: every step each wave publishes the first and last
+// row of every stage's centre plane, one barrier, and reads its
+// neighbours' (two LDS buffers alternate, so one barrier per step
+// suffices).  The valid region shrinks by one lane / row per stage on each
+// side, so the halo is H = B + 1 lanes and rows (the +1 for the closing
+// half kick) and a block writes 64 - 2H columns of WY*R - 2H rows.  Row and
+// column indices are wrapped once per thread, the plane index by one
+// conditional add per loaded plane.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Stream3Desc {
+  const T* u_in;
+  const T* p_in;
+  const T* eu_in;
+  const T* ep_in;
+  T* u_out;
+  T* p_out;
+  T* eu_out;
+  T* ep_out;
+  const T* c2;
+  long long sstride;
+  int nx, ny, nz;
+  int ncb, nyb, nseg, Lz;  // column blocks, row blocks, z segments, planes per segment
+  int nstates;
+  T h, idx2;
+  int nsteps, first, last;
+};
+
+template <typename T, bool COMP, int B, int R, int WY>
+__global__ __launch_bounds__(64 * WY) void k_prop_stream3d(Stream3Desc<T> a) {
+  constexpr int H = B + 1;
+  constexpr int XV = 64 - 2 * H;  // output columns of a block
+  constexpr int YR = WY * R;      // rows of a block
+  constexpr int YV = YR - 2 * H;  // output rows of a block
+  constexpr int NX = COMP ? 2 : 1;
+  // [buffer][field u / e][stage][first / last row][wave][lane]
+  __shared__ T xch[2][NX][B + 1][2][WY][64];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  // blocks of one XCD (block ids congruent mod 8) take consecutive streams,
+  // so that neighbouring blocks, which share halo columns and rows, share
+  // an L2
+  const long long nblk = (long long)a.nstates * a.nseg * a.nyb * a.ncb;
+  long long blk = blockIdx.x;
+  if ((nblk & 7) == 0) blk = (blk & 7) * (nblk >> 3) + (blk >> 3);
+  const int cb = (int)(blk % a.ncb);
+  const int yb = (int)((blk / a.ncb) % a.nyb);
+  const int seg = (int)((blk / ((long long)a.ncb * a.nyb)) % a.nseg);
+  const int state = (int)(blk / ((long long)a.ncb * a.nyb * a.nseg));
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int gx = wrap_idx(cb * XV - H + lane, nx);
+  const bool out_lane = lane >= H && lane < 64 - H && (cb * XV + lane - H) < nx;
+  long long rowoff[R];  // (y * nx + x) of this thread's rows
+  bool out_row[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int yr = w * R + r;  // row within the block
+    const int gy = wrap_idx(yb * YV - H + yr, ny);
+    rowoff[r] = (long long)gy * nx + gx;
+    out_row[r] = out_lane && yr >= H && yr < YR - H && (yb * YV + yr - H) < ny;
+  }
+  const long long plane = (long long)nx * ny;
+  const int Z0 = seg * a.Lz;
+  const int Z1 = min(Z0 + a.Lz, nz);
+  const long long base = (long long)state * a.sstride;
+  const T h = a.h;
+  const int ns = a.nsteps;
+  const bool first = a.first, last = a.last;
+  // stage j window: level-j planes (z-1, z, z+1), z = t - 2j; the pending
+  // plane z+2 comes from stage j-1 (or memory, for j = 0) in step t
+  T wu[B + 1][3][R], weu[B + 1][3][R], wp[B + 1][2][R], wep[B + 1][2][R], wk[B + 1][2][R];
+  T qu[B + 1][R], qp[B + 1][R], qeu[B + 1][R], qep[B + 1][R], qk[B + 1][R];
+#pragma unroll
+  for (int j = 0; j <= B; ++j)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      wu[j][0][r] = wu[j][1][r] = wu[j][2][r] = T(0);
+      weu[j][0][r] = weu[j][1][r] = weu[j][2][r] = T(0);
+      wp[j][0][r] = wp[j][1][r] = wep[j][0][r] = wep[j][1][r] = T(0);
+      wk[j][0][r] = wk[j][1][r] = T(0);
+      qu[j][r] = qp[j][r] = qeu[j][r] = qep[j][r] = qk[j][r] = T(0);
+    }
+  const int tout = last ? 2 * B : 2 * (B - 1);  // lag of the written level
+  const int tbeg = Z0 - H - 2;
+  const int tend = Z1 - 1 + tout;  // inclusive
+  int zl = tbeg + 2;               // plane loaded this step, wrapped below
+  zl = zl < 0 ? zl + nz : zl;
+  for (int t = tbeg; t <= tend; ++t) {
+    // level 0, plane t+2 -> pending slot of stage 0
+    if (t + 2 < Z1 + H) {
+      const long long po = (long long)zl * plane;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const long long gi = base + po + rowoff[r];
+        qu[0][r] = a.u_in[gi];
+        qp[0][r] = a.p_in[gi];
+        qk[0][r] = a.c2[po + rowoff[r]] * a.idx2;
+        if (COMP) {
+          qeu[0][r] = first ? T(0) : a.eu_in[gi];
+          qep[0][r] = first ? T(0) : a.ep_in[gi];
+        }
+      }
+    }
+    zl = zl + 1 == nz ? 0 : zl + 1;
+    // publish the first and last row of every stage's centre plane
+    const int buf = t & 1;
+#pragma unroll
+    for (int j = 0; j <= B; ++j) {
+      xch[buf][0][j][0][w][lane] = wu[j][1][0];
+      xch[buf][0][j][1][w][lane] = wu[j][1][R - 1];
+      if (COMP) {
+        xch[buf][NX - 1][j][0][w][lane] = weu[j][1][0];
+        xch[buf][NX - 1][j][1][w][lane] = weu[j][1][R - 1];
+      }
+    }
+    __syncthreads();
+    // y neighbours of the first and last row (zero outside the block: those
+    // rows are in the halo)
+    T au[B + 1], bu[B + 1], ae[B + 1], be[B + 1];
+#pragma unroll
+    for (int j = 0; j <= B; ++j) {
+      au[j] = w > 0 ? xch[buf][0][j][1][w - 1][lane] : T(0);
+      bu[j] = w < WY - 1 ? xch[buf][0][j][0][w + 1][lane] : T(0);
+      ae[j] = (COMP && w > 0) ? xch[buf][NX - 1][j][1][w - 1][lane] : T(0);
+      be[j] = (COMP && w < WY - 1) ? xch[buf][NX - 1][j][0][w + 1][lane] : T(0);
+    }
+    // second difference of x on the centre plane of stage j, row r
+    auto lap_of = [&](const T (&win)[3][R], T above, T below, int r) -> T {
+      const T c = win[1][r];
+      const T ym = r > 0 ? win[1][r - 1] : above;
+      const T yp = r < R - 1 ? win[1][r + 1] : below;
+      return (lane_up(c) - T(2) * c + lane_down(c)) + (ym - T(2) * c + yp) +
+             (win[0][r] - T(2) * c + win[2][r]);
+    };
+    // stages 0..B-1: kick + drift (stages past nsteps pass the plane through)
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const T uc = wu[j][1][r];
+        T un = uc, pn = wp[j][0][r], eu = weu[j][1][r], ep = wep[j][0][r];
+        const T kj = wk[j][0][r];
+        if (j < ns) {
+          T lap = lap_of(wu[j], au[j], bu[j], r);
+          if (COMP) lap -= lap_of(weu[j], ae[j], be[j], r);
+          const T wgt = (j == 0 && first) ? h * T(0.5) : h;
+          kadd<T, COMP>(pn, ep, wgt * (kj * lap));
+          kadd<T, COMP>(un, eu, h * pn);
+        }
+        qu[j + 1][r] = un;
+        qp[j + 1][r] = pn;
+        qeu[j + 1][r] = eu;
+        qep[j + 1][r] = ep;
+        qk[j + 1][r] = kj;
+        if (j == B - 1 && !last) {
+          const int oz = t - 2 * j;
+          if (out_row[r] && oz >= Z0 && oz < Z1) {
+            const long long gi = base + (long long)oz * plane + rowoff[r];
+            a.u_out[gi] = un;
+            a.p_out[gi] = pn;
+            if (COMP) {
+              a.eu_out[gi] = eu;
+              a.ep_out[gi] = ep;
+            }
+          }
+        }
+      }
+    }
+    // stage B: closing half kick of the slice, then fold and write
+    if (last) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const T uc = wu[B][1][r];
+        const T ec = weu[B][1][r];
+        T lap = lap_of(wu[B], au[B], bu[B], r);
+        if (COMP) lap -= lap_of(weu[B], ae[B], be[B], r);
+        T pn = wp[B][0][r], ep = wep[B][0][r];
+        kadd<T, COMP>(pn, ep, h * T(0.5) * (wk[B][0][r] * lap));
+        const int oz = t - 2 * B;
+        if (out_row[r] && oz >= Z0 && oz < Z1) {
+          const long long gi = base + (long long)oz * plane + rowoff[r];
+          if (COMP) {
+            a.u_out[gi] = uc - ec;
+            a.p_out[gi] = pn - ep;
+          } else {
+            a.u_out[gi] = uc;
+            a.p_out[gi] = pn;
+          }
+        }
+      }
+    }
+    // advance every window by one plane, taking in the pending plane
+#pragma unroll
+    for (int j = 0; j <= B; ++j)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        wu[j][0][r] = wu[j][1][r];
+        wu[j][1][r] = wu[j][2][r];
+        wu[j][2][r] = qu[j][r];
+        wp[j][0][r] = wp[j][1][r];
+        wp[j][1][r] = qp[j][r];
+        weu[j][0][r] = weu[j][1][r];
+        weu[j][1][r] = weu[j][2][r];
+        weu[j][2][r] = qeu[j][r];
+        wep[j][0][r] = wep[j][1][r];
+        wep[j][1][r] = qep[j][r];
+        wk[j][0][r] = wk[j][1][r];
+        wk[j][1][r] = qk[j][r];
+      }
+  }
+}
+
 // tile geometry per dimension: interior and the largest halo of one launch
 struct TileCfg {
   int tx, ty, tz, hmax;
@@ -674,6 +898,109 @@ void propagate_stream2d(const Grid& g, const T* c2, const T* u_src, const T* p_s
                                              m, h, comp, wa, wb, fine, st);
 }
 
+// launch shape of the 3D streaming kernel per state type: time steps per
+// launch, rows per wave, waves per workgroup
+template <typename T>
+struct Stream3Cfg {
+  static constexpr int B = 2;
+  static constexpr int R = sizeof(T) == 4 ? 2 : 1;
+  static constexpr int WY = 16;
+};
+
+// waves per workgroup of the 3D streaming kernel (PW_STREAM3D_WAVES = 8
+// selects half-height blocks: more halo rows, two workgroups per CU)
+int stream3d_waves() {
+  static const int w = [] {
+    const char* e = getenv("PW_STREAM3D_WAVES");  // tuning override
+    return (e && atoi(e) == 8) ? 8 : 16;
+  }();
+  return w;
+}
+
+template <typename T, bool COMP>
+void dispatch_stream3d(const Stream3Desc<T>& a, hipStream_t st) {
+  using C = Stream3Cfg<T>;
+  const long long nblk = (long long)a.nstates * a.nseg * a.nyb * a.ncb;
+  if (nblk >= (1LL << 31)) fail(PW_EINVAL, "too many streams for one launch");
+  if (stream3d_waves() == 8)
+    hipLaunchKernelGGL((k_prop_stream3d<T, COMP, C::B, C::R, 8>), dim3((unsigned)nblk),
+                       dim3(64 * 8), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_prop_stream3d<T, COMP, C::B, C::R, C::WY>), dim3((unsigned)nblk),
+                       dim3(64 * C::WY), 0, st, a);
+  PW_LAUNCH_CHECK();
+}
+
+// 3D streams: blocks of (64 - 2H) columns by (WY R - 2H) rows, z segments
+// sized so that about kStream3Target workgroups fill the chip (segments of
+// at least 16 planes, or of 2 B planes when even that leaves few blocks)
+constexpr long long kStream3Target = 1024;
+
+template <typename T>
+void propagate_stream3d(const Grid& g, const T* c2, const T* u_src, const T* p_src, T* u_dst,
+                        T* p_dst, long long sstride, int nstates, int m, T h, bool comp,
+                        StateSet<T> wa, StateSet<T> wb, hipStream_t st) {
+  using C = Stream3Cfg<T>;
+  constexpr int B = C::B, H = B + 1;
+  constexpr int XV = 64 - 2 * H;
+  const int YV = stream3d_waves() * C::R - 2 * H;
+  Stream3Desc<T> a{};
+  a.c2 = c2;
+  a.sstride = sstride;
+  a.nx = g.n[0];
+  a.ny = g.n[1];
+  a.nz = g.n[2];
+  if (a.nx < H || a.ny < H || a.nz < H) fail(PW_EINVAL, "3D grid smaller than the stencil halo");
+  a.nstates = nstates;
+  a.h = h;
+  a.idx2 = T(1.0 / (g.dx * g.dx));
+  a.ncb = (a.nx + XV - 1) / XV;
+  a.nyb = (a.ny + YV - 1) / YV;
+  const long long blocks = (long long)nstates * a.ncb * a.nyb;
+  const int minz = blocks < 256 ? 2 * B : 16;
+  long long nseg = (kStream3Target + blocks - 1) / blocks;
+  nseg = std::max(1LL, std::min(nseg, (long long)((a.nz + minz - 1) / minz)));
+  a.Lz = (int)((a.nz + nseg - 1) / nseg);
+  a.nseg = (a.nz + a.Lz - 1) / a.Lz;
+  const int nl = (m + B - 1) / B;
+  if (nl > 1 && (wa.u == nullptr || wb.u == nullptr || (comp && (wa.eu == nullptr || wb.eu == nullptr))))
+    fail(PW_EINVAL, "propagation needs scratch state sets");
+  const T* cu = u_src;
+  const T* cp = p_src;
+  const T* ceu = nullptr;
+  const T* cep = nullptr;
+  for (int l = 0; l < nl; ++l) {
+    a.first = (l == 0);
+    a.last = (l == nl - 1);
+    a.nsteps = std::min(B, m - l * B);
+    a.u_in = cu;
+    a.p_in = cp;
+    a.eu_in = ceu;
+    a.ep_in = cep;
+    StateSet<T> out;
+    if (a.last) {
+      out.u = u_dst;
+      out.p = p_dst;
+    } else {
+      out = ((nl - 1 - l) % 2 == 1) ? wa : wb;
+    }
+    a.u_out = out.u;
+    a.p_out = out.p;
+    a.eu_out = out.eu;
+    a.ep_out = out.ep;
+    if (comp) {
+      if constexpr (sizeof(T) == 4) dispatch_stream3d<T, true>(a, st);
+      else fail(PW_EINVAL, "compensation is an FP32 mode");
+    } else {
+      dispatch_stream3d<T, false>(a, st);
+    }
+    cu = out.u;
+    cp = out.p;
+    ceu = out.eu;
+    cep = out.ep;
+  }
+}
+
 TileCfg tile_cfg(int dim) { return dim == 1 ? kTile1 : (dim == 2 ? kTile2 : kTile3); }
 
 bool use_line(const Grid& g) { return g.dim == 1 && g.n[0] <= 4096; }
@@ -720,9 +1047,30 @@ const double* leapfrog_levels2d(const Grid& g, const double* c2, const double* u
   return cp;
 }
 
+void launch_plan(const Grid& g, bool is_double, int nstates, int m, int* launches, int* spl) {
+  int b;
+  if (use_line(g)) {
+    b = std::max(m, 1);
+  } else if (g.dim == 2) {
+    b = is_double ? stream_depth<double>() : stream_depth<float>();
+    if (!is_double) {
+      constexpr int XV = 64 - 2 * (stream_depth<float>() + 1);
+      const long long lanes = (long long)nstates * ((g.n[0] + XV - 1) / XV);
+      if (lanes * ((g.n[1] + 31) / 32) < 256) b = 4;
+    }
+  } else if (g.dim == 3) {
+    b = Stream3Cfg<float>::B;
+  } else {
+    b = tile_cfg(g.dim).hmax - 1;
+  }
+  *spl = b;
+  *launches = m <= 0 ? 0 : (m + b - 1) / b;
+}
+
 int steps_per_launch(const Grid& g, bool is_double) {
   if (use_line(g)) return 1 << 30;
   if (g.dim == 2) return is_double ? stream_depth<double>() : stream_depth<float>();
+  if (g.dim == 3) return Stream3Cfg<float>::B;
   return tile_cfg(g.dim).hmax - 1;
 }
 
@@ -769,6 +1117,11 @@ void propagate(const Grid& g, const T* c2, const T* u_src, const T* p_src, T* u_
   if (g.dim == 2) {
     propagate_stream2d<T>(g, c2, u_src, p_src, u_dst, p_dst, sstride, nstates, m, h, comp, wa, wb,
                           fine, st);
+    return;
+  }
+  if (g.dim == 3) {
+    propagate_stream3d<T>(g, c2, u_src, p_src, u_dst, p_dst, sstride, nstates, m, h, comp, wa, wb,
+                          st);
     return;
   }
   const TileCfg c = tile_cfg(g.dim);

@@ -117,15 +117,19 @@ def oracle_pool(n=None):
 def derived_gates(Q, w, u0, p0, K, ref, pmap=None, floor=1e-12,
                   **oracle_kwargs):
     """Per-norm gates (energy, l2, max; see state_errors) for an FP64
-    end-to-end comparison, each max(floor, 256 A eps, 16 S, 16 D) with,
-    from three more oracle runs:
+    end-to-end comparison, each max(floor, 256 A eps, 16 S, 16 D, 16 L)
+    with, from four more oracle runs:
     A  the amplification of a 1e-13 relative perturbation of u0;
     S  the spread of Algorithm 1 over the order of its data columns;
     D  the spread over the SVD routine of Algorithm 1 (LAPACK's QR-iteration
        driver in place of divide and conquer): both drivers are backward
        stable, so D is how far a correct SVD may move the iteration through
        the singular directions the truncation keeps but the data determine
-       only to eps sigma_1 / sigma_i.
+       only to eps sigma_1 / sigma_i;
+    L  the spread over the form of the correction: Omega and Lambda^dag
+       applied to each of its two terms (Algorithm 3 as written) or once to
+       their difference, with the mean of the difference (the GPU's form):
+       in the two-term form the mean is a difference of two large sums.
     ``ref`` is the oracle run the GPU is compared with."""
     import functools
 
@@ -141,6 +145,8 @@ def derived_gates(Q, w, u0, p0, K, ref, pmap=None, floor=1e-12,
     svd = functools.partial(scipy.linalg.svd, lapack_driver="gesvd")
     runs["D"] = O.theta_parareal(Q, w.c, u0, p0, K, pmap=pmap, svd=svd,
                                  **oracle_kwargs)
+    runs["L"] = O.theta_parareal(Q, w.c, u0, p0, K, pmap=pmap,
+                                 sweep="difference", **oracle_kwargs)
     spread = {}
     for key, r in runs.items():
         spread[key] = np.max([state_errors(r.u[n], r.p[n], ref.u[n], ref.p[n],
@@ -148,5 +154,6 @@ def derived_gates(Q, w, u0, p0, K, ref, pmap=None, floor=1e-12,
                               for n in range(1, Q.N + 1)], axis=0)
     gates = np.maximum.reduce([np.full(3, floor),
                                256 * spread["A"] / eps_in * 2.0 ** -52,
-                               16 * spread["S"], 16 * spread["D"]])
+                               16 * spread["S"], 16 * spread["D"],
+                               16 * spread["L"]])
     return gates, spread

@@ -665,3 +665,45 @@ def test_cubic_interp_2d_separable():
     ref = np.array([O.interp(row, 3, "cubic") for row in V])
     ref = np.array([O.interp(col, 3, "cubic") for col in ref.T]).T
     np.testing.assert_allclose(g, ref, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# l2 error (Sec. 6 preamble, beside the energy error)
+# ---------------------------------------------------------------------------
+def test_l2_error_closed_form():
+    """||a cos + b sin|| over n equispaced points is sqrt(n (a^2 + b^2) / 2)
+    exactly (discrete orthogonality), so the relative l2 error of
+    cos + eps sin against cos is eps; a constant shift c of u, which the
+    energy norm does not see, gives c sqrt(2)."""
+    n = 200
+    x = np.arange(n) / n
+    ref = np.cos(2 * np.pi * 3 * x)
+    for eps in (1e-3, 1e-9):
+        u = ref + eps * np.sin(2 * np.pi * 5 * x)
+        assert abs(O.l2_error(u, ref) - eps) <= 1e-12 * eps + 1e-15
+    assert abs(O.l2_error(ref + 0.1, ref) - 0.1 * math.sqrt(2)) < 1e-14
+    c = np.ones(n)
+    assert O.energy(ref + 0.1 - ref, 0 * ref, c, 1 / n) < 1e-25
+    assert O.l2_error(np.zeros(n), np.zeros(n)) == 0.0
+
+
+# ---------------------------------------------------------------------------
+# the one-term form of the correction (same linear map, other rounding)
+# ---------------------------------------------------------------------------
+def test_difference_form_of_the_sweep_is_the_same_map():
+    """Omega and Lambda^dag applied once to Lambda(w - U_n) with the mean
+    of w - U_n equal the two-term form of Algorithm 3 to rounding, and
+    keep the exactness of converged slices."""
+    n, N, K = 48, 6, 3
+    x = np.arange(n) / n
+    c = 1.0 + 0.2 * np.sin(2 * np.pi * x)
+    u0 = np.exp(-(x - 0.5) ** 2 / 0.05 ** 2)
+    Q = O.Problem((n,), 4, 0.6, N, 16, 4, 4, 1e-6)
+    a = O.theta_parareal(Q, c, u0, 0 * u0, K)
+    b = O.theta_parareal(Q, c, u0, 0 * u0, K, sweep="difference")
+    for k in range(1, N + 1):
+        e = O.energy_error(b.u[k], b.p[k], a.u[k], a.p[k], c, 1 / n)
+        assert e < 1e-12, (k, e)
+    ref_u, _ = O.serial_fine(Q, c, u0, 0 * u0)
+    for k in range(K + 1):
+        assert np.array_equal(b.u[k], ref_u[k])
