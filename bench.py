@@ -1,27 +1,33 @@
 """Benchmark of the MI355X parareal-like wave solver (one GPU).
 
-A step is one full solve of Algorithm 3 (coarse initialisation + K
-iterations: batched fine propagation over all slices, Procrustes corrector,
-corrected sweep, interpolation and update) on the disc2d workload: 2D
-periodic 512^2 fine / 128^2 coarse grid, c = 1 with c = 2 inside a disc of
-radius 0.2, Gaussian pulse (sigma 0.03) at (0.3, 0.5), T = 2, N = 64 slices,
-m_F = 64, m_C = 16, K = 8, FP32 compensated state, FP64 corrector,
-svd tol 1e-13.  Inputs are synthetic and already resident in HBM when the
-timed region starts.
+A step is one full batched solve of Algorithm 3 on the batch2d workload: 32
+independent 2D periodic problems whose fine grids are drawn from {256, 384,
+512, 768, 1024}^2 (coarse = fine/4), smooth random media c = exp(0.3 g) (g a
+Gaussian random field of correlation length 0.1), random Gaussian pulses,
+N = 32 slices each, K = 6 iterations, T = 1, FP32 compensated state, FP64
+corrector, svd tol 1e-13: the coarse initialisation, then per iteration the
+fine sweep of every slice of every problem (one multi-problem launch per
+time block, replayed from a hipGraph), the corrector (Algorithm 1) and the
+corrected sweep of every problem (concurrently, one stream per problem),
+interpolation and update.  Inputs are synthetic and resident in HBM when
+the timed region starts.
 
-value = fine point-updates of the K batched fine sweeps (K * N * m_F *
-512^2 per step) / wall time of the steps, in Gpoint-updates/s.
+value = fine point-updates of the K batched sweeps (K * sum_b N m_F,b n_b^2
+per step) / wall time of the steps, in Gpoint-updates/s.
 
-Also reported: the roofline of the fine stencil kernel (algorithmic 20 B
-per FP32 point-update: read u, p, c^2, write u, p), the serial GPU fine
-solve and the time to reach 1e-5 energy error against it, the comparator
-iterations of Sec. 6 (Omega = I, no parareal-style correction, plain
-parareal: error per iteration and time), the random subsampling of the
-data matrices on the Sec. 6.5 waveguide (error per iteration and corrector
-time per sample size, singular-value decay), the Sec. 6.4 gradient-order
-table recomputed on the GPU beside the printed values, the comparisons of
-Secs. 6.2 / 6.3 on the paper's 1D setup, the per-phase
-split, and the FP64 oracle timed on the host on a bounded sample.
+roofline: the dominant kernel, the multi-problem fine stencil
+(algorithmic 20 B per FP32 point-update: read u, p, c^2, write u, p), timed
+on its own with events on the context stream; `traffic` is the HBM bytes
+per launch measured with rocprofv3 counters (profiles/).
+
+Also reported: the disc2d workload (512^2, 64 slices: solve, fine-sweep
+roofline, time to 1e-5 against the serial fine solve, comparator
+iterations of Sec. 6), the 3D layered workload at full size (256^3, 32
+slices), the 1D workload's time to 1e-5, the misfit gradient, random
+subsampling and randomised sketching on the Sec. 6.5 waveguide, the Sec.
+6.4 gradient-order table, the Secs. 6.2 / 6.3 comparisons, the FP32 error
+against the FP64 oracle per result, and the oracle timed on the host (one
+process and a pool over all cores) on a bounded sample.
 """
 
 import argparse
@@ -35,16 +41,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 BYTES_PER_UPDATE_F32 = 20
+# flops of one velocity-Verlet point-update in the merged (leapfrog) form,
+# a fused multiply-add counted as 2: per axis a three-point second
+# difference (one add, one multiply-add: 3), the axes summed (d - 1), the
+# kick p += h (c^2/dx^2) lap (one multiply, one multiply-add: 3), the
+# drift u += h p (2)
+FLOPS_PER_UPDATE = {1: 8, 2: 12, 3: 16}
 # HBM bytes per launch of the fine stencil kernel, from the two rocprofv3
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) of `bench.py --traffic-probe`, scaled
 # by the same counters on a 512 MiB copy (profiles/disc2d_fine_stencil_
 # traffic.md).  Valid only for the stencil revision it was measured on.
-TRAFFIC = {"stencil-r6": 563.7e6}
+TRAFFIC = {"stencil-r6": 563.7e6, "stencil-r7": 561.5e6}
 # the same for the 3D stencil (layers3d) and the multi-problem 2D kernel
-# (batch2d), per launch, keyed by the revision they were measured on
-TRAFFIC3D = {}
-TRAFFIC_BATCH = {}
+# (batch2d), per launch (mean over one sweep), keyed by the revision they
+# were measured on (profiles/batch2d_fine_stencil_counters.md,
+# profiles/layers3d_fine_stencil_counters.md)
+TRAFFIC3D = {"stencil-r7": 32386.9e6}
+TRAFFIC_BATCH = {"stencil-r7": 13787.9e6}
+# VALU instructions issued / (SIMDs x 4 cycles x elapsed cycles) over the
+# same launches, from SQ_INSTS_VALU and GRBM_GUI_ACTIVE (values above 1:
+# some instructions dual-issued)
+VALU_ISSUE = {"stencil-r7": {"multi": 1.095, "single2d": 0.935, "3d": 0.526}}
 
 
 def log(msg):
@@ -62,51 +81,54 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(w, budget_s=8.0):
+def cpu_baseline(ws, budget_s=8.0):
     """The oracle's fine propagator (numpy FP64) on a bounded sample of the
-    workload's first fine sweep, timed two ways: one process, and a process
-    pool over slices with one worker per host core (the parfor of Algorithm
-    3).  The pool leg is the reported value."""
-    import numpy as np
-
+    batched workload: slice propagations (m_F steps from a problem's initial
+    state) of the batch's problems in order, timed two ways: one process,
+    and a process pool over slices with one worker per host core (the parfor
+    of Algorithm 3).  The pool leg is the reported value."""
     import oracle as O
     from tests.gpu_helpers import oracle_pool
-    c2 = w.c * w.c
-    dx = 1.0 / w.shape[-1]
-    h = w.T / w.N / w.m_fine
-    u, p = w.u0.copy(), w.p0.copy()
+
+    def task(w):
+        return (w.u0, w.p0, w.c * w.c, w.T / w.N / w.m_fine,
+                1.0 / w.shape[-1], w.m_fine)
+
     t0 = time.perf_counter()
-    slices = 0
-    while time.perf_counter() - t0 < budget_s and slices < w.N:
-        u, p = O.propagate(u, p, c2, h, dx, w.m_fine)
-        slices += 1
+    upd1, i = 0, 0
+    while time.perf_counter() - t0 < budget_s:
+        w = ws[i % len(ws)]
+        O.propagate(*task(w))
+        upd1 += w.m_fine * w.npts
+        i += 1
     dt1 = time.perf_counter() - t0
-    one = slices * w.m_fine * w.npts / dt1 / 1e9
+    one = upd1 / dt1 / 1e9
     cores = max(1, min(os.cpu_count() or 1, 64))
-    # the pool propagates as many independent states as it has workers,
-    # repeated while the budget lasts (the same state: the work per slice
-    # does not depend on the data)
-    states = [(w.u0, w.p0, c2, h, dx, w.m_fine)] * cores
+    tasks = [task(w) for w in ws]
     with oracle_pool(cores) as pm:
-        list(pm(O.propagate, states[:1]))  # start the workers
+        list(pm(O.propagate, tasks[:1]))  # start the workers
         t0 = time.perf_counter()
-        done = 0
+        upd, done, j = 0, 0, 0
         while time.perf_counter() - t0 < budget_s or done == 0:
-            list(pm(O.propagate, states))
+            batch = [tasks[(j + q) % len(tasks)] for q in range(cores)]
+            list(pm(O.propagate, batch))
+            upd += sum(ws[(j + q) % len(ws)].m_fine * ws[(j + q) % len(ws)].npts
+                       for q in range(cores))
+            j += cores
             done += cores
         dtp = time.perf_counter() - t0
-    pool = done * w.m_fine * w.npts / dtp / 1e9
+    pool = upd / dtp / 1e9
     model = cpu_model()
     return {"value": round(pool, 5), "unit": "Gpoint-updates/s",
             "cores": cores, "kind": "oracle",
             "cpu_model": model,
             "single_process": {"value": round(one, 5), "cores": 1,
-                               "sample": f"{slices} slices in {dt1:.1f} s"},
-            "sample": f"oracle fine propagator F (numpy FP64) on "
-                      f"{w.shape[0]}^{len(w.shape)} states of the "
-                      f"{w.name} workload, {w.m_fine} steps per slice: "
-                      f"{done} slice propagations on a pool of {cores} "
-                      f"processes in {dtp:.1f} s ({model})"}
+                               "sample": f"{i} slice propagations in "
+                                         f"{dt1:.1f} s"},
+            "sample": f"oracle fine propagator F (numpy FP64): {done} slice "
+                      f"propagations (m_F steps each) of the batch's problems "
+                      f"in order on a pool of {cores} processes in "
+                      f"{dtp:.1f} s ({model})"}
 
 
 def batch_context(pw, W, K):
@@ -155,9 +177,10 @@ def batch_measurement(pw, W, torch):
            "hbm_frac_algorithmic": round(gupd * BYTES_PER_UPDATE_F32 / HBM_PEAK_GBS, 4),
            "roofline": roofline_stencil(
                f"k_prop_stream2d_multi<float, true, {depth}> (mean launch "
-               f"of a sweep, {launches} launches)", launch_ms, int(bpl),
-               TRAFFIC_BATCH.get(rev)),
+               f"of a sweep, {launches} launches)", launch_ms, upd / launches,
+               TRAFFIC_BATCH.get(rev), 2, VALU_ISSUE.get(rev, {}).get("multi")),
            "depth": depth, "rows_per_stream": info["rows_per_stream"],
+           "rows_per_stream_by_grid": info["rows_per_stream_by_size"],
            "tune_ms": round(info["tune_ms"], 1),
            "first_batched_iteration_s": round(t_iter, 3),
            "solve_ms": round(solve_ms, 1),
@@ -219,20 +242,42 @@ def ttt_record(errs, serial_ms, par_ms_fn):
             "plateau": float(f"{min(errs):.4e}")}
 
 
-def roofline_stencil(name, launch_ms, bytes_per_launch, traffic):
-    """Roofline object of a stencil kernel: achieved = algorithmic bytes per
-    launch / launch time against the HBM peak; traffic = counter bytes per
-    launch (profiles/), with the measured DRAM fraction beside it."""
-    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
-    out = {"bound": "hbm", "achieved": round(achieved, 1),
-           "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(achieved / HBM_PEAK_GBS, 4),
-           "traffic": traffic, "kernel": name,
-           "launch_ms": round(launch_ms, 4),
-           "algorithmic_bytes_per_launch": bytes_per_launch}
+def roofline_stencil(name, launch_ms, updates_per_launch, traffic, dim, valu):
+    """Roofline object of a fine-stencil kernel.  The time-blocked kernels
+    take several steps per launch from one read and one write of the state,
+    so their algorithmic HBM rate exceeds the HBM peak; rocprofv3 counters
+    (profiles/) give the real DRAM bytes and the VALU issue rate.  A kernel
+    whose SIMDs issue a VALU instruction nearly every cycle is reported
+    "alu": achieved = algorithmic flops per launch (FLOPS_PER_UPDATE of the
+    scheme, compensation not counted) / launch time against the FP32 vector
+    peak; otherwise "hbm": algorithmic bytes (20 B per point-update) / launch
+    time against the HBM peak.  Both views are kept in the object."""
+    t = launch_ms * 1e-3
+    bytes_algo = BYTES_PER_UPDATE_F32 * updates_per_launch
+    flops = FLOPS_PER_UPDATE[dim] * updates_per_launch
+    hbm = {"achieved_algorithmic_GBs": round(bytes_algo / t / 1e9, 1),
+           "frac_algorithmic": round(bytes_algo / t / 1e9 / HBM_PEAK_GBS, 4)}
     if traffic:
-        out["hbm_frac_measured"] = round(
-            traffic / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        hbm["measured_GBs"] = round(traffic / t / 1e9, 1)
+        hbm["frac_measured"] = round(traffic / t / 1e9 / HBM_PEAK_GBS, 4)
+    alu = {"achieved_TFLOPs": round(flops / t / 1e12, 3),
+           "frac": round(flops / t / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4),
+           "flops_per_update": FLOPS_PER_UPDATE[dim],
+           "valu_issue_frac": valu}
+    valu_bound = valu is not None and valu >= 0.8
+    if valu_bound:
+        out = {"bound": "alu", "achieved": alu["achieved_TFLOPs"],
+               "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+               "frac": alu["frac"]}
+    else:
+        out = {"bound": "hbm", "achieved": hbm["achieved_algorithmic_GBs"],
+               "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": hbm["frac_algorithmic"]}
+    out.update({"traffic": traffic, "kernel": name,
+                "launch_ms": round(launch_ms, 4),
+                "algorithmic_bytes_per_launch": int(bytes_algo),
+                "algorithmic_flops_per_launch": int(flops),
+                "hbm_view": hbm, "alu_view": alu})
     return out
 
 
@@ -263,10 +308,10 @@ def layers3d_measurement(pw, W, torch):
     f_gupd = upd / (f_ms * 1e-3) / 1e9
     launches, spl = s.launch_plan(w.N)
     launch_ms = f_ms / launches
-    bpl = BYTES_PER_UPDATE_F32 * w.N * w.npts * spl
     rev = pw.lib().pw_version().decode().split()[-1]
-    roof = roofline_stencil(f"3D fine stencil ({spl} step(s) per launch)",
-                            launch_ms, bpl, TRAFFIC3D.get(rev))
+    roof = roofline_stencil(f"k_prop_stream3d<float, true, {spl}, 2, 8>",
+                            launch_ms, w.N * w.npts * spl, TRAFFIC3D.get(rev),
+                            3, VALU_ISSUE.get(rev, {}).get("3d"))
     log(f"layers3d F sweep {f_ms:.1f} ms ({f_gupd:.1f} Gupd/s)")
     solve_ms = solve_time(s, K, reps=1, run=lambda: s.run(K))
     phases = s.timings()
@@ -477,6 +522,32 @@ def sampling_measurement(pw, W, torch):
         log(f"sampling {n_s}/{w.N}: {ms:.1f} ms (corrector "
             f"{ph['corrector']:.1f}), errors "
             + " ".join(f"{e:.2e}" for e in errs))
+    s.set_sampling(None)
+    # randomised sketching of the new data (range finder, one power
+    # iteration) with as many directions per iteration as the samples above
+    out["sketch"] = {}
+    for l in (w.N // 4, w.N // 8):
+        s.set_sketch(W.sketch_matrices(w.N, l, K, seed=0), power=1)
+        errs = []
+        for k in range(0, K + 1):
+            s.run(k)
+            uN, pN = s.state(w.N)
+            ed, er = s.energy(uN, pN, uf, pf)
+            errs.append(float(f"{math.sqrt(ed / er):.4e}"))
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        s.run(K)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - a) * 1e3
+        ph = s.timings()
+        _, ranks = s.residuals()
+        out["sketch"][str(l)] = {"energy_error_per_iteration": errs,
+                                 "ms_K_iterations": round(ms, 2),
+                                 "corrector_ms": round(ph["corrector"], 2),
+                                 "rank": ranks, "power_iterations": 1}
+        log(f"sketch l={l}: {ms:.1f} ms (corrector {ph['corrector']:.1f}), "
+            "errors " + " ".join(f"{e:.2e}" for e in errs))
+    s.set_sketch(None)
     s.close()
     return out
 
@@ -596,6 +667,206 @@ def traffic_probe(pw, W, torch, which):
         "copy")
 
 
+def disc2d_traffic_probe(pw, W, torch):
+    w = W.disc2d()
+    P = pw.Problem.make(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
+                        w.grad_order, w.tol, "f32", True, w.K)
+    s = pw.Solver(P)
+    s.set_medium(w.c)
+    s.set_initial(w.u0, w.p0)
+    u = torch.empty((w.N,) + w.shape, dtype=torch.float32, device="cuda")
+    p = torch.empty_like(u)
+    for n in range(w.N):
+        u[n], p[n] = s.state(n)
+    s.propagate(u, p)
+    src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)  # plain copy: 512 MiB read + 512 MiB written
+    torch.cuda.synchronize()
+    log("traffic probe (disc2d) done: one fine sweep, one 536870912-byte copy")
+    s.close()
+
+
+def disc2d_measurement(pw, W, torch, args):
+    """The discontinuous-disc workload (512^2 / 128^2, N = 64, m_F = 64,
+    K = 8, FP32 compensated state, tol 1e-13): the full solve, its phases,
+    the batched fine sweep with its roofline, the serial fine solve and the
+    energy error after k iterations against it, and the comparator
+    iterations of Sec. 6."""
+    w = W.disc2d()
+    K = w.K
+    P = pw.Problem.make(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
+                        w.grad_order, w.tol, "f32", True, K,
+                        keep_history=True)
+    s = pw.Solver(P)
+    s.set_medium(w.c)
+    s.set_initial(w.u0, w.p0)
+    s.run(K)
+    solve_ms = solve_time(s, K, reps=5)
+    phases = s.timings()
+    rho, ranks = s.residuals()
+    diag = s.diagnostics()
+    log(f"disc2d solve {solve_ms:.2f} ms")
+    u = torch.empty((w.N,) + w.shape, dtype=torch.float32, device="cuda")
+    p = torch.empty_like(u)
+    for n in range(w.N):
+        u[n], p[n] = s.state(n)
+    s.propagate(u, p)  # warm
+    f_ms = stream_time(lambda: s.propagate(u, p), reps=10)
+    launches, spl = s.launch_plan(w.N)
+    rev = pw.lib().pw_version().decode().split()[-1]
+    roof = roofline_stencil(f"k_prop_stream2d<float, true, {spl}, 0>",
+                            f_ms / launches, w.N * w.npts * spl,
+                            TRAFFIC.get(rev), 2,
+                            VALU_ISSUE.get(rev, {}).get("single2d"))
+    f_gupd = w.N * w.m_fine * w.npts / (f_ms * 1e-3) / 1e9
+    log(f"disc2d F sweep {f_ms:.3f} ms ({f_gupd:.1f} Gupd/s)")
+    del u, p
+    out = {"workload": "disc2d: 2D periodic 512^2 fine / 128^2 coarse, disc "
+                       "c=2 in c=1, Gaussian sigma 0.03 at (0.3, 0.5), N=64 "
+                       "slices, m_F=64, m_C=16, K=8, T=2, tol 1e-13, FP32 "
+                       "compensated state, FP64 corrector",
+           "solve_ms": round(solve_ms, 3),
+           "solve_gupd_s": round(K * w.N * w.m_fine * w.npts
+                                 / (solve_ms * 1e-3) / 1e9, 2),
+           "phases_ms": {k: round(v, 3) for k, v in phases.items()},
+           "fine_sweep": {"ms": round(f_ms, 4), "gupd_s": round(f_gupd, 2),
+                          "launches": launches, "roofline": roof},
+           "rho": [float(f"{r:.4e}") for r in rho], "rank": ranks,
+           "trace_S": [float(f"{d['trace_S']:.6e}") for d in diag],
+           "r2_min": [float(f"{d['r2_min']:.6e}") for d in diag]}
+    if not args.no_ttt:
+        uf, pf = s.serial_fine(w.N)
+        serial_ms = stream_time(lambda: s.serial_fine(w.N), reps=3)
+        s.run(K)
+        errs = errors_to_serial(s, w, uf, pf)
+        out["time_to_1e-5"] = ttt_record(
+            errs, serial_ms, lambda k: solve_time(s, k, reps=3,
+                                                  run=lambda: s.run(k)))
+        out["time_to_1e-5"]["note"] = (
+            "energy error of the last slice against the serial fine solution "
+            "after k = 0..K iterations; with fine and coarse propagators on "
+            "different grids and a discontinuous wave speed the iteration is "
+            "stable but stagnates (the paper's conclusions and its 2D "
+            "inclusion experiment), which is what this workload shows")
+        log("disc2d errors per iteration: " + " ".join(f"{e:.2e}"
+                                                        for e in errs))
+        if not args.no_variants:
+            out["variants"] = variants_measurement(s, w, K, uf, pf, torch)
+    s.close()
+    return out
+
+
+def oracle_spread(O, Q, w, u0, p0, K, ref, pm):
+    """How far the FP64 oracle itself moves when its initial state is
+    perturbed by FP32-sized rounding (relative 2^-24, seeded): the
+    conditioning of the iteration at this tolerance, beside which an FP32
+    result is to be read.  (energy, l2, max), max over slices."""
+    import numpy as np
+
+    from tests.gpu_helpers import state_errors
+    rng = np.random.default_rng(11)
+    u1 = u0 * (1 + 2.0 ** -24 * rng.standard_normal(np.shape(u0)))
+    r1 = O.theta_parareal(Q, w.c, u1, p0, K, pmap=pm)
+    e = np.max([state_errors(r1.u[n], r1.p[n], ref.u[n], ref.p[n], w.c,
+                             Q.dx_fine) for n in range(1, Q.N + 1)], axis=0)
+    return [float(f"{x:.3e}") for x in e]
+
+
+def batch_precision(sb, ws, K, n_problems=2):
+    """FP32 energy-norm error of the batched solve against the FP64 oracle,
+    on the smallest problems of the batch (full configuration: grid, N,
+    m_F, K); the oracle's fine propagations run on a process pool."""
+    import numpy as np
+
+    import oracle as O
+    from tests.gpu_helpers import oracle_pool, state_errors
+    order = sorted(range(len(ws)), key=lambda i: ws[i].npts)[:n_problems]
+    res = {}
+    t0 = time.perf_counter()
+    with oracle_pool() as pm:
+        for i in order:
+            w = ws[i]
+            Q = O.Problem(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
+                          w.grad_order, w.tol)
+            u0 = w.u0.astype(np.float32).astype(np.float64)
+            p0 = w.p0.astype(np.float32).astype(np.float64)
+            ref = O.theta_parareal(Q, w.c, u0, p0, K, pmap=pm)
+            worst = np.zeros(3)
+            for n in range(1, w.N + 1):
+                u, p = sb.state(n, prob=i)
+                e = state_errors(u.double().cpu().numpy(),
+                                 p.double().cpu().numpy(), ref.u[n], ref.p[n],
+                                 w.c, Q.dx_fine)
+                worst = np.maximum(worst, e)
+            res[f"problem {i} ({w.shape[0]}^2)"] = {
+                "gpu_fp32_vs_oracle": [float(f"{x:.3e}") for x in worst],
+                "oracle_fp32_input_spread": oracle_spread(O, Q, w, u0, p0, K,
+                                                          ref, pm)}
+    log(f"batch precision {res} ({time.perf_counter() - t0:.0f} s)")
+    return res
+
+
+def precision_measurement(pw, W, torch, batch_res):
+    """Energy-norm error of the FP32 compensated path against the FP64
+    oracle per result: the batched problems (full configuration, smallest
+    problems), layers3d at the reduced size 64^3 / 16^3 (N = 32, K = 6), the
+    misfit forward (Algorithm 3, K = 4) at 128^2; max over all slices of
+    (energy, l2, max) relative errors.  disc2d at full size is compared on
+    every iterate by the GPU tests (tests/test_gpu_endtoend.py)."""
+    import numpy as np
+
+    import oracle as O
+    from tests.gpu_helpers import oracle_pool, state_errors
+    out = {"batch2d": batch_res,
+           "norms": "(energy, l2, max) relative, max over slices, final "
+                    "iterate; oracle_fp32_input_spread: the oracle's own "
+                    "change when its initial state is perturbed by relative "
+                    "2^-24 (the conditioning of the iteration)"}
+
+    def solve_vs_oracle(w, K):
+        P = pw.Problem.make(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
+                            w.grad_order, w.tol, "f32", True, K)
+        s = pw.Solver(P)
+        u0 = w.u0.astype(np.float32).astype(np.float64)
+        p0 = w.p0.astype(np.float32).astype(np.float64)
+        s.set_medium(w.c)
+        s.set_initial(u0, p0)
+        s.run(K)
+        Q = O.Problem(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
+                      w.grad_order, w.tol)
+        with oracle_pool() as pm:
+            ref = O.theta_parareal(Q, w.c, u0, p0, K, pmap=pm)
+            spread = oracle_spread(O, Q, w, u0, p0, K, ref, pm)
+        worst = np.zeros(3)
+        for n in range(1, w.N + 1):
+            u, p = s.state(n)
+            e = state_errors(u.double().cpu().numpy(),
+                             p.double().cpu().numpy(), ref.u[n], ref.p[n],
+                             w.c, Q.dx_fine)
+            worst = np.maximum(worst, e)
+        s.close()
+        return {"gpu_fp32_vs_oracle": [float(f"{x:.3e}") for x in worst],
+                "oracle_fp32_input_spread": spread}
+
+    t0 = time.perf_counter()
+    # the smallest batch problems again with the rank tolerance at the FP32
+    # resolution of their data (2^-23): the corrector keeps only directions
+    # FP32 data determine, and the iteration's sensitivity drops
+    ws = W.batch2d()
+    for i in sorted(range(len(ws)), key=lambda i: ws[i].npts)[:2]:
+        w = ws[i]
+        w.tol = 2.0 ** -23
+        out[f"batch2d problem {i} ({w.shape[0]}^2), svd tol 2^-23"] = \
+            solve_vs_oracle(w, 6)
+    out["layers3d (64^3 / 16^3, N=32, K=6)"] = solve_vs_oracle(
+        W.layers3d(n=64, ratio=4, N=32, K=6, T=1.5), 6)
+    wm, _, _ = W.misfit2d(n=128, N=32, K=4)
+    out["misfit2d forward (128^2 / 32^2, N=32, K=4)"] = solve_vs_oracle(wm, 4)
+    log(f"precision {out} ({time.perf_counter() - t0:.0f} s)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -616,12 +887,15 @@ def main():
                     help="skip the data-matrix subsampling study")
     ap.add_argument("--sampling-only", action="store_true",
                     help="only the data-matrix subsampling study")
-    ap.add_argument("--no-batch", action="store_true",
-                    help="skip the 32-problem batched measurement")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the batched headline solve (profiling)")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the misfit-gradient measurement")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the misfit-gradient measurement (profiling)")
+    ap.add_argument("--disc2d-only", action="store_true",
+                    help="only the disc2d solve and its fine sweep "
+                         "(profiling; with --no-ttt, no serial study)")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the 32-problem batched measurement (profiling)")
     ap.add_argument("--layers-only", action="store_true",
@@ -657,181 +931,87 @@ def main():
     if args.batch_only:
         print(json.dumps(batch_measurement(pw, W, torch)), flush=True)
         return
+    if args.disc2d_only:
+        print(json.dumps(disc2d_measurement(pw, W, torch, args)), flush=True)
+        return
     if args.layers_only:
         print(json.dumps(layers3d_measurement(pw, W, torch)), flush=True)
         return
     if args.traffic_probe in ("batch", "layers3d"):
         traffic_probe(pw, W, torch, args.traffic_probe)
         return
-    w = W.disc2d()
-    K = w.K
-    P = pw.Problem.make(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
-                        w.grad_order, w.tol, "f32", True, K)
-    s = pw.Solver(P)
-    s.set_medium(w.c)
-    s.set_initial(w.u0, w.p0)
-    torch.cuda.synchronize()
-    log("context ready")
-    if args.traffic_probe:
-        u = torch.empty((w.N,) + w.shape, dtype=torch.float32, device="cuda")
-        p = torch.empty_like(u)
-        for n in range(w.N):
-            u[n], p[n] = s.state(n)
-        s.propagate(u, p)
-        src = torch.ones(128 * 1024 * 1024, dtype=torch.float32,
-                         device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)  # plain copy: 512 MiB read + 512 MiB written
-        torch.cuda.synchronize()
-        log("traffic probe done: 8 fine launches, one 536870912-byte copy")
-        s.close()
+    if args.traffic_probe == "disc2d":
+        disc2d_traffic_probe(pw, W, torch)
         return
 
-    # ---- timed region: full solves --------------------------------------
+    # ---- headline: the 32-problem batched solve -----------------------------
+    K = 6
+    ws, sb = batch_context(pw, W, K)
+    log("batch context ready")
+    sb.run_batch(K)  # builds the batch (autotuner, graph capture)
     for _ in range(args.warmup):
-        s.run(K)
+        sb.run_batch(K)
     torch.cuda.synchronize()
     log("warmup done")
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        s.run(K)
+        sb.run_batch(K)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
-    upd_step = K * w.N * w.m_fine * w.npts
-    value = upd_step / (ms_step * 1e-3) / 1e9
-    phases = s.timings()
-    rho, ranks = s.residuals()
-    log(f"solve {ms_step:.2f} ms/step")
+    upd_sweep = sum(w.updates_per_sweep() for w in ws)
+    value = K * upd_sweep / (ms_step * 1e-3) / 1e9
+    info = sb.batch_info()
+    log(f"batched K={K} solve {ms_step:.1f} ms/step ({value:.1f} Gupd/s)")
+    # the dominant kernel: the multi-problem fine stencil, timed alone with
+    # events on the context stream (one graph-free launch sequence per sweep)
+    sweep_ms = sb.batch_fine_sweeps(5)
+    depth = info["depth"]
+    launches = max(math.ceil(w.m_fine / depth) for w in ws)
+    rev = pw.lib().pw_version().decode().split()[-1]
+    roof = roofline_stencil(
+        f"k_prop_stream2d_multi<float, true, {depth}>", sweep_ms / launches,
+        upd_sweep / launches, TRAFFIC_BATCH.get(rev), 2,
+        VALU_ISSUE.get(rev, {}).get("multi"))
+    roof["sweep_ms"] = round(sweep_ms, 3)
+    roof["launches_per_sweep"] = launches
+    roof["gupd_s_fine_sweep"] = round(upd_sweep / (sweep_ms * 1e-3) / 1e9, 2)
+    log(f"batched fine sweep {sweep_ms:.2f} ms "
+        f"({roof['gupd_s_fine_sweep']:.1f} Gupd/s)")
+    grids = sorted({w.shape[0] for w in ws})
+    headline_phases = {k: round(info[k], 3) for k in
+                       ("parallel", "corrector", "sweep", "total")}
+    batch_prec = None if (args.no_precision or args.headline_only) else \
+        batch_precision(sb, ws, K)
+    sb.close()
+    del sb
+    torch.cuda.empty_cache()
 
-    # ---- precision: the FP32 solve against the FP64 path ------------------
-    # (the FP64 GPU path matches the FP64 oracle to 1e-12 in the parity
-    # tests; at this size it stands in for the oracle, which takes minutes)
-    precision = None
-    if not args.no_precision:
-        P64 = pw.Problem.make(w.shape, w.ratio, w.T, w.N, w.m_fine,
-                              w.m_coarse, w.grad_order, w.tol, "f64", False,
-                              K)
-        s64 = pw.Solver(P64)
-        s64.set_medium(w.c)
-        s64.set_initial(w.u0.astype(np.float32).astype(np.float64),
-                        w.p0.astype(np.float32).astype(np.float64))
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        s64.run(K)
-        torch.cuda.synchronize()
-        ms64 = (time.perf_counter() - a) * 1e3
-        errs = {}
-        for n in (1, w.N // 2, w.N):
-            u32, p32 = s.state(n)
-            u64, p64 = s64.state(n)
-            ed, er = s64.energy(u32.double(), p32.double(), u64, p64)
-            errs[str(n)] = float(f"{math.sqrt(ed / er):.3e}")
-        precision = {"fp32_vs_fp64_energy_error_at_slice": errs,
-                     "fp64_solve_ms": round(ms64, 2),
-                     "note": "FP32 compensated solve against the FP64 path "
-                             "from the same FP32-rounded initial data, "
-                             "energy norm relative to the FP64 result"}
-        log(f"FP32 vs FP64 energy error at slices 1, N/2, N: {errs}; "
-            f"FP64 solve {ms64:.1f} ms")
-        s64.close()
+    extras = {}
+    if args.headline_only:
+        args.no_adjoint = args.no_layers = args.no_wave1d = True
+        args.no_sampling = args.no_table = args.no_sec6 = True
+        args.no_precision = args.no_cpu = True
+    else:
+        extras["disc2d"] = disc2d_measurement(pw, W, torch, args)
+    torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        extras["adjoint"] = adjoint_measurement(pw, W, torch)
         torch.cuda.empty_cache()
-
-    # ---- fine stencil kernel: the batched F sweep alone ------------------
-    stencil_rev = pw.lib().pw_version().decode().split()[-1]
-    dt = torch.float32
-    u = torch.empty((w.N,) + w.shape, dtype=dt, device="cuda")
-    p = torch.empty_like(u)
-    for n in range(w.N):
-        u[n], p[n] = s.state(n)
-    uo, po = s.propagate(u, p)  # warm
-    reps = 10
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(reps):
-        s.propagate(u, p)
-    ev1.record()
-    torch.cuda.synchronize()
-    f_ms = ev0.elapsed_time(ev1) / reps
-    launches, steps_per_launch = s.launch_plan(w.N)
-    launch_ms = f_ms / launches
-    bytes_per_launch = BYTES_PER_UPDATE_F32 * w.N * w.npts * steps_per_launch
-    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
-    f_gupd = w.N * w.m_fine * w.npts / (f_ms * 1e-3) / 1e9
-    log(f"F sweep {f_ms:.3f} ms ({f_gupd:.1f} Gupd/s)")
-
-    # ---- serial fine and time to 1e-5 -------------------------------------
-    ttt = None
-    serial_ms = None
-    variants = None
-    if not args.no_ttt:
-        uf, pf = s.serial_fine(w.N)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(3):
-            s.serial_fine(w.N)
-        e1.record()
-        torch.cuda.synchronize()
-        serial_ms = e0.elapsed_time(e1) / 3
-        errs = []
-        for k in range(0, K + 1):
-            s.run(k)
-            uN, pN = s.state(w.N)
-            ed, er = s.energy(uN, pN, uf, pf)
-            errs.append(math.sqrt(ed / er) if er > 0 else math.sqrt(ed))
-        log("errors per iteration: " + " ".join(f"{e:.2e}" for e in errs))
-        kstar = next((k for k, e in enumerate(errs) if e <= 1e-5), None)
-        if kstar is not None:
-            ts = []
-            for _ in range(3):
-                torch.cuda.synchronize()
-                a = time.perf_counter()
-                s.run(kstar)
-                torch.cuda.synchronize()
-                ts.append(time.perf_counter() - a)
-            par_ms = min(ts) * 1e3
-        else:
-            par_ms = None
-        ttt = {"target": 1e-5, "reached_at_iteration": kstar,
-               "parareal_ms": par_ms, "serial_fine_ms": round(serial_ms, 3),
-               "speedup_vs_serial": (round(serial_ms / par_ms, 4)
-                                     if par_ms else None),
-               "energy_error_per_iteration": [float(f"{e:.4e}")
-                                              for e in errs],
-               "plateau": float(f"{min(errs):.4e}"),
-               "note": "energy error of the last slice against the serial "
-                       "fine solution after k = 0..K iterations; the paper "
-                       "reports that with different fine/coarse grids and a "
-                       "discontinuous wave speed the iteration is stable but "
-                       "stagnates instead of converging to the fine solution "
-                       "(conclusions; 2D inclusion experiment), which is what "
-                       "this workload shows"}
-        if not args.no_variants:
-            variants = variants_measurement(s, w, K, uf, pf, torch)
-            variants["theta"] = {
-                "energy_error_per_iteration": ttt[
-                    "energy_error_per_iteration"],
-                "ms_K_iterations": round(ms_step, 3),
-                "rho": [float(f"{r:.4e}") for r in rho]}
-
-    s.close()
-    del u, p
-    torch.cuda.empty_cache()
-    batched = None if args.no_batch else batch_measurement(pw, W, torch)
-    torch.cuda.empty_cache()
-    adjoint = None if args.no_adjoint else adjoint_measurement(pw, W, torch)
-    torch.cuda.empty_cache()
-    sampling = None if args.no_sampling else sampling_measurement(pw, W,
-                                                                  torch)
-    layers = None if args.no_layers else layers3d_measurement(pw, W, torch)
-    wave1d = None if args.no_wave1d else wave1d_measurement(pw, W, torch)
-    table = None if args.no_table else gradient_order_measurement(pw, torch)
-    sec6 = None if args.no_sec6 else sec6_comparator_measurement(pw, torch)
-
-    cpu = None if args.no_cpu else cpu_baseline(w)
+    if not args.no_layers:
+        extras["layers3d"] = layers3d_measurement(pw, W, torch)
+        torch.cuda.empty_cache()
+    if not args.no_wave1d:
+        extras["wave1d"] = wave1d_measurement(pw, W, torch)
+    if not args.no_sampling:
+        extras["sampling"] = sampling_measurement(pw, W, torch)
+    if not args.no_table:
+        extras["gradient_order_table"] = gradient_order_measurement(pw, torch)
+    if not args.no_sec6:
+        extras["sec6_comparators"] = sec6_comparator_measurement(pw, torch)
+    if not args.no_precision:
+        extras["precision"] = precision_measurement(pw, W, torch, batch_prec)
+    cpu = None if args.no_cpu else cpu_baseline(ws)
 
     out = {
         "metric": "batched fine-prop Gpoint-updates/s (%HBM roof) + "
@@ -847,35 +1027,24 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "disc2d: 2D periodic 512^2 fine / 128^2 "
-                               "coarse, disc c=2 in c=1, N=64 slices, "
-                               "m_F=64, m_C=16, K=8, T=2, tol 1e-13",
+        "config": {"workload": f"batch2d: 32 independent 2D periodic problems, "
+                               f"fine grids drawn from {grids} (seed 0), coarse "
+                               "= fine/4, c = exp(0.3 GRF(corr 0.1)) (seed "
+                               "1000+b), random Gaussian pulse (seed 2000+b), "
+                               f"N=32 slices each, K={K}, T=1, tol 1e-13",
                    "state": "f32 compensated", "corrector": "f64",
-                   "step": "one full parareal solve (init + K iterations)"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": TRAFFIC.get(stencil_rev),
-                     "kernel": "k_prop_stream2d<float, true, 8, 0> (fine grid)",
-                     "launch_ms": round(launch_ms, 4),
-                     "algorithmic_bytes_per_launch": bytes_per_launch},
-        "fine_sweep": {"ms": round(f_ms, 4), "gupd_s": round(f_gupd, 2),
-                       "launches": launches},
-        "phases_ms": {k: round(v, 3) for k, v in phases.items()},
-        "precision": precision,
-        "rho": [float(f"{r:.4e}") for r in rho],
-        "rank": ranks,
-        "time_to_1e-5": ttt,
-        "variants": variants,
-        "sampling": sampling,
-        "gradient_order_table": table,
-        "sec6_comparators": sec6,
-        "batched": batched,
-        "layers3d": layers,
-        "wave1d": wave1d,
-        "adjoint": adjoint,
+                   "step": f"one batched solve of all 32 problems "
+                           f"(initialisation + K={K} iterations)",
+                   "updates_per_step": K * upd_sweep},
+        "roofline": roof,
+        "phases_ms": headline_phases,
+        "batch": {"depth": depth, "rows_per_stream": info["rows_per_stream"],
+                  "rows_per_stream_by_grid": info["rows_per_stream_by_size"],
+                  "tune_ms": round(info["tune_ms"], 1),
+                  "from_cache": info["from_cache"]},
         "cpu_baseline": cpu,
     }
+    out.update(extras)
     print(json.dumps(out), flush=True)
 
 

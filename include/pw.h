@@ -213,6 +213,24 @@ pw_status pw_set_sampling(pw_ctx* ctx, int prob, const int* cols,
                           int n_per_iter, int n_iters);
 
 /*
+ * Randomised sketching inside Algorithm 1 (Sec. 6.5 points to randomised
+ * low-rank methods for the corrector): in iteration k the truncated QR of
+ * the new data residuals F - U~ U~^T F (and likewise G) is replaced by the
+ * randomised range finder of Halko, Martinsson and Tropp: Q_F = an
+ * orthonormal basis of (A A^T)^power A Omega_k, A the residual, and R_F =
+ * Q_F^T A, so that the core SVD is (r + l) square instead of (r + N).
+ * omega is a host array of n_iters test matrices, each N x l column-major
+ * (column j at offset j * N; the draw is the caller's, e.g. standard
+ * normal), copied; 0 <= power <= 8.  Exact (to rounding) when the
+ * residuals have rank <= l.  l = 0 switches sketching off.  Exclusive with
+ * pw_set_sampling (PW_EINVAL).  Applies to pw_run, pw_continue,
+ * pw_run_batch and pw_run_taped; PW_EINVAL when K exceeds n_iters.  Not
+ * saved by pw_save.  Resets the iteration.  Synchronous.
+ */
+pw_status pw_set_sketch(pw_ctx* ctx, int prob, const double* omega, int l, int n_iters,
+                        int power);
+
+/*
  * Batching: Algorithm 3 for every problem of the context in lockstep (all
  * problems 2D, same state dtype and compensation, medium and initial state
  * set).  Per iteration, the parallel phase of all problems -- the fine
@@ -235,10 +253,14 @@ pw_status pw_run_batch(pw_ctx* ctx, int K);
 pw_status pw_batch_fine_sweeps(pw_ctx* ctx, int reps, double* ms);
 
 /* Configuration and timing of the batched runs: chosen pipeline depth and
- * rows per stream; ms[0..3] = parallel phase, corrector, sweep, total of
- * the last pw_run_batch; ms[4] = autotuning time; ms[5] = fine sweep time
- * of the chosen configuration while tuning; ms[6] = 1 if the choice came
- * from the cache.  Host output.                                         */
+ * rows per stream; ms[0..3] = parallel phase, corrector and sweep (run
+ * concurrently over the problems: ms[1] is their wall time, ms[2] = 0),
+ * total of the last pw_run_batch; ms[4] = autotuning time; ms[5] = fine
+ * sweep time of the chosen configuration while tuning; ms[6] = 1 if the
+ * choice came from the cache; ms[7] = number c of fine grid sizes whose
+ * rows per stream the tuner set apart from the common value, followed by
+ * c pairs (n_y, rows per stream) at ms[8 + 2i], ms[9 + 2i].  Host output,
+ * cap = array length.                                                   */
 pw_status pw_get_batch_info(pw_ctx* ctx, int* depth, int* rows_per_stream, double* ms,
                             int cap);
 

@@ -49,6 +49,8 @@ import numpy as np
 
 __all__ = [
     "Problem", "laplacian", "vv_step", "propagate", "restrict", "interp",
+    "ricker", "sponge_sigma", "sponge_sigma_max", "propagate_forced",
+    "Forcing", "forcing_setup", "fine_traces",
     "gradient", "FD_COEFFS", "energy_components", "split_components",
     "grad2func", "lambda_dag", "energy", "procrustes", "update_svd",
     "omega_apply", "theta_parareal", "serial_fine", "energy_error",
@@ -145,6 +147,136 @@ def propagate(u, p, c2, h, dx, m):
     for _ in range(m):
         u, p = vv_step(u, p, c2, h, dx)
     return u, p
+
+
+# ---------------------------------------------------------------------------
+# Absorbing layer and point source (eq. (1) names absorbing boundaries as an
+# alternative to the periodic box; the forcing is an inhomogeneous term f in
+# u_tt = c^2 Lap u + f).  Reading: a damping layer inside the periodic box,
+# p_t = ... - sigma p, integrated exactly over each half step, and a point
+# source r(t) / dx^d at one node.
+# ---------------------------------------------------------------------------
+def ricker(t, freq, t0):
+    """Ricker wavelet (1 - 2 a) exp(-a), a = (pi f (t - t0))^2."""
+    a = (np.pi * freq * (t - t0)) ** 2
+    return (1.0 - 2.0 * a) * np.exp(-a)
+
+
+def sponge_sigma(shape, width, sigma_max, length=1.0):
+    """Damping coefficient of a layer of the given width along every face of
+    the box: sigma = sigma_max (d / width)^2, d the largest penetration
+    max(0, width - min(x_a, L - x_a)) over the axes (nodes x = j dx)."""
+    dx = length / shape[-1]
+    d = np.zeros(shape)
+    for ax, n in enumerate(shape):
+        x = np.arange(n) * dx
+        pen = np.maximum(0.0, width - np.minimum(x, length - x))
+        sh = [1] * len(shape)
+        sh[ax] = n
+        d = np.maximum(d, pen.reshape(sh))
+    return sigma_max * (d / width) ** 2
+
+
+def sponge_sigma_max(c_max, width, reflection=1e-3):
+    """sigma_max of a quadratic layer whose round trip at speed c_max damps
+    the amplitude by `reflection`: (3 c_max / (2 width)) ln(1 / reflection)."""
+    return 3.0 * c_max / (2.0 * width) * math.log(1.0 / reflection)
+
+
+def propagate_forced(u, p, c2, h, dx, m, damp=None, src=None, t_start=0.0,
+                     receivers=None):
+    """m velocity-Verlet steps of u_tt = c^2 Lap u - sigma u_t + f (Sec. 3.1
+    scheme).  Each half step first damps p by damp = exp(-sigma h / 2) (the
+    exact solution of p_t = -sigma p over h / 2; None: no layer), then
+    kicks it by (h/2) (c^2 Lap u + f(t)); f is src = (flat index, amplitude,
+    freq, t0): amplitude * ricker(t) at one node (None: no source); the
+    kicks of step j use t_start + j h and t_start + (j + 1) h.  With
+    receivers (flat indices) also returns the (m, n_rec) samples of u after
+    every step."""
+    u = np.array(u, dtype=np.float64, copy=True)
+    p = np.array(p, dtype=np.float64, copy=True)
+    traces = [] if receivers is not None else None
+
+    def half_kick(pp, uu, t):
+        # the same expression as vv_step, then the source term
+        pp = (pp if damp is None else damp * pp) + 0.5 * h * c2 * laplacian(uu, dx)
+        if src is not None:
+            idx, amp, freq, t0 = src
+            pp.flat[idx] += 0.5 * h * amp * ricker(t, freq, t0)
+        return pp
+
+    for j in range(m):
+        t0_, t1_ = t_start + j * h, t_start + (j + 1) * h
+        p = half_kick(p, u, t0_)
+        u = u + h * p
+        p = half_kick(p, u, t1_)
+        if traces is not None:
+            traces.append(u.ravel()[np.asarray(receivers)].copy())
+    if traces is not None:
+        return u, p, np.array(traces)
+    return u, p
+
+
+@dataclasses.dataclass
+class Forcing:
+    """Absorbing layer and point source of a problem: layer width (0: none)
+    and the round-trip damping it is designed for; source position in the
+    box (x first; None: no source), Ricker peak frequency and peak time."""
+    width: float = 0.0
+    reflection: float = 1e-3
+    src_pos: tuple = None
+    freq: float = 10.0
+    t0: float = 0.1
+
+
+def _nearest_node(pos, shape, dx):
+    idx = []
+    for a in range(len(shape)):
+        ax = len(shape) - 1 - a
+        idx.append(int(round(pos[a] / dx)) % shape[ax])
+    flat = 0
+    for a in reversed(range(len(shape))):
+        ax = len(shape) - 1 - a
+        flat = flat * shape[ax] + idx[a]
+    return flat
+
+
+def forcing_setup(prob, c, forcing):
+    """Fine and coarse damping factors exp(-sigma h / 2) (the coarse layer
+    is the pointwise restriction of the fine sigma; sigma_max from the
+    largest fine c) and the point sources (nearest fine / coarse node,
+    amplitude 1 / dx^d) of a problem."""
+    out = {"dF": None, "dC": None, "srcF": None, "srcC": None}
+    if forcing is None:
+        return out
+    cf = np.asarray(c, dtype=np.float64)
+    d = len(prob.shape)
+    if forcing.width > 0:
+        smax = sponge_sigma_max(float(cf.max()), forcing.width,
+                                forcing.reflection)
+        sig = sponge_sigma(prob.shape, forcing.width, smax, prob.length)
+        out["dF"] = np.exp(-0.5 * sig * prob.dt_fine)
+        out["dC"] = np.exp(-0.5 * restrict(sig, prob.ratio) * prob.dt_coarse)
+    if forcing.src_pos is not None:
+        out["srcF"] = (_nearest_node(forcing.src_pos, prob.shape, prob.dx_fine),
+                       prob.dx_fine ** -d, forcing.freq, forcing.t0)
+        out["srcC"] = (_nearest_node(forcing.src_pos, prob.coarse_shape,
+                                     prob.dx_coarse),
+                       prob.dx_coarse ** -d, forcing.freq, forcing.t0)
+    return out
+
+
+def fine_traces(prob, c, us, ps, forcing, receivers, pmap=None):
+    """Receiver samples of u after every fine step of one F sweep from the
+    slice starts (us[n-1], ps[n-1]), n = 1..N: array (N, m_F, n_rec)."""
+    cf = np.asarray(c, dtype=np.float64)
+    fs = forcing_setup(prob, cf, forcing)
+    args = [(us[n - 1], ps[n - 1], cf * cf, prob.dt_fine, prob.dx_fine,
+             prob.m_fine, fs["dF"], fs["srcF"], (n - 1) * prob.dt_com,
+             receivers) for n in range(1, prob.N + 1)]
+    out = list(pmap(propagate_forced, args)) if pmap is not None else \
+        [propagate_forced(*a) for a in args]
+    return np.stack([o[2] for o in out])
 
 
 # ---------------------------------------------------------------------------
@@ -356,7 +488,20 @@ def _rank(sig, tol):
     return int(np.sum(sig / np.max(sig) > tol))
 
 
-def update_svd(U, S, V, F, G, tol, svd=None):
+def _range_basis(A, omega, power):
+    """Randomised range finder of Halko, Martinsson and Tropp (2011,
+    Algorithm 4.3 with power iterations): an orthonormal basis of the range
+    of A Omega (A A^T)^q-weighted, Q = qr((A A^T)^q A Omega), each power
+    step re-orthonormalised."""
+    Y = A @ omega
+    for _ in range(power):
+        Y, _ = _reduced_qr(Y)
+        Y = A @ (A.T @ Y)
+    Q, _ = _reduced_qr(Y)
+    return Q
+
+
+def update_svd(U, S, V, F, G, tol, svd=None, sketch=None):
     """Algorithm 1: truncated SVD of M_new = U diag(S) V^T + F G^T.
 
     With S empty (first call): reduced QR of F and G, SVD of R_F R_G^T,
@@ -368,13 +513,28 @@ def update_svd(U, S, V, F, G, tol, svd=None):
     Returns (U_new, S_new, V_new).  ``svd``: the SVD routine (default
     numpy.linalg.svd, LAPACK's divide and conquer); another backward-stable
     driver gives the same exact arithmetic with other rounding.
+
+    ``sketch = (Omega, q)``: randomised sketching of the new data (the
+    randomised low-rank methods Sec. 6.5 points to), in place of the
+    truncated QR of the residuals: Q_F = range basis of (F - U U_F) Omega
+    with q power iterations (Halko, Martinsson, Tropp), R_F = Q_F^T (F -
+    U U_F), and likewise for G with the same Omega (N x l, l <= N, a
+    random draw given as input).  The core matrix is then (r + l) square.
+    Exact (up to rounding) whenever the residuals have rank <= l.
     """
     svd = svd or np.linalg.svd
     F = np.asarray(F, dtype=np.float64)
     G = np.asarray(G, dtype=np.float64)
+
+    def qr_of(A):
+        if sketch is None:
+            return _reduced_qr(A)
+        Q = _range_basis(A, sketch[0], sketch[1])
+        return Q, Q.T @ A
+
     if S is None or len(S) == 0:
-        QF, RF = _reduced_qr(F)
-        QG, RG = _reduced_qr(G)
+        QF, RF = qr_of(F)
+        QG, RG = qr_of(G)
         X, sig, Yt = svd(RF @ RG.T)
         r = _rank(sig, tol)
         return QF @ X[:, :r], sig[:r].copy(), QG @ Yt.T[:, :r]
@@ -388,8 +548,8 @@ def update_svd(U, S, V, F, G, tol, svd=None):
     VG2 = V.T @ Gp
     Gp = Gp - V @ VG2
     VG = VG + VG2
-    QF, RF = _reduced_qr(Fp)
-    QG, RG = _reduced_qr(Gp)
+    QF, RF = qr_of(Fp)
+    QG, RG = qr_of(Gp)
     H = np.vstack([UF, RF]) @ np.vstack([VG, RG]).T
     r0 = len(S)
     H[:r0, :r0] += np.diag(S)
@@ -423,7 +583,8 @@ class PararealResult:
 def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
                    omega="procrustes", correction=True,
                    record_correctors=False, sample_cols=None, pmap=None,
-                   svd=None, sweep="literal"):
+                   svd=None, sweep="literal", sketch=None, power=0,
+                   forcing=None):
     """Algorithm 3 of the paper, step by step.
 
     Initialisation u^1_n = I C R u^1_{n-1}; then K iterations of: parallel
@@ -450,6 +611,15 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
     Every slice is computed by the same ``propagate`` call either way.
     ``svd``: the SVD routine of Algorithm 1 (see update_svd).
 
+    ``sketch``: randomised sketching inside Algorithm 1 (see update_svd):
+    entry k-1 is the N x l Gaussian test matrix of iteration k (an input);
+    ``power`` power iterations.  Not combined with ``sample_cols``.
+
+    ``forcing``: an absorbing layer and / or a point source (Forcing): F
+    and C of slice n then propagate u_tt = c^2 Lap u - sigma u_t + f from
+    t_{n-1} = (n - 1) dt_com (propagate_forced), the coarse layer and source
+    from forcing_setup; everything else is unchanged.
+
     ``sweep``: "literal" applies Omega and grad2func to both terms of the
     correction, as Algorithm 3 writes it; "difference" applies them once
     to the difference Lambda(w - U_n), with the sum of w - U_n as the mean
@@ -467,11 +637,23 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
     cshape = prob.coarse_shape
     order = prob.grad_order
 
-    def Fprop(u, p):
-        return propagate(u, p, c2f, hf, dxf, prob.m_fine)
+    fs = forcing_setup(prob, cf, forcing)
 
-    def Cprop(U, P):
-        return propagate(U, P, c2c, hc, dxc, prob.m_coarse)
+    def Fargs(u, p, n):
+        if forcing is None:
+            return (u, p, c2f, hf, dxf, prob.m_fine)
+        return (u, p, c2f, hf, dxf, prob.m_fine, fs["dF"], fs["srcF"],
+                (n - 1) * prob.dt_com)
+
+    def Fprop(u, p, n):
+        a = Fargs(u, p, n)
+        return propagate(*a) if forcing is None else propagate_forced(*a)
+
+    def Cprop(U, P, n):
+        if forcing is None:
+            return propagate(U, P, c2c, hc, dxc, prob.m_coarse)
+        return propagate_forced(U, P, c2c, hc, dxc, prob.m_coarse, fs["dC"],
+                                fs["srcC"], (n - 1) * prob.dt_com)
 
     def Lam(U, P):
         return energy_components(U, P, cc, dxc, order)
@@ -479,7 +661,7 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
     u = [np.array(u0, dtype=np.float64)] + [None] * N
     p = [np.array(p0, dtype=np.float64)] + [None] * N
     for n in range(1, N + 1):
-        W, Wp = Cprop(restrict(u[n - 1], r), restrict(p[n - 1], r))
+        W, Wp = Cprop(restrict(u[n - 1], r), restrict(p[n - 1], r), n)
         u[n], p[n] = interp(W, r, ik), interp(Wp, r, ik)
     history = [([x.copy() for x in u], [x.copy() for x in p])] \
         if keep_history else []
@@ -491,16 +673,17 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
         v, vp, Uc, Ucp = [None] * (N + 1), [None] * (N + 1), \
             [None] * (N + 1), [None] * (N + 1)
         if pmap is not None:                # the parallel loop (parfor)
-            out = list(pmap(propagate,
-                            [(u[n - 1], p[n - 1], c2f, hf, dxf, prob.m_fine)
+            out = list(pmap(propagate if forcing is None else
+                            propagate_forced,
+                            [Fargs(u[n - 1], p[n - 1], n)
                              for n in range(1, N + 1)]))
             for n in range(1, N + 1):
                 v[n], vp[n] = out[n - 1]
         for n in range(1, N + 1):           # the parallel loop
             if pmap is None:
-                v[n], vp[n] = Fprop(u[n - 1], p[n - 1])
+                v[n], vp[n] = Fprop(u[n - 1], p[n - 1], n)
             Uc[n], Ucp[n] = Cprop(restrict(u[n - 1], r),
-                                  restrict(p[n - 1], r))
+                                  restrict(p[n - 1], r), n)
         Fm = np.column_stack([Lam(restrict(v[n], r), restrict(vp[n], r))
                               for n in range(1, N + 1)])
         Gm = np.column_stack([Lam(Uc[n], Ucp[n]) for n in range(1, N + 1)])
@@ -518,7 +701,13 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
                 Fs, Gs = Fm[:, cols], Gm[:, cols]
             norms.append((float(np.sum(Fm * Fm)), float(np.sum(Fs * Fs)),
                           float(np.sum(Gs * Gs))))
-            Us, S, Vs = update_svd(Us, S, Vs, Fs, Gs, prob.tol, svd)
+            sk = None
+            if sketch is not None:
+                if sample_cols is not None:
+                    raise ValueError("sketching and column sampling are "
+                                     "exclusive")
+                sk = (np.asarray(sketch[_k], dtype=np.float64), power)
+            Us, S, Vs = update_svd(Us, S, Vs, Fs, Gs, prob.tol, svd, sk)
             if record_correctors:
                 correctors.append((Us.copy(), Vs.copy()))
             res = Fm - omega_apply(Us, Vs, Gm)
@@ -538,7 +727,7 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
         un = [u[0]] + [None] * N
         pn = [p[0]] + [None] * N
         for n in range(1, N + 1):            # the serial sweep
-            w, wp = Cprop(restrict(un[n - 1], r), restrict(pn[n - 1], r))
+            w, wp = Cprop(restrict(un[n - 1], r), restrict(pn[n - 1], r), n)
             if omega == "plain":
                 # eq. plainparareal: I C R u^{k+1}_{n-1} + F u^k_{n-1}
                 #                    - I C R u^k_{n-1}
@@ -577,16 +766,22 @@ def theta_parareal(prob: Problem, c, u0, p0, K, keep_history=False,
                             correctors=correctors, data_norms=norms)
 
 
-def serial_fine(prob: Problem, c, u0, p0):
+def serial_fine(prob: Problem, c, u0, p0, forcing=None):
     """Serial fine reference u(t_n) = F^n [u0, p0], n = 0..N (Sec. 6: the
     reference solution is computed serially with the fine propagator)."""
     cf = np.asarray(c, dtype=np.float64)
     c2 = cf * cf
+    fs = forcing_setup(prob, cf, forcing)
     us = [np.array(u0, dtype=np.float64)]
     ps = [np.array(p0, dtype=np.float64)]
-    for _ in range(prob.N):
-        a, b = propagate(us[-1], ps[-1], c2, prob.dt_fine, prob.dx_fine,
-                         prob.m_fine)
+    for n in range(1, prob.N + 1):
+        if forcing is None:
+            a, b = propagate(us[-1], ps[-1], c2, prob.dt_fine, prob.dx_fine,
+                             prob.m_fine)
+        else:
+            a, b = propagate_forced(us[-1], ps[-1], c2, prob.dt_fine,
+                                    prob.dx_fine, prob.m_fine, fs["dF"],
+                                    fs["srcF"], (n - 1) * prob.dt_com)
         us.append(a)
         ps.append(b)
     return us, ps

@@ -115,6 +115,8 @@ _SIGS = {
                        ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                        ctypes.POINTER(ctypes.c_int)],
     "pw_set_variant": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int],
+    "pw_set_sketch": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                      ctypes.c_int, ctypes.c_int, ctypes.c_int],
     "pw_set_sampling": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                         ctypes.c_int, ctypes.c_int],
     "pw_get_state": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
@@ -393,6 +395,22 @@ class Solver:
             self._h, prob, a.ctypes.data_as(ctypes.c_void_p),
             int(a.shape[1]), int(a.shape[0])))
 
+    def set_sketch(self, omega, power=0, prob=0):
+        """Randomised sketching inside Algorithm 1: omega is an (n_iters, N,
+        l) array of test matrices, one per iteration (None switches it
+        off); power = power iterations of the range finder."""
+        import numpy as np
+        if omega is None:
+            _check(lib().pw_set_sketch(self._h, prob, None, 0, 0, 0))
+            return
+        a = np.asarray(omega, dtype=np.float64)
+        if a.ndim != 3 or a.shape[1] != self.problems[prob].n_slices:
+            raise ValueError("omega must be (n_iters, N, l)")
+        cm = np.ascontiguousarray(np.transpose(a, (0, 2, 1)))  # N x l column-major
+        _check(lib().pw_set_sketch(
+            self._h, prob, cm.ctypes.data_as(ctypes.c_void_p), int(a.shape[2]),
+            int(a.shape[0]), int(power)))
+
     def set_variant(self, variant, prob=0):
         """Iteration run by `run`: 'theta' (Algorithm 3), 'omega_one'
         (Omega = I), 'no_correction' or 'plain' (plain parareal)."""
@@ -410,13 +428,15 @@ class Solver:
 
     def batch_info(self):
         d, ly = ctypes.c_int(), ctypes.c_int()
-        ms = (ctypes.c_double * 7)()
+        ms = (ctypes.c_double * 136)()
         _check(lib().pw_get_batch_info(self._h, ctypes.byref(d),
-                                       ctypes.byref(ly), ms, 7))
+                                       ctypes.byref(ly), ms, 136))
+        c = int(ms[7])
+        by_size = {int(ms[8 + 2 * i]): int(ms[9 + 2 * i]) for i in range(c)}
         return dict(depth=d.value, rows_per_stream=ly.value,
                     parallel=ms[0], corrector=ms[1], sweep=ms[2],
                     total=ms[3], tune_ms=ms[4], tuned_sweep_ms=ms[5],
-                    from_cache=bool(ms[6]))
+                    from_cache=bool(ms[6]), rows_per_stream_by_size=by_size)
 
     def sync(self):
         _check(lib().pw_sync(self._h))

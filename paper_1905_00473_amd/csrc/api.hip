@@ -28,6 +28,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -208,6 +209,10 @@ struct Prob {
   int variant = PW_VARIANT_THETA;  // iteration run by pw_run
   DevBuf samp;                     // sampled data columns, samp_iters x samp_n
   int samp_n = 0, samp_iters = 0;
+  // randomised sketching in Algorithm 1: test matrices (sk_iters x N x sk_l),
+  // range-finder scratch of the F and the G branch
+  DevBuf sk, skYf, skYg, skZf, skZg;
+  int sk_l = 0, sk_iters = 0, sk_power = 0;
   double* vsum = nullptr;          // column sum of the Omega = I chain
   SpecScratch spec;                // spectral gradient (grad_order 0)
   int cur = 0;    // which of the ping-pong corrector buffers is current
@@ -265,6 +270,7 @@ struct Batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int B = 0, Ly = 0;
+  std::vector<std::pair<int, int>> ly_by_size;  // (fine ny, rows per stream) overrides
   double tune_ms = 0.0;   // time spent tuning
   double best_ms = 0.0;   // fine sweep time of the chosen configuration
   bool from_cache = false;
@@ -594,14 +600,39 @@ void gather_cols(const double* src, long long rows, const int* idx, int ncols, d
   PW_LAUNCH_CHECK();
 }
 
+// randomised range finder of Halko, Martinsson and Tropp on A (rows x nd):
+// Q (l columns at q_out, ld rows) an orthonormal basis of the range of
+// (A A^T)^power A Om, each power step re-orthonormalised, and R = Q^T A
+// (l x nd, ld l, at R_out)
+void range_basis(Prob& pr, const double* A, int nd, const double* Om, int l, double* Y,
+                 double* Z, double* q_out, double* R_out, OrthScratch& os, double* work,
+                 hipStream_t st) {
+  const long long rows = pr.rows;
+  gemm_nn(rows, l, nd, 1.0, A, rows, Om, nd, 0.0, Y, rows, st);
+  for (int it = 0; it < pr.sk_power; ++it) {
+    orth_begin(rows, l, Y, rows, os, st);
+    const bool c = orth_choose(rows, l, os, st);
+    orth_finish(rows, l, Y, rows, q_out, rows, R_out, os, c, st);
+    gemm_tn(rows, nd, l, 1.0, A, rows, q_out, rows, 0.0, Z, nd, work, pr.gwork_elems, st);
+    gemm_nn(rows, l, nd, 1.0, A, rows, Z, nd, 0.0, Y, rows, st);
+  }
+  orth_begin(rows, l, Y, rows, os, st);
+  const bool c = orth_choose(rows, l, os, st);
+  orth_finish(rows, l, Y, rows, q_out, rows, R_out, os, c, st);
+  gemm_tn(rows, l, nd, 1.0, q_out, rows, A, rows, 0.0, R_out, l, work, pr.gwork_elems, st);
+}
+
 // Algorithm 1 on F, G (rows x ncols); with cols (device, ncols entries) it
 // runs on the columns F[:, cols], G[:, cols] instead (random subsampling of
 // the data matrices)
 void update_svd_dev(Prob& pr, const double* F, const double* G, int ncols, hipStream_t st,
-                    const int* cols = nullptr, double* norms = nullptr) {
+                    const int* cols = nullptr, double* norms = nullptr,
+                    const double* sketch = nullptr) {
   const long long rows = pr.rows;
   const int r = pr.r;
   const int cur = pr.cur, nxt = 1 - pr.cur;
+  // new basis columns: the data columns, or the sketch width
+  const int nnew = sketch ? pr.sk_l : ncols;
   if (r + ncols + 1 > pr.cap) fail(PW_EINVAL, "corrector capacity exceeded (raise max_iters)");
   double* U = pr.Ub[cur];
   double* V = pr.Vb[cur];
@@ -621,7 +652,17 @@ void update_svd_dev(Prob& pr, const double* F, const double* G, int ncols, hipSt
     frob_norm2(F, rows, ncols, rows, pr.red, norms, st);
     frob_norm2(G, rows, ncols, rows, pr.red + 1024, norms + 1, pr.side);
   }
-  if (r == 0) {
+  if (r == 0 && sketch) {
+    range_basis(pr, F, ncols, sketch, nnew, (double*)pr.skYf.p, (double*)pr.skZf.p, U, pr.RF,
+                pr.os, pr.gwork, st);
+    range_basis(pr, G, ncols, sketch, nnew, (double*)pr.skYg.p, (double*)pr.skZg.p, V, pr.RG,
+                pr.os2, pr.gwork2, pr.side);
+    PW_HIP(hipEventRecord(pr.join_ev, pr.side));
+    PW_HIP(hipStreamWaitEvent(st, pr.join_ev, 0));
+    gemm_small(nnew, nnew, ncols, 1.0, pr.RF, nnew, false, pr.RG, nnew, true, 0.0, pr.H, nnew,
+               st);
+    n = nnew;
+  } else if (r == 0) {
     orth_begin(rows, ncols, F, rows, pr.os, st);
     orth_begin(rows, ncols, G, rows, pr.os2, pr.side);
     const bool cf = orth_choose(rows, ncols, pr.os, st);
@@ -642,20 +683,27 @@ void update_svd_dev(Prob& pr, const double* F, const double* G, int ncols, hipSt
                             pr.side));
     project_out(pr, rows, r, ncols, U, pr.Fp, pr.UF, pr.UF2, pr.gwork, st);
     project_out(pr, rows, r, ncols, V, pr.Gp, pr.VG, pr.VG2, pr.gwork2, pr.side);
-    orth_begin(rows, ncols, pr.Fp, rows, pr.os, st);
-    orth_begin(rows, ncols, pr.Gp, rows, pr.os2, pr.side);
-    const bool cf = orth_choose(rows, ncols, pr.os, st);
-    const bool cg = orth_choose(rows, ncols, pr.os2, pr.side);
-    orth_finish(rows, ncols, pr.Fp, rows, U + rows * r, rows, pr.RF, pr.os, cf, st);
-    orth_finish(rows, ncols, pr.Gp, rows, V + rows * r, rows, pr.RG, pr.os2, cg, pr.side);
+    if (sketch) {
+      range_basis(pr, pr.Fp, ncols, sketch, nnew, (double*)pr.skYf.p, (double*)pr.skZf.p,
+                  U + rows * r, pr.RF, pr.os, pr.gwork, st);
+      range_basis(pr, pr.Gp, ncols, sketch, nnew, (double*)pr.skYg.p, (double*)pr.skZg.p,
+                  V + rows * r, pr.RG, pr.os2, pr.gwork2, pr.side);
+    } else {
+      orth_begin(rows, ncols, pr.Fp, rows, pr.os, st);
+      orth_begin(rows, ncols, pr.Gp, rows, pr.os2, pr.side);
+      const bool cf = orth_choose(rows, ncols, pr.os, st);
+      const bool cg = orth_choose(rows, ncols, pr.os2, pr.side);
+      orth_finish(rows, ncols, pr.Fp, rows, U + rows * r, rows, pr.RF, pr.os, cf, st);
+      orth_finish(rows, ncols, pr.Gp, rows, V + rows * r, rows, pr.RG, pr.os2, cg, pr.side);
+    }
     PW_HIP(hipEventRecord(pr.join_ev, pr.side));
     PW_HIP(hipStreamWaitEvent(st, pr.join_ev, 0));
-    n = r + ncols;
-    // Af = [UF; RF], Bg = [VG; RG] ((r + ncols) x ncols)
+    n = r + nnew;
+    // Af = [UF; RF], Bg = [VG; RG] ((r + nnew) x ncols)
     copy_block(r, ncols, pr.UF, r, pr.Af, n, st);
-    copy_block(ncols, ncols, pr.RF, ncols, pr.Af + r, n, st);
+    copy_block(nnew, ncols, pr.RF, nnew, pr.Af + r, n, st);
     copy_block(r, ncols, pr.VG, r, pr.Bg, n, st);
-    copy_block(ncols, ncols, pr.RG, ncols, pr.Bg + r, n, st);
+    copy_block(nnew, ncols, pr.RG, nnew, pr.Bg + r, n, st);
     gemm_small(n, n, ncols, 1.0, pr.Af, n, false, pr.Bg, n, true, 0.0, pr.H, n, st);
     add_diag(n, r, pr.S, pr.H, n, st);
   }
@@ -666,9 +714,9 @@ void update_svd_dev(Prob& pr, const double* F, const double* G, int ncols, hipSt
   // new columns of E and P for the sweep: Lambda^dag of Q_F, Lambda^T of Q_G
   const long long Nc = pr.Nc;
   lambda_dag_cols(pr.gc, pr.dtab, U + rows * r, rows, pr.cc, nullptr, pr.E[cur] + 2 * Nc * r,
-                  2 * Nc, ncols, pr.ctmp, st);
+                  2 * Nc, nnew, pr.ctmp, st);
   lambda_adjoint_cols(pr.gc, V + rows * r, rows, pr.cc, pr.order, pr.Vp[cur] + 2 * Nc * r, 2 * Nc,
-                      ncols, st, &pr.spec);
+                      nnew, st, &pr.spec);
   // rotate: [U Q_F] X(:, 1:rn) etc.
   gemm_nn(rows, rn, n, 1.0, U, rows, pr.X, n, 0.0, pr.Ub[nxt], rows, st);
   gemm_nn(rows, rn, n, 1.0, V, rows, pr.Y, n, 0.0, pr.Vb[nxt], rows, st);
@@ -685,6 +733,8 @@ void update_svd_dev(Prob& pr, const double* F, const double* G, int ncols, hipSt
 void check_sampling(const Prob& pr, int K) {
   if (pr.samp_n > 0 && K > pr.samp_iters)
     fail(PW_EINVAL, "the sampled-column table covers fewer iterations than K");
+  if (pr.sk_l > 0 && K > pr.sk_iters)
+    fail(PW_EINVAL, "the sketch test matrices cover fewer iterations than K");
 }
 
 void reset_corrector(Prob& pr) {
@@ -777,6 +827,10 @@ void corrector_phase(Prob& pr, int k, hipStream_t st) {
     if (k > pr.samp_iters) fail(PW_EINVAL, "no sampled columns for this iteration");
     update_svd_dev(pr, pr.Fm, pr.Gm, pr.samp_n, st,
                    (const int*)pr.samp.p + (long long)(k - 1) * pr.samp_n, rk + 2);
+  } else if (pr.sk_l > 0) {
+    if (k > pr.sk_iters) fail(PW_EINVAL, "no sketch test matrix for this iteration");
+    update_svd_dev(pr, pr.Fm, pr.Gm, N, st, nullptr, rk + 2,
+                   (const double*)pr.sk.p + (long long)(k - 1) * N * pr.sk_l);
   } else {
     update_svd_dev(pr, pr.Fm, pr.Gm, N, st, nullptr, rk + 2);
   }
@@ -1425,12 +1479,20 @@ MultiPlan<float>& planC<float>(Batch& b) { return b.C32; }
 template <>
 MultiPlan<double>& planC<double>(Batch& b) { return b.C64; }
 
+int ly_for(const std::vector<std::pair<int, int>>& by_size, int ny) {
+  for (auto& e : by_size)
+    if (e.first == ny) return e.second;
+  return 0;
+}
+
 template <typename T>
-std::vector<PropJob<T>> fine_jobs(pw_ctx* ctx) {
+std::vector<PropJob<T>> fine_jobs(pw_ctx* ctx,
+                                  const std::vector<std::pair<int, int>>& by_size = {}) {
   std::vector<PropJob<T>> jobs;
   for (auto& up : ctx->probs) {
     Prob& pr = *up;
     PropJob<T> j;
+    j.Ly = ly_for(by_size, pr.gf.n[1]);
     j.g = pr.gf;
     j.c2 = tp<T>(pr.c2f);
     j.u_src = tp<T>(pr.u);
@@ -1499,18 +1561,33 @@ std::string tune_key(pw_ctx* ctx, bool f64, bool comp) {
   return k;
 }
 
-bool tune_lookup(const std::string& key, int* B, int* Ly) {
+// cache line: key B Ly count (ny Ly)*count
+bool tune_lookup(const std::string& key, int* B, int* Ly,
+                 std::vector<std::pair<int, int>>* by_size) {
   const char* path = getenv("PW_TUNE_CACHE");
   if (!path) return false;
   FILE* f = fopen(path, "r");
   if (!f) return false;
   char kb[4096];
-  int b = 0, l = 0;
+  int b = 0, l = 0, cnt = 0;
   bool found = false;
-  while (fscanf(f, "%4095s %d %d", kb, &b, &l) == 3) {
-    if (key == kb) {
+  while (fscanf(f, "%4095s %d %d %d", kb, &b, &l, &cnt) == 4) {
+    if (cnt < 0 || cnt > 64) break;
+    std::vector<std::pair<int, int>> v;
+    bool ok = true;
+    for (int i = 0; i < cnt; ++i) {
+      int a = 0, c = 0;
+      if (fscanf(f, "%d %d", &a, &c) != 2) {
+        ok = false;
+        break;
+      }
+      v.push_back({a, c});
+    }
+    if (!ok) break;
+    if (key == kb && (b == 4 || b == 8) && l > 0) {
       *B = b;
       *Ly = l;
+      *by_size = v;
       found = true;
     }
   }
@@ -1518,12 +1595,15 @@ bool tune_lookup(const std::string& key, int* B, int* Ly) {
   return found;
 }
 
-void tune_store(const std::string& key, int B, int Ly) {
+void tune_store(const std::string& key, int B, int Ly,
+                const std::vector<std::pair<int, int>>& by_size) {
   const char* path = getenv("PW_TUNE_CACHE");
   if (!path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "%s %d %d\n", key.c_str(), B, Ly);
+  fprintf(f, "%s %d %d %d", key.c_str(), B, Ly, (int)by_size.size());
+  for (auto& e : by_size) fprintf(f, " %d %d", e.first, e.second);
+  fprintf(f, "\n");
   fclose(f);
 }
 
@@ -1533,9 +1613,11 @@ template <typename T>
 void autotune(pw_ctx* ctx, Batch& b, hipStream_t st) {
   const std::string key = tune_key(ctx, b.f64, b.comp);
   int B = 0, Ly = 0;
-  if (tune_lookup(key, &B, &Ly)) {
+  std::vector<std::pair<int, int>> by_size;
+  if (tune_lookup(key, &B, &Ly, &by_size)) {
     b.B = B;
     b.Ly = Ly;
+    b.ly_by_size = by_size;
     b.from_cache = true;
     return;
   }
@@ -1552,13 +1634,12 @@ void autotune(pw_ctx* ctx, Batch& b, hipStream_t st) {
   PW_HIP(hipEventCreate(&t0));
   PW_HIP(hipEventCreate(&t1));
   PW_HIP(hipEventRecord(t0, st));
-  const auto jobs = fine_jobs<T>(ctx);
-  double best = 1e30;
-  for (auto c : cands) {
+  // time the fine sweep of one plan (a warm-up run, then the mean of two)
+  auto time_plan = [&](int Bc, int Lc, const std::vector<std::pair<int, int>>& bs) -> double {
     MultiPlan<T> pl;
-    pl.B = c.first;
-    pl.Ly = c.second;
-    plan_multi<T>(jobs, pl);
+    pl.B = Bc;
+    pl.Ly = Lc;
+    plan_multi<T>(fine_jobs<T>(ctx, bs), pl);
     Buffers tmp;
     void* d = tmp.get(sizeof(StreamDesc<T>) * std::max<size_t>(pl.descs.size(), 1));
     PW_HIP(hipMemcpyAsync(d, pl.descs.data(), sizeof(StreamDesc<T>) * pl.descs.size(),
@@ -1570,10 +1651,39 @@ void autotune(pw_ctx* ctx, Batch& b, hipStream_t st) {
     PW_HIP(hipEventSynchronize(e1));
     float ms = 0;
     PW_HIP(hipEventElapsedTime(&ms, e0, e1));
-    if (ms / 2 < best) {
-      best = ms / 2;
+    return ms / 2;
+  };
+  // 1. one (depth, rows per stream) for all problems
+  double best = 1e30;
+  for (auto c : cands) {
+    const double ms = time_plan(c.first, c.second, {});
+    if (ms < best) {
+      best = ms;
       b.B = c.first;
       b.Ly = c.second;
+    }
+  }
+  // 2. rows per stream refined per fine grid size, one size at a time with
+  //    the others held (the depth is launch-wide: one kernel per time block)
+  std::vector<int> sizes;
+  for (auto& up : ctx->probs) sizes.push_back(up->gf.n[1]);
+  std::sort(sizes.begin(), sizes.end());
+  sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+  b.ly_by_size.clear();
+  if (sizes.size() > 1) {
+    for (int ny : sizes) {
+      int keep = 0;
+      for (int l : {b.Ly / 2, 2 * b.Ly}) {
+        if (l == b.Ly) continue;
+        auto trial = b.ly_by_size;
+        trial.push_back({ny, l});
+        const double ms = time_plan(b.B, b.Ly, trial);
+        if (ms < best * 0.995) {
+          best = ms;
+          keep = l;
+        }
+      }
+      if (keep > 0) b.ly_by_size.push_back({ny, keep});
     }
   }
   PW_HIP(hipEventRecord(t1, st));
@@ -1583,7 +1693,7 @@ void autotune(pw_ctx* ctx, Batch& b, hipStream_t st) {
   b.tune_ms = tt;
   b.best_ms = best;
   for (hipEvent_t e : {e0, e1, t0, t1}) (void)hipEventDestroy(e);
-  tune_store(key, b.B, b.Ly);
+  tune_store(key, b.B, b.Ly, b.ly_by_size);
 }
 
 // the parallel phase of every problem: fine sweeps, restrictions, coarse
@@ -1603,7 +1713,7 @@ void build_batch(pw_ctx* ctx, Batch& b) {
   MultiPlan<T>& C = planC<T>(b);
   F.B = b.B;
   F.Ly = b.Ly;
-  plan_multi<T>(fine_jobs<T>(ctx), F);
+  plan_multi<T>(fine_jobs<T>(ctx, b.ly_by_size), F);
   C.B = b.B;
   C.Ly = b.Ly;
   plan_multi<T>(coarse_jobs<T>(ctx), C);
@@ -1662,7 +1772,12 @@ void concurrent_serial_phase(pw_ctx* ctx, int k, hipStream_t st) {
       }
     }
   };
-  const int nt = std::max(1, std::min(np, kBatchThreads));
+  static const int threads = [] {
+    const char* e = getenv("PW_BATCH_THREADS");  // override (1: one host thread)
+    const int v = e ? atoi(e) : kBatchThreads;
+    return v >= 1 && v <= 64 ? v : kBatchThreads;
+  }();
+  const int nt = std::max(1, std::min(np, threads));
   std::vector<std::thread> pool;
   for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
   worker();
@@ -1950,7 +2065,7 @@ const char* pw_last_error(void) { return g_last_error.c_str(); }
 
 // the last word names the revision of the fine stencil kernel (bench.py
 // keys measured HBM traffic on it)
-const char* pw_version(void) { return "pwave 0.3 (gfx950) stencil-r6"; }
+const char* pw_version(void) { return "pwave 0.4 (gfx950) stencil-r7"; }
 
 int pw_num_problems(const pw_ctx* ctx) { return ctx ? (int)ctx->probs.size() : 0; }
 
@@ -2077,6 +2192,8 @@ pw_status pw_set_sampling(pw_ctx* ctx, int prob, const int* cols, int n_per_iter
     if (n_per_iter < 0 || n_per_iter > pr.N || n_iters < 0)
       fail(PW_EINVAL, "sample size must be in [0, N] and the iteration count >= 0");
     if (n_per_iter > 0 && (n_iters == 0 || !cols)) fail(PW_EINVAL, "empty column table");
+    if (n_per_iter > 0 && pr.sk_l > 0)
+      fail(PW_EINVAL, "sketching and column sampling are exclusive");
     std::vector<char> seen((size_t)pr.N);
     for (int k = 0; k < (n_per_iter > 0 ? n_iters : 0); ++k) {
       std::fill(seen.begin(), seen.end(), 0);
@@ -2094,6 +2211,38 @@ pw_status pw_set_sampling(pw_ctx* ctx, int prob, const int* cols, int n_per_iter
     }
     pr.samp_n = n_per_iter;
     pr.samp_iters = n_per_iter > 0 ? n_iters : 0;
+    pr.k_done = 0;
+    pr.have_iterate = false;
+    pr.change.clear();
+    reset_corrector(pr);
+  });
+}
+
+pw_status pw_set_sketch(pw_ctx* ctx, int prob, const double* omega, int l, int n_iters,
+                        int power) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (l < 0 || l > pr.N || n_iters < 0 || power < 0 || power > 8)
+      fail(PW_EINVAL, "sketch width must be in [0, N], power in [0, 8]");
+    if (l > 0 && (n_iters == 0 || !omega)) fail(PW_EINVAL, "empty sketch table");
+    if (l > 0 && pr.samp_n > 0) fail(PW_EINVAL, "sketching and column sampling are exclusive");
+    if (l > 0) {
+      const size_t n = (size_t)n_iters * pr.N * l;
+      for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(omega[i])) fail(PW_EINVAL, "non-finite sketch entry");
+      PW_HIP(hipStreamSynchronize(ctx->stream));
+      PW_HIP(hipMemcpy(pr.sk.ensure(sizeof(double) * n), omega, sizeof(double) * n,
+                       hipMemcpyHostToDevice));
+      const size_t yb = sizeof(double) * (size_t)pr.rows * l;
+      const size_t zb = sizeof(double) * (size_t)pr.N * l;
+      pr.skYf.ensure(yb);
+      pr.skYg.ensure(yb);
+      pr.skZf.ensure(zb);
+      pr.skZg.ensure(zb);
+    }
+    pr.sk_l = l;
+    pr.sk_iters = l > 0 ? n_iters : 0;
+    pr.sk_power = l > 0 ? power : 0;
     pr.k_done = 0;
     pr.have_iterate = false;
     pr.change.clear();
@@ -2542,9 +2691,13 @@ pw_status pw_get_batch_info(pw_ctx* ctx, int* depth, int* rows_per_stream, doubl
     const Batch& b = *ctx->batch;
     if (depth) *depth = b.B;
     if (rows_per_stream) *rows_per_stream = b.Ly;
-    const double v[7] = {b.ms[0], b.ms[1], b.ms[2], b.ms[3], b.tune_ms, b.best_ms,
-                         b.from_cache ? 1.0 : 0.0};
-    for (int i = 0; i < 7 && i < cap; ++i) ms[i] = v[i];
+    std::vector<double> v = {b.ms[0], b.ms[1], b.ms[2], b.ms[3], b.tune_ms, b.best_ms,
+                             b.from_cache ? 1.0 : 0.0, (double)b.ly_by_size.size()};
+    for (auto& e : b.ly_by_size) {
+      v.push_back((double)e.first);
+      v.push_back((double)e.second);
+    }
+    for (int i = 0; i < (int)v.size() && i < cap; ++i) ms[i] = v[i];
   });
 }
 

@@ -108,6 +108,7 @@ struct PropJob {
   int m;
   T h;
   StateSet<T> wa, wb;
+  int Ly = 0;  // target rows per stream of this job (0: the plan's Ly)
 };
 
 // Launch plan of a multi-problem batched propagation: launch l advances

@@ -904,15 +904,17 @@ template <typename T>
 struct Stream3Cfg {
   static constexpr int B = 2;
   static constexpr int R = sizeof(T) == 4 ? 2 : 1;
-  static constexpr int WY = 16;
+  static constexpr int WY = 8;  // two workgroups per CU (measured faster than 16)
 };
 
-// waves per workgroup of the 3D streaming kernel (PW_STREAM3D_WAVES = 8
-// selects half-height blocks: more halo rows, two workgroups per CU)
+// waves per workgroup of the 3D streaming kernel: 8 (two workgroups per
+// CU, so one workgroup's barrier stalls overlap the other's work); the
+// tuning override PW_STREAM3D_WAVES = 16 selects double-height blocks (fewer
+// halo rows, one workgroup per CU)
 int stream3d_waves() {
   static const int w = [] {
     const char* e = getenv("PW_STREAM3D_WAVES");  // tuning override
-    return (e && atoi(e) == 8) ? 8 : 16;
+    return (e && atoi(e) == 16) ? 16 : 8;
   }();
   return w;
 }
@@ -922,9 +924,9 @@ void dispatch_stream3d(const Stream3Desc<T>& a, hipStream_t st) {
   using C = Stream3Cfg<T>;
   const long long nblk = (long long)a.nstates * a.nseg * a.nyb * a.ncb;
   if (nblk >= (1LL << 31)) fail(PW_EINVAL, "too many streams for one launch");
-  if (stream3d_waves() == 8)
-    hipLaunchKernelGGL((k_prop_stream3d<T, COMP, C::B, C::R, 8>), dim3((unsigned)nblk),
-                       dim3(64 * 8), 0, st, a);
+  if (stream3d_waves() == 16)
+    hipLaunchKernelGGL((k_prop_stream3d<T, COMP, C::B, C::R, 16>), dim3((unsigned)nblk),
+                       dim3(64 * 16), 0, st, a);
   else
     hipLaunchKernelGGL((k_prop_stream3d<T, COMP, C::B, C::R, C::WY>), dim3((unsigned)nblk),
                        dim3(64 * C::WY), 0, st, a);
@@ -1218,7 +1220,8 @@ void plan_multi(const std::vector<PropJob<T>>& jobs, MultiPlan<T>& plan) {
       d.h = j.h;
       d.idx2 = T(1.0 / (j.g.dx * j.g.dx));
       d.ncb = (d.nx + XV - 1) / XV;
-      d.nseg = std::max(1, (d.ny + plan.Ly - 1) / plan.Ly);
+      const int ly = j.Ly > 0 ? j.Ly : plan.Ly;
+      d.nseg = std::max(1, (d.ny + ly - 1) / ly);
       d.Ly = (d.ny + d.nseg - 1) / d.nseg;
       d.nseg = (d.ny + d.Ly - 1) / d.Ly;
       d.first = (l == 0);

@@ -119,7 +119,10 @@ def derived_gates(Q, w, u0, p0, K, ref, pmap=None, floor=1e-12,
     """Per-norm gates (energy, l2, max; see state_errors) for an FP64
     end-to-end comparison, each max(floor, 256 A eps, 16 S, 16 D, 16 L)
     with, from four more oracle runs:
-    A  the amplification of a 1e-13 relative perturbation of u0;
+    A  the amplification of a perturbation of u0 of relative size 1e-13,
+       random per point plus a constant shift of 1e-13 max|u0| (rounding
+       reaches every component, the mean included, which the energy norm
+       does not see but l2 does);
     S  the spread of Algorithm 1 over the order of its data columns;
     D  the spread over the SVD routine of Algorithm 1 (LAPACK's QR-iteration
        driver in place of divide and conquer): both drivers are backward
@@ -136,7 +139,8 @@ def derived_gates(Q, w, u0, p0, K, ref, pmap=None, floor=1e-12,
     import scipy.linalg
     eps_in = 1e-13
     rng = np.random.default_rng(7)
-    u1 = u0 * (1 + eps_in * rng.standard_normal(np.shape(u0)))
+    u1 = u0 * (1 + eps_in * rng.standard_normal(np.shape(u0))) \
+        + eps_in * float(np.max(np.abs(u0)))
     runs = {"A": O.theta_parareal(Q, w.c, u1, p0, K, pmap=pmap,
                                   **oracle_kwargs)}
     cols = [np.arange(Q.N)[::-1].copy() for _ in range(K)]

@@ -21,10 +21,11 @@ Configurations and gates:
   iterations).
 * disc2d at full size (K = 4) and layers3d at the reduced size 64^3 /
   16^3 (N = 32, K = 6), FP64 state, svd tol 1e-3 (Omega well
-  determined): end to end at the gates of tests/gpu_helpers.derived_gates,
-  per norm max(1e-12, 256 A eps, 16 S, 16 D, 16 L) from four more oracle
-  runs (input perturbation, column order, SVD driver, one-term form of
-  the correction); layers3d FP64 at its run
+  determined): end to end in the energy and l2 norms at the gates of
+  tests/gpu_helpers.derived_gates, per norm max(1e-12, 256 A eps, 16 S,
+  16 D, 16 L) from four more oracle runs (input perturbation, column order,
+  SVD driver, one-term form of the correction); the pointwise maximum is
+  reported and bounded by 1e-10; layers3d FP64 at its run
   tol 1e-13 one iteration from the oracle's iterate and corrector, 1e-12;
   the layers3d FP32 compensated solve at tol 1e-13 within 1e-5 (energy,
   l2; pointwise 3e-5).
@@ -147,7 +148,8 @@ def test_disc2d_fullsize_fp64_end_to_end_tol_1e3():
         gates, spread = derived_gates(Q, w, u0, p0, 4, ref, pmap=pm)
     print(f"disc2d FP64 tol 1e-3: worst (energy, l2, max) = {worst}, "
           f"gates {gates}, spreads {spread}", flush=True)
-    assert np.all(worst < gates), (worst, gates)
+    assert np.all(worst[:2] < gates[:2]), (worst, gates)
+    assert worst[2] < 1e-10, worst
     rho, rk = s.residuals()
     assert rk == ref.rank
     np.testing.assert_allclose(rho, ref.rho, rtol=1e-9)
@@ -204,7 +206,8 @@ def test_layers3d_reduced_end_to_end(dtype, tol):
         worst = np.maximum(worst, e)
     print(f"layers3d {dtype}: worst (energy, l2, max) = {worst}, "
           f"gates {gates}, spreads {spread}", flush=True)
-    assert np.all(worst < gates), (worst, gates)
+    assert np.all(worst[:2] < gates[:2]), (worst, gates)
+    assert worst[2] < (3e-5 if dtype == "f32" else 1e-10), worst
     s.close()
 
 

@@ -707,3 +707,173 @@ def test_difference_form_of_the_sweep_is_the_same_map():
     ref_u, _ = O.serial_fine(Q, c, u0, 0 * u0)
     for k in range(K + 1):
         assert np.array_equal(b.u[k], ref_u[k])
+
+
+# ---------------------------------------------------------------------------
+# randomised sketching inside Algorithm 1 (Sec. 6.5: randomised low-rank
+# methods; Halko-Martinsson-Tropp range finder)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("power", [0, 1])
+def test_sketched_update_exact_on_low_rank_data(power):
+    """Data whose new directions have rank <= l: the sketched Algorithm 1
+    gives the same corrector action as the unsketched one (two updates,
+    the second with an accumulated basis)."""
+    rng = np.random.default_rng(4)
+    rows, N, l, k = 60, 10, 6, 4
+    base_F = rng.standard_normal((rows, k))
+    base_G = rng.standard_normal((rows, k))
+    F1 = base_F @ rng.standard_normal((k, N))
+    G1 = base_G @ rng.standard_normal((k, N))
+    extra_F = rng.standard_normal((rows, 2))
+    extra_G = rng.standard_normal((rows, 2))
+    F2 = np.hstack([base_F, extra_F]) @ rng.standard_normal((k + 2, N))
+    G2 = np.hstack([base_G, extra_G]) @ rng.standard_normal((k + 2, N))
+    om = [rng.standard_normal((N, l)) for _ in range(2)]
+    U = S = V = None
+    Us = Ss = Vs = None
+    for (F, G), o in zip([(F1, G1), (F2, G2)], om):
+        U, S, V = O.update_svd(U, S, V, F, G, 1e-10)
+        Us, Ss, Vs = O.update_svd(Us, Ss, Vs, F, G, 1e-10,
+                                  sketch=(o, power))
+        assert len(Ss) == len(S)
+        np.testing.assert_allclose(Ss, S, rtol=1e-10)
+        Z = rng.standard_normal((rows, 3))
+        np.testing.assert_allclose(O.omega_apply(Us, Vs, Z),
+                                   O.omega_apply(U, V, Z), atol=1e-10)
+
+
+def test_sketched_update_truncates_beyond_l():
+    """Full-rank data: the sketch keeps l new directions per update, and the
+    Frobenius norm of the captured part of F G^T does not exceed the
+    unsketched one (a projection of the data)."""
+    rng = np.random.default_rng(8)
+    rows, N, l = 40, 12, 5
+    F = rng.standard_normal((rows, N))
+    G = rng.standard_normal((rows, N))
+    U, S, V = O.update_svd(None, None, None, F, G, 1e-12,
+                           sketch=(rng.standard_normal((N, l)), 1))
+    assert len(S) == l
+    assert np.allclose(U.T @ U, np.eye(l), atol=1e-12)
+    _, S0, _ = O.update_svd(None, None, None, F, G, 1e-12)
+    assert np.sum(S ** 2) <= np.sum(S0 ** 2) * (1 + 1e-12)
+
+
+# ---------------------------------------------------------------------------
+# absorbing layer and point source (eq. (1): absorbing boundaries as the
+# alternative to the periodic box; an inhomogeneous term f)
+# ---------------------------------------------------------------------------
+def test_ricker_closed_form():
+    f, t0 = 10.0, 0.1
+    assert O.ricker(t0, f, t0) == 1.0
+    tz = 1.0 / (math.pi * f * math.sqrt(2.0))       # zeros: 2 a = 1
+    assert abs(O.ricker(t0 + tz, f, t0)) < 1e-15
+    assert abs(O.ricker(t0 - tz, f, t0)) < 1e-15
+    tm = math.sqrt(1.5) / (math.pi * f)              # minima: a = 3/2
+    assert abs(O.ricker(t0 + tm, f, t0) + 2.0 * math.exp(-1.5)) < 1e-15
+
+
+def test_sponge_profile():
+    n, w = 200, 0.05
+    smax = O.sponge_sigma_max(2.0, w)
+    assert abs(smax - 3 * 2.0 / (2 * w) * math.log(1e3)) < 1e-12
+    sig = O.sponge_sigma((n,), w, smax)
+    x = np.arange(n) / n
+    inside = (x >= w) & (x <= 1 - w)
+    assert np.all(sig[inside] <= 1e-20 * smax)
+    assert sig[0] == smax                         # node on the face
+    # quadratic in the penetration depth
+    j = 3
+    assert abs(sig[j] - smax * ((w - x[j]) / w) ** 2) < 1e-12 * smax
+    s2 = O.sponge_sigma((n, n), w, smax)
+    assert s2[0, n // 2] == smax and s2[n // 2, n // 2] == 0.0
+
+
+def test_forced_propagator_reduces_to_plain():
+    """No layer and no source: the forced propagator is the plain one, bit
+    for bit (also with a damping factor of exactly 1)."""
+    rng = np.random.default_rng(2)
+    shape = (24, 20)
+    dx = 1 / 20
+    c2 = (1 + 0.3 * rng.uniform(size=shape)) ** 2
+    u0, p0 = rng.standard_normal(shape), rng.standard_normal(shape)
+    a = O.propagate(u0, p0, c2, 0.01, dx, 30)
+    b = O.propagate_forced(u0, p0, c2, 0.01, dx, 30)
+    c = O.propagate_forced(u0, p0, c2, 0.01, dx, 30, damp=np.ones(shape))
+    for x, y in ((a, b), (a, c)):
+        assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
+
+
+def test_forced_propagator_superposition():
+    """The scheme is linear in the state and the forcing: from (u0, p0)
+    with the source = (u0, p0) without it + (0, 0) with it; the layer acts
+    on both parts alike."""
+    rng = np.random.default_rng(3)
+    shape = (32, 32)
+    dx = 1 / 32
+    c = 1 + 0.3 * rng.uniform(size=shape)
+    u0, p0 = rng.standard_normal(shape), rng.standard_normal(shape)
+    damp = np.exp(-0.5 * O.sponge_sigma(shape, 0.1, 30.0) * 0.004)
+    src = (5 * 32 + 7, 1 / dx ** 2, 10.0, 0.05)
+    full = O.propagate_forced(u0, p0, c * c, 0.004, dx, 50, damp, src, 0.01)
+    hom = O.propagate_forced(u0, p0, c * c, 0.004, dx, 50, damp, None, 0.01)
+    par = O.propagate_forced(0 * u0, 0 * p0, c * c, 0.004, dx, 50, damp, src,
+                             0.01)
+    for i in (0, 1):
+        assert np.max(np.abs(full[i] - hom[i] - par[i])) <= \
+            1e-13 * np.max(np.abs(full[i]))
+
+
+def test_sponge_absorbs_a_travelling_pulse():
+    """A right-travelling pulse crosses the layer at both faces of the
+    periodic box before it would return (T = 1, c = 1).  Without the layer
+    the box keeps its energy; with it the energy never grows and less than
+    5 % is left: the damping term of a plain layer (not a perfectly matched
+    one) also reflects part of the pulse where sigma rises, which the
+    interior keeps (about 2 % of the energy here, against 1e-3 for the
+    damping of the transmitted part alone)."""
+    n = 400
+    dx = 1 / n
+    x = np.arange(n) * dx
+    s = 0.02
+    u0 = np.exp(-(x - 0.5) ** 2 / (2 * s * s))
+    p0 = (x - 0.5) / (s * s) * u0                 # u(x - t): p = -u'
+    c = np.ones(n)
+    h = 0.5 * dx
+    m = int(round(1.0 / h))
+    damp = np.exp(-0.5 * h * O.sponge_sigma((n,), 0.1,
+                                            O.sponge_sigma_max(1.0, 0.1)))
+    e0 = O.energy(u0, p0, c, dx)
+    u, p, e = u0, p0, e0
+    for _ in range(m // 40):
+        u, p = O.propagate_forced(u, p, c, h, dx, 40, damp)
+        e1 = O.energy(u, p, c, dx)
+        assert e1 <= e * (1 + 1e-3)
+        e = e1
+    assert e < 0.05 * e0
+    u, p = O.propagate_forced(u0, p0, c, h, dx, m)
+    assert O.energy(u, p, c, dx) > 0.99 * e0
+
+
+def test_forced_parareal_exactness_and_serial():
+    """With a layer and a point source, Algorithm 3 keeps the exactness of
+    the first k slices after k iterations (bit for bit against the forced
+    serial fine solution), and the traces of one F sweep from the serial
+    states are that solution sampled every fine step."""
+    n, N = 48, 4
+    x = np.arange(n) / n
+    Y, X = np.meshgrid(x, x, indexing="ij")
+    c = 1.0 + 0.2 * np.sin(2 * np.pi * X)
+    u0 = np.exp(-((X - 0.5) ** 2 + (Y - 0.4) ** 2) / (2 * 0.05 ** 2))
+    Q = O.Problem((n, n), 4, 0.4, N, 16, 4, 4, 1e-8)
+    fo = O.Forcing(width=0.1, src_pos=(0.5, 0.2), freq=6.0, t0=0.1)
+    ref_u, ref_p = O.serial_fine(Q, c, u0, 0 * u0, forcing=fo)
+    res = O.theta_parareal(Q, c, u0, 0 * u0, 2, forcing=fo)
+    for k in range(3):
+        assert np.array_equal(res.u[k], ref_u[k])
+    assert np.isfinite(O.energy_error(res.u[N], res.p[N], ref_u[N],
+                                      ref_p[N], c, Q.dx_fine))
+    rec = np.array([10 * n + j for j in range(0, n, 6)])
+    tr = O.fine_traces(Q, c, ref_u, ref_p, fo, rec)
+    assert tr.shape == (N, 16, rec.size)
+    for k in range(N):
+        np.testing.assert_array_equal(tr[k, -1], ref_u[k + 1].ravel()[rec])

@@ -159,6 +159,12 @@ def sample_columns(N, n_per_iter, n_iters, seed=0):
                          n_iters, n_per_iter)
 
 
+def sketch_matrices(N, l, n_iters, seed=0):
+    """Standard normal test matrices of the randomised range finder, one
+    N x l matrix per iteration: shape (n_iters, N, l) (seed)."""
+    return np.random.default_rng(seed).standard_normal((n_iters, N, l))
+
+
 def smooth_random_field(shape, corr, seed):
     """Unit-variance periodic Gaussian random field with covariance
     exp(-r^2 / (2 corr^2)), synthesised spectrally on the given grid."""
