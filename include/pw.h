@@ -393,6 +393,25 @@ pw_status pw_energy(pw_ctx* ctx, int prob, const void* u, const void* p,
 pw_status pw_error_norms(pw_ctx* ctx, int prob, const void* u, const void* p,
                          const void* u_ref, const void* p_ref, double* out);
 
+/* Allocation-free form of pw_error_norms, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  No context: `desc` gives the fine
+ * grid (dim, n_fine, 1 on unused axes), the gradient order (0 takes the
+ * fourth-order difference, as pw_energy does for the spectral gradient) and
+ * the state dtype; c is the fine-grid c^2 field (double, device, x fastest),
+ * u, p, u_ref, p_ref device fields of the state dtype (u_ref, p_ref may both
+ * be NULL), out a device buffer of 4 doubles that receives out[0..3] as
+ * pw_error_norms (the same kernels, the same bits).  Runs asynchronously on
+ * `stream` (NULL: the null stream) and allocates nothing: the reduction's
+ * partial sums use a fixed 32 KiB device array of the library, one per GPU,
+ * held until the process ends.  Grids of 2^31 points or more and bad
+ * descriptions give PW_EINVAL before any device work.  All calls on one
+ * GPU share that array: calls that overlap on one GPU (other streams or
+ * host threads) race and must be serialised by the caller.            */
+pw_status pw_energy_noalloc(const pw_problem* desc, const double* c,
+                            const void* u, const void* p, const void* u_ref,
+                            const void* p_ref, double* out, void* stream);
+
 /* Checkpoint of the whole context: per problem the medium, u0, the current
  * iterate, kept history, corrector (U~, S~, V~ and the sweep columns),
  * per-iteration records, comparator variant and sampling table, written to

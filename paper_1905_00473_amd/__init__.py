@@ -147,6 +147,7 @@ _SIGS = {
                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                   ctypes.POINTER(ctypes.c_double),
                   ctypes.POINTER(ctypes.c_double)],
+    "pw_energy_noalloc": [ctypes.c_void_p] * 8,
     "pw_get_timings": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                        ctypes.c_int],
     "pw_run_batch": [ctypes.c_void_p, ctypes.c_int],
@@ -177,6 +178,15 @@ def lib():
             raise RuntimeError(
                 f"{LIB_PATH} is missing: build it with "
                 "`python -m paper_1905_00473_amd.build` (no fallback exists)")
+        # torch (ROCm) carries its own HIP runtime beside the one the
+        # library links; have torch's initialised before the library's is
+        # loaded, the order of every torch-driven caller (loading the
+        # library first has left its runtime reporting no device)
+        try:
+            import torch
+            torch.cuda.is_available()
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, args in _SIGS.items():
             f = getattr(L, name)
