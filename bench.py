@@ -372,45 +372,53 @@ def wave1d_measurement(pw, W, torch):
                         "1e-14", "time_to_1e-5": ttt}
 
 
-def serial_traces(pw, torch, w, c, receivers):
-    """Receiver traces u_n(x_r), n = 1..N, of the serial fine solution on
-    medium c (the synthetic data of the misfit workload)."""
-    P = pw.Problem.make(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
-                        w.grad_order, w.tol, "f64", False, 1)
+def forced_problem(pw, w, fd, dtype, compensated, max_iters):
+    return pw.Problem.make(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
+                           w.grad_order, w.tol, dtype, compensated,
+                           max_iters, sponge_width=fd["width"],
+                           sponge_reflection=fd["reflection"],
+                           sponge_cmax=fd["c_max"])
+
+
+def serial_record(pw, torch, w, fd, c, receivers):
+    """The receiver record, every fine step, of the serial fine solution on
+    medium c (the synthetic data of the misfit workload): the serial chain
+    u(t_n) taken as the iterate, then one more sweep (FP64)."""
+    P = forced_problem(pw, w, fd, "f64", False, 1)
     s = pw.Solver(P)
     s.set_medium(c)
+    s.set_source(fd["src_pos"], fd["freq"], fd["t0"])
     s.set_initial(w.u0, w.p0)
+    s.run(0)
     u, p = s.state(0)
-    u, p = u[None].contiguous(), p[None].contiguous()
-    rec = torch.as_tensor(receivers, device="cuda")
-    out = []
-    for _ in range(w.N):
-        u, p = s.propagate(u, p)
-        out.append(u.reshape(-1)[rec])
-    d = torch.stack(out).double().contiguous()
+    for n in range(1, w.N):
+        u, p = s.serial_fine(n)
+        s.set_iterate(n, u, p)
+    d = s.trace_sweep(torch.as_tensor(receivers, device="cuda"))
     s.close()
     return d
 
 
 def adjoint_measurement(pw, W, torch, reps=3):
     """Gradient of the receiver misfit with respect to c^2 (misfit2d
-    recipe): taped forward (Algorithm 3, FP32 compensated states) + traces
-    + backward (FP64 adjoint, checkpoints every 64 fine steps)."""
-    w, rec, target = W.misfit2d()
-    data = serial_traces(pw, torch, w, target, rec)
-    P = pw.Problem.make(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
-                        w.grad_order, w.tol, w.dtype, w.compensated, w.K)
-    s = pw.Solver(P)
+    recipe: absorbing layer, point source, a record every fine step): taped
+    forward (Algorithm 3, FP32 compensated states) + the record's sweep +
+    backward (FP64 adjoint, checkpoints every 64 fine steps)."""
+    w, rec, target, fd = W.misfit2d()
+    data = serial_record(pw, torch, w, fd, target, rec)
+    s = pw.Solver(forced_problem(pw, w, fd, w.dtype, w.compensated, w.K))
     s.set_medium(w.c)
+    s.set_source(fd["src_pos"], fd["freq"], fd["t0"])
     s.set_initial(w.u0, w.p0)
     recd = torch.as_tensor(rec, device="cuda")
+    dt = w.T / w.N / w.m_fine
 
     def once():
         s.run_taped(w.K)
-        tr = s.traces(recd)
-        seed = tr - data
-        g = s.backward(recd, seed, wrt="c2", checkpoint_every=64)
-        return 0.5 * float((seed * seed).sum()), g
+        r = s.trace_sweep(recd)
+        res = r - data
+        g = s.backward_sweep(recd, dt * res, wrt="c2", checkpoint_every=64)
+        return 0.5 * dt * float((res * res).sum()), g
 
     J, g = once()  # allocates the tape and the work buffers
     torch.cuda.synchronize()
@@ -423,10 +431,12 @@ def adjoint_measurement(pw, W, torch, reps=3):
     fwd_upd = w.K * w.N * w.m_fine * w.npts
     log(f"adjoint: gradient {ms:.1f} ms (taped forward {tm['taped']:.1f}, "
         f"backward {tm['backward']:.1f})")
-    out = {"workload": "misfit2d: 2D periodic 512^2 / 128^2, c = 1 + 2 s "
-                       "(GRF, seed 0), N=32, m_F=96, m_C=24, K=4, 128 "
-                       "receivers, data from the serial fine solve on the "
-                       "seed-1 medium",
+    out = {"workload": "misfit2d: 2D 512^2 / 128^2, absorbing layer 0.05 "
+                       "(round trip 1e-3), Ricker source f=10 at (0.5, 0.1), "
+                       "c = 1 + 2 s (GRF, seed 0), N=32, m_F=96, m_C=24, K=4, "
+                       "128 receivers at y=0.9 recorded every fine step, data "
+                       "the record of the serial fine solve on the seed-1 "
+                       "medium",
            "forward_state": "f32 compensated", "adjoint": "f64",
            "checkpoint_every": 64,
            "gradient_ms": round(ms, 2),
@@ -757,8 +767,9 @@ def disc2d_measurement(pw, W, torch, args):
     return out
 
 
-def oracle_spread(O, Q, w, u0, p0, K, ref, pm):
-    """How far the FP64 oracle itself moves when its initial state is
+def oracle_spread(O, Q, w, u0, p0, K, ref, pm, **kw):
+    """How far the FP64 oracle itself moves when its initial state (the
+    medium, when the initial state is zero and a source drives the run) is
     perturbed by FP32-sized rounding (relative 2^-24, seeded): the
     conditioning of the iteration at this tolerance, beside which an FP32
     result is to be read.  (energy, l2, max), max over slices."""
@@ -766,8 +777,13 @@ def oracle_spread(O, Q, w, u0, p0, K, ref, pm):
 
     from tests.gpu_helpers import state_errors
     rng = np.random.default_rng(11)
-    u1 = u0 * (1 + 2.0 ** -24 * rng.standard_normal(np.shape(u0)))
-    r1 = O.theta_parareal(Q, w.c, u1, p0, K, pmap=pm)
+    c1 = w.c
+    if np.any(u0):
+        u1 = u0 * (1 + 2.0 ** -24 * rng.standard_normal(np.shape(u0)))
+    else:
+        u1 = u0
+        c1 = w.c * (1 + 2.0 ** -24 * rng.standard_normal(np.shape(w.c)))
+    r1 = O.theta_parareal(Q, c1, u1, p0, K, pmap=pm, **kw)
     e = np.max([state_errors(r1.u[n], r1.p[n], ref.u[n], ref.p[n], w.c,
                              Q.dx_fine) for n in range(1, Q.N + 1)], axis=0)
     return [float(f"{x:.3e}") for x in e]
@@ -824,20 +840,26 @@ def precision_measurement(pw, W, torch, batch_res):
                     "change when its initial state is perturbed by relative "
                     "2^-24 (the conditioning of the iteration)"}
 
-    def solve_vs_oracle(w, K):
-        P = pw.Problem.make(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
-                            w.grad_order, w.tol, "f32", True, K)
+    def solve_vs_oracle(w, K, fd=None):
+        if fd is None:
+            P = pw.Problem.make(w.shape, w.ratio, w.T, w.N, w.m_fine,
+                                w.m_coarse, w.grad_order, w.tol, "f32", True, K)
+        else:
+            P = forced_problem(pw, w, fd, "f32", True, K)
         s = pw.Solver(P)
         u0 = w.u0.astype(np.float32).astype(np.float64)
         p0 = w.p0.astype(np.float32).astype(np.float64)
         s.set_medium(w.c)
+        if fd is not None:
+            s.set_source(fd["src_pos"], fd["freq"], fd["t0"])
         s.set_initial(u0, p0)
         s.run(K)
         Q = O.Problem(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
                       w.grad_order, w.tol)
+        kw = {} if fd is None else {"forcing": O.Forcing(**fd)}
         with oracle_pool() as pm:
-            ref = O.theta_parareal(Q, w.c, u0, p0, K, pmap=pm)
-            spread = oracle_spread(O, Q, w, u0, p0, K, ref, pm)
+            ref = O.theta_parareal(Q, w.c, u0, p0, K, pmap=pm, **kw)
+            spread = oracle_spread(O, Q, w, u0, p0, K, ref, pm, **kw)
         worst = np.zeros(3)
         for n in range(1, w.N + 1):
             u, p = s.state(n)
@@ -861,8 +883,9 @@ def precision_measurement(pw, W, torch, batch_res):
             solve_vs_oracle(w, 6)
     out["layers3d (64^3 / 16^3, N=32, K=6)"] = solve_vs_oracle(
         W.layers3d(n=64, ratio=4, N=32, K=6, T=1.5), 6)
-    wm, _, _ = W.misfit2d(n=128, N=32, K=4)
-    out["misfit2d forward (128^2 / 32^2, N=32, K=4)"] = solve_vs_oracle(wm, 4)
+    wm, _, _, fdm = W.misfit2d(n=128, N=32, K=4)
+    out["misfit2d forward (128^2 / 32^2, N=32, K=4, layer and source)"] = \
+        solve_vs_oracle(wm, 4, fdm)
     log(f"precision {out} ({time.perf_counter() - t0:.0f} s)")
     return out
 

@@ -90,7 +90,28 @@ typedef struct {
   int keep_history;    /* 1: keep every iterate u^k_n, k = 1..max_iters+1, on
                           the device for pw_get_iterate ((max_iters + 1) N
                           fine states); 0: only the current one         */
+  int bc;              /* pw_bc: PW_PERIODIC, or PW_SPONGE (2D only)         */
+  double sponge_width; /* PW_SPONGE: layer width, a fraction of the box in
+                          (0, 0.5)                                         */
+  double sponge_reflection; /* PW_SPONGE: amplitude left after a round trip
+                          through the layer at c_max (0: 1e-3)             */
+  double sponge_cmax;  /* PW_SPONGE: the c_max of sigma_max (0: the largest
+                          c of the medium, taken at pw_set_medium)         */
 } pw_problem;
+
+/* Boundary of the box.  The paper's problem (eq. (1)) allows periodic,
+ * absorbing or PML boundaries; the method itself is stated for the
+ * periodic box, where the Fourier-based Lambda^dag of Sec. 4 holds.
+ * PW_SPONGE keeps the periodic box and damps the waves in a layer of
+ * width w along every face: u_tt = c^2 Lap u - sigma u_t, with
+ * sigma = sigma_max (d / w)^2, d the largest penetration of a node into
+ * the layer over the axes, sigma_max = (3 c_max / (2 w)) ln(1 / R).  Each
+ * velocity-Verlet half kick first multiplies p by exp(-sigma h / 2) (the
+ * exact decay over h / 2); the coarse propagator uses sigma at the coarse
+ * nodes.  Every other step of Algorithm 3 is unchanged.  The layer is a
+ * function of position only: the gradient of pw_backward holds it fixed.
+ * 2D problems only (PW_EINVAL otherwise).                               */
+typedef enum { PW_PERIODIC = 0, PW_SPONGE = 1 } pw_bc;
 
 /* The interpolation I from the coarse to the fine grid: trigonometric
  * (the interpft of Sec. 6, the default), periodic piecewise linear, or
@@ -125,6 +146,23 @@ const char* pw_version(void);
  * either grid.  on_device: 1 if c is a device pointer, 0 for host.       */
 pw_status pw_set_medium(pw_ctx* ctx, int prob, const double* c,
                         int on_device);
+
+/* Point source f(x, t) = r(t) delta_h(x - x_s) added to eq. (1)
+ * (u_tt = c^2 Lap u + f): r is the Ricker wavelet (1 - 2a) exp(-a),
+ * a = (pi freq (t - t0))^2, placed at the grid node nearest to pos (box
+ * coordinates, x first, dim values; nearest fine node for F, nearest
+ * coarse node for C) with weight 1 / dx^dim of that grid.  Slice n
+ * propagates from t_{n-1} = (n - 1) T / N, so every kick of F and C adds
+ * (its weight) * r(t) at the source node.  The correction of Algorithm 3
+ * acts on differences of coarse propagations, in which the source
+ * cancels: the sweep's coarse propagations of differences (and the
+ * corrector-coordinate recurrence) use C without the source.  pos = NULL
+ * removes the source.  freq > 0.  2D problems only; the comparator
+ * PW_VARIANT_NO_CORRECTION, which propagates states rather than
+ * differences, and batches (pw_run_batch) refuse a problem with a source
+ * (PW_EINVAL).  Resets the iteration.                                   */
+pw_status pw_set_source(pw_ctx* ctx, int prob, const double* pos, double freq,
+                        double t0);
 
 /* Set the initial state u0, p0 (double fields on the fine grid, eq. (1)),
  * converted to the state dtype.  Resets the iteration (k = 0).          */
@@ -321,8 +359,9 @@ pw_status pw_get_residuals(pw_ctx* ctx, int prob, double* rho_host,
 pw_status pw_get_diagnostics(pw_ctx* ctx, int prob, double* out, int cap, int* count);
 
 /* Serial fine reference u(t_n) = F^n [u0, p0] (Sec. 6: computed serially
- * with the fine propagator) written to caller device buffers u_dev, p_dev
- * of n_points elements of the state dtype.  0 <= n <= N.               */
+ * with the fine propagator; with a source, step n of the chain propagates
+ * slice n) written to caller device buffers u_dev, p_dev of n_points
+ * elements of the state dtype.  0 <= n <= N.                            */
 pw_status pw_serial_fine(pw_ctx* ctx, int prob, int n, void* u_dev,
                          void* p_dev);
 
@@ -333,7 +372,9 @@ pw_status pw_serial_fine(pw_ctx* ctx, int prob, int n, void* u_dev,
 
 /* F (grid = PW_FINE) or C (PW_COARSE) of problem `prob` applied to
  * n_states states: u_out[s], p_out[s] = prop(u_in[s], p_in[s]) in the
- * state dtype (Sec. 3.1).  Inputs and outputs may not overlap.          */
+ * state dtype (Sec. 3.1).  Inputs and outputs may not overlap.  With a
+ * layer and source, state s propagates slice s + 1 (from t = s T / N), as
+ * in the parallel step of Algorithm 3.                                   */
 pw_status pw_propagate(pw_ctx* ctx, int prob, int grid, const void* u_in,
                        const void* p_in, void* u_out, void* p_out,
                        int n_states);
@@ -414,8 +455,8 @@ pw_status pw_energy_noalloc(const pw_problem* desc, const double* c,
 
 /* Checkpoint of the whole context: per problem the medium, u0, the current
  * iterate, kept history, corrector (U~, S~, V~ and the sweep columns),
- * per-iteration records, comparator variant and sampling table, written to
- * the file `path` (host byte order, format tag PWCKPT01).  pw_load restores
+ * per-iteration records, comparator variant, sampling table and source,
+ * written to the file `path` (host byte order, format tag PWCKPT02).  pw_load restores
  * it into a context created with the same problem descriptions (PW_EINVAL
  * otherwise, or for a damaged file; the state is then unspecified until the
  * next set_* / run), after which pw_continue resumes the iteration exactly
@@ -492,6 +533,29 @@ pw_status pw_traces(pw_ctx* ctx, int prob, const long long* receivers,
 pw_status pw_backward(pw_ctx* ctx, int prob, const long long* receivers,
                       int n_rec, const double* seed, double* grad,
                       int on_device, int wrt_velocity, int checkpoint_every);
+
+/* A receiver record of the current iterate sampled in time: one more
+ * batched F sweep from the slice starts u_{n-1}, n = 1..N (with the layer
+ * and source), recording u at the receivers after every fine step:
+ * out[((n-1) * m_fine + i) * n_rec + r] = u of slice n after step i + 1 at
+ * receiver r (FP64, N x m_fine x n_rec).  Receivers are distinct flat
+ * fine-grid indices (x fastest, int64; PW_EINVAL for one outside [0, Nf)
+ * or repeated).  2D problems only.  on_device applies to receivers and
+ * out.  Synchronous.                                                     */
+pw_status pw_trace_sweep(pw_ctx* ctx, int prob, const long long* receivers,
+                         int n_rec, double* out, int on_device);
+
+/* Gradient of J = sum seed[((n-1) * m_fine + i) * n_rec + r] * (the
+ * record of pw_trace_sweep) through the last taped or frozen run, with its
+ * correctors and the layer held fixed (the vector-Jacobian product of
+ * pw_trace_sweep after that run).  For the misfit J = 1/2 dt sum (trace -
+ * data)^2 of a record sampled every fine step pass seed = dt (trace -
+ * data).  Arguments, checkpointing, work buffers and errors as
+ * pw_backward (the record's sweep adds its N states to the fine adjoint).
+ * Synchronous.                                                          */
+pw_status pw_backward_sweep(pw_ctx* ctx, int prob, const long long* receivers,
+                            int n_rec, const double* seed, double* grad,
+                            int on_device, int wrt_velocity, int checkpoint_every);
 
 #ifdef __cplusplus
 }

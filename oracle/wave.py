@@ -165,12 +165,15 @@ def ricker(t, freq, t0):
 def sponge_sigma(shape, width, sigma_max, length=1.0):
     """Damping coefficient of a layer of the given width along every face of
     the box: sigma = sigma_max (d / width)^2, d the largest penetration
-    max(0, width - min(x_a, L - x_a)) over the axes (nodes x = j dx)."""
+    max(0, width - min(x_a, L_a - x_a)) over the axes (nodes x = j dx, the
+    spacing dx = length / n_x of every axis, so the box is L_a = n_a dx
+    long along axis a)."""
     dx = length / shape[-1]
     d = np.zeros(shape)
     for ax, n in enumerate(shape):
         x = np.arange(n) * dx
-        pen = np.maximum(0.0, width - np.minimum(x, length - x))
+        L = n * dx
+        pen = np.maximum(0.0, width - np.minimum(x, L - x))
         sh = [1] * len(shape)
         sh[ax] = n
         d = np.maximum(d, pen.reshape(sh))
@@ -227,6 +230,7 @@ class Forcing:
     src_pos: tuple = None
     freq: float = 10.0
     t0: float = 0.1
+    c_max: float = None     # speed in sigma_max (None: the largest c given)
 
 
 def _nearest_node(pos, shape, dx):
@@ -252,8 +256,8 @@ def forcing_setup(prob, c, forcing):
     cf = np.asarray(c, dtype=np.float64)
     d = len(prob.shape)
     if forcing.width > 0:
-        smax = sponge_sigma_max(float(cf.max()), forcing.width,
-                                forcing.reflection)
+        cmax = float(cf.max()) if forcing.c_max is None else forcing.c_max
+        smax = sponge_sigma_max(cmax, forcing.width, forcing.reflection)
         sig = sponge_sigma(prob.shape, forcing.width, smax, prob.length)
         out["dF"] = np.exp(-0.5 * sig * prob.dt_fine)
         out["dC"] = np.exp(-0.5 * restrict(sig, prob.ratio) * prob.dt_coarse)

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)),
                         "libpwave.so")
 F32, F64 = 0, 1
 FINE, COARSE = 0, 1
+PERIODIC, SPONGE = 0, 1
 
 _STATUS = {0: "PW_OK", -1: "PW_EINVAL", -2: "PW_EUNSTABLE", -3: "PW_ENOMEM",
            -4: "PW_EHIP", -5: "PW_ESTATE", -6: "PW_ENUMERIC"}
@@ -48,14 +49,21 @@ class Problem(ctypes.Structure):
         ("max_iters", ctypes.c_int),
         ("interp", ctypes.c_int),
         ("keep_history", ctypes.c_int),
+        ("bc", ctypes.c_int),
+        ("sponge_width", ctypes.c_double),
+        ("sponge_reflection", ctypes.c_double),
+        ("sponge_cmax", ctypes.c_double),
     ]
 
     @classmethod
     def make(cls, shape, ratio, T, N, m_fine, m_coarse, grad_order=4,
              tol=1e-14, dtype="f64", compensated=False, max_iters=8,
-             interp="trig", keep_history=False):
+             interp="trig", keep_history=False, sponge_width=0.0,
+             sponge_reflection=0.0, sponge_cmax=0.0):
         """shape: fine grid in numpy order (x last); interp: "trig",
-        "linear" or "cubic"; keep_history: keep every iterate u^k_n."""
+        "linear" or "cubic"; keep_history: keep every iterate u^k_n;
+        sponge_width > 0: an absorbing layer of that width (PW_SPONGE, 2D;
+        reflection 0 means 1e-3, cmax 0 the medium's largest c)."""
         p = cls()
         p.dim = len(shape)
         xyz = list(reversed(shape)) + [1] * (3 - len(shape))
@@ -73,6 +81,11 @@ class Problem(ctypes.Structure):
         p.max_iters = int(max_iters)
         p.interp = {"trig": 0, "linear": 1, "cubic": 2}.get(interp, interp)
         p.keep_history = int(bool(keep_history))
+        if sponge_width > 0:
+            p.bc = SPONGE
+            p.sponge_width = float(sponge_width)
+            p.sponge_reflection = float(sponge_reflection)
+            p.sponge_cmax = float(sponge_cmax)
         return p
 
 
@@ -148,6 +161,13 @@ _SIGS = {
                   ctypes.POINTER(ctypes.c_double),
                   ctypes.POINTER(ctypes.c_double)],
     "pw_energy_noalloc": [ctypes.c_void_p] * 8,
+    "pw_set_source": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                      ctypes.c_double, ctypes.c_double],
+    "pw_trace_sweep": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                       ctypes.c_int, ctypes.c_void_p, ctypes.c_int],
+    "pw_backward_sweep": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                          ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                          ctypes.c_int, ctypes.c_int, ctypes.c_int],
     "pw_get_timings": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                        ctypes.c_int],
     "pw_run_batch": [ctypes.c_void_p, ctypes.c_int],
@@ -503,6 +523,41 @@ class Solver:
                                _ptr(out), 1))
         return out
 
+    def set_source(self, pos, freq=10.0, t0=0.1, prob=0):
+        """Ricker point source at the node nearest to pos (box coordinates,
+        x first; None removes it), peak frequency freq, peak time t0."""
+        if pos is None:
+            _check(lib().pw_set_source(self._h, prob, None, 0.0, 0.0))
+            return
+        arr = (ctypes.c_double * len(pos))(*[float(x) for x in pos])
+        _check(lib().pw_set_source(self._h, prob, arr, float(freq), float(t0)))
+
+    def trace_sweep(self, receivers, prob=0):
+        """(N, m_fine, n_rec) float64: u at the receivers after every fine
+        step of one more F sweep from the current iterate (distinct flat
+        fine indices)."""
+        import torch
+        rec = self._receivers(receivers)
+        P = self.problems[prob]
+        out = torch.empty((P.n_slices, P.m_fine, rec.numel()),
+                          dtype=torch.float64, device="cuda")
+        _check(lib().pw_trace_sweep(self._h, prob, _ptr(rec), rec.numel(),
+                                    _ptr(out), 1))
+        return out
+
+    def backward_sweep(self, receivers, seed, wrt="c2", checkpoint_every=64,
+                       prob=0):
+        """Vector-Jacobian product of trace_sweep() through the last taped
+        or frozen run (seed: (N, m_fine, n_rec))."""
+        import torch
+        rec = self._receivers(receivers)
+        sd = self._dev(seed, torch.float64)
+        g = torch.empty(self.shape(prob), dtype=torch.float64, device="cuda")
+        _check(lib().pw_backward_sweep(self._h, prob, _ptr(rec), rec.numel(),
+                                       _ptr(sd), _ptr(g), 1, int(wrt == "c"),
+                                       int(checkpoint_every)))
+        return g
+
     def backward(self, receivers, seed, wrt="c2", checkpoint_every=64,
                  prob=0):
         """Vector-Jacobian product of traces() through the last taped or
@@ -667,6 +722,39 @@ def _traces_function():
     return _PararealTraces
 
 
+def _record_function():
+    import torch
+
+    class _PararealRecord(torch.autograd.Function):
+        """record = PararealRecord.apply(c, solver, receivers, K, prob): the
+        receiver record (N x m_fine x n_rec, float64) of one more F sweep
+        from the iterate u^{K+1} of Algorithm 3 run on medium c (the
+        trace_sweep of a taped run); the backward pass gives d/dc with the
+        correctors and the absorbing layer held fixed
+        (pw_backward_sweep)."""
+
+        @staticmethod
+        def forward(ctx, c, solver, receivers, K, prob=0):
+            solver.set_medium(c.detach(), prob)
+            solver.run_taped(K, prob)
+            ctx.solver, ctx.receivers, ctx.prob = solver, receivers, prob
+            ctx.tape_id = solver.tape_id(prob)
+            return solver.trace_sweep(receivers, prob)
+
+        @staticmethod
+        def backward(ctx, grad_record):
+            if ctx.solver.tape_id(ctx.prob) != ctx.tape_id:
+                raise PwError(-5, "the solver ran another taped forward since "
+                                  "this graph was recorded; its tape is gone "
+                                  "(use one Solver per live graph)")
+            g = ctx.solver.backward_sweep(ctx.receivers,
+                                          grad_record.contiguous(), wrt="c",
+                                          prob=ctx.prob)
+            return g, None, None, None, None
+
+    return _PararealRecord
+
+
 class _Lazy:
     def __init__(self, make):
         self._make, self._obj = make, None
@@ -679,3 +767,6 @@ class _Lazy:
 
 #: torch.autograd.Function over pw_run_taped / pw_traces / pw_backward
 PararealTraces = _Lazy(_traces_function)
+#: torch.autograd.Function over pw_run_taped / pw_trace_sweep /
+#: pw_backward_sweep (a receiver record sampled every fine step)
+PararealRecord = _Lazy(_record_function)

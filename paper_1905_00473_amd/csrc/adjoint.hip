@@ -161,11 +161,21 @@ __global__ void k_adj_kick(double* lu, const double* lp, long long sl, const dou
 // and written per state.
 constexpr int kAdjGroup = 8;
 
-template <int D>
+// Layer (2D): the kick at level i multiplies p by s(x) and weighs the
+// acceleration by W(x): s = d, W = h/2 at level 0 (first half kick of the
+// slice), s = d^2, W = h/2 (1 + d) where two half kicks meet, with
+// d = min(dmx[x], dmy[y]).  Its reverse: lu' = lu + Lap(W c2 lp'),
+// lp_out = s lp', g += W lp' Lap u_i.
+__device__ __forceinline__ double layer_d(const double* dmx, const double* dmy, int x, int y) {
+  return fmin(dmx[x], dmy[y]);
+}
+
+template <int D, bool FORCED = false>
 __global__ void k_adj_step_grp(const double* lu, const double* lp, long long sl, double* lu2,
                                double* lp2, long long sl2, const double* u, long long su,
                                double* gacc, long long sg, const double* c2, double w, double h,
-                               G3 g, int nxb, int nblk, int ns) {
+                               G3 g, int nxb, int nblk, int ns, const double* dmx,
+                               const double* dmy, int lev0) {
   const Pt q = point(g, nxb, nblk);  // q.s: state group
   if (!q.ok) return;
   const Nbr<D> nb = neighbours<D>(q, g);
@@ -174,6 +184,25 @@ __global__ void k_adj_step_grp(const double* lu, const double* lp, long long sl,
   double cn[2 * D];
 #pragma unroll
   for (int k = 0; k < 2 * D; ++k) cn[k] = c2[J + nb.off[k]];
+  // FORCED (2D): the weights W at J and its neighbours, the factor at J
+  double WJ = w, sJ = 1.0;
+  if constexpr (FORCED) {
+    if (dmx) {
+      const int xp = q.x + 1 < g.nx ? q.x + 1 : 0, xm = q.x > 0 ? q.x - 1 : g.nx - 1;
+      const int yp = q.y + 1 < g.ny ? q.y + 1 : 0, ym = q.y > 0 ? q.y - 1 : g.ny - 1;
+      const double dJ = layer_d(dmx, dmy, q.x, q.y);
+      const double dn[4] = {layer_d(dmx, dmy, xp, q.y), layer_d(dmx, dmy, xm, q.y),
+                            layer_d(dmx, dmy, q.x, yp), layer_d(dmx, dmy, q.x, ym)};
+      WJ = lev0 ? 0.5 * h : 0.5 * h * (1.0 + dJ);
+      sJ = lev0 ? dJ : dJ * dJ;
+#pragma unroll
+      for (int k = 0; k < 2 * D; ++k) cn[k] *= lev0 ? 0.5 * h : 0.5 * h * (1.0 + dn[k]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 2 * D; ++k) cn[k] *= w;
+    }
+  }
+  const double ccw = FORCED ? cc * WJ : cc;
   double gsum = 0.0;
   const int s1 = min(ns, (q.s + 1) * kAdjGroup);
 #pragma unroll 2
@@ -181,17 +210,40 @@ __global__ void k_adj_step_grp(const double* lu, const double* lp, long long sl,
     const double* lus = lu + (long long)s * sl;
     const double* lps = lp + (long long)s * sl;
     const double lpc = fma(h, lus[J], lps[J]);
-    double a = -2.0 * D * cc * lpc;
+    double a = -2.0 * D * ccw * lpc;
 #pragma unroll
     for (int k = 0; k < 2 * D; ++k) {
       const long long o = J + nb.off[k];
       a += cn[k] * fma(h, lus[o], lps[o]);
     }
-    lu2[(long long)s * sl2 + J] = lus[J] + w * a * g.idx2;
-    lp2[(long long)s * sl2 + J] = lpc;
-    gsum += w * lpc * lap_nb<D>(u + (long long)s * su, J, nb, g.idx2);
+    if constexpr (FORCED) {
+      lu2[(long long)s * sl2 + J] = lus[J] + a * g.idx2;
+      lp2[(long long)s * sl2 + J] = sJ * lpc;
+      gsum += WJ * lpc * lap_nb<D>(u + (long long)s * su, J, nb, g.idx2);
+    } else {
+      lu2[(long long)s * sl2 + J] = lus[J] + w * a * g.idx2;
+      lp2[(long long)s * sl2 + J] = lpc;
+      gsum += w * lpc * lap_nb<D>(u + (long long)s * su, J, nb, g.idx2);
+    }
   }
   gacc[(long long)q.s * sg + J] += gsum;
+}
+
+// lp <- d lp (the layer's factor of a closing half kick, 2D)
+__global__ void k_damp_fields(double* lp, long long sl, const double* dmx, const double* dmy,
+                              G3 g, int nxb, int nblk) {
+  const Pt q = point(g, nxb, nblk);
+  if (!q.ok) return;
+  lp[(long long)q.s * sl + q.J] *= layer_d(dmx, dmy, q.x, q.y);
+}
+
+// lu[s sl + rec[r]] += seeds[(s m_tr + step) n_rec + r] (distinct receivers)
+__global__ void k_inject_seeds(double* lu, long long sl, const long long* rec, int nrec,
+                               const double* seeds, int m_tr, int step, int ns) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)nrec * ns) return;
+  const int s = (int)(t / nrec), r = (int)(t - (long long)s * nrec);
+  lu[(long long)s * sl + rec[r]] += seeds[((long long)s * m_tr + step) * nrec + r];
 }
 
 // Reverse leapfrog steps in 2D as a row stream, RB steps per launch
@@ -224,8 +276,18 @@ struct AdjStreamDesc {
   double w[kAdjRB];
   int top, nsteps;
   int nx, ny, ncb, nseg, Ly, nstates;
+  // forced launches: the layer (null: none), the level of the slice at
+  // segment level 0, and the receiver seeds (null: none; see Force)
+  const double* dmx;
+  const double* dmy;
+  int lev_base;
+  const int* rec_rows;
+  const int* rec_map;
+  const double* seeds;
+  int n_rec, m_tr;
 };
 
+template <bool FORCED>
 __global__ __launch_bounds__(256) void k_adj_stream2d(AdjStreamDesc a) {
   constexpr int B = kAdjRB;
   constexpr int H = B;
@@ -256,6 +318,16 @@ __global__ __launch_bounds__(256) void k_adj_stream2d(AdjStreamDesc a) {
   const double* lui = a.lu_in + (long long)st * a.s_in;
   const double* lpi = a.lp_in + (long long)st * a.s_in;
   double* gs = a.gacc + (long long)st * a.sg;
+  const bool damp = FORCED && a.dmx != nullptr;
+  const double dcol = damp ? a.dmx[gx] : 1.0;
+  // level 0 of the slice is a half kick: W = h/2, factor d; elsewhere
+  // W = h/2 (1 + d), factor d^2 (see k_adj_step_grp)
+  auto weight = [&](int lev, double d) { return lev == 0 ? 0.5 * a.h : 0.5 * a.h * (1.0 + d); };
+  auto dlayer = [&](int y) {
+    int r = y % ny;
+    if (r < 0) r += ny;
+    return damp ? fmin(dcol, a.dmy[r]) : 1.0;
+  };
   const double* ul[B];
 #pragma unroll
   for (int j = 0; j < B; ++j)
@@ -305,8 +377,16 @@ __global__ __launch_bounds__(256) void k_adj_stream2d(AdjStreamDesc a) {
         lu_ += lane_upv(uc);
         lu_ += wu[j][2];
         lu_ += wu[j][0];
-        lo = lc + a.w[j] * aa * a.idx2;
-        go = gc + a.w[j] * pc * (lu_ * a.idx2);
+        if constexpr (FORCED) {
+          const int lev = a.lev_base + a.top - j;
+          const double d = dlayer(r);
+          lo = lc + aa * a.idx2;  // W is inside q
+          go = gc + weight(lev, d) * pc * (lu_ * a.idx2);
+          po = (lev == 0 ? d : d * d) * pc;
+        } else {
+          lo = lc + a.w[j] * aa * a.idx2;
+          go = gc + a.w[j] * pc * (lu_ * a.idx2);
+        }
       }
       (void)r;
       ol[j] = lo;
@@ -335,10 +415,26 @@ __global__ __launch_bounds__(256) void k_adj_stream2d(AdjStreamDesc a) {
     for (int j = 0; j < B; ++j) {
       const int rin = t + 2 - 2 * j;  // row of the pending slot of stage j
       const long long gi = rowidx(rin);
+      double wq_in = 1.0;
+      if constexpr (FORCED) {
+        if (j < a.nsteps) {
+          const int lev = a.lev_base + a.top - j;
+          wq_in = weight(lev, dlayer(rin));
+          // receiver seed of u at level lev + 1 (record index lev)
+          if (a.seeds) {
+            int ry = rin % ny;
+            if (ry < 0) ry += ny;
+            if (a.rec_rows[ry]) {
+              const int rid = a.rec_map[gi];
+              if (rid >= 0) pl[j] += a.seeds[((long long)st * a.m_tr + lev) * a.n_rec + rid];
+            }
+          }
+        }
+      }
       const double lpn = (j < a.nsteps) ? fma(a.h, pl[j], pp[j]) : pp[j];
       wq[j][0] = wq[j][1];
       wq[j][1] = wq[j][2];
-      wq[j][2] = a.c2[gi] * lpn;
+      wq[j][2] = FORCED ? wq_in * (a.c2[gi] * lpn) : a.c2[gi] * lpn;
       wu[j][0] = wu[j][1];
       wu[j][1] = wu[j][2];
       wu[j][2] = ul[j][gi];
@@ -574,9 +670,15 @@ void copy_fields(const double* in, long long si, double* out, long long so, long
 template <int D>
 void vv_adjoint_d(const Grid& grid, const double* c2, const double* u0, const double* p0,
                 long long s0, double* lu, double* lp, long long sl, double* gacc, long long sg,
-                int ns, int m, double h, int ckpt, const AdjScratch& sc, hipStream_t st) {
+                int ns, int m, double h, int ckpt, const AdjScratch& sc, hipStream_t st,
+                const Force<double>* fo) {
   if (ns == 0 || m == 0) return;
   if (ckpt < 1) fail(PW_EINVAL, "checkpoint interval must be >= 1");
+  if (fo && D != 2) fail(PW_EINVAL, "the absorbing layer and source are 2D only");
+  if (fo && fo->seeds && (!fo->rec || !fo->rec_rows || !fo->rec_map || fo->m_tr < m))
+    fail(PW_EINVAL, "receiver seeds need the receiver tables and m steps per state");
+  const double* dmx = fo ? fo->dmp_x : nullptr;
+  const double* dmy = fo ? fo->dmp_y : nullptr;
   const long long np = grid.npts();
   const G3 g = g3(grid);
   const PtLaunch pl = pt_launch(g, ns);
@@ -597,7 +699,7 @@ void vv_adjoint_d(const Grid& grid, const double* c2, const double* u0, const do
       // the streaming propagator, levels into the segment store
       const double* pf = leapfrog_levels2d(grid, c2, sc.ck_u + seg * S, sc.ck_p + seg * S,
                                            sc.p_tmp, sc.p_tmp2, np, ns, ckpt, h, seg == 0, sc.seg,
-                                           S, st);
+                                           S, st, fo, seg * ckpt);
       copy_fields(sc.seg + (long long)(ckpt - 1) * S, np, sc.ck_u + (seg + 1) * S, np, np, ns,
                   st);
       copy_fields(pf, np, sc.ck_p + (seg + 1) * S, np, np, ns, st);
@@ -631,7 +733,7 @@ void vv_adjoint_d(const Grid& grid, const double* c2, const double* u0, const do
     copy_fields(sc.ck_u + seg * S, np, sc.seg, np, np, ns, st);
     if (D == 2) {
       leapfrog_levels2d(grid, c2, sc.ck_u + seg * S, sc.ck_p + seg * S, sc.p_tmp, sc.p_tmp2, np,
-                        ns, len, h, i0 == 0, sc.seg + S, S, st);
+                        ns, len, h, i0 == 0, sc.seg + S, S, st, fo, i0);
     } else {
       copy_fields(sc.ck_p + seg * S, np, sc.p_tmp, np, np, ns, st);
       for (int i = 0; i < len; ++i) {
@@ -648,12 +750,27 @@ void vv_adjoint_d(const Grid& grid, const double* c2, const double* u0, const do
                          (const double*)(sc.seg + (long long)len * S), np, gacc, sg, c2, 0.5 * h,
                          g, pl.nxb, pl.nblk);
       PW_LAUNCH_CHECK();
+      if (dmx) {  // the closing half kick's factor d
+        hipLaunchKernelGGL(k_damp_fields, gr, dim3(kTB), 0, st, lpa, sa, dmx, dmy, g, pl.nxb,
+                           pl.nblk);
+        PW_LAUNCH_CHECK();
+      }
     }
     if (D == 2 && (long long)ns * np >= (1LL << 18)) {
       // kAdjRB reverse steps per launch (launches too small to fill the
       // chip, such as one coarse state, keep one step per launch: a stream
       // is a serial chain of row steps)
       AdjStreamDesc d{};
+      if (fo) {
+        d.dmx = dmx;
+        d.dmy = dmy;
+        d.lev_base = i0;
+        d.rec_rows = fo->rec_rows;
+        d.rec_map = fo->rec_map;
+        d.seeds = fo->seeds;
+        d.n_rec = fo->n_rec;
+        d.m_tr = fo->m_tr;
+      }
       d.useg = sc.seg;
       d.s_lev = S;
       d.s_u = np;
@@ -692,7 +809,12 @@ void vv_adjoint_d(const Grid& grid, const double* c2, const double* u0, const do
         d.lu_out = lub;
         d.lp_out = lpb;
         d.s_out = sb;
-        hipLaunchKernelGGL(k_adj_stream2d, dim3((unsigned)((nw + 3) / 4)), dim3(256), 0, st, d);
+        if (fo)
+          hipLaunchKernelGGL(k_adj_stream2d<true>, dim3((unsigned)((nw + 3) / 4)), dim3(256), 0,
+                             st, d);
+        else
+          hipLaunchKernelGGL(k_adj_stream2d<false>, dim3((unsigned)((nw + 3) / 4)), dim3(256), 0,
+                             st, d);
         PW_LAUNCH_CHECK();
         std::swap(lua, lub);
         std::swap(lpa, lpb);
@@ -701,10 +823,31 @@ void vv_adjoint_d(const Grid& grid, const double* c2, const double* u0, const do
       }
     } else {
       for (int i = len - 1; i >= 0; --i) {
-        hipLaunchKernelGGL(k_adj_step_grp<D>, pg.grid, dim3(kTB), 0, st, (const double*)lua,
-                           (const double*)lpa, sa, lub, lpb, sb,
+        if (fo && fo->seeds) {  // receiver seeds of u at level i0 + i + 1
+          const long long nt = (long long)fo->n_rec * ns;
+          hipLaunchKernelGGL(k_inject_seeds, dim3(nblocks(nt)), dim3(kTB), 0, st, lua, sa, fo->rec,
+                             fo->n_rec, fo->seeds, fo->m_tr, i0 + i, ns);
+          PW_LAUNCH_CHECK();
+        }
+        if constexpr (D == 2) {
+          if (fo) {
+            hipLaunchKernelGGL((k_adj_step_grp<D, true>), pg.grid, dim3(kTB), 0, st,
+                               (const double*)lua, (const double*)lpa, sa, lub, lpb, sb,
+                               (const double*)(sc.seg + (long long)i * S), np, gacc, sg, c2,
+                               wk(i0 + i), h, g, pg.nxb, pg.nblk, ns, dmx, dmy,
+                               (int)(i0 + i == 0));
+            PW_LAUNCH_CHECK();
+            std::swap(lua, lub);
+            std::swap(lpa, lpb);
+            std::swap(sa, sb);
+            continue;
+          }
+        }
+        hipLaunchKernelGGL((k_adj_step_grp<D, false>), pg.grid, dim3(kTB), 0, st,
+                           (const double*)lua, (const double*)lpa, sa, lub, lpb, sb,
                            (const double*)(sc.seg + (long long)i * S), np, gacc, sg, c2,
-                           wk(i0 + i), h, g, pg.nxb, pg.nblk, ns);
+                           wk(i0 + i), h, g, pg.nxb, pg.nblk, ns, (const double*)nullptr,
+                           (const double*)nullptr, 0);
         PW_LAUNCH_CHECK();
         std::swap(lua, lub);
         std::swap(lpa, lpb);
@@ -720,13 +863,14 @@ void vv_adjoint_d(const Grid& grid, const double* c2, const double* u0, const do
 
 void vv_adjoint(const Grid& grid, const double* c2, const double* u0, const double* p0,
                 long long s0, double* lu, double* lp, long long sl, double* gacc, long long sg,
-                int ns, int m, double h, int ckpt, const AdjScratch& sc, hipStream_t st) {
+                int ns, int m, double h, int ckpt, const AdjScratch& sc, hipStream_t st,
+                const Force<double>* fo) {
   if (grid.dim == 1)
-    vv_adjoint_d<1>(grid, c2, u0, p0, s0, lu, lp, sl, gacc, sg, ns, m, h, ckpt, sc, st);
+    vv_adjoint_d<1>(grid, c2, u0, p0, s0, lu, lp, sl, gacc, sg, ns, m, h, ckpt, sc, st, fo);
   else if (grid.dim == 2)
-    vv_adjoint_d<2>(grid, c2, u0, p0, s0, lu, lp, sl, gacc, sg, ns, m, h, ckpt, sc, st);
+    vv_adjoint_d<2>(grid, c2, u0, p0, s0, lu, lp, sl, gacc, sg, ns, m, h, ckpt, sc, st, fo);
   else
-    vv_adjoint_d<3>(grid, c2, u0, p0, s0, lu, lp, sl, gacc, sg, ns, m, h, ckpt, sc, st);
+    vv_adjoint_d<3>(grid, c2, u0, p0, s0, lu, lp, sl, gacc, sg, ns, m, h, ckpt, sc, st, fo);
 }
 
 void interp_transpose(const Grid& f, const Grid& c, int ratio, const double* const* tables,

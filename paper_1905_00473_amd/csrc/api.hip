@@ -96,7 +96,7 @@ struct Tape {
   int K = 0;                // iterations of the last taped / frozen run
   int Kc = 0;               // iterations with recorded correctors
   long long epoch = -1;     // medium/initial epoch of the recorded run
-  void* us = nullptr;       // Kcap x N fields, state dtype: u^k_n, n = 0..N-1
+  void* us = nullptr;       // (Kcap + 1) x N fields, state dtype: u^k_n, n = 0..N-1
   void* ps = nullptr;
   double* W = nullptr;      // 2Nc x N: initialisation coarse states W_0..W_{N-1}
   double* Din = nullptr;    // Kcap x (2Nc x N)
@@ -231,8 +231,21 @@ struct Prob {
   double ms[4] = {0, 0, 0, 0};
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> pev;  // per-iteration phase events (4 per iteration)
+  // absorbing layer (PW_SPONGE) and point source (pw_set_source), 2D:
+  // per-axis layer factors exp(-sigma_a h / 2) of the fine and the coarse
+  // grid ([x | y], nx + ny values), in the state dtype and in double
+  bool sponge = false;
+  double sponge_smax = 0.0;
+  void *layF_t = nullptr, *layC_t = nullptr;
+  double *layF_d = nullptr, *layC_d = nullptr;
+  bool have_src = false;
+  double src_pos[3] = {0, 0, 0}, src_freq = 0.0, src_t0 = 0.0;
+  int srcF[2] = {-1, -1}, srcC[2] = {-1, -1};  // nearest fine / coarse node (x, y)
+  // receiver record (pw_trace_sweep, pw_backward_sweep): per-row flags,
+  // per-node receiver index, the sweep's output states
+  DevBuf rec_rows, rec_map, trace_u, trace_p;
   // adjoint
-  long long epoch = 0;     // bumped by set_medium / set_initial
+  long long epoch = 0;     // bumped by set_medium / set_initial / set_source
   std::unique_ptr<Tape> tape;
   DevBuf stage_rec, stage_seed, stage_out;
   double adj_ms[2] = {0, 0};  // last taped forward, last backward
@@ -332,6 +345,16 @@ void validate(const pw_problem& P) {
   if (P.interp != PW_INTERP_TRIG && P.interp != PW_INTERP_LINEAR && P.interp != PW_INTERP_CUBIC)
     fail(PW_EINVAL, "interp must be PW_INTERP_TRIG, PW_INTERP_LINEAR or PW_INTERP_CUBIC");
   if (P.keep_history != 0 && P.keep_history != 1) fail(PW_EINVAL, "keep_history must be 0 or 1");
+  if (P.bc != PW_PERIODIC && P.bc != PW_SPONGE) fail(PW_EINVAL, "bc must be PW_PERIODIC or PW_SPONGE");
+  if (P.bc == PW_SPONGE) {
+    if (P.dim != 2) fail(PW_EINVAL, "the absorbing layer is implemented for 2D problems only");
+    if (!(P.sponge_width > 0 && P.sponge_width < 0.5))
+      fail(PW_EINVAL, "sponge_width must be in (0, 0.5)");
+    if (!(P.sponge_reflection >= 0 && P.sponge_reflection < 1))
+      fail(PW_EINVAL, "sponge_reflection must be in [0, 1) (0: 1e-3)");
+    if (!(P.sponge_cmax >= 0) || !std::isfinite(P.sponge_cmax))
+      fail(PW_EINVAL, "sponge_cmax must be >= 0 (0: from the medium)");
+  }
 }
 
 void setup(Prob& pr, const pw_problem& P) {
@@ -464,6 +487,14 @@ void setup(Prob& pr, const pw_problem& P) {
     pr.spec.rtmp = m.get_n<double>((long long)P.dim * Nc * N);
     pr.spec.ures = m.get_n<double>(Nc * N);
   }
+  pr.sponge = P.bc == PW_SPONGE;
+  if (pr.sponge) {
+    const long long nf = pr.gf.n[0] + pr.gf.n[1], nc = pr.gc.n[0] + pr.gc.n[1];
+    pr.layF_t = m.get(ts * nf);
+    pr.layC_t = m.get(ts * nc);
+    pr.layF_d = m.get_n<double>(nf);
+    pr.layC_d = m.get_n<double>(nc);
+  }
   pr.res = m.get_n<double>((long long)kRes * (P.max_iters + 1));
   pr.chg = m.get_n<double>(4LL * N);
   if (P.keep_history) {
@@ -525,28 +556,123 @@ StateSet<T> coarse_work(Prob& pr, int s) {
                      tp<T>(pr.cw[s][3])};
 }
 
+// ---- absorbing layer and point source (PW_SPONGE, pw_set_source) --------
+// The layer: sigma = sigma_max (d / w)^2, d the largest penetration of a
+// node into the layer over the axes, so sigma is the largest of the
+// per-axis sigma_a and the factor exp(-sigma h / 2) the smallest of the
+// per-axis factors: one table per axis, min taken in the kernels.  The
+// coarse grid takes sigma at its nodes (fine node ratio * J).
+std::vector<double> layer_axis(int n_fine, double dx, int ratio, double w, double smax, double h) {
+  const double L = n_fine * dx;
+  const int nc = n_fine / ratio;
+  std::vector<double> d((size_t)nc);
+  for (int J = 0; J < nc; ++J) {
+    const double x = (double)(ratio * J) * dx;
+    const double pen = std::max(0.0, w - std::min(x, L - x));
+    const double q = pen / w;
+    const double sig = smax * (q * q);
+    d[(size_t)J] = std::exp(-0.5 * sig * h);
+  }
+  return d;
+}
+
 template <typename T>
-void prop_fine(Prob& pr, const T* u, const T* p, T* uo, T* po, int n, hipStream_t st) {
+void upload_cast(void* dst, const std::vector<double>& v) {
+  std::vector<T> c(v.size());
+  for (size_t i = 0; i < v.size(); ++i) c[i] = (T)v[i];
+  PW_HIP(hipMemcpy(dst, c.data(), sizeof(T) * c.size(), hipMemcpyHostToDevice));
+}
+
+// tables of the layer for the medium's c_max (host copy of c given)
+void setup_layer(Prob& pr, double cmax_medium) {
+  if (!pr.sponge) return;
+  const pw_problem& P = pr.P;
+  const double w = P.sponge_width;
+  const double R = P.sponge_reflection > 0 ? P.sponge_reflection : 1e-3;
+  const double cmax = P.sponge_cmax > 0 ? P.sponge_cmax : cmax_medium;
+  pr.sponge_smax = 3.0 * cmax / (2.0 * w) * std::log(1.0 / R);
+  for (int g = 0; g < 2; ++g) {
+    const int ratio = g == 0 ? 1 : pr.ratio;
+    const double h = g == 0 ? pr.hF : pr.hC;
+    std::vector<double> t = layer_axis(pr.gf.n[0], pr.gf.dx, ratio, w, pr.sponge_smax, h);
+    std::vector<double> ty = layer_axis(pr.gf.n[1], pr.gf.dx, ratio, w, pr.sponge_smax, h);
+    t.insert(t.end(), ty.begin(), ty.end());
+    double* dd = g == 0 ? pr.layF_d : pr.layC_d;
+    void* dt = g == 0 ? pr.layF_t : pr.layC_t;
+    PW_HIP(hipMemcpy(dd, t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice));
+    if (pr.f64) upload_cast<double>(dt, t);
+    else upload_cast<float>(dt, t);
+  }
+}
+
+// Force of a propagation of problem pr on the fine or coarse grid, in
+// precision T (tables: the state dtype's, or double); with the source when
+// `source` (states s start at t_base + s t_state)
+template <typename T>
+Force<T> make_force(const Prob& pr, bool fine, bool source, double t_base, double t_state,
+                    bool state_tables) {
+  Force<T> f;
+  const Grid& g = fine ? pr.gf : pr.gc;
+  if (pr.sponge) {
+    const T* base = state_tables ? tp<T>(fine ? pr.layF_t : pr.layC_t)
+                                 : reinterpret_cast<const T*>(fine ? pr.layF_d : pr.layC_d);
+    f.dmp_x = base;
+    f.dmp_y = base + g.n[0];
+  }
+  if (source && pr.have_src) {
+    const int* node = fine ? pr.srcF : pr.srcC;
+    f.sx = node[0];
+    f.sy = node[1];
+    f.amp = std::pow(g.dx, -(double)g.dim);
+    f.freq = pr.src_freq;
+    f.t0 = pr.src_t0;
+  }
+  f.t_base = t_base;
+  f.t_state = t_state;
+  f.hd = fine ? pr.hF : pr.hC;
+  return f;
+}
+
+bool forced(const Prob& pr) { return pr.sponge || pr.have_src; }
+
+// F of n states; state s propagates slice first_slice + s (from
+// t = (first_slice + s - 1) T / N; only the source depends on it)
+template <typename T>
+void prop_fine(Prob& pr, const T* u, const T* p, T* uo, T* po, int n, hipStream_t st,
+               int first_slice = 1) {
   if (n > pr.N) fail(PW_EINVAL, "too many fine states for one batched propagation");
+  const double dtc = pr.P.T / pr.N;
+  Force<T> fo;
+  if (forced(pr)) fo = make_force<T>(pr, true, true, (first_slice - 1) * dtc, dtc, true);
   propagate<T>(pr.gf, tp<T>(pr.c2f), u, p, uo, po, pr.Nf, n, pr.mF, (T)pr.hF, pr.comp,
-               fine_work<T>(pr, 0), fine_work<T>(pr, 1), st, true);
+               fine_work<T>(pr, 0), fine_work<T>(pr, 1), st, true, forced(pr) ? &fo : nullptr);
 }
 
+// C of n states (slices first_slice, first_slice + 1, ... as prop_fine)
 template <typename T>
-void prop_coarse(Prob& pr, const T* u, const T* p, T* uo, T* po, int n, hipStream_t st) {
+void prop_coarse(Prob& pr, const T* u, const T* p, T* uo, T* po, int n, hipStream_t st,
+                 int first_slice = 1) {
   if (n > pr.N + 1) fail(PW_EINVAL, "too many coarse states for one batched propagation");
+  const double dtc = pr.P.T / pr.N;
+  Force<T> fo;
+  if (forced(pr)) fo = make_force<T>(pr, false, true, (first_slice - 1) * dtc, dtc, true);
   propagate<T>(pr.gc, tp<T>(pr.c2c), u, p, uo, po, pr.Nc, n, pr.mC, (T)pr.hC, pr.comp,
-               coarse_work<T>(pr, 0), coarse_work<T>(pr, 1), st);
+               coarse_work<T>(pr, 0), coarse_work<T>(pr, 1), st, false,
+               forced(pr) ? &fo : nullptr);
 }
 
-// FP64 coarse propagation of state columns [u (Nc) ; p (Nc)] (linear C)
+// FP64 coarse propagation of state columns [u (Nc) ; p (Nc)] (linear C: the
+// layer, never the source -- the columns are differences of states or
+// corrector directions)
 void prop_coarse_cols(Prob& pr, const double* in, double* out, int ncols, hipStream_t st) {
   const long long Nc = pr.Nc;
   if (ncols > std::max(pr.rmax + 1, pr.N)) fail(PW_EINVAL, "too many coarse columns");
   StateSet<double> a{pr.dw[0], pr.dw[0] + Nc, nullptr, nullptr};
   StateSet<double> b{pr.dw[1], pr.dw[1] + Nc, nullptr, nullptr};
+  Force<double> fo;
+  if (pr.sponge) fo = make_force<double>(pr, false, false, 0.0, 0.0, false);
   propagate<double>(pr.gc, pr.c2c_d, in, in + Nc, out, out + Nc, 2 * Nc, ncols, pr.mC, pr.hC,
-                    false, a, b, st);
+                    false, a, b, st, false, pr.sponge ? &fo : nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -798,7 +924,7 @@ void init_phase(Prob& pr, hipStream_t st) {
   for (int n = 1; n <= N; ++n) {
     const T* su = n == 1 ? Rc : Uc + (n - 2) * Nc;
     const T* sp = n == 1 ? Rcp : Ucp + (n - 2) * Nc;
-    prop_coarse<T>(pr, su, sp, Uc + (n - 1) * Nc, Ucp + (n - 1) * Nc, 1, st);
+    prop_coarse<T>(pr, su, sp, Uc + (n - 1) * Nc, Ucp + (n - 1) * Nc, 1, st, n);
   }
   interp_add<T>(pr.gf, pr.gc, pr.ratio, pr.itab, Uc, Nc, (const T*)nullptr, u + Nf, Nf, N,
                 pr.itmp, st);
@@ -1216,7 +1342,7 @@ void serial_fine_typed(Prob& pr, int n, T* uo, T* po, hipStream_t st) {
   for (int i = 0; i < n; ++i) {
     T* du = (i == n - 1) ? uo : bu[i % 2];
     T* dp = (i == n - 1) ? po : bp[i % 2];
-    prop_fine<T>(pr, su, sp, du, dp, 1, st);
+    prop_fine<T>(pr, su, sp, du, dp, 1, st, i + 1);
     su = du;
     sp = dp;
   }
@@ -1239,8 +1365,10 @@ void ensure_tape(Prob& pr, int K) {
   t.epoch = -1;
   const long long N = pr.N, Nf = pr.Nf, Nc = pr.Nc;
   t.Kcap = Kc;
-  t.us = m.get(pr.tsize * Nf * N * Kc);
-  t.ps = m.get(pr.tsize * Nf * N * Kc);
+  // levels 0..Kc-1: slice starts of the iterations; level K: those of the
+  // final iterate u^{K+1} (the start of a receiver record's sweep)
+  t.us = m.get(pr.tsize * Nf * N * (Kc + 1));
+  t.ps = m.get(pr.tsize * Nf * N * (Kc + 1));
   t.W = m.get_n<double>(2 * Nc * N);
   t.Din = m.get_n<double>(2 * Nc * N * Kc);
   t.delta = m.get_n<double>(2 * Nc * N * Kc);
@@ -1314,6 +1442,8 @@ void run_taped_typed(Prob& pr, int K, bool frozen, hipStream_t st) {
       pr.change.push_back(std::nan(""));
     }
   }
+  PW_HIP(hipMemcpyAsync((char*)t.us + sbytes * K, pr.u, sbytes, hipMemcpyDeviceToDevice, st));
+  PW_HIP(hipMemcpyAsync((char*)t.ps + sbytes * K, pr.p, sbytes, hipMemcpyDeviceToDevice, st));
   PW_HIP(hipEventRecord(e1, st));
   PW_HIP(hipEventSynchronize(e1));
   float ms = 0;
@@ -1374,9 +1504,13 @@ void ensure_backward(Prob& pr, int ckpt) {
 
 // d J / d c^2 of J = sum_{n, r} seed[n][r] u^{K+1}_{n+1}(x_r) through the
 // recorded run (frozen correctors), written to t.grad (fine grid, FP64).
+// rec_rows != null: J = sum seed[n][i][r] (u of slice n + 1 after step i + 1
+// of the sweep from u^{K+1}_n) at x_r, the record of pw_trace_sweep (rec_rows,
+// rec_map: its receiver tables on the device).
 template <typename T>
 void backward_typed(Prob& pr, const long long* rec, int nrec, const double* seed, int ckpt,
-                    hipStream_t st) {
+                    hipStream_t st, const int* rec_rows = nullptr,
+                    const int* rec_map = nullptr) {
   Tape& t = *pr.tape;
   const int N = pr.N, K = t.K;
   const long long Nf = pr.Nf, Nc = pr.Nc;
@@ -1396,7 +1530,34 @@ void backward_typed(Prob& pr, const long long* rec, int nrec, const double* seed
   // slot n of A holds the adjoint of the state u_n ([u; p], n = 0..N)
   double* A = t.La;
   double* B = t.Lb;
-  receiver_scatter(seed, rec, nrec, N, A + F2, F2, st);
+  const double dtc = pr.P.T / N;
+  // the layer and source of F, C (slice n from t_{n-1}) and the layer
+  // alone for the coarse propagations of differences
+  Force<double> fF, fCl;
+  if (forced(pr)) {
+    fF = make_force<double>(pr, true, true, 0.0, dtc, false);
+    fCl = make_force<double>(pr, false, false, 0.0, 0.0, false);
+  }
+  const Force<double>* pF = forced(pr) ? &fF : nullptr;
+  const Force<double>* pCl = pr.sponge ? &fCl : nullptr;
+  if (rec_rows) {
+    // the record's sweep from u^{K+1}_n, n = 0..N-1 (tape level K): its
+    // adjoint, with the seeds entering after every step, lands in slots
+    // 0..N-1
+    widen_fields<T>(tp<T>(t.us) + Nf * N * K, Nf, t.Wf, F2, Nf, N, st);
+    widen_fields<T>(tp<T>(t.ps) + Nf * N * K, Nf, t.Wf + Nf, F2, Nf, N, st);
+    Force<double> fS = make_force<double>(pr, true, true, 0.0, dtc, false);
+    fS.rec = rec;
+    fS.rec_rows = rec_rows;
+    fS.rec_map = rec_map;
+    fS.n_rec = nrec;
+    fS.m_tr = pr.mF;
+    fS.seeds = seed;
+    vv_adjoint(gf, t.c2f, t.Wf, t.Wf + Nf, F2, A, A + Nf, F2, t.GF, Nf, N, pr.mF, pr.hF, ckpt,
+               t.as, st, &fS);
+  } else {
+    receiver_scatter(seed, rec, nrec, N, A + F2, F2, st);
+  }
   for (int k = K; k >= 1; --k) {
     const int kk = k - 1;
     const double* E = t.E + ecols * kk;
@@ -1420,7 +1581,7 @@ void backward_typed(Prob& pr, const long long* rec, int nrec, const double* seed
     copy_fields(Din, C2 * N, t.X, C2 * N, C2 * N, 1, st);
     add_inplace(t.X + C2, dl, C2 * (N - 1), st);
     vv_adjoint(gc, pr.c2c_d, t.X, t.X + Nc, C2, t.LA, t.LA + Nc, C2, t.GC, Nc, N, pr.mC, pr.hC,
-               ckpt, t.as, st);
+               ckpt, t.as, st, pCl);
     // LA column n now holds the adjoint of Din_{n+1} = R v_n - R u^k_n
     restrict_transpose_add(gf, pr.ratio, gc, t.LA + C2, C2, A + F2, F2, 1.0, N - 1, st);
     restrict_transpose_add(gf, pr.ratio, gc, t.LA + C2 + Nc, C2, A + F2 + Nf, F2, 1.0, N - 1,
@@ -1429,7 +1590,7 @@ void backward_typed(Prob& pr, const long long* rec, int nrec, const double* seed
     widen_fields<T>(tp<T>(t.us) + Nf * N * kk, Nf, t.Wf, F2, Nf, N, st);
     widen_fields<T>(tp<T>(t.ps) + Nf * N * kk, Nf, t.Wf + Nf, F2, Nf, N, st);
     vv_adjoint(gf, t.c2f, t.Wf, t.Wf + Nf, F2, A + F2, A + F2 + Nf, F2, t.GF, Nf, N, pr.mF, pr.hF,
-               ckpt, t.as, st);
+               ckpt, t.as, st, pF);
     // slot n of A: adjoint of u^k_{n-1} through F; shift into B and add the
     // -R^T part of Din
     copy_fields(A + 2 * F2, F2, B + F2, F2, F2, N - 1, st);
@@ -1447,8 +1608,10 @@ void backward_typed(Prob& pr, const long long* rec, int nrec, const double* seed
   for (int n = N; n >= 1; --n) {
     add_inplace(lam, t.Y + C2 * (n - 1), C2, st);
     const double* Wn = t.W + C2 * (n - 1);
+    Force<double> fCn;
+    if (forced(pr)) fCn = make_force<double>(pr, false, true, (n - 1) * dtc, 0.0, false);
     vv_adjoint(gc, pr.c2c_d, Wn, Wn + Nc, C2, lam, lam + Nc, C2, t.GC, Nc, 1, pr.mC, pr.hC, ckpt,
-               t.as, st);
+               t.as, st, forced(pr) ? &fCn : nullptr);
   }
   // the gradient: fine accumulators + R^T of the coarse ones
   sum_fields(t.GC, Nc, N, t.gc, Nc, false, st);
@@ -1887,22 +2050,53 @@ void rebuild_sweep_columns(Prob& pr, hipStream_t st) {
   set_dc_column(pr.Vp[cur], 2 * Nc, r, Nc, 1.0, st);
 }
 
+// the point source of pw_set_source (pos = null: none)
+void set_source(Prob& pr, const double* pos, double freq, double t0) {
+  if (!pos) {
+    pr.have_src = false;
+    return;
+  }
+  if (pr.gf.dim != 2) fail(PW_EINVAL, "the point source is implemented for 2D problems only");
+  if (!(freq > 0) || !std::isfinite(freq) || !std::isfinite(t0))
+    fail(PW_EINVAL, "the source needs a positive finite frequency and a finite t0");
+  for (int a = 0; a < pr.gf.dim; ++a)
+    if (!std::isfinite(pos[a])) fail(PW_EINVAL, "source position must be finite");
+  // nearest node (ties to even), periodic
+  for (int g = 0; g < 2; ++g) {
+    const Grid& gr = g == 0 ? pr.gf : pr.gc;
+    int* node = g == 0 ? pr.srcF : pr.srcC;
+    for (int a = 0; a < 2; ++a) {
+      const double j = std::nearbyint(pos[a] / gr.dx);
+      long long k = (long long)std::fmod(j, (double)gr.n[a]);
+      if (k < 0) k += gr.n[a];
+      node[a] = (int)k;
+    }
+  }
+  for (int a = 0; a < 3; ++a) pr.src_pos[a] = a < pr.gf.dim ? pos[a] : 0.0;
+  pr.src_freq = freq;
+  pr.src_t0 = t0;
+  pr.have_src = true;
+}
+
 // ---- checkpoint files ---------------------------------------------------
-// Layout (host byte order): "PWCKPT01", int32 number of problems, then per
-// problem: its pw_problem fields as 16 int64 / double slots, int32 flags
+// Layout (host byte order): "PWCKPT02", int32 number of problems, then per
+// problem: its pw_problem fields as 20 int64 / double slots, int32 flags
 // [have_medium, have_initial, have_iterate, variant, k_done, r, cur,
-// samp_n, samp_iters, n_ranks, n_change, history levels, 0, 0, 0, 0], then
-// the blocks that exist: c (Nf doubles); u0, p0 (state dtype); the current
-// iterate n = 1..N; the history levels; ranks; change; the per-iteration
-// record; U~, V~ (rows x r), S~ (r), E, P (2 Nc x (r + 1)); the sampling table.
-constexpr char kCkptMagic[9] = "PWCKPT01";
+// samp_n, samp_iters, n_ranks, n_change, history levels, have_source, 0, 0,
+// 0], then the blocks that exist: c (Nf doubles); u0, p0 (state dtype); the
+// current iterate n = 1..N; the history levels; ranks; change; the
+// per-iteration record; U~, V~ (rows x r), S~ (r), E, P (2 Nc x (r + 1));
+// the sampling table; the source (x, y, freq, t0).
+constexpr char kCkptMagic[9] = "PWCKPT02";
+constexpr int kSlots = 20;
 
 void problem_slots(const pw_problem& P, double* d) {
-  const double v[16] = {(double)P.dim, (double)P.n_fine[0], (double)P.n_fine[1],
-                        (double)P.n_fine[2], (double)P.ratio, P.T, (double)P.n_slices,
-                        (double)P.m_fine, (double)P.m_coarse, (double)P.grad_order, P.svd_tol,
-                        (double)P.state_dtype, (double)P.compensated, (double)P.max_iters,
-                        (double)P.interp, (double)P.keep_history};
+  const double v[kSlots] = {(double)P.dim, (double)P.n_fine[0], (double)P.n_fine[1],
+                            (double)P.n_fine[2], (double)P.ratio, P.T, (double)P.n_slices,
+                            (double)P.m_fine, (double)P.m_coarse, (double)P.grad_order,
+                            P.svd_tol, (double)P.state_dtype, (double)P.compensated,
+                            (double)P.max_iters, (double)P.interp, (double)P.keep_history,
+                            (double)P.bc, P.sponge_width, P.sponge_reflection, P.sponge_cmax};
   std::memcpy(d, v, sizeof(v));
 }
 
@@ -1936,14 +2130,14 @@ void rd_dev(FILE* f, void* d, size_t bytes, hipStream_t st) {
 }
 
 void save_problem(FILE* f, Prob& pr, hipStream_t st) {
-  double slots[16];
+  double slots[kSlots];
   problem_slots(pr.P, slots);
   wr(f, slots, sizeof(slots));
   const int levels = pr.hist_u && pr.have_iterate ? pr.k_done + 1 : 0;
   const int32_t fl[16] = {pr.have_medium, pr.have_initial, pr.have_iterate, pr.variant,
                           pr.k_done, pr.r, pr.cur, pr.samp_n, pr.samp_iters,
-                          (int32_t)pr.ranks.size(), (int32_t)pr.change.size(), levels, 0, 0, 0,
-                          0};
+                          (int32_t)pr.ranks.size(), (int32_t)pr.change.size(), levels,
+                          pr.have_src, 0, 0, 0};
   wr(f, fl, sizeof(fl));
   const size_t fb = pr.tsize * pr.Nf;
   const long long rows = pr.rows, Nc = pr.Nc;
@@ -1971,6 +2165,10 @@ void save_problem(FILE* f, Prob& pr, hipStream_t st) {
   wr_dev(f, pr.E[pr.cur], sizeof(double) * 2 * Nc * (pr.r + 1), st);
   wr_dev(f, pr.Vp[pr.cur], sizeof(double) * 2 * Nc * (pr.r + 1), st);
   if (pr.samp_n > 0) wr_dev(f, pr.samp.p, sizeof(int) * (size_t)pr.samp_n * pr.samp_iters, st);
+  if (pr.have_src) {
+    const double sb[4] = {pr.src_pos[0], pr.src_pos[1], pr.src_freq, pr.src_t0};
+    wr(f, sb, sizeof(sb));
+  }
 }
 
 template <typename T>
@@ -1979,7 +2177,7 @@ void load_medium_typed(Prob& pr, hipStream_t st) {
 }
 
 void load_problem(FILE* f, Prob& pr, hipStream_t st) {
-  double slots[16], mine[16];
+  double slots[kSlots], mine[kSlots];
   rd(f, slots, sizeof(slots));
   problem_slots(pr.P, mine);
   if (std::memcmp(slots, mine, sizeof(slots)) != 0)
@@ -2001,12 +2199,16 @@ void load_problem(FILE* f, Prob& pr, hipStream_t st) {
   if (have_medium) {
     std::vector<double> c((size_t)pr.Nf);
     rd(f, c.data(), sizeof(double) * c.size());
-    for (double x : c)
+    double cmax = 0.0;
+    for (double x : c) {
       if (!(x > 0.0) || !std::isfinite(x)) fail(PW_EINVAL, "checkpoint medium not positive");
+      cmax = std::max(cmax, x);
+    }
     PW_HIP(hipMemcpyAsync(pr.cf, c.data(), sizeof(double) * c.size(), hipMemcpyHostToDevice, st));
     if (pr.f64) load_medium_typed<double>(pr, st);
     else load_medium_typed<float>(pr, st);
     PW_HIP(hipStreamSynchronize(st));
+    setup_layer(pr, cmax);
   }
   if (have_initial) {
     rd_dev(f, pr.u, fb, st);
@@ -2039,6 +2241,13 @@ void load_problem(FILE* f, Prob& pr, hipStream_t st) {
     for (int x : tab)
       if (x < 0 || x >= pr.N) fail(PW_EINVAL, "checkpoint sampling table out of range");
     PW_HIP(hipMemcpy(pr.samp.ensure(bytes), tab.data(), bytes, hipMemcpyHostToDevice));
+  }
+  if (fl[12]) {
+    double sb[4];
+    rd(f, sb, sizeof(sb));
+    set_source(pr, sb, sb[2], sb[3]);
+  } else {
+    set_source(pr, nullptr, 0.0, 0.0);
   }
   pr.have_medium = have_medium;
   pr.have_initial = have_initial;
@@ -2129,8 +2338,21 @@ pw_status pw_set_medium(pw_ctx* ctx, int prob, const double* c, int on_device) {
     if (pr.f64) set_medium_typed<double>(pr, st);
     else set_medium_typed<float>(pr, st);
     PW_HIP(hipStreamSynchronize(st));
+    setup_layer(pr, cmax);
     pr.have_medium = true;
     ++pr.epoch;
+  });
+}
+
+pw_status pw_set_source(pw_ctx* ctx, int prob, const double* pos, double freq, double t0) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    set_source(pr, pos, freq, t0);
+    ++pr.epoch;
+    pr.k_done = 0;
+    pr.have_iterate = false;
+    pr.change.clear();
+    reset_corrector(pr);
   });
 }
 
@@ -2163,6 +2385,9 @@ pw_status pw_run(pw_ctx* ctx, int prob, int K, double stop_tol, int* k_done) {
     if (K < 0 || K > pr.P.max_iters) fail(PW_EINVAL, "K must be in [0, max_iters]");
     if (!(stop_tol >= 0)) fail(PW_EINVAL, "stop_tol must be >= 0");
     check_sampling(pr, K);
+    if (pr.have_src && pr.variant == PW_VARIANT_NO_CORRECTION)
+      fail(PW_EINVAL, "the comparator without correction propagates states, not differences: "
+                      "it does not take a source");
     if (pr.f64) run_typed<double>(pr, K, stop_tol, ctx->stream);
     else run_typed<float>(pr, K, stop_tol, ctx->stream);
     if (k_done) *k_done = pr.k_done;
@@ -2179,6 +2404,8 @@ pw_status pw_continue(pw_ctx* ctx, int prob, int K, int update_corrector, double
       fail(PW_EINVAL, "k_done + K must not exceed max_iters");
     if (!(stop_tol >= 0)) fail(PW_EINVAL, "stop_tol must be >= 0");
     if (update_corrector) check_sampling(pr, pr.k_done + K);
+    if (pr.have_src && pr.variant == PW_VARIANT_NO_CORRECTION)
+      fail(PW_EINVAL, "the comparator without correction does not take a source");
     if (pr.f64) continue_typed<double>(pr, K, update_corrector != 0, stop_tol, ctx->stream);
     else continue_typed<float>(pr, K, update_corrector != 0, stop_tol, ctx->stream);
     if (k_done) *k_done = pr.k_done;
@@ -2641,6 +2868,7 @@ pw_status pw_run_batch(pw_ctx* ctx, int K) {
       if (!pr.have_medium || !pr.have_initial)
         fail(PW_ESTATE, "set medium and initial state of every problem first");
       if (pr.gf.dim != 2) fail(PW_EINVAL, "batched runs need 2D problems");
+      if (forced(pr)) fail(PW_EINVAL, "batched runs take periodic problems without a source");
       if (pr.variant != PW_VARIANT_THETA)
         fail(PW_EINVAL, "batched runs execute Algorithm 3 only (a problem has a variant set)");
       if (pr.f64 != p0.f64 || pr.comp != p0.comp)
@@ -2761,6 +2989,122 @@ const long long* stage_receivers(Prob& pr, const long long* rec, int nrec, int o
   return d;
 }
 
+}  // extern "C"
+
+namespace {
+
+// receiver tables of a record (pw_trace_sweep, pw_backward_sweep): the
+// receivers are checked on the host (inside the grid, distinct), the
+// per-row flags and per-node indices uploaded; returns the device list
+const long long* record_tables(Prob& pr, const long long* rec, int nrec, int on_device,
+                               hipStream_t st) {
+  if (pr.gf.dim != 2) fail(PW_EINVAL, "receiver records are implemented for 2D problems only");
+  const long long* d = stage_receivers(pr, rec, nrec, on_device, st);
+  if (nrec == 0) return d;
+  std::vector<long long> h((size_t)nrec);
+  if (on_device) {
+    PW_HIP(hipMemcpyAsync(h.data(), rec, sizeof(long long) * nrec, hipMemcpyDeviceToHost, st));
+    PW_HIP(hipStreamSynchronize(st));
+  } else {
+    std::memcpy(h.data(), rec, sizeof(long long) * nrec);
+  }
+  std::vector<int> map((size_t)pr.Nf, -1), rows((size_t)pr.gf.n[1], 0);
+  for (int r = 0; r < nrec; ++r) {
+    const long long x = h[(size_t)r];
+    if (map[(size_t)x] >= 0) fail(PW_EINVAL, "receivers of a record must be distinct nodes");
+    map[(size_t)x] = r;
+    rows[(size_t)(x / pr.gf.n[0])] = 1;
+  }
+  PW_HIP(hipMemcpyAsync(pr.rec_map.ensure(sizeof(int) * map.size()), map.data(),
+                        sizeof(int) * map.size(), hipMemcpyHostToDevice, st));
+  PW_HIP(hipMemcpyAsync(pr.rec_rows.ensure(sizeof(int) * rows.size()), rows.data(),
+                        sizeof(int) * rows.size(), hipMemcpyHostToDevice, st));
+  PW_HIP(hipStreamSynchronize(st));
+  return d;
+}
+
+template <typename T>
+void trace_sweep_typed(Prob& pr, const long long* rec, int nrec, double* out, hipStream_t st) {
+  const double dtc = pr.P.T / pr.N;
+  Force<T> fo = make_force<T>(pr, true, true, 0.0, dtc, true);
+  fo.rec = rec;
+  fo.rec_rows = (const int*)pr.rec_rows.p;
+  fo.rec_map = (const int*)pr.rec_map.p;
+  fo.n_rec = nrec;
+  fo.m_tr = pr.mF;
+  fo.traces = out;
+  const size_t bytes = pr.tsize * pr.Nf * pr.N;
+  T* uo = (T*)pr.trace_u.ensure(bytes);
+  T* po = (T*)pr.trace_p.ensure(bytes);
+  propagate<T>(pr.gf, tp<T>(pr.c2f), tp<T>(pr.u), tp<T>(pr.p), uo, po, pr.Nf, pr.N, pr.mF,
+               (T)pr.hF, pr.comp, fine_work<T>(pr, 0), fine_work<T>(pr, 1), st, true, &fo);
+}
+
+// shared by pw_backward (record at the coupling times) and
+// pw_backward_sweep (record of every fine step)
+void backward_common(pw_ctx* ctx, int prob, const long long* receivers, int n_rec,
+                     const double* seed, double* grad, int on_device, int wrt_velocity,
+                     int checkpoint_every, bool sweep) {
+  Prob& pr = get_prob(ctx, prob);
+  hipStream_t st = ctx->stream;
+  if (!pr.tape || pr.tape->epoch < 0)
+    fail(PW_ESTATE, "pw_backward needs a run by pw_run_taped or pw_run_frozen");
+  if (pr.tape->epoch != pr.epoch)
+    fail(PW_ESTATE, "medium or initial state changed since the taped run");
+  if (!grad) fail(PW_EINVAL, "null gradient output");
+  const int ckpt = checkpoint_every > 0 ? checkpoint_every : 64;
+  const long long* rec = sweep ? record_tables(pr, receivers, n_rec, on_device, st)
+                               : stage_receivers(pr, receivers, n_rec, on_device, st);
+  const long long ns = (long long)pr.N * n_rec * (sweep ? pr.mF : 1);
+  const double* sd = nullptr;
+  if (n_rec > 0) {
+    if (!seed) fail(PW_EINVAL, "null seed");
+    sd = (const double*)stage_in(seed, ns, on_device, pr,
+                                 (double*)pr.stage_seed.ensure(sizeof(double) * ns), st);
+  }
+  ensure_backward(pr, ckpt);
+  const int* rows = sweep && n_rec > 0 ? (const int*)pr.rec_rows.p : nullptr;
+  const int* map = sweep && n_rec > 0 ? (const int*)pr.rec_map.p : nullptr;
+  if (sweep && n_rec == 0) rec = nullptr;
+  if (pr.f64) backward_typed<double>(pr, rec, n_rec, sd, ckpt, st, rows, map);
+  else backward_typed<float>(pr, rec, n_rec, sd, ckpt, st, rows, map);
+  Tape& t = *pr.tape;
+  double* g = t.grad;
+  if (wrt_velocity) {
+    // d J / d c = 2 c d J / d c^2
+    mul_fields(pr.cf, t.grad, t.Wf, pr.Nf, 2.0, st);
+    g = t.Wf;
+  }
+  PW_HIP(hipMemcpyAsync(grad, g, sizeof(double) * pr.Nf,
+                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+  PW_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace
+
+extern "C" {
+
+pw_status pw_trace_sweep(pw_ctx* ctx, int prob, const long long* receivers, int n_rec,
+                         double* out, int on_device) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    hipStream_t st = ctx->stream;
+    if (!pr.have_medium) fail(PW_ESTATE, "set the medium first");
+    if (!pr.have_iterate && !(pr.tape && pr.tape->epoch == pr.epoch))
+      fail(PW_ESTATE, "pw_trace_sweep needs an iterate (a run first)");
+    const long long* rec = record_tables(pr, receivers, n_rec, on_device, st);
+    if (n_rec == 0) return;
+    if (!out) fail(PW_EINVAL, "null output");
+    const long long n = (long long)pr.N * pr.mF * n_rec;
+    double* dst = on_device ? out : (double*)pr.stage_out.ensure(sizeof(double) * n);
+    if (pr.f64) trace_sweep_typed<double>(pr, rec, n_rec, dst, st);
+    else trace_sweep_typed<float>(pr, rec, n_rec, dst, st);
+    if (!on_device)
+      PW_HIP(hipMemcpyAsync(out, dst, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    PW_HIP(hipStreamSynchronize(st));
+  });
+}
+
 pw_status pw_traces(pw_ctx* ctx, int prob, const long long* receivers, int n_rec, double* out,
                     int on_device) {
   return guarded([&] {
@@ -2785,39 +3129,21 @@ pw_status pw_traces(pw_ctx* ctx, int prob, const long long* receivers, int n_rec
   });
 }
 
+pw_status pw_backward_sweep(pw_ctx* ctx, int prob, const long long* receivers, int n_rec,
+                            const double* seed, double* grad, int on_device, int wrt_velocity,
+                            int checkpoint_every) {
+  return guarded([&] {
+    backward_common(ctx, prob, receivers, n_rec, seed, grad, on_device, wrt_velocity,
+                    checkpoint_every, true);
+  });
+}
+
 pw_status pw_backward(pw_ctx* ctx, int prob, const long long* receivers, int n_rec,
                       const double* seed, double* grad, int on_device, int wrt_velocity,
                       int checkpoint_every) {
   return guarded([&] {
-    Prob& pr = get_prob(ctx, prob);
-    hipStream_t st = ctx->stream;
-    if (!pr.tape || pr.tape->epoch < 0)
-      fail(PW_ESTATE, "pw_backward needs a run by pw_run_taped or pw_run_frozen");
-    if (pr.tape->epoch != pr.epoch)
-      fail(PW_ESTATE, "medium or initial state changed since the taped run");
-    if (!grad) fail(PW_EINVAL, "null gradient output");
-    const int ckpt = checkpoint_every > 0 ? checkpoint_every : 64;
-    const long long* rec = stage_receivers(pr, receivers, n_rec, on_device, st);
-    const long long ns = (long long)pr.N * n_rec;
-    const double* sd = nullptr;
-    if (n_rec > 0) {
-      if (!seed) fail(PW_EINVAL, "null seed");
-      sd = (const double*)stage_in(seed, ns, on_device, pr,
-                                   (double*)pr.stage_seed.ensure(sizeof(double) * ns), st);
-    }
-    ensure_backward(pr, ckpt);
-    if (pr.f64) backward_typed<double>(pr, rec, n_rec, sd, ckpt, st);
-    else backward_typed<float>(pr, rec, n_rec, sd, ckpt, st);
-    Tape& t = *pr.tape;
-    double* g = t.grad;
-    if (wrt_velocity) {
-      // d J / d c = 2 c d J / d c^2
-      mul_fields(pr.cf, t.grad, t.Wf, pr.Nf, 2.0, st);
-      g = t.Wf;
-    }
-    PW_HIP(hipMemcpyAsync(grad, g, sizeof(double) * pr.Nf,
-                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
-    PW_HIP(hipStreamSynchronize(st));
+    backward_common(ctx, prob, receivers, n_rec, seed, grad, on_device, wrt_velocity,
+                    checkpoint_every, false);
   });
 }
 

@@ -46,6 +46,31 @@ struct Grid {
 // ping-pong between time blocks (each nstates*sstride elements; the e*
 // arrays are only used with compensation).  When m is done in a single
 // launch the scratch sets are not touched.
+// Absorbing layer, point source and receivers of a 2D propagation (the
+// forcing of PW_SPONGE and pw_set_source, include/pw.h).  Every member is
+// optional.  A kick of state s at level i (time t_base + s t_state + i h)
+// first multiplies p by the layer's factor -- d at the first and last half
+// kick of a slice, d^2 where two half kicks meet, d = min(dmp_x[x],
+// dmp_y[y]) = exp(-sigma h / 2) -- then adds its weight (h/2 or h/2 (1+d))
+// times c^2 Lap u + amp r(t) (the last term at the source node only).
+template <typename T>
+struct Force {
+  const T* dmp_x = nullptr;  // layer factor per column (null: no layer)
+  const T* dmp_y = nullptr;  // per row
+  int sx = -1, sy = -1;      // source node (sx < 0: no source)
+  double amp = 0.0, freq = 0.0, t0 = 0.0;  // weight 1 / dx^2, Ricker frequency, peak time
+  double t_base = 0.0;       // start time of the slice of state 0
+  double t_state = 0.0;      // added per state index
+  double hd = 0.0;           // the step h in double (source times)
+  // receivers: per row nonzero if the row holds one; per node its index or -1
+  const int* rec_rows = nullptr;
+  const int* rec_map = nullptr;
+  const long long* rec = nullptr;  // flat node of every receiver
+  int n_rec = 0, m_tr = 0;         // receivers, steps per state of the record
+  double* traces = nullptr;        // forward: u after step i of state s at [(s m_tr + i) n_rec + r]
+  const double* seeds = nullptr;   // adjoint: added to the adjoint of that u, same layout
+};
+
 template <typename T>
 struct StateSet {
   T* u = nullptr;
@@ -56,10 +81,13 @@ struct StateSet {
 
 // `fine` only selects which (otherwise identical) kernel instantiation is
 // launched, so that fine- and coarse-grid launches are told apart in traces.
+// fo (2D grids only): the layer, source and receiver record of the
+// propagation (null: none; see Force).
 template <typename T>
 void propagate(const Grid& g, const T* c2, const T* u_src, const T* p_src, T* u_dst, T* p_dst,
                long long sstride, int nstates, int m, T h, bool compensated, StateSet<T> work_a,
-               StateSet<T> work_b, hipStream_t stream, bool fine = false);
+               StateSet<T> work_b, hipStream_t stream, bool fine = false,
+               const Force<T>* fo = nullptr);
 
 // largest number of steps one launch of the tiled kernel may take for this
 // grid (the whole propagation when the grid is one periodic line in LDS)
@@ -92,6 +120,10 @@ struct StreamDesc {
   // launch at lv_out + j * lv_stride (state s at offset s * sstride)
   T* lv_out;
   long long lv_stride;
+  // forced launches: layer, source, receivers and the level of the slice
+  // at which this launch starts
+  Force<T> f;
+  int step0;
 };
 
 // one propagation of a batch: nstates states of one 2D problem by m steps
@@ -358,11 +390,13 @@ struct AdjScratch {
 // of the trajectory, `level0`, else h) and drifts; u of levels i0+1..i0+m
 // goes to lv + (k - 1) lv_stride, k = 1..m.  p ping-pongs between pa and pb
 // (both distinct from p_src); the returned pointer holds p_{i0+m-1/2}.
-// No closing half kick.
+// No closing half kick.  fo: the layer and source of the trajectory (its
+// receiver members are ignored), i0 the level of the slice at u_src.
 const double* leapfrog_levels2d(const Grid& g, const double* c2, const double* u_src,
                                 const double* p_src, double* pa, double* pb, long long sstride,
                                 int nstates, int m, double h, bool level0, double* lv,
-                                long long lv_stride, hipStream_t stream);
+                                long long lv_stride, hipStream_t stream,
+                                const Force<double>* fo = nullptr, int i0 = 0);
 
 // Reverse of m velocity-Verlet steps (size h, medium c2) of ns states whose
 // inputs are (u0, p0) (state s at offset s * s0).  (lu, lp) hold the adjoint
@@ -370,10 +404,15 @@ const double* leapfrog_levels2d(const Grid& g, const double* c2, const double* u
 // the ns fields gacc[s * sg + J] receive d J / d c2(J) of the ns states:
 // only their sum over s is defined (states 8q .. 8q+7 add their
 // contributions of a reverse step to field q).  The forward trajectory is
-// recomputed from checkpoints taken every `ckpt` steps.
+// recomputed from checkpoints taken every `ckpt` steps.  fo (2D only):
+// the layer and source of the forward propagation (the adjoint applies the
+// layer's factors; the source enters only the recomputed trajectory) and,
+// with fo->seeds, the derivative of J with respect to u at the receivers
+// after every step, added to the adjoint as the reverse pass reaches it.
 void vv_adjoint(const Grid& g, const double* c2, const double* u0, const double* p0,
                 long long s0, double* lu, double* lp, long long sl, double* gacc, long long sg,
-                int ns, int m, double h, int ckpt, const AdjScratch& sc, hipStream_t stream);
+                int ns, int m, double h, int ckpt, const AdjScratch& sc, hipStream_t stream,
+                const Force<double>* fo = nullptr);
 
 template <typename T>
 void widen_fields(const T* in, long long si, double* out, long long so, long long np, int ns,

@@ -318,8 +318,31 @@ __device__ __forceinline__ T lane_down(T v) {  // value of lane + 1
   return lane_shift<0x130>(v);
 }
 
-// one stream (wavefront) of problem descriptor `a`; wid = local wave index
-template <typename T, bool COMP, int B, bool LV = false>
+// p <- f p with the compensation term carried along: the exact product
+// f s is s' + r (r from one fused multiply-add), so the compensated value
+// s - e becomes s' - (f e - r)
+template <typename T, bool COMP>
+__device__ __forceinline__ void kscale(T& s, T& e, T f) {
+  if constexpr (COMP) {
+    const T sf = s * f;
+    const T r = fma(f, s, -sf);
+    e = fma(f, e, -r);
+    s = sf;
+  } else {
+    s *= f;
+  }
+}
+
+// Ricker wavelet (1 - 2a) exp(-a), a = (pi f (t - t0))^2
+__device__ __forceinline__ double ricker_wavelet(double t, double f, double t0) {
+  const double b = 3.141592653589793 * f * (t - t0);
+  const double a = b * b;
+  return (1.0 - 2.0 * a) * exp(-a);
+}
+
+// one stream (wavefront) of problem descriptor `a`; wid = local wave index.
+// FORCED: the layer, source and receivers of a.f (see Force)
+template <typename T, bool COMP, int B, bool LV = false, bool FORCED = false>
 __device__ __forceinline__ void stream2d_body(const StreamDesc<T>& a, long long wid, int lane) {
   constexpr int H = B + 1;
   constexpr int XV = 64 - 2 * H;  // output columns per wave
@@ -352,6 +375,22 @@ __device__ __forceinline__ void stream2d_body(const StreamDesc<T>& a, long long 
   const int tout = last ? 2 * B : 2 * (B - 1);  // lag of the written level
   const int tbeg = Y0 - H - 2;
   const int tend = Y1 - 1 + tout;  // inclusive
+  // forced launches: this lane's column factor of the layer, the slice
+  // start time of this state
+  const bool damp = FORCED && a.f.dmp_x != nullptr;
+  const T dcol = damp ? a.f.dmp_x[gx] : T(1);
+  const double tslice = FORCED ? a.f.t_base + state * a.f.t_state : 0.0;
+  // kick of level `lev` on row r: damp p, then add w (c^2 Lap u + source)
+  auto forced_kick = [&](T& pn, T& ep, T kl, int r, int lev, bool half) {
+    const int ry = wrap_idx(r, ny);
+    const T d = damp ? min(dcol, a.f.dmp_y[ry]) : T(1);
+    if (damp) kscale<T, COMP>(pn, ep, half ? d : d * d);
+    const T w = half ? h * T(0.5) : h * T(0.5) * (T(1) + d);
+    T acc = kl;
+    if (ry == a.f.sy && gx == a.f.sx)
+      acc += T(a.f.amp * ricker_wavelet(tslice + lev * a.f.hd, a.f.freq, a.f.t0));
+    kadd<T, COMP>(pn, ep, w * acc);
+  };
   for (int t = tbeg; t <= tend; ++t) {
     // level 0, row t+2 -> pending slot of stage 0
     if (t + 2 < Y1 + H) {
@@ -377,9 +416,23 @@ __device__ __forceinline__ void stream2d_body(const StreamDesc<T>& a, long long 
         if (COMP)
           lap -= (lane_up(eu) - T(2) * eu + lane_down(eu)) +
                  (weu[j][0] - T(2) * eu + weu[j][2]);
-        const T w = (j == 0 && first) ? h * T(0.5) : h;
-        kadd<T, COMP>(pn, ep, w * (kj * lap));
+        if constexpr (FORCED) {
+          forced_kick(pn, ep, kj * lap, t - 2 * j, a.step0 + j, j == 0 && first);
+        } else {
+          const T w = (j == 0 && first) ? h * T(0.5) : h;
+          kadd<T, COMP>(pn, ep, w * (kj * lap));
+        }
         kadd<T, COMP>(un, eu, h * pn);
+        if constexpr (FORCED) {
+          // receiver record: u after step step0 + j + 1 of the slice
+          const int orow = t - 2 * j;
+          if (a.f.rec_rows && orow >= Y0 && orow < Y1 && a.f.rec_rows[orow]) {
+            const int rid = a.f.rec_map[(long long)orow * nx + gx];
+            if (out_lane && rid >= 0)
+              a.f.traces[((long long)state * a.f.m_tr + a.step0 + j) * a.f.n_rec + rid] =
+                  COMP ? (double)un - (double)eu : (double)un;
+          }
+        }
       }
       qu[j + 1] = un;
       qp[j + 1] = pn;
@@ -412,7 +465,10 @@ __device__ __forceinline__ void stream2d_body(const StreamDesc<T>& a, long long 
       if (COMP)
         lap -= (lane_up(ec) - T(2) * ec + lane_down(ec)) + (weu[B][0] - T(2) * ec + weu[B][2]);
       T pn = wp[B][0], ep = wep[B][0];
-      kadd<T, COMP>(pn, ep, h * T(0.5) * (wk[B][0] * lap));
+      if constexpr (FORCED)
+        forced_kick(pn, ep, wk[B][0] * lap, t - 2 * B, a.step0 + ns, true);
+      else
+        kadd<T, COMP>(pn, ep, h * T(0.5) * (wk[B][0] * lap));
       const int orow = t - 2 * B;
       if (out_lane && orow >= Y0 && orow < Y1) {
         const long long gi = base + (long long)orow * nx + gx;
@@ -463,14 +519,23 @@ __global__ __launch_bounds__(256) void k_prop_stream2d(StreamDesc<T> a) {
   stream2d_body<T, COMP, B>(a, wid, threadIdx.x & 63);
 }
 
+// the same with the layer, source and receivers of a.f
+template <typename T, bool COMP, int B>
+__global__ __launch_bounds__(256) void k_prop_stream2d_forced(StreamDesc<T> a) {
+  const long long nwaves = (long long)a.nstates * a.ncb * a.nseg;
+  const long long wid = launch_wave(nwaves);
+  if (wid >= nwaves) return;
+  stream2d_body<T, COMP, B, false, true>(a, wid, threadIdx.x & 63);
+}
+
 // the same with every produced level of u written to a.lv_out (the forward
 // recomputation of the adjoint)
-template <typename T, int B>
+template <typename T, int B, bool FORCED>
 __global__ __launch_bounds__(256) void k_prop_stream2d_levels(StreamDesc<T> a) {
   const long long nwaves = (long long)a.nstates * a.ncb * a.nseg;
   const long long wid = launch_wave(nwaves);
   if (wid >= nwaves) return;
-  stream2d_body<T, false, B, true>(a, wid, threadIdx.x & 63);
+  stream2d_body<T, false, B, true, FORCED>(a, wid, threadIdx.x & 63);
 }
 
 // many problems of different grids in one launch: wave -> problem through
@@ -784,11 +849,14 @@ constexpr int stream_depth() {
 }
 
 template <typename T, bool COMP, int B = stream_depth<T>()>
-void dispatch_stream2d(const StreamDesc<T>& a, bool fine, hipStream_t st) {
+void dispatch_stream2d(const StreamDesc<T>& a, bool fine, bool forced, hipStream_t st) {
   const long long nwaves = (long long)a.nstates * a.ncb * a.nseg;
   const long long nblk = (nwaves + 3) / 4;
   if (nblk >= (1LL << 31)) fail(PW_EINVAL, "too many streams for one launch");
-  if (fine)
+  if (forced)
+    hipLaunchKernelGGL((k_prop_stream2d_forced<T, COMP, B>), dim3((unsigned)nblk), dim3(256), 0,
+                       st, a);
+  else if (fine)
     hipLaunchKernelGGL((k_prop_stream2d<T, COMP, B, 0>), dim3((unsigned)nblk), dim3(256), 0, st,
                        a);
   else
@@ -828,8 +896,10 @@ void stream_geometry(StreamDesc<T>& a, int nstates, long long want_default = 0) 
 template <typename T, int B>
 void propagate_stream2d_b(const Grid& g, const T* c2, const T* u_src, const T* p_src, T* u_dst,
                           T* p_dst, long long sstride, int nstates, int m, T h, bool comp,
-                          StateSet<T> wa, StateSet<T> wb, bool fine, hipStream_t st) {
+                          StateSet<T> wa, StateSet<T> wb, bool fine, hipStream_t st,
+                          const Force<T>* fo) {
   StreamDesc<T> a{};
+  if (fo) a.f = *fo;
   a.c2 = c2;
   a.sstride = sstride;
   a.nx = g.n[0];
@@ -864,11 +934,12 @@ void propagate_stream2d_b(const Grid& g, const T* c2, const T* u_src, const T* p
     a.p_out = out.p;
     a.eu_out = out.eu;
     a.ep_out = out.ep;
+    a.step0 = l * B;
     if (comp) {
-      if constexpr (sizeof(T) == 4) dispatch_stream2d<T, true, B>(a, fine, st);
+      if constexpr (sizeof(T) == 4) dispatch_stream2d<T, true, B>(a, fine, fo != nullptr, st);
       else fail(PW_EINVAL, "compensation is an FP32 mode");
     } else {
-      dispatch_stream2d<T, false, B>(a, fine, st);
+      dispatch_stream2d<T, false, B>(a, fine, fo != nullptr, st);
     }
     cu = out.u;
     cp = out.p;
@@ -884,18 +955,19 @@ void propagate_stream2d_b(const Grid& g, const T* c2, const T* u_src, const T* p
 template <typename T>
 void propagate_stream2d(const Grid& g, const T* c2, const T* u_src, const T* p_src, T* u_dst,
                         T* p_dst, long long sstride, int nstates, int m, T h, bool comp,
-                        StateSet<T> wa, StateSet<T> wb, bool fine, hipStream_t st) {
+                        StateSet<T> wa, StateSet<T> wb, bool fine, hipStream_t st,
+                        const Force<T>* fo) {
   if constexpr (sizeof(T) == 4) {
     constexpr int XV = 64 - 2 * (stream_depth<T>() + 1);
     const long long lanes = (long long)nstates * ((g.n[0] + XV - 1) / XV);
     if (lanes * ((g.n[1] + 31) / 32) < 256) {
       propagate_stream2d_b<T, 4>(g, c2, u_src, p_src, u_dst, p_dst, sstride, nstates, m, h, comp,
-                                 wa, wb, fine, st);
+                                 wa, wb, fine, st, fo);
       return;
     }
   }
   propagate_stream2d_b<T, stream_depth<T>()>(g, c2, u_src, p_src, u_dst, p_dst, sstride, nstates,
-                                             m, h, comp, wa, wb, fine, st);
+                                             m, h, comp, wa, wb, fine, st, fo);
 }
 
 // launch shape of the 3D streaming kernel per state type: time steps per
@@ -1012,7 +1084,8 @@ bool use_line(const Grid& g) { return g.dim == 1 && g.n[0] <= 4096; }
 const double* leapfrog_levels2d(const Grid& g, const double* c2, const double* u_src,
                                 const double* p_src, double* pa, double* pb, long long sstride,
                                 int nstates, int m, double h, bool level0, double* lv,
-                                long long lv_stride, hipStream_t st) {
+                                long long lv_stride, hipStream_t st, const Force<double>* fo,
+                                int i0) {
   if (g.dim != 2) fail(PW_EINVAL, "leapfrog_levels2d: 2D grids only");
   if (nstates <= 0 || m <= 0) return p_src;
   if (pa == p_src || pb == p_src || pa == pb) fail(PW_EINVAL, "leapfrog_levels2d: p buffers alias");
@@ -1028,6 +1101,11 @@ const double* leapfrog_levels2d(const Grid& g, const double* c2, const double* u
   stream_geometry(a, nstates, 3072);  // measured best for the level-writing kernel
   a.lv_stride = lv_stride;
   a.last = 0;  // leapfrog form: no closing half kick
+  if (fo) {
+    a.f = *fo;
+    a.f.rec_rows = nullptr;  // the recomputation records nothing
+    a.f.traces = nullptr;
+  }
   const int nl = (m + B - 1) / B;
   const double* cp = p_src;
   for (int l = 0; l < nl; ++l) {
@@ -1039,10 +1117,15 @@ const double* leapfrog_levels2d(const Grid& g, const double* c2, const double* u
     a.u_out = lv + (long long)(l * B + a.nsteps - 1) * lv_stride;
     a.p_out = po;
     a.lv_out = lv + (long long)(l * B) * lv_stride;
+    a.step0 = i0 + l * B;
     const long long nwaves = (long long)a.nstates * a.ncb * a.nseg;
     if ((nwaves + 3) / 4 >= (1LL << 31)) fail(PW_EINVAL, "too many streams for one launch");
-    hipLaunchKernelGGL((k_prop_stream2d_levels<double, B>), dim3((unsigned)((nwaves + 3) / 4)),
-                       dim3(256), 0, st, a);
+    if (fo)
+      hipLaunchKernelGGL((k_prop_stream2d_levels<double, B, true>),
+                         dim3((unsigned)((nwaves + 3) / 4)), dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_prop_stream2d_levels<double, B, false>),
+                         dim3((unsigned)((nwaves + 3) / 4)), dim3(256), 0, st, a);
     PW_LAUNCH_CHECK();
     cp = po;
   }
@@ -1079,8 +1162,10 @@ int steps_per_launch(const Grid& g, bool is_double) {
 template <typename T>
 void propagate(const Grid& g, const T* c2, const T* u_src, const T* p_src, T* u_dst, T* p_dst,
                long long sstride, int nstates, int m, T h, bool compensated, StateSet<T> wa,
-               StateSet<T> wb, hipStream_t st, bool fine) {
+               StateSet<T> wb, hipStream_t st, bool fine, const Force<T>* fo) {
   if (nstates <= 0) return;
+  if (fo && g.dim != 2) fail(PW_EINVAL, "the absorbing layer and source are 2D only");
+  if (fo && fo->traces && m <= 0) fail(PW_EINVAL, "a receiver record needs time steps");
   if (m <= 0) {
     for (int s = 0; s < nstates; ++s) {
       PW_HIP(hipMemcpyAsync(u_dst + (long long)s * sstride, u_src + (long long)s * sstride,
@@ -1118,7 +1203,7 @@ void propagate(const Grid& g, const T* c2, const T* u_src, const T* p_src, T* u_
   }
   if (g.dim == 2) {
     propagate_stream2d<T>(g, c2, u_src, p_src, u_dst, p_dst, sstride, nstates, m, h, comp, wa, wb,
-                          fine, st);
+                          fine, st, fo);
     return;
   }
   if (g.dim == 3) {
@@ -1306,9 +1391,10 @@ template void run_multi<double>(const MultiPlan<double>&, const StreamDesc<doubl
 
 template void propagate<float>(const Grid&, const float*, const float*, const float*, float*,
                                float*, long long, int, int, float, bool, StateSet<float>,
-                               StateSet<float>, hipStream_t, bool);
+                               StateSet<float>, hipStream_t, bool, const Force<float>*);
 template void propagate<double>(const Grid&, const double*, const double*, const double*,
                                 double*, double*, long long, int, int, double, bool,
-                                StateSet<double>, StateSet<double>, hipStream_t, bool);
+                                StateSet<double>, StateSet<double>, hipStream_t, bool,
+                                const Force<double>*);
 
 }  // namespace pw

@@ -34,11 +34,30 @@ def test_version_and_error_string():
 
 
 def test_problem_struct_layout():
-    # int dim, int n[3], int ratio, double T, int N, mF, mC, order,
-    # double tol, int dtype, comp, max_iters, interp, keep_history
-    assert ctypes.sizeof(pw.Problem) == 80
-    assert pw.Problem.T.offset == 24
-    assert pw.Problem.svd_tol.offset == 48
+    """The ctypes mirror of pw_problem has the size and field offsets that
+    a C compiler gives the header's struct."""
+    import shutil
+    import subprocess
+    import tempfile
+    names = [n for n, _ in pw.Problem._fields_]
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = "#include <stddef.h>\n#include <stdio.h>\n#include \"pw.h\"\n" \
+          "int main(void) { printf(\"%zu\", sizeof(pw_problem));" + "".join(
+              f' printf(" %zu", offsetof(pw_problem, {n}));' for n in names) + \
+          " return 0; }\n"
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        open(c, "w").write(src)
+        subprocess.run([cc, "-I", os.path.dirname(HEADER), c, "-o", exe],
+                       check=True)
+        got = [int(x) for x in subprocess.run([exe], check=True,
+                                              capture_output=True,
+                                              text=True).stdout.split()]
+    assert got[0] == ctypes.sizeof(pw.Problem)
+    assert got[1:] == [getattr(pw.Problem, n).offset for n in names]
 
 
 def _create(P):
@@ -80,6 +99,21 @@ def test_invalid_problems_rejected_before_any_device_work():
     bad_axis = mk()
     bad_axis.n_fine[2] = 3
     cases.append((bad_axis, "unused axes"))
+    # the absorbing layer: 2D only, width in (0, 0.5), reflection in [0, 1)
+    bad_bc = mk()
+    bad_bc.bc = 2
+    cases.append((bad_bc, "bc must be"))
+    sp1d = pw.Problem.make((64,), 4, 0.25, 4, 8, 2, sponge_width=0.1)
+    cases.append((sp1d, "2D problems only"))
+    wide = mk()
+    wide.bc, wide.sponge_width = pw.SPONGE, 0.5
+    cases.append((wide, "sponge_width"))
+    refl = mk()
+    refl.bc, refl.sponge_width, refl.sponge_reflection = pw.SPONGE, 0.1, 1.0
+    cases.append((refl, "sponge_reflection"))
+    cmax = mk()
+    cmax.bc, cmax.sponge_width, cmax.sponge_cmax = pw.SPONGE, 0.1, -1.0
+    cases.append((cmax, "sponge_cmax"))
     for P, msg in cases:
         st, err = _create(P)
         assert st == -1, (msg, st, err)

@@ -224,18 +224,30 @@ def test_backward_call_order_and_argument_errors():
 
 def test_full_size_gradient_directional_fd():
     """At the full misfit workload size (512^2, N = 32, m_F = 96, 128
-    receivers; FP64 states, K = 2, checkpoints every 64 steps) the oracle
-    cannot run; the property checked is <grad, e> = central difference of J
-    through the GPU's frozen forward, for a smooth random direction e."""
+    receivers recorded every fine step, absorbing layer and point source;
+    FP64 states, K = 2, checkpoints every 64 steps) the oracle cannot run;
+    the property checked is <grad, e> = central difference of J through the
+    GPU's frozen forward, for a smooth random direction e."""
+    import paper_1905_00473_amd as pw
     K = 2
-    w, rec, _ = W.misfit2d(K=K, dtype="f64", compensated=False)
+    w, rec, _, fd = W.misfit2d(K=K, dtype="f64", compensated=False)
     print(f"full-size adjoint {w.shape} N={w.N} m_F={w.m_fine}", flush=True)
-    data = 0.01 * np.random.default_rng(3).standard_normal((w.N, rec.size))
-    s, _ = _solver(w, K)
+    data = 0.01 * np.random.default_rng(3).standard_normal(
+        (w.N, w.m_fine, rec.size))
+    P = pw.Problem.make(w.shape, w.ratio, w.T, w.N, w.m_fine, w.m_coarse,
+                        w.grad_order, w.tol, "f64", False, K,
+                        sponge_width=fd["width"],
+                        sponge_reflection=fd["reflection"],
+                        sponge_cmax=fd["c_max"])
+    s = pw.Solver(P)
+    s.set_medium(w.c)
+    s.set_source(fd["src_pos"], fd["freq"], fd["t0"])
+    s.set_initial(w.u0, w.p0)
+    dt = w.T / w.N / w.m_fine
     s.run_taped(K)
-    seed = to_np(s.traces(rec)) - data
-    J0 = 0.5 * float(np.sum(seed * seed))
-    g = to_np(s.backward(rec, seed, wrt="c2", checkpoint_every=64))
+    res = to_np(s.trace_sweep(rec)) - data
+    J0 = 0.5 * dt * float(np.sum(res * res))
+    g = to_np(s.backward_sweep(rec, dt * res, wrt="c2", checkpoint_every=64))
     assert np.all(np.isfinite(g)) and np.abs(g).max() > 0
     e = W.smooth_random_field(w.shape, 0.05, 7)
     c2 = w.c * w.c
@@ -244,12 +256,12 @@ def test_full_size_gradient_directional_fd():
     def J_at(x):
         s.set_medium(np.sqrt(x))
         s.run_frozen(K)
-        d = to_np(s.traces(rec)) - data
-        return 0.5 * float(np.sum(d * d))
+        d = to_np(s.trace_sweep(rec)) - data
+        return 0.5 * dt * float(np.sum(d * d))
 
-    fd = (J_at(c2 + eps * e) - J_at(c2 - eps * e)) / (2 * eps)
+    fd_ = (J_at(c2 + eps * e) - J_at(c2 - eps * e)) / (2 * eps)
     ad = float(np.sum(g * e))
-    assert ad == pytest.approx(fd, rel=1e-5, abs=1e-12 * J0), (ad, fd)
+    assert ad == pytest.approx(fd_, rel=1e-5, abs=1e-12 * J0), (ad, fd_)
     s.close()
 
 

@@ -22,12 +22,15 @@ Workloads (fine grid / coarse grid, unit periodic box):
   m_C = 19), K = 6, FP32 compensated state, tol 1e-13.
 
 * ``misfit_case`` small receiver-misfit problems in 1D/2D/3D (smooth
-  medium, Ricker-shaped initial pulse, a line of receivers, random data)
-  and ``misfit2d`` the full-size one: 512^2 / 128^2, c = 1 + 2 s with s a
-  min-max normalised Gaussian random field (correlation 0.1, seed 0),
-  Ricker-shaped pulse of peak frequency 10 at (0.5, 0.1), 128 receivers
-  at x = (i + 1/2)/128, y = 0.9 (nearest nodes), T = 1, N = 32, m_F = 96,
-  m_C = 24, K = 4; target medium for the data: the same recipe, seed 1.
+  medium, Ricker-shaped initial pulse, a line of receivers, random data),
+  ``forced_misfit_case`` the same in 2D with an absorbing layer and a point
+  source, and ``misfit2d`` the full-size one: 512^2 / 128^2, c = 1 + 2 s
+  with s a min-max normalised Gaussian random field (correlation 0.1, seed
+  0), zero initial state, an absorbing layer of width 0.05 (round trip
+  1e-3 at c_max = 3), a Ricker source of peak frequency 10 (peak time 0.1)
+  at (0.5, 0.1), 128 receivers at x = (i + 1/2)/128, y = 0.9 (nearest
+  nodes) recorded every fine step, T = 1, N = 32, m_F = 96, m_C = 24,
+  K = 4; target medium for the data: the same recipe, seed 1.
 * ``random_pulses`` seeded Gaussian-pulse states (test inputs of the
   propagators at full size).
 * ``waveguide2d`` the low-rank study of the data matrices (Sec. 6.5):
@@ -287,6 +290,30 @@ def misfit_case(shape=(32, 32), ratio=4, N=4, K=2, T=0.25, m_fine=8,
     return w, receivers, data
 
 
+def forced_misfit_case(shape=(32, 32), ratio=4, N=4, K=2, T=0.25, m_fine=8,
+                       m_coarse=2, tol=1e-6, seed=0, dtype="f64", width=0.2,
+                       c_max=2.0):
+    """A small misfit problem with an absorbing layer and a point source:
+    the medium and receivers of misfit_case, zero initial state, a layer of
+    the given width (sigma_max for c_max, round trip 1e-3), a Ricker source
+    (peak frequency 8, peak time 0.05) at x = 0.5, y = 0.3 (2D; 0.3 along x
+    in 1D) and data 0.01 * N(0, 1) of shape (N, m_fine, n_receivers) for a
+    record sampled every fine step (seed).  Returns (Workload, receivers,
+    data, forcing) with forcing a dict of the layer and source parameters
+    (x first)."""
+    w, receivers, _ = misfit_case(shape, ratio, N, K, T, m_fine, m_coarse,
+                                  tol, seed, dtype)
+    w.name = "forced_misfit_case"
+    w.u0 = np.zeros(w.shape)
+    w.p0 = np.zeros(w.shape)
+    pos = (0.3,) if len(w.shape) == 1 else (0.5, 0.3) + (0.5,) * (len(w.shape) - 2)
+    forcing = {"width": width, "reflection": 1e-3, "src_pos": pos,
+               "freq": 8.0, "t0": 0.05, "c_max": c_max}
+    data = 0.01 * np.random.default_rng(seed).standard_normal(
+        (N, m_fine, receivers.size))
+    return w, receivers, data, forcing
+
+
 def misfit_medium(shape, seed):
     """c = 1 + 2 s, s a min-max normalised Gaussian random field of
     correlation length 0.1 (seed)."""
@@ -297,13 +324,19 @@ def misfit_medium(shape, seed):
 
 def misfit2d(n=512, ratio=4, N=32, K=4, T=1.0, dtype="f32",
              compensated=True, n_receivers=128):
-    """The full-size receiver-misfit workload (medium seed 0; the data are
-    traces for the target medium misfit_medium(shape, 1)).
-    Returns (Workload, receivers, target medium)."""
+    """The full-size receiver-misfit workload with an absorbing layer and a
+    point source: medium seed 0 (target medium misfit_medium(shape, 1) for
+    the data), zero initial state, a layer of width 0.05 on every face
+    (round trip 1e-3 at c_max = 3, the medium's upper bound), a Ricker
+    source of peak frequency 10 and peak time 0.1 at (0.5, 0.1), 128
+    receivers at x = (i + 1/2) / 128, y = 0.9 (nearest nodes), the record
+    sampled every fine step.  Returns (Workload, receivers, target medium,
+    forcing) with forcing a dict of the layer and source parameters (x
+    first)."""
     shape = (n, n)
     c = misfit_medium(shape, 0)
     target = misfit_medium(shape, 1)
-    u0 = ricker_pulse(shape, (0.1, 0.5), 10.0)
+    u0 = np.zeros(shape)
     p0 = np.zeros(shape)
     m_f = _steps_for_courant(3.0, n, T / N)
     xs = np.floor((np.arange(n_receivers) + 0.5) / n_receivers * n + 0.5)
@@ -311,7 +344,9 @@ def misfit2d(n=512, ratio=4, N=32, K=4, T=1.0, dtype="f32",
     receivers = (y * n + xs.astype(np.int64)).astype(np.int64)
     w = Workload("misfit2d", shape, ratio, T, N, m_f, m_f // 4, K, 1e-13, 4,
                  dtype, compensated, c, u0, p0)
-    return w, receivers, target
+    forcing = {"width": 0.05, "reflection": 1e-3, "src_pos": (0.5, 0.1),
+               "freq": 10.0, "t0": 0.1, "c_max": 3.0}
+    return w, receivers, target, forcing
 
 
 BY_NAME = {"wave1d": wave1d, "disc2d": disc2d, "layers3d": layers3d,
