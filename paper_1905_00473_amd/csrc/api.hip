@@ -535,8 +535,6 @@ void setup(Prob& pr, const pw_problem& P) {
   pr.os2.work = pr.gwork2;
   pr.os2.work_elems = pr.gwork_elems;
   for (int i = 0; i < 4; ++i) PW_HIP(hipEventCreate(&pr.ev[i]));
-  PW_HIP(hipStreamCreateWithFlags(&pr.side, hipStreamNonBlocking));
-  PW_HIP(hipStreamCreateWithFlags(&pr.own, hipStreamNonBlocking));
   PW_HIP(hipEventCreateWithFlags(&pr.done_ev, hipEventDisableTiming));
   PW_HIP(hipEventCreateWithFlags(&pr.fork_ev, hipEventDisableTiming));
   PW_HIP(hipEventCreateWithFlags(&pr.join_ev, hipEventDisableTiming));
@@ -2288,6 +2286,18 @@ pw_status pw_create(const pw_problem* probs, int n_problems, void* stream, pw_ct
       setup(*pr, probs[i]);
       ctx->probs.push_back(std::move(pr));
     }
+    // The runtime spreads streams over its hardware queues in creation
+    // order (round robin).  Problem i's own stream (its corrector and
+    // sweep in a batch, the F branch of Algorithm 1) is created i-th and
+    // its side stream (the G branch) in a second pass rotated by two, so
+    // that the own streams cover every queue and a problem's two branches
+    // sit on different queues (created in pairs, the own streams of all
+    // problems shared half of the queues).
+    for (int i = 0; i < n_problems; ++i)
+      PW_HIP(hipStreamCreateWithFlags(&ctx->probs[(size_t)i]->own, hipStreamNonBlocking));
+    for (int i = 0; i < n_problems; ++i)
+      PW_HIP(hipStreamCreateWithFlags(&ctx->probs[(size_t)((i + 2) % n_problems)]->side,
+                                      hipStreamNonBlocking));
     PW_HIP(hipDeviceSynchronize());
     *out = ctx.release();
   });
