@@ -206,6 +206,7 @@ struct Prob {
   hipStream_t own = nullptr;
   hipEvent_t done_ev = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  hipEvent_t pre_ev = nullptr;  // batch: this problem's core matrix is formed
   int variant = PW_VARIANT_THETA;  // iteration run by pw_run
   DevBuf samp;                     // sampled data columns, samp_iters x samp_n
   int samp_n = 0, samp_iters = 0;
@@ -256,6 +257,7 @@ struct Prob {
       if (e) (void)hipEventDestroy(e);
     if (fork_ev) (void)hipEventDestroy(fork_ev);
     if (join_ev) (void)hipEventDestroy(join_ev);
+    if (pre_ev) (void)hipEventDestroy(pre_ev);
     if (side) (void)hipStreamDestroy(side);
     if (own) (void)hipStreamDestroy(own);
     if (done_ev) (void)hipEventDestroy(done_ev);
@@ -290,8 +292,12 @@ struct Batch {
   double ms[4] = {0, 0, 0, 0};
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t fork_ev = nullptr;  // end of the parallel phase (problem streams wait on it)
+  hipEvent_t svd_ev = nullptr;   // the problems' SVDs are done
+  void* svd_jobs = nullptr;      // device scratch of svd_jacobi_multi
+  int* svd_counts = nullptr;
   ~Batch() {
     if (fork_ev) (void)hipEventDestroy(fork_ev);
+    if (svd_ev) (void)hipEventDestroy(svd_ev);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -538,6 +544,7 @@ void setup(Prob& pr, const pw_problem& P) {
   PW_HIP(hipEventCreateWithFlags(&pr.done_ev, hipEventDisableTiming));
   PW_HIP(hipEventCreateWithFlags(&pr.fork_ev, hipEventDisableTiming));
   PW_HIP(hipEventCreateWithFlags(&pr.join_ev, hipEventDisableTiming));
+  PW_HIP(hipEventCreateWithFlags(&pr.pre_ev, hipEventDisableTiming));
 }
 
 // ---------------------------------------------------------------------------
@@ -749,9 +756,18 @@ void range_basis(Prob& pr, const double* A, int nd, const double* Om, int l, dou
 // Algorithm 1 on F, G (rows x ncols); with cols (device, ncols entries) it
 // runs on the columns F[:, cols], G[:, cols] instead (random subsampling of
 // the data matrices)
-void update_svd_dev(Prob& pr, const double* F, const double* G, int ncols, hipStream_t st,
-                    const int* cols = nullptr, double* norms = nullptr,
-                    const double* sketch = nullptr) {
+// Algorithm 1 in two halves around the SVD of its core matrix: the first
+// forms H (n x n, pr.H) and returns n and the number of new basis columns;
+// the second takes the SVD (pr.X, pr.Y, pr.sig, pr.rank_dev) and updates
+// the corrector.  update_svd_dev runs both with the SVD in between; the
+// batch runs the SVDs of all its problems together (svd_jacobi_multi).
+struct SvdPending {
+  int n = 0, nnew = 0;
+};
+
+SvdPending update_svd_begin(Prob& pr, const double* F, const double* G, int ncols,
+                            hipStream_t st, const int* cols = nullptr, double* norms = nullptr,
+                            const double* sketch = nullptr) {
   const long long rows = pr.rows;
   const int r = pr.r;
   const int cur = pr.cur, nxt = 1 - pr.cur;
@@ -831,7 +847,20 @@ void update_svd_dev(Prob& pr, const double* F, const double* G, int ncols, hipSt
     gemm_small(n, n, ncols, 1.0, pr.Af, n, false, pr.Bg, n, true, 0.0, pr.H, n, st);
     add_diag(n, r, pr.S, pr.H, n, st);
   }
-  svd_jacobi(n, pr.H, pr.X, pr.Y, pr.sig, pr.tol, pr.rank_dev, pr.Hw, pr.Vw, pr.counters, st);
+  return SvdPending{n, nnew};
+}
+
+SvdJob svd_job(Prob& pr, int n) {
+  return SvdJob{n,        pr.H,  pr.X,  pr.Y,  pr.sig,     pr.tol,
+                pr.rank_dev, pr.Hw, pr.Vw, pr.counters};
+}
+
+void update_svd_end(Prob& pr, const SvdPending& sp, hipStream_t st) {
+  const long long rows = pr.rows;
+  const int r = pr.r, n = sp.n, nnew = sp.nnew;
+  const int cur = pr.cur, nxt = 1 - pr.cur;
+  double* U = pr.Ub[cur];
+  double* V = pr.Vb[cur];
   int rn = 0;
   sync_rank(pr, st, &rn);
   rn = std::min(rn, pr.rmax);
@@ -852,6 +881,15 @@ void update_svd_dev(Prob& pr, const double* F, const double* G, int ncols, hipSt
     PW_HIP(hipMemcpyAsync(pr.S, pr.sig, sizeof(double) * rn, hipMemcpyDeviceToDevice, st));
   pr.cur = nxt;
   pr.r = rn;
+}
+
+void update_svd_dev(Prob& pr, const double* F, const double* G, int ncols, hipStream_t st,
+                    const int* cols = nullptr, double* norms = nullptr,
+                    const double* sketch = nullptr) {
+  const SvdPending sp = update_svd_begin(pr, F, G, ncols, st, cols, norms, sketch);
+  const SvdJob q = svd_job(pr, sp.n);
+  svd_jacobi(q.n, q.H, q.X, q.Y, q.sig, q.tol, q.rank_dev, q.Hw, q.Vw, q.counters, st);
+  update_svd_end(pr, sp, st);
 }
 
 void check_sampling(const Prob& pr, int K) {
@@ -937,9 +975,10 @@ void restrict_phase(Prob& pr, hipStream_t st) {
   restrict_fields<T>(pr.gf, pr.ratio, pr.gc, tp<T>(pr.p), pr.Nf, tp<T>(pr.Rcp), pr.Nc, pr.N, st);
 }
 
-// 2. data matrices, Algorithm 1 and the residual rho_k
+// 2. data matrices, Algorithm 1 and the residual rho_k, in two halves
+// around the SVD of Algorithm 1's core matrix (see update_svd_begin)
 template <typename T>
-void corrector_phase(Prob& pr, int k, hipStream_t st) {
+SvdPending corrector_begin(Prob& pr, int k, hipStream_t st) {
   const int N = pr.N;
   const long long Nf = pr.Nf, Nc = pr.Nc, rows = pr.rows;
   energy_columns<T>(pr.gf, pr.ratio, pr.gc, tp<T>(pr.v), tp<T>(pr.vp), Nf, pr.cc, pr.order,
@@ -949,15 +988,23 @@ void corrector_phase(Prob& pr, int k, hipStream_t st) {
   double* rk = pr.res + (long long)kRes * (k - 1);
   if (pr.samp_n > 0) {
     if (k > pr.samp_iters) fail(PW_EINVAL, "no sampled columns for this iteration");
-    update_svd_dev(pr, pr.Fm, pr.Gm, pr.samp_n, st,
-                   (const int*)pr.samp.p + (long long)(k - 1) * pr.samp_n, rk + 2);
-  } else if (pr.sk_l > 0) {
-    if (k > pr.sk_iters) fail(PW_EINVAL, "no sketch test matrix for this iteration");
-    update_svd_dev(pr, pr.Fm, pr.Gm, N, st, nullptr, rk + 2,
-                   (const double*)pr.sk.p + (long long)(k - 1) * N * pr.sk_l);
-  } else {
-    update_svd_dev(pr, pr.Fm, pr.Gm, N, st, nullptr, rk + 2);
+    return update_svd_begin(pr, pr.Fm, pr.Gm, pr.samp_n, st,
+                            (const int*)pr.samp.p + (long long)(k - 1) * pr.samp_n, rk + 2);
   }
+  if (pr.sk_l > 0) {
+    if (k > pr.sk_iters) fail(PW_EINVAL, "no sketch test matrix for this iteration");
+    return update_svd_begin(pr, pr.Fm, pr.Gm, N, st, nullptr, rk + 2,
+                            (const double*)pr.sk.p + (long long)(k - 1) * N * pr.sk_l);
+  }
+  return update_svd_begin(pr, pr.Fm, pr.Gm, N, st, nullptr, rk + 2);
+}
+
+template <typename T>
+void corrector_end(Prob& pr, int k, const SvdPending& sp, hipStream_t st) {
+  const int N = pr.N;
+  const long long rows = pr.rows;
+  double* rk = pr.res + (long long)kRes * (k - 1);
+  update_svd_end(pr, sp, st);
   pr.ranks.push_back(pr.r);
   // rho_k: || F - U (V^T G) ||_F / ||F||_F
   const int r = pr.r;
@@ -968,6 +1015,14 @@ void corrector_phase(Prob& pr, int k, hipStream_t st) {
   frob_norm2(pr.Fp, rows, N, rows, pr.red, rk, st);
   frob_norm2(pr.Fm, rows, N, rows, pr.red, rk + 1, st);
   vec_sum(pr.S, r, rk + 4, st);
+}
+
+template <typename T>
+void corrector_phase(Prob& pr, int k, hipStream_t st) {
+  const SvdPending sp = corrector_begin<T>(pr, k, st);
+  const SvdJob q = svd_job(pr, sp.n);
+  svd_jacobi(q.n, q.H, q.X, q.Y, q.sig, q.tol, q.rank_dev, q.Hw, q.Vw, q.counters, st);
+  corrector_end<T>(pr, k, sp, st);
 }
 
 // a_n = R v_{n-1} - R u^k_{n-1} (double coarse columns), v_0 = u0 -> column 0
@@ -1897,18 +1952,11 @@ void build_batch(pw_ctx* ctx, Batch& b) {
   b.built = true;
 }
 
-// The corrector (data matrices, Algorithm 1) and the corrected sweep of
-// every problem of a batch, after the batched parallel phase enqueued on
-// `st`: each problem runs on its own stream, driven by one of a few host
-// threads, so that the problems' chains of small launches and the host
-// synchronisations inside Algorithm 1 (the rank read-back, the Jacobi
-// convergence test) overlap across problems.  The context stream then
-// waits for every problem.
-template <typename T>
-void concurrent_serial_phase(pw_ctx* ctx, int k, hipStream_t st) {
+// run fn(problem index) for every problem on a pool of host threads; the
+// first error is rethrown after every problem stream has drained
+template <typename Fn>
+void for_problems(pw_ctx* ctx, Fn fn) {
   const int np = (int)ctx->probs.size();
-  hipEvent_t start = ctx->batch->fork_ev;
-  PW_HIP(hipEventRecord(start, st));
   std::atomic<int> next{0};
   std::vector<Error> errs;
   std::mutex mu;
@@ -1916,12 +1964,8 @@ void concurrent_serial_phase(pw_ctx* ctx, int k, hipStream_t st) {
     for (;;) {
       const int i = next.fetch_add(1);
       if (i >= np) return;
-      Prob& pr = *ctx->probs[(size_t)i];
       try {
-        PW_HIP(hipStreamWaitEvent(pr.own, start, 0));
-        corrector_phase<T>(pr, k, pr.own);
-        sweep_phase<T>(pr, pr.own);
-        PW_HIP(hipEventRecord(pr.done_ev, pr.own));
+        fn(i);
       } catch (const Error& e) {
         std::lock_guard<std::mutex> lock(mu);
         errs.push_back(e);
@@ -1944,10 +1988,52 @@ void concurrent_serial_phase(pw_ctx* ctx, int k, hipStream_t st) {
   worker();
   for (auto& th : pool) th.join();
   if (!errs.empty()) {
-    // let every problem stream drain before reporting
     for (auto& up : ctx->probs) (void)hipStreamSynchronize(up->own);
     throw errs.front();
   }
+}
+
+// The corrector (data matrices, Algorithm 1) and the corrected sweep of
+// every problem of a batch, after the batched parallel phase enqueued on
+// `st`: each problem's Algorithm 1 up to its core matrix on its own stream
+// (driven by one of a few host threads, so that the problems' chains of
+// small launches and host synchronisations overlap), then the SVDs of all
+// core matrices together on `st` (one launch per Jacobi round for all of
+// them), then each problem's rest of Algorithm 1 and its sweep on its own
+// stream again.  The context stream then waits for every problem.
+template <typename T>
+void concurrent_serial_phase(pw_ctx* ctx, int k, hipStream_t st) {
+  const int np = (int)ctx->probs.size();
+  Batch& b = *ctx->batch;
+  hipEvent_t start = b.fork_ev;
+  PW_HIP(hipEventRecord(start, st));
+  std::vector<SvdPending> sp((size_t)np);
+  for_problems(ctx, [&](int i) {
+    Prob& pr = *ctx->probs[(size_t)i];
+    PW_HIP(hipStreamWaitEvent(pr.own, start, 0));
+    sp[(size_t)i] = corrector_begin<T>(pr, k, pr.own);
+    PW_HIP(hipEventRecord(pr.pre_ev, pr.own));
+  });
+  std::vector<SvdJob> jobs;
+  for (int i = 0; i < np; ++i) {
+    Prob& pr = *ctx->probs[(size_t)i];
+    PW_HIP(hipStreamWaitEvent(st, pr.pre_ev, 0));
+    jobs.push_back(svd_job(pr, sp[(size_t)i].n));
+  }
+  if (!b.svd_jobs) {
+    b.svd_jobs = b.mem.get(2 * (size_t)np * svd_multi_job_bytes());
+    b.svd_counts = b.mem.get_n<int>(np);
+    PW_HIP(hipEventCreateWithFlags(&b.svd_ev, hipEventDisableTiming));
+  }
+  svd_jacobi_multi(jobs, b.svd_jobs, b.svd_counts, st);
+  PW_HIP(hipEventRecord(b.svd_ev, st));
+  for_problems(ctx, [&](int i) {
+    Prob& pr = *ctx->probs[(size_t)i];
+    PW_HIP(hipStreamWaitEvent(pr.own, b.svd_ev, 0));
+    corrector_end<T>(pr, k, sp[(size_t)i], pr.own);
+    sweep_phase<T>(pr, pr.own);
+    PW_HIP(hipEventRecord(pr.done_ev, pr.own));
+  });
   for (auto& up : ctx->probs) PW_HIP(hipStreamWaitEvent(st, up->done_ev, 0));
 }
 

@@ -467,15 +467,21 @@ __device__ __forceinline__ void pair_rotation(const double* G, int i, int partne
   *rot = true;
 }
 
-// rows of one staged block column (the block path takes n <= kJRows)
+// rows of one staged block column (the block path takes n <= kJRows; a
+// launch whose matrices all have n <= kJRowsSmall stages only that many,
+// with a quarter of the LDS, so that several workgroups share a CU)
 constexpr int kJRows = 1024;
-constexpr int kJLd = kJRows + 1;  // odd stride: the 16 columns fall in distinct LDS banks
+constexpr int kJRowsSmall = 256;
 
-__global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round, double* H,
-                                                      double* V, int* counter,
-                                                      const double* fro2, double* cnorm2) {
-  constexpr int RPT = kJRows / 256;  // staged rows per thread and column
-  constexpr int VT = 8;              // V tiles per wave prefetched at the start
+// one block pair of one round (see k_jacobi_block); lb: the workgroup's
+// index among the pairs of this matrix
+template <int ROWS>
+__device__ __forceinline__ void jacobi_block_pair(int n, int npb, int round, int lb, double* H,
+                                                  double* V, int* counter, const double* fro2,
+                                                  double* cnorm2) {
+  constexpr int kJLd = ROWS + 1;  // odd stride: the 16 columns fall in distinct LDS banks
+  constexpr int RPT = ROWS / 256;  // staged rows per thread and column
+  constexpr int VT = 8;            // V tiles per wave prefetched at the start
   __shared__ double Hs[kJC * kJLd];
   __shared__ double Gp[4][kJC * kJC];
   __shared__ double G[2][kJC * kJC];
@@ -490,7 +496,7 @@ __global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round,
   // which moves to a neighbouring pair index from one round to the next,
   // mostly stays in the same XCD's L2
   const int np2 = npb / 2, per = (np2 + 7) / 8;
-  const int pair = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  const int pair = (lb % 8) * per + lb / 8;
   if (pair >= np2) return;
   int bp = rr_index(pair, round, npb);
   int bq = rr_index(npb - 1 - pair, round, npb);
@@ -704,9 +710,16 @@ __global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round,
   if (tid == 0) atomicAdd(counter, nrot);
 }
 
+template <int ROWS>
+__global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round, double* H,
+                                                      double* V, int* counter,
+                                                      const double* fro2, double* cnorm2) {
+  jacobi_block_pair<ROWS>(n, npb, round, (int)blockIdx.x, H, V, counter, fro2, cnorm2);
+}
+
 // column order of the next sweep: descending norm, ties by index (one
 // workgroup; n <= kJRows).  perm[k] = the column that goes to position k.
-__global__ __launch_bounds__(1024) void k_norm_order(int n, const double* nrm, int* perm) {
+__device__ __forceinline__ void norm_order(int n, const double* nrm, int* perm) {
   __shared__ double v[kJRows];
   // NaN sorts last, so that the ranks always form a permutation
   for (int c = threadIdx.x; c < n; c += 1024) v[c] = nrm[c] == nrm[c] ? nrm[c] : -1.0;
@@ -717,6 +730,68 @@ __global__ __launch_bounds__(1024) void k_norm_order(int n, const double* nrm, i
     for (int k = 0; k < n; ++k) rank += (v[k] > x) | ((v[k] == x) & (k < c));
     perm[rank] = c;
   }
+}
+
+__global__ __launch_bounds__(1024) void k_norm_order(int n, const double* nrm, int* perm) {
+  norm_order(n, nrm, perm);
+}
+
+// ---- many Jacobi SVDs in lockstep (the correctors of a batch) ------------
+// One launch per round covers the block pairs of every matrix still
+// sweeping: workgroups [block_begin, block_begin + 8 ceil(npb / 16)) take
+// one matrix's pairs, which are computed exactly as in its own launch.
+struct JacobiJob {
+  int n, npb, block_begin;
+  double *Hc, *Hn, *Vc, *Vn;  // current columns and the gather target
+  int* pos;                   // this sweep's column order
+  double* cnorm2;
+  const double* fro2;
+  int* counter;               // this sweep's rotation count
+};
+
+__device__ __forceinline__ int job_of(const JacobiJob* jobs, int nj, int blk) {
+  int lo = 0, hi = nj - 1;  // last job with block_begin <= blk
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].block_begin <= blk) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int ROWS>
+__global__ __launch_bounds__(256) void k_jacobi_block_multi(const JacobiJob* jobs, int nj,
+                                                            int round) {
+  const JacobiJob& j = jobs[job_of(jobs, nj, (int)blockIdx.x)];
+  if (round >= j.npb - 1) return;  // this matrix has fewer rounds per sweep
+  jacobi_block_pair<ROWS>(j.n, j.npb, round, (int)blockIdx.x - j.block_begin, j.Hc, j.Vc,
+                          j.counter, j.fro2, j.cnorm2);
+}
+
+__global__ __launch_bounds__(1024) void k_norm_order_multi(const JacobiJob* jobs) {
+  const JacobiJob& j = jobs[blockIdx.x];
+  norm_order(j.n, j.cnorm2, j.pos);
+}
+
+// Hn(:, k) = Hc(:, pos[k]), Vn likewise, for job blockIdx.y
+__global__ void k_gather_cols2_multi(const JacobiJob* jobs) {
+  const JacobiJob& j = jobs[blockIdx.y];
+  const int n = j.n;
+  const long long nn = (long long)n * n;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nn;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(e / n), i = (int)(e % n);
+    const int pk = j.pos[k];
+    const bool ok = (unsigned)pk < (unsigned)n;
+    const long long src = (long long)(ok ? pk : 0) * n + i;
+    j.Hn[e] = ok ? j.Hc[src] : 0.0;
+    j.Vn[e] = ok ? j.Vc[src] : 0.0;
+  }
+}
+
+__global__ void k_collect_counters(const JacobiJob* jobs, int nj, int* out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nj) out[t] = *jobs[t].counter;
 }
 
 // Hd(:, k) = Hs(:, perm[k]) and Vd(:, k) = Vs(:, perm[k]) (n x n, column-major)
@@ -1353,8 +1428,8 @@ void svd_jacobi(int n, const double* H, double* X, double* Y, double* sig, doubl
       std::swap(Hc, Hn);
       std::swap(Vc, Vn);
       for (int round = 0; round < npb - 1; ++round) {
-        hipLaunchKernelGGL(k_jacobi_block, dim3(8 * ((npb / 2 + 7) / 8)), dim3(256), 0, st, n, npb,
-                           round, Hc, Vc, counters + sw, (const double*)fro2, cnorm2);
+        hipLaunchKernelGGL(k_jacobi_block<kJRows>, dim3(8 * ((npb / 2 + 7) / 8)), dim3(256), 0,
+                           st, n, npb, round, Hc, Vc, counters + sw, (const double*)fro2, cnorm2);
         PW_LAUNCH_CHECK();
       }
     } else {
@@ -1378,6 +1453,131 @@ void svd_jacobi(int n, const double* H, double* X, double* Y, double* sig, doubl
                      (const double*)Vc, (const int*)pos, (const double*)sig_u, X, Y);
   PW_LAUNCH_CHECK();
 }
+
+// Many matrices at once: each is set up, swept and finished as by
+// svd_jacobi (same kernels per block pair, same column order, same stopping
+// rule per matrix), but every round is one launch over the block pairs of
+// all matrices still sweeping, and one read-back per sweep serves all.
+// Matrices outside the block path's sizes are handled by svd_jacobi.
+void svd_jacobi_multi(const std::vector<SvdJob>& jobs, void* jobs_dev, int* counts_dev,
+                      hipStream_t st) {
+  constexpr int maxsweeps = 40;
+  struct State {
+    JacobiJob j;
+    int* counters;
+    double* sig_u;
+    size_t qi;  // index of the job
+  };
+  std::vector<State> act, done;
+  const bool force_columns = getenv("PW_JACOBI_COLUMNS") != nullptr;
+  for (size_t qi = 0; qi < jobs.size(); ++qi) {
+    const SvdJob& q = jobs[qi];
+    const int n = q.n;
+    if (n < 2 * kJC || n > kJRows || force_columns) {
+      svd_jacobi(n, q.H, q.X, q.Y, q.sig, q.tol, q.rank_dev, q.Hw, q.Vw, q.counters, st);
+      continue;
+    }
+    const long long nn = (long long)n * n;
+    State a;
+    a.j.n = n;
+    const int nb = (n + kJB - 1) / kJB;
+    a.j.npb = nb + (nb & 1);
+    a.j.block_begin = 0;
+    a.j.Hc = q.Hw;
+    a.j.Hn = q.Hw + nn;
+    a.j.Vc = q.Vw;
+    a.j.Vn = q.Vw + nn;
+    double* ws = q.Hw + 2 * nn;
+    a.sig_u = ws;
+    a.j.pos = (int*)(ws + n);
+    double* fro2 = ws + 2 * n + 8;
+    a.j.fro2 = fro2;
+    a.j.cnorm2 = ws + 2 * n + 16;
+    a.j.counter = nullptr;
+    a.counters = q.counters;
+    a.qi = qi;
+    PW_HIP(hipMemcpyAsync(a.j.Hc, q.H, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_identity, dim3(nblocks(nn)), dim3(kTB), 0, st, n, a.j.Vc);
+    PW_LAUNCH_CHECK();
+    PW_HIP(hipMemsetAsync(q.counters, 0, sizeof(int) * maxsweeps, st));
+    frob_norm2(a.j.Hc, n, n, n, q.sig, fro2, st);
+    hipLaunchKernelGGL(k_col_norms, dim3((n + 3) / 4), dim3(256), 0, st, n,
+                       (const double*)a.j.Hc, a.j.cnorm2);
+    PW_LAUNCH_CHECK();
+    act.push_back(a);
+  }
+  std::vector<JacobiJob> ga, ro;  // host copies of the uploaded records (alive until the sync)
+  JacobiJob* dga = (JacobiJob*)jobs_dev;
+  JacobiJob* dro = dga + jobs.size();
+  std::vector<int> cnt;
+  for (int sw = 0; sw < maxsweeps && !act.empty(); ++sw) {
+    const int na = (int)act.size();
+    ga.clear();
+    long long nnmax = 0;
+    for (State& a : act) {
+      a.j.counter = a.counters + sw;
+      ga.push_back(a.j);
+      nnmax = std::max(nnmax, (long long)a.j.n * a.j.n);
+    }
+    PW_HIP(hipMemcpyAsync(dga, ga.data(), sizeof(JacobiJob) * na, hipMemcpyHostToDevice, st));
+    // this sweep's column order and the gathered columns
+    hipLaunchKernelGGL(k_norm_order_multi, dim3((unsigned)na), dim3(1024), 0, st,
+                       (const JacobiJob*)dga);
+    PW_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_gather_cols2_multi, dim3(std::min(nblocks(nnmax), 2048u), (unsigned)na),
+                       dim3(kTB), 0, st, (const JacobiJob*)dga);
+    PW_LAUNCH_CHECK();
+    ro.clear();
+    int blocks = 0, maxr = 0, nmax = 0;
+    for (State& a : act) {
+      std::swap(a.j.Hc, a.j.Hn);
+      std::swap(a.j.Vc, a.j.Vn);
+      a.j.block_begin = blocks;
+      blocks += 8 * ((a.j.npb / 2 + 7) / 8);
+      maxr = std::max(maxr, a.j.npb - 1);
+      nmax = std::max(nmax, a.j.n);
+      ro.push_back(a.j);
+    }
+    PW_HIP(hipMemcpyAsync(dro, ro.data(), sizeof(JacobiJob) * na, hipMemcpyHostToDevice, st));
+    for (int round = 0; round < maxr; ++round) {
+      if (nmax <= kJRowsSmall)
+        hipLaunchKernelGGL(k_jacobi_block_multi<kJRowsSmall>, dim3((unsigned)blocks), dim3(256), 0,
+                           st, (const JacobiJob*)dro, na, round);
+      else
+        hipLaunchKernelGGL(k_jacobi_block_multi<kJRows>, dim3((unsigned)blocks), dim3(256), 0, st,
+                           (const JacobiJob*)dro, na, round);
+      PW_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_collect_counters, dim3(nblocks(na)), dim3(kTB), 0, st,
+                       (const JacobiJob*)dro, na, counts_dev);
+    PW_LAUNCH_CHECK();
+    cnt.assign((size_t)na, 0);
+    PW_HIP(hipMemcpyAsync(cnt.data(), counts_dev, sizeof(int) * na, hipMemcpyDeviceToHost, st));
+    PW_HIP(hipStreamSynchronize(st));
+    std::vector<State> keep;
+    for (int i = 0; i < na; ++i) (cnt[(size_t)i] == 0 ? done : keep).push_back(act[(size_t)i]);
+    act.swap(keep);
+  }
+  for (const State& a : act) done.push_back(a);  // the sweep limit reached
+  // singular values, order and rank of every matrix, as svd_jacobi
+  for (const State& a : done) {
+    const SvdJob& q = jobs[a.qi];
+    const int n = a.j.n;
+    const long long nn = (long long)n * n;
+    hipLaunchKernelGGL(k_col_norms, dim3((n + 3) / 4), dim3(256), 0, st, n, (const double*)a.j.Hc,
+                       a.sig_u);
+    PW_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sort_rank, dim3(1), dim3(1024), 0, st, n, (const double*)a.sig_u,
+                       a.j.pos, q.tol, q.rank_dev, q.sig);
+    PW_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_scatter_svd, dim3(nblocks(nn)), dim3(kTB), 0, st, n,
+                       (const double*)a.j.Hc, (const double*)a.j.Vc, (const int*)a.j.pos,
+                       (const double*)a.sig_u, q.X, q.Y);
+    PW_LAUNCH_CHECK();
+  }
+}
+
+size_t svd_multi_job_bytes() { return sizeof(JacobiJob); }
 
 // one step of the serial recurrence: t_n = b_n + M t_{n-1} (M: dim x dim,
 // column-major).  A workgroup owns 64 rows (lane = row); its 16 waves sum

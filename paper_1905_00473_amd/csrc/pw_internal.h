@@ -343,6 +343,24 @@ void orth_finish(long long rows, int n, const double* A, long long lda, double* 
 void svd_jacobi(int n, const double* H, double* X, double* Y, double* sig, double tol,
                 int* rank_dev, double* Hw, double* Vw, int* counters, hipStream_t stream);
 
+// the arguments of one svd_jacobi call
+struct SvdJob {
+  int n;
+  const double* H;
+  double *X, *Y, *sig;
+  double tol;
+  int* rank_dev;
+  double *Hw, *Vw;
+  int* counters;
+};
+// svd_jacobi of every job, the block pairs of all of them in one launch per
+// round (same results as separate calls).  jobs_dev: device scratch of
+// 2 * jobs.size() * svd_multi_job_bytes() bytes; counts_dev: jobs.size()
+// ints.  Synchronises the stream once per sweep.
+size_t svd_multi_job_bytes();
+void svd_jacobi_multi(const std::vector<SvdJob>& jobs, void* jobs_dev, int* counts_dev,
+                      hipStream_t stream);
+
 // linear recurrence t_1 = b_1, t_n = b_n + M t_{n-1} (t, b: dim x N
 // column-major, M: dim x dim).  Scratch: two dim x dim matrices and two
 // dim x N blocks.
