@@ -390,10 +390,9 @@ def serial_record(pw, torch, w, fd, c, receivers):
     s.set_source(fd["src_pos"], fd["freq"], fd["t0"])
     s.set_initial(w.u0, w.p0)
     s.run(0)
-    u, p = s.state(0)
+    us, ps = s.serial_fine_states()
     for n in range(1, w.N):
-        u, p = s.serial_fine(n)
-        s.set_iterate(n, u, p)
+        s.set_iterate(n, us[n], ps[n])
     d = s.trace_sweep(torch.as_tensor(receivers, device="cuda"))
     s.close()
     return d

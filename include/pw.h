@@ -365,6 +365,11 @@ pw_status pw_get_diagnostics(pw_ctx* ctx, int prob, double* out, int cap, int* c
 pw_status pw_serial_fine(pw_ctx* ctx, int prob, int n, void* u_dev,
                          void* p_dev);
 
+/* The serial fine reference at every coupling time: u(t_n), p(t_n) for
+ * n = 0..N written to u_dev + n * n_points, p_dev + n * n_points (N + 1
+ * fields of the state dtype each), from one chain of N propagations.    */
+pw_status pw_serial_fine_states(pw_ctx* ctx, int prob, void* u_dev, void* p_dev);
+
 /* ------------------------------------------------------------------------
  * Building blocks of the path, exposed for parity checks.  All pointers
  * are device pointers; n_states fields are processed in one launch.

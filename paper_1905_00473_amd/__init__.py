@@ -161,6 +161,8 @@ _SIGS = {
                   ctypes.POINTER(ctypes.c_double),
                   ctypes.POINTER(ctypes.c_double)],
     "pw_energy_noalloc": [ctypes.c_void_p] * 8,
+    "pw_serial_fine_states": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                              ctypes.c_void_p],
     "pw_set_source": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                       ctypes.c_double, ctypes.c_double],
     "pw_trace_sweep": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
@@ -491,6 +493,17 @@ class Solver:
         u = torch.empty(self.shape(prob), dtype=self.dtype(prob), device="cuda")
         p = torch.empty_like(u)
         _check(lib().pw_serial_fine(self._h, prob, int(n), _ptr(u), _ptr(p)))
+        return u, p
+
+    def serial_fine_states(self, prob=0):
+        """(N + 1, *grid) u and p: the serial fine reference at every
+        coupling time t_n, n = 0..N."""
+        import torch
+        N = self.problems[prob].n_slices
+        u = torch.empty((N + 1,) + self.shape(prob), dtype=self.dtype(prob),
+                        device="cuda")
+        p = torch.empty_like(u)
+        _check(lib().pw_serial_fine_states(self._h, prob, _ptr(u), _ptr(p)))
         return u, p
 
     def timings(self, prob=0):

@@ -229,6 +229,22 @@ __global__ void k_adj_step_grp(const double* lu, const double* lp, long long sl,
   gacc[(long long)q.s * sg + J] += gsum;
 }
 
+// per-point fields of the layer for the reverse streams (2D): d =
+// min(dmx[x], dmy[y]); wf = (1 + d) / 2, s2 = d^2, dd = d, c2e = c2 wf
+__global__ void k_layer_fields(int nx, int ny, const double* dmx, const double* dmy,
+                               const double* c2, double* wf, double* s2, double* dd,
+                               double* c2e) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)nx * ny) return;
+  const int x = (int)(t % nx), y = (int)(t / nx);
+  const double d = fmin(dmx[x], dmy[y]);
+  const double w = 0.5 * (1.0 + d);
+  wf[t] = w;
+  s2[t] = d * d;
+  dd[t] = d;
+  c2e[t] = c2[t] * w;
+}
+
 // lp <- d lp (the layer's factor of a closing half kick, 2D)
 __global__ void k_damp_fields(double* lp, long long sl, const double* dmx, const double* dmy,
                               G3 g, int nxb, int nblk) {
@@ -276,10 +292,13 @@ struct AdjStreamDesc {
   double w[kAdjRB];
   int top, nsteps;
   int nx, ny, ncb, nseg, Ly, nstates;
-  // forced launches: the layer (null: none), the level of the slice at
-  // segment level 0, and the receiver seeds (null: none; see Force)
-  const double* dmx;
-  const double* dmy;
+  // forced launches: the layer as per-point fields (null: none; see
+  // Force), the level of the slice at segment level 0, and the receiver
+  // seeds (null: none)
+  const double* wf;
+  const double* s2;
+  const double* dd;
+  const double* c2e;
   int lev_base;
   const int* rec_rows;
   const int* rec_map;
@@ -287,7 +306,9 @@ struct AdjStreamDesc {
   int n_rec, m_tr;
 };
 
-template <bool FORCED>
+// FORCED: the layer (and the level-0 half kick); SEEDS: also the receiver
+// seeds (a separate instantiation, as for the forward record)
+template <bool FORCED, bool SEEDS = false>
 __global__ __launch_bounds__(256) void k_adj_stream2d(AdjStreamDesc a) {
   constexpr int B = kAdjRB;
   constexpr int H = B;
@@ -318,15 +339,18 @@ __global__ __launch_bounds__(256) void k_adj_stream2d(AdjStreamDesc a) {
   const double* lui = a.lu_in + (long long)st * a.s_in;
   const double* lpi = a.lp_in + (long long)st * a.s_in;
   double* gs = a.gacc + (long long)st * a.sg;
-  const bool damp = FORCED && a.dmx != nullptr;
-  const double dcol = damp ? a.dmx[gx] : 1.0;
-  // level 0 of the slice is a half kick: W = h/2, factor d; elsewhere
-  // W = h/2 (1 + d), factor d^2 (see k_adj_step_grp)
-  auto weight = [&](int lev, double d) { return lev == 0 ? 0.5 * a.h : 0.5 * a.h * (1.0 + d); };
-  auto dlayer = [&](int y) {
+  // the layer: a kick at level 0 of the slice is a half kick (weight h/2,
+  // factor d); elsewhere two half kicks meet (weight h/2 (1 + d) = h wf,
+  // factor d^2), so that W c2 = h c2e: the unforced formulas with c2e in
+  // place of c2, the gradient weight wf and the factor applied to lp'
+  const bool damp = FORCED && a.c2e != nullptr;
+  // row of a logical index within one period of the grid (the general
+  // modulo only for grids smaller than the stream's reach)
+  auto near_row = [&](int y) {
+    const int w = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+    if ((unsigned)w < (unsigned)ny) return w;
     int r = y % ny;
-    if (r < 0) r += ny;
-    return damp ? fmin(dcol, a.dmy[r]) : 1.0;
+    return r < 0 ? r + ny : r;
   };
   const double* ul[B];
 #pragma unroll
@@ -377,14 +401,17 @@ __global__ __launch_bounds__(256) void k_adj_stream2d(AdjStreamDesc a) {
         lu_ += lane_upv(uc);
         lu_ += wu[j][2];
         lu_ += wu[j][0];
+        lo = lc + a.w[j] * aa * a.idx2;
         if constexpr (FORCED) {
-          const int lev = a.lev_base + a.top - j;
-          const double d = dlayer(r);
-          lo = lc + aa * a.idx2;  // W is inside q
-          go = gc + weight(lev, d) * pc * (lu_ * a.idx2);
-          po = (lev == 0 ? d : d * d) * pc;
+          if (damp) {
+            const bool lev0 = a.lev_base + a.top - j == 0;
+            const double dc = a.dd[(long long)near_row(r) * nx + gx];
+            go = gc + a.w[j] * (lev0 ? 1.0 : 0.5 * (1.0 + dc)) * pc * (lu_ * a.idx2);
+            po = (lev0 ? dc : dc * dc) * pc;
+          } else {
+            go = gc + a.w[j] * pc * (lu_ * a.idx2);
+          }
         } else {
-          lo = lc + a.w[j] * aa * a.idx2;
           go = gc + a.w[j] * pc * (lu_ * a.idx2);
         }
       }
@@ -415,15 +442,14 @@ __global__ __launch_bounds__(256) void k_adj_stream2d(AdjStreamDesc a) {
     for (int j = 0; j < B; ++j) {
       const int rin = t + 2 - 2 * j;  // row of the pending slot of stage j
       const long long gi = rowidx(rin);
-      double wq_in = 1.0;
+      const double* cq = a.c2;
       if constexpr (FORCED) {
         if (j < a.nsteps) {
           const int lev = a.lev_base + a.top - j;
-          wq_in = weight(lev, dlayer(rin));
+          if (damp && lev != 0) cq = a.c2e;
           // receiver seed of u at level lev + 1 (record index lev)
-          if (a.seeds) {
-            int ry = rin % ny;
-            if (ry < 0) ry += ny;
+          if (SEEDS) {
+            const int ry = near_row(rin);
             if (a.rec_rows[ry]) {
               const int rid = a.rec_map[gi];
               if (rid >= 0) pl[j] += a.seeds[((long long)st * a.m_tr + lev) * a.n_rec + rid];
@@ -434,7 +460,7 @@ __global__ __launch_bounds__(256) void k_adj_stream2d(AdjStreamDesc a) {
       const double lpn = (j < a.nsteps) ? fma(a.h, pl[j], pp[j]) : pp[j];
       wq[j][0] = wq[j][1];
       wq[j][1] = wq[j][2];
-      wq[j][2] = FORCED ? wq_in * (a.c2[gi] * lpn) : a.c2[gi] * lpn;
+      wq[j][2] = cq[gi] * lpn;
       wu[j][0] = wu[j][1];
       wu[j][1] = wu[j][2];
       wu[j][2] = ul[j][gi];
@@ -762,8 +788,11 @@ void vv_adjoint_d(const Grid& grid, const double* c2, const double* u0, const do
       // is a serial chain of row steps)
       AdjStreamDesc d{};
       if (fo) {
-        d.dmx = dmx;
-        d.dmy = dmy;
+        if (dmx && !fo->c2e) fail(PW_EINVAL, "the layer's reverse streams need its fields");
+        d.wf = fo->wf;
+        d.s2 = fo->s2;
+        d.dd = fo->dd;
+        d.c2e = fo->c2e;
         d.lev_base = i0;
         d.rec_rows = fo->rec_rows;
         d.rec_map = fo->rec_map;
@@ -809,7 +838,10 @@ void vv_adjoint_d(const Grid& grid, const double* c2, const double* u0, const do
         d.lu_out = lub;
         d.lp_out = lpb;
         d.s_out = sb;
-        if (fo)
+        if (fo && fo->seeds)
+          hipLaunchKernelGGL((k_adj_stream2d<true, true>), dim3((unsigned)((nw + 3) / 4)),
+                             dim3(256), 0, st, d);
+        else if (fo)
           hipLaunchKernelGGL(k_adj_stream2d<true>, dim3((unsigned)((nw + 3) / 4)), dim3(256), 0,
                              st, d);
         else
@@ -871,6 +903,15 @@ void vv_adjoint(const Grid& grid, const double* c2, const double* u0, const doub
     vv_adjoint_d<2>(grid, c2, u0, p0, s0, lu, lp, sl, gacc, sg, ns, m, h, ckpt, sc, st, fo);
   else
     vv_adjoint_d<3>(grid, c2, u0, p0, s0, lu, lp, sl, gacc, sg, ns, m, h, ckpt, sc, st, fo);
+}
+
+void layer_fields(const Grid& g, const double* dmx, const double* dmy, const double* c2,
+                  double* out, hipStream_t st) {
+  if (g.dim != 2) fail(PW_EINVAL, "the absorbing layer is 2D only");
+  const long long np = g.npts();
+  hipLaunchKernelGGL(k_layer_fields, dim3(nblocks(np)), dim3(kTB), 0, st, g.n[0], g.n[1], dmx,
+                     dmy, c2, out, out + np, out + 2 * np, out + 3 * np);
+  PW_LAUNCH_CHECK();
 }
 
 void interp_transpose(const Grid& f, const Grid& c, int ratio, const double* const* tables,

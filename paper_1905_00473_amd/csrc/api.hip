@@ -113,6 +113,7 @@ struct Tape {
   double *gc = nullptr, *grad = nullptr, *c2f = nullptr;
   double *Y = nullptr, *LA = nullptr, *X = nullptr;  // 2Nc x N
   double *Cn = nullptr, *Cr = nullptr, *Sr = nullptr, *Sn = nullptr, *MT = nullptr;
+  double *layF = nullptr, *layC = nullptr;  // layer fields (wf, s2, dd, c2e) per grid
   AdjScratch as;
 };
 
@@ -242,6 +243,9 @@ struct Prob {
   bool have_src = false;
   double src_pos[3] = {0, 0, 0}, src_freq = 0.0, src_t0 = 0.0;
   int srcF[2] = {-1, -1}, srcC[2] = {-1, -1};  // nearest fine / coarse node (x, y)
+  // the wavelet at every level of every slice: [n - 1][i] = r((n - 1) T / N
+  // + i h), n = 1..N, i = 0..m, for the fine and the coarse step
+  DevBuf srcF_tab, srcC_tab;
   // receiver record (pw_trace_sweep, pw_backward_sweep): per-row flags,
   // per-node receiver index, the sweep's output states
   DevBuf rec_rows, rec_map, trace_u, trace_p;
@@ -612,9 +616,10 @@ void setup_layer(Prob& pr, double cmax_medium) {
 
 // Force of a propagation of problem pr on the fine or coarse grid, in
 // precision T (tables: the state dtype's, or double); with the source when
-// `source` (states s start at t_base + s t_state)
+// `source`: state s propagates slice first_slice + s (per_state) or
+// first_slice (all states)
 template <typename T>
-Force<T> make_force(const Prob& pr, bool fine, bool source, double t_base, double t_state,
+Force<T> make_force(const Prob& pr, bool fine, bool source, int first_slice, bool per_state,
                     bool state_tables) {
   Force<T> f;
   const Grid& g = fine ? pr.gf : pr.gc;
@@ -626,15 +631,14 @@ Force<T> make_force(const Prob& pr, bool fine, bool source, double t_base, doubl
   }
   if (source && pr.have_src) {
     const int* node = fine ? pr.srcF : pr.srcC;
+    const int m = fine ? pr.mF : pr.mC;
     f.sx = node[0];
     f.sy = node[1];
     f.amp = std::pow(g.dx, -(double)g.dim);
-    f.freq = pr.src_freq;
-    f.t0 = pr.src_t0;
+    f.src_tab = (const double*)(fine ? pr.srcF_tab.p : pr.srcC_tab.p) +
+                (long long)(first_slice - 1) * (m + 1);
+    f.src_stride = per_state ? m + 1 : 0;
   }
-  f.t_base = t_base;
-  f.t_state = t_state;
-  f.hd = fine ? pr.hF : pr.hC;
   return f;
 }
 
@@ -646,9 +650,8 @@ template <typename T>
 void prop_fine(Prob& pr, const T* u, const T* p, T* uo, T* po, int n, hipStream_t st,
                int first_slice = 1) {
   if (n > pr.N) fail(PW_EINVAL, "too many fine states for one batched propagation");
-  const double dtc = pr.P.T / pr.N;
   Force<T> fo;
-  if (forced(pr)) fo = make_force<T>(pr, true, true, (first_slice - 1) * dtc, dtc, true);
+  if (forced(pr)) fo = make_force<T>(pr, true, true, first_slice, true, true);
   propagate<T>(pr.gf, tp<T>(pr.c2f), u, p, uo, po, pr.Nf, n, pr.mF, (T)pr.hF, pr.comp,
                fine_work<T>(pr, 0), fine_work<T>(pr, 1), st, true, forced(pr) ? &fo : nullptr);
 }
@@ -658,9 +661,8 @@ template <typename T>
 void prop_coarse(Prob& pr, const T* u, const T* p, T* uo, T* po, int n, hipStream_t st,
                  int first_slice = 1) {
   if (n > pr.N + 1) fail(PW_EINVAL, "too many coarse states for one batched propagation");
-  const double dtc = pr.P.T / pr.N;
   Force<T> fo;
-  if (forced(pr)) fo = make_force<T>(pr, false, true, (first_slice - 1) * dtc, dtc, true);
+  if (forced(pr)) fo = make_force<T>(pr, false, true, first_slice, true, true);
   propagate<T>(pr.gc, tp<T>(pr.c2c), u, p, uo, po, pr.Nc, n, pr.mC, (T)pr.hC, pr.comp,
                coarse_work<T>(pr, 0), coarse_work<T>(pr, 1), st, false,
                forced(pr) ? &fo : nullptr);
@@ -675,7 +677,7 @@ void prop_coarse_cols(Prob& pr, const double* in, double* out, int ncols, hipStr
   StateSet<double> a{pr.dw[0], pr.dw[0] + Nc, nullptr, nullptr};
   StateSet<double> b{pr.dw[1], pr.dw[1] + Nc, nullptr, nullptr};
   Force<double> fo;
-  if (pr.sponge) fo = make_force<double>(pr, false, false, 0.0, 0.0, false);
+  if (pr.sponge) fo = make_force<double>(pr, false, false, 1, false, false);
   propagate<double>(pr.gc, pr.c2c_d, in, in + Nc, out, out + Nc, 2 * Nc, ncols, pr.mC, pr.hC,
                     false, a, b, st, false, pr.sponge ? &fo : nullptr);
 }
@@ -1539,6 +1541,10 @@ void ensure_backward(Prob& pr, int ckpt) {
   t.Sr = m.get_n<double>(d1 * N);
   t.Sn = m.get_n<double>(d1 * N);
   t.MT = m.get_n<double>(d1 * d1);
+  if (pr.sponge) {
+    t.layF = m.get_n<double>(4 * Nf);
+    t.layC = m.get_n<double>(4 * Nc);
+  }
   // one time level holds N fine states (>= N coarse columns)
   const int msteps = std::max(pr.mF, pr.mC);
   AdjScratch& a = t.as;
@@ -1583,13 +1589,27 @@ void backward_typed(Prob& pr, const long long* rec, int nrec, const double* seed
   // slot n of A holds the adjoint of the state u_n ([u; p], n = 0..N)
   double* A = t.La;
   double* B = t.Lb;
-  const double dtc = pr.P.T / N;
   // the layer and source of F, C (slice n from t_{n-1}) and the layer
   // alone for the coarse propagations of differences
   Force<double> fF, fCl;
+  // the layer's per-point fields for the reverse streams
+  auto with_fields = [&](Force<double> f, bool fine) {
+    if (!pr.sponge) return f;
+    const double* base = fine ? t.layF : t.layC;
+    const long long np = fine ? Nf : Nc;
+    f.wf = base;
+    f.s2 = base + np;
+    f.dd = base + 2 * np;
+    f.c2e = base + 3 * np;
+    return f;
+  };
+  if (pr.sponge) {
+    layer_fields(gf, pr.layF_d, pr.layF_d + gf.n[0], t.c2f, t.layF, st);
+    layer_fields(gc, pr.layC_d, pr.layC_d + gc.n[0], pr.c2c_d, t.layC, st);
+  }
   if (forced(pr)) {
-    fF = make_force<double>(pr, true, true, 0.0, dtc, false);
-    fCl = make_force<double>(pr, false, false, 0.0, 0.0, false);
+    fF = with_fields(make_force<double>(pr, true, true, 1, true, false), true);
+    fCl = with_fields(make_force<double>(pr, false, false, 1, false, false), false);
   }
   const Force<double>* pF = forced(pr) ? &fF : nullptr;
   const Force<double>* pCl = pr.sponge ? &fCl : nullptr;
@@ -1599,7 +1619,7 @@ void backward_typed(Prob& pr, const long long* rec, int nrec, const double* seed
     // 0..N-1
     widen_fields<T>(tp<T>(t.us) + Nf * N * K, Nf, t.Wf, F2, Nf, N, st);
     widen_fields<T>(tp<T>(t.ps) + Nf * N * K, Nf, t.Wf + Nf, F2, Nf, N, st);
-    Force<double> fS = make_force<double>(pr, true, true, 0.0, dtc, false);
+    Force<double> fS = with_fields(make_force<double>(pr, true, true, 1, true, false), true);
     fS.rec = rec;
     fS.rec_rows = rec_rows;
     fS.rec_map = rec_map;
@@ -1662,7 +1682,7 @@ void backward_typed(Prob& pr, const long long* rec, int nrec, const double* seed
     add_inplace(lam, t.Y + C2 * (n - 1), C2, st);
     const double* Wn = t.W + C2 * (n - 1);
     Force<double> fCn;
-    if (forced(pr)) fCn = make_force<double>(pr, false, true, (n - 1) * dtc, 0.0, false);
+    if (forced(pr)) fCn = with_fields(make_force<double>(pr, false, true, n, false, false), false);
     vv_adjoint(gc, pr.c2c_d, Wn, Wn + Nc, C2, lam, lam + Nc, C2, t.GC, Nc, 1, pr.mC, pr.hC, ckpt,
                t.as, st, forced(pr) ? &fCn : nullptr);
   }
@@ -2159,6 +2179,23 @@ void set_source(Prob& pr, const double* pos, double freq, double t0) {
   for (int a = 0; a < 3; ++a) pr.src_pos[a] = a < pr.gf.dim ? pos[a] : 0.0;
   pr.src_freq = freq;
   pr.src_t0 = t0;
+  // the Ricker wavelet (1 - 2a) exp(-a), a = (pi f (t - t0))^2, at the kick
+  // times of every slice, t = (n - 1) T / N + i h
+  const double dtc = pr.P.T / pr.N;
+  for (int g = 0; g < 2; ++g) {
+    const int m = g == 0 ? pr.mF : pr.mC;
+    const double h = g == 0 ? pr.hF : pr.hC;
+    std::vector<double> tab((size_t)pr.N * (m + 1));
+    for (int n = 0; n < pr.N; ++n)
+      for (int i = 0; i <= m; ++i) {
+        const double b = M_PI * freq * ((n * dtc + i * h) - t0);
+        const double a = b * b;
+        tab[(size_t)n * (m + 1) + i] = (1.0 - 2.0 * a) * std::exp(-a);
+      }
+    DevBuf& dst = g == 0 ? pr.srcF_tab : pr.srcC_tab;
+    PW_HIP(hipMemcpy(dst.ensure(sizeof(double) * tab.size()), tab.data(),
+                     sizeof(double) * tab.size(), hipMemcpyHostToDevice));
+  }
   pr.have_src = true;
 }
 
@@ -2759,6 +2796,28 @@ pw_status pw_serial_fine(pw_ctx* ctx, int prob, int n, void* u, void* p) {
   });
 }
 
+pw_status pw_serial_fine_states(pw_ctx* ctx, int prob, void* u, void* p) {
+  return guarded([&] {
+    Prob& pr = get_prob(ctx, prob);
+    if (!pr.have_medium || !pr.have_initial) fail(PW_ESTATE, "set medium and initial state first");
+    if (!u || !p) fail(PW_EINVAL, "null output");
+    hipStream_t st = ctx->stream;
+    const size_t fb = pr.tsize * pr.Nf;
+    PW_HIP(hipMemcpyAsync(u, pr.u, fb, hipMemcpyDeviceToDevice, st));
+    PW_HIP(hipMemcpyAsync(p, pr.p, fb, hipMemcpyDeviceToDevice, st));
+    for (int n = 1; n <= pr.N; ++n) {
+      char* uo = (char*)u + fb * n;
+      char* po = (char*)p + fb * n;
+      if (pr.f64)
+        prop_fine<double>(pr, (const double*)(uo - fb), (const double*)(po - fb), (double*)uo,
+                          (double*)po, 1, st, n);
+      else
+        prop_fine<float>(pr, (const float*)(uo - fb), (const float*)(po - fb), (float*)uo,
+                         (float*)po, 1, st, n);
+    }
+  });
+}
+
 pw_status pw_propagate(pw_ctx* ctx, int prob, int grid, const void* u_in, const void* p_in,
                        void* u_out, void* p_out, int n_states) {
   return guarded([&] {
@@ -3121,8 +3180,7 @@ const long long* record_tables(Prob& pr, const long long* rec, int nrec, int on_
 
 template <typename T>
 void trace_sweep_typed(Prob& pr, const long long* rec, int nrec, double* out, hipStream_t st) {
-  const double dtc = pr.P.T / pr.N;
-  Force<T> fo = make_force<T>(pr, true, true, 0.0, dtc, true);
+  Force<T> fo = make_force<T>(pr, true, true, 1, true, true);
   fo.rec = rec;
   fo.rec_rows = (const int*)pr.rec_rows.p;
   fo.rec_map = (const int*)pr.rec_map.p;

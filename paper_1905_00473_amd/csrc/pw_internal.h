@@ -48,23 +48,29 @@ struct Grid {
 // launch the scratch sets are not touched.
 // Absorbing layer, point source and receivers of a 2D propagation (the
 // forcing of PW_SPONGE and pw_set_source, include/pw.h).  Every member is
-// optional.  A kick of state s at level i (time t_base + s t_state + i h)
-// first multiplies p by the layer's factor -- d at the first and last half
-// kick of a slice, d^2 where two half kicks meet, d = min(dmp_x[x],
-// dmp_y[y]) = exp(-sigma h / 2) -- then adds its weight (h/2 or h/2 (1+d))
-// times c^2 Lap u + amp r(t) (the last term at the source node only).
+// optional.  A kick of state s at level i first multiplies p by the
+// layer's factor -- d at the first and last half kick of a slice, d^2
+// where two half kicks meet, d = min(dmp_x[x], dmp_y[y]) = exp(-sigma h /
+// 2) -- then adds its weight (h/2 or h/2 (1+d)) times c^2 Lap u + amp r(t)
+// (the last term at the source node only; r(t) of state s at level i is
+// src_tab[s src_stride + i], the wavelet at that state's slice time).
 template <typename T>
 struct Force {
   const T* dmp_x = nullptr;  // layer factor per column (null: no layer)
   const T* dmp_y = nullptr;  // per row
   int sx = -1, sy = -1;      // source node (sx < 0: no source)
-  double amp = 0.0, freq = 0.0, t0 = 0.0;  // weight 1 / dx^2, Ricker frequency, peak time
-  double t_base = 0.0;       // start time of the slice of state 0
-  double t_state = 0.0;      // added per state index
-  double hd = 0.0;           // the step h in double (source times)
+  double amp = 0.0;          // weight 1 / dx^2
+  const double* src_tab = nullptr;  // r(t) per state and level
+  int src_stride = 0;
   // receivers: per row nonzero if the row holds one; per node its index or -1
   const int* rec_rows = nullptr;
   const int* rec_map = nullptr;
+  // reverse pass (FP64) over many states: per-point fields of the layer,
+  // wf = (1 + d) / 2, s2 = d^2, dd = d, c2e = c2 wf (null: from dmp_x/y)
+  const double* wf = nullptr;
+  const double* s2 = nullptr;
+  const double* dd = nullptr;
+  const double* c2e = nullptr;
   const long long* rec = nullptr;  // flat node of every receiver
   int n_rec = 0, m_tr = 0;         // receivers, steps per state of the record
   double* traces = nullptr;        // forward: u after step i of state s at [(s m_tr + i) n_rec + r]
@@ -431,6 +437,12 @@ void vv_adjoint(const Grid& g, const double* c2, const double* u0, const double*
                 long long s0, double* lu, double* lp, long long sl, double* gacc, long long sg,
                 int ns, int m, double h, int ckpt, const AdjScratch& sc, hipStream_t stream,
                 const Force<double>* fo = nullptr);
+
+// the fields wf, s2, dd, c2e (see Force) of the layer with per-axis factor
+// tables dmx, dmy on grid g and medium c2, into out (4 npts doubles, in
+// that order)
+void layer_fields(const Grid& g, const double* dmx, const double* dmy, const double* c2,
+                  double* out, hipStream_t stream);
 
 template <typename T>
 void widen_fields(const T* in, long long si, double* out, long long so, long long np, int ns,

@@ -58,6 +58,13 @@ __device__ __forceinline__ int wrap_idx(int g, int n) {
   return g < 0 ? g + n : g;
 }
 
+// the same for an index within one period of the range (one add or
+// subtract); the general form only where it is not (tiny grids)
+__device__ __forceinline__ int wrap_near(int g, int n) {
+  const int w = g < 0 ? g + n : (g >= n ? g - n : g);
+  return (unsigned)w < (unsigned)n ? w : wrap_idx(g, n);
+}
+
 // s += x, with Kahan compensation e when COMP
 template <typename T, bool COMP>
 __device__ __forceinline__ void kadd(T& s, T& e, T x) {
@@ -333,16 +340,11 @@ __device__ __forceinline__ void kscale(T& s, T& e, T f) {
   }
 }
 
-// Ricker wavelet (1 - 2a) exp(-a), a = (pi f (t - t0))^2
-__device__ __forceinline__ double ricker_wavelet(double t, double f, double t0) {
-  const double b = 3.141592653589793 * f * (t - t0);
-  const double a = b * b;
-  return (1.0 - 2.0 * a) * exp(-a);
-}
-
 // one stream (wavefront) of problem descriptor `a`; wid = local wave index.
-// FORCED: the layer, source and receivers of a.f (see Force)
-template <typename T, bool COMP, int B, bool LV = false, bool FORCED = false>
+// FORCED: the layer and source of a.f (see Force); REC: also its receiver
+// record (a separate instantiation: the recording code holds registers
+// that would cost the other forced launches a wave per SIMD)
+template <typename T, bool COMP, int B, bool LV = false, bool FORCED = false, bool REC = false>
 __device__ __forceinline__ void stream2d_body(const StreamDesc<T>& a, long long wid, int lane) {
   constexpr int H = B + 1;
   constexpr int XV = 64 - 2 * H;  // output columns per wave
@@ -379,16 +381,16 @@ __device__ __forceinline__ void stream2d_body(const StreamDesc<T>& a, long long 
   // start time of this state
   const bool damp = FORCED && a.f.dmp_x != nullptr;
   const T dcol = damp ? a.f.dmp_x[gx] : T(1);
-  const double tslice = FORCED ? a.f.t_base + state * a.f.t_state : 0.0;
+  const double* srow = FORCED && a.f.sx >= 0 ? a.f.src_tab + (long long)state * a.f.src_stride
+                                             : nullptr;
   // kick of level `lev` on row r: damp p, then add w (c^2 Lap u + source)
   auto forced_kick = [&](T& pn, T& ep, T kl, int r, int lev, bool half) {
-    const int ry = wrap_idx(r, ny);
+    const int ry = wrap_near(r, ny);
     const T d = damp ? min(dcol, a.f.dmp_y[ry]) : T(1);
     if (damp) kscale<T, COMP>(pn, ep, half ? d : d * d);
     const T w = half ? h * T(0.5) : h * T(0.5) * (T(1) + d);
     T acc = kl;
-    if (ry == a.f.sy && gx == a.f.sx)
-      acc += T(a.f.amp * ricker_wavelet(tslice + lev * a.f.hd, a.f.freq, a.f.t0));
+    if (srow && ry == a.f.sy && gx == a.f.sx) acc += T(a.f.amp * srow[lev]);
     kadd<T, COMP>(pn, ep, w * acc);
   };
   for (int t = tbeg; t <= tend; ++t) {
@@ -423,7 +425,7 @@ __device__ __forceinline__ void stream2d_body(const StreamDesc<T>& a, long long 
           kadd<T, COMP>(pn, ep, w * (kj * lap));
         }
         kadd<T, COMP>(un, eu, h * pn);
-        if constexpr (FORCED) {
+        if constexpr (REC) {
           // receiver record: u after step step0 + j + 1 of the slice
           const int orow = t - 2 * j;
           if (a.f.rec_rows && orow >= Y0 && orow < Y1 && a.f.rec_rows[orow]) {
@@ -519,13 +521,13 @@ __global__ __launch_bounds__(256) void k_prop_stream2d(StreamDesc<T> a) {
   stream2d_body<T, COMP, B>(a, wid, threadIdx.x & 63);
 }
 
-// the same with the layer, source and receivers of a.f
-template <typename T, bool COMP, int B>
+// the same with the layer and source of a.f (REC: and its receivers)
+template <typename T, bool COMP, int B, bool REC>
 __global__ __launch_bounds__(256) void k_prop_stream2d_forced(StreamDesc<T> a) {
   const long long nwaves = (long long)a.nstates * a.ncb * a.nseg;
   const long long wid = launch_wave(nwaves);
   if (wid >= nwaves) return;
-  stream2d_body<T, COMP, B, false, true>(a, wid, threadIdx.x & 63);
+  stream2d_body<T, COMP, B, false, true, REC>(a, wid, threadIdx.x & 63);
 }
 
 // the same with every produced level of u written to a.lv_out (the forward
@@ -853,9 +855,12 @@ void dispatch_stream2d(const StreamDesc<T>& a, bool fine, bool forced, hipStream
   const long long nwaves = (long long)a.nstates * a.ncb * a.nseg;
   const long long nblk = (nwaves + 3) / 4;
   if (nblk >= (1LL << 31)) fail(PW_EINVAL, "too many streams for one launch");
-  if (forced)
-    hipLaunchKernelGGL((k_prop_stream2d_forced<T, COMP, B>), dim3((unsigned)nblk), dim3(256), 0,
-                       st, a);
+  if (forced && a.f.traces)
+    hipLaunchKernelGGL((k_prop_stream2d_forced<T, COMP, B, true>), dim3((unsigned)nblk),
+                       dim3(256), 0, st, a);
+  else if (forced)
+    hipLaunchKernelGGL((k_prop_stream2d_forced<T, COMP, B, false>), dim3((unsigned)nblk),
+                       dim3(256), 0, st, a);
   else if (fine)
     hipLaunchKernelGGL((k_prop_stream2d<T, COMP, B, 0>), dim3((unsigned)nblk), dim3(256), 0, st,
                        a);

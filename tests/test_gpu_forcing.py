@@ -106,12 +106,20 @@ def test_forced_propagators_match_oracle(case, prec):
 
 
 def test_forced_serial_fine_matches_oracle():
+    """pw_serial_fine (one time) and pw_serial_fine_states (every coupling
+    time, one chain): the same states bit for bit, and the oracle's."""
     w, _, _, _, fo, s, Q = _setup("2d_ragged")
     us, ps = O.serial_fine(Q, w.c, w.u0, w.p0, forcing=fo)
+    au, ap = s.serial_fine_states()
+    assert tuple(au.shape) == (w.N + 1,) + w.shape
+    for n in range(w.N + 1):
+        err = rel_energy_err(to_np(au[n]), to_np(ap[n]), us[n], ps[n], w.c,
+                             Q.dx_fine)
+        assert err < 1e-12 or n == 0 and err == 0.0, (n, err)
     for n in (1, w.N // 2, w.N):
         u, p = s.serial_fine(n)
-        err = rel_energy_err(to_np(u), to_np(p), us[n], ps[n], w.c, Q.dx_fine)
-        assert err < 1e-12, (n, err)
+        assert np.array_equal(to_np(u), to_np(au[n]))
+        assert np.array_equal(to_np(p), to_np(ap[n]))
     s.close()
 
 
