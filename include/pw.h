@@ -459,9 +459,11 @@ pw_status pw_energy_noalloc(const pw_problem* desc, const double* c,
                             const void* p_ref, double* out, void* stream);
 
 /* Checkpoint of the whole context: per problem the medium, u0, the current
- * iterate, kept history, corrector (U~, S~, V~ and the sweep columns),
- * per-iteration records, comparator variant, sampling table and source,
- * written to the file `path` (host byte order, format tag PWCKPT02).  pw_load restores
+ * iterate, kept history, corrector (U~, S~, V~, the sweep columns and
+ * their coarse propagation C E), per-iteration records, comparator
+ * variant, sampling table and source, written to the file `path` (host
+ * byte order, format tag PWCKPT02; files written without C E still load,
+ * and C E is then formed again at the next sweep).  pw_load restores
  * it into a context created with the same problem descriptions (PW_EINVAL
  * otherwise, or for a damaged file; the state is then unspecified until the
  * next set_* / run), after which pw_continue resumes the iteration exactly

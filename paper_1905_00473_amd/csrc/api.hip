@@ -173,7 +173,13 @@ struct Prob {
   double* Acol = nullptr;  // 2Nc x N
   double* E[2] = {nullptr, nullptr};   // 2Nc x cap
   double* Vp[2] = {nullptr, nullptr};  // 2Nc x cap
-  double* CE = nullptr;                // 2Nc x (rmax+1)
+  double* CE = nullptr;                // 2Nc x (rmax+1), scratch
+  // C E[cur] carried along with E: the new directions of an update are
+  // propagated once and the rest rotates with E (C is linear)
+  double* CEb[2] = {nullptr, nullptr};  // 2Nc x cap
+  double* cdc = nullptr;                // C applied to the DC column, 2Nc
+  bool ce_ok = false;                   // CEb[cur](:, 0:r+1) = C E[cur](:, 0:r+1)
+  bool cdc_ok = false;
   double* dw[2] = {nullptr, nullptr};  // FP64 coarse work, 2Nc x max(rmax+1, N)
   double* delta = nullptr;             // 2Nc x N
   // corrector
@@ -444,6 +450,9 @@ void setup(Prob& pr, const pw_problem& P) {
     pr.Vb[s] = m.get_n<double>(rows * cap);
   }
   pr.CE = m.get_n<double>(2 * Nc * (pr.rmax + 1));
+  pr.CEb[0] = m.get_n<double>(2 * Nc * cap);
+  pr.CEb[1] = m.get_n<double>(2 * Nc * cap);
+  pr.cdc = m.get_n<double>(2 * Nc);
   pr.delta = m.get_n<double>(2 * Nc * N);
   pr.Fm = m.get_n<double>(rows * N);
   pr.Gm = m.get_n<double>(rows * N);
@@ -872,6 +881,10 @@ void update_svd_end(Prob& pr, const SvdPending& sp, hipStream_t st) {
                   2 * Nc, nnew, pr.ctmp, st);
   lambda_adjoint_cols(pr.gc, V + rows * r, rows, pr.cc, pr.order, pr.Vp[cur] + 2 * Nc * r, 2 * Nc,
                       nnew, st, &pr.spec);
+  // C E: only the new directions go through C; the rest is in CEb[cur]
+  const bool carry = pr.ce_ok || r == 0;
+  if (carry)
+    prop_coarse_cols(pr, pr.E[cur] + 2 * Nc * r, pr.CEb[cur] + 2 * Nc * r, nnew, st);
   // rotate: [U Q_F] X(:, 1:rn) etc.
   gemm_nn(rows, rn, n, 1.0, U, rows, pr.X, n, 0.0, pr.Ub[nxt], rows, st);
   gemm_nn(rows, rn, n, 1.0, V, rows, pr.Y, n, 0.0, pr.Vb[nxt], rows, st);
@@ -879,6 +892,16 @@ void update_svd_end(Prob& pr, const SvdPending& sp, hipStream_t st) {
   gemm_nn(2 * Nc, rn, n, 1.0, pr.Vp[cur], 2 * Nc, pr.Y, n, 0.0, pr.Vp[nxt], 2 * Nc, st);
   set_dc_column(pr.E[nxt], 2 * Nc, rn, Nc, 1.0 / (double)Nc, st);
   set_dc_column(pr.Vp[nxt], 2 * Nc, rn, Nc, 1.0, st);
+  if (carry) {
+    gemm_nn(2 * Nc, rn, n, 1.0, pr.CEb[cur], 2 * Nc, pr.X, n, 0.0, pr.CEb[nxt], 2 * Nc, st);
+    if (!pr.cdc_ok) {
+      prop_coarse_cols(pr, pr.E[nxt] + 2 * Nc * rn, pr.cdc, 1, st);
+      pr.cdc_ok = true;
+    }
+    PW_HIP(hipMemcpyAsync(pr.CEb[nxt] + 2 * Nc * rn, pr.cdc, sizeof(double) * 2 * Nc,
+                          hipMemcpyDeviceToDevice, st));
+  }
+  pr.ce_ok = carry;
   if (rn > 0)
     PW_HIP(hipMemcpyAsync(pr.S, pr.sig, sizeof(double) * rn, hipMemcpyDeviceToDevice, st));
   pr.cur = nxt;
@@ -904,6 +927,7 @@ void check_sampling(const Prob& pr, int K) {
 void reset_corrector(Prob& pr) {
   pr.r = 0;
   pr.cur = 0;
+  pr.ce_ok = false;
   pr.ranks.clear();
 }
 
@@ -1039,12 +1063,23 @@ void sweep_inputs(Prob& pr, hipStream_t st) {
 }
 
 // delta_n = E t_n with t_n = P^T Acol_n + (P^T C E) t_{n-1}, t_0 = 0: the
-// serial sweep in corrector coordinates (Acol already formed)
-void corrector_chain(Prob& pr, const double* E, const double* P, int dim, hipStream_t st) {
+// serial sweep in corrector coordinates (Acol already formed).  With
+// carry, E is the current corrector's E[cur] and C E comes from CEb[cur]
+// (formed here when it is not carried yet); otherwise E (a taped copy) is
+// propagated in full.
+void corrector_chain(Prob& pr, const double* E, const double* P, int dim, hipStream_t st,
+                     bool carry = false) {
   const int N = pr.N;
   const long long Nc = pr.Nc;
-  prop_coarse_cols(pr, E, pr.CE, dim, st);
-  gemm_tn(2 * Nc, dim, dim, 1.0, P, 2 * Nc, pr.CE, 2 * Nc, 0.0, pr.M, dim, pr.gwork,
+  double* CE = pr.CE;
+  if (carry) {
+    CE = pr.CEb[pr.cur];
+    if (!pr.ce_ok) prop_coarse_cols(pr, E, CE, dim, st);
+    pr.ce_ok = true;
+  } else {
+    prop_coarse_cols(pr, E, CE, dim, st);
+  }
+  gemm_tn(2 * Nc, dim, dim, 1.0, P, 2 * Nc, CE, 2 * Nc, 0.0, pr.M, dim, pr.gwork,
           pr.gwork_elems, st);
   gemm_tn(2 * Nc, dim, N, 1.0, P, 2 * Nc, pr.Acol, 2 * Nc, 0.0, pr.Bn, dim, pr.gwork,
           pr.gwork_elems, st);
@@ -1070,10 +1105,11 @@ void sweep_update(Prob& pr, bool add_v, hipStream_t st) {
 // 3.-4. corrected sweep in corrector coordinates and the update:
 // delta_n = Lambda^dag Omega Lambda C (a_n + delta_{n-1}) (R I = 1)
 template <typename T>
-void sweep_core(Prob& pr, const double* E, const double* P, int dim, hipStream_t st) {
+void sweep_core(Prob& pr, const double* E, const double* P, int dim, hipStream_t st,
+                bool carry) {
   sweep_inputs<T>(pr, st);
   prop_coarse_cols(pr, pr.Din, pr.Acol, pr.N, st);
-  corrector_chain(pr, E, P, dim, st);
+  corrector_chain(pr, E, P, dim, st, carry);
   sweep_update<T>(pr, true, st);
 }
 
@@ -1166,7 +1202,7 @@ void sweep_no_correction(Prob& pr, hipStream_t st) {
   cast_to_double<T>(tp<T>(pr.Rcp), pr.Din + Nc, Nc, st);
   if (pr.N > 1) fill(pr.Acol + C2, C2 * (pr.N - 1), 0.0, st);
   prop_coarse_cols(pr, pr.Din, pr.Acol, 1, st);
-  corrector_chain(pr, pr.E[pr.cur], pr.Vp[pr.cur], pr.r + 1, st);
+  corrector_chain(pr, pr.E[pr.cur], pr.Vp[pr.cur], pr.r + 1, st, true);
   sweep_update<T>(pr, false, st);
 }
 
@@ -1176,7 +1212,7 @@ void sweep_phase(Prob& pr, hipStream_t st) {
     case PW_VARIANT_OMEGA_ONE: sweep_serial_chain<T>(pr, true, st); break;
     case PW_VARIANT_PLAIN: sweep_serial_chain<T>(pr, false, st); break;
     case PW_VARIANT_NO_CORRECTION: sweep_no_correction<T>(pr, st); break;
-    default: sweep_core<T>(pr, pr.E[pr.cur], pr.Vp[pr.cur], pr.r + 1, st);
+    default: sweep_core<T>(pr, pr.E[pr.cur], pr.Vp[pr.cur], pr.r + 1, st, true);
   }
 }
 
@@ -1353,6 +1389,8 @@ __global__ void k_square(const double* in, double* out, long long n) {
 template <typename T>
 void set_medium_typed(Prob& pr, hipStream_t st) {
   const long long Nf = pr.Nf, Nc = pr.Nc;
+  pr.ce_ok = false;  // C changes
+  pr.cdc_ok = false;
   restrict_fields<double>(pr.gf, pr.ratio, pr.gc, pr.cf, Nf, pr.cc, Nc, 1, st);
   double* tmp = pr.c2c_d;  // coarse c^2 in double
   hipLaunchKernelGGL(k_square, dim3((unsigned)((Nc + 255) / 256)), dim3(256), 0, st,
@@ -1487,7 +1525,8 @@ void run_taped_typed(Prob& pr, int K, bool frozen, hipStream_t st) {
       P = t.P + ecols * kk;
       dim = t.dims[kk];
     }
-    sweep_core<T>(pr, E, P, dim, st);
+    // C E in full, as the backward forms it from the taped E
+    sweep_core<T>(pr, E, P, dim, st, false);
     PW_HIP(hipMemcpyAsync(t.Din + 2 * Nc * N * kk, pr.Din, sizeof(double) * 2 * Nc * N,
                           hipMemcpyDeviceToDevice, st));
     PW_HIP(hipMemcpyAsync(t.delta + 2 * Nc * N * kk, pr.delta, sizeof(double) * 2 * Nc * N,
@@ -2143,6 +2182,7 @@ const void* stage_in(const double* src, long long n, int on_device, Prob& pr, do
 void rebuild_sweep_columns(Prob& pr, hipStream_t st) {
   const long long rows = pr.rows, Nc = pr.Nc;
   const int r = pr.r, cur = pr.cur;
+  pr.ce_ok = false;
   for (int j0 = 0; j0 < r; j0 += pr.N) {
     const int nc = std::min(pr.N, r - j0);
     lambda_dag_cols(pr.gc, pr.dtab, pr.Ub[cur] + rows * j0, rows, pr.cc, nullptr,
@@ -2203,11 +2243,13 @@ void set_source(Prob& pr, const double* pos, double freq, double t0) {
 // Layout (host byte order): "PWCKPT02", int32 number of problems, then per
 // problem: its pw_problem fields as 20 int64 / double slots, int32 flags
 // [have_medium, have_initial, have_iterate, variant, k_done, r, cur,
-// samp_n, samp_iters, n_ranks, n_change, history levels, have_source, 0, 0,
-// 0], then the blocks that exist: c (Nf doubles); u0, p0 (state dtype); the
-// current iterate n = 1..N; the history levels; ranks; change; the
-// per-iteration record; U~, V~ (rows x r), S~ (r), E, P (2 Nc x (r + 1));
-// the sampling table; the source (x, y, freq, t0).
+// samp_n, samp_iters, n_ranks, n_change, history levels, have_source,
+// have_CE, 0, 0], then the blocks that exist: c (Nf doubles); u0, p0 (state
+// dtype); the current iterate n = 1..N; the history levels; ranks; change;
+// the per-iteration record; U~, V~ (rows x r), S~ (r), E, P (2 Nc x (r + 1));
+// the sampling table; the source (x, y, freq, t0); C E (2 Nc x (r + 1)).
+// A file without C E (have_CE = 0) loads; C E is then formed in full at the
+// next sweep.
 constexpr char kCkptMagic[9] = "PWCKPT02";
 constexpr int kSlots = 20;
 
@@ -2258,7 +2300,7 @@ void save_problem(FILE* f, Prob& pr, hipStream_t st) {
   const int32_t fl[16] = {pr.have_medium, pr.have_initial, pr.have_iterate, pr.variant,
                           pr.k_done, pr.r, pr.cur, pr.samp_n, pr.samp_iters,
                           (int32_t)pr.ranks.size(), (int32_t)pr.change.size(), levels,
-                          pr.have_src, 0, 0, 0};
+                          pr.have_src, pr.ce_ok && pr.have_medium, 0, 0};
   wr(f, fl, sizeof(fl));
   const size_t fb = pr.tsize * pr.Nf;
   const long long rows = pr.rows, Nc = pr.Nc;
@@ -2290,6 +2332,7 @@ void save_problem(FILE* f, Prob& pr, hipStream_t st) {
     const double sb[4] = {pr.src_pos[0], pr.src_pos[1], pr.src_freq, pr.src_t0};
     wr(f, sb, sizeof(sb));
   }
+  if (fl[13]) wr_dev(f, pr.CEb[pr.cur], sizeof(double) * 2 * Nc * (pr.r + 1), st);
 }
 
 template <typename T>
@@ -2313,7 +2356,7 @@ void load_problem(FILE* f, Prob& pr, hipStream_t st) {
       samp_n > pr.N || samp_iters < 0 || n_ranks < 0 || n_ranks > pr.P.max_iters ||
       n_change < 0 || n_change > pr.P.max_iters || levels < 0 ||
       levels > (pr.hist_u ? k_done + 1 : 0) || (have_iterate && !have_initial) ||
-      (!have_medium && (have_iterate || r > 0)))
+      (!have_medium && (have_iterate || r > 0 || fl[13])) || fl[13] < 0 || fl[13] > 1)
     fail(PW_EINVAL, "inconsistent checkpoint header");
   const size_t fb = pr.tsize * pr.Nf;
   const long long rows = pr.rows, Nc = pr.Nc;
@@ -2370,6 +2413,8 @@ void load_problem(FILE* f, Prob& pr, hipStream_t st) {
   } else {
     set_source(pr, nullptr, 0.0, 0.0);
   }
+  if (fl[13]) rd_dev(f, pr.CEb[cur], sizeof(double) * 2 * Nc * (r + 1), st);
+  pr.ce_ok = fl[13] != 0;
   pr.have_medium = have_medium;
   pr.have_initial = have_initial;
   pr.have_iterate = have_iterate;
