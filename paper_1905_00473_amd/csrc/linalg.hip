@@ -1335,10 +1335,15 @@ void orth_finish(long long rows, int n, const double* A, long long lda, double* 
     return;
   }
   // More than 64 columns: column blocks of 64 by block classical
-  // Gram-Schmidt with reorthogonalisation, each pass followed by a
-  // Householder QR of the block:
-  //   W = A_b - Qp C1 = Q1 R1;  Q1 - Qp C2 = Q_b R2
-  //   => A_b = Qp (C1 + C2 R1) + Q_b (R2 R1)
+  // Gram-Schmidt, projection passes each followed by a Householder QR of
+  // the block:
+  //   W = A_b - Qp C1 = Q1 R1;  Q1 - Qp C2 = Q2 R2;  Q2 - Qp C3 = Q_b R3
+  //   => A_b = Qp (C1 + C2 R1 + C3 R2 R1) + Q_b (R3 R2 R1)
+  // Two passes are not enough when A_b is numerically rank deficient
+  // against Qp: then Q1 - Qp C2 is ill conditioned, its QR amplifies the
+  // rounding left along Qp (orthogonality lost to ~1e-9 on such data), and
+  // the third pass, applied to a block already orthogonal to Qp but for
+  // that amplified rounding, restores it to rounding level.
   // With fewer rows than columns only the first m = rows columns are
   // factored that way (their Q, noise directions included, is a complete
   // orthonormal basis); the remaining columns get R = Q^T A and zero Q
@@ -1363,6 +1368,15 @@ void orth_finish(long long rows, int n, const double* A, long long lda, double* 
       gemm_tn(rows, b0, nb, 1.0, Q, ldq, Qb, ldq, 0.0, s.C, b0, s.work, s.work_elems, st);
       gemm_nn(rows, nb, b0, -1.0, Q, ldq, s.C, b0, 1.0, Qb, ldq, st);
       gemm_small(b0, nb, nb, 1.0, s.C, b0, false, s.R1, nb, false, 1.0, Rtop, n, st);
+      PW_HIP(hipMemcpy2DAsync(s.W, sizeof(double) * rows, Qb, sizeof(double) * ldq,
+                              sizeof(double) * rows, nb, hipMemcpyDeviceToDevice, st));
+      tsqr(rows, nb, s.W, rows, Qb, ldq, s.R2, s, st);
+      gemm_small(nb, nb, nb, 1.0, s.R2, nb, false, s.R1, nb, false, 0.0, Rbb, n, st);
+      // third pass: Rtop += C3 (R2 R1), Rbb = R3 (R2 R1)
+      gemm_tn(rows, b0, nb, 1.0, Q, ldq, Qb, ldq, 0.0, s.C, b0, s.work, s.work_elems, st);
+      gemm_nn(rows, nb, b0, -1.0, Q, ldq, s.C, b0, 1.0, Qb, ldq, st);
+      gemm_small(b0, nb, nb, 1.0, s.C, b0, false, Rbb, (int)n, false, 1.0, Rtop, n, st);
+      copy_block(nb, nb, Rbb, n, s.R1, nb, st);
       PW_HIP(hipMemcpy2DAsync(s.W, sizeof(double) * rows, Qb, sizeof(double) * ldq,
                               sizeof(double) * rows, nb, hipMemcpyDeviceToDevice, st));
       tsqr(rows, nb, s.W, rows, Qb, ldq, s.R2, s, st);
