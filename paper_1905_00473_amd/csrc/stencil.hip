@@ -976,37 +976,35 @@ void propagate_stream2d(const Grid& g, const T* c2, const T* u_src, const T* p_s
 }
 
 // launch shape of the 3D streaming kernel per state type: time steps per
-// launch, rows per wave, waves per workgroup
+// launch, rows per wave, waves per workgroup.  FP32 (compensated): 3 steps
+// of 64 x 24 blocks, 211 VGPRs, one workgroup of 8 waves per CU; measured
+// on the layers3d sweep (256^3, 32 states, 76 steps) against the other
+// shapes that fit the register file without spilling, (B, R) = (2, 2) 243
+// ms, (3, 2) 292, (2, 3) 276, (2, 4) 254, (4, 2) 325, (3, 3) 205 ms (all
+// bit-identical).  FP64: 2 steps of 64 x 8 blocks (a third step would
+// leave no output rows).  Build-time overrides PW_S3_B / PW_S3_R (FP32)
+// for such sweeps.
+#ifndef PW_S3_B
+#define PW_S3_B 3
+#endif
+#ifndef PW_S3_R
+#define PW_S3_R 3
+#endif
 template <typename T>
 struct Stream3Cfg {
-  static constexpr int B = 2;
-  static constexpr int R = sizeof(T) == 4 ? 2 : 1;
-  static constexpr int WY = 8;  // two workgroups per CU (measured faster than 16)
+  static constexpr int B = sizeof(T) == 4 ? PW_S3_B : 2;
+  static constexpr int R = sizeof(T) == 4 ? PW_S3_R : 1;
+  static constexpr int WY = 8;
+  static_assert(WY * R > 2 * (B + 1), "3D blocks need output rows");
 };
-
-// waves per workgroup of the 3D streaming kernel: 8 (two workgroups per
-// CU, so one workgroup's barrier stalls overlap the other's work); the
-// tuning override PW_STREAM3D_WAVES = 16 selects double-height blocks (fewer
-// halo rows, one workgroup per CU)
-int stream3d_waves() {
-  static const int w = [] {
-    const char* e = getenv("PW_STREAM3D_WAVES");  // tuning override
-    return (e && atoi(e) == 16) ? 16 : 8;
-  }();
-  return w;
-}
 
 template <typename T, bool COMP>
 void dispatch_stream3d(const Stream3Desc<T>& a, hipStream_t st) {
   using C = Stream3Cfg<T>;
   const long long nblk = (long long)a.nstates * a.nseg * a.nyb * a.ncb;
   if (nblk >= (1LL << 31)) fail(PW_EINVAL, "too many streams for one launch");
-  if (stream3d_waves() == 16)
-    hipLaunchKernelGGL((k_prop_stream3d<T, COMP, C::B, C::R, 16>), dim3((unsigned)nblk),
-                       dim3(64 * 16), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_prop_stream3d<T, COMP, C::B, C::R, C::WY>), dim3((unsigned)nblk),
-                       dim3(64 * C::WY), 0, st, a);
+  hipLaunchKernelGGL((k_prop_stream3d<T, COMP, C::B, C::R, C::WY>), dim3((unsigned)nblk),
+                     dim3(64 * C::WY), 0, st, a);
   PW_LAUNCH_CHECK();
 }
 
@@ -1022,7 +1020,7 @@ void propagate_stream3d(const Grid& g, const T* c2, const T* u_src, const T* p_s
   using C = Stream3Cfg<T>;
   constexpr int B = C::B, H = B + 1;
   constexpr int XV = 64 - 2 * H;
-  const int YV = stream3d_waves() * C::R - 2 * H;
+  const int YV = C::WY * C::R - 2 * H;
   Stream3Desc<T> a{};
   a.c2 = c2;
   a.sstride = sstride;
@@ -1149,7 +1147,7 @@ void launch_plan(const Grid& g, bool is_double, int nstates, int m, int* launche
       if (lanes * ((g.n[1] + 31) / 32) < 256) b = 4;
     }
   } else if (g.dim == 3) {
-    b = Stream3Cfg<float>::B;
+    b = is_double ? Stream3Cfg<double>::B : Stream3Cfg<float>::B;
   } else {
     b = tile_cfg(g.dim).hmax - 1;
   }
@@ -1160,7 +1158,7 @@ void launch_plan(const Grid& g, bool is_double, int nstates, int m, int* launche
 int steps_per_launch(const Grid& g, bool is_double) {
   if (use_line(g)) return 1 << 30;
   if (g.dim == 2) return is_double ? stream_depth<double>() : stream_depth<float>();
-  if (g.dim == 3) return Stream3Cfg<float>::B;
+  if (g.dim == 3) return is_double ? Stream3Cfg<double>::B : Stream3Cfg<float>::B;
   return tile_cfg(g.dim).hmax - 1;
 }
 
