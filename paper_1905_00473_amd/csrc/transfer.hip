@@ -262,7 +262,7 @@ template <typename Tin, typename Tout, bool FINAL>
 void interp_pass(const Tin* in, long long sin, Tout* out, long long sout, const Tout* v,
                  const double* tab, int outer, int nc, int ratio, int inner, int nfields,
                  hipStream_t st) {
-  constexpr int RJ = 4;
+  constexpr int RJ = 8;
   if (ratio == 4 || ratio == 2) {
     const long long n = (long long)outer * ((nc + RJ - 1) / RJ) * inner * nfields;
     const size_t smem = sizeof(double) * (size_t)ratio * nc;
