@@ -379,6 +379,15 @@ __global__ __launch_bounds__(256) void k_adj_stream2d(AdjStreamDesc a) {
       pp[0] = lpi[gi];
       pg[0] = (t + 2 >= Y0 && t + 2 < Y1) ? gs[gi] : 0.0;
     }
+    // the layer factor of every stage's centre row, loaded together ahead
+    // of the stages (the row index is wave-uniform)
+    double ddv[B];
+    if constexpr (FORCED) {
+      const int tu = __builtin_amdgcn_readfirstlane(t);
+#pragma unroll
+      for (int j = 0; j < B; ++j)
+        ddv[j] = (damp && j < a.nsteps) ? a.dd[(long long)near_row(tu - 2 * j) * nx + gx] : 1.0;
+    }
     // every stage takes its pending row into its windows (lp', q) and
     // loads the same row of its u level; then processes its centre row
     double ol[B], op[B], og[B];
@@ -405,7 +414,7 @@ __global__ __launch_bounds__(256) void k_adj_stream2d(AdjStreamDesc a) {
         if constexpr (FORCED) {
           if (damp) {
             const bool lev0 = a.lev_base + a.top - j == 0;
-            const double dc = a.dd[(long long)near_row(r) * nx + gx];
+            const double dc = ddv[j];
             go = gc + a.w[j] * (lev0 ? 1.0 : 0.5 * (1.0 + dc)) * pc * (lu_ * a.idx2);
             po = (lev0 ? dc : dc * dc) * pc;
           } else {

@@ -383,17 +383,35 @@ __device__ __forceinline__ void stream2d_body(const StreamDesc<T>& a, long long 
   const T dcol = damp ? a.f.dmp_x[gx] : T(1);
   const double* srow = FORCED && a.f.sx >= 0 ? a.f.src_tab + (long long)state * a.f.src_stride
                                              : nullptr;
-  // kick of level `lev` on row r: damp p, then add w (c^2 Lap u + source)
-  auto forced_kick = [&](T& pn, T& ep, T kl, int r, int lev, bool half) {
-    const int ry = wrap_near(r, ny);
-    const T d = damp ? min(dcol, a.f.dmp_y[ry]) : T(1);
+  // kick on a stage's row: damp p by the row's layer factor drow, then
+  // add w (c^2 Lap u + source), the source value sv being that of the
+  // row (zero off the source row)
+  auto forced_kick = [&](T& pn, T& ep, T kl, T drow, double sv, bool half) {
+    const T d = damp ? min(dcol, drow) : T(1);
     if (damp) kscale<T, COMP>(pn, ep, half ? d : d * d);
     const T w = half ? h * T(0.5) : h * T(0.5) * (T(1) + d);
     T acc = kl;
-    if (srow && ry == a.f.sy && gx == a.f.sx) acc += T(a.f.amp * srow[lev]);
+    if (sv != 0.0 && gx == a.f.sx) acc += T(sv);
     kadd<T, COMP>(pn, ep, w * acc);
   };
   for (int t = tbeg; t <= tend; ++t) {
+    // forced launches: the row factors of every stage's row for this step,
+    // from the wave-uniform row index (scalar loads, issued together)
+    T drow[B + 1];
+    double srcv[B + 1];
+    if constexpr (FORCED) {
+      const int tu = __builtin_amdgcn_readfirstlane(t);
+#pragma unroll
+      for (int j = 0; j <= B; ++j) {
+        const int ry = wrap_near(tu - 2 * j, ny);
+        drow[j] = damp ? a.f.dmp_y[ry] : T(1);
+        // stage j kicks level step0 + j when j < nsteps; stage B closes the
+        // slice at level step0 + nsteps
+        const bool act = j < B ? j < ns : (bool)last;
+        const int lev = a.step0 + (j < B ? j : ns);
+        srcv[j] = (srow && act && ry == a.f.sy) ? a.f.amp * srow[lev] : 0.0;
+      }
+    }
     // level 0, row t+2 -> pending slot of stage 0
     if (t + 2 < Y1 + H) {
       const int gy = wrap_idx(t + 2, ny);
@@ -419,7 +437,7 @@ __device__ __forceinline__ void stream2d_body(const StreamDesc<T>& a, long long 
           lap -= (lane_up(eu) - T(2) * eu + lane_down(eu)) +
                  (weu[j][0] - T(2) * eu + weu[j][2]);
         if constexpr (FORCED) {
-          forced_kick(pn, ep, kj * lap, t - 2 * j, a.step0 + j, j == 0 && first);
+          forced_kick(pn, ep, kj * lap, drow[j], srcv[j], j == 0 && first);
         } else {
           const T w = (j == 0 && first) ? h * T(0.5) : h;
           kadd<T, COMP>(pn, ep, w * (kj * lap));
@@ -468,7 +486,7 @@ __device__ __forceinline__ void stream2d_body(const StreamDesc<T>& a, long long 
         lap -= (lane_up(ec) - T(2) * ec + lane_down(ec)) + (weu[B][0] - T(2) * ec + weu[B][2]);
       T pn = wp[B][0], ep = wep[B][0];
       if constexpr (FORCED)
-        forced_kick(pn, ep, wk[B][0] * lap, t - 2 * B, a.step0 + ns, true);
+        forced_kick(pn, ep, wk[B][0] * lap, drow[B], srcv[B], true);
       else
         kadd<T, COMP>(pn, ep, h * T(0.5) * (wk[B][0] * lap));
       const int orow = t - 2 * B;
