@@ -475,15 +475,21 @@ constexpr int kJRowsSmall = 256;
 
 // one block pair of one round (see k_jacobi_block); lb: the workgroup's
 // index among the pairs of this matrix
+// threads of a block-pair workgroup: 8 waves (the staging, the Gram matrix
+// and the updates split over all of them; the 16 x 16 inner sweep on the
+// first four)
+constexpr int kJT = 512;
+constexpr int kJW = kJT / 64;
+
 template <int ROWS>
 __device__ __forceinline__ void jacobi_block_pair(int n, int npb, int round, int lb, double* H,
                                                   double* V, int* counter, const double* fro2,
                                                   double* cnorm2) {
   constexpr int kJLd = ROWS + 1;  // odd stride: the 16 columns fall in distinct LDS banks
-  constexpr int RPT = ROWS / 256;  // staged rows per thread and column
-  constexpr int VT = 8;            // V tiles per wave prefetched at the start
+  constexpr int RPT = (ROWS + kJT - 1) / kJT;  // staged rows per thread and column
+  constexpr int VT = 4;            // V tiles per wave prefetched at the start
   __shared__ double Hs[kJC * kJLd];
-  __shared__ double Gp[4][kJC * kJC];
+  __shared__ double Gp[kJW][kJC * kJC];
   __shared__ double G[2][kJC * kJC];
   __shared__ double W[2][kJC * kJC];
   __shared__ signed char part[kJC - 1][kJC];
@@ -513,7 +519,7 @@ __device__ __forceinline__ void jacobi_block_pair(int n, int npb, int round, int
   double va[VT][4];
 #pragma unroll
   for (int u = 0; u < VT; ++u) {
-    const int ra = 16 * (wave + 4 * u) + (lane & 15);
+    const int ra = 16 * (wave + kJW * u) + (lane & 15);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int gk = gcol(4 * t + (lane >> 4));
@@ -529,7 +535,7 @@ __device__ __forceinline__ void jacobi_block_pair(int n, int npb, int round, int
       const int gc = gcol(c);
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
-        const int row = tid + 256 * r;
+        const int row = tid + kJT * r;
         v[c][r] = (gc < n && row < n) ? H[(long long)gc * n + row] : 0.0;
       }
     }
@@ -538,7 +544,7 @@ __device__ __forceinline__ void jacobi_block_pair(int n, int npb, int round, int
     for (int c = 0; c < kJC; ++c)
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
-        const int row = tid + 256 * r;
+        const int row = tid + kJT * r;
         if (row < n64) Hs[c * kJLd + row] = v[c][r];
       }
   }
@@ -552,14 +558,16 @@ __device__ __forceinline__ void jacobi_block_pair(int n, int npb, int round, int
   if (tid == 0) nrot = 0;
   __syncthreads();
   // 1. Gram matrix D = B^T B of the staged block B (n x 16) on the matrix
-  //    cores, rows split over the 4 waves.  Operand lane l: A[l%16][l/16] =
-  //    B^T[l%16][k0 + l/16] = B[k0 + l/16][l%16], the same value for both.
+  //    cores, rows split over the 8 waves (wave w: rows 4 (w mod 4) + 16 s +
+  //    {0..3}, s = 0..3, of the (w / 4)-th 64-row half of every 128 rows).
+  //    Operand lane l: A[l%16][l/16] = B^T[l%16][k0 + l/16] = B[k0 +
+  //    l/16][l%16], the same value for both.
   {
     // rows beyond n are zero in the staged block up to the next multiple
     // of 64 (cleared above), so full groups of four steps need no test
     v4d acc0 = v4d{0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
     const double* col = Hs + (lane & 15) * kJLd + (lane >> 4);
-    for (int k0 = 4 * wave; k0 < n; k0 += 64) {
+    for (int k0 = 4 * (wave & 3) + 64 * (wave >> 2); k0 < n; k0 += 128) {
       const double x0 = col[k0], x1 = col[k0 + 16], x2 = col[k0 + 32], x3 = col[k0 + 48];
       acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, x0, acc0, 0, 0, 0);
       acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, x1, acc1, 0, 0, 0);
@@ -570,22 +578,28 @@ __device__ __forceinline__ void jacobi_block_pair(int n, int npb, int round, int
       Gp[wave][(4 * v + (lane >> 4)) * kJC + (lane & 15)] = acc0[v] + acc1[v];
   }
   __syncthreads();
-  G[0][tid] = Gp[0][tid] + Gp[1][tid] + Gp[2][tid] + Gp[3][tid];
-  W[0][tid] = (tid / kJC == tid % kJC) ? 1.0 : 0.0;
+  // the partial Gram matrices summed in a fixed order
+  auto gram_sum = [&](int e) {
+    double x = Gp[0][e];
+#pragma unroll
+    for (int w = 1; w < kJW; ++w) x += Gp[w][e];
+    return x;
+  };
+  if (tid < kJC * kJC) {
+    G[0][tid] = gram_sum(tid);
+    W[0][tid] = (tid / kJC == tid % kJC) ? 1.0 : 0.0;
+  }
   if (tid == 0) any_rot = 0;
   // squared norms of the block's columns, for the ordering of the next sweep
   // (the diagonal of G, summed in the same order)
-  if (tid < kJC && gcol(tid) < n) {
-    const int d = tid * (kJC + 1);
-    cnorm2[gcol(tid)] = Gp[0][d] + Gp[1][d] + Gp[2][d] + Gp[3][d];
-  }
+  if (tid < kJC && gcol(tid) < n) cnorm2[gcol(tid)] = gram_sum(tid * (kJC + 1));
   __syncthreads();
   // a pair is rotated only if it is above the threshold in the current
   // Gram matrix; if no pair of the fresh one is, the sweep below would
   // leave everything unchanged: skip it
   const double noise2 = 4.9e-32 * (*fro2);
   const double thr2 = 4.5e-16 * 4.5e-16 * (double)n;
-  {
+  if (tid < kJC * kJC) {
     const int pi_ = tid / kJC, pj_ = tid % kJC;
     if (pi_ < pj_ && gcol(pj_) < n) {
       const double al = G[0][pi_ * kJC + pi_], be = G[0][pj_ * kJC + pj_];
@@ -602,7 +616,9 @@ __device__ __forceinline__ void jacobi_block_pair(int n, int npb, int round, int
   //    it: no second barrier per round.  The partners of this thread's row
   //    and column index in the 15 rounds are packed four bits each into one
   //    register.
-  const int i = tid / kJC, j = tid % kJC;  // this thread's Gram / rotation entry
+  // (threads 0..255, the first four waves; the others keep the barriers)
+  const bool inner = tid < kJC * kJC;
+  const int i = inner ? tid / kJC : 0, j = tid % kJC;  // this thread's Gram / rotation entry
   const int src_i = (lane & ~(kJC - 1)) | i;
   unsigned long long packi = 0, packj = 0;
   for (int r = 0; r < kJC - 1; ++r) {
@@ -611,6 +627,11 @@ __device__ __forceinline__ void jacobi_block_pair(int n, int npb, int round, int
   }
   int cur = 0, myrot = 0;
   for (int r = 0; r < kJC - 1; ++r) {
+    if (!inner) {
+      cur ^= 1;
+      __syncthreads();
+      continue;
+    }
     const double* Gc = G[cur];
     const double* Wc = W[cur];
     const int pi = (int)((packi >> (4 * r)) & 15), pj = (int)((packj >> (4 * r)) & 15);
@@ -673,7 +694,7 @@ __device__ __forceinline__ void jacobi_block_pair(int n, int npb, int round, int
       if (row < n && gc < n) X[(long long)gc * n + row] = acc[v];
     }
   };
-  for (int tile = 16 * wave; tile < n; tile += 64) {
+  for (int tile = 16 * wave; tile < n; tile += 16 * kJW) {
     const int ra = tile + (lane & 15);
     v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -686,7 +707,7 @@ __device__ __forceinline__ void jacobi_block_pair(int n, int npb, int round, int
   }
 #pragma unroll
   for (int u = 0; u < VT; ++u) {
-    const int tile = 16 * (wave + 4 * u);
+    const int tile = 16 * (wave + kJW * u);
     if (tile < n) {
       v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -694,7 +715,7 @@ __device__ __forceinline__ void jacobi_block_pair(int n, int npb, int round, int
       store(V, tile, acc);
     }
   }
-  for (int tile = 16 * (wave + 4 * VT); tile < n; tile += 64) {
+  for (int tile = 16 * (wave + kJW * VT); tile < n; tile += 16 * kJW) {
     const int ra = tile + (lane & 15);
     double a[4];
 #pragma unroll
@@ -711,7 +732,7 @@ __device__ __forceinline__ void jacobi_block_pair(int n, int npb, int round, int
 }
 
 template <int ROWS>
-__global__ __launch_bounds__(256) void k_jacobi_block(int n, int npb, int round, double* H,
+__global__ __launch_bounds__(kJT) void k_jacobi_block(int n, int npb, int round, double* H,
                                                       double* V, int* counter,
                                                       const double* fro2, double* cnorm2) {
   jacobi_block_pair<ROWS>(n, npb, round, (int)blockIdx.x, H, V, counter, fro2, cnorm2);
@@ -760,7 +781,7 @@ __device__ __forceinline__ int job_of(const JacobiJob* jobs, int nj, int blk) {
 }
 
 template <int ROWS>
-__global__ __launch_bounds__(256) void k_jacobi_block_multi(const JacobiJob* jobs, int nj,
+__global__ __launch_bounds__(kJT) void k_jacobi_block_multi(const JacobiJob* jobs, int nj,
                                                             int round) {
   const JacobiJob& j = jobs[job_of(jobs, nj, (int)blockIdx.x)];
   if (round >= j.npb - 1) return;  // this matrix has fewer rounds per sweep
@@ -1442,7 +1463,7 @@ void svd_jacobi(int n, const double* H, double* X, double* Y, double* sig, doubl
       std::swap(Hc, Hn);
       std::swap(Vc, Vn);
       for (int round = 0; round < npb - 1; ++round) {
-        hipLaunchKernelGGL(k_jacobi_block<kJRows>, dim3(8 * ((npb / 2 + 7) / 8)), dim3(256), 0,
+        hipLaunchKernelGGL(k_jacobi_block<kJRows>, dim3(8 * ((npb / 2 + 7) / 8)), dim3(kJT), 0,
                            st, n, npb, round, Hc, Vc, counters + sw, (const double*)fro2, cnorm2);
         PW_LAUNCH_CHECK();
       }
@@ -1555,10 +1576,10 @@ void svd_jacobi_multi(const std::vector<SvdJob>& jobs, void* jobs_dev, int* coun
     PW_HIP(hipMemcpyAsync(dro, ro.data(), sizeof(JacobiJob) * na, hipMemcpyHostToDevice, st));
     for (int round = 0; round < maxr; ++round) {
       if (nmax <= kJRowsSmall)
-        hipLaunchKernelGGL(k_jacobi_block_multi<kJRowsSmall>, dim3((unsigned)blocks), dim3(256), 0,
+        hipLaunchKernelGGL(k_jacobi_block_multi<kJRowsSmall>, dim3((unsigned)blocks), dim3(kJT), 0,
                            st, (const JacobiJob*)dro, na, round);
       else
-        hipLaunchKernelGGL(k_jacobi_block_multi<kJRows>, dim3((unsigned)blocks), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_jacobi_block_multi<kJRows>, dim3((unsigned)blocks), dim3(kJT), 0, st,
                            (const JacobiJob*)dro, na, round);
       PW_LAUNCH_CHECK();
     }
