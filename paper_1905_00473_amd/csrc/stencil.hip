@@ -602,7 +602,11 @@ __global__ __launch_bounds__(256) void k_prop_stream2d_multi(const StreamDesc<T>
 // side, so the halo is H = B + 1 lanes and rows (the +1 for the closing
 // half kick) and a block writes 64 - 2H columns of WY*R - 2H rows.  Row and
 // column indices are wrapped once per thread, the plane index by one
-// conditional add per loaded plane.
+// conditional add per loaded plane.  Registers go to the u and p windows
+// only: each stage reads c^2 of its centre plane from memory, the stages
+// run last to first so that a stage's result lands directly in the next
+// stage's window, and only the last launch of a slice (LAST) carries the
+// window of the closing half kick.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct Stream3Desc {
@@ -623,15 +627,18 @@ struct Stream3Desc {
   int nsteps, first, last;
 };
 
-template <typename T, bool COMP, int B, int R, int WY>
+template <typename T, bool COMP, int B, int R, int WY, bool LAST>
 __global__ __launch_bounds__(64 * WY) void k_prop_stream3d(Stream3Desc<T> a) {
   constexpr int H = B + 1;
+  // stages that hold a window: stage B (the closing half kick) only in the
+  // last launch of a slice; the other launches keep no registers for it
+  constexpr int NW = LAST ? B + 1 : B;
   constexpr int XV = 64 - 2 * H;  // output columns of a block
   constexpr int YR = WY * R;      // rows of a block
   constexpr int YV = YR - 2 * H;  // output rows of a block
   constexpr int NX = COMP ? 2 : 1;
   // [buffer][field u / e][stage][first / last row][wave][lane]
-  __shared__ T xch[2][NX][B + 1][2][WY][64];
+  __shared__ T xch[2][NX][NW][2][WY][64];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   // blocks of one XCD (block ids congruent mod 8) take consecutive streams,
@@ -647,26 +654,34 @@ __global__ __launch_bounds__(64 * WY) void k_prop_stream3d(Stream3Desc<T> a) {
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const int gx = wrap_idx(cb * XV - H + lane, nx);
   const bool out_lane = lane >= H && lane < 64 - H && (cb * XV + lane - H) < nx;
-  long long rowoff[R];  // (y * nx + x) of this thread's rows
+  // byte offset of this thread's row r inside a plane (a plane of one state
+  // holds fewer than 2^31 bytes): every access is a wave-uniform plane
+  // address plus this 32-bit offset
+  unsigned rowb[R];
   bool out_row[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int yr = w * R + r;  // row within the block
     const int gy = wrap_idx(yb * YV - H + yr, ny);
-    rowoff[r] = (long long)gy * nx + gx;
+    rowb[r] = (unsigned)(gy * nx + gx) * (unsigned)sizeof(T);
     out_row[r] = out_lane && yr >= H && yr < YR - H && (yb * YV + yr - H) < ny;
   }
+  auto ld = [&](const T* pl, int r) -> T {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(pl) + rowb[r]);
+  };
+  auto st = [&](T* pl, int r, T v) { *reinterpret_cast<T*>(reinterpret_cast<char*>(pl) + rowb[r]) = v; };
   const long long plane = (long long)nx * ny;
   const int Z0 = seg * a.Lz;
   const int Z1 = min(Z0 + a.Lz, nz);
   const long long base = (long long)state * a.sstride;
   const T h = a.h;
   const int ns = a.nsteps;
-  const bool first = a.first, last = a.last;
+  const bool first = a.first;
+  constexpr bool last = LAST;
   // stage j window: level-j planes (z-1, z, z+1), z = t - 2j; the pending
   // plane z+2 comes from stage j-1 (or memory, for j = 0) in step t
-  T wu[B + 1][3][R], weu[B + 1][3][R], wp[B + 1][2][R], wep[B + 1][2][R], wk[B + 1][2][R];
-  T qu[B + 1][R], qp[B + 1][R], qeu[B + 1][R], qep[B + 1][R], qk[B + 1][R];
+  T wu[B + 1][3][R], weu[B + 1][3][R], wp[B + 1][2][R], wep[B + 1][2][R];
+  T qu[R], qp[R], qeu[R], qep[R];
 #pragma unroll
   for (int j = 0; j <= B; ++j)
 #pragma unroll
@@ -674,27 +689,31 @@ __global__ __launch_bounds__(64 * WY) void k_prop_stream3d(Stream3Desc<T> a) {
       wu[j][0][r] = wu[j][1][r] = wu[j][2][r] = T(0);
       weu[j][0][r] = weu[j][1][r] = weu[j][2][r] = T(0);
       wp[j][0][r] = wp[j][1][r] = wep[j][0][r] = wep[j][1][r] = T(0);
-      wk[j][0][r] = wk[j][1][r] = T(0);
-      qu[j][r] = qp[j][r] = qeu[j][r] = qep[j][r] = qk[j][r] = T(0);
     }
+#pragma unroll
+  for (int r = 0; r < R; ++r) qu[r] = qp[r] = qeu[r] = qep[r] = T(0);
   const int tout = last ? 2 * B : 2 * (B - 1);  // lag of the written level
   const int tbeg = Z0 - H - 2;
   const int tend = Z1 - 1 + tout;  // inclusive
   int zl = tbeg + 2;               // plane loaded this step, wrapped below
   zl = zl < 0 ? zl + nz : zl;
+  // centre plane of stage j (t - 2j, wrapped): c^2 is read there by each
+  // stage from memory (an L2 hit: stage 0 read the plane's u and p two
+  // steps per stage earlier) instead of riding the register pipeline
+  int zs[B + 1];
+#pragma unroll
+  for (int j = 0; j <= B; ++j) zs[j] = ((tbeg - 2 * j) % nz + nz) % nz;
   for (int t = tbeg; t <= tend; ++t) {
     // level 0, plane t+2 -> pending slot of stage 0
     if (t + 2 < Z1 + H) {
-      const long long po = (long long)zl * plane;
+      const long long po = base + (long long)zl * plane;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const long long gi = base + po + rowoff[r];
-        qu[0][r] = a.u_in[gi];
-        qp[0][r] = a.p_in[gi];
-        qk[0][r] = a.c2[po + rowoff[r]] * a.idx2;
+        qu[r] = ld(a.u_in + po, r);
+        qp[r] = ld(a.p_in + po, r);
         if (COMP) {
-          qeu[0][r] = first ? T(0) : a.eu_in[gi];
-          qep[0][r] = first ? T(0) : a.ep_in[gi];
+          qeu[r] = first ? T(0) : ld(a.eu_in + po, r);
+          qep[r] = first ? T(0) : ld(a.ep_in + po, r);
         }
       }
     }
@@ -702,7 +721,7 @@ __global__ __launch_bounds__(64 * WY) void k_prop_stream3d(Stream3Desc<T> a) {
     // publish the first and last row of every stage's centre plane
     const int buf = t & 1;
 #pragma unroll
-    for (int j = 0; j <= B; ++j) {
+    for (int j = 0; j < NW; ++j) {
       xch[buf][0][j][0][w][lane] = wu[j][1][0];
       xch[buf][0][j][1][w][lane] = wu[j][1][R - 1];
       if (COMP) {
@@ -715,7 +734,7 @@ __global__ __launch_bounds__(64 * WY) void k_prop_stream3d(Stream3Desc<T> a) {
     // rows are in the halo)
     T au[B + 1], bu[B + 1], ae[B + 1], be[B + 1];
 #pragma unroll
-    for (int j = 0; j <= B; ++j) {
+    for (int j = 0; j < NW; ++j) {
       au[j] = w > 0 ? xch[buf][0][j][1][w - 1][lane] : T(0);
       bu[j] = w < WY - 1 ? xch[buf][0][j][0][w + 1][lane] : T(0);
       ae[j] = (COMP && w > 0) ? xch[buf][NX - 1][j][1][w - 1][lane] : T(0);
@@ -729,81 +748,91 @@ __global__ __launch_bounds__(64 * WY) void k_prop_stream3d(Stream3Desc<T> a) {
       return (lane_up(c) - T(2) * c + lane_down(c)) + (ym - T(2) * c + yp) +
              (win[0][r] - T(2) * c + win[2][r]);
     };
-    // stages 0..B-1: kick + drift (stages past nsteps pass the plane through)
+    // stages last to first: once stage j + 1 has used its window and moved
+    // it on by one plane, stage j writes its result straight into that
+    // window's top slot, so no pending plane stays live across the step
 #pragma unroll
-    for (int j = 0; j < B; ++j) {
+    for (int j = B; j >= 0; --j) {
+      if (j == B) {
+        // closing half kick of the slice, then fold and write
+        if constexpr (LAST) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const T uc = wu[j][1][r];
-        T un = uc, pn = wp[j][0][r], eu = weu[j][1][r], ep = wep[j][0][r];
-        const T kj = wk[j][0][r];
-        if (j < ns) {
-          T lap = lap_of(wu[j], au[j], bu[j], r);
-          if (COMP) lap -= lap_of(weu[j], ae[j], be[j], r);
-          const T wgt = (j == 0 && first) ? h * T(0.5) : h;
-          kadd<T, COMP>(pn, ep, wgt * (kj * lap));
-          kadd<T, COMP>(un, eu, h * pn);
-        }
-        qu[j + 1][r] = un;
-        qp[j + 1][r] = pn;
-        qeu[j + 1][r] = eu;
-        qep[j + 1][r] = ep;
-        qk[j + 1][r] = kj;
-        if (j == B - 1 && !last) {
-          const int oz = t - 2 * j;
-          if (out_row[r] && oz >= Z0 && oz < Z1) {
-            const long long gi = base + (long long)oz * plane + rowoff[r];
-            a.u_out[gi] = un;
-            a.p_out[gi] = pn;
-            if (COMP) {
-              a.eu_out[gi] = eu;
-              a.ep_out[gi] = ep;
+          for (int r = 0; r < R; ++r) {
+            const T uc = wu[B][1][r];
+            const T ec = weu[B][1][r];
+            T lap = lap_of(wu[B], au[B], bu[B], r);
+            if (COMP) lap -= lap_of(weu[B], ae[B], be[B], r);
+            T pn = wp[B][0][r], ep = wep[B][0][r];
+            const T kb = ld(a.c2 + (long long)zs[B] * plane, r) * a.idx2;
+            kadd<T, COMP>(pn, ep, h * T(0.5) * (kb * lap));
+            const int oz = t - 2 * B;
+            if (out_row[r] && oz >= Z0 && oz < Z1) {
+              const long long go = base + (long long)oz * plane;
+              if (COMP) {
+                st(a.u_out + go, r, uc - ec);
+                st(a.p_out + go, r, pn - ep);
+              } else {
+                st(a.u_out + go, r, uc);
+                st(a.p_out + go, r, pn);
+              }
             }
           }
         }
-      }
-    }
-    // stage B: closing half kick of the slice, then fold and write
-    if (last) {
+      } else {
+        // kick + drift (stages past nsteps pass the plane through)
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const T uc = wu[B][1][r];
-        const T ec = weu[B][1][r];
-        T lap = lap_of(wu[B], au[B], bu[B], r);
-        if (COMP) lap -= lap_of(weu[B], ae[B], be[B], r);
-        T pn = wp[B][0][r], ep = wep[B][0][r];
-        kadd<T, COMP>(pn, ep, h * T(0.5) * (wk[B][0][r] * lap));
-        const int oz = t - 2 * B;
-        if (out_row[r] && oz >= Z0 && oz < Z1) {
-          const long long gi = base + (long long)oz * plane + rowoff[r];
-          if (COMP) {
-            a.u_out[gi] = uc - ec;
-            a.p_out[gi] = pn - ep;
-          } else {
-            a.u_out[gi] = uc;
-            a.p_out[gi] = pn;
+        for (int r = 0; r < R; ++r) {
+          const T uc = wu[j][1][r];
+          T un = uc, pn = wp[j][0][r], eu = weu[j][1][r], ep = wep[j][0][r];
+          if (j < ns) {
+            const T kj = ld(a.c2 + (long long)zs[j] * plane, r) * a.idx2;
+            T lap = lap_of(wu[j], au[j], bu[j], r);
+            if (COMP) lap -= lap_of(weu[j], ae[j], be[j], r);
+            const T wgt = (j == 0 && first) ? h * T(0.5) : h;
+            kadd<T, COMP>(pn, ep, wgt * (kj * lap));
+            kadd<T, COMP>(un, eu, h * pn);
+          }
+          if (j == B - 1 && !last) {
+            const int oz = t - 2 * j;
+            if (out_row[r] && oz >= Z0 && oz < Z1) {
+              const long long go = base + (long long)oz * plane;
+              st(a.u_out + go, r, un);
+              st(a.p_out + go, r, pn);
+              if (COMP) {
+                st(a.eu_out + go, r, eu);
+                st(a.ep_out + go, r, ep);
+              }
+            }
+          }
+          if (j + 1 < NW) {
+            wu[j + 1][2][r] = un;
+            wp[j + 1][1][r] = pn;
+            weu[j + 1][2][r] = eu;
+            wep[j + 1][1][r] = ep;
           }
         }
       }
-    }
-    // advance every window by one plane, taking in the pending plane
+      // stage j's window moves on by one plane; its top slot is written by
+      // stage j - 1 next (for stage 0, from the plane loaded above)
 #pragma unroll
-    for (int j = 0; j <= B; ++j)
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
+      for (int r = 0; r < R && j < NW; ++r) {
         wu[j][0][r] = wu[j][1][r];
         wu[j][1][r] = wu[j][2][r];
-        wu[j][2][r] = qu[j][r];
         wp[j][0][r] = wp[j][1][r];
-        wp[j][1][r] = qp[j][r];
         weu[j][0][r] = weu[j][1][r];
         weu[j][1][r] = weu[j][2][r];
-        weu[j][2][r] = qeu[j][r];
         wep[j][0][r] = wep[j][1][r];
-        wep[j][1][r] = qep[j][r];
-        wk[j][0][r] = wk[j][1][r];
-        wk[j][1][r] = qk[j][r];
       }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      wu[0][2][r] = qu[r];
+      wp[0][1][r] = qp[r];
+      weu[0][2][r] = qeu[r];
+      wep[0][1][r] = qep[r];
+    }
+#pragma unroll
+    for (int j = 0; j <= B; ++j) zs[j] = zs[j] + 1 == nz ? 0 : zs[j] + 1;
   }
 }
 
@@ -1002,26 +1031,38 @@ void propagate_stream2d(const Grid& g, const T* c2, const T* u_src, const T* p_s
 }
 
 // launch shape of the 3D streaming kernel per state type: time steps per
-// launch, rows per wave, waves per workgroup.  FP32 (compensated): 3 steps
-// of 64 x 24 blocks, 211 VGPRs, one workgroup of 8 waves per CU; measured
-// on the layers3d sweep (256^3, 32 states, 76 steps) against the other
-// shapes that fit the register file without spilling, (B, R) = (2, 2) 243
-// ms, (3, 2) 292, (2, 3) 276, (2, 4) 254, (4, 2) 325, (3, 3) 205 ms (all
-// bit-identical).  FP64: 2 steps of 64 x 8 blocks (a third step would
-// leave no output rows).  Build-time overrides PW_S3_B / PW_S3_R (FP32)
-// for such sweeps.
+// launch, rows per wave, waves per workgroup.  FP32 (compensated): 4 steps
+// of 64 x 32 blocks, one workgroup of 16 waves per CU (119 VGPRs; the last
+// launch of a slice, which also holds the closing half kick, 128 with a
+// few spilled).  Measured on the layers3d sweep (256^3, 32 states, 76
+// steps), all shapes bit-identical, (B, R, WY) = (4, 2, 16) 183 ms against
+// (3, 2, 16) 185, (4, 2, 12) 198, (3, 2, 12) 209, (3, 3, 12) 235, (2, 3,
+// 16) 261 and (3, 3, 8) 252; the kernel that carried c^2 in registers and
+// every stage window in every launch ran (3, 3, 8) in 206 ms.  FP64: 2
+// steps of 64 x 8 blocks (a third step would leave no output rows).
+// Build-time overrides PW_S3_B / PW_S3_R / PW_S3_WY / PW_S3_WYL (FP32) for
+// such sweeps.
 #ifndef PW_S3_B
-#define PW_S3_B 3
+#define PW_S3_B 4
 #endif
 #ifndef PW_S3_R
-#define PW_S3_R 3
+#define PW_S3_R 2
+#endif
+#ifndef PW_S3_WY
+#define PW_S3_WY 16
+#endif
+#ifndef PW_S3_WYL
+#define PW_S3_WYL 12
 #endif
 template <typename T>
 struct Stream3Cfg {
   static constexpr int B = sizeof(T) == 4 ? PW_S3_B : 2;
   static constexpr int R = sizeof(T) == 4 ? PW_S3_R : 1;
-  static constexpr int WY = 8;
-  static_assert(WY * R > 2 * (B + 1), "3D blocks need output rows");
+  static constexpr int WY = sizeof(T) == 4 ? PW_S3_WY : 8;
+  // waves of the last launch of a slice, whose closing half kick holds one
+  // more stage window (at 16 waves it would spill)
+  static constexpr int WYL = sizeof(T) == 4 ? PW_S3_WYL : 8;
+  static_assert(WY * R > 2 * (B + 1) && WYL * R > 2 * (B + 1), "3D blocks need output rows");
 };
 
 template <typename T, bool COMP>
@@ -1029,8 +1070,12 @@ void dispatch_stream3d(const Stream3Desc<T>& a, hipStream_t st) {
   using C = Stream3Cfg<T>;
   const long long nblk = (long long)a.nstates * a.nseg * a.nyb * a.ncb;
   if (nblk >= (1LL << 31)) fail(PW_EINVAL, "too many streams for one launch");
-  hipLaunchKernelGGL((k_prop_stream3d<T, COMP, C::B, C::R, C::WY>), dim3((unsigned)nblk),
-                     dim3(64 * C::WY), 0, st, a);
+  if (a.last)
+    hipLaunchKernelGGL((k_prop_stream3d<T, COMP, C::B, C::R, C::WYL, true>), dim3((unsigned)nblk),
+                       dim3(64 * C::WYL), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_prop_stream3d<T, COMP, C::B, C::R, C::WY, false>), dim3((unsigned)nblk),
+                       dim3(64 * C::WY), 0, st, a);
   PW_LAUNCH_CHECK();
 }
 
@@ -1046,7 +1091,6 @@ void propagate_stream3d(const Grid& g, const T* c2, const T* u_src, const T* p_s
   using C = Stream3Cfg<T>;
   constexpr int B = C::B, H = B + 1;
   constexpr int XV = 64 - 2 * H;
-  const int YV = C::WY * C::R - 2 * H;
   Stream3Desc<T> a{};
   a.c2 = c2;
   a.sstride = sstride;
@@ -1054,17 +1098,23 @@ void propagate_stream3d(const Grid& g, const T* c2, const T* u_src, const T* p_s
   a.ny = g.n[1];
   a.nz = g.n[2];
   if (a.nx < H || a.ny < H || a.nz < H) fail(PW_EINVAL, "3D grid smaller than the stencil halo");
+  if ((long long)a.nx * a.ny * (long long)sizeof(T) >= (1LL << 31))
+    fail(PW_EINVAL, "3D plane of 2^31 bytes or more");
   a.nstates = nstates;
   a.h = h;
   a.idx2 = T(1.0 / (g.dx * g.dx));
-  a.ncb = (a.nx + XV - 1) / XV;
-  a.nyb = (a.ny + YV - 1) / YV;
-  const long long blocks = (long long)nstates * a.ncb * a.nyb;
-  const int minz = blocks < 256 ? 2 * B : 16;
-  long long nseg = (kStream3Target + blocks - 1) / blocks;
-  nseg = std::max(1LL, std::min(nseg, (long long)((a.nz + minz - 1) / minz)));
-  a.Lz = (int)((a.nz + nseg - 1) / nseg);
-  a.nseg = (a.nz + a.Lz - 1) / a.Lz;
+  // block geometry for a workgroup of wy waves
+  auto geometry = [&](int wy) {
+    const int YV = wy * C::R - 2 * H;
+    a.ncb = (a.nx + XV - 1) / XV;
+    a.nyb = (a.ny + YV - 1) / YV;
+    const long long blocks = (long long)nstates * a.ncb * a.nyb;
+    const int minz = blocks < 256 ? 2 * B : 16;
+    long long nseg = (kStream3Target + blocks - 1) / blocks;
+    nseg = std::max(1LL, std::min(nseg, (long long)((a.nz + minz - 1) / minz)));
+    a.Lz = (int)((a.nz + nseg - 1) / nseg);
+    a.nseg = (a.nz + a.Lz - 1) / a.Lz;
+  };
   const int nl = (m + B - 1) / B;
   if (nl > 1 && (wa.u == nullptr || wb.u == nullptr || (comp && (wa.eu == nullptr || wb.eu == nullptr))))
     fail(PW_EINVAL, "propagation needs scratch state sets");
@@ -1076,6 +1126,7 @@ void propagate_stream3d(const Grid& g, const T* c2, const T* u_src, const T* p_s
     a.first = (l == 0);
     a.last = (l == nl - 1);
     a.nsteps = std::min(B, m - l * B);
+    geometry(a.last ? C::WYL : C::WY);
     a.u_in = cu;
     a.p_in = cp;
     a.eu_in = ceu;
