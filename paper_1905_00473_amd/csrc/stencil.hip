@@ -1032,10 +1032,12 @@ void propagate_stream2d(const Grid& g, const T* c2, const T* u_src, const T* p_s
 
 // launch shape of the 3D streaming kernel per state type: time steps per
 // launch, rows per wave, waves per workgroup.  FP32 (compensated): 4 steps
-// of 64 x 32 blocks, one workgroup of 16 waves per CU (119 VGPRs; the last
-// launch of a slice, which also holds the closing half kick, 128 with a
-// few spilled).  Measured on the layers3d sweep (256^3, 32 states, 76
-// steps), all shapes bit-identical, (B, R, WY) = (4, 2, 16) 183 ms against
+// of 64 x 32 blocks, one workgroup of 16 waves per CU (119 VGPRs); the
+// last launch of a slice, which also holds the closing half kick, runs 12
+// waves on 64 x 24 blocks (148 VGPRs; at 16 waves it spills).  Measured on the layers3d sweep (256^3, 32 states, 76
+// steps), all shapes bit-identical: the last launch at 12 waves 173 ms,
+// at 8 waves 183 and at 16 (spilling) 184; with the last launch also at
+// 16 waves, (B, R, WY) = (4, 2, 16) 183 ms against
 // (3, 2, 16) 185, (4, 2, 12) 198, (3, 2, 12) 209, (3, 3, 12) 235, (2, 3,
 // 16) 261 and (3, 3, 8) 252; the kernel that carried c^2 in registers and
 // every stage window in every launch ran (3, 3, 8) in 206 ms.  FP64: 2
