@@ -161,18 +161,20 @@ def test_gradient_matches_gpu_finite_differences(case):
     s.close()
 
 
-def test_fp32_compensated_gradient_close_to_oracle():
+@pytest.mark.parametrize("K", [1, 2])
+@pytest.mark.parametrize("case", ["2d", "1d", "3d"])
+def test_fp32_compensated_gradient_close_to_oracle(case, K):
     """FP32 compensated states, FP64 adjoint: the gradient follows the
-    FP64 oracle to the accuracy of the FP32 trajectory."""
-    K = 2
-    w, rec, data = W.misfit_case(K=K, **CASES["2d"])
+    FP64 oracle (from the same FP32-rounded initial state) to 1e-5 of its
+    maximum, the FP32 tolerance of the state."""
+    w, rec, data = W.misfit_case(K=K, **CASES[case])
     s, u0 = _solver(w, K, dtype="f32", compensated=True)
     s.run_taped(K)
     seed = to_np(s.traces(rec)) - data
     g = to_np(s.backward(rec, seed))
     _, g_ref, _, _, _ = _oracle(w, u0, K, rec, data)
     err = np.abs(g - g_ref).max()
-    assert err <= 1e-4 * np.abs(g_ref).max(), (err, np.abs(g_ref).max())
+    assert err <= 1e-5 * np.abs(g_ref).max(), (err, np.abs(g_ref).max())
     s.close()
 
 
