@@ -86,6 +86,46 @@ def test_propagator_parity(name, make, dtype, grid):
         assert np.max(np.abs(to_np(uo[k]) - ru)) / scale < (1e-12 if dtype == "f64" else 1e-5)
 
 
+@pytest.mark.parametrize("m", [1, 7, 8])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_propagator_parity_3d_ragged(dtype, m):
+    """3D F on a grid of unequal sides that are not multiples of the
+    streaming blocks' output columns and rows, for step counts that end on
+    a partial launch (7), on whole launches (8) and within one launch (1):
+    the last launch of a slice runs its own block geometry."""
+    import torch
+    import paper_1905_00473_amd as pw
+    shape = (26, 50, 72)  # (z, y, x)
+    h = 0.004  # c dt / dx <= 1.5 * 0.004 * 72 = 0.43 (3D bound 1/sqrt 3)
+    P = pw.Problem.make(shape, 2, 4 * m * h, 4, m, m, 2, 1e-14, dtype,
+                        dtype == "f32", 1)
+    Q = O.Problem(shape, 2, 4 * m * h, 4, m, m, 2, 1e-14)
+    g = np.meshgrid(*[np.arange(n) / n for n in shape], indexing="ij")
+    c = 1.0 + 0.3 * np.sin(2 * np.pi * g[2]) * np.cos(2 * np.pi * g[1]) + 0.1 * g[0]
+    s = pw.Solver(P)
+    s.set_medium(c)
+    rng = np.random.default_rng(5)
+    us, ps = [], []
+    for _ in range(3):
+        ph = sum(2 * np.pi * rng.integers(1, 4) * x for x in g)
+        us.append(np.cos(ph + rng.uniform()) + 0.1 * rng.standard_normal(shape))
+        ps.append(np.sin(ph) * rng.uniform(0.5, 2))
+    td = torch.float64 if dtype == "f64" else torch.float32
+    u = torch.tensor(np.stack(us), dtype=td, device="cuda")
+    p = torch.tensor(np.stack(ps), dtype=td, device="cuda")
+    uo, po = s.propagate(u, p)
+    c2 = c * c
+    if dtype == "f32":
+        c2 = c2.astype(np.float32).astype(np.float64)
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    for k in range(3):
+        ru, rp = O.propagate(to_np(u[k]), to_np(p[k]), c2, Q.dt_fine, Q.dx_fine, m)
+        err = rel_energy_err(to_np(uo[k]), to_np(po[k]), ru, rp, c, Q.dx_fine)
+        assert err < tol, (dtype, m, k, err)
+        assert np.max(np.abs(to_np(uo[k]) - ru)) / np.max(np.abs(ru)) < tol
+    s.close()
+
+
 def test_batched_equals_single_bitwise():
     import torch
     w = W.disc2d(n=72, ratio=4, N=4, K=2, T=0.25)
