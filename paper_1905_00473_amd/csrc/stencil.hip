@@ -1040,10 +1040,15 @@ void propagate_stream2d(const Grid& g, const T* c2, const T* u_src, const T* p_s
 // 16 waves, (B, R, WY) = (4, 2, 16) 183 ms against
 // (3, 2, 16) 185, (4, 2, 12) 198, (3, 2, 12) 209, (3, 3, 12) 235, (2, 3,
 // 16) 261 and (3, 3, 8) 252; the kernel that carried c^2 in registers and
-// every stage window in every launch ran (3, 3, 8) in 206 ms.  FP64: 2
-// steps of 64 x 8 blocks (a third step would leave no output rows).
-// Build-time overrides PW_S3_B / PW_S3_R / PW_S3_WY / PW_S3_WYL (FP32) for
-// such sweeps.
+// every stage window in every launch ran (3, 3, 8) in 206 ms.  FP64
+// (uncompensated): 3 steps of 64 x 32 blocks of 16 waves (98 VGPRs), the
+// last launch 8 waves (126 VGPRs); the FP64 layers3d sweep (256^3, 32
+// states) takes 178 ms against (B, R, WY, last) = (3, 2, 16, 12) 185,
+// (4, 2, 16, 12) 182, (2, 1, 16, 16) 211, (2, 2, 16, 12) 225, (2, 2, 8, 8)
+// 234, (4, 1, 16, 16) 275 and the earlier (2, 1, 8, 8) 368, all
+// bit-identical.  Build-time overrides PW_S3_B / PW_S3_R / PW_S3_WY /
+// PW_S3_WYL (FP32) and PW_S3D_B / PW_S3D_R / PW_S3D_WY / PW_S3D_WYL (FP64)
+// for such sweeps.
 #ifndef PW_S3_B
 #define PW_S3_B 4
 #endif
@@ -1056,14 +1061,26 @@ void propagate_stream2d(const Grid& g, const T* c2, const T* u_src, const T* p_s
 #ifndef PW_S3_WYL
 #define PW_S3_WYL 12
 #endif
+#ifndef PW_S3D_B
+#define PW_S3D_B 3
+#endif
+#ifndef PW_S3D_R
+#define PW_S3D_R 2
+#endif
+#ifndef PW_S3D_WY
+#define PW_S3D_WY 16
+#endif
+#ifndef PW_S3D_WYL
+#define PW_S3D_WYL 8
+#endif
 template <typename T>
 struct Stream3Cfg {
-  static constexpr int B = sizeof(T) == 4 ? PW_S3_B : 2;
-  static constexpr int R = sizeof(T) == 4 ? PW_S3_R : 1;
-  static constexpr int WY = sizeof(T) == 4 ? PW_S3_WY : 8;
+  static constexpr int B = sizeof(T) == 4 ? PW_S3_B : PW_S3D_B;
+  static constexpr int R = sizeof(T) == 4 ? PW_S3_R : PW_S3D_R;
+  static constexpr int WY = sizeof(T) == 4 ? PW_S3_WY : PW_S3D_WY;
   // waves of the last launch of a slice, whose closing half kick holds one
   // more stage window (at 16 waves it would spill)
-  static constexpr int WYL = sizeof(T) == 4 ? PW_S3_WYL : 8;
+  static constexpr int WYL = sizeof(T) == 4 ? PW_S3_WYL : PW_S3D_WYL;
   static_assert(WY * R > 2 * (B + 1) && WYL * R > 2 * (B + 1), "3D blocks need output rows");
 };
 
