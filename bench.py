@@ -54,21 +54,22 @@ FLOPS_PER_UPDATE = {1: 8, 2: 12, 3: 16}
 # by the same counters on a 512 MiB copy (profiles/disc2d_fine_stencil_
 # traffic.md).  Valid only for the stencil revision it was measured on.
 TRAFFIC = {"stencil-r6": 563.7e6, "stencil-r7": 561.5e6, "stencil-r8": 563.3e6,
-           "stencil-r9": 563.6e6}
+           "stencil-r9": 563.6e6, "stencil-r10": 563.5e6}
 # the same for the 3D stencil (layers3d) and the multi-problem 2D kernel
 # (batch2d), per launch (mean over one sweep), keyed by the revision they
 # were measured on (profiles/batch2d_fine_stencil_counters.md,
 # profiles/layers3d_fine_stencil_counters.md)
 TRAFFIC3D = {"stencil-r7": 32386.9e6, "stencil-r8": 24877.7e6,
-             "stencil-r9": 21802.8e6}
+             "stencil-r9": 21802.8e6, "stencil-r10": 21796.3e6}
 TRAFFIC_BATCH = {"stencil-r7": 13787.9e6, "stencil-r8": 13780.4e6,
-                 "stencil-r9": 13787.3e6}
+                 "stencil-r9": 13787.3e6, "stencil-r10": 13792.9e6}
 # VALU instructions issued / (SIMDs x 4 cycles x elapsed cycles) over the
 # same launches, from SQ_INSTS_VALU and GRBM_GUI_ACTIVE (values above 1:
 # some instructions dual-issued)
 VALU_ISSUE = {"stencil-r7": {"multi": 1.095, "single2d": 0.935, "3d": 0.526},
               "stencil-r8": {"multi": 1.121, "single2d": 0.944, "3d": 0.544},
-              "stencil-r9": {"multi": 1.097, "single2d": 0.933, "3d": 0.567}}
+              "stencil-r9": {"multi": 1.097, "single2d": 0.933, "3d": 0.567},
+              "stencil-r10": {"multi": 1.097, "single2d": 0.932, "3d": 0.567}}
 
 
 def log(msg):

@@ -2440,7 +2440,7 @@ const char* pw_last_error(void) { return g_last_error.c_str(); }
 
 // the last word names the revision of the fine stencil kernel (bench.py
 // keys measured HBM traffic on it)
-const char* pw_version(void) { return "pwave 0.4 (gfx950) stencil-r9"; }
+const char* pw_version(void) { return "pwave 0.4 (gfx950) stencil-r10"; }
 
 int pw_num_problems(const pw_ctx* ctx) { return ctx ? (int)ctx->probs.size() : 0; }
 
